@@ -1,0 +1,293 @@
+"""CPU oracle for the SFC cluster neighbour list and the SPH density pass.
+
+TEST INFRASTRUCTURE ONLY: plain, slow, obviously correct reference code that
+the GPU library is checked against. Only the tests, the smoke check and the
+CPU-baseline leg of the benchmark may import it; the GPU library never does,
+and the two share no code.
+
+Every function cites the part of the paper it follows ("GPU-Native Compressed
+Neighbor Lists with a Space-Filling-Curve Data Layout"). The heavy loops live
+in ``oracle.c`` (built with gcc, ``-ffp-contract=off``); library primitives
+(numpy's stable argsort, min/max) serve as single steps.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lock = threading.Lock()
+_lib = None
+
+KEY_BITS = 21
+SC_SIZE = 64   # particles per super-cluster (Sec. II-A)
+WAVE = 64      # segment width: the AMD wavefront (Sec. II-C)
+
+
+def build(force: bool = False) -> str:
+    """Compile oracle.c into liboracle.so with gcc (no GPU code involved)."""
+    if force or not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-fopenmp", "-ffp-contract=off",
+               "-fno-fast-math", "-D_DEFAULT_SOURCE", "-o", tmp, _SRC, "-lm"]
+        subprocess.run(cmd, check=True)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        build()
+        lib = C.CDLL(_LIB)
+        f32p = np.ctypeslib.ndpointer(np.float32, flags="C_CONTIGUOUS")
+        u64p = np.ctypeslib.ndpointer(np.uint64, flags="C_CONTIGUOUS")
+        i64p = np.ctypeslib.ndpointer(np.int64, flags="C_CONTIGUOUS")
+        f64p = np.ctypeslib.ndpointer(np.float64, flags="C_CONTIGUOUS")
+        i32p = np.ctypeslib.ndpointer(np.int32, flags="C_CONTIGUOUS")
+        u32p = np.ctypeslib.ndpointer(np.uint32, flags="C_CONTIGUOUS")
+        u16p = np.ctypeslib.ndpointer(np.uint16, flags="C_CONTIGUOUS")
+        u8p = np.ctypeslib.ndpointer(np.uint8, flags="C_CONTIGUOUS")
+        lib.orc_hilbert3.restype = C.c_uint64
+        lib.orc_hilbert3.argtypes = [C.c_uint32, C.c_uint32, C.c_uint32, C.c_int]
+        lib.orc_hilbert_keys.restype = None
+        lib.orc_hilbert_keys.argtypes = [C.c_int64, f32p, f32p, f32p, f32p, u64p]
+        lib.orc_is_pair.restype = C.c_int
+        lib.orc_is_pair.argtypes = [C.c_float] * 8
+        lib.orc_max_degree.restype = C.c_int64
+        lib.orc_max_degree.argtypes = [C.c_int64, f32p, f32p, f32p, f32p, C.c_int]
+        lib.orc_pairs_csr.restype = None
+        lib.orc_pairs_csr.argtypes = [C.c_int64, f32p, f32p, f32p, f32p, C.c_int, i64p, C.c_void_p]
+        lib.orc_cluster_list.restype = C.c_int
+        lib.orc_cluster_list.argtypes = [C.c_int64, f32p, f32p, f32p, f32p, C.c_int, C.c_int, C.c_int64,
+                                         C.c_void_p, C.c_int64, C.POINTER(C.c_void_p),
+                                         C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]
+        lib.orc_free.restype = None
+        lib.orc_free.argtypes = [C.c_void_p]
+        lib.orc_encode_block_symbols.restype = C.c_int
+        lib.orc_encode_block_symbols.argtypes = [u32p, C.c_int, u8p, u8p, C.POINTER(C.c_int), u8p,
+                                                 C.POINTER(C.c_int)]
+        lib.orc_encode_sc.restype = C.c_int64
+        lib.orc_encode_sc.argtypes = [C.c_int64, u32p, u16p, C.c_int, C.c_int, C.c_void_p]
+        lib.orc_decode_sc.restype = C.c_int64
+        lib.orc_decode_sc.argtypes = [u32p, C.c_int64, C.c_int, C.c_int, u32p, u16p]
+        lib.orc_kernel_w.restype = C.c_double
+        lib.orc_kernel_w.argtypes = [C.c_double, C.c_double]
+        lib.orc_density.restype = None
+        lib.orc_density.argtypes = [C.c_int64, f32p, f32p, f32p, f32p, C.c_void_p, C.c_int, f64p, i32p]
+        lib.orc_num_threads.restype = C.c_int
+        lib.orc_num_threads.argtypes = []
+        _lib = lib
+        return lib
+
+
+def _f32(a):
+    return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def num_threads() -> int:
+    return int(_load().orc_num_threads())
+
+
+# --------------------------------------------------------------------------
+# Sec. II-A: Hilbert order, stable sort, clusters
+# --------------------------------------------------------------------------
+
+def hilbert3(x: int, y: int, z: int, bits: int = KEY_BITS) -> int:
+    """Hilbert index of integer cell (x, y, z) on a 2^bits grid (Skilling)."""
+    return int(_load().orc_hilbert3(x, y, z, bits))
+
+
+def hilbert_keys(x, y, z, box) -> np.ndarray:
+    """63-bit keys of positions quantised to 21 bits per axis inside box
+    = (xmin, xmax, ymin, ymax, zmin, zmax)."""
+    x, y, z = _f32(x), _f32(y), _f32(z)
+    out = np.empty(x.shape[0], dtype=np.uint64)
+    _load().orc_hilbert_keys(x.shape[0], x, y, z, _f32(box), out)
+    return out
+
+
+def sfc_order(keys) -> np.ndarray:
+    """Permutation putting particles in ascending key order, ties kept in
+    input order (a stable sort; library primitive)."""
+    return np.argsort(np.asarray(keys), kind="stable").astype(np.uint32)
+
+
+def cluster_bboxes(x, y, z, h, cs: int) -> np.ndarray:
+    """Per cluster of cs consecutive particles: (lo.x, lo.y, lo.z, h_max,
+    hi.x, hi.y, hi.z, 0) as float32 (exact min / max)."""
+    n = len(x)
+    nc = (n + cs - 1) // cs
+    out = np.zeros((nc, 8), dtype=np.float32)
+    for c in range(0, nc):
+        s = slice(c * cs, min(n, c * cs + cs))
+        out[c, 0], out[c, 1], out[c, 2] = x[s].min(), y[s].min(), z[s].min()
+        out[c, 3] = h[s].max()
+        out[c, 4], out[c, 5], out[c, 6] = x[s].max(), y[s].max(), z[s].max()
+    return out
+
+
+# --------------------------------------------------------------------------
+# Sec. II-A: pair set and cluster-pair list
+# --------------------------------------------------------------------------
+
+def is_pair(xi, yi, zi, hi, xj, yj, zj, hj) -> bool:
+    return bool(_load().orc_is_pair(xi, yi, zi, hi, xj, yj, zj, hj))
+
+
+def pairs_csr(x, y, z, h, method: str = "brute"):
+    """Pair set P as CSR (offs[n+1], nbr ascending per particle)."""
+    x, y, z, h = _f32(x), _f32(y), _f32(z), _f32(h)
+    n = x.shape[0]
+    g = 1 if method == "grid" else 0
+    offs = np.zeros(n + 1, dtype=np.int64)
+    lib = _load()
+    lib.orc_pairs_csr(n, x, y, z, h, g, offs, None)
+    nbr = np.zeros(max(1, int(offs[-1])), dtype=np.int64)
+    lib.orc_pairs_csr(n, x, y, z, h, g, offs, nbr.ctypes.data)
+    return offs, nbr[: offs[-1]]
+
+
+def max_degree(x, y, z, h, method: str = "grid") -> int:
+    x, y, z, h = _f32(x), _f32(y), _f32(z), _f32(h)
+    return int(_load().orc_max_degree(x.shape[0], x, y, z, h, 1 if method == "grid" else 0))
+
+
+def cluster_list(x, y, z, h, cs: int = 8, method: str = "grid", sc_ids=None):
+    """Cluster-pair list of Sec. II-A: per selected super-cluster the
+    ascending j-cluster indices and their i-cluster bitmasks.
+
+    Returns (offs[nsel+1] int64, j uint32, mask uint16)."""
+    x, y, z, h = _f32(x), _f32(y), _f32(z), _f32(h)
+    n = x.shape[0]
+    lib = _load()
+    g = 1 if method == "grid" else 0
+    md = int(lib.orc_max_degree(n, x, y, z, h, g))
+    if sc_ids is None:
+        nsel = (n + SC_SIZE - 1) // SC_SIZE
+        ids_ptr = None
+        ids = None
+    else:
+        ids = np.ascontiguousarray(sc_ids, dtype=np.int64)
+        nsel = ids.shape[0]
+        ids_ptr = ids.ctypes.data
+    po, pj, pm = C.c_void_p(), C.c_void_p(), C.c_void_p()
+    rc = lib.orc_cluster_list(n, x, y, z, h, cs, g, nsel, ids_ptr, md, C.byref(po), C.byref(pj), C.byref(pm))
+    if rc != 0:
+        raise MemoryError("oracle cluster list")
+    offs = np.ctypeslib.as_array(C.cast(po, C.POINTER(C.c_int64)), shape=(nsel + 1,)).copy()
+    tot = int(offs[-1])
+    j = np.ctypeslib.as_array(C.cast(pj, C.POINTER(C.c_uint32)), shape=(max(tot, 1),))[:tot].copy()
+    m = np.ctypeslib.as_array(C.cast(pm, C.POINTER(C.c_uint16)), shape=(max(tot, 1),))[:tot].copy()
+    for p in (po, pj, pm):
+        lib.orc_free(p)
+    return offs, j, m
+
+
+# --------------------------------------------------------------------------
+# Sec. II-B / II-C: nibble encoding
+# --------------------------------------------------------------------------
+
+def block_symbols(values):
+    """Symbols of one block of difference values (Sec. II-B): (bitmask as a
+    0/1 list, info nibbles, data nibbles)."""
+    v = np.ascontiguousarray(values, dtype=np.uint32)
+    cnt = v.shape[0]
+    bits = np.zeros(max(cnt, 1), np.uint8)
+    info = np.zeros(max(cnt, 1), np.uint8)
+    data = np.zeros(max(cnt * 8, 1), np.uint8)
+    ni, nd = C.c_int(0), C.c_int(0)
+    if _load().orc_encode_block_symbols(v, cnt, bits, info, C.byref(ni), data, C.byref(nd)) != 0:
+        raise ValueError("difference value 0 cannot be encoded")
+    return list(bits[:cnt]), list(info[: ni.value]), list(data[: nd.value])
+
+
+def encode_sc(j, mask, cs: int = 8, compress: bool = True) -> np.ndarray:
+    """Word stream (uint32) of one super-cluster: masks, then the j indices
+    (raw or in nibble segments)."""
+    j = np.ascontiguousarray(j, dtype=np.uint32)
+    mask = np.ascontiguousarray(mask, dtype=np.uint16)
+    lib = _load()
+    nw = lib.orc_encode_sc(j.shape[0], j, mask, cs, int(compress), None)
+    if nw < 0:
+        raise ValueError("list not strictly ascending")
+    out = np.zeros(max(int(nw), 1), dtype=np.uint32)
+    lib.orc_encode_sc(j.shape[0], j, mask, cs, int(compress), out.ctypes.data)
+    return out[: int(nw)]
+
+
+def decode_sc(words, nj: int, cs: int = 8, compress: bool = True):
+    w = np.ascontiguousarray(words, dtype=np.uint32)
+    if w.shape[0] == 0:
+        w = np.zeros(1, np.uint32)
+    j = np.zeros(max(nj, 1), np.uint32)
+    m = np.zeros(max(nj, 1), np.uint16)
+    used = _load().orc_decode_sc(w, nj, cs, int(compress), j, m)
+    if used < 0:
+        raise ValueError("malformed stream")
+    return j[:nj], m[:nj], int(used)
+
+
+def encode_all(offs, j, mask, cs: int = 8, compress: bool = True):
+    """Whole list: sc_info (n_sc x 2 uint32: word offset, n_j) and the pool
+    (uint32 words), super-clusters laid out in order."""
+    nsc = offs.shape[0] - 1
+    info = np.zeros((nsc, 2), dtype=np.uint32)
+    parts = []
+    pos = 0
+    for s in range(nsc):
+        a, b = int(offs[s]), int(offs[s + 1])
+        words = encode_sc(j[a:b], mask[a:b], cs, compress) if b > a else np.zeros(0, np.uint32)
+        info[s, 0] = pos
+        info[s, 1] = b - a
+        parts.append(words)
+        pos += words.shape[0]
+    pool = np.concatenate(parts) if parts else np.zeros(0, np.uint32)
+    return info, pool
+
+
+# --------------------------------------------------------------------------
+# Sec. II-D, Listing 1: SPH density and neighbour counts (FP64)
+# --------------------------------------------------------------------------
+
+def kernel_w(r: float, h: float) -> float:
+    return float(_load().orc_kernel_w(r, h))
+
+
+def density(x, y, z, h, m=None, method: str = "grid"):
+    """(rho float64, nnb int32): gather density with support h_i and the
+    number of j != i inside h_i (decided by the FP32 pair formula)."""
+    x, y, z, h = _f32(x), _f32(y), _f32(z), _f32(h)
+    n = x.shape[0]
+    rho = np.zeros(max(n, 1), np.float64)
+    nnb = np.zeros(max(n, 1), np.int32)
+    mm = None if m is None else _f32(m)
+    _load().orc_density(n, x, y, z, h, None if mm is None else mm.ctypes.data,
+                        1 if method == "grid" else 0, rho, nnb)
+    return rho[:n], nnb[:n]
+
+
+# --------------------------------------------------------------------------
+# The whole path on one system
+# --------------------------------------------------------------------------
+
+def pipeline(x, y, z, h, box, m=None, cs: int = 8, compress: bool = True, method: str = "grid"):
+    """Hilbert keys -> stable order -> SFC-ordered arrays -> cluster list ->
+    encoding -> density, all in SFC order. Returns a dict."""
+    keys = hilbert_keys(x, y, z, box)
+    perm = sfc_order(keys)
+    xs, ys, zs, hs = (np.asarray(a)[perm] for a in (x, y, z, h))
+    ms = None if m is None else np.asarray(m)[perm]
+    offs, jj, mm = cluster_list(xs, ys, zs, hs, cs, method)
+    info, pool = encode_all(offs, jj, mm, cs, compress)
+    rho, nnb = density(xs, ys, zs, hs, ms, method)
+    return dict(keys=keys, perm=perm, sorted_keys=keys[perm], x=xs, y=ys, z=zs, h=hs, m=ms,
+                offs=offs, j=jj, mask=mm, sc_info=info, pool=pool, rho=rho, nnb=nnb)

@@ -1,0 +1,621 @@
+/*
+ * CPU oracle for the SFC cluster neighbour list and the SPH density pass.
+ *
+ * TEST INFRASTRUCTURE ONLY. This file is the plain, slow, obviously correct
+ * reference that the GPU library is checked against. It shares no code with
+ * the GPU library and the product path never calls it.
+ *
+ * What it computes (paper: "GPU-Native Compressed Neighbor Lists with a
+ * Space-Filling-Curve Data Layout"):
+ *   - Hilbert keys of quantised positions (Sec. II-A: particles are kept in
+ *     Hilbert order; the curve variant is Skilling's transpose algorithm,
+ *     J. Skilling, AIP Conf. Proc. 707, 2004).
+ *   - The particle pair set P = {(i,j): i != j, d2 < max(h_i,h_j)^2} under one
+ *     fixed FP32 formula (Sec. II-A, per-particle interaction radii).
+ *   - The cluster-pair list: per super-cluster of 64 particles, the ascending
+ *     j-cluster indices with one bit per i-cluster (Sec. II-A).
+ *   - The nibble encoding of Sec. II-B / Table I, laid out in segments of one
+ *     wavefront width (Sec. II-C).
+ *   - SPH densities rho_i = sum_j m_j W(r_ij, h_i) and neighbour counts in
+ *     FP64 (Sec. II-D, Listing 1).
+ *
+ * Must be compiled with -ffp-contract=off: the FP32 pair test below spells
+ * out every rounding step and no other contraction is allowed.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_KEY_BITS 21
+
+/* ------------------------------------------------------------------------- */
+/* Hilbert keys                                                               */
+/* ------------------------------------------------------------------------- */
+
+/* Skilling's AxesToTranspose for three axes of `bits` bits, then the
+ * transposed words are read out most-significant bit first, x before y
+ * before z, three bits per level. */
+uint64_t orc_hilbert3(uint32_t x, uint32_t y, uint32_t z, int bits)
+{
+    uint32_t X[3] = {x, y, z};
+    uint32_t top = 1u << (bits - 1);
+    /* undo excess work: walk the levels from the top */
+    for (uint32_t q = top; q > 1; q >>= 1) {
+        uint32_t p = q - 1;
+        for (int i = 0; i < 3; i++) {
+            if (X[i] & q) {
+                X[0] ^= p; /* invert low bits of axis 0 */
+            } else {
+                uint32_t t = (X[0] ^ X[i]) & p; /* swap low bits of axes 0 and i */
+                X[0] ^= t;
+                X[i] ^= t;
+            }
+        }
+    }
+    /* Gray encode */
+    X[1] ^= X[0];
+    X[2] ^= X[1];
+    uint32_t t = 0;
+    for (uint32_t q = top; q > 1; q >>= 1)
+        if (X[2] & q) t ^= q - 1;
+    for (int i = 0; i < 3; i++) X[i] ^= t;
+    /* interleave */
+    uint64_t key = 0;
+    for (int b = bits - 1; b >= 0; b--) {
+        uint64_t d = ((uint64_t)((X[0] >> b) & 1u) << 2) | ((uint64_t)((X[1] >> b) & 1u) << 1) |
+                     (uint64_t)((X[2] >> b) & 1u);
+        key = (key << 3) | d;
+    }
+    return key;
+}
+
+/* Quantise one coordinate to 21 bits: q = trunc(f32(f32(x - lo) * s)),
+ * clamped to [0, 2^21 - 1]; s = f32(2^21 / (hi - lo)) in double. */
+static float orc_scale(float lo, float hi)
+{
+    return (float)(2097152.0 / ((double)hi - (double)lo));
+}
+
+static uint32_t orc_quantise(float x, float lo, float s)
+{
+    float t = x - lo;
+    t = t * s;
+    if (!(t > 0.0f)) return 0u;
+    if (t >= 2097151.0f) return 2097151u;
+    return (uint32_t)t;
+}
+
+void orc_hilbert_keys(int64_t n, const float *x, const float *y, const float *z, const float *box,
+                      uint64_t *keys)
+{
+    float sx = orc_scale(box[0], box[1]), sy = orc_scale(box[2], box[3]), sz = orc_scale(box[4], box[5]);
+    for (int64_t i = 0; i < n; i++) {
+        uint32_t qx = orc_quantise(x[i], box[0], sx);
+        uint32_t qy = orc_quantise(y[i], box[2], sy);
+        uint32_t qz = orc_quantise(z[i], box[4], sz);
+        keys[i] = orc_hilbert3(qx, qy, qz, ORC_KEY_BITS);
+    }
+}
+
+/* ------------------------------------------------------------------------- */
+/* The FP32 pair test                                                         */
+/* ------------------------------------------------------------------------- */
+
+/* d2 = fma(dz, dz, fma(dy, dy, dx*dx)) with dx = f32(x_j - x_i) etc.;
+ * the pair is in P iff d2 < f32(max(h_i, h_j)^2), strictly. */
+static float orc_d2(float xi, float yi, float zi, float xj, float yj, float zj)
+{
+    float dx = xj - xi;
+    float dy = yj - yi;
+    float dz = zj - zi;
+    float dxx = dx * dx;
+    return fmaf(dz, dz, fmaf(dy, dy, dxx));
+}
+
+int orc_is_pair(float xi, float yi, float zi, float hi, float xj, float yj, float zj, float hj)
+{
+    float d2 = orc_d2(xi, yi, zi, xj, yj, zj);
+    float r = hi > hj ? hi : hj;
+    float r2 = r * r;
+    return d2 < r2;
+}
+
+/* Own-radius (gather) test used by the density and the neighbour count. */
+static int orc_in_own_radius(float xi, float yi, float zi, float hi, float xj, float yj, float zj)
+{
+    float d2 = orc_d2(xi, yi, zi, xj, yj, zj);
+    float r2 = hi * hi;
+    return d2 < r2;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Cell list (a textbook uniform grid, Quentrec & Brot 1973)                  */
+/* ------------------------------------------------------------------------- */
+
+typedef struct {
+    double lo[3], edge;
+    int64_t dim[3];
+    int64_t *start; /* ncell + 1 */
+    int64_t *idx;   /* particles sorted by cell */
+} orc_grid;
+
+static int64_t grid_cell1(const orc_grid *g, int a, double v)
+{
+    int64_t c = (int64_t)floor((v - g->lo[a]) / g->edge);
+    if (c < 0) c = 0;
+    if (c >= g->dim[a]) c = g->dim[a] - 1;
+    return c;
+}
+
+/* Cells of edge >= max radius * (1 + 2^-20): every FP32-accepted pair lies in
+ * adjacent cells, since FP32 rounding accepts pairs at most a few ulp beyond R. */
+static void grid_build(orc_grid *g, int64_t n, const float *x, const float *y, const float *z,
+                       const float *h)
+{
+    double lo[3] = {INFINITY, INFINITY, INFINITY}, hi[3] = {-INFINITY, -INFINITY, -INFINITY};
+    double hmax = 0.0;
+    const float *p[3] = {x, y, z};
+    for (int64_t i = 0; i < n; i++) {
+        for (int a = 0; a < 3; a++) {
+            if (p[a][i] < lo[a]) lo[a] = p[a][i];
+            if (p[a][i] > hi[a]) hi[a] = p[a][i];
+        }
+        if (h[i] > hmax) hmax = h[i];
+    }
+    if (n == 0) { lo[0] = lo[1] = lo[2] = 0.0; hi[0] = hi[1] = hi[2] = 0.0; }
+    double edge = hmax * (1.0 + ldexp(1.0, -20));
+    double ext = 0.0;
+    for (int a = 0; a < 3; a++) if (hi[a] - lo[a] > ext) ext = hi[a] - lo[a];
+    /* keep the cell count near N: a coarser grid is still exact, just slower */
+    double cap = ceil(cbrt((double)(n > 1 ? n : 1))) + 1.0;
+    if (edge <= 0.0 || ext / edge > cap) edge = ext / cap;
+    if (edge <= 0.0) edge = 1.0;
+    g->edge = edge;
+    int64_t ncell = 1;
+    for (int a = 0; a < 3; a++) {
+        g->lo[a] = lo[a];
+        g->dim[a] = (int64_t)floor((hi[a] - lo[a]) / edge) + 1;
+        ncell *= g->dim[a];
+    }
+    g->start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
+    g->idx = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    int64_t *cell = (int64_t *)malloc((size_t)(n > 0 ? n : 1) * sizeof(int64_t));
+    for (int64_t i = 0; i < n; i++) {
+        int64_t c = (grid_cell1(g, 2, z[i]) * g->dim[1] + grid_cell1(g, 1, y[i])) * g->dim[0] +
+                    grid_cell1(g, 0, x[i]);
+        cell[i] = c;
+        g->start[c + 1]++;
+    }
+    for (int64_t c = 0; c < ncell; c++) g->start[c + 1] += g->start[c];
+    int64_t *fill = (int64_t *)malloc((size_t)ncell * sizeof(int64_t));
+    memcpy(fill, g->start, (size_t)ncell * sizeof(int64_t));
+    for (int64_t i = 0; i < n; i++) g->idx[fill[cell[i]]++] = i;
+    free(fill);
+    free(cell);
+}
+
+static void grid_free(orc_grid *g)
+{
+    free(g->start);
+    free(g->idx);
+}
+
+static int cmp_i64(const void *a, const void *b)
+{
+    int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
+    return (x > y) - (x < y);
+}
+
+/* Neighbours of particle i in P, ascending, written to out (capacity cap).
+ * Returns the count (which may exceed cap; then only cap are written). */
+static int64_t neighbours_of(const orc_grid *g, int use_grid, int64_t n, const float *x, const float *y,
+                             const float *z, const float *h, int64_t i, int64_t *out, int64_t cap)
+{
+    int64_t cnt = 0;
+    if (!use_grid) {
+        for (int64_t j = 0; j < n; j++) {
+            if (j == i) continue;
+            if (orc_is_pair(x[i], y[i], z[i], h[i], x[j], y[j], z[j], h[j])) {
+                if (cnt < cap) out[cnt] = j;
+                cnt++;
+            }
+        }
+        return cnt;
+    }
+    int64_t cx = grid_cell1(g, 0, x[i]), cy = grid_cell1(g, 1, y[i]), cz = grid_cell1(g, 2, z[i]);
+    for (int64_t az = cz - 1; az <= cz + 1; az++) {
+        if (az < 0 || az >= g->dim[2]) continue;
+        for (int64_t ay = cy - 1; ay <= cy + 1; ay++) {
+            if (ay < 0 || ay >= g->dim[1]) continue;
+            for (int64_t ax = cx - 1; ax <= cx + 1; ax++) {
+                if (ax < 0 || ax >= g->dim[0]) continue;
+                int64_t c = (az * g->dim[1] + ay) * g->dim[0] + ax;
+                for (int64_t k = g->start[c]; k < g->start[c + 1]; k++) {
+                    int64_t j = g->idx[k];
+                    if (j == i) continue;
+                    if (orc_is_pair(x[i], y[i], z[i], h[i], x[j], y[j], z[j], h[j])) {
+                        if (cnt < cap) out[cnt] = j;
+                        cnt++;
+                    }
+                }
+            }
+        }
+    }
+    if (cnt <= cap) qsort(out, (size_t)cnt, sizeof(int64_t), cmp_i64);
+    return cnt;
+}
+
+/* Maximum |P_i| over all i (to size buffers). */
+int64_t orc_max_degree(int64_t n, const float *x, const float *y, const float *z, const float *h,
+                       int use_grid)
+{
+    orc_grid g;
+    memset(&g, 0, sizeof g);
+    if (use_grid) grid_build(&g, n, x, y, z, h);
+    int64_t mx = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(max : mx)
+    for (int64_t i = 0; i < n; i++) {
+        int64_t c = neighbours_of(&g, use_grid, n, x, y, z, h, i, NULL, 0);
+        if (c > mx) mx = c;
+    }
+    if (use_grid) grid_free(&g);
+    return mx;
+}
+
+/* Pair set as CSR: offs[n+1], nbr[offs[i]..offs[i+1]) ascending.
+ * Call with nbr == NULL to get the counts in offs only. */
+void orc_pairs_csr(int64_t n, const float *x, const float *y, const float *z, const float *h, int use_grid,
+                   int64_t *offs, int64_t *nbr)
+{
+    orc_grid g;
+    memset(&g, 0, sizeof g);
+    if (use_grid) grid_build(&g, n, x, y, z, h);
+    if (nbr == NULL) {
+        offs[0] = 0;
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; i++) offs[i + 1] = neighbours_of(&g, use_grid, n, x, y, z, h, i, NULL, 0);
+        for (int64_t i = 0; i < n; i++) offs[i + 1] += offs[i];
+    } else {
+#pragma omp parallel for schedule(dynamic, 256)
+        for (int64_t i = 0; i < n; i++)
+            neighbours_of(&g, use_grid, n, x, y, z, h, i, nbr + offs[i], offs[i + 1] - offs[i]);
+    }
+    if (use_grid) grid_free(&g);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Cluster-pair list (Sec. II-A)                                              */
+/* ------------------------------------------------------------------------- */
+
+/* Super-cluster s holds particles [64 s, 64 s + 64); its i-clusters are the
+ * cs-sized runs inside it (bit c of a mask = i-cluster c of the super-cluster).
+ * Its list holds every j-cluster that contains a j with (i, j) in P for some i
+ * of the super-cluster, ascending, with bit c set iff such an i lies in
+ * i-cluster c. */
+typedef struct {
+    int64_t count;
+    uint32_t *j;
+    uint16_t *mask;
+} orc_sc_list;
+
+static void sc_list_one(const orc_grid *g, int use_grid, int64_t n, const float *x, const float *y,
+                        const float *z, const float *h, int cs, int64_t s, uint16_t *marks,
+                        int64_t *touched, int64_t *nb, int64_t nbcap, orc_sc_list *out)
+{
+    int64_t nt = 0;
+    for (int64_t i = 64 * s; i < 64 * s + 64 && i < n; i++) {
+        int c = (int)((i - 64 * s) / cs);
+        int64_t cnt = neighbours_of(g, use_grid, n, x, y, z, h, i, nb, nbcap);
+        if (cnt > nbcap) abort(); /* caller sizes nbcap from orc_max_degree */
+        for (int64_t k = 0; k < cnt; k++) {
+            int64_t cj = nb[k] / cs;
+            if (marks[cj] == 0) touched[nt++] = cj;
+            marks[cj] |= (uint16_t)(1u << c);
+        }
+    }
+    qsort(touched, (size_t)nt, sizeof(int64_t), cmp_i64);
+    out->count = nt;
+    out->j = (uint32_t *)malloc((size_t)(nt > 0 ? nt : 1) * sizeof(uint32_t));
+    out->mask = (uint16_t *)malloc((size_t)(nt > 0 ? nt : 1) * sizeof(uint16_t));
+    for (int64_t k = 0; k < nt; k++) {
+        out->j[k] = (uint32_t)touched[k];
+        out->mask[k] = marks[touched[k]];
+        marks[touched[k]] = 0;
+    }
+}
+
+/* Builds the list for the super-clusters in sc_ids (or all if sc_ids == NULL,
+ * nsel = number of super-clusters). Results are returned as CSR over the
+ * selection: *out_offs (nsel+1), *out_j, *out_mask, malloc'ed here and
+ * released with orc_free. Returns 0, or -1 on allocation failure. */
+int orc_cluster_list(int64_t n, const float *x, const float *y, const float *z, const float *h, int cs,
+                     int use_grid, int64_t nsel, const int64_t *sc_ids, int64_t max_degree,
+                     int64_t **out_offs, uint32_t **out_j, uint16_t **out_mask)
+{
+    int64_t nclu = (n + cs - 1) / cs;
+    orc_grid g;
+    memset(&g, 0, sizeof g);
+    if (use_grid) grid_build(&g, n, x, y, z, h);
+    orc_sc_list *lists = (orc_sc_list *)calloc((size_t)(nsel > 0 ? nsel : 1), sizeof(orc_sc_list));
+    int64_t nbcap = max_degree > 0 ? max_degree : 1;
+#pragma omp parallel
+    {
+        uint16_t *marks = (uint16_t *)calloc((size_t)(nclu > 0 ? nclu : 1), sizeof(uint16_t));
+        int64_t *touched = (int64_t *)malloc((size_t)(nclu > 0 ? nclu : 1) * sizeof(int64_t));
+        int64_t *nb = (int64_t *)malloc((size_t)nbcap * sizeof(int64_t));
+#pragma omp for schedule(dynamic, 4)
+        for (int64_t k = 0; k < nsel; k++) {
+            int64_t s = sc_ids ? sc_ids[k] : k;
+            sc_list_one(&g, use_grid, n, x, y, z, h, cs, s, marks, touched, nb, nbcap, &lists[k]);
+        }
+        free(marks);
+        free(touched);
+        free(nb);
+    }
+    if (use_grid) grid_free(&g);
+    int64_t *offs = (int64_t *)malloc((size_t)(nsel + 1) * sizeof(int64_t));
+    offs[0] = 0;
+    for (int64_t k = 0; k < nsel; k++) offs[k + 1] = offs[k] + lists[k].count;
+    uint32_t *jj = (uint32_t *)malloc((size_t)(offs[nsel] > 0 ? offs[nsel] : 1) * sizeof(uint32_t));
+    uint16_t *mm = (uint16_t *)malloc((size_t)(offs[nsel] > 0 ? offs[nsel] : 1) * sizeof(uint16_t));
+    for (int64_t k = 0; k < nsel; k++) {
+        memcpy(jj + offs[k], lists[k].j, (size_t)lists[k].count * sizeof(uint32_t));
+        memcpy(mm + offs[k], lists[k].mask, (size_t)lists[k].count * sizeof(uint16_t));
+        free(lists[k].j);
+        free(lists[k].mask);
+    }
+    free(lists);
+    *out_offs = offs;
+    *out_j = jj;
+    *out_mask = mm;
+    return 0;
+}
+
+void orc_free(void *p) { free(p); }
+
+/* ------------------------------------------------------------------------- */
+/* Nibble encoding (Sec. II-B, Tables I and II; layout Sec. II-C)            */
+/* ------------------------------------------------------------------------- */
+
+/* Number of hexadecimal digits of v >= 1. */
+static int nibbles_of(uint32_t v)
+{
+    int k = 0;
+    while (v) {
+        k++;
+        v >>= 4;
+    }
+    return k;
+}
+
+/* One block of `count` (<= w) difference values, in symbols:
+ *   bits[k]  = 1 iff v_k != 1 (Table I: the bitmask marks the non-one values)
+ *   info     = one nibble per non-one value, in order: v + 6 for v in [2, 9],
+ *              otherwise (number of data nibbles) - 1
+ *   data     = for every value above 9, its hexadecimal digits, most
+ *              significant first, in order.
+ * Returns 0, or -1 if a value is 0 (a sorted unique list never has one). */
+int orc_encode_block_symbols(const uint32_t *v, int count, uint8_t *bits, uint8_t *info, int *ninfo,
+                             uint8_t *data, int *ndata)
+{
+    int ni = 0, nd = 0;
+    for (int k = 0; k < count; k++) {
+        uint32_t val = v[k];
+        if (val == 0) return -1;
+        if (val == 1) {
+            bits[k] = 0;
+            continue;
+        }
+        bits[k] = 1;
+        if (val <= 9) {
+            info[ni++] = (uint8_t)(val + 6);
+        } else {
+            int nn = nibbles_of(val);
+            info[ni++] = (uint8_t)(nn - 1);
+            for (int d = nn - 1; d >= 0; d--) data[nd++] = (uint8_t)((val >> (4 * d)) & 0xFu);
+        }
+    }
+    *ninfo = ni;
+    *ndata = nd;
+    return 0;
+}
+
+/* Size in 4-byte words of one super-cluster's stream.
+ *   nsub = 64 / cs i-clusters; mask bytes per entry = 2 if nsub == 16 else 1.
+ *   mask area: n_j mask entries, padded to 4 bytes.
+ *   uncompressed: n_j u32 j-cluster indices.
+ *   compressed: per block of 64 differences (first difference taken from -1):
+ *     8-byte bitmask (bit k = lane k), then the info nibbles and the data
+ *     nibbles as one nibble stream (nibble t in byte t/2, low half first),
+ *     padded to 4 bytes. */
+static int64_t mask_bytes_per_entry(int cs) { return (64 / cs == 16) ? 2 : 1; }
+
+int64_t orc_encode_sc(int64_t nj, const uint32_t *j, const uint16_t *mask, int cs, int compress,
+                      uint32_t *out /* may be NULL to size */)
+{
+    int64_t mb = mask_bytes_per_entry(cs);
+    int64_t mwords = (nj * mb + 3) / 4;
+    int64_t w = 0;
+    if (out) {
+        memset(out, 0, (size_t)mwords * 4);
+        uint8_t *mbytes = (uint8_t *)out;
+        for (int64_t k = 0; k < nj; k++) {
+            if (mb == 2) {
+                mbytes[2 * k] = (uint8_t)(mask[k] & 0xFF);
+                mbytes[2 * k + 1] = (uint8_t)(mask[k] >> 8);
+            } else {
+                mbytes[k] = (uint8_t)mask[k];
+            }
+        }
+    }
+    w = mwords;
+    if (!compress) {
+        if (out)
+            for (int64_t k = 0; k < nj; k++) out[w + k] = j[k];
+        return w + nj;
+    }
+    uint32_t v[64];
+    uint8_t bits[64], info[64], data[64 * 8];
+    for (int64_t b0 = 0; b0 < nj; b0 += 64) {
+        int cnt = (int)(nj - b0 < 64 ? nj - b0 : 64);
+        for (int k = 0; k < cnt; k++) {
+            int64_t idx = b0 + k;
+            uint32_t prev = idx == 0 ? 0xFFFFFFFFu : j[idx - 1]; /* j_{-1} = -1 */
+            v[k] = j[idx] - prev;
+        }
+        int ni, nd;
+        if (orc_encode_block_symbols(v, cnt, bits, info, &ni, data, &nd) != 0) return -1;
+        int64_t nib = ni + nd;
+        int64_t seg_words = 2 + (nib + 7) / 8;
+        if (out) {
+            uint64_t m = 0;
+            for (int k = 0; k < cnt; k++) m |= (uint64_t)bits[k] << k;
+            uint32_t *seg = out + w;
+            memset(seg, 0, (size_t)seg_words * 4);
+            seg[0] = (uint32_t)(m & 0xFFFFFFFFu);
+            seg[1] = (uint32_t)(m >> 32);
+            uint8_t *stream = (uint8_t *)(seg + 2);
+            for (int64_t t = 0; t < nib; t++) {
+                uint8_t nbl = t < ni ? info[t] : data[t - ni];
+                stream[t / 2] |= (uint8_t)(nbl << (4 * (t % 2)));
+            }
+        }
+        w += seg_words;
+    }
+    return w;
+}
+
+/* Inverse of orc_encode_sc. Returns words consumed, or -1 on a malformed
+ * stream. */
+int64_t orc_decode_sc(const uint32_t *in, int64_t nj, int cs, int compress, uint32_t *j, uint16_t *mask)
+{
+    int64_t mb = mask_bytes_per_entry(cs);
+    int64_t mwords = (nj * mb + 3) / 4;
+    const uint8_t *mbytes = (const uint8_t *)in;
+    for (int64_t k = 0; k < nj; k++)
+        mask[k] = mb == 2 ? (uint16_t)(mbytes[2 * k] | (mbytes[2 * k + 1] << 8)) : mbytes[k];
+    int64_t w = mwords;
+    if (!compress) {
+        for (int64_t k = 0; k < nj; k++) j[k] = in[w + k];
+        return w + nj;
+    }
+    uint32_t prev = 0xFFFFFFFFu;
+    for (int64_t b0 = 0; b0 < nj; b0 += 64) {
+        int cnt = (int)(nj - b0 < 64 ? nj - b0 : 64);
+        const uint32_t *seg = in + w;
+        uint64_t m = (uint64_t)seg[0] | ((uint64_t)seg[1] << 32);
+        const uint8_t *stream = (const uint8_t *)(seg + 2);
+        int ni = 0;
+        for (int k = 0; k < cnt; k++) ni += (int)((m >> k) & 1u);
+        int64_t ti = 0, td = ni;
+        for (int k = 0; k < cnt; k++) {
+            uint32_t val = 1;
+            if ((m >> k) & 1u) {
+                uint32_t inf = (stream[ti / 2] >> (4 * (ti % 2))) & 0xFu;
+                ti++;
+                if (inf >= 8) {
+                    val = inf - 6;
+                } else {
+                    val = 0;
+                    for (uint32_t d = 0; d <= inf; d++) {
+                        val = (val << 4) | ((stream[td / 2] >> (4 * (td % 2))) & 0xFu);
+                        td++;
+                    }
+                    if (val < 10) return -1;
+                }
+            }
+            prev = prev + val;
+            j[b0 + k] = prev;
+        }
+        w += 2 + (td + 7) / 8;
+    }
+    return w;
+}
+
+/* ------------------------------------------------------------------------- */
+/* SPH density (Sec. II-D, Listing 1) in FP64                                 */
+/* ------------------------------------------------------------------------- */
+
+/* M4 cubic spline with compact support h, 3-D normalisation 8/(pi h^3):
+ *   W = 8/(pi h^3) * (1 - 6 q^2 + 6 q^3)  for 0 <= q < 1/2
+ *     = 8/(pi h^3) * 2 (1 - q)^3          for 1/2 <= q < 1
+ *     = 0                                  otherwise, q = r/h. */
+double orc_kernel_w(double r, double h)
+{
+    double q = r / h;
+    double norm = 8.0 / (M_PI * h * h * h);
+    if (q < 0.5) return norm * (1.0 - 6.0 * q * q + 6.0 * q * q * q);
+    if (q < 1.0) {
+        double t = 1.0 - q;
+        return norm * 2.0 * t * t * t;
+    }
+    return 0.0;
+}
+
+/* rho_i = m_i W(0, h_i) + sum over j != i with d2 < f32(h_i^2) of m_j W(r_ij, h_i),
+ * r_ij from the exact FP64 differences of the FP32 coordinates. The set of j
+ * is decided by the same FP32 test as the pair set. nnb_i = size of that set.
+ * m == NULL means unit masses. */
+void orc_density(int64_t n, const float *x, const float *y, const float *z, const float *h, const float *m,
+                 int use_grid, double *rho, int32_t *nnb)
+{
+    orc_grid g;
+    memset(&g, 0, sizeof g);
+    if (use_grid) grid_build(&g, n, x, y, z, h);
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t i = 0; i < n; i++) {
+        double mi = m ? (double)m[i] : 1.0;
+        double acc = mi * orc_kernel_w(0.0, (double)h[i]);
+        int32_t cnt = 0;
+        int64_t cx = 0, cy = 0, cz = 0, r0 = 0, r1 = 0;
+        if (use_grid) {
+            cx = grid_cell1(&g, 0, x[i]);
+            cy = grid_cell1(&g, 1, y[i]);
+            cz = grid_cell1(&g, 2, z[i]);
+            r0 = -1;
+            r1 = 1;
+        }
+        for (int64_t az = cz + r0; az <= cz + r1; az++) {
+            for (int64_t ay = cy + r0; ay <= cy + r1; ay++) {
+                for (int64_t ax = cx + r0; ax <= cx + r1; ax++) {
+                    int64_t k0 = 0, k1 = n;
+                    if (use_grid) {
+                        if (az < 0 || az >= g.dim[2] || ay < 0 || ay >= g.dim[1] || ax < 0 || ax >= g.dim[0])
+                            continue;
+                        int64_t c = (az * g.dim[1] + ay) * g.dim[0] + ax;
+                        k0 = g.start[c];
+                        k1 = g.start[c + 1];
+                    }
+                    for (int64_t k = k0; k < k1; k++) {
+                        int64_t j = use_grid ? g.idx[k] : k;
+                        if (j == i) continue;
+                        if (!orc_in_own_radius(x[i], y[i], z[i], h[i], x[j], y[j], z[j])) continue;
+                        double dx = (double)x[j] - (double)x[i];
+                        double dy = (double)y[j] - (double)y[i];
+                        double dz = (double)z[j] - (double)z[i];
+                        double r = sqrt(dx * dx + dy * dy + dz * dz);
+                        double mj = m ? (double)m[j] : 1.0;
+                        acc += mj * orc_kernel_w(r, (double)h[i]);
+                        cnt++;
+                    }
+                }
+            }
+        }
+        rho[i] = acc;
+        if (nnb) nnb[i] = cnt;
+    }
+    if (use_grid) grid_free(&g);
+}
+
+int orc_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
