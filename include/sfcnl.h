@@ -1,0 +1,162 @@
+/*
+ * sfcnl -- compressed space-filling-curve cluster neighbour lists on gfx950.
+ *
+ * C ABI of the GPU library. The operations follow "GPU-Native Compressed
+ * Neighbor Lists with a Space-Filling-Curve Data Layout":
+ *   sfc_sort        Hilbert keys and SFC order of the particles (Sec. II-A)
+ *   sfc_gather      particle fields into SFC order (Sec. II-A, II-C)
+ *   build_clusters  fixed-size clusters of SFC-consecutive particles and their
+ *                   bounding boxes (Sec. II-A)
+ *   build_nlist     octree traversal, cluster-pair list with per-i-cluster
+ *                   bitmasks, nibble compression (Sec. II-A, II-B, II-C)
+ *   nlist_pass      decompress and compute the SPH density sum and neighbour
+ *                   counts (Sec. II-A "neighbor pass", Sec. II-D, Listing 1)
+ *
+ * Conventions shared by every call:
+ *   - d_* arguments are device pointers, h_* arguments are host pointers. The
+ *     caller owns every buffer; the library only borrows them for the call.
+ *   - Work is enqueued on the context's HIP stream. Calls return as soon as
+ *     the work is enqueued, except build_nlist, which waits for its own
+ *     kernels to read back list size and error flags.
+ *   - Every call returns an sfcnl status (0 on success, negative on failure)
+ *     and never throws. sfcnl_last_error() gives a text for the last failure
+ *     on that context.
+ *   - Particle indices are 32-bit: n must be below 2^31.
+ *   - Errors found on the device (non-finite coordinates, radii <= 0 or
+ *     non-finite) are latched in the context and returned as SFCNL_E_INPUT by
+ *     the next build_nlist or sfcnl_sync.
+ */
+#ifndef SFCNL_H
+#define SFCNL_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SFCNL_OK 0
+#define SFCNL_E_ARG (-1)      /* bad argument; nothing was enqueued */
+#define SFCNL_E_INPUT (-2)    /* non-finite position or bad radius found on the device */
+#define SFCNL_E_CAPACITY (-3) /* output or workspace too small; required sizes reported */
+#define SFCNL_E_HIP (-4)      /* a HIP runtime call failed */
+
+/* Super-cluster size: 64 particles, one wavefront (Sec. II-A). */
+#define SFCNL_SC_SIZE 64
+/* Hilbert key resolution: 21 bits per axis, 63-bit keys. */
+#define SFCNL_KEY_BITS 21
+
+typedef struct sfcnl_ctx_s *sfcnl_ctx;
+
+/* Creates a context bound to `device` and `stream` (a hipStream_t, NULL for
+ * the null stream). Allocates a few KiB of device status memory and pinned
+ * host memory for the read-back of build_nlist. */
+int sfcnl_create(sfcnl_ctx *out, int device, void *stream);
+void sfcnl_destroy(sfcnl_ctx ctx);
+/* Re-binds the context to another stream of the same device. */
+int sfcnl_set_stream(sfcnl_ctx ctx, void *stream);
+const char *sfcnl_last_error(sfcnl_ctx ctx);
+/* Waits for the stream and returns the latched device-side error, if any
+ * (the latch is cleared). */
+int sfcnl_sync(sfcnl_ctx ctx);
+/* Library version string. */
+const char *sfcnl_version(void);
+
+/* ---- 1. SFC order (Sec. II-A) ------------------------------------------
+ * Positions are quantised to 21 bits per axis inside h_box = {xmin, xmax,
+ * ymin, ymax, zmin, zmax} (host array; max > min on every axis):
+ *   q = trunc(f32(f32(x - xmin) * s)), s = f32(2^21 / (xmax - xmin)),
+ *   clamped to [0, 2^21 - 1],
+ * and mapped to a 63-bit Hilbert key (Skilling's transpose form, x the most
+ * significant axis of each 3-bit digit). The particles are then ordered by key
+ * with a stable sort (ties keep input order).
+ *   d_keys_out [n] u64: sorted keys.
+ *   d_perm_out [n] u32: perm[k] = input index of the k-th particle in order.
+ *   d_ws / ws_bytes: scratch of at least sfc_sort_workspace(n) bytes. */
+int sfc_sort_workspace(int64_t n, size_t *ws_bytes);
+int sfc_sort(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y, const float *d_z,
+             const float *h_box, uint64_t *d_keys_out, uint32_t *d_perm_out, void *d_ws, size_t ws_bytes);
+
+/* out[f][k] = in[f][perm[k]] for nfields (1..8) float arrays of length n.
+ * h_in / h_out are host arrays of device pointers; out must not alias in. */
+int sfc_gather(sfcnl_ctx ctx, int64_t n, const uint32_t *d_perm, int nfields, const float *const *h_in,
+               float *const *h_out);
+
+/* ---- 2. Clusters (Sec. II-A) ---------------------------------------------
+ * Cluster c holds SFC-ordered particles [cs*c, min(cs*c + cs, n)). For each
+ * cluster: d_bbox_out[8c .. 8c+7] = {lo.x, lo.y, lo.z, max h, hi.x, hi.y,
+ * hi.z, 0} (exact FP32 min / max). cluster_size must be 8. Inputs must be in
+ * SFC order. Also checks inputs (latched as SFCNL_E_INPUT). */
+int build_clusters(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y, const float *d_z,
+                   const float *d_h, int cluster_size, float *d_bbox_out);
+
+/* ---- 3. Neighbour list (Sec. II-A, II-B, II-C) ---------------------------
+ * Pair set: (i, j) with i != j and d2 < f32(max(h_i, h_j)^2), where
+ * dx = f32(x_j - x_i) (likewise y, z) and d2 = fma(dz, dz, fma(dy, dy, dx*dx)).
+ * Super-cluster s = particles [64 s, 64 s + 64) = i-clusters 8 s .. 8 s + 7.
+ * Its list holds every j-cluster containing a j paired with some i of s, in
+ * ascending order, each with an 8-bit mask whose bit c is set iff some i of
+ * i-cluster 8 s + c has a pair in the j-cluster.
+ *
+ * Output layout (all little-endian 32-bit words):
+ *   d_sc_info [n_sc][2] u32: {word offset into the pool, n_j}, n_sc = ceil(n / 64).
+ *   pool at that offset: n_j mask bytes, padded to 4 bytes; then
+ *     compress == 0: n_j u32 j-cluster indices;
+ *     compress == 1: per block of 64 index differences (the first from -1):
+ *       u64 bitmask (bit k set iff difference k is not 1), then one info
+ *       nibble per set bit (v + 6 for v in [2, 9], else number of data
+ *       nibbles - 1), then the data nibbles of every value above 9, most
+ *       significant first; nibble t in byte t/2, low half first; padded to
+ *       4 bytes (Sec. II-B, Table I; segments one wavefront wide, Sec. II-C).
+ * Super-clusters are laid out in order, so the pool is deterministic.
+ *
+ * Inputs: SFC-ordered d_keys (from sfc_sort), positions, radii, and the
+ * cluster boxes of build_clusters. opts:
+ *   cluster_size  must be 8.
+ *   compress      0 or 1.
+ *   leaf_bucket   octree leaves hold at most this many particles (8..256).
+ *   max_j_per_sc  capacity of the per-super-cluster staging list.
+ * Workspace: at least build_nlist_workspace(n, opts) bytes.
+ * Returns SFCNL_OK, or SFCNL_E_CAPACITY when the pool (pool_bytes) or the
+ * staging list is too small: then *h_used_bytes is the pool size needed and
+ * *h_max_nj the largest list length, and a retry with enough room yields the
+ * identical list. On success *h_used_bytes is the pool size used. Waits for
+ * the stream. */
+typedef struct {
+    int cluster_size;
+    int compress;
+    int leaf_bucket;
+    int max_j_per_sc;
+} sfcnl_nlist_opts;
+
+int build_nlist_workspace(int64_t n, const sfcnl_nlist_opts *opts, size_t *ws_bytes);
+int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_x, const float *d_y,
+                const float *d_z, const float *d_h, const float *d_bbox, const sfcnl_nlist_opts *opts,
+                void *d_ws, size_t ws_bytes, uint32_t *d_sc_info, uint32_t *d_pool, size_t pool_bytes,
+                size_t *h_used_bytes, int64_t *h_max_nj);
+
+/* ---- 4. Neighbour pass (Sec. II-A, Sec. II-D Listing 1) ------------------
+ * Decompresses each super-cluster's list and evaluates every 8x8 particle
+ * tile of a listed (j-cluster, set mask bit) pair:
+ *   rho_i = m_i W(0, h_i) + sum_{j != i, d2 < f32(h_i^2)} m_j W(r_ij, h_i)
+ *   nnb_i = number of such j,
+ * W the M4 cubic spline of compact support h (3-D norm 8 / (pi h^3)), in
+ * FP32. d_m == NULL means unit masses; d_nnb may be NULL. Outputs in SFC
+ * order. */
+int nlist_pass(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, const uint32_t *d_sc_info,
+               const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z,
+               const float *d_h, const float *d_m, float *d_rho, int32_t *d_nnb);
+
+/* Decodes the whole list on the device into flat arrays: super-cluster s's
+ * entries go to [d_offsets[s], d_offsets[s] + n_j), with d_offsets the
+ * exclusive prefix sum of n_j (caller-computed, n_sc + 1 entries). Used to
+ * check the device decoder on its own. */
+int nlist_decode(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, const uint32_t *d_sc_info,
+                 const uint32_t *d_pool, const uint32_t *d_offsets, uint32_t *d_j, uint16_t *d_mask);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SFCNL_H */

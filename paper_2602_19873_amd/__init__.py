@@ -1,0 +1,252 @@
+"""Compressed SFC cluster neighbour lists on MI355X (gfx950).
+
+Python binding of libsfcnl.so. Functions carry the names of the C ABI and only
+marshal arguments: every step runs in the library's HIP kernels. PyTorch
+provides device memory and the stream.
+
+Method: "GPU-Native Compressed Neighbor Lists with a Space-Filling-Curve Data
+Layout" -- Hilbert order (Sec. II-A), 8-particle clusters and 64-particle
+super-clusters (Sec. II-A), octree traversal with per-particle radii
+(Sec. II-A), nibble compression (Sec. II-B, II-C) and the neighbour pass
+(Sec. II-A, II-D).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _lib
+
+__all__ = ["Context", "NeighbourList", "SfcnlError", "sfc_sort", "sfc_gather", "build_clusters",
+           "build_nlist", "nlist_pass", "nlist_decode", "Pipeline", "SC_SIZE", "CLUSTER_SIZE"]
+
+SC_SIZE = 64
+CLUSTER_SIZE = 8
+
+
+class SfcnlError(RuntimeError):
+    def __init__(self, code: int, msg: str):
+        super().__init__("sfcnl error %d: %s" % (code, msg))
+        self.code = code
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _check_f32(t, n, name):
+    if t.dtype != torch.float32 or not t.is_cuda or not t.is_contiguous() or t.numel() != n:
+        raise ValueError("%s must be a contiguous float32 device tensor of %d elements" % (name, n))
+
+
+class Context:
+    """A library context bound to one device and (by default) torch's current stream."""
+
+    def __init__(self, device: int | None = None, stream: torch.cuda.Stream | None = None):
+        self.lib = _lib.load()
+        self.device = torch.cuda.current_device() if device is None else int(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        h = C.c_void_p()
+        rc = self.lib.sfcnl_create(C.byref(h), self.device, C.c_void_p(self.stream.cuda_stream))
+        if rc != 0:
+            raise SfcnlError(rc, "sfcnl_create failed")
+        self.handle = h
+
+    def check(self, rc):
+        if rc != 0:
+            raise SfcnlError(rc, self.lib.sfcnl_last_error(self.handle).decode())
+
+    def sync(self):
+        self.check(self.lib.sfcnl_sync(self.handle))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.sfcnl_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def empty(self, shape, dtype):
+        return torch.empty(shape, dtype=dtype, device="cuda:%d" % self.device)
+
+
+def sfc_sort_workspace(n: int) -> int:
+    b = C.c_size_t()
+    if _lib.load().sfc_sort_workspace(n, C.byref(b)) != 0:
+        raise SfcnlError(_lib.E_ARG, "sfc_sort_workspace")
+    return b.value
+
+
+def sfc_sort(ctx: Context, x, y, z, box, keys=None, perm=None, ws=None):
+    """Hilbert keys and stable SFC order. Returns (sorted keys u64 as int64, perm int32)."""
+    n = x.numel()
+    for t, nm in ((x, "x"), (y, "y"), (z, "z")):
+        _check_f32(t, n, nm)
+    keys = ctx.empty(n, torch.int64) if keys is None else keys
+    perm = ctx.empty(n, torch.int32) if perm is None else perm
+    need = sfc_sort_workspace(n)
+    ws = ctx.empty(max(need, 1), torch.uint8) if ws is None or ws.numel() < need else ws
+    hb = (C.c_float * 6)(*[float(v) for v in box])
+    ctx.check(ctx.lib.sfc_sort(ctx.handle, n, _ptr(x), _ptr(y), _ptr(z), hb, _ptr(keys), _ptr(perm), _ptr(ws),
+                               ws.numel()))
+    return keys, perm
+
+
+def sfc_gather(ctx: Context, perm, fields, outs=None):
+    n = perm.numel()
+    nf = len(fields)
+    outs = [torch.empty_like(f) for f in fields] if outs is None else outs
+    for f in list(fields) + list(outs):
+        _check_f32(f, n, "field")
+    ins = (C.c_void_p * nf)(*[f.data_ptr() for f in fields])
+    ous = (C.c_void_p * nf)(*[o.data_ptr() for o in outs])
+    ctx.check(ctx.lib.sfc_gather(ctx.handle, n, _ptr(perm), nf, ins, ous))
+    return outs
+
+
+def build_clusters(ctx: Context, x, y, z, h, cluster_size: int = CLUSTER_SIZE, bbox=None):
+    """Per-cluster boxes (n_clusters x 8 float32: lo xyz, max h, hi xyz, 0)."""
+    n = x.numel()
+    nc = (n + cluster_size - 1) // cluster_size
+    bbox = ctx.empty((max(nc, 1), 8), torch.float32) if bbox is None else bbox
+    ctx.check(ctx.lib.build_clusters(ctx.handle, n, _ptr(x), _ptr(y), _ptr(z), _ptr(h), cluster_size, _ptr(bbox)))
+    return bbox
+
+
+@dataclass
+class NeighbourList:
+    n: int
+    cluster_size: int
+    compress: bool
+    sc_info: torch.Tensor     # (n_sc, 2) int32 view of u32 {word offset, n_j}
+    pool: torch.Tensor        # int32 view of u32 words
+    used_bytes: int
+    max_nj: int
+
+    @property
+    def n_sc(self) -> int:
+        return (self.n + SC_SIZE - 1) // SC_SIZE
+
+    def bytes_per_particle(self) -> float:
+        return (self.used_bytes + 8 * self.n_sc) / max(self.n, 1)
+
+
+def _opts(cluster_size, compress, leaf_bucket, max_j_per_sc):
+    return _lib.NlistOpts(cluster_size, int(bool(compress)), leaf_bucket, max_j_per_sc)
+
+
+def build_nlist_workspace(n, cluster_size=CLUSTER_SIZE, compress=True, leaf_bucket=64, max_j_per_sc=512) -> int:
+    b = C.c_size_t()
+    o = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc)
+    if _lib.load().build_nlist_workspace(n, C.byref(o), C.byref(b)) != 0:
+        raise SfcnlError(_lib.E_ARG, "build_nlist_workspace")
+    return b.value
+
+
+def build_nlist(ctx: Context, keys, x, y, z, h, bbox, compress: bool = True, leaf_bucket: int = 64,
+                max_j_per_sc: int = 512, cluster_size: int = CLUSTER_SIZE, pool=None, ws=None, sc_info=None,
+                grow: bool = True):
+    """Builds the compressed cluster-pair list. Grows the staging list and the
+    pool and retries when the library reports they are too small (unless
+    grow=False, which raises)."""
+    n = x.numel()
+    nsc = (n + SC_SIZE - 1) // SC_SIZE
+    sc_info = ctx.empty((max(nsc, 1), 2), torch.int32) if sc_info is None else sc_info
+    if pool is None:
+        pool = ctx.empty(max(1024, 5 * n), torch.int32)
+    while True:
+        o = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc)
+        need = build_nlist_workspace(n, cluster_size, compress, leaf_bucket, max_j_per_sc)
+        if ws is None or ws.numel() < need:
+            ws = ctx.empty(max(need, 1), torch.uint8)
+        used = C.c_size_t()
+        maxnj = C.c_int64()
+        rc = ctx.lib.build_nlist(ctx.handle, n, _ptr(keys), _ptr(x), _ptr(y), _ptr(z), _ptr(h), _ptr(bbox),
+                                 C.byref(o), _ptr(ws), ws.numel(), _ptr(sc_info), _ptr(pool), pool.numel() * 4,
+                                 C.byref(used), C.byref(maxnj))
+        if rc == _lib.E_CAPACITY and grow:
+            if maxnj.value > max_j_per_sc:
+                max_j_per_sc = int(maxnj.value)
+            if used.value > pool.numel() * 4:
+                pool = ctx.empty(used.value // 4 + 1024, torch.int32)
+            continue
+        ctx.check(rc)
+        nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, used.value, maxnj.value)
+        nl.ws = ws
+        nl.max_j_per_sc = max_j_per_sc
+        return nl
+
+
+def nlist_pass(ctx: Context, nl: NeighbourList, x, y, z, h, m=None, rho=None, nnb=None, want_counts=True):
+    """SPH density (and neighbour counts) from the compressed list."""
+    n = nl.n
+    rho = ctx.empty(n, torch.float32) if rho is None else rho
+    if want_counts and nnb is None:
+        nnb = ctx.empty(n, torch.int32)
+    ctx.check(ctx.lib.nlist_pass(ctx.handle, n, nl.cluster_size, int(nl.compress), _ptr(nl.sc_info), _ptr(nl.pool),
+                                 _ptr(x), _ptr(y), _ptr(z), _ptr(h), _ptr(m), _ptr(rho),
+                                 _ptr(nnb) if want_counts else None))
+    return rho, nnb
+
+
+def nlist_decode(ctx: Context, nl: NeighbourList):
+    """Decodes the list on the device: (offsets int64 host, j uint32 numpy, mask uint16 numpy)."""
+    import numpy as np
+    info = nl.sc_info.cpu().numpy().view(np.uint32)
+    nj = info[:, 1].astype(np.int64)
+    offs = np.zeros(nl.n_sc + 1, dtype=np.int64)
+    np.cumsum(nj, out=offs[1:])
+    total = int(offs[-1])
+    d_offs = torch.from_numpy(offs[:-1].astype(np.int32)).to(nl.sc_info.device)
+    j = ctx.empty(max(total, 1), torch.int32)
+    m = ctx.empty(max(total, 1), torch.int16)
+    ctx.check(ctx.lib.nlist_decode(ctx.handle, nl.n, nl.cluster_size, int(nl.compress), _ptr(nl.sc_info),
+                                   _ptr(nl.pool), _ptr(d_offs), _ptr(j), _ptr(m)))
+    torch.cuda.synchronize(nl.sc_info.device)
+    return offs, j[:total].cpu().numpy().view(np.uint32), m[:total].cpu().numpy().view(np.uint16)
+
+
+class Pipeline:
+    """The whole path on one system with every buffer preallocated:
+    sfc_sort -> sfc_gather -> build_clusters -> build_nlist -> nlist_pass."""
+
+    def __init__(self, ctx: Context, n: int, box, compress: bool = True, leaf_bucket: int = 64,
+                 max_j_per_sc: int = 512, with_mass: bool = False):
+        self.ctx, self.n, self.box = ctx, n, tuple(float(v) for v in box)
+        self.compress, self.leaf_bucket, self.max_j_per_sc = compress, leaf_bucket, max_j_per_sc
+        nsc = (n + SC_SIZE - 1) // SC_SIZE
+        nc = (n + CLUSTER_SIZE - 1) // CLUSTER_SIZE
+        e = ctx.empty
+        self.keys, self.perm = e(max(n, 1), torch.int64), e(max(n, 1), torch.int32)
+        self.sort_ws = e(max(sfc_sort_workspace(n), 1), torch.uint8)
+        nf = 5 if with_mass else 4
+        self.sorted = [e(max(n, 1), torch.float32) for _ in range(nf)]
+        self.bbox = e((max(nc, 1), 8), torch.float32)
+        self.sc_info = e((max(nsc, 1), 2), torch.int32)
+        self.pool = e(max(1024, 6 * n), torch.int32)
+        self.ws = e(max(build_nlist_workspace(n, CLUSTER_SIZE, compress, leaf_bucket, max_j_per_sc), 1), torch.uint8)
+        self.rho, self.nnb = e(max(n, 1), torch.float32), e(max(n, 1), torch.int32)
+        self.nl = None
+
+    def step(self, x, y, z, h, m=None, want_counts=True):
+        ctx, n = self.ctx, self.n
+        sfc_sort(ctx, x, y, z, self.box, self.keys, self.perm, self.sort_ws)
+        fields = [x, y, z, h] + ([m] if m is not None else [])
+        outs = self.sorted[:len(fields)]
+        sfc_gather(ctx, self.perm, fields, outs)
+        xs, ys, zs, hs = outs[:4]
+        ms = outs[4] if m is not None else None
+        build_clusters(ctx, xs, ys, zs, hs, CLUSTER_SIZE, self.bbox)
+        nl = build_nlist(ctx, self.keys, xs, ys, zs, hs, self.bbox, self.compress, self.leaf_bucket,
+                         self.max_j_per_sc, pool=self.pool, ws=self.ws, sc_info=self.sc_info)
+        if nl.pool is not self.pool or nl.ws is not self.ws:  # grown on a retry: keep the larger buffers
+            self.pool, self.ws, self.max_j_per_sc = nl.pool, nl.ws, nl.max_j_per_sc
+        self.nl = nl
+        nlist_pass(ctx, nl, xs, ys, zs, hs, ms, self.rho, self.nnb if want_counts else None, want_counts)
+        return nl

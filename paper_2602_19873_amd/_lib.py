@@ -1,0 +1,73 @@
+"""ctypes declarations of libsfcnl.so (the C ABI of include/sfcnl.h).
+
+Loading fails loudly if the library has not been built: there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsfcnl.so")
+
+OK = 0
+E_ARG = -1
+E_INPUT = -2
+E_CAPACITY = -3
+E_HIP = -4
+
+SYMBOLS = [
+    "sfcnl_create", "sfcnl_destroy", "sfcnl_set_stream", "sfcnl_last_error", "sfcnl_sync", "sfcnl_version",
+    "sfc_sort_workspace", "sfc_sort", "sfc_gather", "build_clusters", "build_nlist_workspace", "build_nlist",
+    "nlist_pass", "nlist_decode",
+]
+
+
+class NlistOpts(C.Structure):
+    _fields_ = [("cluster_size", C.c_int), ("compress", C.c_int), ("leaf_bucket", C.c_int),
+                ("max_j_per_sc", C.c_int)]
+
+
+_lib = None
+
+
+def load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError("libsfcnl.so is not built (run __graft_entry__.build() or "
+                           "python paper_2602_19873_amd/build.py)")
+    lib = C.CDLL(LIB_PATH)
+    vp, i64, sz, i32 = C.c_void_p, C.c_int64, C.c_size_t, C.c_int
+    lib.sfcnl_create.argtypes = [C.POINTER(vp), i32, vp]
+    lib.sfcnl_create.restype = i32
+    lib.sfcnl_destroy.argtypes = [vp]
+    lib.sfcnl_destroy.restype = None
+    lib.sfcnl_set_stream.argtypes = [vp, vp]
+    lib.sfcnl_set_stream.restype = i32
+    lib.sfcnl_last_error.argtypes = [vp]
+    lib.sfcnl_last_error.restype = C.c_char_p
+    lib.sfcnl_sync.argtypes = [vp]
+    lib.sfcnl_sync.restype = i32
+    lib.sfcnl_version.argtypes = []
+    lib.sfcnl_version.restype = C.c_char_p
+    lib.sfc_sort_workspace.argtypes = [i64, C.POINTER(sz)]
+    lib.sfc_sort_workspace.restype = i32
+    lib.sfc_sort.argtypes = [vp, i64, vp, vp, vp, C.POINTER(C.c_float), vp, vp, vp, sz]
+    lib.sfc_sort.restype = i32
+    lib.sfc_gather.argtypes = [vp, i64, vp, i32, C.POINTER(vp), C.POINTER(vp)]
+    lib.sfc_gather.restype = i32
+    lib.build_clusters.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp]
+    lib.build_clusters.restype = i32
+    lib.build_nlist_workspace.argtypes = [i64, C.POINTER(NlistOpts), C.POINTER(sz)]
+    lib.build_nlist_workspace.restype = i32
+    lib.build_nlist.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, C.POINTER(NlistOpts), vp, sz, vp, vp, sz,
+                                C.POINTER(sz), C.POINTER(i64)]
+    lib.build_nlist.restype = i32
+    lib.nlist_pass.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.nlist_pass.restype = i32
+    lib.nlist_decode.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp]
+    lib.nlist_decode.restype = i32
+    _lib = lib
+    return lib

@@ -1,0 +1,83 @@
+// Context, error reporting and status read-back of the sfcnl library.
+#include <stdlib.h>
+#include <string.h>
+
+#include "internal.h"
+
+namespace sfcnl {
+
+int set_err(sfcnl_ctx ctx, int code, const char *fmt, ...) {
+    if (ctx) {
+        va_list ap;
+        va_start(ap, fmt);
+        vsnprintf(ctx->err, sizeof ctx->err, fmt, ap);
+        va_end(ap);
+    }
+    return code;
+}
+
+}  // namespace sfcnl
+
+using namespace sfcnl;
+
+extern "C" const char *sfcnl_version(void) { return "sfcnl 0.1 gfx950"; }
+
+extern "C" int sfcnl_create(sfcnl_ctx *out, int device, void *stream) {
+    if (!out) return SFCNL_E_ARG;
+    *out = nullptr;
+    sfcnl_ctx c = (sfcnl_ctx)calloc(1, sizeof(sfcnl_ctx_s));
+    if (!c) return SFCNL_E_ARG;
+    c->device = device;
+    c->stream = (hipStream_t)stream;
+    if (hipSetDevice(device) != hipSuccess) {
+        free(c);
+        return SFCNL_E_HIP;
+    }
+    if (hipMalloc((void **)&c->d_status, kStWords * sizeof(uint32_t)) != hipSuccess) {
+        free(c);
+        return SFCNL_E_HIP;
+    }
+    if (hipHostMalloc((void **)&c->h_status, kStWords * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+        (void)hipFree(c->d_status);
+        free(c);
+        return SFCNL_E_HIP;
+    }
+    memset(c->h_status, 0, kStWords * sizeof(uint32_t));
+    if (fill_u32(c, c->d_status, kStWords, 0) != SFCNL_OK || hipStreamSynchronize(c->stream) != hipSuccess) {
+        (void)hipHostFree(c->h_status);
+        (void)hipFree(c->d_status);
+        free(c);
+        return SFCNL_E_HIP;
+    }
+    *out = c;
+    return SFCNL_OK;
+}
+
+extern "C" void sfcnl_destroy(sfcnl_ctx ctx) {
+    if (!ctx) return;
+    (void)hipStreamSynchronize(ctx->stream);
+    (void)hipHostFree(ctx->h_status);
+    (void)hipFree(ctx->d_status);
+    free(ctx);
+}
+
+extern "C" int sfcnl_set_stream(sfcnl_ctx ctx, void *stream) {
+    if (!ctx) return SFCNL_E_ARG;
+    ctx->stream = (hipStream_t)stream;
+    return SFCNL_OK;
+}
+
+extern "C" const char *sfcnl_last_error(sfcnl_ctx ctx) { return ctx ? ctx->err : "null context"; }
+
+extern "C" int sfcnl_sync(sfcnl_ctx ctx) {
+    if (!ctx) return SFCNL_E_ARG;
+    SFCNL_HIP(ctx, hipMemcpyAsync(ctx->h_status, ctx->d_status, sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
+    SFCNL_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    uint32_t e = ctx->h_status[kStInputErr];
+    if (e) {
+        int rc = fill_u32(ctx, ctx->d_status + kStInputErr, 1, 0);
+        if (rc) return rc;
+        return set_err(ctx, SFCNL_E_INPUT, "input error flags 0x%x (1: non-finite position, 2: bad radius, 4: bad permutation)", e);
+    }
+    return SFCNL_OK;
+}

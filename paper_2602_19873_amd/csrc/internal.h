@@ -1,0 +1,139 @@
+// Internal declarations of the sfcnl GPU library (gfx950, wave64).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdarg.h>
+#include <stddef.h>
+#include <stdint.h>
+#include <stdio.h>
+
+#include "sfcnl.h"
+
+namespace sfcnl {
+
+constexpr int kWave = 64;
+constexpr int kScSize = SFCNL_SC_SIZE;   // particles per super-cluster
+constexpr int kCs = 8;                   // particles per cluster
+constexpr int kSub = kScSize / kCs;      // i-clusters per super-cluster
+
+// Status block words (device, mirrored into pinned host memory).
+enum StatusWord : int {
+    kStInputErr = 0,     // bit 0: non-finite coordinate, bit 1: bad radius
+    kStPoolOverflow = 1, // set if the pool is too small
+    kStMaxNj = 2,        // largest list length (atomicMax)
+    kStTotalLo = 3,      // total pool words (exclusive scan total)
+    kStScratch = 4,      // set if a staging list overflowed
+    kStTree = 5,         // octree invariant broken (internal error)
+    kStWords = 16
+};
+
+}  // namespace sfcnl
+
+struct sfcnl_ctx_s {
+    int device;
+    hipStream_t stream;
+    uint32_t *d_status;
+    uint32_t *h_status;
+    char err[512];
+};
+
+namespace sfcnl {
+
+int set_err(sfcnl_ctx ctx, int code, const char *fmt, ...);
+
+#define SFCNL_HIP(ctx, call)                                                                   \
+    do {                                                                                       \
+        hipError_t e_ = (call);                                                                \
+        if (e_ != hipSuccess)                                                                  \
+            return ::sfcnl::set_err(ctx, SFCNL_E_HIP, "%s failed: %s", #call, hipGetErrorString(e_)); \
+    } while (0)
+
+#define SFCNL_LAUNCHED(ctx) SFCNL_HIP(ctx, hipGetLastError())
+
+inline unsigned blocks_for(int64_t n, int per_block) { return (unsigned)((n + per_block - 1) / per_block); }
+
+inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+
+// Carves aligned sub-buffers out of a caller workspace.
+struct Carver {
+    char *base;
+    size_t used;
+    template <class T>
+    T *take(size_t count) {
+        used = align_up(used, 256);
+        T *p = reinterpret_cast<T *>(base ? base + used : nullptr);
+        used += count * sizeof(T);
+        return p;
+    }
+};
+
+// ---- device-wide exclusive scan of u32 (scan.hip) ----
+size_t scan_tmp_bytes(int64_t n);
+// out[i] = sum_{k<i} in[i]; *d_total = sum (may be null). in and out may alias.
+int scan_u32(sfcnl_ctx ctx, const uint32_t *in, uint32_t *out, int64_t n, uint32_t *d_total, void *tmp);
+// Fills n u32 words with a value (a kernel, so it can sit inside a captured graph).
+int fill_u32(sfcnl_ctx ctx, uint32_t *p, int64_t n, uint32_t v);
+
+// ---- pieces of build_nlist (octree.hip, traverse.hip) ----
+struct Octree {
+    int64_t n;
+    int bucket;
+    // per particle
+    int8_t *cdig;      // common 3-bit digits with the previous key (-1 for particle 0)
+    int8_t *lam;       // common digits of key[p] and key[p + bucket] (-1 if out of range)
+    int8_t *lleaf;     // octree level of the leaf holding p
+    uint32_t *node_at; // index of the first node starting at particle p (leaf starts)
+    // per node (capacity = n + 22 upper bound)
+    uint32_t *nfirst, *nend, *nesc;
+    uint8_t *nlevel, *nleaf, *nnchild;
+    uint32_t *nchild;  // 8 per node
+    uint32_t *nparent;
+    uint32_t *nvisit;
+    float4 *nbox;      // 2 per node: lo (x, y, z, hmax), hi (x, y, z, -)
+    uint32_t *d_nnodes;
+    void *scan_tmp;
+};
+
+void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket);
+int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x, const float *y,
+                 const float *z, const float *h);
+
+}  // namespace sfcnl
+
+// ---------------------------------------------------------------------------
+// Device helpers (wave64)
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ int sfc_lane() { return (int)__lane_id(); }
+
+__device__ __forceinline__ uint64_t sfc_lt_mask() { return (1ull << sfc_lane()) - 1ull; }
+
+__device__ __forceinline__ uint64_t sfc_ballot(bool p) { return (uint64_t)__ballot(p); }
+
+__device__ __forceinline__ int sfc_popc(uint64_t v) { return __popcll(v); }
+
+// Uniform-lane read (index must be wave-uniform).
+__device__ __forceinline__ uint32_t sfc_readlane(uint32_t v, int lane) {
+    return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+__device__ __forceinline__ float sfc_readlane_f(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+__device__ __forceinline__ uint32_t sfc_incl_scan(uint32_t v) {
+    const int l = sfc_lane();
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) {
+        uint32_t t = __shfl_up(v, d, 64);
+        if (l >= d) v += t;
+    }
+    return v;
+}
+
+// Common leading 3-bit digits of two 63-bit keys (21 if equal).
+__device__ __forceinline__ int sfc_common_digits(uint64_t a, uint64_t b) {
+    uint64_t x = a ^ b;
+    if (x == 0) return 21;
+    return (__clzll((long long)x) - 1) / 3;
+}

@@ -1,0 +1,505 @@
+// Clusters, octree traversal and compressed list encoding (Sec. II-A, II-B,
+// II-C).
+//
+// One wavefront builds the list of one super-cluster (64 particles = 8
+// i-clusters of 8). Lane (il, jl) = (lane / 8, lane % 8) holds particle il of
+// every i-cluster, so one 64-lane compare covers one 8x8 cluster pair.
+//
+// Traversal: depth-first from the root with an LDS stack; at an internal node
+// up to 8 lanes test the children's boxes against the super-cluster box and
+// push the survivors in reverse key order, so leaves come out in key order
+// and the list is sorted without a sort (Sec. II-A). At a leaf, the j-clusters
+// overlapping its particle range are tested 8 at a time: 64 lanes test 8
+// i-cluster boxes x 8 j-cluster boxes, then every surviving (i-cluster,
+// j-cluster) pair gets its 64 exact particle tests. Box tests are conservative
+// under FP32 rounding (rounding is monotone), so they never drop a pair the
+// exact test keeps; the masks are exact.
+//
+// The list is staged per super-cluster, its encoded size is computed on the
+// fly, a prefix sum places the super-clusters in order, and a second kernel
+// writes masks and nibble segments.
+#include "internal.h"
+
+namespace sfcnl {
+namespace {
+
+constexpr int kWavesPerBlock = 4;
+constexpr int kStackCap = 160;  // 1 + 7 * 21 pushes at most
+constexpr int kSegCap = 80;     // words of one 64-value segment: 2 + (64 + 512 + 7) / 8
+
+__device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned g) {
+    // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
+    // range of super-clusters so neighbouring ones share its L2
+    const unsigned per = g / 8, rem = g % 8, x = b % 8, i = b / 8;
+    return x < rem ? x * (per + 1) + i : rem * (per + 1) + (x - rem) * per + i;
+}
+
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+// Boxes carry .w of lo = largest radius inside. True if some particle pair
+// across the two boxes could satisfy d2 < max(h_i, h_j)^2.
+__device__ __forceinline__ bool boxes_near(float4 alo, float4 ahi, float4 blo, float4 bhi) {
+    float gx = fmaxf(fmaxf(blo.x - ahi.x, alo.x - bhi.x), 0.0f);
+    float gy = fmaxf(fmaxf(blo.y - ahi.y, alo.y - bhi.y), 0.0f);
+    float gz = fmaxf(fmaxf(blo.z - ahi.z, alo.z - bhi.z), 0.0f);
+    float gxx = gx * gx;
+    float d2 = __builtin_fmaf(gz, gz, __builtin_fmaf(gy, gy, gxx));
+    float ra = alo.w * alo.w, rb = blo.w * blo.w;
+    return d2 < fmaxf(ra, rb);
+}
+
+__device__ __forceinline__ uint32_t nibbles_of(uint32_t v) { return (32u - (uint32_t)__clz((int)v) + 3u) >> 2; }
+
+// ---------------------------------------------------------------------------
+// Clusters: bounding boxes and radius maxima, input checks.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void k_cluster_bbox(int64_t n, const float *__restrict__ x,
+                                                      const float *__restrict__ y, const float *__restrict__ z,
+                                                      const float *__restrict__ h, float4 *__restrict__ bbox,
+                                                      uint32_t *status) {
+    int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c >= (n + kCs - 1) / kCs) return;
+    float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
+    float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+    uint32_t bad = 0;
+#pragma unroll
+    for (int k = 0; k < kCs; k++) {
+        int64_t p = c * kCs + k;
+        if (p < n) {
+            float px = x[p], py = y[p], pz = z[p], ph = h[p];
+            if (!(isfinite(px) && isfinite(py) && isfinite(pz))) bad |= 1u;
+            if (!(isfinite(ph) && ph > 0.0f)) bad |= 2u;
+            lo.x = fminf(lo.x, px);
+            lo.y = fminf(lo.y, py);
+            lo.z = fminf(lo.z, pz);
+            lo.w = fmaxf(lo.w, ph);
+            hi.x = fmaxf(hi.x, px);
+            hi.y = fmaxf(hi.y, py);
+            hi.z = fmaxf(hi.z, pz);
+        }
+    }
+    bbox[2 * c] = lo;
+    bbox[2 * c + 1] = hi;
+    if (bad) atomicOr(&status[kStInputErr], bad);
+}
+
+// ---------------------------------------------------------------------------
+// Traversal
+// ---------------------------------------------------------------------------
+struct TravArgs {
+    int64_t n;
+    uint32_t nsc, nclu, cap;
+    int compress;
+    const float *x, *y, *z, *h;
+    const float4 *bbox;
+    const uint32_t *nfirst, *nend, *nchild;
+    const uint8_t *nleaf, *nnchild;
+    const float4 *nbox;
+    uint32_t *list_j;
+    uint8_t *list_m;
+    uint32_t *sc_nj, *sc_words;
+    uint32_t *status;
+};
+
+__global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
+    __shared__ uint32_t s_stack[kWavesPerBlock][kStackCap];
+    const int lane = sfc_lane();
+    const int w = threadIdx.x / kWave;
+    const uint32_t s = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
+    if (s >= a.nsc) return;
+    const int il = lane >> 3, jl = lane & 7;
+    const int64_t n = a.n;
+    const uint64_t lt = sfc_lt_mask();
+
+    // i particles: lane holds particle il of every i-cluster c
+    float ix[kSub], iy[kSub], iz[kSub], ih2[kSub];
+    uint32_t ivalid = 0;
+#pragma unroll
+    for (int c = 0; c < kSub; c++) {
+        int64_t i = (int64_t)s * kScSize + c * kCs + il;
+        bool v = i < n;
+        ix[c] = v ? a.x[i] : 0.0f;
+        iy[c] = v ? a.y[i] : 0.0f;
+        iz[c] = v ? a.z[i] : 0.0f;
+        float hh = v ? a.h[i] : 0.0f;
+        ih2[c] = hh * hh;
+        ivalid |= (v ? 1u : 0u) << c;
+    }
+    // i-cluster il's box (lanes with the same il hold the same box)
+    const uint32_t ic = s * kSub + il;
+    const bool icv = ic < a.nclu;
+    float4 clo = icv ? a.bbox[2 * ic] : make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
+    float4 chi = icv ? a.bbox[2 * ic + 1] : make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+    // super-cluster box = union of its i-cluster boxes (uniform)
+    float4 slo = clo, shi = chi;
+#pragma unroll
+    for (int d = 8; d < 64; d <<= 1) {
+        slo.x = fminf(slo.x, __shfl_xor(slo.x, d, 64));
+        slo.y = fminf(slo.y, __shfl_xor(slo.y, d, 64));
+        slo.z = fminf(slo.z, __shfl_xor(slo.z, d, 64));
+        slo.w = fmaxf(slo.w, __shfl_xor(slo.w, d, 64));
+        shi.x = fmaxf(shi.x, __shfl_xor(shi.x, d, 64));
+        shi.y = fmaxf(shi.y, __shfl_xor(shi.y, d, 64));
+        shi.z = fmaxf(shi.z, __shfl_xor(shi.z, d, 64));
+    }
+    slo = make_float4(sfc_readlane_f(slo.x, 0), sfc_readlane_f(slo.y, 0), sfc_readlane_f(slo.z, 0),
+                      sfc_readlane_f(slo.w, 0));
+    shi = make_float4(sfc_readlane_f(shi.x, 0), sfc_readlane_f(shi.y, 0), sfc_readlane_f(shi.z, 0), 0.0f);
+
+    uint32_t *stack = s_stack[w];
+    int sp = 0;
+    if (lane == 0) stack[0] = 0;  // root
+    sp = 1;
+    wave_sync();
+
+    int64_t last = -1;  // highest j-cluster already tested
+    uint32_t nj = 0, prevj = 0xFFFFFFFFu, blk_cnt = 0, blk_nib = 0, seg_words = 0;
+    uint32_t *out_j = a.list_j + (size_t)s * a.cap;
+    uint8_t *out_m = a.list_m + (size_t)s * a.cap;
+
+    while (sp > 0) {
+        sp--;
+        const uint32_t k = (uint32_t)__builtin_amdgcn_readfirstlane((int)stack[sp]);
+        if (a.nleaf[k]) {
+            int64_t c0 = a.nfirst[k] / kCs;
+            const int64_t c1 = (a.nend[k] - 1) / kCs;
+            if (c0 <= last) c0 = last + 1;
+            for (int64_t cb = c0; cb <= c1; cb += 8) {
+                const int64_t cj = cb + jl;
+                const bool vj = cj <= c1;
+                bool hit = false;
+                if (vj && icv) hit = boxes_near(clo, chi, a.bbox[2 * cj], a.bbox[2 * cj + 1]);
+                const uint64_t bal = sfc_ballot(hit);
+                uint64_t any = bal;
+                any |= any >> 32;
+                any |= any >> 16;
+                any |= any >> 8;
+                uint32_t anyj = (uint32_t)(any & 0xFFu);
+                while (anyj) {
+                    const int jc = __ffs(anyj) - 1;
+                    anyj &= anyj - 1u;
+                    // bit c of cmask = bit (8c + jc) of the ballot
+                    const uint32_t cmask =
+                        (uint32_t)((((bal >> jc) & 0x0101010101010101ull) * 0x0102040810204080ull) >> 56);
+                    const uint32_t cjv = (uint32_t)(cb + jc);
+                    const int64_t jp = (int64_t)cjv * kCs + jl;
+                    const bool vjp = jp < n;
+                    const float xj = vjp ? a.x[jp] : 0.0f, yj = vjp ? a.y[jp] : 0.0f, zj = vjp ? a.z[jp] : 0.0f;
+                    const float hj = vjp ? a.h[jp] : 0.0f;
+                    const float hj2 = hj * hj;
+                    uint32_t mask = 0;
+#pragma unroll
+                    for (int c = 0; c < kSub; c++) {
+                        if ((cmask >> c) & 1u) {
+                            const float dx = xj - ix[c];
+                            const float dy = yj - iy[c];
+                            const float dz = zj - iz[c];
+                            const float dxx = dx * dx;
+                            const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
+                            const int64_t i = (int64_t)s * kScSize + c * kCs + il;
+                            const bool pr = vjp && ((ivalid >> c) & 1u) && jp != i && d2 < fmaxf(ih2[c], hj2);
+                            if (sfc_ballot(pr)) mask |= 1u << c;
+                        }
+                    }
+                    if (mask) {
+                        if (nj < a.cap && lane == 0) {
+                            out_j[nj] = cjv;
+                            out_m[nj] = (uint8_t)mask;
+                        }
+                        const uint32_t v = cjv - prevj;
+                        prevj = cjv;
+                        blk_nib += v == 1u ? 0u : (v <= 9u ? 1u : 1u + nibbles_of(v));
+                        if (++blk_cnt == 64u) {
+                            seg_words += 2u + (blk_nib + 7u) / 8u;
+                            blk_cnt = 0;
+                            blk_nib = 0;
+                        }
+                        nj++;
+                    }
+                }
+            }
+            if (c1 > last) last = c1;
+        } else {
+            const uint32_t nc = a.nnchild[k];
+            const bool act = lane < (int)nc;
+            uint32_t ch = 0;
+            bool keep = false;
+            if (act) {
+                ch = a.nchild[8 * (size_t)k + lane];
+                keep = boxes_near(slo, shi, a.nbox[2 * (size_t)ch], a.nbox[2 * (size_t)ch + 1]);
+            }
+            const uint64_t b = sfc_ballot(keep);
+            const int cnt = sfc_popc(b);
+            if (sp + cnt > kStackCap) {  // cannot happen in a valid octree (depth <= 21)
+                if (lane == 0) atomicOr(&a.status[kStTree], 8u);
+                break;
+            }
+            if (keep) {
+                const int r = sfc_popc(b & lt);
+                stack[sp + cnt - 1 - r] = ch;  // first child on top
+            }
+            sp += cnt;
+            wave_sync();
+        }
+    }
+    if (blk_cnt) seg_words += 2u + (blk_nib + 7u) / 8u;
+    if (lane == 0) {
+        const uint32_t mwords = (nj + 3u) / 4u;
+        a.sc_nj[s] = nj;
+        a.sc_words[s] = mwords + (a.compress ? seg_words : nj);
+        atomicMax(&a.status[kStMaxNj], nj);
+        if (nj > a.cap) atomicOr(&a.status[kStScratch], 1u);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Encoder: masks, then raw indices or 64-wide nibble segments.
+// ---------------------------------------------------------------------------
+struct EncArgs {
+    uint32_t nsc, cap;
+    int compress;
+    const uint32_t *list_j;
+    const uint8_t *list_m;
+    const uint32_t *sc_nj, *sc_off;  // sc_off has nsc + 1 entries
+    uint32_t *sc_info;
+    uint32_t *pool;
+    uint64_t pool_words;
+    uint32_t *status;
+};
+
+__global__ __launch_bounds__(256) void k_encode(EncArgs a) {
+    __shared__ uint32_t s_seg[kWavesPerBlock][kSegCap];
+    const int lane = sfc_lane();
+    const int w = threadIdx.x / kWave;
+    const uint32_t s = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
+    if (s >= a.nsc) return;
+    const uint32_t nj = a.sc_nj[s];
+    const uint32_t off = a.sc_off[s];
+    const uint32_t words = a.sc_off[s + 1] - off;
+    if (lane == 0) {
+        a.sc_info[2 * s] = off;
+        a.sc_info[2 * s + 1] = nj;
+    }
+    if (nj > a.cap) return;
+    if ((uint64_t)off + words > a.pool_words) {
+        if (lane == 0) atomicOr(&a.status[kStPoolOverflow], 1u);
+        return;
+    }
+    const uint32_t *lj = a.list_j + (size_t)s * a.cap;
+    const uint8_t *lm = a.list_m + (size_t)s * a.cap;
+    uint32_t *out = a.pool + off;
+    const uint32_t mwords = (nj + 3u) / 4u;
+    for (uint32_t q = lane; q < mwords; q += kWave) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int b = 0; b < 4; b++) {
+            uint32_t e = 4 * q + b;
+            if (e < nj) word |= (uint32_t)lm[e] << (8 * b);
+        }
+        out[q] = word;
+    }
+    out += mwords;
+    if (!a.compress) {
+        for (uint32_t e = lane; e < nj; e += kWave) out[e] = lj[e];
+        return;
+    }
+    uint32_t *seg = s_seg[w];
+    const uint64_t lt = sfc_lt_mask();
+    uint32_t prevj = 0xFFFFFFFFu;
+    for (uint32_t b0 = 0; b0 < nj; b0 += kWave) {
+        const uint32_t cnt = nj - b0 < (uint32_t)kWave ? nj - b0 : (uint32_t)kWave;
+        const bool valid = (uint32_t)lane < cnt;
+        const uint32_t j = valid ? lj[b0 + lane] : 0u;
+        uint32_t jprev = __shfl_up(j, 1, 64);
+        if (lane == 0) jprev = prevj;
+        const uint32_t v = j - jprev;
+        const bool nonone = valid && v != 1u;
+        const uint64_t m = sfc_ballot(nonone);
+        const bool small = v <= 9u;
+        const uint32_t nn = nibbles_of(v);
+        const uint32_t ndata = (nonone && !small) ? nn : 0u;
+        const uint32_t info = small ? v + 6u : nn - 1u;
+        const uint32_t ninfo = (uint32_t)sfc_popc(m);
+        const uint32_t ipos = (uint32_t)sfc_popc(m & lt);
+        const uint32_t incl = sfc_incl_scan(ndata);
+        const uint32_t dpos = ninfo + incl - ndata;
+        const uint32_t total_nib = ninfo + sfc_readlane(incl, kWave - 1);
+        const uint32_t segw = 2u + (total_nib + 7u) / 8u;
+        for (uint32_t q = lane; q < segw; q += kWave) seg[q] = 0u;
+        wave_sync();
+        if (lane == 0) {
+            seg[0] = (uint32_t)m;
+            seg[1] = (uint32_t)(m >> 32);
+        }
+        if (nonone) {
+            atomicOr(&seg[2 + ipos / 8], info << (4 * (ipos % 8)));
+            for (uint32_t d = 0; d < ndata; d++) {
+                const uint32_t nib = (v >> (4 * (ndata - 1 - d))) & 0xFu;
+                const uint32_t t = dpos + d;
+                atomicOr(&seg[2 + t / 8], nib << (4 * (t % 8)));
+            }
+        }
+        wave_sync();
+        for (uint32_t q = lane; q < segw; q += kWave) out[q] = seg[q];
+        wave_sync();
+        out += segw;
+        prevj = sfc_readlane(j, (int)cnt - 1);
+    }
+}
+
+__global__ void k_finish(const uint32_t *total, uint32_t *status) { status[kStTotalLo] = *total; }
+
+struct NlistWs {
+    Octree tree;
+    uint32_t *list_j;
+    uint8_t *list_m;
+    uint32_t *sc_nj, *sc_words, *sc_off;
+    void *scan_tmp;
+};
+
+void carve_nlist(Carver &cv, NlistWs &ws, int64_t n, const sfcnl_nlist_opts &o) {
+    const uint32_t nsc = (uint32_t)((n + kScSize - 1) / kScSize);
+    octree_carve(cv, ws.tree, n, o.leaf_bucket);
+    ws.list_j = cv.take<uint32_t>((size_t)nsc * o.max_j_per_sc);
+    ws.list_m = cv.take<uint8_t>((size_t)nsc * o.max_j_per_sc);
+    ws.sc_nj = cv.take<uint32_t>(nsc);
+    ws.sc_words = cv.take<uint32_t>(nsc);
+    ws.sc_off = cv.take<uint32_t>((size_t)nsc + 1);
+    ws.scan_tmp = cv.take<char>(scan_tmp_bytes(nsc));
+}
+
+int check_opts(sfcnl_ctx ctx, const sfcnl_nlist_opts *o) {
+    if (!o) return set_err(ctx, SFCNL_E_ARG, "null options");
+    if (o->cluster_size != kCs) return set_err(ctx, SFCNL_E_ARG, "cluster_size %d not supported (8)", o->cluster_size);
+    if (o->compress != 0 && o->compress != 1) return set_err(ctx, SFCNL_E_ARG, "compress must be 0 or 1");
+    if (o->leaf_bucket < 8 || o->leaf_bucket > 256)
+        return set_err(ctx, SFCNL_E_ARG, "leaf_bucket %d outside [8, 256]", o->leaf_bucket);
+    if (o->max_j_per_sc < 1) return set_err(ctx, SFCNL_E_ARG, "max_j_per_sc must be positive");
+    return SFCNL_OK;
+}
+
+}  // namespace
+}  // namespace sfcnl
+
+using namespace sfcnl;
+
+extern "C" int build_clusters(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y, const float *d_z,
+                              const float *d_h, int cluster_size, float *d_bbox_out) {
+    if (!ctx) return SFCNL_E_ARG;
+    if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "build_clusters: n out of range");
+    if (cluster_size != kCs) return set_err(ctx, SFCNL_E_ARG, "build_clusters: cluster_size %d not supported", cluster_size);
+    if (n == 0) return SFCNL_OK;
+    if (!d_x || !d_y || !d_z || !d_h || !d_bbox_out) return set_err(ctx, SFCNL_E_ARG, "build_clusters: null pointer");
+    const int64_t nclu = (n + kCs - 1) / kCs;
+    k_cluster_bbox<<<blocks_for(nclu, 256), 256, 0, ctx->stream>>>(n, d_x, d_y, d_z, d_h,
+                                                                   reinterpret_cast<float4 *>(d_bbox_out), ctx->d_status);
+    SFCNL_LAUNCHED(ctx);
+    return SFCNL_OK;
+}
+
+extern "C" int build_nlist_workspace(int64_t n, const sfcnl_nlist_opts *opts, size_t *ws_bytes) {
+    if (n < 0 || !ws_bytes || !opts || check_opts(nullptr, opts)) return SFCNL_E_ARG;
+    Carver cv{nullptr, 0};
+    NlistWs ws;
+    carve_nlist(cv, ws, n, *opts);
+    *ws_bytes = align_up(cv.used, 256) + 256;
+    return SFCNL_OK;
+}
+
+extern "C" int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_x, const float *d_y,
+                           const float *d_z, const float *d_h, const float *d_bbox, const sfcnl_nlist_opts *opts,
+                           void *d_ws, size_t ws_bytes, uint32_t *d_sc_info, uint32_t *d_pool, size_t pool_bytes,
+                           size_t *h_used_bytes, int64_t *h_max_nj) {
+    if (!ctx) return SFCNL_E_ARG;
+    int rc = check_opts(ctx, opts);
+    if (rc) return rc;
+    if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "build_nlist: n out of range");
+    if (!h_used_bytes || !h_max_nj) return set_err(ctx, SFCNL_E_ARG, "build_nlist: null result pointer");
+    *h_used_bytes = 0;
+    *h_max_nj = 0;
+    if (n == 0) return SFCNL_OK;
+    if (!d_keys || !d_x || !d_y || !d_z || !d_h || !d_bbox || !d_ws || !d_sc_info || (!d_pool && pool_bytes))
+        return set_err(ctx, SFCNL_E_ARG, "build_nlist: null pointer");
+    size_t need;
+    build_nlist_workspace(n, opts, &need);
+    if (ws_bytes < need) return set_err(ctx, SFCNL_E_ARG, "build_nlist: workspace %zu < %zu bytes", ws_bytes, need);
+
+    Carver cv{reinterpret_cast<char *>(d_ws), 0};
+    NlistWs ws;
+    carve_nlist(cv, ws, n, *opts);
+    const uint32_t nsc = (uint32_t)((n + kScSize - 1) / kScSize);
+    const uint32_t nclu = (uint32_t)((n + kCs - 1) / kCs);
+    hipStream_t st = ctx->stream;
+
+    rc = fill_u32(ctx, ctx->d_status + kStPoolOverflow, kStWords - kStPoolOverflow, 0);
+    if (rc) return rc;
+    rc = octree_build(ctx, ws.tree, d_keys, d_x, d_y, d_z, d_h);
+    if (rc) return rc;
+
+    TravArgs ta;
+    ta.n = n;
+    ta.nsc = nsc;
+    ta.nclu = nclu;
+    ta.cap = (uint32_t)opts->max_j_per_sc;
+    ta.compress = opts->compress;
+    ta.x = d_x;
+    ta.y = d_y;
+    ta.z = d_z;
+    ta.h = d_h;
+    ta.bbox = reinterpret_cast<const float4 *>(d_bbox);
+    ta.nfirst = ws.tree.nfirst;
+    ta.nend = ws.tree.nend;
+    ta.nchild = ws.tree.nchild;
+    ta.nleaf = ws.tree.nleaf;
+    ta.nnchild = ws.tree.nnchild;
+    ta.nbox = ws.tree.nbox;
+    ta.list_j = ws.list_j;
+    ta.list_m = ws.list_m;
+    ta.sc_nj = ws.sc_nj;
+    ta.sc_words = ws.sc_words;
+    ta.status = ctx->d_status;
+    const unsigned gb = blocks_for(nsc, kWavesPerBlock);
+    k_traverse<<<gb, 256, 0, st>>>(ta);
+    SFCNL_LAUNCHED(ctx);
+    rc = scan_u32(ctx, ws.sc_words, ws.sc_off, nsc, ws.sc_off + nsc, ws.scan_tmp);
+    if (rc) return rc;
+
+    EncArgs ea;
+    ea.nsc = nsc;
+    ea.cap = ta.cap;
+    ea.compress = opts->compress;
+    ea.list_j = ws.list_j;
+    ea.list_m = ws.list_m;
+    ea.sc_nj = ws.sc_nj;
+    ea.sc_off = ws.sc_off;
+    ea.sc_info = d_sc_info;
+    ea.pool = d_pool;
+    ea.pool_words = pool_bytes / 4;
+    ea.status = ctx->d_status;
+    k_encode<<<gb, 256, 0, st>>>(ea);
+    SFCNL_LAUNCHED(ctx);
+    k_finish<<<1, 1, 0, st>>>(ws.sc_off + nsc, ctx->d_status);
+    SFCNL_LAUNCHED(ctx);
+
+    SFCNL_HIP(ctx, hipMemcpyAsync(ctx->h_status, ctx->d_status, kStWords * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
+    SFCNL_HIP(ctx, hipStreamSynchronize(st));
+    const uint32_t *hs = ctx->h_status;
+    *h_used_bytes = (size_t)hs[kStTotalLo] * 4;
+    *h_max_nj = hs[kStMaxNj];
+    if (hs[kStInputErr]) {
+        uint32_t e = hs[kStInputErr];
+        rc = fill_u32(ctx, ctx->d_status + kStInputErr, 1, 0);
+        if (rc) return rc;
+        return set_err(ctx, SFCNL_E_INPUT, "input error flags 0x%x (1: non-finite position, 2: bad radius, 4: bad permutation)", e);
+    }
+    if (hs[kStTree]) return set_err(ctx, SFCNL_E_HIP, "internal error: octree invariant broken (0x%x)", hs[kStTree]);
+    if (hs[kStScratch])
+        return set_err(ctx, SFCNL_E_CAPACITY, "a super-cluster lists %u j-clusters > max_j_per_sc %d", hs[kStMaxNj],
+                       opts->max_j_per_sc);
+    if (hs[kStPoolOverflow])
+        return set_err(ctx, SFCNL_E_CAPACITY, "pool of %zu bytes < %zu needed", pool_bytes, *h_used_bytes);
+    return SFCNL_OK;
+}

@@ -1,0 +1,125 @@
+// Device-wide exclusive prefix sum of u32 words (reduce, scan the tile sums,
+// scan tiles again and add), plus a fill kernel.
+#include "internal.h"
+
+namespace sfcnl {
+namespace {
+
+constexpr int kThreads = 256;
+constexpr int kItems = 4;
+constexpr int kTile = kThreads * kItems;
+
+// Exclusive scan of one value per thread over a 256-thread block.
+__device__ uint32_t block_excl_scan(uint32_t v, uint32_t *s_waves, uint32_t *total) {
+    const int lane = sfc_lane();
+    const int w = threadIdx.x / kWave;
+    uint32_t inc = sfc_incl_scan(v);
+    if (lane == kWave - 1) s_waves[w] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+#pragma unroll
+    for (int k = 0; k < kThreads / kWave; k++) {
+        uint32_t t = s_waves[k];
+        if (k < w) before += t;
+        all += t;
+    }
+    __syncthreads();
+    if (total) *total = all;
+    return before + inc - v;
+}
+
+__global__ __launch_bounds__(kThreads) void k_reduce(const uint32_t *__restrict__ in, int64_t n,
+                                                     uint32_t *__restrict__ sums) {
+    __shared__ uint32_t s_w[kThreads / kWave];
+    int64_t base = (int64_t)blockIdx.x * kTile;
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; k++) {
+        int64_t i = base + k * kThreads + threadIdx.x;
+        if (i < n) acc += in[i];
+    }
+    uint32_t tot;
+    block_excl_scan(acc, s_w, &tot);
+    if (threadIdx.x == 0) sums[blockIdx.x] = tot;
+}
+
+__global__ __launch_bounds__(1024) void k_top(uint32_t *__restrict__ sums, int64_t nb, uint32_t *total) {
+    __shared__ uint32_t s_w[1024 / kWave];
+    const int t = threadIdx.x;
+    int64_t per = (nb + 1023) / 1024;
+    int64_t b0 = t * per, b1 = b0 + per < nb ? b0 + per : nb;
+    uint32_t acc = 0;
+    for (int64_t b = b0; b < b1; b++) acc += sums[b];
+    // block scan over 1024 threads (16 waves)
+    const int lane = sfc_lane(), w = t / kWave;
+    uint32_t inc = sfc_incl_scan(acc);
+    if (lane == kWave - 1) s_w[w] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int k = 0; k < 1024 / kWave; k++) {
+        uint32_t v = s_w[k];
+        if (k < w) before += v;
+        all += v;
+    }
+    uint32_t run = before + inc - acc;
+    for (int64_t b = b0; b < b1; b++) {
+        uint32_t v = sums[b];
+        sums[b] = run;
+        run += v;
+    }
+    if (t == 0 && total) *total = all;
+}
+
+__global__ __launch_bounds__(kThreads) void k_down(const uint32_t *in, uint32_t *out, int64_t n,
+                                                   const uint32_t *__restrict__ sums) {
+    __shared__ uint32_t s_w[kThreads / kWave];
+    int64_t base = (int64_t)blockIdx.x * kTile + (int64_t)threadIdx.x * kItems;
+    uint32_t v[kItems];
+    uint32_t acc = 0;
+#pragma unroll
+    for (int k = 0; k < kItems; k++) {
+        v[k] = (base + k < n) ? in[base + k] : 0u;
+        acc += v[k];
+    }
+    uint32_t run = block_excl_scan(acc, s_w, nullptr) + sums[blockIdx.x];
+#pragma unroll
+    for (int k = 0; k < kItems; k++) {
+        if (base + k < n) out[base + k] = run;
+        run += v[k];
+    }
+}
+
+__global__ void k_fill(uint32_t *p, int64_t n, uint32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+}  // namespace
+
+size_t scan_tmp_bytes(int64_t n) { return align_up((size_t)(blocks_for(n, kTile) + 1) * 4, 256); }
+
+int scan_u32(sfcnl_ctx ctx, const uint32_t *in, uint32_t *out, int64_t n, uint32_t *d_total, void *tmp) {
+    if (n <= 0) {
+        if (d_total) return fill_u32(ctx, d_total, 1, 0);
+        return SFCNL_OK;
+    }
+    unsigned nb = blocks_for(n, kTile);
+    uint32_t *sums = reinterpret_cast<uint32_t *>(tmp);
+    // k_down reads its tile before writing, so in == out is allowed
+    k_reduce<<<nb, kThreads, 0, ctx->stream>>>(in, n, sums);
+    SFCNL_LAUNCHED(ctx);
+    k_top<<<1, 1024, 0, ctx->stream>>>(sums, nb, d_total);
+    SFCNL_LAUNCHED(ctx);
+    k_down<<<nb, kThreads, 0, ctx->stream>>>(in, out, n, sums);
+    SFCNL_LAUNCHED(ctx);
+    return SFCNL_OK;
+}
+
+int fill_u32(sfcnl_ctx ctx, uint32_t *p, int64_t n, uint32_t v) {
+    if (n <= 0) return SFCNL_OK;
+    k_fill<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(p, n, v);
+    SFCNL_LAUNCHED(ctx);
+    return SFCNL_OK;
+}
+
+}  // namespace sfcnl

@@ -1,0 +1,357 @@
+// SFC order of the particles (Sec. II-A): 63-bit Hilbert keys, a stable LSD
+// radix sort of (key, index), and the gather of particle fields.
+#include "internal.h"
+
+namespace sfcnl {
+namespace {
+
+// ---------------------------------------------------------------------------
+// Hilbert keys
+// ---------------------------------------------------------------------------
+
+// Bit b of v (21 bits) moves to bit 3b.
+__device__ __forceinline__ uint64_t spread3(uint32_t v) {
+    uint64_t x = v & 0x1fffffu;
+    x = (x | (x << 32)) & 0x001f00000000ffffull;
+    x = (x | (x << 16)) & 0x001f0000ff0000ffull;
+    x = (x | (x << 8)) & 0x100f00f00f00f00full;
+    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
+    x = (x | (x << 2)) & 0x1249249249249249ull;
+    return x;
+}
+
+// Hilbert index of a 21-bit cell (Skilling 2004, transpose form): walk the
+// levels from the top, at each level inverting or exchanging the lower bits
+// of axis 0 against every axis, then Gray-encode across the axes, then read
+// the transposed words out with axis 0 as the top bit of each 3-bit digit.
+__device__ __forceinline__ uint64_t hilbert_key(uint32_t a0, uint32_t a1, uint32_t a2) {
+#pragma unroll
+    for (int b = 20; b >= 1; b--) {
+        const uint32_t q = 1u << b, low = q - 1u;
+        if (a0 & q) a0 ^= low;
+        uint32_t t1 = (a0 ^ a1) & low;
+        if (a1 & q) {
+            a0 ^= low;
+        } else {
+            a0 ^= t1;
+            a1 ^= t1;
+        }
+        uint32_t t2 = (a0 ^ a2) & low;
+        if (a2 & q) {
+            a0 ^= low;
+        } else {
+            a0 ^= t2;
+            a2 ^= t2;
+        }
+    }
+    a1 ^= a0;
+    a2 ^= a1;
+    uint32_t flip = 0;
+#pragma unroll
+    for (int b = 20; b >= 1; b--)
+        if (a2 & (1u << b)) flip ^= (1u << b) - 1u;
+    a0 ^= flip;
+    a1 ^= flip;
+    a2 ^= flip;
+    return (spread3(a0) << 2) | (spread3(a1) << 1) | spread3(a2);
+}
+
+__device__ __forceinline__ uint32_t quantise(float x, float lo, float s) {
+    float t = x - lo;
+    t = t * s;
+    if (!(t > 0.0f)) return 0u;
+    if (t >= 2097151.0f) return 2097151u;
+    return (uint32_t)t;
+}
+
+__global__ __launch_bounds__(256) void k_keys(int64_t n, const float *__restrict__ x, const float *__restrict__ y,
+                                              const float *__restrict__ z, float lox, float sx, float loy, float sy,
+                                              float loz, float sz, uint64_t *__restrict__ keys,
+                                              uint32_t *__restrict__ idx, uint32_t *status) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float px = x[i], py = y[i], pz = z[i];
+    if (!(isfinite(px) && isfinite(py) && isfinite(pz))) atomicOr(&status[kStInputErr], 1u);
+    keys[i] = hilbert_key(quantise(px, lox, sx), quantise(py, loy, sy), quantise(pz, loz, sz));
+    idx[i] = (uint32_t)i;
+}
+
+// ---------------------------------------------------------------------------
+// Stable LSD radix sort, 8-bit digits, 8 passes. Per pass: tile histograms,
+// a scan over tiles per digit, and a scatter that ranks each tile stably in
+// LDS before writing runs of equal digits out contiguously.
+// ---------------------------------------------------------------------------
+
+constexpr int kThreads = 256;
+constexpr int kItems = 8;
+constexpr int kTile = kThreads * kItems;
+constexpr int kWavesPerBlock = kThreads / kWave;
+constexpr int kRadix = 256;
+constexpr int kPasses = 8;
+
+__global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
+                                                   uint32_t ntiles, uint32_t *__restrict__ hist) {
+    __shared__ uint32_t s_h[kRadix];
+    const int t = threadIdx.x;
+    s_h[t] = 0;
+    __syncthreads();
+    int64_t base = (int64_t)blockIdx.x * kTile;
+#pragma unroll
+    for (int k = 0; k < kItems; k++) {
+        int64_t i = base + k * kThreads + t;
+        if (i < n) atomicAdd(&s_h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+    }
+    __syncthreads();
+    hist[(size_t)t * ntiles + blockIdx.x] = s_h[t];
+}
+
+// One block per digit: exclusive scan of hist[d][0..ntiles) in place.
+__global__ __launch_bounds__(kThreads) void k_digit_scan(uint32_t *__restrict__ hist, uint32_t ntiles,
+                                                         uint32_t *__restrict__ digit_tot) {
+    __shared__ uint32_t s_w[kWavesPerBlock];
+    uint32_t *row = hist + (size_t)blockIdx.x * ntiles;
+    const int t = threadIdx.x, lane = sfc_lane(), w = t / kWave;
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < ntiles; c0 += kThreads * 4) {
+        uint32_t v[4], acc = 0;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            uint32_t i = c0 + t * 4 + k;
+            v[k] = i < ntiles ? row[i] : 0u;
+            acc += v[k];
+        }
+        uint32_t inc = sfc_incl_scan(acc);
+        if (lane == kWave - 1) s_w[w] = inc;
+        __syncthreads();
+        uint32_t before = 0, all = 0;
+#pragma unroll
+        for (int k = 0; k < kWavesPerBlock; k++) {
+            if (k < w) before += s_w[k];
+            all += s_w[k];
+        }
+        __syncthreads();
+        uint32_t run = carry + before + inc - acc;
+#pragma unroll
+        for (int k = 0; k < 4; k++) {
+            uint32_t i = c0 + t * 4 + k;
+            if (i < ntiles) row[i] = run;
+            run += v[k];
+        }
+        carry += all;
+    }
+    if (t == 0) digit_tot[blockIdx.x] = carry;
+}
+
+__global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
+                                                      uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
+                                                      int64_t n, int shift, uint32_t ntiles,
+                                                      const uint32_t *__restrict__ hist,
+                                                      const uint32_t *__restrict__ digit_tot) {
+    __shared__ uint64_t s_keys[kTile];
+    __shared__ uint32_t s_vals[kTile];
+    __shared__ uint32_t s_cnt[kWavesPerBlock][kRadix];
+    __shared__ uint32_t s_gbase[kRadix];
+    __shared__ uint32_t s_w[2][kWavesPerBlock];
+
+    const int t = threadIdx.x, lane = sfc_lane(), w = t / kWave;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    const int tile_n = (int)((n - base) < kTile ? (n - base) : kTile);
+
+#pragma unroll
+    for (int k = 0; k < kWavesPerBlock; k++) s_cnt[k][t] = 0;
+    __syncthreads();
+
+    uint64_t key[kItems];
+    uint32_t val[kItems], lrank[kItems];
+    const uint64_t lt = sfc_lt_mask();
+#pragma unroll
+    for (int k = 0; k < kItems; k++) {
+        int li = w * (kItems * kWave) + k * kWave + lane;  // striped: wave, item, lane
+        bool valid = li < tile_n;
+        key[k] = valid ? kin[base + li] : 0ull;
+        val[k] = valid ? vin[base + li] : 0u;
+        uint32_t d = (uint32_t)(key[k] >> shift) & 255u;
+        uint64_t m = sfc_ballot(valid);
+#pragma unroll
+        for (int b = 0; b < 8; b++) {
+            bool bit = (d >> b) & 1u;
+            uint64_t bb = sfc_ballot(valid && bit);
+            m &= bit ? bb : ~bb;
+        }
+        uint32_t r = (uint32_t)sfc_popc(m & lt);
+        uint32_t before = valid ? s_cnt[w][d] : 0u;
+        __builtin_amdgcn_wave_barrier();
+        lrank[k] = before + r;
+        if (valid && r == 0) s_cnt[w][d] = before + (uint32_t)sfc_popc(m);
+        __builtin_amdgcn_wave_barrier();
+    }
+    __syncthreads();
+
+    // per digit t: prefix over waves, then the tile-local start of digit t
+    uint32_t c[kWavesPerBlock], tot = 0;
+#pragma unroll
+    for (int k = 0; k < kWavesPerBlock; k++) {
+        c[k] = s_cnt[k][t];
+        tot += c[k];
+    }
+    uint32_t dt = digit_tot[t];
+    uint32_t inc_tile = sfc_incl_scan(tot);
+    uint32_t inc_glob = sfc_incl_scan(dt);
+    if (lane == kWave - 1) {
+        s_w[0][w] = inc_tile;
+        s_w[1][w] = inc_glob;
+    }
+    __syncthreads();
+    uint32_t tile_start = inc_tile - tot, glob_start = inc_glob - dt;
+    for (int k = 0; k < w; k++) {
+        tile_start += s_w[0][k];
+        glob_start += s_w[1][k];
+    }
+    uint32_t run = tile_start;
+#pragma unroll
+    for (int k = 0; k < kWavesPerBlock; k++) {
+        s_cnt[k][t] = run;
+        run += c[k];
+    }
+    s_gbase[t] = glob_start + hist[(size_t)t * ntiles + blockIdx.x] - tile_start;
+    __syncthreads();
+
+#pragma unroll
+    for (int k = 0; k < kItems; k++) {
+        int li = w * (kItems * kWave) + k * kWave + lane;
+        if (li < tile_n) {
+            uint32_t d = (uint32_t)(key[k] >> shift) & 255u;
+            uint32_t lp = s_cnt[w][d] + lrank[k];
+            s_keys[lp] = key[k];
+            s_vals[lp] = val[k];
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < kItems; k++) {
+        int lp = k * kThreads + t;
+        if (lp < tile_n) {
+            uint64_t kk = s_keys[lp];
+            uint32_t d = (uint32_t)(kk >> shift) & 255u;
+            uint32_t gp = s_gbase[d] + (uint32_t)lp;
+            kout[gp] = kk;
+            vout[gp] = s_vals[lp];
+        }
+    }
+}
+
+struct GatherArgs {
+    const float *in[8];
+    float *out[8];
+    int nf;
+};
+
+__global__ __launch_bounds__(256) void k_gather(int64_t n, const uint32_t *__restrict__ perm, GatherArgs a,
+                                                uint32_t *status) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t p = perm[i];
+    if (p >= (uint64_t)n) {  // not a permutation of [0, n): report, never read outside
+        atomicOr(&status[kStInputErr], 4u);
+        p = 0;
+    }
+#pragma unroll
+    for (int f = 0; f < 8; f++)
+        if (f < a.nf) a.out[f][i] = a.in[f][p];
+}
+
+struct SortWs {
+    uint64_t *ktmp;
+    uint32_t *vtmp;
+    uint32_t *hist;
+    uint32_t *dtot;
+};
+
+size_t carve_sort(Carver &cv, SortWs &s, int64_t n) {
+    uint32_t ntiles = blocks_for(n, kTile);
+    s.ktmp = cv.take<uint64_t>((size_t)n);
+    s.vtmp = cv.take<uint32_t>((size_t)n);
+    s.hist = cv.take<uint32_t>((size_t)kRadix * ntiles);
+    s.dtot = cv.take<uint32_t>(kRadix);
+    return cv.used;
+}
+
+float box_scale(float lo, float hi) { return (float)(2097152.0 / ((double)hi - (double)lo)); }
+
+}  // namespace
+}  // namespace sfcnl
+
+using namespace sfcnl;
+
+extern "C" int sfc_sort_workspace(int64_t n, size_t *ws_bytes) {
+    if (n < 0 || !ws_bytes) return SFCNL_E_ARG;
+    Carver cv{nullptr, 0};
+    SortWs s;
+    *ws_bytes = align_up(carve_sort(cv, s, n), 256) + 256;
+    return SFCNL_OK;
+}
+
+extern "C" int sfc_sort(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y, const float *d_z,
+                        const float *h_box, uint64_t *d_keys_out, uint32_t *d_perm_out, void *d_ws,
+                        size_t ws_bytes) {
+    if (!ctx) return SFCNL_E_ARG;
+    if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "sfc_sort: n=%lld out of range", (long long)n);
+    if (n == 0) return SFCNL_OK;
+    if (!d_x || !d_y || !d_z || !h_box || !d_keys_out || !d_perm_out || !d_ws)
+        return set_err(ctx, SFCNL_E_ARG, "sfc_sort: null pointer");
+    for (int a = 0; a < 3; a++)
+        if (!(h_box[2 * a + 1] > h_box[2 * a]) || !__builtin_isfinite(h_box[2 * a]) || !__builtin_isfinite(h_box[2 * a + 1]))
+            return set_err(ctx, SFCNL_E_ARG, "sfc_sort: box axis %d empty or not finite", a);
+    size_t need;
+    sfc_sort_workspace(n, &need);
+    if (ws_bytes < need)
+        return set_err(ctx, SFCNL_E_ARG, "sfc_sort: workspace %zu bytes < %zu needed", ws_bytes, need);
+    Carver cv{reinterpret_cast<char *>(d_ws), 0};
+    SortWs s;
+    carve_sort(cv, s, n);
+
+    hipStream_t st = ctx->stream;
+    k_keys<<<blocks_for(n, 256), 256, 0, st>>>(n, d_x, d_y, d_z, h_box[0], box_scale(h_box[0], h_box[1]), h_box[2],
+                                               box_scale(h_box[2], h_box[3]), h_box[4], box_scale(h_box[4], h_box[5]),
+                                               d_keys_out, d_perm_out, ctx->d_status);
+    SFCNL_LAUNCHED(ctx);
+    const uint32_t ntiles = blocks_for(n, kTile);
+    uint64_t *ka = d_keys_out, *kb = s.ktmp;
+    uint32_t *va = d_perm_out, *vb = s.vtmp;
+    for (int pass = 0; pass < kPasses; pass++) {
+        int shift = 8 * pass;
+        k_hist<<<ntiles, kThreads, 0, st>>>(ka, n, shift, ntiles, s.hist);
+        SFCNL_LAUNCHED(ctx);
+        k_digit_scan<<<kRadix, kThreads, 0, st>>>(s.hist, ntiles, s.dtot);
+        SFCNL_LAUNCHED(ctx);
+        k_scatter<<<ntiles, kThreads, 0, st>>>(ka, va, kb, vb, n, shift, ntiles, s.hist, s.dtot);
+        SFCNL_LAUNCHED(ctx);
+        uint64_t *tk = ka;
+        ka = kb;
+        kb = tk;
+        uint32_t *tv = va;
+        va = vb;
+        vb = tv;
+    }
+    // an even number of passes leaves the result in the output buffers
+    return SFCNL_OK;
+}
+
+extern "C" int sfc_gather(sfcnl_ctx ctx, int64_t n, const uint32_t *d_perm, int nfields, const float *const *h_in,
+                          float *const *h_out) {
+    if (!ctx) return SFCNL_E_ARG;
+    if (n < 0 || n >= (int64_t(1) << 31) || nfields < 1 || nfields > 8 || !h_in || !h_out)
+        return set_err(ctx, SFCNL_E_ARG, "sfc_gather: bad arguments");
+    if (n == 0) return SFCNL_OK;
+    if (!d_perm) return set_err(ctx, SFCNL_E_ARG, "sfc_gather: null perm");
+    GatherArgs a{};
+    a.nf = nfields;
+    for (int f = 0; f < nfields; f++) {
+        if (!h_in[f] || !h_out[f]) return set_err(ctx, SFCNL_E_ARG, "sfc_gather: null field %d", f);
+        a.in[f] = h_in[f];
+        a.out[f] = h_out[f];
+    }
+    k_gather<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, d_perm, a, ctx->d_status);
+    SFCNL_LAUNCHED(ctx);
+    return SFCNL_OK;
+}
