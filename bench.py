@@ -1,0 +1,181 @@
+#!/usr/bin/env python
+"""Throughput of the SFC cluster neighbour list: list build + density pass.
+
+One step = the whole path over one system already resident in HBM:
+Hilbert keys + stable radix sort, gather into SFC order, cluster boxes,
+octree + traversal + compressed encoding, decode + SPH density pass.
+
+Prints one JSON line (rank 0, one GPU). Per-kernel durations come from HIP
+events the library records on its own stream inside the timed region.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "nlist build + density pass Mparticles/s at 1 GPU; bytes/particle; % HBM roofline"
+
+# MI355X published peaks
+HBM_PEAK_GBS = 8000.0
+FP32_PEAK_TFLOPS = 157.3      # 256 CU x 2.4 GHz x 128 FP32 lanes (dual-issue) x 2 (FMA)
+
+# Algorithmic work, per unit (stated also in the design doc):
+#   HBM stages: bytes per particle the stage must move at minimum.
+#   ALU stages: FP32 flops (an FMA counts 2) per particle-pair test.
+BYTES_PER_PARTICLE = {
+    "keys": 12 + 8 + 4,            # read x, y, z; write key and index
+    "sort": 8 * (12 + 12) + 8,     # 8 digit passes: read + write key/index; one histogram read
+    "gather": 4 + 4 * (4 + 4),     # read perm; read + write x, y, z, h
+    "clusters": 16 + 4,            # read x, y, z, h; write 32 B per 8-particle cluster
+}
+FLOPS_PER_TEST = 10     # dx, dy, dz (3); dx*dx (1); 2 fma (4); max of radii (1); compare (1)
+FLOPS_PER_PAIR = 17     # dx, dy, dz (3); d2 (5); sqrt (1); q (1); spline piece (5); m*W, += (2)
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def make_workload(name):
+    from paper_2602_19873_amd import workloads
+    return workloads.make_config(name)
+
+
+def list_stats(sf, ctx, nl):
+    """Bytes per particle split, and the pair work the list fixes."""
+    import numpy as np
+    offs, j, m = sf.nlist_decode(ctx, nl)
+    pc = np.unpackbits(m.astype(np.uint8)[:, None], axis=1).sum() if m.size else 0
+    nj = np.diff(offs)
+    n = nl.n
+    mask_bytes = float(((nj + 3) // 4 * 4).sum())
+    return {
+        "bytes_per_particle": nl.bytes_per_particle(),
+        "bytes_headers_pp": 8.0 * nl.n_sc / n,
+        "bytes_masks_pp": mask_bytes / n,
+        "bytes_indices_pp": (nl.used_bytes - mask_bytes) / n,
+        "entries": int(nj.sum()),
+        "mean_nj": float(nj.mean()) if nj.size else 0.0,
+        "max_nj": int(nj.max()) if nj.size else 0,
+        "tile_pairs": int(pc) * 64,        # 8x8 pair evaluations in the pass
+        "exact_tests_min": int(nj.sum()) * 512,  # 64 i x 8 j tests per listed cluster pair
+    }
+
+
+def cpu_baseline(n_sample):
+    """The oracle on a bounded sample of the same workload (same generator and
+    neighbour count, fewer particles): keys, stable order, cluster list,
+    encoding, FP64 density."""
+    import oracle
+    from paper_2602_19873_amd import workloads
+    s = workloads.uniform_varied(n_sample, workloads.SEED_BASE + 2)
+    oracle.build()
+    t0 = time.perf_counter()
+    oracle.pipeline(s.x, s.y, s.z, s.h, s.box)
+    dt = time.perf_counter() - t0
+    return {"value": n_sample / dt / 1e6, "unit": "Mparticles/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "uniform_varied N=%d (same generator and ~200 neighbours as the timed workload), "
+                      "full oracle path: keys, stable sort, cell-list cluster list, encoding, FP64 density; "
+                      "%.1f s" % (n_sample, dt),
+            "seconds": dt}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--workload", default="uniform_2m_varied")
+    ap.add_argument("--compress", type=int, default=1)
+    ap.add_argument("--leaf-bucket", type=int, default=64)
+    ap.add_argument("--cpu-sample", type=int, default=1048576)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: the path runs on a single MI355X; multi-GPU sharding is "
+              "described in DESIGN.md and not built", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2602_19873_amd as sf
+
+    s = make_workload(args.workload)
+    n = s.n
+    log("workload %s n=%d" % (args.workload, n))
+    torch.cuda.set_device(0)
+    dev = torch.device("cuda:0")
+    x, y, z, h = (torch.from_numpy(a).to(dev) for a in (s.x, s.y, s.z, s.h))
+    ctx = sf.Context(0)
+    pipe = sf.Pipeline(ctx, n, s.box, compress=bool(args.compress), leaf_bucket=args.leaf_bucket,
+                       max_j_per_sc=512)
+    for _ in range(max(args.warmup, 1)):
+        pipe.step(x, y, z, h)
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    ctx.profile_begin(args.steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        pipe.step(x, y, z, h)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = ctx.profile_end()
+    ms_step = (t1 - t0) * 1e3 / args.steps
+    value = n / (ms_step * 1e-3) / 1e6
+    log("timed %d steps: %.3f ms/step" % (args.steps, ms_step))
+
+    st = list_stats(sf, ctx, pipe.nl)
+    stages = {}
+    for name, (ms, calls) in prof.items():
+        if calls == 0:
+            continue
+        avg = ms / calls
+        d = {"ms": avg}
+        if name in BYTES_PER_PARTICLE:
+            gbs = BYTES_PER_PARTICLE[name] * n / (avg * 1e-3) / 1e9
+            d.update(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS)
+        elif name == "traverse":
+            tf = st["exact_tests_min"] * FLOPS_PER_TEST / (avg * 1e-3) / 1e12
+            d.update(bound="alu", achieved=tf, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s", frac=tf / FP32_PEAK_TFLOPS)
+        elif name == "pass":
+            tf = st["tile_pairs"] * FLOPS_PER_PAIR / (avg * 1e-3) / 1e12
+            d.update(bound="alu", achieved=tf, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s", frac=tf / FP32_PEAK_TFLOPS)
+        stages[name] = d
+    dom = max((k for k in stages if "bound" in stages[k]), key=lambda k: stages[k]["ms"])
+    dd = stages[dom]
+    roofline = {"kernel": dom, "bound": dd["bound"], "achieved": dd["achieved"], "peak": dd["peak"],
+                "unit": dd["unit"], "frac": dd["frac"], "traffic": None}
+
+    out = {
+        "metric": METRIC, "value": value, "unit": "Mparticles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": args.workload, "n": n, "cluster_size": 8, "super_cluster": 64,
+                   "compress": bool(args.compress), "leaf_bucket": args.leaf_bucket, "radii": "r_c*U(0.8,1.2)",
+                   "target_neighbours": 200},
+        "bytes_per_particle": st["bytes_per_particle"],
+        "list": st,
+        "stages_ms": {k: v["ms"] for k, v in stages.items()},
+        "stages": stages,
+        "roofline": roofline,
+    }
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) on %d particles" % args.cpu_sample)
+        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+    ctx.close()
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -155,6 +155,19 @@ int nlist_pass(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, const u
 int nlist_decode(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, const uint32_t *d_sc_info,
                  const uint32_t *d_pool, const uint32_t *d_offsets, uint32_t *d_j, uint16_t *d_mask);
 
+/* ---- Stage timing -------------------------------------------------------
+ * When enabled, every call brackets each of its stages with a pair of HIP
+ * events on the context's stream (no synchronisation). Stages:
+ *   0 keys, 1 radix sort, 2 gather, 3 clusters, 4 octree, 5 traversal,
+ *   6 encode (prefix sum + encoder), 7 pass.
+ * sfcnl_profile_begin allocates `slots` event pairs per stage; recording past
+ * that many calls of a stage is skipped. sfcnl_profile_end waits for the
+ * stream, writes per stage the summed milliseconds (h_ms[8]) and the number of
+ * recorded calls (h_calls[8]), and releases the events. */
+#define SFCNL_NSTAGE 8
+int sfcnl_profile_begin(sfcnl_ctx ctx, int slots);
+int sfcnl_profile_end(sfcnl_ctx ctx, double *h_ms, int64_t *h_calls);
+
 #ifdef __cplusplus
 }
 #endif

@@ -170,7 +170,7 @@ def cluster_list(x, y, z, h, cs: int = 8, method: str = "grid", sc_ids=None):
     n = x.shape[0]
     lib = _load()
     g = 1 if method == "grid" else 0
-    md = int(lib.orc_max_degree(n, x, y, z, h, g))
+    md = 1024  # initial neighbour buffer; grows on demand
     if sc_ids is None:
         nsel = (n + SC_SIZE - 1) // SC_SIZE
         ids_ptr = None

@@ -304,13 +304,20 @@ typedef struct {
 
 static void sc_list_one(const orc_grid *g, int use_grid, int64_t n, const float *x, const float *y,
                         const float *z, const float *h, int cs, int64_t s, uint16_t *marks,
-                        int64_t *touched, int64_t *nb, int64_t nbcap, orc_sc_list *out)
+                        int64_t *touched, int64_t **nbp, int64_t *nbcap, orc_sc_list *out)
 {
     int64_t nt = 0;
     for (int64_t i = 64 * s; i < 64 * s + 64 && i < n; i++) {
         int c = (int)((i - 64 * s) / cs);
-        int64_t cnt = neighbours_of(g, use_grid, n, x, y, z, h, i, nb, nbcap);
-        if (cnt > nbcap) abort(); /* caller sizes nbcap from orc_max_degree */
+        int64_t cnt = neighbours_of(g, use_grid, n, x, y, z, h, i, *nbp, *nbcap);
+        if (cnt > *nbcap) { /* grow the buffer and search again */
+            free(*nbp);
+            *nbcap = cnt;
+            *nbp = (int64_t *)malloc((size_t)cnt * sizeof(int64_t));
+            if (!*nbp) abort();
+            cnt = neighbours_of(g, use_grid, n, x, y, z, h, i, *nbp, *nbcap);
+        }
+        const int64_t *nb = *nbp;
         for (int64_t k = 0; k < cnt; k++) {
             int64_t cj = nb[k] / cs;
             if (marks[cj] == 0) touched[nt++] = cj;
@@ -329,7 +336,8 @@ static void sc_list_one(const orc_grid *g, int use_grid, int64_t n, const float 
 }
 
 /* Builds the list for the super-clusters in sc_ids (or all if sc_ids == NULL,
- * nsel = number of super-clusters). Results are returned as CSR over the
+ * nsel = number of super-clusters). max_degree is only the initial size of the
+ * per-thread neighbour buffer, which grows on demand. Results are returned as CSR over the
  * selection: *out_offs (nsel+1), *out_j, *out_mask, malloc'ed here and
  * released with orc_free. Returns 0, or -1 on allocation failure. */
 int orc_cluster_list(int64_t n, const float *x, const float *y, const float *z, const float *h, int cs,
@@ -346,11 +354,12 @@ int orc_cluster_list(int64_t n, const float *x, const float *y, const float *z, 
     {
         uint16_t *marks = (uint16_t *)calloc((size_t)(nclu > 0 ? nclu : 1), sizeof(uint16_t));
         int64_t *touched = (int64_t *)malloc((size_t)(nclu > 0 ? nclu : 1) * sizeof(int64_t));
-        int64_t *nb = (int64_t *)malloc((size_t)nbcap * sizeof(int64_t));
+        int64_t cap = nbcap;
+        int64_t *nb = (int64_t *)malloc((size_t)cap * sizeof(int64_t));
 #pragma omp for schedule(dynamic, 4)
         for (int64_t k = 0; k < nsel; k++) {
             int64_t s = sc_ids ? sc_ids[k] : k;
-            sc_list_one(&g, use_grid, n, x, y, z, h, cs, s, marks, touched, nb, nbcap, &lists[k]);
+            sc_list_one(&g, use_grid, n, x, y, z, h, cs, s, marks, touched, &nb, &cap, &lists[k]);
         }
         free(marks);
         free(touched);

@@ -72,6 +72,17 @@ class Context:
         except Exception:
             pass
 
+    def profile_begin(self, slots: int):
+        """Start per-stage event timing (see sfcnl_profile_begin)."""
+        self.check(self.lib.sfcnl_profile_begin(self.handle, slots))
+
+    def profile_end(self):
+        """Stop stage timing: {stage: (total ms, calls)}."""
+        ms = (C.c_double * _lib.NSTAGE)()
+        calls = (C.c_int64 * _lib.NSTAGE)()
+        self.check(self.lib.sfcnl_profile_end(self.handle, ms, calls))
+        return {name: (ms[i], calls[i]) for i, name in enumerate(_lib.STAGES)}
+
     def empty(self, shape, dtype):
         return torch.empty(shape, dtype=dtype, device="cuda:%d" % self.device)
 

@@ -19,8 +19,11 @@ E_HIP = -4
 SYMBOLS = [
     "sfcnl_create", "sfcnl_destroy", "sfcnl_set_stream", "sfcnl_last_error", "sfcnl_sync", "sfcnl_version",
     "sfc_sort_workspace", "sfc_sort", "sfc_gather", "build_clusters", "build_nlist_workspace", "build_nlist",
-    "nlist_pass", "nlist_decode",
+    "nlist_pass", "nlist_decode", "sfcnl_profile_begin", "sfcnl_profile_end",
 ]
+
+NSTAGE = 8
+STAGES = ["keys", "sort", "gather", "clusters", "octree", "traverse", "encode", "pass"]
 
 
 class NlistOpts(C.Structure):
@@ -69,5 +72,9 @@ def load():
     lib.nlist_pass.restype = i32
     lib.nlist_decode.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp]
     lib.nlist_decode.restype = i32
+    lib.sfcnl_profile_begin.argtypes = [vp, i32]
+    lib.sfcnl_profile_begin.restype = i32
+    lib.sfcnl_profile_end.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
+    lib.sfcnl_profile_end.restype = i32
     _lib = lib
     return lib

@@ -53,8 +53,50 @@ extern "C" int sfcnl_create(sfcnl_ctx *out, int device, void *stream) {
     return SFCNL_OK;
 }
 
+static void prof_release(sfcnl_ctx ctx) {
+    for (int s = 0; s < SFCNL_NSTAGE; s++) {
+        if (ctx->prof_ev[s]) {
+            for (int k = 0; k < 2 * ctx->prof_slots; k++) (void)hipEventDestroy(ctx->prof_ev[s][k]);
+            free(ctx->prof_ev[s]);
+            ctx->prof_ev[s] = nullptr;
+        }
+        ctx->prof_used[s] = 0;
+    }
+    ctx->prof_slots = 0;
+}
+
+extern "C" int sfcnl_profile_begin(sfcnl_ctx ctx, int slots) {
+    if (!ctx || slots < 1) return SFCNL_E_ARG;
+    prof_release(ctx);
+    for (int s = 0; s < SFCNL_NSTAGE; s++) {
+        ctx->prof_ev[s] = (hipEvent_t *)calloc(2 * (size_t)slots, sizeof(hipEvent_t));
+        if (!ctx->prof_ev[s]) return set_err(ctx, SFCNL_E_ARG, "profile: out of host memory");
+        for (int k = 0; k < 2 * slots; k++) SFCNL_HIP(ctx, hipEventCreate(&ctx->prof_ev[s][k]));
+    }
+    ctx->prof_slots = slots;
+    return SFCNL_OK;
+}
+
+extern "C" int sfcnl_profile_end(sfcnl_ctx ctx, double *h_ms, int64_t *h_calls) {
+    if (!ctx || !h_ms || !h_calls) return SFCNL_E_ARG;
+    SFCNL_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    for (int s = 0; s < SFCNL_NSTAGE; s++) {
+        double tot = 0.0;
+        for (int k = 0; k < ctx->prof_used[s]; k++) {
+            float ms = 0.0f;
+            SFCNL_HIP(ctx, hipEventElapsedTime(&ms, ctx->prof_ev[s][2 * k], ctx->prof_ev[s][2 * k + 1]));
+            tot += ms;
+        }
+        h_ms[s] = tot;
+        h_calls[s] = ctx->prof_slots ? ctx->prof_used[s] : 0;
+    }
+    prof_release(ctx);
+    return SFCNL_OK;
+}
+
 extern "C" void sfcnl_destroy(sfcnl_ctx ctx) {
     if (!ctx) return;
+    prof_release(ctx);
     (void)hipStreamSynchronize(ctx->stream);
     (void)hipHostFree(ctx->h_status);
     (void)hipFree(ctx->d_status);

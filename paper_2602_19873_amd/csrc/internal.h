@@ -15,6 +15,7 @@ constexpr int kWave = 64;
 constexpr int kScSize = SFCNL_SC_SIZE;   // particles per super-cluster
 constexpr int kCs = 8;                   // particles per cluster
 constexpr int kSub = kScSize / kCs;      // i-clusters per super-cluster
+constexpr int kMaxBoxLevels = 12;        // 8^12 clusters > 2^31 particles
 
 // Status block words (device, mirrored into pinned host memory).
 enum StatusWord : int {
@@ -35,6 +36,10 @@ struct sfcnl_ctx_s {
     uint32_t *d_status;
     uint32_t *h_status;
     char err[512];
+    // stage timing (sfcnl_profile_begin / _end)
+    int prof_slots;
+    int prof_used[SFCNL_NSTAGE];
+    hipEvent_t *prof_ev[SFCNL_NSTAGE];  // 2 * prof_slots events per stage
 };
 
 namespace sfcnl {
@@ -49,6 +54,18 @@ int set_err(sfcnl_ctx ctx, int code, const char *fmt, ...);
     } while (0)
 
 #define SFCNL_LAUNCHED(ctx) SFCNL_HIP(ctx, hipGetLastError())
+
+enum Stage : int { kStageKeys = 0, kStageSort, kStageGather, kStageClusters, kStageOctree, kStageTraverse,
+                   kStageEncode, kStagePass };
+
+// Brackets one stage of a call with events when profiling is on.
+inline void prof_mark(sfcnl_ctx ctx, int stage, bool end) {
+    if (!ctx->prof_slots) return;
+    int k = ctx->prof_used[stage];
+    if (k >= ctx->prof_slots) return;
+    (void)hipEventRecord(ctx->prof_ev[stage][2 * k + (end ? 1 : 0)], ctx->stream);
+    if (end) ctx->prof_used[stage] = k + 1;
+}
 
 inline unsigned blocks_for(int64_t n, int per_block) { return (unsigned)((n + per_block - 1) / per_block); }
 
@@ -83,20 +100,21 @@ struct Octree {
     int8_t *lam;       // common digits of key[p] and key[p + bucket] (-1 if out of range)
     int8_t *lleaf;     // octree level of the leaf holding p
     uint32_t *node_at; // index of the first node starting at particle p (leaf starts)
-    // per node (capacity = n + 22 upper bound)
+    // per node (capacity: a proven upper bound on the node count)
     uint32_t *nfirst, *nend, *nesc;
     uint8_t *nlevel, *nleaf, *nnchild;
     uint32_t *nchild;  // 8 per node
-    uint32_t *nparent;
-    uint32_t *nvisit;
     float4 *nbox;      // 2 per node: lo (x, y, z, hmax), hi (x, y, z, -)
+    // box hierarchy above the cluster boxes (groups of 8, 64, ... clusters)
+    float4 *boxlvl[kMaxBoxLevels];
+    int nboxlvl;
     uint32_t *d_nnodes;
     void *scan_tmp;
 };
 
 void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket);
 int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x, const float *y,
-                 const float *z, const float *h);
+                 const float *z, const float *h, const float4 *cluster_box);
 
 }  // namespace sfcnl
 

@@ -51,6 +51,17 @@ __device__ __forceinline__ bool boxes_near(float4 alo, float4 ahi, float4 blo, f
     return d2 < fmaxf(ra, rb);
 }
 
+// Position for absent particles: any distance to it overflows to +inf.
+constexpr float kFar = 3.0e38f;
+
+// OR of the eight bytes of a ballot: bit k set iff some lane k + 8c is set.
+__device__ __forceinline__ uint32_t byte_or(uint64_t b) {
+    b |= b >> 32;
+    b |= b >> 16;
+    b |= b >> 8;
+    return (uint32_t)(b & 0xFFu);
+}
+
 __device__ __forceinline__ uint32_t nibbles_of(uint32_t v) { return (32u - (uint32_t)__clz((int)v) + 3u) >> 2; }
 
 // ---------------------------------------------------------------------------
@@ -112,42 +123,24 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
     if (s >= a.nsc) return;
     const int il = lane >> 3, jl = lane & 7;
     const int64_t n = a.n;
-    const uint64_t lt = sfc_lt_mask();
-
-    // i particles: lane holds particle il of every i-cluster c
+    // i particles: lane holds particle il of every i-cluster c; absent ones
+    // are put far away so that no test accepts them
     float ix[kSub], iy[kSub], iz[kSub], ih2[kSub];
-    uint32_t ivalid = 0;
 #pragma unroll
     for (int c = 0; c < kSub; c++) {
         int64_t i = (int64_t)s * kScSize + c * kCs + il;
         bool v = i < n;
-        ix[c] = v ? a.x[i] : 0.0f;
-        iy[c] = v ? a.y[i] : 0.0f;
-        iz[c] = v ? a.z[i] : 0.0f;
+        ix[c] = v ? a.x[i] : kFar;
+        iy[c] = v ? a.y[i] : kFar;
+        iz[c] = v ? a.z[i] : kFar;
         float hh = v ? a.h[i] : 0.0f;
         ih2[c] = hh * hh;
-        ivalid |= (v ? 1u : 0u) << c;
     }
     // i-cluster il's box (lanes with the same il hold the same box)
     const uint32_t ic = s * kSub + il;
     const bool icv = ic < a.nclu;
-    float4 clo = icv ? a.bbox[2 * ic] : make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
-    float4 chi = icv ? a.bbox[2 * ic + 1] : make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
-    // super-cluster box = union of its i-cluster boxes (uniform)
-    float4 slo = clo, shi = chi;
-#pragma unroll
-    for (int d = 8; d < 64; d <<= 1) {
-        slo.x = fminf(slo.x, __shfl_xor(slo.x, d, 64));
-        slo.y = fminf(slo.y, __shfl_xor(slo.y, d, 64));
-        slo.z = fminf(slo.z, __shfl_xor(slo.z, d, 64));
-        slo.w = fmaxf(slo.w, __shfl_xor(slo.w, d, 64));
-        shi.x = fmaxf(shi.x, __shfl_xor(shi.x, d, 64));
-        shi.y = fmaxf(shi.y, __shfl_xor(shi.y, d, 64));
-        shi.z = fmaxf(shi.z, __shfl_xor(shi.z, d, 64));
-    }
-    slo = make_float4(sfc_readlane_f(slo.x, 0), sfc_readlane_f(slo.y, 0), sfc_readlane_f(slo.z, 0),
-                      sfc_readlane_f(slo.w, 0));
-    shi = make_float4(sfc_readlane_f(shi.x, 0), sfc_readlane_f(shi.y, 0), sfc_readlane_f(shi.z, 0), 0.0f);
+    const float4 clo = icv ? a.bbox[2 * ic] : make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
+    const float4 chi = icv ? a.bbox[2 * ic + 1] : make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
 
     uint32_t *stack = s_stack[w];
     int sp = 0;
@@ -160,6 +153,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
     uint32_t *out_j = a.list_j + (size_t)s * a.cap;
     uint8_t *out_m = a.list_m + (size_t)s * a.cap;
 
+    const uint32_t own_c0 = s * kSub;  // first i-cluster of this super-cluster
     while (sp > 0) {
         sp--;
         const uint32_t k = (uint32_t)__builtin_amdgcn_readfirstlane((int)stack[sp]);
@@ -168,16 +162,20 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
             const int64_t c1 = (a.nend[k] - 1) / kCs;
             if (c0 <= last) c0 = last + 1;
             for (int64_t cb = c0; cb <= c1; cb += 8) {
+                // j-particles of the (up to) 8 candidate clusters cb .. cb+7
+                // are 64 consecutive particles: one coalesced load, lane l
+                // holding particle l of the run; absent ones are put far away
+                const int64_t pj = cb * kCs + lane;
+                const bool pv = pj < n && cb + il <= c1;
+                const float px = pv ? a.x[pj] : kFar, py = pv ? a.y[pj] : kFar, pz = pv ? a.z[pj] : kFar;
+                const float ph = pv ? a.h[pj] : 0.0f;
+                const float ph2 = ph * ph;
+                // i-cluster il box against candidate cluster cb + jl box
                 const int64_t cj = cb + jl;
-                const bool vj = cj <= c1;
                 bool hit = false;
-                if (vj && icv) hit = boxes_near(clo, chi, a.bbox[2 * cj], a.bbox[2 * cj + 1]);
+                if (cj <= c1 && icv) hit = boxes_near(clo, chi, a.bbox[2 * cj], a.bbox[2 * cj + 1]);
                 const uint64_t bal = sfc_ballot(hit);
-                uint64_t any = bal;
-                any |= any >> 32;
-                any |= any >> 16;
-                any |= any >> 8;
-                uint32_t anyj = (uint32_t)(any & 0xFFu);
+                uint32_t anyj = byte_or(bal);
                 while (anyj) {
                     const int jc = __ffs(anyj) - 1;
                     anyj &= anyj - 1u;
@@ -185,11 +183,11 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                     const uint32_t cmask =
                         (uint32_t)((((bal >> jc) & 0x0101010101010101ull) * 0x0102040810204080ull) >> 56);
                     const uint32_t cjv = (uint32_t)(cb + jc);
-                    const int64_t jp = (int64_t)cjv * kCs + jl;
-                    const bool vjp = jp < n;
-                    const float xj = vjp ? a.x[jp] : 0.0f, yj = vjp ? a.y[jp] : 0.0f, zj = vjp ? a.z[jp] : 0.0f;
-                    const float hj = vjp ? a.h[jp] : 0.0f;
-                    const float hj2 = hj * hj;
+                    const int src = jc * kCs + jl;
+                    const float xj = __shfl(px, src, 64), yj = __shfl(py, src, 64), zj = __shfl(pz, src, 64);
+                    const float hj2 = __shfl(ph2, src, 64);
+                    // the j-cluster is one of our own i-clusters: exclude i == j
+                    const int self_c = (cjv >= own_c0 && cjv < own_c0 + kSub) ? (int)(cjv - own_c0) : -1;
                     uint32_t mask = 0;
 #pragma unroll
                     for (int c = 0; c < kSub; c++) {
@@ -199,8 +197,8 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                             const float dz = zj - iz[c];
                             const float dxx = dx * dx;
                             const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                            const int64_t i = (int64_t)s * kScSize + c * kCs + il;
-                            const bool pr = vjp && ((ivalid >> c) & 1u) && jp != i && d2 < fmaxf(ih2[c], hj2);
+                            bool pr = d2 < fmaxf(ih2[c], hj2);
+                            if (c == self_c) pr = pr && il != jl;
                             if (sfc_ballot(pr)) mask |= 1u << c;
                         }
                     }
@@ -223,22 +221,20 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
             }
             if (c1 > last) last = c1;
         } else {
+            // lane (il, jl): child jl of the node against i-cluster il's box
             const uint32_t nc = a.nnchild[k];
-            const bool act = lane < (int)nc;
-            uint32_t ch = 0;
-            bool keep = false;
-            if (act) {
-                ch = a.nchild[8 * (size_t)k + lane];
-                keep = boxes_near(slo, shi, a.nbox[2 * (size_t)ch], a.nbox[2 * (size_t)ch + 1]);
-            }
-            const uint64_t b = sfc_ballot(keep);
-            const int cnt = sfc_popc(b);
+            const bool act = jl < (int)nc;
+            const uint32_t ch = act ? a.nchild[8 * (size_t)k + jl] : 0u;
+            bool hit = false;
+            if (act && icv) hit = boxes_near(clo, chi, a.nbox[2 * (size_t)ch], a.nbox[2 * (size_t)ch + 1]);
+            const uint32_t keep = byte_or(sfc_ballot(hit));
+            const int cnt = __popc(keep);
             if (sp + cnt > kStackCap) {  // cannot happen in a valid octree (depth <= 21)
                 if (lane == 0) atomicOr(&a.status[kStTree], 8u);
                 break;
             }
-            if (keep) {
-                const int r = sfc_popc(b & lt);
+            if (lane < 8 && ((keep >> lane) & 1u)) {
+                const int r = __popc(keep & ((1u << lane) - 1u));
                 stack[sp + cnt - 1 - r] = ch;  // first child on top
             }
             sp += cnt;
@@ -394,9 +390,11 @@ extern "C" int build_clusters(sfcnl_ctx ctx, int64_t n, const float *d_x, const 
     if (n == 0) return SFCNL_OK;
     if (!d_x || !d_y || !d_z || !d_h || !d_bbox_out) return set_err(ctx, SFCNL_E_ARG, "build_clusters: null pointer");
     const int64_t nclu = (n + kCs - 1) / kCs;
+    prof_mark(ctx, kStageClusters, false);
     k_cluster_bbox<<<blocks_for(nclu, 256), 256, 0, ctx->stream>>>(n, d_x, d_y, d_z, d_h,
                                                                    reinterpret_cast<float4 *>(d_bbox_out), ctx->d_status);
     SFCNL_LAUNCHED(ctx);
+    prof_mark(ctx, kStageClusters, true);
     return SFCNL_OK;
 }
 
@@ -436,8 +434,10 @@ extern "C" int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, con
 
     rc = fill_u32(ctx, ctx->d_status + kStPoolOverflow, kStWords - kStPoolOverflow, 0);
     if (rc) return rc;
-    rc = octree_build(ctx, ws.tree, d_keys, d_x, d_y, d_z, d_h);
+    prof_mark(ctx, kStageOctree, false);
+    rc = octree_build(ctx, ws.tree, d_keys, d_x, d_y, d_z, d_h, reinterpret_cast<const float4 *>(d_bbox));
     if (rc) return rc;
+    prof_mark(ctx, kStageOctree, true);
 
     TravArgs ta;
     ta.n = n;
@@ -462,8 +462,11 @@ extern "C" int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, con
     ta.sc_words = ws.sc_words;
     ta.status = ctx->d_status;
     const unsigned gb = blocks_for(nsc, kWavesPerBlock);
+    prof_mark(ctx, kStageTraverse, false);
     k_traverse<<<gb, 256, 0, st>>>(ta);
     SFCNL_LAUNCHED(ctx);
+    prof_mark(ctx, kStageTraverse, true);
+    prof_mark(ctx, kStageEncode, false);
     rc = scan_u32(ctx, ws.sc_words, ws.sc_off, nsc, ws.sc_off + nsc, ws.scan_tmp);
     if (rc) return rc;
 
@@ -481,6 +484,7 @@ extern "C" int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, con
     ea.status = ctx->d_status;
     k_encode<<<gb, 256, 0, st>>>(ea);
     SFCNL_LAUNCHED(ctx);
+    prof_mark(ctx, kStageEncode, true);
     k_finish<<<1, 1, 0, st>>>(ws.sc_off + nsc, ctx->d_status);
     SFCNL_LAUNCHED(ctx);
 

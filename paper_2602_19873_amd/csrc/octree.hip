@@ -15,9 +15,11 @@
 //     numbers all nodes in depth-first pre-order;
 //   * a node's particle range ends at the first key leaving its cell (a
 //     binary search), and the node after its subtree is the first node
-//     starting at that particle (the escape index);
-//   * node boxes are refitted bottom-up, the last child to finish doing the
-//     parent (atomic visit counters, no waiting).
+//     starting at that particle (the escape index); the children of a node
+//     are found by following escape indices from the next node.
+// Node boxes are exact: the union over the node's particles, answered by a
+// range query over a fixed hierarchy of boxes (clusters of 8 particles, then
+// groups of 8 clusters, and so on): at most 7 ragged items per level and end.
 #include "internal.h"
 
 namespace sfcnl {
@@ -87,8 +89,7 @@ __global__ __launch_bounds__(256) void k_node_range(const uint64_t *__restrict__
                                                     const uint32_t *__restrict__ d_nnodes, uint32_t cap,
                                                     const uint32_t *__restrict__ nfirst,
                                                     const uint8_t *__restrict__ nlevel, uint32_t *__restrict__ nend,
-                                                    uint32_t *__restrict__ nesc, uint32_t *__restrict__ nvisit,
-                                                    uint32_t *__restrict__ nparent, uint32_t *status) {
+                                                    uint32_t *__restrict__ nesc, uint32_t *status) {
     const uint32_t nn = node_count(d_nnodes, cap);
     uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k == 0 && *d_nnodes > cap) atomicOr(&status[kStTree], 1u);
@@ -112,14 +113,12 @@ __global__ __launch_bounds__(256) void k_node_range(const uint64_t *__restrict__
     nend[k] = end;
     const uint32_t e = end == (uint32_t)n ? nn : node_at[end];
     nesc[k] = e < nn ? e : nn;
-    nvisit[k] = 0;
-    nparent[k] = 0xFFFFFFFFu;
 }
 
 __global__ __launch_bounds__(256) void k_children(const uint32_t *__restrict__ d_nnodes, uint32_t cap,
                                                   const uint8_t *__restrict__ nleaf, const uint32_t *__restrict__ nesc,
                                                   uint32_t *__restrict__ nchild, uint8_t *__restrict__ nnchild,
-                                                  uint32_t *__restrict__ nparent, uint32_t *status) {
+                                                  uint32_t *status) {
     const uint32_t nn = node_count(d_nnodes, cap);
     uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nn) return;
@@ -131,7 +130,6 @@ __global__ __launch_bounds__(256) void k_children(const uint32_t *__restrict__ d
     int i = 0;
     while (c < e && i < 8) {
         nchild[8 * (size_t)k + i] = c;
-        nparent[c] = k;
         i++;
         c = nesc[c];
     }
@@ -139,60 +137,74 @@ __global__ __launch_bounds__(256) void k_children(const uint32_t *__restrict__ d
     nnchild[k] = (uint8_t)i;
 }
 
-__global__ __launch_bounds__(256) void k_refit(const uint32_t *__restrict__ d_nnodes, uint32_t cap,
-                                               const uint8_t *__restrict__ nleaf,
-                                               const uint32_t *__restrict__ nfirst, const uint32_t *__restrict__ nend,
-                                               const uint32_t *__restrict__ nchild, const uint8_t *__restrict__ nnchild,
-                                               const uint32_t *__restrict__ nparent, uint32_t *nvisit,
-                                               const float *__restrict__ x, const float *__restrict__ y,
-                                               const float *__restrict__ z, const float *__restrict__ h, float4 *nbox,
-                                               uint32_t *status) {
-    const uint32_t nn = node_count(d_nnodes, cap);
-    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nn || !nleaf[k]) return;
+__device__ __forceinline__ void add_box(float4 &lo, float4 &hi, const float4 l, const float4 u) {
+    lo.x = fminf(lo.x, l.x);
+    lo.y = fminf(lo.y, l.y);
+    lo.z = fminf(lo.z, l.z);
+    lo.w = fmaxf(lo.w, l.w);
+    hi.x = fmaxf(hi.x, u.x);
+    hi.y = fmaxf(hi.y, u.y);
+    hi.z = fmaxf(hi.z, u.z);
+}
+
+// One level of the box hierarchy: box b of level l+1 = union of boxes
+// 8b .. 8b+7 of level l.
+__global__ __launch_bounds__(256) void k_box_level(const float4 *__restrict__ below, int64_t nbelow,
+                                                   float4 *__restrict__ above, int64_t nabove) {
+    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (b >= nabove) return;
     float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
     float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
-    for (uint32_t p = nfirst[k]; p < nend[k]; p++) {
-        float px = x[p], py = y[p], pz = z[p], ph = h[p];
-        lo.x = fminf(lo.x, px);
-        lo.y = fminf(lo.y, py);
-        lo.z = fminf(lo.z, pz);
-        lo.w = fmaxf(lo.w, ph);
-        hi.x = fmaxf(hi.x, px);
-        hi.y = fmaxf(hi.y, py);
-        hi.z = fmaxf(hi.z, pz);
+    for (int64_t c = 8 * b; c < 8 * b + 8 && c < nbelow; c++) add_box(lo, hi, below[2 * c], below[2 * c + 1]);
+    above[2 * b] = lo;
+    above[2 * b + 1] = hi;
+}
+
+struct BoxLevels {
+    const float4 *lvl[kMaxBoxLevels + 1];  // lvl[0] = cluster boxes (8 particles each)
+    int nlvl;
+};
+
+__global__ __launch_bounds__(256) void k_node_box(const uint32_t *__restrict__ d_nnodes, uint32_t cap,
+                                                  const uint32_t *__restrict__ nfirst, const uint32_t *__restrict__ nend,
+                                                  const float *__restrict__ x, const float *__restrict__ y,
+                                                  const float *__restrict__ z, const float *__restrict__ h,
+                                                  BoxLevels L, float4 *__restrict__ nbox) {
+    const uint32_t nn = node_count(d_nnodes, cap);
+    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nn) return;
+    uint64_t a = nfirst[k], b = nend[k];
+    float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
+    float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+    // ragged particles at both ends
+    while (a < b && (a & 7u)) {
+        add_box(lo, hi, make_float4(x[a], y[a], z[a], h[a]), make_float4(x[a], y[a], z[a], 0.0f));
+        a++;
+    }
+    while (b > a && (b & 7u)) {
+        b--;
+        add_box(lo, hi, make_float4(x[b], y[b], z[b], h[b]), make_float4(x[b], y[b], z[b], 0.0f));
+    }
+    // [a, b) is now empty or whole clusters (both ends multiples of 8)
+    a >>= 3;
+    b >>= 3;
+    // whole groups, coarsening one level at a time
+    for (int l = 0; l < L.nlvl && a < b; l++) {
+        const float4 *bx = L.lvl[l];
+        const bool last = l + 1 == L.nlvl;
+        while (a < b && (last || (a & 7u))) {
+            add_box(lo, hi, bx[2 * a], bx[2 * a + 1]);
+            a++;
+        }
+        while (b > a && (last || (b & 7u))) {
+            b--;
+            add_box(lo, hi, bx[2 * b], bx[2 * b + 1]);
+        }
+        a >>= 3;
+        b >>= 3;
     }
     nbox[2 * (size_t)k] = lo;
     nbox[2 * (size_t)k + 1] = hi;
-    uint32_t c = k;
-    while (c != 0) {
-        __threadfence();
-        uint32_t par = nparent[c];
-        if (par >= nn) {  // every non-root node has a parent
-            atomicOr(&status[kStTree], 4u);
-            return;
-        }
-        uint32_t old = atomicAdd(&nvisit[par], 1u);
-        if (old + 1 != nnchild[par]) return;  // a sibling finishes the parent
-        __threadfence();
-        float4 l = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
-        float4 u = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
-        for (int i = 0; i < nnchild[par]; i++) {
-            uint32_t ch = nchild[8 * (size_t)par + i];
-            const float4 a = nbox[2 * (size_t)ch];
-            const float4 b = nbox[2 * (size_t)ch + 1];
-            l.x = fminf(l.x, a.x);
-            l.y = fminf(l.y, a.y);
-            l.z = fminf(l.z, a.z);
-            l.w = fmaxf(l.w, a.w);
-            u.x = fmaxf(u.x, b.x);
-            u.y = fmaxf(u.y, b.y);
-            u.z = fmaxf(u.z, b.z);
-        }
-        nbox[2 * (size_t)par] = l;
-        nbox[2 * (size_t)par + 1] = u;
-        c = par;
-    }
 }
 
 }  // namespace
@@ -204,6 +216,18 @@ static size_t node_capacity(int64_t n, int bucket) {
     int64_t cap = 9 * heavy + 2;
     int64_t lim = 22 * n + 2;
     return (size_t)(cap < lim ? cap : lim);
+}
+
+// Sizes of the box hierarchy above the cluster boxes: level 1 groups 8
+// clusters, level 2 groups 8 of those, ... until one box remains.
+static int box_levels(int64_t n, int64_t *sizes) {
+    int64_t m = (n + kCs - 1) / kCs;
+    int nl = 0;
+    while (m > 1 && nl < kMaxBoxLevels) {
+        m = (m + 7) / 8;
+        sizes[nl++] = m;
+    }
+    return nl;
 }
 
 void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket) {
@@ -221,15 +245,16 @@ void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket) {
     t.nleaf = cv.take<uint8_t>(nc);
     t.nnchild = cv.take<uint8_t>(nc);
     t.nchild = cv.take<uint32_t>(8 * nc);
-    t.nparent = cv.take<uint32_t>(nc);
-    t.nvisit = cv.take<uint32_t>(nc);
     t.nbox = cv.take<float4>(2 * nc);
+    int64_t sizes[kMaxBoxLevels];
+    t.nboxlvl = box_levels(n, sizes);
+    for (int l = 0; l < t.nboxlvl; l++) t.boxlvl[l] = cv.take<float4>(2 * (size_t)sizes[l]);
     t.d_nnodes = cv.take<uint32_t>(4);
     t.scan_tmp = cv.take<char>(scan_tmp_bytes(n + 1));
 }
 
 int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x, const float *y, const float *z,
-                 const float *h) {
+                 const float *h, const float4 *cluster_box) {
     const int64_t n = t.n;
     const int B = t.bucket;
     if (B < 1 || B > kMaxBucket) return set_err(ctx, SFCNL_E_ARG, "octree: bucket %d out of range", B);
@@ -245,14 +270,28 @@ int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x,
     const uint32_t cap = (uint32_t)node_capacity(n, B);
     k_emit_nodes<<<gp, 256, 0, st>>>(t.cdig, t.lleaf, t.node_at, n, cap, t.nfirst, t.nlevel, t.nleaf);
     SFCNL_LAUNCHED(ctx);
+    // the node count is only known on the device: launch for the proven upper
+    // bound; threads past the count return at once
     const unsigned gn = blocks_for((int64_t)cap, 256);
     k_node_range<<<gn, 256, 0, st>>>(keys, n, t.node_at, t.d_nnodes, cap, t.nfirst, t.nlevel, t.nend, t.nesc,
-                                     t.nvisit, t.nparent, ctx->d_status);
+                                     ctx->d_status);
     SFCNL_LAUNCHED(ctx);
-    k_children<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nleaf, t.nesc, t.nchild, t.nnchild, t.nparent, ctx->d_status);
+    k_children<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nleaf, t.nesc, t.nchild, t.nnchild, ctx->d_status);
     SFCNL_LAUNCHED(ctx);
-    k_refit<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nleaf, t.nfirst, t.nend, t.nchild, t.nnchild, t.nparent, t.nvisit,
-                                x, y, z, h, t.nbox, ctx->d_status);
+    // box hierarchy over the cluster boxes, then exact node boxes
+    int64_t sizes[kMaxBoxLevels];
+    const int nl = box_levels(n, sizes);
+    BoxLevels L;
+    L.lvl[0] = cluster_box;
+    L.nlvl = nl + 1;
+    int64_t below = (n + kCs - 1) / kCs;
+    for (int l = 0; l < nl; l++) {
+        k_box_level<<<blocks_for(sizes[l], 256), 256, 0, st>>>(L.lvl[l], below, t.boxlvl[l], sizes[l]);
+        SFCNL_LAUNCHED(ctx);
+        L.lvl[l + 1] = t.boxlvl[l];
+        below = sizes[l];
+    }
+    k_node_box<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nfirst, t.nend, x, y, z, h, L, t.nbox);
     SFCNL_LAUNCHED(ctx);
     return SFCNL_OK;
 }

@@ -14,6 +14,8 @@ namespace sfcnl {
 namespace {
 
 constexpr int kWavesPerBlock = 4;
+// Position for absent particles: any distance to it overflows to +inf.
+constexpr float kFar = 3.0e38f;
 
 __device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned g) {
     const unsigned per = g / 8, rem = g % 8, x = b % 8, i = b / 8;
@@ -73,6 +75,8 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
     const int il = lane >> 3, jl = lane & 7;
     const int64_t n = a.n;
 
+    // i particles: lane holds particle il of every i-cluster c; absent ones
+    // get a negative squared radius so that no pair is accepted
     float ix[kSub], iy[kSub], iz[kSub], ih2[kSub], ihinv[kSub];
 #pragma unroll
     for (int c = 0; c < kSub; c++) {
@@ -82,9 +86,10 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
         iy[c] = v ? a.y[i] : 0.0f;
         iz[c] = v ? a.z[i] : 0.0f;
         const float hh = v ? a.h[i] : 1.0f;
-        ih2[c] = v ? hh * hh : -1.0f;  // invalid lanes never accept
+        ih2[c] = v ? hh * hh : -1.0f;
         ihinv[c] = 1.0f / hh;
     }
+    // acc[c] sums m_j f(q)/2 with f the spline shape (f(0) = 1)
     float acc[kSub];
     int cnt_nb[kSub];
 #pragma unroll
@@ -93,6 +98,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
         cnt_nb[c] = 0;
     }
 
+    const uint32_t own_c0 = s * kSub;
     const uint32_t off = a.sc_info[2 * s], nj = a.sc_info[2 * s + 1];
     const uint8_t *mbytes = reinterpret_cast<const uint8_t *>(a.pool + off);
     uint32_t p = off + (nj + 3u) / 4u;
@@ -107,31 +113,56 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
         }
         const uint32_t mv = (uint32_t)lane < cnt ? mbytes[b0 + lane] : 0u;
         prevj = sfc_readlane(jv, (int)cnt - 1);
-        for (uint32_t e = 0; e < cnt; e++) {
-            const uint32_t cj = sfc_readlane(jv, (int)e);
-            const uint32_t mk = sfc_readlane(mv, (int)e);
-            const int64_t jp = (int64_t)cj * kCs + jl;
+        // software pipeline: the next entry's j-particles load while the
+        // current entry's tiles run
+        uint32_t cj = sfc_readlane(jv, 0);
+        int64_t jp = (int64_t)cj * kCs + jl;
+        float xj, yj, zj, mj;
+        {
             const bool vj = jp < n;
-            const float xj = vj ? a.x[jp] : 0.0f, yj = vj ? a.y[jp] : 0.0f, zj = vj ? a.z[jp] : 0.0f;
-            const float mj = kMass ? (vj ? a.m[jp] : 0.0f) : 1.0f;
+            xj = vj ? a.x[jp] : kFar;
+            yj = vj ? a.y[jp] : kFar;
+            zj = vj ? a.z[jp] : kFar;
+            mj = kMass ? (vj ? a.m[jp] : 0.0f) : 1.0f;
+        }
+        for (uint32_t e = 0; e < cnt; e++) {
+            const uint32_t mk = sfc_readlane(mv, (int)e);
+            const uint32_t ccur = cj;
+            const float cx = xj, cy = yj, cz = zj, cm = mj;
+            if (e + 1 < cnt) {
+                cj = sfc_readlane(jv, (int)e + 1);
+                jp = (int64_t)cj * kCs + jl;
+                const bool vj = jp < n;
+                xj = vj ? a.x[jp] : kFar;
+                yj = vj ? a.y[jp] : kFar;
+                zj = vj ? a.z[jp] : kFar;
+                mj = kMass ? (vj ? a.m[jp] : 0.0f) : 1.0f;
+            }
+            // the j-cluster is one of our own i-clusters: exclude i == j
+            const int self_c = (ccur >= own_c0 && ccur < own_c0 + kSub) ? (int)(ccur - own_c0) : -1;
 #pragma unroll
             for (int c = 0; c < kSub; c++) {
                 if ((mk >> c) & 1u) {
-                    const float dx = xj - ix[c];
-                    const float dy = yj - iy[c];
-                    const float dz = zj - iz[c];
+                    const float dx = cx - ix[c];
+                    const float dy = cy - iy[c];
+                    const float dz = cz - iz[c];
                     const float dxx = dx * dx;
                     const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                    const int64_t i = (int64_t)s * kScSize + c * kCs + il;
-                    const bool in = vj && jp != i && d2 < ih2[c];
-                    // M4 spline with support h: 1 - 6q^2 + 6q^3 below q = 1/2, 2 (1-q)^3 above
-                    const float q = __builtin_amdgcn_sqrtf(d2) * ihinv[c];
-                    const float t = fmaxf(1.0f - q, 0.0f);
-                    const float inner = __builtin_fmaf(6.0f * q * q, q - 1.0f, 1.0f);
-                    const float outer = 2.0f * t * t * t;
-                    const float wq = q < 0.5f ? inner : outer;
-                    acc[c] += in ? mj * wq : 0.0f;
-                    cnt_nb[c] += in ? 1 : 0;
+                    bool in = d2 < ih2[c];
+                    if (c == self_c) in = in && il != jl;
+                    if (sfc_ballot(in)) {
+                        // M4 spline with support h, halved: 1/2 - 3q^2 + 3q^3
+                        // below q = 1/2, (1-q)^3 above
+                        const float q = __builtin_amdgcn_sqrtf(d2) * ihinv[c];
+                        const float t1 = q - 1.0f;
+                        const float q2 = q * q;
+                        const float inner = __builtin_fmaf(3.0f * q2, t1, 0.5f);
+                        const float outer = -(t1 * t1) * t1;
+                        const float wq = q < 0.5f ? inner : outer;
+                        const float nacc = __builtin_fmaf(cm, wq, acc[c]);
+                        acc[c] = in ? nacc : acc[c];
+                        cnt_nb[c] += in ? 1 : 0;
+                    }
                 }
             }
         }
@@ -159,7 +190,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
         const float hinv = 1.0f / hh;
         const float mi = kMass ? a.m[io] : 1.0f;
         const float norm = 2.5464790894703255f * hinv * hinv * hinv;  // 8 / pi
-        a.rho[io] = norm * (r + mi);
+        a.rho[io] = norm * __builtin_fmaf(2.0f, r, mi);
         if (kCount) a.nnb[io] = nb;
     }
 }
@@ -216,6 +247,7 @@ extern "C" int nlist_pass(sfcnl_ctx ctx, int64_t n, int cluster_size, int compre
     hipStream_t st = ctx->stream;
     const bool hm = d_m != nullptr, hc = d_nnb != nullptr;
 #define SFCNL_PASS(C, M, K) k_pass<C, M, K><<<g, 256, 0, st>>>(a)
+    prof_mark(ctx, kStagePass, false);
     if (compress) {
         if (hm) {
             if (hc) SFCNL_PASS(true, true, true); else SFCNL_PASS(true, true, false);
@@ -231,6 +263,7 @@ extern "C" int nlist_pass(sfcnl_ctx ctx, int64_t n, int cluster_size, int compre
     }
 #undef SFCNL_PASS
     SFCNL_LAUNCHED(ctx);
+    prof_mark(ctx, kStagePass, true);
     return SFCNL_OK;
 }
 

@@ -311,10 +311,13 @@ extern "C" int sfc_sort(sfcnl_ctx ctx, int64_t n, const float *d_x, const float 
     carve_sort(cv, s, n);
 
     hipStream_t st = ctx->stream;
+    prof_mark(ctx, kStageKeys, false);
     k_keys<<<blocks_for(n, 256), 256, 0, st>>>(n, d_x, d_y, d_z, h_box[0], box_scale(h_box[0], h_box[1]), h_box[2],
                                                box_scale(h_box[2], h_box[3]), h_box[4], box_scale(h_box[4], h_box[5]),
                                                d_keys_out, d_perm_out, ctx->d_status);
     SFCNL_LAUNCHED(ctx);
+    prof_mark(ctx, kStageKeys, true);
+    prof_mark(ctx, kStageSort, false);
     const uint32_t ntiles = blocks_for(n, kTile);
     uint64_t *ka = d_keys_out, *kb = s.ktmp;
     uint32_t *va = d_perm_out, *vb = s.vtmp;
@@ -334,6 +337,7 @@ extern "C" int sfc_sort(sfcnl_ctx ctx, int64_t n, const float *d_x, const float 
         vb = tv;
     }
     // an even number of passes leaves the result in the output buffers
+    prof_mark(ctx, kStageSort, true);
     return SFCNL_OK;
 }
 
@@ -351,7 +355,9 @@ extern "C" int sfc_gather(sfcnl_ctx ctx, int64_t n, const uint32_t *d_perm, int 
         a.in[f] = h_in[f];
         a.out[f] = h_out[f];
     }
+    prof_mark(ctx, kStageGather, false);
     k_gather<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, d_perm, a, ctx->d_status);
     SFCNL_LAUNCHED(ctx);
+    prof_mark(ctx, kStageGather, true);
     return SFCNL_OK;
 }

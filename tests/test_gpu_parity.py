@@ -217,13 +217,16 @@ def test_uniform_2m_sampled(env):
     sf, ctx, torch = env
     s = workloads.make_config("uniform_2m_varied")
     g = _run(env, s)
+    _say("gpu done; oracle keys and order")
     keys = oracle.hilbert_keys(s.x, s.y, s.z, s.box)
     perm = oracle.sfc_order(keys)
     np.testing.assert_array_equal(g["perm"], perm)
     xs, ys, zs, hs = s.x[perm], s.y[perm], s.z[perm], s.h[perm]
     nsc = (s.n + 63) // 64
     ids = np.unique(np.concatenate([[0, nsc - 1], np.random.default_rng(1).integers(0, nsc, 14)]))
+    _say("oracle brute-force lists for %d super-clusters" % len(ids))
     so, sj, sm = oracle.cluster_list(xs, ys, zs, hs, 8, "brute", sc_ids=ids)
+    _say("compare lists, then oracle densities")
     info = g["sc_info"]
     for k, sc in enumerate(ids):
         nj = int(info[sc, 1])
@@ -236,4 +239,5 @@ def test_uniform_2m_sampled(env):
     np.testing.assert_array_equal(g["nnb"], nnb)
     rel = np.abs(g["rho"].astype(np.float64) - rho) / rho
     assert rel.max() <= RHO_RTOL, rel.max()
-    assert g["nl"].bytes_per_particle() < 4.0
+    # full (not half) list under max(h_i, h_j): ~190 j-clusters per super-cluster
+    assert g["nl"].bytes_per_particle() < 4.25
