@@ -94,7 +94,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--workload", default="uniform_2m_varied")
     ap.add_argument("--compress", type=int, default=1)
-    ap.add_argument("--leaf-bucket", type=int, default=64)
+    ap.add_argument("--leaf-bucket", type=int, default=128)
     ap.add_argument("--cpu-sample", type=int, default=1048576)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()

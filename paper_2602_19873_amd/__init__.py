@@ -152,7 +152,7 @@ def _opts(cluster_size, compress, leaf_bucket, max_j_per_sc):
     return _lib.NlistOpts(cluster_size, int(bool(compress)), leaf_bucket, max_j_per_sc)
 
 
-def build_nlist_workspace(n, cluster_size=CLUSTER_SIZE, compress=True, leaf_bucket=64, max_j_per_sc=512) -> int:
+def build_nlist_workspace(n, cluster_size=CLUSTER_SIZE, compress=True, leaf_bucket=128, max_j_per_sc=512) -> int:
     b = C.c_size_t()
     o = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc)
     if _lib.load().build_nlist_workspace(n, C.byref(o), C.byref(b)) != 0:
@@ -160,7 +160,7 @@ def build_nlist_workspace(n, cluster_size=CLUSTER_SIZE, compress=True, leaf_buck
     return b.value
 
 
-def build_nlist(ctx: Context, keys, x, y, z, h, bbox, compress: bool = True, leaf_bucket: int = 64,
+def build_nlist(ctx: Context, keys, x, y, z, h, bbox, compress: bool = True, leaf_bucket: int = 128,
                 max_j_per_sc: int = 512, cluster_size: int = CLUSTER_SIZE, pool=None, ws=None, sc_info=None,
                 grow: bool = True):
     """Builds the compressed cluster-pair list. Grows the staging list and the
@@ -227,7 +227,7 @@ class Pipeline:
     """The whole path on one system with every buffer preallocated:
     sfc_sort -> sfc_gather -> build_clusters -> build_nlist -> nlist_pass."""
 
-    def __init__(self, ctx: Context, n: int, box, compress: bool = True, leaf_bucket: int = 64,
+    def __init__(self, ctx: Context, n: int, box, compress: bool = True, leaf_bucket: int = 128,
                  max_j_per_sc: int = 512, with_mass: bool = False):
         self.ctx, self.n, self.box = ctx, n, tuple(float(v) for v in box)
         self.compress, self.leaf_bucket, self.max_j_per_sc = compress, leaf_bucket, max_j_per_sc

@@ -95,6 +95,7 @@ int fill_u32(sfcnl_ctx ctx, uint32_t *p, int64_t n, uint32_t v);
 struct Octree {
     int64_t n;
     int bucket;
+    uint32_t node_cap;  // capacity of the per-node and child-slot arrays
     // per particle
     int8_t *cdig;      // common 3-bit digits with the previous key (-1 for particle 0)
     int8_t *lam;       // common digits of key[p] and key[p + bucket] (-1 if out of range)
@@ -105,6 +106,9 @@ struct Octree {
     uint8_t *nlevel, *nleaf, *nnchild;
     uint32_t *nchild;  // 8 per node
     float4 *nbox;      // 2 per node: lo (x, y, z, hmax), hi (x, y, z, -)
+    uint32_t *cbase;   // first child slot of each node, minus one
+    float4 *cs_box;    // child slots: box of the child (2 per slot)
+    uint4 *cs_rec;     // child slots: {first, end, child count, first child slot}
     // box hierarchy above the cluster boxes (groups of 8, 64, ... clusters)
     float4 *boxlvl[kMaxBoxLevels];
     int nboxlvl;

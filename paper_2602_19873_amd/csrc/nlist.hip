@@ -106,9 +106,9 @@ struct TravArgs {
     int compress;
     const float *x, *y, *z, *h;
     const float4 *bbox;
-    const uint32_t *nfirst, *nend, *nchild;
-    const uint8_t *nleaf, *nnchild;
-    const float4 *nbox;
+    const float4 *cs_box;  // octree child slots (slot 0 = root)
+    const uint4 *cs_rec;
+    uint32_t nslots;       // capacity of the slot arrays
     uint32_t *list_j;
     uint8_t *list_m;
     uint32_t *sc_nj, *sc_words;
@@ -116,7 +116,7 @@ struct TravArgs {
 };
 
 __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
-    __shared__ uint32_t s_stack[kWavesPerBlock][kStackCap];
+    __shared__ uint4 s_stack[kWavesPerBlock][kStackCap];
     const int lane = sfc_lane();
     const int w = threadIdx.x / kWave;
     const uint32_t s = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
@@ -142,9 +142,11 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
     const float4 clo = icv ? a.bbox[2 * ic] : make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
     const float4 chi = icv ? a.bbox[2 * ic + 1] : make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
 
-    uint32_t *stack = s_stack[w];
+    // stack of node records {first, end, child count (0 = leaf), first child
+    // slot}; a node is pushed only after its box passed the test
+    uint4 *stack = s_stack[w];
     int sp = 0;
-    if (lane == 0) stack[0] = 0;  // root
+    if (lane == 0) stack[0] = a.cs_rec[0];  // root
     sp = 1;
     wave_sync();
 
@@ -156,24 +158,48 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
     const uint32_t own_c0 = s * kSub;  // first i-cluster of this super-cluster
     while (sp > 0) {
         sp--;
-        const uint32_t k = (uint32_t)__builtin_amdgcn_readfirstlane((int)stack[sp]);
-        if (a.nleaf[k]) {
-            int64_t c0 = a.nfirst[k] / kCs;
-            const int64_t c1 = (a.nend[k] - 1) / kCs;
+        const uint4 rv = stack[sp];
+        const uint32_t nfirst = (uint32_t)__builtin_amdgcn_readfirstlane((int)rv.x);
+        const uint32_t nend = (uint32_t)__builtin_amdgcn_readfirstlane((int)rv.y);
+        const uint32_t nchild = (uint32_t)__builtin_amdgcn_readfirstlane((int)rv.z);
+        const uint32_t cslot = (uint32_t)__builtin_amdgcn_readfirstlane((int)rv.w);
+        if (nend > (uint64_t)n || nfirst >= nend || cslot + nchild > a.nslots) {  // only on a broken tree
+            if (lane == 0) atomicOr(&a.status[kStTree], 16u);
+            break;
+        }
+        if (nchild == 0) {
+            int64_t c0 = nfirst / kCs;
+            const int64_t c1 = (nend - 1) / kCs;
             if (c0 <= last) c0 = last + 1;
-            for (int64_t cb = c0; cb <= c1; cb += 8) {
-                // j-particles of the (up to) 8 candidate clusters cb .. cb+7
-                // are 64 consecutive particles: one coalesced load, lane l
-                // holding particle l of the run; absent ones are put far away
+            // j-particles of the (up to) 8 candidate clusters cb .. cb+7 are
+            // 64 consecutive particles: one coalesced load, lane l holding
+            // particle l of the run; absent ones are put far away. The next
+            // batch of the leaf is loaded while this one is tested.
+            float px, py, pz, ph, nx, ny, nz, nh;
+            float4 blo, bhi, nlo, nhi;
+            auto load_batch = [&](int64_t cb, float &x_, float &y_, float &z_, float &h_, float4 &lo_, float4 &hi_) {
                 const int64_t pj = cb * kCs + lane;
                 const bool pv = pj < n && cb + il <= c1;
-                const float px = pv ? a.x[pj] : kFar, py = pv ? a.y[pj] : kFar, pz = pv ? a.z[pj] : kFar;
-                const float ph = pv ? a.h[pj] : 0.0f;
+                x_ = pv ? a.x[pj] : kFar;
+                y_ = pv ? a.y[pj] : kFar;
+                z_ = pv ? a.z[pj] : kFar;
+                h_ = pv ? a.h[pj] : 0.0f;
+                const int64_t cj = cb + jl;
+                if (cj <= c1) {
+                    lo_ = a.bbox[2 * cj];
+                    hi_ = a.bbox[2 * cj + 1];
+                } else {
+                    lo_ = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
+                    hi_ = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+                }
+            };
+            if (c0 <= c1) load_batch(c0, nx, ny, nz, nh, nlo, nhi);
+            for (int64_t cb = c0; cb <= c1; cb += 8) {
+                px = nx; py = ny; pz = nz; ph = nh; blo = nlo; bhi = nhi;
+                if (cb + 8 <= c1) load_batch(cb + 8, nx, ny, nz, nh, nlo, nhi);
                 const float ph2 = ph * ph;
                 // i-cluster il box against candidate cluster cb + jl box
-                const int64_t cj = cb + jl;
-                bool hit = false;
-                if (cj <= c1 && icv) hit = boxes_near(clo, chi, a.bbox[2 * cj], a.bbox[2 * cj + 1]);
+                const bool hit = icv && boxes_near(clo, chi, blo, bhi);
                 const uint64_t bal = sfc_ballot(hit);
                 uint32_t anyj = byte_or(bal);
                 while (anyj) {
@@ -222,11 +248,15 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
             if (c1 > last) last = c1;
         } else {
             // lane (il, jl): child jl of the node against i-cluster il's box
-            const uint32_t nc = a.nnchild[k];
-            const bool act = jl < (int)nc;
-            const uint32_t ch = act ? a.nchild[8 * (size_t)k + jl] : 0u;
+            const bool act = jl < (int)nchild;
+            const uint32_t slot = cslot + (uint32_t)jl;
             bool hit = false;
-            if (act && icv) hit = boxes_near(clo, chi, a.nbox[2 * (size_t)ch], a.nbox[2 * (size_t)ch + 1]);
+            uint4 crec = make_uint4(0u, 0u, 0u, 0u);
+            if (act) {
+                const float4 lo = a.cs_box[2 * (size_t)slot], hi = a.cs_box[2 * (size_t)slot + 1];
+                crec = a.cs_rec[slot];
+                hit = icv && boxes_near(clo, chi, lo, hi);
+            }
             const uint32_t keep = byte_or(sfc_ballot(hit));
             const int cnt = __popc(keep);
             if (sp + cnt > kStackCap) {  // cannot happen in a valid octree (depth <= 21)
@@ -235,7 +265,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
             }
             if (lane < 8 && ((keep >> lane) & 1u)) {
                 const int r = __popc(keep & ((1u << lane) - 1u));
-                stack[sp + cnt - 1 - r] = ch;  // first child on top
+                stack[sp + cnt - 1 - r] = crec;  // first child on top
             }
             sp += cnt;
             wave_sync();
@@ -450,12 +480,9 @@ extern "C" int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, con
     ta.z = d_z;
     ta.h = d_h;
     ta.bbox = reinterpret_cast<const float4 *>(d_bbox);
-    ta.nfirst = ws.tree.nfirst;
-    ta.nend = ws.tree.nend;
-    ta.nchild = ws.tree.nchild;
-    ta.nleaf = ws.tree.nleaf;
-    ta.nnchild = ws.tree.nnchild;
-    ta.nbox = ws.tree.nbox;
+    ta.cs_box = ws.tree.cs_box;
+    ta.cs_rec = ws.tree.cs_rec;
+    ta.nslots = ws.tree.node_cap;
     ta.list_j = ws.list_j;
     ta.list_m = ws.list_m;
     ta.sc_nj = ws.sc_nj;

@@ -207,6 +207,46 @@ __global__ __launch_bounds__(256) void k_node_box(const uint32_t *__restrict__ d
     nbox[2 * (size_t)k + 1] = hi;
 }
 
+// Child counts as u32 for the prefix sum that places every node's children
+// in one contiguous run of child slots.
+__global__ __launch_bounds__(256) void k_child_count(const uint32_t *__restrict__ d_nnodes, uint32_t cap,
+                                                     const uint8_t *__restrict__ nnchild, uint32_t *__restrict__ cbase) {
+    const uint32_t nn = node_count(d_nnodes, cap);
+    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nn) return;
+    cbase[k] = nnchild[k];
+}
+
+// Child slot 0 holds the root; node k's children occupy slots
+// 1 + cbase[k] ... in key order. A slot carries the child's box and its
+// record {first, end, child count (0 = leaf), first child slot}, so the
+// traversal reads everything about a child with one round trip.
+__global__ __launch_bounds__(256) void k_child_slots(const uint32_t *__restrict__ d_nnodes, uint32_t cap,
+                                                     const uint32_t *__restrict__ nfirst,
+                                                     const uint32_t *__restrict__ nend,
+                                                     const uint32_t *__restrict__ nchild,
+                                                     const uint8_t *__restrict__ nnchild,
+                                                     const uint32_t *__restrict__ cbase, const float4 *__restrict__ nbox,
+                                                     float4 *__restrict__ cs_box, uint4 *__restrict__ cs_rec) {
+    const uint32_t nn = node_count(d_nnodes, cap);
+    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k >= nn) return;
+    if (k == 0) {
+        cs_box[0] = nbox[0];
+        cs_box[1] = nbox[1];
+        cs_rec[0] = make_uint4(nfirst[0], nend[0], nnchild[0], 1u + cbase[0]);
+    }
+    const uint32_t nc = nnchild[k];
+    for (uint32_t i = 0; i < nc; i++) {
+        const uint32_t c = nchild[8 * (size_t)k + i];
+        const uint32_t slot = 1u + cbase[k] + i;
+        if (c >= nn || slot >= cap) continue;  // only on a broken tree (reported elsewhere)
+        cs_box[2 * (size_t)slot] = nbox[2 * (size_t)c];
+        cs_box[2 * (size_t)slot + 1] = nbox[2 * (size_t)c + 1];
+        cs_rec[slot] = make_uint4(nfirst[c], nend[c], nnchild[c], 1u + cbase[c]);
+    }
+}
+
 }  // namespace
 
 static size_t node_capacity(int64_t n, int bucket) {
@@ -234,6 +274,7 @@ void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket) {
     t.n = n;
     t.bucket = bucket;
     size_t nc = node_capacity(n, bucket);
+    t.node_cap = (uint32_t)nc;
     t.cdig = cv.take<int8_t>((size_t)n);
     t.lam = cv.take<int8_t>((size_t)n);
     t.lleaf = cv.take<int8_t>((size_t)n);
@@ -246,11 +287,14 @@ void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket) {
     t.nnchild = cv.take<uint8_t>(nc);
     t.nchild = cv.take<uint32_t>(8 * nc);
     t.nbox = cv.take<float4>(2 * nc);
+    t.cbase = cv.take<uint32_t>(nc);
+    t.cs_box = cv.take<float4>(2 * nc);
+    t.cs_rec = cv.take<uint4>(nc);
     int64_t sizes[kMaxBoxLevels];
     t.nboxlvl = box_levels(n, sizes);
     for (int l = 0; l < t.nboxlvl; l++) t.boxlvl[l] = cv.take<float4>(2 * (size_t)sizes[l]);
     t.d_nnodes = cv.take<uint32_t>(4);
-    t.scan_tmp = cv.take<char>(scan_tmp_bytes(n + 1));
+    t.scan_tmp = cv.take<char>(scan_tmp_bytes((int64_t)nc > n + 1 ? (int64_t)nc : n + 1));
 }
 
 int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x, const float *y, const float *z,
@@ -292,6 +336,15 @@ int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x,
         below = sizes[l];
     }
     k_node_box<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nfirst, t.nend, x, y, z, h, L, t.nbox);
+    SFCNL_LAUNCHED(ctx);
+    // contiguous child slots (the node count is on the device: scan the
+    // capacity, counts past the node count are never read)
+    k_child_count<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nnchild, t.cbase);
+    SFCNL_LAUNCHED(ctx);
+    rc = scan_u32(ctx, t.cbase, t.cbase, (int64_t)cap, nullptr, t.scan_tmp);
+    if (rc) return rc;
+    k_child_slots<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nfirst, t.nend, t.nchild, t.nnchild, t.cbase, t.nbox,
+                                      t.cs_box, t.cs_rec);
     SFCNL_LAUNCHED(ctx);
     return SFCNL_OK;
 }
