@@ -12,7 +12,6 @@ from __future__ import annotations
 
 import argparse
 import json
-import math
 import os
 import sys
 import time
@@ -36,6 +35,8 @@ BYTES_PER_PARTICLE = {
     "clusters": 16 + 4,            # read x, y, z, h; write 32 B per 8-particle cluster
 }
 FLOPS_PER_TEST = 10     # dx, dy, dz (3); dx*dx (1); 2 fma (4); max of radii (1); compare (1)
+# Counted tests and evaluations: 64 per set mask bit of the final list (the 8x8
+# tiles that establish the list in the build and that the pass evaluates).
 FLOPS_PER_PAIR = 17     # dx, dy, dz (3); d2 (5); sqrt (1); q (1); spline piece (5); m*W, += (2)
 
 
@@ -64,27 +65,49 @@ def list_stats(sf, ctx, nl):
         "entries": int(nj.sum()),
         "mean_nj": float(nj.mean()) if nj.size else 0.0,
         "max_nj": int(nj.max()) if nj.size else 0,
-        "tile_pairs": int(pc) * 64,        # 8x8 pair evaluations in the pass
-        "exact_tests_min": int(nj.sum()) * 512,  # 64 i x 8 j tests per listed cluster pair
+        "tile_pairs": int(pc) * 64,        # 64 pair tests per set mask bit (8x8 tile)
     }
 
 
-def cpu_baseline(n_sample):
-    """The oracle on a bounded sample of the same workload (same generator and
-    neighbour count, fewer particles): keys, stable order, cluster list,
-    encoding, FP64 density."""
+def cpu_baseline(s):
+    """The oracle, as it stands, on the timed workload itself: keys, stable
+    order, cell-list cluster list, encoding, FP64 density."""
     import oracle
-    from paper_2602_19873_amd import workloads
-    s = workloads.uniform_varied(n_sample, workloads.SEED_BASE + 2)
     oracle.build()
     t0 = time.perf_counter()
     oracle.pipeline(s.x, s.y, s.z, s.h, s.box)
     dt = time.perf_counter() - t0
-    return {"value": n_sample / dt / 1e6, "unit": "Mparticles/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "uniform_varied N=%d (same generator and ~200 neighbours as the timed workload), "
-                      "full oracle path: keys, stable sort, cell-list cluster list, encoding, FP64 density; "
-                      "%.1f s" % (n_sample, dt),
+    return {"value": s.n / dt / 1e6, "unit": "Mparticles/s", "cores": oracle.num_threads(), "kind": "oracle",
+            "sample": "the full timed workload (%s, N=%d), one run of the whole oracle path: Hilbert keys, "
+                      "stable sort, cell-list cluster list, nibble encoding, FP64 density; %.1f s"
+                      % (s.name, s.n, dt),
             "seconds": dt}
+
+
+def source_sha(path):
+    import hashlib
+    with open(path, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()[:12]
+
+
+def read_traffic(kernel, n):
+    """HBM bytes per launch of `kernel` from the committed counter summary, or
+    None if there is none or the kernel's source changed since it was taken."""
+    path = os.path.join(ROOT, "profiles", "counters_uniform_2m.txt")
+    if not os.path.exists(path):
+        return None
+    rec = {}
+    with open(path) as f:
+        for line in f:
+            if line.startswith("traffic "):
+                kv = dict(t.split("=", 1) for t in line.split()[1:])
+                rec[kv["kernel"]] = kv
+    kv = rec.get(kernel)
+    if not kv or int(kv["n"]) != n:
+        return None
+    if kv["source_sha"] != source_sha(os.path.join(ROOT, "paper_2602_19873_amd", "csrc", kv["source"])):
+        return None
+    return float(kv["bytes_per_launch"])
 
 
 def main():
@@ -95,7 +118,8 @@ def main():
     ap.add_argument("--workload", default="uniform_2m_varied")
     ap.add_argument("--compress", type=int, default=1)
     ap.add_argument("--leaf-bucket", type=int, default=128)
-    ap.add_argument("--cpu-sample", type=int, default=1048576)
+    ap.add_argument("--copy-probe", type=int, default=0,
+                    help="after warm-up, copy this many MiB once (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     args = ap.parse_args()
 
@@ -122,6 +146,13 @@ def main():
         pipe.step(x, y, z, h)
     torch.cuda.synchronize()
     log("warmup done")
+    if args.copy_probe:
+        src = torch.empty(args.copy_probe << 20, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        log("copy probe: %d MiB" % args.copy_probe)
 
     ctx.profile_begin(args.steps)
     torch.cuda.synchronize()
@@ -146,7 +177,7 @@ def main():
             gbs = BYTES_PER_PARTICLE[name] * n / (avg * 1e-3) / 1e9
             d.update(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS)
         elif name == "traverse":
-            tf = st["exact_tests_min"] * FLOPS_PER_TEST / (avg * 1e-3) / 1e12
+            tf = st["tile_pairs"] * FLOPS_PER_TEST / (avg * 1e-3) / 1e12
             d.update(bound="alu", achieved=tf, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s", frac=tf / FP32_PEAK_TFLOPS)
         elif name == "pass":
             tf = st["tile_pairs"] * FLOPS_PER_PAIR / (avg * 1e-3) / 1e12
@@ -154,8 +185,11 @@ def main():
         stages[name] = d
     dom = max((k for k in stages if "bound" in stages[k]), key=lambda k: stages[k]["ms"])
     dd = stages[dom]
-    roofline = {"kernel": dom, "bound": dd["bound"], "achieved": dd["achieved"], "peak": dd["peak"],
-                "unit": dd["unit"], "frac": dd["frac"], "traffic": None}
+    kernel_of = {"traverse": ("k_traverse", "nlist.hip"), "pass": ("k_pass", "pass.hip")}
+    traffic = read_traffic(kernel_of[dom][0], n) if dom in kernel_of else None
+    roofline = {"kernel": kernel_of.get(dom, (dom,))[0], "bound": dd["bound"], "achieved": dd["achieved"],
+                "peak": dd["peak"], "unit": dd["unit"], "frac": dd["frac"], "traffic": traffic,
+                "avg_ms": dd["ms"]}
 
     out = {
         "metric": METRIC, "value": value, "unit": "Mparticles/s", "n_gpus": 1, "steps": args.steps,
@@ -171,8 +205,8 @@ def main():
         "roofline": roofline,
     }
     if not args.no_cpu_baseline:
-        log("cpu baseline (oracle) on %d particles" % args.cpu_sample)
-        out["cpu_baseline"] = cpu_baseline(args.cpu_sample)
+        log("cpu baseline (oracle) on %d particles" % n)
+        out["cpu_baseline"] = cpu_baseline(s)
     ctx.close()
     print(json.dumps(out), flush=True)
 
