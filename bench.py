@@ -110,6 +110,45 @@ def read_traffic(kernel, n):
     return float(kv["bytes_per_launch"])
 
 
+def run_hiter(args, sf, torch, ctx):
+    """Time to drive every particle of the 1/r sphere to target +- 1 own-radius
+    neighbours from the plain starting guess (one global mean-density radius),
+    by list rebuilds. Positions are fixed, so the SFC order is computed once
+    outside the timed region."""
+    from paper_2602_19873_amd import workloads
+    T = args.target
+    s = workloads.evrard_sphere(args.n or 8388608, workloads.SEED_BASE + 3, target=T, seed_h=args.seed_h)
+    n = s.n
+    log("h-iteration: %s n=%d target=%d seed=%s" % (s.name, n, T, args.seed_h))
+    dev = torch.device("cuda:0")
+    x, y, z, h = (torch.from_numpy(a).to(dev) for a in (s.x, s.y, s.z, s.h))
+    keys, perm = sf.sfc_sort(ctx, x, y, z, s.box)
+    xs, ys, zs, h0 = sf.sfc_gather(ctx, perm, [x, y, z, h])
+    hw = torch.empty_like(h0)
+    bufs = {}
+    times, rounds = [], []
+    for rep in range(args.warmup + args.steps):
+        hw.copy_(h0)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        res = sf.h_iterate(ctx, keys, xs, ys, zs, hw, target=T, tol=1, max_iters=64, **bufs)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        bufs = dict(ws=res.nl.ws, pool=res.nl.pool, max_j_per_sc=res.nl.max_j_per_sc)
+        if rep >= args.warmup:
+            times.append(dt)
+            rounds.append(res.iters)
+        log("rep %d: %d rounds, %.1f ms, converged=%s" % (rep, res.iters, dt * 1e3, res.converged))
+    t = sorted(times)[len(times) // 2]
+    out = {"metric": "h-iteration to target +- 1 neighbours, Mparticles/s (N / time to convergence)",
+           "value": n / t / 1e6, "unit": "Mparticles/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
+           "ms_to_converge": t * 1e3, "rounds": rounds[0], "ms_per_round": t * 1e3 / rounds[0],
+           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": s.name, "n": n, "target": T, "tol": 1, "seed_h": args.seed_h,
+                      "cluster_size": 8}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +160,10 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after warm-up, copy this many MiB once (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--mode", choices=["step", "hiter"], default="step")
+    ap.add_argument("--target", type=int, default=100)
+    ap.add_argument("--seed-h", choices=["global", "analytic"], default="global")
+    ap.add_argument("--n", type=int, default=0)
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -132,6 +175,13 @@ def main():
     import numpy as np
     import torch
     import paper_2602_19873_amd as sf
+
+    if args.mode == "hiter":
+        torch.cuda.set_device(0)
+        ctx = sf.Context(0)
+        run_hiter(args, sf, torch, ctx)
+        ctx.close()
+        return
 
     s = make_workload(args.workload)
     n = s.n

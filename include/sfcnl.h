@@ -41,6 +41,7 @@ extern "C" {
 #define SFCNL_E_INPUT (-2)    /* non-finite position or bad radius found on the device */
 #define SFCNL_E_CAPACITY (-3) /* output or workspace too small; required sizes reported */
 #define SFCNL_E_HIP (-4)      /* a HIP runtime call failed */
+#define SFCNL_E_NOCONV (-5)   /* sfcnl_h_iterate: iteration limit reached, particles unconverged */
 
 /* Super-cluster size: 64 particles, one wavefront (Sec. II-A). */
 #define SFCNL_SC_SIZE 64
@@ -154,6 +155,42 @@ int nlist_pass(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, const u
  * check the device decoder on its own. */
 int nlist_decode(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, const uint32_t *d_sc_info,
                  const uint32_t *d_pool, const uint32_t *d_offsets, uint32_t *d_j, uint16_t *d_mask);
+
+/* ---- 5. Smoothing-length iteration -----------------------------------------
+ * Drives every particle's radius h_i to `target` +- `tol` own-radius
+ * neighbours (the count n_i of nlist_pass) by rebuilding the list. The paper
+ * rebuilds its list every step with variable radii (Sec. IV); the iteration
+ * rule itself is this library's:
+ *   converged      |n_i - target| <= tol: h_i is left unchanged (n_i depends on
+ *                  h_i only, so it stays converged);
+ *   otherwise      the bracket is narrowed (lo_i = h_i if n_i < target - tol,
+ *                  hi_i = h_i if n_i > target + tol), then
+ *                  h' = 2 h_i if n_i = 0, else h_i * cbrt(target / n_i) clamped
+ *                  to [h_i / 2, 2 h_i]; if h' is not strictly inside
+ *                  (lo_i, hi_i), h' = (lo_i + hi_i) / 2 (or hi_i / 2 while
+ *                  lo_i = 0, 2 lo_i while hi_i is unbounded).
+ * Each round: build_clusters, build_nlist, nlist_pass, update; it stops when no
+ * particle moved, after max_iters rounds, or on an error.
+ * Arrays are in SFC order (sfc_sort + sfc_gather). d_h is updated in place.
+ * d_bracket [2n] holds {lo_i, hi_i}; it is initialised to {0, +inf} unless
+ * opts->resume is set, which continues an interrupted run (for instance after
+ * SFCNL_E_CAPACITY, with larger buffers). On SFCNL_OK the list, d_rho and
+ * d_nnb describe the final radii. Returns SFCNL_E_NOCONV when max_iters rounds
+ * left *h_unconverged particles unconverged. d_bbox is caller scratch of
+ * 8 floats per cluster. *h_iters counts the rounds of this call. */
+typedef struct {
+    int target;
+    int tol;
+    int max_iters;
+    int resume;
+} sfcnl_hiter_opts;
+
+int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_x, const float *d_y,
+                    const float *d_z, float *d_h, float *d_bracket, const float *d_m,
+                    const sfcnl_nlist_opts *nl_opts, const sfcnl_hiter_opts *it_opts, float *d_bbox, void *d_ws,
+                    size_t ws_bytes, uint32_t *d_sc_info, uint32_t *d_pool, size_t pool_bytes, float *d_rho,
+                    int32_t *d_nnb, int *h_iters, int64_t *h_unconverged, size_t *h_used_bytes,
+                    int64_t *h_max_nj);
 
 /* ---- Stage timing -------------------------------------------------------
  * When enabled, every call brackets each of its stages with a pair of HIP

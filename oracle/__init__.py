@@ -291,3 +291,43 @@ def pipeline(x, y, z, h, box, m=None, cs: int = 8, compress: bool = True, method
     rho, nnb = density(xs, ys, zs, hs, ms, method)
     return dict(keys=keys, perm=perm, sorted_keys=keys[perm], x=xs, y=ys, z=zs, h=hs, m=ms,
                 offs=offs, j=jj, mask=mm, sc_info=info, pool=pool, rho=rho, nnb=nnb)
+
+
+# --------------------------------------------------------------------------
+# Smoothing-length iteration (not from the paper: the rule this project uses
+# to drive each particle to a target own-radius neighbour count; the paper
+# rebuilds its list every step with per-particle radii, Sec. IV)
+# --------------------------------------------------------------------------
+
+def h_iterate(x, y, z, h0, target: int, tol: int = 1, max_iters: int = 64, method: str = "grid"):
+    """Plain reference of the rule: a particle with |n - target| <= tol keeps
+    its h; otherwise its bracket narrows (lower bound if too few neighbours,
+    upper if too many) and h moves to 2h (n = 0) or h (target/n)^(1/3) clamped
+    to [h/2, 2h], replaced by the bracket midpoint (or the doubled lower /
+    halved upper bound while one side is open) when outside the bracket.
+    Update arithmetic in FP64, h stored in FP32, counts from density().
+    Returns (h, rounds, unconverged)."""
+    h = np.ascontiguousarray(h0, dtype=np.float32).copy()
+    n = h.shape[0]
+    lo = np.zeros(n)
+    hi = np.full(n, np.inf)
+    for it in range(max_iters):
+        _, cnt = density(x, y, z, h, None, method)
+        dev = cnt.astype(np.int64) - target
+        move = np.abs(dev) > tol
+        if not move.any():
+            return h, it + 1, 0
+        hc = h.astype(np.float64)
+        few = move & (dev < 0)
+        many = move & (dev > 0)
+        lo[few] = np.maximum(lo[few], hc[few])
+        hi[many] = np.minimum(hi[many], hc[many])
+        with np.errstate(divide="ignore"):
+            hn = np.where(cnt == 0, 2.0 * hc, hc * np.cbrt(target / np.maximum(cnt, 1)))
+        hn = np.where(cnt == 0, hn, np.clip(hn, 0.5 * hc, 2.0 * hc))
+        out = ~((hn > lo) & (hn < hi))
+        mid = np.where(np.isinf(hi), 2.0 * lo, np.where(lo == 0.0, 0.5 * hi, 0.5 * (lo + hi)))
+        hn = np.where(out, mid, hn)
+        h = np.where(move, hn, hc).astype(np.float32)
+    _, cnt = density(x, y, z, h, None, method)
+    return h, max_iters, int((np.abs(cnt.astype(np.int64) - target) > tol).sum())

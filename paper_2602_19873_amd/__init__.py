@@ -20,7 +20,8 @@ import torch
 from . import _lib
 
 __all__ = ["Context", "NeighbourList", "SfcnlError", "sfc_sort", "sfc_gather", "build_clusters",
-           "build_nlist", "nlist_pass", "nlist_decode", "Pipeline", "SC_SIZE", "CLUSTER_SIZE"]
+           "build_nlist", "nlist_pass", "nlist_decode", "h_iterate", "HIterResult", "Pipeline", "SC_SIZE",
+           "CLUSTER_SIZE"]
 
 SC_SIZE = 64
 CLUSTER_SIZE = 8
@@ -221,6 +222,67 @@ def nlist_decode(ctx: Context, nl: NeighbourList):
                                    _ptr(nl.pool), _ptr(d_offs), _ptr(j), _ptr(m)))
     torch.cuda.synchronize(nl.sc_info.device)
     return offs, j[:total].cpu().numpy().view(np.uint32), m[:total].cpu().numpy().view(np.uint16)
+
+
+@dataclass
+class HIterResult:
+    iters: int            # rounds run (over all resumed calls)
+    unconverged: int      # particles outside target +- tol after the last round
+    converged: bool
+    nl: NeighbourList     # list at the final radii (valid when converged)
+    rho: torch.Tensor
+    nnb: torch.Tensor
+
+
+def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, max_iters: int = 64, m=None,
+              compress: bool = True, leaf_bucket: int = 128, max_j_per_sc: int = 512, bracket=None, bbox=None,
+              ws=None, pool=None, sc_info=None, rho=None, nnb=None, raise_noconv: bool = False,
+              resume: bool = False):
+    """Iterates the SFC-ordered radii h (updated in place) to target +- tol
+    own-radius neighbours (sfcnl_h_iterate). Grows list buffers and resumes
+    when the library reports them too small."""
+    n = x.numel()
+    nsc = (n + SC_SIZE - 1) // SC_SIZE
+    nc = (n + CLUSTER_SIZE - 1) // CLUSTER_SIZE
+    e = ctx.empty
+    bracket = e(max(2 * n, 2), torch.float32) if bracket is None else bracket
+    bbox = e((max(nc, 1), 8), torch.float32) if bbox is None else bbox
+    sc_info = e((max(nsc, 1), 2), torch.int32) if sc_info is None else sc_info
+    pool = e(max(1024, 6 * n), torch.int32) if pool is None else pool
+    rho = e(max(n, 1), torch.float32) if rho is None else rho
+    nnb = e(max(n, 1), torch.int32) if nnb is None else nnb
+    total, resume = 0, int(bool(resume))
+    while True:
+        if total >= max_iters:
+            nl = NeighbourList(n, CLUSTER_SIZE, bool(compress), sc_info[:nsc], pool, 0, 0)
+            return HIterResult(total, n, False, nl, rho, nnb)
+        need = build_nlist_workspace(n, CLUSTER_SIZE, compress, leaf_bucket, max_j_per_sc)
+        if ws is None or ws.numel() < need:
+            ws = e(max(need, 1), torch.uint8)
+        no = _opts(CLUSTER_SIZE, compress, leaf_bucket, max_j_per_sc)
+        io = _lib.HiterOpts(target, tol, max_iters - total, resume)
+        iters, unconv, used, maxnj = C.c_int(), C.c_int64(), C.c_size_t(), C.c_int64()
+        rc = ctx.lib.sfcnl_h_iterate(ctx.handle, n, _ptr(keys), _ptr(x), _ptr(y), _ptr(z), _ptr(h), _ptr(bracket),
+                                     _ptr(m), C.byref(no), C.byref(io), _ptr(bbox), _ptr(ws), ws.numel(),
+                                     _ptr(sc_info), _ptr(pool), pool.numel() * 4, _ptr(rho), _ptr(nnb),
+                                     C.byref(iters), C.byref(unconv), C.byref(used), C.byref(maxnj))
+        total += iters.value
+        if rc == _lib.E_CAPACITY:
+            # the round that overflowed did not update h (only completed
+            # rounds are counted): run it again with room
+            if maxnj.value > max_j_per_sc:
+                max_j_per_sc = int(maxnj.value)
+            if used.value > pool.numel() * 4:
+                pool = e(used.value // 4 + 1024, torch.int32)
+            resume = 1
+            continue
+        if rc == _lib.E_NOCONV and not raise_noconv:
+            nl = NeighbourList(n, CLUSTER_SIZE, bool(compress), sc_info[:nsc], pool, used.value, maxnj.value)
+            return HIterResult(total, unconv.value, False, nl, rho, nnb)
+        ctx.check(rc)
+        nl = NeighbourList(n, CLUSTER_SIZE, bool(compress), sc_info[:nsc], pool, used.value, maxnj.value)
+        nl.ws, nl.max_j_per_sc = ws, max_j_per_sc
+        return HIterResult(total, unconv.value, True, nl, rho, nnb)
 
 
 class Pipeline:

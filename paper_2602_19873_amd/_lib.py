@@ -15,11 +15,12 @@ E_ARG = -1
 E_INPUT = -2
 E_CAPACITY = -3
 E_HIP = -4
+E_NOCONV = -5
 
 SYMBOLS = [
     "sfcnl_create", "sfcnl_destroy", "sfcnl_set_stream", "sfcnl_last_error", "sfcnl_sync", "sfcnl_version",
     "sfc_sort_workspace", "sfc_sort", "sfc_gather", "build_clusters", "build_nlist_workspace", "build_nlist",
-    "nlist_pass", "nlist_decode", "sfcnl_profile_begin", "sfcnl_profile_end",
+    "nlist_pass", "nlist_decode", "sfcnl_profile_begin", "sfcnl_profile_end", "sfcnl_h_iterate",
 ]
 
 NSTAGE = 8
@@ -29,6 +30,10 @@ STAGES = ["keys", "sort", "gather", "clusters", "octree", "traverse", "encode", 
 class NlistOpts(C.Structure):
     _fields_ = [("cluster_size", C.c_int), ("compress", C.c_int), ("leaf_bucket", C.c_int),
                 ("max_j_per_sc", C.c_int)]
+
+
+class HiterOpts(C.Structure):
+    _fields_ = [("target", C.c_int), ("tol", C.c_int), ("max_iters", C.c_int), ("resume", C.c_int)]
 
 
 _lib = None
@@ -72,6 +77,10 @@ def load():
     lib.nlist_pass.restype = i32
     lib.nlist_decode.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp]
     lib.nlist_decode.restype = i32
+    lib.sfcnl_h_iterate.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, C.POINTER(NlistOpts), C.POINTER(HiterOpts),
+                                    vp, vp, sz, vp, vp, sz, vp, vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(sz),
+                                    C.POINTER(i64)]
+    lib.sfcnl_h_iterate.restype = i32
     lib.sfcnl_profile_begin.argtypes = [vp, i32]
     lib.sfcnl_profile_begin.restype = i32
     lib.sfcnl_profile_end.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]

@@ -25,6 +25,7 @@ enum StatusWord : int {
     kStTotalLo = 3,      // total pool words (exclusive scan total)
     kStScratch = 4,      // set if a staging list overflowed
     kStTree = 5,         // octree invariant broken (internal error)
+    kStUnconverged = 6,  // h iteration: particles that moved this round
     kStWords = 16
 };
 

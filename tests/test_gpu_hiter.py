@@ -1,0 +1,102 @@
+"""Smoothing-length iteration on the GPU (sfcnl_h_iterate through the C ABI).
+
+The trajectory of h is not compared (cbrt differs between libraries); what
+is checked: the oracle, given the GPU's final radii, finds every particle
+within target +- tol, the same counts, the same list bytes and densities
+within 1e-5."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_19873_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2602_19873_amd as sf
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    torch.cuda.set_device(0)
+    ctx = sf.Context(0)
+    yield sf, ctx, torch
+    ctx.close()
+
+
+def _sorted_inputs(env, s):
+    sf, ctx, torch = env
+    dev = torch.device("cuda:0")
+    x, y, z, h = (torch.from_numpy(np.ascontiguousarray(a)).to(dev) for a in (s.x, s.y, s.z, s.h))
+    keys, perm = sf.sfc_sort(ctx, x, y, z, s.box)
+    xs, ys, zs, hs = sf.sfc_gather(ctx, perm, [x, y, z, h])
+    return keys, xs, ys, zs, hs
+
+
+def _check_final(s_sorted, res, T, tol):
+    xs, ys, zs, hf = s_sorted
+    rho, cnt = oracle.density(xs, ys, zs, hf, None, "grid")
+    assert np.all(np.abs(cnt - T) <= tol)
+    np.testing.assert_array_equal(res.nnb.cpu().numpy()[: len(xs)], cnt)
+    rel = np.abs(res.rho.cpu().numpy()[: len(xs)].astype(np.float64) - rho) / rho
+    assert rel.max() <= 1e-5
+    offs, jj, mm = oracle.cluster_list(xs, ys, zs, hf, 8, "grid")
+    info, pool = oracle.encode_all(offs, jj, mm, 8, True)
+    np.testing.assert_array_equal(res.nl.sc_info.cpu().numpy().view(np.uint32), info)
+    np.testing.assert_array_equal(res.nl.pool.cpu().numpy().view(np.uint32)[: res.nl.used_bytes // 4], pool)
+
+
+@pytest.mark.parametrize("kind,n,T", [("sphere", 60000, 100), ("uniform", 30000, 50), ("plummer", 30000, 150)])
+def test_converges_and_matches_oracle(env, kind, n, T):
+    sf, ctx, torch = env
+    if kind == "sphere":
+        s = workloads.evrard_sphere(n, 71, target=T)
+    elif kind == "uniform":
+        s = workloads.uniform_global(n, 72, target=2.0 * T)  # start with twice the neighbours
+    else:
+        s = workloads.plummer(n, 73, target=T)
+    _say("case %s n=%d T=%d" % (kind, n, T))
+    keys, xs, ys, zs, hs = _sorted_inputs(env, s)
+    res = sf.h_iterate(ctx, keys, xs, ys, zs, hs, target=T, tol=1, max_iters=64)
+    torch.cuda.synchronize()
+    _say("converged=%s rounds=%d" % (res.converged, res.iters))
+    assert res.converged and res.unconverged == 0
+    hf = hs.cpu().numpy()
+    _check_final((xs.cpu().numpy(), ys.cpu().numpy(), zs.cpu().numpy(), hf), res, T, 1)
+
+
+def test_noconv_then_resume(env):
+    sf, ctx, torch = env
+    s = workloads.evrard_sphere(20000, 74, target=60)
+    keys, xs, ys, zs, hs = _sorted_inputs(env, s)
+    bracket = torch.empty(2 * s.n, dtype=torch.float32, device="cuda")
+    r1 = sf.h_iterate(ctx, keys, xs, ys, zs, hs, target=60, tol=1, max_iters=1, bracket=bracket)
+    assert not r1.converged and r1.unconverged > 0 and r1.iters == 1
+    with pytest.raises(sf.SfcnlError) as ei:
+        sf.h_iterate(ctx, keys, xs, ys, zs, hs, target=60, tol=1, max_iters=1, bracket=bracket, resume=True,
+                     raise_noconv=True)
+    assert ei.value.code == -5
+    r2 = sf.h_iterate(ctx, keys, xs, ys, zs, hs, target=60, tol=1, max_iters=64, bracket=bracket, resume=True)
+    assert r2.converged
+    _check_final((xs.cpu().numpy(), ys.cpu().numpy(), zs.cpu().numpy(), hs.cpu().numpy()), r2, 60, 1)
+
+
+def test_capacity_growth_keeps_trajectory(env):
+    sf, ctx, torch = env
+    s = workloads.evrard_sphere(30000, 75, target=100)
+    keys, xs, ys, zs, hs = _sorted_inputs(env, s)
+    h_a = hs.clone()
+    h_b = hs.clone()
+    ra = sf.h_iterate(ctx, keys, xs, ys, zs, h_a, target=100, tol=1, max_iters=64, max_j_per_sc=4096)
+    rb = sf.h_iterate(ctx, keys, xs, ys, zs, h_b, target=100, tol=1, max_iters=64, max_j_per_sc=8,
+                      pool=torch.empty(64, dtype=torch.int32, device="cuda"))
+    assert ra.converged and rb.converged and ra.iters == rb.iters
+    assert torch.equal(h_a, h_b)
