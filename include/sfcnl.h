@@ -176,8 +176,8 @@ int nlist_decode(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, const
  * opts->resume is set, which continues an interrupted run (for instance after
  * SFCNL_E_CAPACITY, with larger buffers). On SFCNL_OK the list, d_rho and
  * d_nnb describe the final radii. Returns SFCNL_E_NOCONV when max_iters rounds
- * left *h_unconverged particles unconverged. d_bbox is caller scratch of
- * 8 floats per cluster. *h_iters counts the rounds of this call. */
+ * left particles unconverged. d_bbox is caller scratch of 8 floats per
+ * cluster. */
 typedef struct {
     int target;
     int tol;
@@ -185,12 +185,72 @@ typedef struct {
     int resume;
 } sfcnl_hiter_opts;
 
+/* Optional learned first step (see section 6): when `seed` is not NULL, the
+ * update of the call's first round uses h * exp(d), d = MLP(features) (the
+ * cube-root rule is the fallback wherever d is not finite or |d| > ln 8; the
+ * bracket test applies as usual). Scratch: d_feat n x 8 bf16, d_delta n
+ * floats. box_edge = largest edge of the key box given to sfc_sort. */
+typedef struct {
+    const float *d_params;
+    uint16_t *d_feat;
+    float *d_delta;
+    float box_edge;
+} sfcnl_hseed;
+
+/* Results of sfcnl_h_iterate (host struct): rounds run by this call,
+ * particles still outside target +- tol, the sum over rounds of the particles
+ * that moved (so moved / n + 1 is the mean number of rounds a particle needed
+ * when all converged), and the list sizes of build_nlist. */
+typedef struct {
+    int iters;
+    int64_t unconverged;
+    int64_t moved;
+    size_t used_bytes;
+    int64_t max_nj;
+} sfcnl_hiter_stats;
+
 int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_x, const float *d_y,
                     const float *d_z, float *d_h, float *d_bracket, const float *d_m,
                     const sfcnl_nlist_opts *nl_opts, const sfcnl_hiter_opts *it_opts, float *d_bbox, void *d_ws,
                     size_t ws_bytes, uint32_t *d_sc_info, uint32_t *d_pool, size_t pool_bytes, float *d_rho,
-                    int32_t *d_nnb, int *h_iters, int64_t *h_unconverged, size_t *h_used_bytes,
-                    int64_t *h_max_nj);
+                    int32_t *d_nnb, const sfcnl_hseed *seed, sfcnl_hiter_stats *h_stats);
+
+/* ---- 6. Learned smoothing-length seed (this library's addition) ------------
+ * An MLP 8 -> 64 -> 64 -> 1 with ReLU predicts a correction to the cube-root
+ * step, d = log(h_converged / h) = -feature0 / 3 + MLP(features), from 8
+ * dimensionless features of a particle at radius h with n own-radius
+ * neighbours: log((n+1)/target); log(cluster box diagonal / h); log(super-
+ * cluster box diagonal / h); log((1 + occupancy)/target) of the particle's
+ * Hilbert-key cell at the three levels around the one whose edge is closest to
+ * h; the fractional part of that level; log(target / 100).
+ * Parameters: SFCNL_MLP_NPARAM floats, W1[64][8], b1[64], W2[64][64], b2[64],
+ * w3[64], b3 (FP32 master copy, caller-owned). The kernels round weights,
+ * inputs and hidden activations to bfloat16 (nearest even) and use the bf16
+ * matrix cores with FP32 accumulation; the back-propagated errors are rounded
+ * to bf16 before entering matrix products (bias gradients are not).
+ *   sfcnl_hseed_features: d_feat [n][8] bf16 for SFC-ordered d_keys, d_h,
+ *     d_nnb and cluster boxes d_bbox; box_edge as above.
+ *   sfcnl_mlp_init: deterministic He-uniform initialisation from `seed`
+ *     (splitmix64 counter stream), zero biases.
+ *   sfcnl_mlp_infer: d_out[i] = MLP(d_feat[i]) - feature0 / 3.
+ *   sfcnl_mlp_grad: loss = mean over the batch of (d(f_k) - t_k)^2 and its
+ *     gradient d_grad [SFCNL_MLP_NPARAM]; sample k of the batch is
+ *     ((start + k) * mul + add) mod nsamp (a permutation of the samples when
+ *     gcd(mul, nsamp) = 1). d_loss (nullable) gets the loss.
+ *   sfcnl_mlp_adam: one Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected,
+ *     step t >= 1) on params with moments d_m, d_v. */
+#define SFCNL_MLP_NPARAM 4801
+#define SFCNL_HSEED_NFEAT 8
+int sfcnl_hseed_features(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_h, const int32_t *d_nnb,
+                         const float *d_bbox, float box_edge, int target, uint16_t *d_feat);
+int sfcnl_mlp_init(sfcnl_ctx ctx, uint64_t seed, float *d_params);
+int sfcnl_mlp_infer(sfcnl_ctx ctx, const float *d_params, int64_t n, const uint16_t *d_feat, float *d_out);
+int sfcnl_mlp_grad_workspace(int64_t batch, size_t *ws_bytes);
+int sfcnl_mlp_grad(sfcnl_ctx ctx, const float *d_params, int64_t nsamp, const uint16_t *d_feat,
+                   const float *d_target, int64_t batch, int64_t start, int64_t mul, int64_t add, void *d_ws,
+                   size_t ws_bytes, float *d_grad, float *d_loss);
+int sfcnl_mlp_adam(sfcnl_ctx ctx, float *d_params, const float *d_grad, float *d_m, float *d_v, int64_t t,
+                   float lr);
 
 /* ---- Stage timing -------------------------------------------------------
  * When enabled, every call brackets each of its stages with a pair of HIP

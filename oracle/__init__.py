@@ -13,6 +13,7 @@ in ``oracle.c`` (built with gcc, ``-ffp-contract=off``); library primitives
 from __future__ import annotations
 
 import ctypes as C
+import math
 import os
 import subprocess
 import threading
@@ -331,3 +332,124 @@ def h_iterate(x, y, z, h0, target: int, tol: int = 1, max_iters: int = 64, metho
         h = np.where(move, hn, hc).astype(np.float32)
     _, cnt = density(x, y, z, h, None, method)
     return h, max_iters, int((np.abs(cnt.astype(np.int64) - target) > tol).sum())
+
+
+# --------------------------------------------------------------------------
+# Learned h-seed (not from the paper): MLP 8 -> 64 -> 64 -> 1 with ReLU whose
+# output plus the cube-root rule's step (-feature0 / 3) predicts
+# d = log(h_converged / h_prev); MSE loss; Adam.
+# Parameter vector layout (4801 floats): W1[64][8], b1[64], W2[64][64], b2[64],
+# w3[64], b3.
+# --------------------------------------------------------------------------
+
+MLP_SIZES = (("W1", (64, 8)), ("b1", (64,)), ("W2", (64, 64)), ("b2", (64,)), ("w3", (64,)), ("b3", (1,)))
+MLP_NPARAM = 4801
+
+
+def mlp_unpack(p):
+    p = np.asarray(p, dtype=np.float64)
+    out, o = {}, 0
+    for name, shp in MLP_SIZES:
+        k = int(np.prod(shp))
+        out[name] = p[o:o + k].reshape(shp)
+        o += k
+    return out
+
+
+def mlp_pack(d):
+    return np.concatenate([np.asarray(d[name], dtype=np.float64).ravel() for name, _ in MLP_SIZES])
+
+
+def bf16(a):
+    """Round to bfloat16 (round to nearest, ties to even), returned as float64."""
+    f = np.ascontiguousarray(np.asarray(a, dtype=np.float64).astype(np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    r = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16) << 16
+    return r.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def mlp_forward(p, feat, quant=False):
+    """feat: (B, 8). With quant, weights, inputs and hidden activations are
+    rounded to bfloat16 where the GPU kernels feed them to the matrix cores;
+    sums are exact (FP64). Returns (y, cache)."""
+    P = mlp_unpack(p)
+    q = bf16 if quant else (lambda a: np.asarray(a, dtype=np.float64))
+    x = q(feat)
+    W1, W2, w3 = q(P["W1"]), q(P["W2"]), q(P["w3"])
+    z1 = x @ W1.T + P["b1"]
+    h1 = q(np.maximum(z1, 0.0))
+    z2 = h1 @ W2.T + P["b2"]
+    h2 = q(np.maximum(z2, 0.0))
+    # the network learns a residual on the cube-root rule's step
+    # log((target / (n+1))^(1/3)) = -feature0 / 3
+    y = h2 @ w3 + P["b3"][0] - x[:, 0] / 3.0
+    return y, dict(x=x, W1=W1, W2=W2, w3=w3, z1=z1, h1=h1, z2=z2, h2=h2)
+
+
+def mlp_loss_grad(p, feat, target, quant=False):
+    """Mean squared error and its gradient (flat, same layout as p). With
+    quant, the back-propagated errors are rounded to bfloat16 before they
+    enter matrix products, as in the GPU kernels (bias gradients use the
+    unrounded errors)."""
+    q = bf16 if quant else (lambda a: np.asarray(a, dtype=np.float64))
+    y, c = mlp_forward(p, feat, quant)
+    B = y.shape[0]
+    r = y - np.asarray(target, dtype=np.float64)
+    loss = float(np.mean(r * r))
+    dy = 2.0 * r / B
+    g = {}
+    g["w3"] = c["h2"].T @ dy
+    g["b3"] = np.array([dy.sum()])
+    d2 = np.outer(dy, c["w3"]) * (c["z2"] > 0)
+    g["b2"] = d2.sum(axis=0)
+    d2q = q(d2)
+    g["W2"] = d2q.T @ c["h1"]
+    d1 = (d2q @ c["W2"]) * (c["z1"] > 0)
+    g["b1"] = d1.sum(axis=0)
+    g["W1"] = q(d1).T @ c["x"]
+    return loss, mlp_pack(g)
+
+
+def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam step (Kingma & Ba 2015), bias-corrected, step t >= 1."""
+    m = b1 * m + (1 - b1) * g
+    v = b2 * v + (1 - b2) * g * g
+    mh = m / (1 - b1 ** t)
+    vh = v / (1 - b2 ** t)
+    return p - lr * mh / (np.sqrt(vh) + eps), m, v
+
+
+def hseed_features(keys_sorted, h, nnb, bbox, edge0: float, target: int):
+    """Features of the learned seed for SFC-ordered particles (float64, before
+    rounding to bf16): log((n+1)/T); log(max(cluster box diagonal / h, 1e-3));
+    the same for the 64-particle super-cluster box; log((1 + occupancy)/T) of
+    the particle's Hilbert-key cell at levels L0-1, L0, L0+1 with
+    L0 = clamp(round(log2(edge0 / h)), 2, 20); log2(edge0 / h) - L0;
+    log(T / 100)."""
+    keys = np.asarray(keys_sorted, dtype=np.uint64)
+    h = np.asarray(h, dtype=np.float64)
+    n = h.shape[0]
+    lt = math.log(target)
+    f = np.zeros((n, 8))
+    f[:, 0] = np.log(np.asarray(nnb, dtype=np.float64) + 1.0) - lt
+    bb = np.asarray(bbox, dtype=np.float64).reshape(-1, 8)
+    c = np.arange(n) // 8
+    diag = np.sqrt(((bb[:, 4:7] - bb[:, 0:3]) ** 2).sum(axis=1))
+    f[:, 1] = np.log(np.maximum(diag[c] / h, 1e-3))
+    nsc = (bb.shape[0] + 7) // 8
+    slo = np.array([bb[8 * k:8 * k + 8, 0:3].min(axis=0) for k in range(nsc)])
+    shi = np.array([bb[8 * k:8 * k + 8, 4:7].max(axis=0) for k in range(nsc)])
+    sdiag = np.sqrt(((shi - slo) ** 2).sum(axis=1))
+    f[:, 2] = np.log(np.maximum(sdiag[c // 8] / h, 1e-3))
+    lev = np.log2(edge0 / h)
+    L0 = np.clip(np.rint(lev), 2, 20).astype(np.int64)
+    for d in (-1, 0, 1):
+        L = L0 + d
+        shift = (3 * (21 - L)).astype(np.uint64)
+        pre = keys >> shift
+        lo = np.searchsorted(keys, pre << shift, side="left")
+        hi = np.searchsorted(keys, (pre + np.uint64(1)) << shift, side="left")
+        f[:, 4 + d] = np.log(1.0 + (hi - lo)) - lt
+    f[:, 6] = lev - L0
+    f[:, 7] = lt - math.log(100.0)
+    return f

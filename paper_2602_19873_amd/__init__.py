@@ -21,7 +21,8 @@ from . import _lib
 
 __all__ = ["Context", "NeighbourList", "SfcnlError", "sfc_sort", "sfc_gather", "build_clusters",
            "build_nlist", "nlist_pass", "nlist_decode", "h_iterate", "HIterResult", "Pipeline", "SC_SIZE",
-           "CLUSTER_SIZE"]
+           "CLUSTER_SIZE", "hseed_features", "mlp_init", "mlp_infer", "mlp_grad", "mlp_adam", "mlp_train",
+           "MLP_NPARAM"]
 
 SC_SIZE = 64
 CLUSTER_SIZE = 8
@@ -232,15 +233,20 @@ class HIterResult:
     nl: NeighbourList     # list at the final radii (valid when converged)
     rho: torch.Tensor
     nnb: torch.Tensor
+    moved: int = 0        # sum over rounds of the particles that moved
+
+    def mean_rounds(self) -> float:
+        return self.moved / max(self.nl.n, 1) + 1.0
 
 
 def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, max_iters: int = 64, m=None,
               compress: bool = True, leaf_bucket: int = 128, max_j_per_sc: int = 512, bracket=None, bbox=None,
               ws=None, pool=None, sc_info=None, rho=None, nnb=None, raise_noconv: bool = False,
-              resume: bool = False):
+              resume: bool = False, mlp_params=None, box_edge: float = 0.0, seed_scratch=None):
     """Iterates the SFC-ordered radii h (updated in place) to target +- tol
-    own-radius neighbours (sfcnl_h_iterate). Grows list buffers and resumes
-    when the library reports them too small."""
+    own-radius neighbours (sfcnl_h_iterate). With mlp_params the first round's
+    update comes from the learned seed. Grows list buffers and resumes when
+    the library reports them too small."""
     n = x.numel()
     nsc = (n + SC_SIZE - 1) // SC_SIZE
     nc = (n + CLUSTER_SIZE - 1) // CLUSTER_SIZE
@@ -251,38 +257,130 @@ def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, m
     pool = e(max(1024, 6 * n), torch.int32) if pool is None else pool
     rho = e(max(n, 1), torch.float32) if rho is None else rho
     nnb = e(max(n, 1), torch.int32) if nnb is None else nnb
-    total, resume = 0, int(bool(resume))
+    hs = None
+    if mlp_params is not None:
+        if not box_edge > 0:
+            raise ValueError("box_edge must be given with mlp_params")
+        if seed_scratch is None:
+            seed_scratch = (e((max(n, 1), _lib.HSEED_NFEAT), torch.int16), e(max(n, 1), torch.float32))
+        hs = _lib.HSeed(mlp_params.data_ptr(), seed_scratch[0].data_ptr(), seed_scratch[1].data_ptr(), box_edge)
+    total, moved, resume = 0, 0, int(bool(resume))
     while True:
         if total >= max_iters:
             nl = NeighbourList(n, CLUSTER_SIZE, bool(compress), sc_info[:nsc], pool, 0, 0)
-            return HIterResult(total, n, False, nl, rho, nnb)
+            return HIterResult(total, n, False, nl, rho, nnb, moved)
         need = build_nlist_workspace(n, CLUSTER_SIZE, compress, leaf_bucket, max_j_per_sc)
         if ws is None or ws.numel() < need:
             ws = e(max(need, 1), torch.uint8)
         no = _opts(CLUSTER_SIZE, compress, leaf_bucket, max_j_per_sc)
         io = _lib.HiterOpts(target, tol, max_iters - total, resume)
-        iters, unconv, used, maxnj = C.c_int(), C.c_int64(), C.c_size_t(), C.c_int64()
+        st = _lib.HiterStats()
+        seed_arg = C.byref(hs) if (hs is not None and total == 0) else None
         rc = ctx.lib.sfcnl_h_iterate(ctx.handle, n, _ptr(keys), _ptr(x), _ptr(y), _ptr(z), _ptr(h), _ptr(bracket),
                                      _ptr(m), C.byref(no), C.byref(io), _ptr(bbox), _ptr(ws), ws.numel(),
-                                     _ptr(sc_info), _ptr(pool), pool.numel() * 4, _ptr(rho), _ptr(nnb),
-                                     C.byref(iters), C.byref(unconv), C.byref(used), C.byref(maxnj))
-        total += iters.value
+                                     _ptr(sc_info), _ptr(pool), pool.numel() * 4, _ptr(rho), _ptr(nnb), seed_arg,
+                                     C.byref(st))
+        total += st.iters
+        moved += st.moved
         if rc == _lib.E_CAPACITY:
             # the round that overflowed did not update h (only completed
             # rounds are counted): run it again with room
-            if maxnj.value > max_j_per_sc:
-                max_j_per_sc = int(maxnj.value)
-            if used.value > pool.numel() * 4:
-                pool = e(used.value // 4 + 1024, torch.int32)
+            if st.max_nj > max_j_per_sc:
+                max_j_per_sc = int(st.max_nj)
+            if st.used_bytes > pool.numel() * 4:
+                pool = e(st.used_bytes // 4 + 1024, torch.int32)
             resume = 1
             continue
-        if rc == _lib.E_NOCONV and not raise_noconv:
-            nl = NeighbourList(n, CLUSTER_SIZE, bool(compress), sc_info[:nsc], pool, used.value, maxnj.value)
-            return HIterResult(total, unconv.value, False, nl, rho, nnb)
-        ctx.check(rc)
-        nl = NeighbourList(n, CLUSTER_SIZE, bool(compress), sc_info[:nsc], pool, used.value, maxnj.value)
+        nl = NeighbourList(n, CLUSTER_SIZE, bool(compress), sc_info[:nsc], pool, st.used_bytes, st.max_nj)
         nl.ws, nl.max_j_per_sc = ws, max_j_per_sc
-        return HIterResult(total, unconv.value, True, nl, rho, nnb)
+        if rc == _lib.E_NOCONV and not raise_noconv:
+            return HIterResult(total, st.unconverged, False, nl, rho, nnb, moved)
+        ctx.check(rc)
+        return HIterResult(total, st.unconverged, True, nl, rho, nnb, moved)
+
+
+# --------------------------------------------------------------------------
+# Learned h-seed: the MLP and its training (sfcnl_mlp_*, sfcnl_hseed_features)
+# --------------------------------------------------------------------------
+
+MLP_NPARAM = _lib.MLP_NPARAM
+
+
+def hseed_features(ctx: Context, keys, h, nnb, bbox, box_edge: float, target: int, feat=None):
+    n = h.numel()
+    feat = ctx.empty((max(n, 1), _lib.HSEED_NFEAT), torch.int16) if feat is None else feat
+    ctx.check(ctx.lib.sfcnl_hseed_features(ctx.handle, n, _ptr(keys), _ptr(h), _ptr(nnb), _ptr(bbox), box_edge,
+                                           target, _ptr(feat)))
+    return feat
+
+
+def mlp_init(ctx: Context, seed: int = 1):
+    p = ctx.empty(MLP_NPARAM, torch.float32)
+    ctx.check(ctx.lib.sfcnl_mlp_init(ctx.handle, seed, _ptr(p)))
+    return p
+
+
+def mlp_infer(ctx: Context, params, feat, out=None):
+    n = feat.shape[0]
+    out = ctx.empty(max(n, 1), torch.float32) if out is None else out
+    ctx.check(ctx.lib.sfcnl_mlp_infer(ctx.handle, _ptr(params), n, _ptr(feat), _ptr(out)))
+    return out
+
+
+def mlp_grad(ctx: Context, params, feat, target, batch: int, start: int = 0, mul: int = 1, add: int = 0,
+             ws=None, grad=None, loss=None):
+    nsamp = feat.shape[0]
+    b = C.c_size_t()
+    ctx.lib.sfcnl_mlp_grad_workspace(batch, C.byref(b))
+    ws = ctx.empty(b.value, torch.uint8) if ws is None or ws.numel() < b.value else ws
+    grad = ctx.empty(MLP_NPARAM, torch.float32) if grad is None else grad
+    loss = ctx.empty(1, torch.float32) if loss is None else loss
+    ctx.check(ctx.lib.sfcnl_mlp_grad(ctx.handle, _ptr(params), nsamp, _ptr(feat), _ptr(target), batch, start, mul,
+                                     add, _ptr(ws), ws.numel(), _ptr(grad), _ptr(loss)))
+    return grad, loss, ws
+
+
+def mlp_adam(ctx: Context, params, grad, m, v, t: int, lr: float):
+    ctx.check(ctx.lib.sfcnl_mlp_adam(ctx.handle, _ptr(params), _ptr(grad), _ptr(m), _ptr(v), t, lr))
+
+
+def _coprime_multiplier(n: int) -> int:
+    import math
+    mul = 2654435761  # a prime near 2^32 / golden ratio
+    while math.gcd(mul, n) != 1:
+        mul += 2
+    return mul
+
+
+def mlp_train(ctx: Context, feat, target, epochs: int = 30, batch: int = 8192, lr: float = 3e-3,
+              lr_final: float = 3e-4, seed: int = 1, params=None, log=None):
+    """Trains the seed MLP with the library's kernels (gradient + Adam per
+    batch, samples visited in a fresh permutation every epoch). Returns
+    (params, losses per epoch)."""
+    n = feat.shape[0]
+    params = mlp_init(ctx, seed) if params is None else params
+    m = torch.zeros(MLP_NPARAM, dtype=torch.float32, device=params.device)
+    v = torch.zeros_like(m)
+    mul = _coprime_multiplier(n)
+    steps = max(1, n // batch)
+    grad, loss, ws = None, None, None
+    losses = []
+    t = 0
+    for ep in range(epochs):
+        acc = 0.0
+        for k in range(steps):
+            t += 1
+            frac = (t - 1) / max(1, epochs * steps - 1)
+            lr_t = lr * (lr_final / lr) ** frac
+            grad, loss, ws = mlp_grad(ctx, params, feat, target, batch, start=k * batch, mul=mul,
+                                      add=(ep * 7919) % n, ws=ws, grad=grad, loss=loss)
+            mlp_adam(ctx, params, grad, m, v, t, lr_t)
+            if k == steps - 1 or k % 32 == 0:
+                acc = float(loss.item())
+        losses.append(acc)
+        if log:
+            log("epoch %d loss %.5f" % (ep, acc))
+    return params, losses
 
 
 class Pipeline:

@@ -21,7 +21,12 @@ SYMBOLS = [
     "sfcnl_create", "sfcnl_destroy", "sfcnl_set_stream", "sfcnl_last_error", "sfcnl_sync", "sfcnl_version",
     "sfc_sort_workspace", "sfc_sort", "sfc_gather", "build_clusters", "build_nlist_workspace", "build_nlist",
     "nlist_pass", "nlist_decode", "sfcnl_profile_begin", "sfcnl_profile_end", "sfcnl_h_iterate",
+    "sfcnl_hseed_features", "sfcnl_mlp_init", "sfcnl_mlp_infer", "sfcnl_mlp_grad_workspace", "sfcnl_mlp_grad",
+    "sfcnl_mlp_adam",
 ]
+
+MLP_NPARAM = 4801
+HSEED_NFEAT = 8
 
 NSTAGE = 8
 STAGES = ["keys", "sort", "gather", "clusters", "octree", "traverse", "encode", "pass"]
@@ -34,6 +39,15 @@ class NlistOpts(C.Structure):
 
 class HiterOpts(C.Structure):
     _fields_ = [("target", C.c_int), ("tol", C.c_int), ("max_iters", C.c_int), ("resume", C.c_int)]
+
+
+class HiterStats(C.Structure):
+    _fields_ = [("iters", C.c_int), ("unconverged", C.c_int64), ("moved", C.c_int64), ("used_bytes", C.c_size_t),
+                ("max_nj", C.c_int64)]
+
+
+class HSeed(C.Structure):
+    _fields_ = [("d_params", C.c_void_p), ("d_feat", C.c_void_p), ("d_delta", C.c_void_p), ("box_edge", C.c_float)]
 
 
 _lib = None
@@ -78,9 +92,20 @@ def load():
     lib.nlist_decode.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp]
     lib.nlist_decode.restype = i32
     lib.sfcnl_h_iterate.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, C.POINTER(NlistOpts), C.POINTER(HiterOpts),
-                                    vp, vp, sz, vp, vp, sz, vp, vp, C.POINTER(i32), C.POINTER(i64), C.POINTER(sz),
-                                    C.POINTER(i64)]
+                                    vp, vp, sz, vp, vp, sz, vp, vp, C.POINTER(HSeed), C.POINTER(HiterStats)]
     lib.sfcnl_h_iterate.restype = i32
+    lib.sfcnl_hseed_features.argtypes = [vp, i64, vp, vp, vp, vp, C.c_float, i32, vp]
+    lib.sfcnl_hseed_features.restype = i32
+    lib.sfcnl_mlp_init.argtypes = [vp, C.c_uint64, vp]
+    lib.sfcnl_mlp_init.restype = i32
+    lib.sfcnl_mlp_infer.argtypes = [vp, vp, i64, vp, vp]
+    lib.sfcnl_mlp_infer.restype = i32
+    lib.sfcnl_mlp_grad_workspace.argtypes = [i64, C.POINTER(sz)]
+    lib.sfcnl_mlp_grad_workspace.restype = i32
+    lib.sfcnl_mlp_grad.argtypes = [vp, vp, i64, vp, vp, i64, i64, i64, i64, vp, sz, vp, vp]
+    lib.sfcnl_mlp_grad.restype = i32
+    lib.sfcnl_mlp_adam.argtypes = [vp, vp, vp, vp, vp, i64, C.c_float]
+    lib.sfcnl_mlp_adam.restype = i32
     lib.sfcnl_profile_begin.argtypes = [vp, i32]
     lib.sfcnl_profile_begin.restype = i32
     lib.sfcnl_profile_end.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]

@@ -1,0 +1,174 @@
+"""Learned h-seed on the GPU: the library's bf16 matrix-core kernels against
+the oracle's MLP with the same rounding points, the feature kernel against the
+oracle's features, training with the library's kernels, and what the trained
+seed gains over the plain iteration."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2602_19873_amd import workloads
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def env():
+    import torch
+    import paper_2602_19873_amd as sf
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    torch.cuda.set_device(0)
+    ctx = sf.Context(0)
+    yield sf, ctx, torch
+    ctx.close()
+
+
+def _bf16_bits(a):
+    f = np.ascontiguousarray(np.asarray(a, dtype=np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    return (((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)).view(np.int16)
+
+
+def _bits_to_f64(b):
+    return (np.asarray(b).view(np.uint16).astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def _rel(a, b):
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-30)
+
+
+def _tensors(p):
+    d = oracle.mlp_unpack(p)
+    return {k: v.ravel() for k, v in d.items()}
+
+
+def test_inference_and_gradient_match_oracle(env):
+    sf, ctx, torch = env
+    rng = np.random.default_rng(11)
+    B = 1000  # not a multiple of 16: ragged last tile
+    p = rng.normal(0, 0.25, oracle.MLP_NPARAM).astype(np.float32)
+    feat_bits = _bf16_bits(rng.normal(0, 1.0, (B, 8)))
+    t = rng.normal(0, 0.5, B).astype(np.float32)
+    dp = torch.from_numpy(p).cuda()
+    dfeat = torch.from_numpy(feat_bits).cuda()
+    dt = torch.from_numpy(t).cuda()
+    y = sf.mlp_infer(ctx, dp, dfeat).cpu().numpy()[:B].astype(np.float64)
+    yo, _ = oracle.mlp_forward(p, _bits_to_f64(feat_bits), quant=True)
+    assert _rel(y, yo) < 1e-3
+    g, loss, _ = sf.mlp_grad(ctx, dp, dfeat, dt, B)
+    lo, go = oracle.mlp_loss_grad(p, _bits_to_f64(feat_bits), t, quant=True)
+    assert abs(float(loss.item()) - lo) <= 1e-3 * lo
+    gg = _tensors(g.cpu().numpy().astype(np.float64))
+    gr = _tensors(go)
+    for k in gr:
+        assert _rel(gg[k], gr[k]) < 1e-3, (k, _rel(gg[k], gr[k]))
+
+
+def test_batch_permutation_and_subset(env):
+    sf, ctx, torch = env
+    rng = np.random.default_rng(12)
+    N, B, mul, add = 3000, 512, 2654435761, 77
+    p = rng.normal(0, 0.25, oracle.MLP_NPARAM).astype(np.float32)
+    fb = _bf16_bits(rng.normal(0, 1.0, (N, 8)))
+    t = rng.normal(0, 0.5, N).astype(np.float32)
+    start = 1024
+    idx = ((start + np.arange(B, dtype=np.int64)) * mul + add) % N
+    g, loss, _ = sf.mlp_grad(ctx, torch.from_numpy(p).cuda(), torch.from_numpy(fb).cuda(), torch.from_numpy(t).cuda(),
+                             B, start=start, mul=mul, add=add)
+    lo, go = oracle.mlp_loss_grad(p, _bits_to_f64(fb[idx]), t[idx], quant=True)
+    assert _rel(g.cpu().numpy().astype(np.float64), go) < 1e-3
+
+
+def test_adam_matches_oracle(env):
+    sf, ctx, torch = env
+    rng = np.random.default_rng(13)
+    p = rng.normal(0, 0.3, oracle.MLP_NPARAM).astype(np.float32)
+    m = rng.normal(0, 0.01, oracle.MLP_NPARAM).astype(np.float32)
+    v = rng.uniform(0, 1e-4, oracle.MLP_NPARAM).astype(np.float32)
+    g = rng.normal(0, 0.1, oracle.MLP_NPARAM).astype(np.float32)
+    dp, dm, dv, dg = (torch.from_numpy(a.copy()).cuda() for a in (p, m, v, g))
+    sf.mlp_adam(ctx, dp, dg, dm, dv, 7, 1e-3)
+    po, mo, vo = oracle.adam_step(p.astype(np.float64), g.astype(np.float64), m.astype(np.float64),
+                                  v.astype(np.float64), 7, 1e-3)
+    assert _rel(dp.cpu().numpy().astype(np.float64) - p, po - p) < 1e-4
+    assert _rel(dm.cpu().numpy().astype(np.float64), mo) < 1e-5
+    assert _rel(dv.cpu().numpy().astype(np.float64), vo) < 1e-5
+
+
+def test_init_is_deterministic(env):
+    sf, ctx, torch = env
+    a = sf.mlp_init(ctx, 5).cpu().numpy()
+    b = sf.mlp_init(ctx, 5).cpu().numpy()
+    c = sf.mlp_init(ctx, 6).cpu().numpy()
+    np.testing.assert_array_equal(a, b)
+    assert not np.array_equal(a, c)
+    P = oracle.mlp_unpack(a.astype(np.float64))
+    assert np.all(P["b1"] == 0) and np.all(P["b2"] == 0) and P["b3"][0] == 0
+    w1max, w1std = float(np.abs(P["W1"]).max()), float(P["W1"].std())
+    # uniform on [-a, a], a = sqrt(6 / 8): standard deviation a / sqrt(3) = 0.5
+    assert w1max <= np.sqrt(6 / 8) and 0.4 < w1std < 0.6, (w1max, w1std)
+
+
+def test_features_match_oracle(env):
+    sf, ctx, torch = env
+    from paper_2602_19873_amd import hseed
+    s = workloads.evrard_sphere(40000, 81, target=100)
+    keys, xs, ys, zs, hs = hseed.sorted_system(ctx, s)
+    bbox = sf.build_clusters(ctx, xs, ys, zs, hs)
+    nl = sf.build_nlist(ctx, keys, xs, ys, zs, hs, bbox)
+    _, nnb = sf.nlist_pass(ctx, nl, xs, ys, zs, hs)
+    feat = sf.hseed_features(ctx, keys, hs, nnb, bbox, hseed.box_edge(s.box), 100)
+    got = _bits_to_f64(feat.cpu().numpy()).reshape(-1, 8)
+    ref = oracle.hseed_features(keys.cpu().numpy().view(np.uint64), hs.cpu().numpy(), nnb.cpu().numpy(),
+                                bbox.cpu().numpy(), hseed.box_edge(s.box), 100)
+    refq = _bits_to_f64(_bf16_bits(ref)).reshape(-1, 8)
+    # equal up to one bf16 step, except where FP32 and FP64 pick different
+    # levels (log2 at a half-integer): allow a tiny fraction of rows
+    close = np.abs(got - refq) <= 2.0 ** -7 * np.maximum(np.abs(refq), 1e-2)
+    assert close.mean() > 0.999
+    assert close.all(axis=1).mean() > 0.995
+
+
+def test_training_fits_and_seed_gains(env):
+    sf, ctx, torch = env
+    import math
+    from paper_2602_19873_amd import hseed
+    _say("building training set")
+    feat, d = hseed.training_set(ctx, n_total=1 << 18, targets=(100,), spread=4.0)
+    _say("training on %d pairs" % feat.shape[0])
+    params, losses = sf.mlp_train(ctx, feat, d, epochs=12, batch=4096)
+    var = float(torch.var(d).item())
+    _say("loss %.4f -> %.4f (target variance %.4f)" % (losses[0], losses[-1], var))
+    assert losses[-1] < 0.1 * var
+    # gain on an unseen system of the training generator, starting radii off by
+    # up to a factor 4 (the plain rule moves at most a factor 2 per round)
+    s = workloads.uniform_varied(200000, 91, target=100)
+    s.h = (s.h * np.exp(np.random.default_rng(92).uniform(-math.log(4), math.log(4), s.n))).astype(np.float32)
+    plain, _ = hseed.iterate(ctx, s, 100)
+    seeded, arrays = hseed.iterate(ctx, s, 100, mlp_params=params)
+    _say("uniform: plain %d rounds (mean %.2f); seeded %d rounds (mean %.2f)" %
+         (plain.iters, plain.mean_rounds(), seeded.iters, seeded.mean_rounds()))
+    assert plain.converged and seeded.converged
+    assert seeded.mean_rounds() < plain.mean_rounds() - 0.3
+    assert seeded.iters <= plain.iters
+    # the seeded result is still exact: the oracle sees every count in range
+    keys, xs, ys, zs, hs = arrays
+    _, cnt = oracle.density(xs.cpu().numpy(), ys.cpu().numpy(), zs.cpu().numpy(), hs.cpu().numpy(), None, "grid")
+    assert np.all(np.abs(cnt - 100) <= 1)
+    np.testing.assert_array_equal(seeded.nnb.cpu().numpy()[: s.n], cnt)
+    # outside the training distribution (1/r sphere) the seed stays correct
+    sp = workloads.evrard_sphere(200000, 82, target=100)
+    p2, _ = hseed.iterate(ctx, sp, 100)
+    s2, arr2 = hseed.iterate(ctx, sp, 100, mlp_params=params)
+    _say("sphere: plain %d rounds (mean %.2f); seeded %d rounds (mean %.2f)" %
+         (p2.iters, p2.mean_rounds(), s2.iters, s2.mean_rounds()))
+    assert s2.converged
+    _, c2 = oracle.density(*(a.cpu().numpy() for a in arr2[1:]), None, "grid")
+    assert np.all(np.abs(c2 - 100) <= 1)
