@@ -149,6 +149,122 @@ def run_hiter(args, sf, torch, ctx):
     print(json.dumps(out), flush=True)
 
 
+def run_batch(args, sf, torch, ctx):
+    """Batch of independent systems (sizes log-uniform in [1e4, 1e6], uniform
+    cube and Plummer sphere alternating), every particle driven to target +- 1
+    own-radius neighbours from the plain starting guess (each system's
+    mean-density radius). Compared: the plain iteration run per system, one
+    call after another, against the batched iteration (one set of launches
+    per round over all systems, replayed from a HIP graph) with the learned
+    seed applied before the first round and the autotuned leaf bucket.
+    Positions are fixed, so the SFC order is computed outside the timed
+    region; the seed's training is a one-off outside it too."""
+    import numpy as np
+    from paper_2602_19873_amd import autotune, hseed, workloads
+    T = args.target
+    systems = workloads.batch_systems(args.nsys, target=T)
+    counts = [s.n for s in systems]
+    ntot = sum(counts)
+    log("batch: %d systems, %d particles (%d .. %d), target %d" % (len(systems), ntot, min(counts), max(counts), T))
+    dev = torch.device("cuda:0")
+    singles = [hseed.sorted_system(ctx, s) for s in systems]
+    h0s = [a[4].clone() for a in singles]
+    b = sf.Batch(ctx, counts, [s.box for s in systems])
+    cat = lambda f: torch.from_numpy(np.ascontiguousarray(np.concatenate([getattr(s, f) for s in systems]))).to(dev)
+    keys, perm = sf.batch_sort(ctx, b, cat("x"), cat("y"), cat("z"))
+    xs, ys, zs, hb = sf.batch_gather(ctx, b, perm, [cat("x"), cat("y"), cat("z"), cat("h")])
+    h0b = hb.clone()
+    real = torch.zeros(b.n_pad, dtype=torch.bool, device=dev)
+    for k in range(b.nsys):
+        real[int(b.pbase[k]):int(b.pbase[k]) + counts[k]] = True
+    torch.cuda.synchronize()
+
+    log("training the seed (before-first-round features)")
+    t0 = time.perf_counter()
+    feat, d = hseed.mixed_training_set(ctx, T, count=args.train_systems, before_first=True)
+    params, losses = sf.mlp_train(ctx, feat, d, epochs=args.train_epochs, batch=4096)
+    torch.cuda.synchronize()
+    train_s = time.perf_counter() - t0
+    log("trained on %d pairs in %.1f s: loss %.4f -> %.4f (target variance %.4f)" %
+        (feat.shape[0], train_s, losses[0], losses[-1], float(torch.var(d).item())))
+
+    def worst_dev(nnb_list):
+        return max(int((n_.long() - T).abs().max().item()) for n_ in nnb_list if n_.numel())
+
+    single_bufs = [dict() for _ in systems]
+
+    def plain_per_system(seeded):
+        rounds, nnbs = [], []
+        for k, (a, h0) in enumerate(zip(singles, h0s)):
+            keys_k, x_k, y_k, z_k, h_k = a
+            h_k.copy_(h0)
+            kw = dict(single_bufs[k])
+            if seeded:
+                kw.update(mlp_params=params, box_edge=hseed.box_edge(systems[k].box),
+                          seed_mode=sf.SEED_BEFORE_FIRST)
+            res = sf.h_iterate(ctx, keys_k, x_k, y_k, z_k, h_k, target=T, tol=1, max_iters=64, **kw)
+            single_bufs[k] = dict(ws=res.nl.ws, pool=res.nl.pool, max_j_per_sc=res.nl.max_j_per_sc)
+            if not res.converged:
+                raise RuntimeError("system %d did not converge" % k)
+            rounds.append(res.iters)
+            nnbs.append(res.nnb[:counts[k]])
+        return rounds, nnbs
+
+    batch_bufs = {}
+    tuned = {"leaf_bucket": 128}
+
+    def batched(seeded, use_graph=True):
+        hb.copy_(h0b)
+        kw = dict(mlp_params=params, seed_mode=sf.SEED_BEFORE_FIRST) if seeded else {}
+        res = sf.batch_h_iterate(ctx, b, keys, xs, ys, zs, hb, target=T, tol=1, max_iters=64, use_graph=use_graph,
+                                 leaf_bucket=tuned["leaf_bucket"], bufs=batch_bufs, **kw)
+        if not res.converged:
+            raise RuntimeError("batch did not converge")
+        return res.sys_rounds.tolist(), [res.nnb[real]]
+
+    def timed(fn, *a):
+        ts, out = [], None
+        for rep in range(args.warmup + args.steps):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            out = fn(*a)
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            if rep >= args.warmup:
+                ts.append(dt)
+            log("  rep %d: %.1f ms, max rounds %d" % (rep, dt * 1e3, max(out[0])))
+        ts.sort()
+        t = ts[len(ts) // 2]
+        return {"ms": t * 1e3, "mparticles_per_s": ntot / t / 1e6, "max_rounds": int(max(out[0])),
+                "mean_system_rounds": float(np.mean(out[0])), "max_abs_dev": worst_dev(out[1])}
+
+    log("plain iteration, per system")
+    plain = timed(plain_per_system, False)
+    log("batched seeded iteration: warm-up run, then leaf-bucket autotune at the converged radii")
+    batched(True)
+    tuned = autotune.tune_batch(ctx, b, keys, xs, ys, zs, hb, tag="batch%d_t%d" % (b.nsys, T))
+    log("autotune: %s" % tuned)
+    log("batched seeded iteration (graph)")
+    best = timed(batched, True)
+    log("batched plain iteration (graph)")
+    bplain = timed(batched, False)
+    log("seeded iteration, per system")
+    sseed = timed(plain_per_system, True)
+    out = {"metric": "h-iteration of a %d-system batch to target +- 1 neighbours, Mparticles/s "
+                     "(total N / time to convergence)" % b.nsys,
+           "value": best["mparticles_per_s"], "unit": "Mparticles/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": best["ms"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "batch_%d_uniform_plummer" % b.nsys, "n_total": ntot, "n_padded": b.n_pad,
+                      "sizes": "log-uniform [1e4, 1e6]", "target": T, "tol": 1, "cluster_size": 8,
+                      "leaf_bucket": tuned["leaf_bucket"]},
+           "batched_seeded_graph": best, "plain_per_system": plain, "batched_plain_graph": bplain,
+           "seeded_per_system": sseed, "speedup_vs_plain_per_system": plain["ms"] / best["ms"],
+           "autotune": tuned, "seed_training": {"pairs": int(feat.shape[0]), "seconds": train_s,
+                                                "loss_first": losses[0], "loss_last": losses[-1]}}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -160,8 +276,11 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after warm-up, copy this many MiB once (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=["step", "hiter"], default="step")
-    ap.add_argument("--target", type=int, default=100)
+    ap.add_argument("--mode", choices=["step", "hiter", "batch"], default="step")
+    ap.add_argument("--target", type=int, default=0, help="neighbour target (hiter 100, batch 150)")
+    ap.add_argument("--nsys", type=int, default=64)
+    ap.add_argument("--train-systems", type=int, default=16)
+    ap.add_argument("--train-epochs", type=int, default=20)
     ap.add_argument("--seed-h", choices=["global", "analytic"], default="global")
     ap.add_argument("--n", type=int, default=0)
     args = ap.parse_args()
@@ -176,10 +295,15 @@ def main():
     import torch
     import paper_2602_19873_amd as sf
 
-    if args.mode == "hiter":
+    if args.mode in ("hiter", "batch"):
         torch.cuda.set_device(0)
         ctx = sf.Context(0)
-        run_hiter(args, sf, torch, ctx)
+        if args.mode == "hiter":
+            args.target = args.target or 100
+            run_hiter(args, sf, torch, ctx)
+        else:
+            args.target = args.target or 150
+            run_batch(args, sf, torch, ctx)
         ctx.close()
         return
 

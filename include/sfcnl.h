@@ -121,9 +121,10 @@ int build_clusters(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y,
  * Workspace: at least build_nlist_workspace(n, opts) bytes.
  * Returns SFCNL_OK, or SFCNL_E_CAPACITY when the pool (pool_bytes) or the
  * staging list is too small: then *h_used_bytes is the pool size needed and
- * *h_max_nj the largest list length, and a retry with enough room yields the
- * identical list. On success *h_used_bytes is the pool size used. Waits for
- * the stream. */
+ * *h_max_nj the largest list length, a retry with enough room yields the
+ * identical list, and the lists that did not fit are recorded as empty in
+ * sc_info (so a pass over it stays inside the pool). On success *h_used_bytes
+ * is the pool size used. Waits for the stream. */
 typedef struct {
     int cluster_size;
     int compress;
@@ -185,16 +186,26 @@ typedef struct {
     int resume;
 } sfcnl_hiter_opts;
 
-/* Optional learned first step (see section 6): when `seed` is not NULL, the
- * update of the call's first round uses h * exp(d), d = MLP(features) (the
- * cube-root rule is the fallback wherever d is not finite or |d| > ln 8; the
- * bracket test applies as usual). Scratch: d_feat n x 8 bf16, d_delta n
- * floats. box_edge = largest edge of the key box given to sfc_sort. */
+/* Optional learned step (see section 6), used when `seed` is not NULL:
+ *   mode SFCNL_SEED_AFTER_FIRST: the update of the call's first round uses
+ *     h * exp(d), d = MLP(features at that round's counts) (the cube-root
+ *     rule is the fallback wherever d is not finite or |d| > ln 8; the
+ *     bracket test applies as usual);
+ *   mode SFCNL_SEED_BEFORE_FIRST: before the first round (unless resuming),
+ *     every radius becomes h * exp(clamp(d, -ln 8, ln 8)), d = MLP(features
+ *     with no count: feature 0 is 0), computed from the cluster boxes at the
+ *     starting radii and the keys; h is unchanged where d is not finite. The
+ *     rounds then follow the rule above.
+ * Scratch: d_feat n x 8 bf16, d_delta n floats. box_edge = largest edge of
+ * the key box given to sfc_sort. */
+#define SFCNL_SEED_AFTER_FIRST 0
+#define SFCNL_SEED_BEFORE_FIRST 1
 typedef struct {
     const float *d_params;
     uint16_t *d_feat;
     float *d_delta;
     float box_edge;
+    int mode;
 } sfcnl_hseed;
 
 /* Results of sfcnl_h_iterate (host struct): rounds run by this call,
@@ -229,7 +240,8 @@ int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const floa
  * matrix cores with FP32 accumulation; the back-propagated errors are rounded
  * to bf16 before entering matrix products (bias gradients are not).
  *   sfcnl_hseed_features: d_feat [n][8] bf16 for SFC-ordered d_keys, d_h,
- *     d_nnb and cluster boxes d_bbox; box_edge as above.
+ *     d_nnb and cluster boxes d_bbox; box_edge as above; d_nnb NULL means no
+ *     count yet (feature 0 = 0).
  *   sfcnl_mlp_init: deterministic He-uniform initialisation from `seed`
  *     (splitmix64 counter stream), zero biases.
  *   sfcnl_mlp_infer: d_out[i] = MLP(d_feat[i]) - feature0 / 3.
@@ -251,6 +263,76 @@ int sfcnl_mlp_grad(sfcnl_ctx ctx, const float *d_params, int64_t nsamp, const ui
                    size_t ws_bytes, float *d_grad, float *d_loss);
 int sfcnl_mlp_adam(sfcnl_ctx ctx, float *d_params, const float *d_grad, float *d_m, float *d_v, int64_t t,
                    float lr);
+
+/* ---- 7. Batches of independent systems (this library's addition) ----------
+ * Many systems of uneven sizes go through one set of launches: every kernel
+ * covers the super-clusters of all systems, each system keeps its own octree
+ * (its root is found per super-cluster), its list stores j-cluster indices
+ * relative to the system's first cluster, and the result for each system is
+ * bit-identical to the single-system calls above on that system alone.
+ *
+ * Layouts. Input particles are the systems concatenated: system s is
+ * [in_off[s], in_off[s+1]) with in_off[0] = 0. The padded (SFC) layout puts
+ * system s at pbase[s] (a multiple of 64) and fills up to pbase[s+1] with
+ * padding: key all ones, permutation entry 0xFFFFFFFF, fields NaN. Outputs for
+ * padding slots are unspecified. Every array below named "padded" has n_padded
+ * entries (d_bbox: 8 floats per 8 padded particles).
+ *
+ *   sfcnl_batch_create: nsys in [1, SFCNL_BATCH_MAX_SYSTEMS]; h_counts[s] >= 0
+ *     particles of system s; h_boxes 6 floats per system (xlo, xhi, ylo, yhi,
+ *     zlo, zhi, as the box of sfc_sort). Copies the tables to the context's
+ *     device and creates a stream of default priority; the batch belongs to
+ *     that device. Total padded size < 2^31.
+ *   sfcnl_batch_layout: sizes; h_in_off / h_pbase (nullable) get nsys + 1
+ *     entries.
+ *   sfcnl_batch_sort: keys of each particle in its system's box (sfc_sort's
+ *     definition), sorted stably by (system, key), spread into the padded
+ *     layout: d_keys_out, d_perm_out padded (perm entries index the input).
+ *   sfcnl_batch_gather: d_out[f][q] = d_in[f][perm[q]], NaN for padding.
+ *   sfcnl_batch_build_clusters / _build_nlist / _pass: build_clusters,
+ *     build_nlist and nlist_pass on padded arrays; sc_info is per padded
+ *     super-cluster (system s owns super-clusters [pbase[s]/64,
+ *     pbase[s+1]/64)) and offsets are into the one shared pool.
+ *   sfcnl_batch_h_iterate: sfcnl_h_iterate on every system at once, with the
+ *     same rule per particle; a converged system is left unchanged while
+ *     others continue. With use_graph, the launches of one round are captured
+ *     once into a HIP graph on the batch's stream and replayed each round
+ *     (the host reads the status block between rounds); the batch's stream is
+ *     ordered after the context's stream on entry and before it on return.
+ *     The seed (nullable) works as in section 5, except that each system's
+ *     box edge comes from its box (seed->box_edge is ignored). h_sys_rounds
+ *     (nullable, nsys entries) gets, per system, the rounds it took part in
+ *     (the rounds up to and including its first round with no particle
+ *     moved). On SFCNL_E_CAPACITY no radius of the failing round changed,
+ *     so a call with resume set and larger buffers continues the run.
+ * The batch calls enqueue on the context's stream, except _h_iterate (see
+ * above), which waits for its stream. */
+#define SFCNL_BATCH_MAX_SYSTEMS 65535
+typedef struct sfcnl_batch_s *sfcnl_batch;
+int sfcnl_batch_create(sfcnl_ctx ctx, int nsys, const int64_t *h_counts, const float *h_boxes, sfcnl_batch *out);
+void sfcnl_batch_destroy(sfcnl_batch b);
+int sfcnl_batch_layout(sfcnl_batch b, int64_t *n_in, int64_t *n_padded, int64_t *h_in_off, int64_t *h_pbase);
+int sfcnl_batch_sort_workspace(sfcnl_batch b, size_t *ws_bytes);
+int sfcnl_batch_sort(sfcnl_ctx ctx, sfcnl_batch b, const float *d_x, const float *d_y, const float *d_z,
+                     uint64_t *d_keys_out, uint32_t *d_perm_out, void *d_ws, size_t ws_bytes);
+int sfcnl_batch_gather(sfcnl_ctx ctx, sfcnl_batch b, const uint32_t *d_perm, int nfields, const float *const *h_in,
+                       float *const *h_out);
+int sfcnl_batch_nlist_workspace(sfcnl_batch b, const sfcnl_nlist_opts *opts, size_t *ws_bytes);
+int sfcnl_batch_build_clusters(sfcnl_ctx ctx, sfcnl_batch b, const float *d_x, const float *d_y, const float *d_z,
+                               const float *d_h, float *d_bbox_out);
+int sfcnl_batch_build_nlist(sfcnl_ctx ctx, sfcnl_batch b, const uint64_t *d_keys, const float *d_x,
+                            const float *d_y, const float *d_z, const float *d_h, const float *d_bbox,
+                            const sfcnl_nlist_opts *opts, void *d_ws, size_t ws_bytes, uint32_t *d_sc_info,
+                            uint32_t *d_pool, size_t pool_bytes, size_t *h_used_bytes, int64_t *h_max_nj);
+int sfcnl_batch_pass(sfcnl_ctx ctx, sfcnl_batch b, int compress, const uint32_t *d_sc_info, const uint32_t *d_pool,
+                     const float *d_x, const float *d_y, const float *d_z, const float *d_h, const float *d_m,
+                     float *d_rho, int32_t *d_nnb);
+int sfcnl_batch_h_iterate(sfcnl_ctx ctx, sfcnl_batch b, const uint64_t *d_keys, const float *d_x, const float *d_y,
+                          const float *d_z, float *d_h, float *d_bracket, const float *d_m,
+                          const sfcnl_nlist_opts *nl_opts, const sfcnl_hiter_opts *it_opts, float *d_bbox,
+                          void *d_ws, size_t ws_bytes, uint32_t *d_sc_info, uint32_t *d_pool, size_t pool_bytes,
+                          float *d_rho, int32_t *d_nnb, const sfcnl_hseed *seed, int use_graph,
+                          sfcnl_hiter_stats *h_stats, int32_t *h_sys_rounds);
 
 /* ---- Stage timing -------------------------------------------------------
  * When enabled, every call brackets each of its stages with a pair of HIP

@@ -425,13 +425,15 @@ def hseed_features(keys_sorted, h, nnb, bbox, edge0: float, target: int):
     the same for the 64-particle super-cluster box; log((1 + occupancy)/T) of
     the particle's Hilbert-key cell at levels L0-1, L0, L0+1 with
     L0 = clamp(round(log2(edge0 / h)), 2, 20); log2(edge0 / h) - L0;
-    log(T / 100)."""
+    log(T / 100). With nnb None (no count yet: the seed applied before the
+    first round) the first feature is 0."""
     keys = np.asarray(keys_sorted, dtype=np.uint64)
     h = np.asarray(h, dtype=np.float64)
     n = h.shape[0]
     lt = math.log(target)
     f = np.zeros((n, 8))
-    f[:, 0] = np.log(np.asarray(nnb, dtype=np.float64) + 1.0) - lt
+    if nnb is not None:
+        f[:, 0] = np.log(np.asarray(nnb, dtype=np.float64) + 1.0) - lt
     bb = np.asarray(bbox, dtype=np.float64).reshape(-1, 8)
     c = np.arange(n) // 8
     diag = np.sqrt(((bb[:, 4:7] - bb[:, 0:3]) ** 2).sum(axis=1))

@@ -22,10 +22,13 @@ from . import _lib
 __all__ = ["Context", "NeighbourList", "SfcnlError", "sfc_sort", "sfc_gather", "build_clusters",
            "build_nlist", "nlist_pass", "nlist_decode", "h_iterate", "HIterResult", "Pipeline", "SC_SIZE",
            "CLUSTER_SIZE", "hseed_features", "mlp_init", "mlp_infer", "mlp_grad", "mlp_adam", "mlp_train",
-           "MLP_NPARAM"]
+           "MLP_NPARAM", "Batch", "batch_create", "batch_sort", "batch_gather", "batch_build_clusters",
+           "batch_build_nlist", "batch_pass", "batch_h_iterate", "BatchIterResult"]
 
 SC_SIZE = 64
 CLUSTER_SIZE = 8
+SEED_AFTER_FIRST = _lib.SEED_AFTER_FIRST
+SEED_BEFORE_FIRST = _lib.SEED_BEFORE_FIRST
 
 
 class SfcnlError(RuntimeError):
@@ -242,7 +245,8 @@ class HIterResult:
 def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, max_iters: int = 64, m=None,
               compress: bool = True, leaf_bucket: int = 128, max_j_per_sc: int = 512, bracket=None, bbox=None,
               ws=None, pool=None, sc_info=None, rho=None, nnb=None, raise_noconv: bool = False,
-              resume: bool = False, mlp_params=None, box_edge: float = 0.0, seed_scratch=None):
+              resume: bool = False, mlp_params=None, box_edge: float = 0.0, seed_scratch=None,
+              seed_mode: int = _lib.SEED_AFTER_FIRST):
     """Iterates the SFC-ordered radii h (updated in place) to target +- tol
     own-radius neighbours (sfcnl_h_iterate). With mlp_params the first round's
     update comes from the learned seed. Grows list buffers and resumes when
@@ -263,7 +267,8 @@ def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, m
             raise ValueError("box_edge must be given with mlp_params")
         if seed_scratch is None:
             seed_scratch = (e((max(n, 1), _lib.HSEED_NFEAT), torch.int16), e(max(n, 1), torch.float32))
-        hs = _lib.HSeed(mlp_params.data_ptr(), seed_scratch[0].data_ptr(), seed_scratch[1].data_ptr(), box_edge)
+        hs = _lib.HSeed(mlp_params.data_ptr(), seed_scratch[0].data_ptr(), seed_scratch[1].data_ptr(), box_edge,
+                        seed_mode)
     total, moved, resume = 0, 0, int(bool(resume))
     while True:
         if total >= max_iters:
@@ -421,3 +426,204 @@ class Pipeline:
         self.nl = nl
         nlist_pass(ctx, nl, xs, ys, zs, hs, ms, self.rho, self.nnb if want_counts else None, want_counts)
         return nl
+
+
+# --------------------------------------------------------------------------
+# Batches of independent systems (sfcnl_batch_*)
+# --------------------------------------------------------------------------
+
+class Batch:
+    """sfcnl_batch_create: a batch of systems with the given particle counts
+    and key boxes (6 floats each) on the context's device."""
+
+    def __init__(self, ctx: Context, counts, boxes):
+        import numpy as np
+        self.ctx = ctx
+        counts = np.ascontiguousarray(np.asarray(counts, dtype=np.int64))
+        boxes = np.ascontiguousarray(np.asarray(boxes, dtype=np.float32).reshape(-1))
+        self.nsys = int(counts.size)
+        if boxes.size != 6 * self.nsys:
+            raise ValueError("need 6 box values per system")
+        h = C.c_void_p()
+        ctx.check(ctx.lib.sfcnl_batch_create(ctx.handle, self.nsys, counts.ctypes.data_as(C.POINTER(C.c_int64)),
+                                             boxes.ctypes.data_as(C.POINTER(C.c_float)), C.byref(h)))
+        self.handle = h
+        n_in, n_pad = C.c_int64(), C.c_int64()
+        self.in_off = np.zeros(self.nsys + 1, dtype=np.int64)
+        self.pbase = np.zeros(self.nsys + 1, dtype=np.int64)
+        ctx.check(ctx.lib.sfcnl_batch_layout(h, C.byref(n_in), C.byref(n_pad),
+                                             self.in_off.ctypes.data_as(C.POINTER(C.c_int64)),
+                                             self.pbase.ctypes.data_as(C.POINTER(C.c_int64))))
+        self.n_in, self.n_pad = n_in.value, n_pad.value
+        self.counts = counts
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.ctx.lib.sfcnl_batch_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def sc_range(self, s: int):
+        return int(self.pbase[s]) // SC_SIZE, int(self.pbase[s + 1]) // SC_SIZE
+
+
+def batch_create(ctx: Context, counts, boxes) -> Batch:
+    return Batch(ctx, counts, boxes)
+
+
+def batch_sort(ctx: Context, b: Batch, x, y, z, keys=None, perm=None, ws=None):
+    """(keys int64 view of u64, perm int32 view of u32), both padded."""
+    wsb = C.c_size_t()
+    ctx.check(ctx.lib.sfcnl_batch_sort_workspace(b.handle, C.byref(wsb)))
+    keys = ctx.empty(max(b.n_pad, 1), torch.int64) if keys is None else keys
+    perm = ctx.empty(max(b.n_pad, 1), torch.int32) if perm is None else perm
+    ws = ctx.empty(max(wsb.value, 1), torch.uint8) if ws is None else ws
+    for t, nm in ((x, "x"), (y, "y"), (z, "z")):
+        _check_f32(t, b.n_in, nm)
+    ctx.check(ctx.lib.sfcnl_batch_sort(ctx.handle, b.handle, _ptr(x), _ptr(y), _ptr(z), _ptr(keys), _ptr(perm),
+                                       _ptr(ws), ws.numel()))
+    return keys, perm
+
+
+def batch_gather(ctx: Context, b: Batch, perm, fields, outs=None):
+    nf = len(fields)
+    outs = [ctx.empty(max(b.n_pad, 1), torch.float32) for _ in range(nf)] if outs is None else outs
+    for f in fields:
+        _check_f32(f, b.n_in, "field")
+    ins = (C.c_void_p * nf)(*[f.data_ptr() for f in fields])
+    out = (C.c_void_p * nf)(*[o.data_ptr() for o in outs])
+    ctx.check(ctx.lib.sfcnl_batch_gather(ctx.handle, b.handle, _ptr(perm), nf, ins, out))
+    return outs
+
+
+def batch_build_clusters(ctx: Context, b: Batch, x, y, z, h, bbox=None):
+    nc = (b.n_pad + CLUSTER_SIZE - 1) // CLUSTER_SIZE
+    bbox = ctx.empty((max(nc, 1), 8), torch.float32) if bbox is None else bbox
+    ctx.check(ctx.lib.sfcnl_batch_build_clusters(ctx.handle, b.handle, _ptr(x), _ptr(y), _ptr(z), _ptr(h),
+                                                 _ptr(bbox)))
+    return bbox
+
+
+def batch_nlist_workspace(b: Batch, compress=True, leaf_bucket=128, max_j_per_sc=512) -> int:
+    out = C.c_size_t()
+    o = _opts(CLUSTER_SIZE, compress, leaf_bucket, max_j_per_sc)
+    if _lib.load().sfcnl_batch_nlist_workspace(b.handle, C.byref(o), C.byref(out)) != 0:
+        raise SfcnlError(_lib.E_ARG, "sfcnl_batch_nlist_workspace")
+    return out.value
+
+
+def batch_build_nlist(ctx: Context, b: Batch, keys, x, y, z, h, bbox, compress: bool = True, leaf_bucket: int = 128,
+                      max_j_per_sc: int = 512, pool=None, ws=None, sc_info=None, grow: bool = True):
+    """The padded batch's list (one pool, sc_info per padded super-cluster)."""
+    n = b.n_pad
+    nsc = n // SC_SIZE
+    sc_info = ctx.empty((max(nsc, 1), 2), torch.int32) if sc_info is None else sc_info
+    pool = ctx.empty(max(1024, 5 * n), torch.int32) if pool is None else pool
+    while True:
+        o = _opts(CLUSTER_SIZE, compress, leaf_bucket, max_j_per_sc)
+        need = batch_nlist_workspace(b, compress, leaf_bucket, max_j_per_sc)
+        if ws is None or ws.numel() < need:
+            ws = ctx.empty(max(need, 1), torch.uint8)
+        used, maxnj = C.c_size_t(), C.c_int64()
+        rc = ctx.lib.sfcnl_batch_build_nlist(ctx.handle, b.handle, _ptr(keys), _ptr(x), _ptr(y), _ptr(z), _ptr(h),
+                                             _ptr(bbox), C.byref(o), _ptr(ws), ws.numel(), _ptr(sc_info), _ptr(pool),
+                                             pool.numel() * 4, C.byref(used), C.byref(maxnj))
+        if rc == _lib.E_CAPACITY and grow:
+            if maxnj.value > max_j_per_sc:
+                max_j_per_sc = int(maxnj.value)
+            if used.value > pool.numel() * 4:
+                pool = ctx.empty(used.value // 4 + 1024, torch.int32)
+            continue
+        ctx.check(rc)
+        nl = NeighbourList(n, CLUSTER_SIZE, bool(compress), sc_info[:nsc], pool, used.value, maxnj.value)
+        nl.ws, nl.max_j_per_sc = ws, max_j_per_sc
+        return nl
+
+
+def batch_pass(ctx: Context, b: Batch, nl: NeighbourList, x, y, z, h, m=None, rho=None, nnb=None):
+    n = b.n_pad
+    rho = ctx.empty(max(n, 1), torch.float32) if rho is None else rho
+    nnb = ctx.empty(max(n, 1), torch.int32) if nnb is None else nnb
+    ctx.check(ctx.lib.sfcnl_batch_pass(ctx.handle, b.handle, int(nl.compress), _ptr(nl.sc_info), _ptr(nl.pool),
+                                       _ptr(x), _ptr(y), _ptr(z), _ptr(h), _ptr(m), _ptr(rho), _ptr(nnb)))
+    return rho, nnb
+
+
+@dataclass
+class BatchIterResult:
+    iters: int
+    unconverged: int
+    converged: bool
+    sys_rounds: "object"  # numpy int32 [nsys]
+    moved: int
+    used_bytes: int
+    rho: torch.Tensor
+    nnb: torch.Tensor
+
+    def mean_rounds(self, n_real: int) -> float:
+        return self.moved / max(n_real, 1) + 1.0
+
+
+def batch_h_iterate(ctx: Context, b: Batch, keys, x, y, z, h, target: int = 100, tol: int = 1, max_iters: int = 64,
+                    m=None, compress: bool = True, leaf_bucket: int = 128, max_j_per_sc: int = 512,
+                    use_graph: bool = True, mlp_params=None, seed_mode: int = _lib.SEED_AFTER_FIRST,
+                    bufs: dict | None = None):
+    """sfcnl_batch_h_iterate on padded SFC-ordered arrays (h updated in
+    place). `bufs` (a dict, filled on first use) keeps every buffer for reuse
+    across calls; buffers grow and the run resumes on SFCNL_E_CAPACITY."""
+    import numpy as np
+    n = b.n_pad
+    nsc = n // SC_SIZE
+    nc = n // CLUSTER_SIZE
+    e = ctx.empty
+    B = {} if bufs is None else bufs
+    if "bracket" not in B:
+        B["bracket"] = e(max(2 * n, 2), torch.float32)
+        B["bbox"] = e((max(nc, 1), 8), torch.float32)
+        B["sc_info"] = e((max(nsc, 1), 2), torch.int32)
+        B["pool"] = e(max(1024, 6 * n), torch.int32)
+        B["rho"] = e(max(n, 1), torch.float32)
+        B["nnb"] = e(max(n, 1), torch.int32)
+    B.setdefault("max_j", max_j_per_sc)
+    hs = None
+    if mlp_params is not None:
+        if "feat" not in B:
+            B["feat"] = e((max(n, 1), _lib.HSEED_NFEAT), torch.int16)
+            B["delta"] = e(max(n, 1), torch.float32)
+        hs = _lib.HSeed(mlp_params.data_ptr(), B["feat"].data_ptr(), B["delta"].data_ptr(), 0.0, seed_mode)
+    rounds = np.zeros(b.nsys, dtype=np.int32)
+    total, moved, resume = 0, 0, 0
+    while True:
+        mj = B["max_j"]
+        need = batch_nlist_workspace(b, compress, leaf_bucket, mj)
+        if "ws" not in B or B["ws"].numel() < need:
+            B["ws"] = e(max(need, 1), torch.uint8)
+        no = _opts(CLUSTER_SIZE, compress, leaf_bucket, mj)
+        io = _lib.HiterOpts(target, tol, max(max_iters - total, 1), resume)
+        st = _lib.HiterStats()
+        r = np.zeros(b.nsys, dtype=np.int32)
+        seed_arg = C.byref(hs) if (hs is not None and total == 0) else None
+        rc = ctx.lib.sfcnl_batch_h_iterate(ctx.handle, b.handle, _ptr(keys), _ptr(x), _ptr(y), _ptr(z), _ptr(h),
+                                           _ptr(B["bracket"]), _ptr(m), C.byref(no), C.byref(io), _ptr(B["bbox"]),
+                                           _ptr(B["ws"]), B["ws"].numel(), _ptr(B["sc_info"]), _ptr(B["pool"]),
+                                           B["pool"].numel() * 4, _ptr(B["rho"]), _ptr(B["nnb"]), seed_arg,
+                                           int(bool(use_graph)), C.byref(st), r.ctypes.data_as(C.POINTER(C.c_int32)))
+        rounds = np.where(r > 0, total + r, rounds)
+        total += st.iters
+        moved += st.moved
+        if rc == _lib.E_CAPACITY:
+            if st.max_nj > mj:
+                B["max_j"] = int(st.max_nj)
+            if st.used_bytes > B["pool"].numel() * 4:
+                B["pool"] = e(st.used_bytes // 4 + 1024, torch.int32)
+            resume = 1
+            continue
+        conv = rc == 0
+        if rc not in (0, _lib.E_NOCONV):
+            ctx.check(rc)
+        return BatchIterResult(total, st.unconverged, conv, rounds, moved, st.used_bytes, B["rho"], B["nnb"])

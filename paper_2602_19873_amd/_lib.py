@@ -22,8 +22,12 @@ SYMBOLS = [
     "sfc_sort_workspace", "sfc_sort", "sfc_gather", "build_clusters", "build_nlist_workspace", "build_nlist",
     "nlist_pass", "nlist_decode", "sfcnl_profile_begin", "sfcnl_profile_end", "sfcnl_h_iterate",
     "sfcnl_hseed_features", "sfcnl_mlp_init", "sfcnl_mlp_infer", "sfcnl_mlp_grad_workspace", "sfcnl_mlp_grad",
-    "sfcnl_mlp_adam",
+    "sfcnl_mlp_adam", "sfcnl_batch_create", "sfcnl_batch_destroy", "sfcnl_batch_layout", "sfcnl_batch_sort_workspace",
+    "sfcnl_batch_sort", "sfcnl_batch_gather", "sfcnl_batch_nlist_workspace", "sfcnl_batch_build_clusters",
+    "sfcnl_batch_build_nlist", "sfcnl_batch_pass", "sfcnl_batch_h_iterate",
 ]
+
+BATCH_MAX_SYSTEMS = 65535
 
 MLP_NPARAM = 4801
 HSEED_NFEAT = 8
@@ -47,7 +51,12 @@ class HiterStats(C.Structure):
 
 
 class HSeed(C.Structure):
-    _fields_ = [("d_params", C.c_void_p), ("d_feat", C.c_void_p), ("d_delta", C.c_void_p), ("box_edge", C.c_float)]
+    _fields_ = [("d_params", C.c_void_p), ("d_feat", C.c_void_p), ("d_delta", C.c_void_p), ("box_edge", C.c_float),
+                ("mode", C.c_int)]
+
+
+SEED_AFTER_FIRST = 0
+SEED_BEFORE_FIRST = 1
 
 
 _lib = None
@@ -110,5 +119,31 @@ def load():
     lib.sfcnl_profile_begin.restype = i32
     lib.sfcnl_profile_end.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
     lib.sfcnl_profile_end.restype = i32
+    P64 = C.POINTER(i64)
+    lib.sfcnl_batch_create.argtypes = [vp, i32, P64, C.POINTER(C.c_float), C.POINTER(vp)]
+    lib.sfcnl_batch_create.restype = i32
+    lib.sfcnl_batch_destroy.argtypes = [vp]
+    lib.sfcnl_batch_destroy.restype = None
+    lib.sfcnl_batch_layout.argtypes = [vp, P64, P64, P64, P64]
+    lib.sfcnl_batch_layout.restype = i32
+    lib.sfcnl_batch_sort_workspace.argtypes = [vp, C.POINTER(sz)]
+    lib.sfcnl_batch_sort_workspace.restype = i32
+    lib.sfcnl_batch_sort.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, sz]
+    lib.sfcnl_batch_sort.restype = i32
+    lib.sfcnl_batch_gather.argtypes = [vp, vp, vp, i32, C.POINTER(vp), C.POINTER(vp)]
+    lib.sfcnl_batch_gather.restype = i32
+    lib.sfcnl_batch_nlist_workspace.argtypes = [vp, C.POINTER(NlistOpts), C.POINTER(sz)]
+    lib.sfcnl_batch_nlist_workspace.restype = i32
+    lib.sfcnl_batch_build_clusters.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.sfcnl_batch_build_clusters.restype = i32
+    lib.sfcnl_batch_build_nlist.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(NlistOpts), vp, sz, vp, vp,
+                                            sz, C.POINTER(sz), P64]
+    lib.sfcnl_batch_build_nlist.restype = i32
+    lib.sfcnl_batch_pass.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.sfcnl_batch_pass.restype = i32
+    lib.sfcnl_batch_h_iterate.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(NlistOpts),
+                                          C.POINTER(HiterOpts), vp, vp, sz, vp, vp, sz, vp, vp, C.POINTER(HSeed),
+                                          i32, C.POINTER(HiterStats), C.POINTER(i32)]
+    lib.sfcnl_batch_h_iterate.restype = i32
     _lib = lib
     return lib

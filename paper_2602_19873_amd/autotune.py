@@ -1,0 +1,82 @@
+"""Launch-shape autotuner for the batched path.
+
+Picks the octree leaf bucket (particles per leaf, the one free shape of the
+list build: small buckets test more node boxes, large ones more candidate
+j-clusters) by timing one list build plus pass of the whole batch for each
+candidate on the batch's own stream order, with the radii the caller passes.
+Results are cached in a JSON file keyed by (GPU architecture, padded-size
+bucket, workload tag), so a later run on the same kind of batch reuses them.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import torch
+
+from . import batch_build_clusters, batch_build_nlist, batch_pass
+
+CANDIDATES = (32, 64, 128, 256)
+
+
+def default_cache_path() -> str:
+    root = os.environ.get("XDG_CACHE_HOME") or os.path.join(os.path.expanduser("~"), ".cache")
+    return os.path.join(root, "sfcnl", "autotune.json")
+
+
+def cache_key(n_pad: int, tag: str) -> str:
+    arch = torch.cuda.get_device_properties(0).gcnArchName.split(":")[0] if torch.cuda.is_available() else "cpu"
+    return "%s/n2^%d/%s" % (arch, int(math.log2(max(n_pad, 1))), tag or "any")
+
+
+def _load(path):
+    try:
+        with open(path) as f:
+            return json.load(f)
+    except (OSError, ValueError):
+        return {}
+
+
+def tune_batch(ctx, b, keys, x, y, z, h, tag: str = "", candidates=CANDIDATES, reps: int = 3,
+               cache_path: str | None = None, use_cache: bool = True) -> dict:
+    """Returns {"leaf_bucket": best, "ms": {bucket: median ms}, "cached": bool}."""
+    path = cache_path or default_cache_path()
+    key = cache_key(b.n_pad, tag)
+    db = _load(path) if use_cache else {}
+    if use_cache and key in db:
+        out = dict(db[key])
+        out["cached"] = True
+        return out
+    st = ctx.stream
+    times = {}
+    bufs = {}
+    for cand in candidates:
+        ms = []
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            bbox = batch_build_clusters(ctx, b, x, y, z, h, bufs.get("bbox"))
+            nl = batch_build_nlist(ctx, b, keys, x, y, z, h, bbox, leaf_bucket=cand, pool=bufs.get("pool"),
+                                   ws=bufs.get("ws"), sc_info=bufs.get("sc_info"),
+                                   max_j_per_sc=bufs.get("max_j", 512))
+            rho, nnb = batch_pass(ctx, b, nl, x, y, z, h, rho=bufs.get("rho"), nnb=bufs.get("nnb"))
+            e1.record(st)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+            bufs.update(bbox=bbox, pool=nl.pool, sc_info=nl.sc_info, max_j=nl.max_j_per_sc, rho=rho, nnb=nnb)
+            if nl.ws is not None and (bufs.get("ws") is None or nl.ws.numel() > bufs["ws"].numel()):
+                bufs["ws"] = nl.ws
+        ms = sorted(ms[1:])  # the first call sizes the buffers
+        times[cand] = ms[len(ms) // 2]
+    best = min(times, key=times.get)
+    out = {"leaf_bucket": int(best), "ms": {str(k): round(v, 4) for k, v in times.items()}}
+    if use_cache:
+        db = _load(path)
+        db[key] = out
+        os.makedirs(os.path.dirname(path), exist_ok=True)
+        with open(path, "w") as f:
+            json.dump(db, f, indent=1, sort_keys=True)
+    out = dict(out)
+    out["cached"] = False
+    return out

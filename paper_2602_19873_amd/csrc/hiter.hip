@@ -2,6 +2,8 @@
 // own-radius neighbour count by rebuilding the list (the paper rebuilds its
 // list every step with per-particle radii, Sec. IV; the update rule is this
 // library's, stated in sfcnl.h).
+#include <vector>
+
 #include "internal.h"
 
 namespace sfcnl {
@@ -14,15 +16,41 @@ __global__ __launch_bounds__(256) void k_bracket_init(int64_t n, float2 *__restr
     if (i < n) br[i] = make_float2(0.0f, INFINITY);
 }
 
+// Learned step before the first round: h *= exp(clamp(d, -ln 8, ln 8)) where
+// d is finite (real particles only).
+__global__ __launch_bounds__(256) void k_seed_apply(int64_t n, float *__restrict__ h, const float *__restrict__ d,
+                                                    SegTable seg) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    if (seg.on()) {
+        const int sy = seg.sc_sys[i / kScSize];
+        if ((uint32_t)i - seg.pbase[sy] >= seg.count[sy]) return;
+    }
+    const float v = d[i];
+    if (__builtin_isfinite(v)) h[i] = h[i] * expf(fminf(fmaxf(v, -kLn8), kLn8));
+}
+
 // One round of the update rule; `proposal` (nullable) holds learned
 // log(h_new / h) values that replace the cube-root step where they are finite
-// and within a factor 8.
+// and within a factor 8. Nothing changes when the round's list could not be
+// built (input, capacity or tree flags set in the status block), so that a
+// round launched without a host check can be repeated after the fix.
+// Batched systems skip their padding and count moves per system (a wave's 64
+// particles are one super-cluster, hence one system).
 __global__ __launch_bounds__(256) void k_h_update(int64_t n, const int32_t *__restrict__ nnb, float *__restrict__ h,
                                                   float2 *__restrict__ br, int target, int tol,
-                                                  const float *__restrict__ proposal, uint32_t *unconverged) {
+                                                  const float *__restrict__ proposal, uint32_t *status, SegTable seg,
+                                                  uint32_t *sys_moved) {
+    if (status[kStInputErr] | status[kStPoolOverflow] | status[kStScratch] | status[kStTree]) return;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool moved = false;
-    if (i < n) {
+    int sy = 0;
+    bool real = i < n;
+    if (seg.on() && i < n) {
+        sy = seg.sc_sys[i / kScSize];
+        real = (uint32_t)i - seg.pbase[sy] < seg.count[sy];
+    }
+    if (real) {
         const int c = nnb[i];
         const int dev = c - target;
         if (dev > tol || dev < -tol) {
@@ -56,7 +84,10 @@ __global__ __launch_bounds__(256) void k_h_update(int64_t n, const int32_t *__re
         }
     }
     const uint64_t m = sfc_ballot(moved);
-    if (sfc_lane() == 0 && m) atomicAdd(unconverged, (uint32_t)sfc_popc(m));
+    if (sfc_lane() == 0 && m) {
+        atomicAdd(&status[kStUnconverged], (uint32_t)sfc_popc(m));
+        if (sys_moved) atomicAdd(&sys_moved[sy], (uint32_t)sfc_popc(m));
+    }
 }
 
 }  // namespace
@@ -86,13 +117,25 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
     }
     if (!d_keys || !d_x || !d_y || !d_z || !d_h || !d_bracket || !d_bbox || !d_rho || !d_nnb)
         return set_err(ctx, SFCNL_E_ARG, "sfcnl_h_iterate: null pointer");
-    if (seed && (!seed->d_params || !seed->d_feat || !seed->d_delta || !(seed->box_edge > 0.0f)))
+    if (seed && (!seed->d_params || !seed->d_feat || !seed->d_delta || !(seed->box_edge > 0.0f) ||
+                 (seed->mode != SFCNL_SEED_AFTER_FIRST && seed->mode != SFCNL_SEED_BEFORE_FIRST)))
         return set_err(ctx, SFCNL_E_ARG, "sfcnl_h_iterate: incomplete seed");
     hipStream_t strm = ctx->stream;
     float2 *br = reinterpret_cast<float2 *>(d_bracket);
     if (!it_opts->resume) {
         k_bracket_init<<<blocks_for(n, 256), 256, 0, strm>>>(n, br);
         SFCNL_LAUNCHED(ctx);
+        if (seed && seed->mode == SFCNL_SEED_BEFORE_FIRST) {
+            int rc = build_clusters(ctx, n, d_x, d_y, d_z, d_h, nl_opts->cluster_size, d_bbox);
+            if (rc) return rc;
+            rc = features_impl(ctx, n, d_keys, d_h, nullptr, d_bbox, seed->box_edge, it_opts->target, seed->d_feat,
+                               SegTable{});
+            if (rc) return rc;
+            rc = sfcnl_mlp_infer(ctx, seed->d_params, n, seed->d_feat, seed->d_delta);
+            if (rc) return rc;
+            k_seed_apply<<<blocks_for(n, 256), 256, 0, strm>>>(n, d_h, seed->d_delta, SegTable{});
+            SFCNL_LAUNCHED(ctx);
+        }
     }
     for (int it = 0; it < it_opts->max_iters; it++) {
         int rc = build_clusters(ctx, n, d_x, d_y, d_z, d_h, nl_opts->cluster_size, d_bbox);
@@ -104,7 +147,7 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
                         d_rho, d_nnb);
         if (rc) return rc;
         const float *proposal = nullptr;
-        if (seed && it == 0) {  // learned first step from the first round's counts
+        if (seed && seed->mode == SFCNL_SEED_AFTER_FIRST && it == 0) {  // learned step from the first counts
             rc = sfcnl_hseed_features(ctx, n, d_keys, d_h, d_nnb, d_bbox, seed->box_edge, it_opts->target,
                                       seed->d_feat);
             if (rc) return rc;
@@ -115,7 +158,7 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
         rc = fill_u32(ctx, ctx->d_status + kStUnconverged, 1, 0);
         if (rc) return rc;
         k_h_update<<<blocks_for(n, 256), 256, 0, strm>>>(n, d_nnb, d_h, br, it_opts->target, it_opts->tol, proposal,
-                                                        ctx->d_status + kStUnconverged);
+                                                        ctx->d_status, SegTable{}, nullptr);
         SFCNL_LAUNCHED(ctx);
         SFCNL_HIP(ctx, hipMemcpyAsync(ctx->h_status + kStUnconverged, ctx->d_status + kStUnconverged,
                                       sizeof(uint32_t), hipMemcpyDeviceToHost, strm));
@@ -126,5 +169,203 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
         if (S.unconverged == 0) return SFCNL_OK;
     }
     return set_err(ctx, SFCNL_E_NOCONV, "sfcnl_h_iterate: %lld particles unconverged after %d rounds",
+                   (long long)S.unconverged, it_opts->max_iters);
+}
+
+// ---------------------------------------------------------------------------
+// Batched iteration: every round is one fixed sequence of launches over all
+// systems (cluster boxes, octrees, traversal, encode, pass, update, status
+// copy), captured once into a graph and replayed; the host only reads the
+// status block between rounds.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct RoundArgs {
+    sfcnl_batch b;
+    const uint64_t *keys;
+    const float *x, *y, *z, *m;
+    float *h;
+    float2 *br;
+    const sfcnl_nlist_opts *nl;
+    const sfcnl_hiter_opts *it;
+    float *bbox;
+    void *ws;
+    size_t ws_bytes;
+    uint32_t *sc_info, *pool;
+    size_t pool_bytes;
+    float *rho;
+    int32_t *nnb;
+};
+
+// Enqueues one round on ctx->stream; `seed` adds the learned first step.
+int enqueue_round(sfcnl_ctx ctx, const RoundArgs &r, const sfcnl_hseed *seed) {
+    const SegTable seg = seg_of(r.b);
+    const int64_t n = r.b->n_pad;
+    int rc = clusters_impl(ctx, n, r.x, r.y, r.z, r.h, r.bbox, seg);
+    if (rc) return rc;
+    rc = nlist_build_impl(ctx, n, r.keys, r.x, r.y, r.z, r.h, r.bbox, *r.nl, r.ws, r.ws_bytes, r.sc_info, r.pool,
+                          r.pool_bytes, seg, false, nullptr, nullptr);
+    if (rc) return rc;
+    rc = pass_impl(ctx, n, r.nl->compress, r.sc_info, r.pool, r.x, r.y, r.z, r.h, r.m, r.rho, r.nnb, seg);
+    if (rc) return rc;
+    const float *proposal = nullptr;
+    if (seed) {
+        rc = features_impl(ctx, n, r.keys, r.h, r.nnb, r.bbox, 1.0f, r.it->target, seed->d_feat, seg);
+        if (rc) return rc;
+        rc = sfcnl_mlp_infer(ctx, seed->d_params, n, seed->d_feat, seed->d_delta);
+        if (rc) return rc;
+        proposal = seed->d_delta;
+    }
+    rc = fill_u32(ctx, ctx->d_status + kStUnconverged, 1, 0);
+    if (rc) return rc;
+    rc = fill_u32(ctx, r.b->d_sys_moved, r.b->nsys, 0);
+    if (rc) return rc;
+    k_h_update<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, r.nnb, r.h, r.br, r.it->target, r.it->tol, proposal,
+                                                           ctx->d_status, seg, r.b->d_sys_moved);
+    SFCNL_LAUNCHED(ctx);
+    SFCNL_HIP(ctx, hipMemcpyAsync(ctx->h_status, ctx->d_status, kStWords * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                  ctx->stream));
+    SFCNL_HIP(ctx, hipMemcpyAsync(r.b->h_sys_moved, r.b->d_sys_moved, r.b->nsys * sizeof(uint32_t),
+                                  hipMemcpyDeviceToHost, ctx->stream));
+    return SFCNL_OK;
+}
+
+// Runs the batch's work on its own stream, ordered after the caller's stream
+// and before the caller's later work; restores the context on every exit.
+struct OnBatchStream {
+    sfcnl_ctx ctx;
+    sfcnl_batch b;
+    hipStream_t user;
+    int prof_slots;
+    OnBatchStream(sfcnl_ctx c, sfcnl_batch bb) : ctx(c), b(bb), user(c->stream), prof_slots(c->prof_slots) {
+        (void)hipEventRecord(b->ev_in, user);
+        (void)hipStreamWaitEvent(b->stream, b->ev_in, 0);
+        ctx->stream = b->stream;
+    }
+    ~OnBatchStream() {
+        (void)hipEventRecord(b->ev_out, b->stream);
+        (void)hipStreamWaitEvent(user, b->ev_out, 0);
+        ctx->stream = user;
+        ctx->prof_slots = prof_slots;
+    }
+};
+
+struct GraphHolder {
+    hipGraph_t g = nullptr;
+    hipGraphExec_t e = nullptr;
+    ~GraphHolder() {
+        if (e) (void)hipGraphExecDestroy(e);
+        if (g) (void)hipGraphDestroy(g);
+    }
+};
+
+}  // namespace
+
+extern "C" int sfcnl_batch_h_iterate(sfcnl_ctx ctx, sfcnl_batch b, const uint64_t *d_keys, const float *d_x,
+                                     const float *d_y, const float *d_z, float *d_h, float *d_bracket,
+                                     const float *d_m, const sfcnl_nlist_opts *nl_opts,
+                                     const sfcnl_hiter_opts *it_opts, float *d_bbox, void *d_ws, size_t ws_bytes,
+                                     uint32_t *d_sc_info, uint32_t *d_pool, size_t pool_bytes, float *d_rho,
+                                     int32_t *d_nnb, const sfcnl_hseed *seed, int use_graph,
+                                     sfcnl_hiter_stats *st_out, int32_t *h_sys_rounds) {
+    if (!ctx) return SFCNL_E_ARG;
+    if (!b || b->device != ctx->device) return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_h_iterate: bad batch");
+    if (!it_opts || !nl_opts || !st_out) return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_h_iterate: null argument");
+    sfcnl_hiter_stats &S = *st_out;
+    S.iters = 0;
+    S.unconverged = b->n_in;
+    S.moved = 0;
+    S.used_bytes = 0;
+    S.max_nj = 0;
+    if (h_sys_rounds)
+        for (int s = 0; s < b->nsys; s++) h_sys_rounds[s] = 0;
+    if (it_opts->target < 1 || it_opts->tol < 0 || it_opts->max_iters < 1)
+        return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_h_iterate: target >= 1, tol >= 0, max_iters >= 1 required");
+    size_t need;
+    if (sfcnl_batch_nlist_workspace(b, nl_opts, &need))
+        return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_h_iterate: bad list options");
+    if (ws_bytes < need)
+        return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_h_iterate: workspace %zu < %zu bytes", ws_bytes, need);
+    if (b->n_in == 0) {
+        S.unconverged = 0;
+        return SFCNL_OK;
+    }
+    if (!d_keys || !d_x || !d_y || !d_z || !d_h || !d_bracket || !d_bbox || !d_ws || !d_sc_info || !d_rho || !d_nnb ||
+        (!d_pool && pool_bytes))
+        return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_h_iterate: null pointer");
+    if (seed && (!seed->d_params || !seed->d_feat || !seed->d_delta ||
+                 (seed->mode != SFCNL_SEED_AFTER_FIRST && seed->mode != SFCNL_SEED_BEFORE_FIRST)))
+        return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_h_iterate: incomplete seed");
+
+    RoundArgs r{b,     d_keys, d_x,    d_y,     d_z,       d_m,    d_h,  reinterpret_cast<float2 *>(d_bracket),
+                nl_opts, it_opts, d_bbox, d_ws, ws_bytes, d_sc_info, d_pool, pool_bytes, d_rho, d_nnb};
+    OnBatchStream on(ctx, b);
+    hipStream_t st = ctx->stream;
+    if (!it_opts->resume) {
+        k_bracket_init<<<blocks_for(b->n_pad, 256), 256, 0, st>>>(b->n_pad, r.br);
+        SFCNL_LAUNCHED(ctx);
+        if (seed && seed->mode == SFCNL_SEED_BEFORE_FIRST) {
+            const SegTable seg = seg_of(b);
+            int rc = clusters_impl(ctx, b->n_pad, d_x, d_y, d_z, d_h, d_bbox, seg);
+            if (rc) return rc;
+            rc = features_impl(ctx, b->n_pad, d_keys, d_h, nullptr, d_bbox, 1.0f, it_opts->target, seed->d_feat, seg);
+            if (rc) return rc;
+            rc = sfcnl_mlp_infer(ctx, seed->d_params, b->n_pad, seed->d_feat, seed->d_delta);
+            if (rc) return rc;
+            k_seed_apply<<<blocks_for(b->n_pad, 256), 256, 0, st>>>(b->n_pad, d_h, seed->d_delta, seg);
+            SFCNL_LAUNCHED(ctx);
+        }
+    }
+    GraphHolder gh;
+    std::vector<char> active((size_t)b->nsys, 1);
+    for (int it = 0; it < it_opts->max_iters; it++) {
+        const sfcnl_hseed *sd = (seed && seed->mode == SFCNL_SEED_AFTER_FIRST && it == 0) ? seed : nullptr;
+        if (use_graph && !sd) {
+            if (!gh.e) {
+                ctx->prof_slots = 0;  // no event records inside the graph
+                SFCNL_HIP(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+                int rc = enqueue_round(ctx, r, nullptr);
+                hipGraph_t g = nullptr;
+                hipError_t e = hipStreamEndCapture(st, &g);
+                gh.g = g;
+                if (rc) return rc;
+                if (e != hipSuccess) return set_err(ctx, SFCNL_E_HIP, "graph capture failed: %s", hipGetErrorString(e));
+                SFCNL_HIP(ctx, hipGraphInstantiate(&gh.e, gh.g, nullptr, nullptr, 0));
+                ctx->prof_slots = on.prof_slots;
+            }
+            SFCNL_HIP(ctx, hipGraphLaunch(gh.e, st));
+        } else {
+            int rc = enqueue_round(ctx, r, sd);
+            if (rc) return rc;
+        }
+        SFCNL_HIP(ctx, hipStreamSynchronize(st));
+        const uint32_t *hs = ctx->h_status;
+        S.used_bytes = (size_t)hs[kStTotalLo] * 4;
+        S.max_nj = hs[kStMaxNj];
+        if (hs[kStInputErr]) {
+            const uint32_t e = hs[kStInputErr];
+            int rc = fill_u32(ctx, ctx->d_status + kStInputErr, 1, 0);
+            if (rc) return rc;
+            return set_err(ctx, SFCNL_E_INPUT, "input error flags 0x%x (1: non-finite position, 2: bad radius)", e);
+        }
+        if (hs[kStTree]) return set_err(ctx, SFCNL_E_HIP, "internal error: octree invariant broken (0x%x)", hs[kStTree]);
+        if (hs[kStScratch])
+            return set_err(ctx, SFCNL_E_CAPACITY, "a super-cluster lists %u j-clusters > max_j_per_sc %d", hs[kStMaxNj],
+                           nl_opts->max_j_per_sc);
+        if (hs[kStPoolOverflow])
+            return set_err(ctx, SFCNL_E_CAPACITY, "pool of %zu bytes < %zu needed", pool_bytes, S.used_bytes);
+        S.iters = it + 1;
+        S.unconverged = hs[kStUnconverged];
+        S.moved += S.unconverged;
+        // a system takes part in a round while its previous round moved a
+        // particle (every system takes part in the first)
+        if (h_sys_rounds)
+            for (int s = 0; s < b->nsys; s++)
+                if (it == 0 || active[s]) h_sys_rounds[s] = it + 1;
+        for (int s = 0; s < b->nsys; s++) active[s] = b->h_sys_moved[s] != 0;
+        if (S.unconverged == 0) return SFCNL_OK;
+    }
+    return set_err(ctx, SFCNL_E_NOCONV, "sfcnl_batch_h_iterate: %lld particles unconverged after %d rounds",
                    (long long)S.unconverged, it_opts->max_iters);
 }

@@ -92,6 +92,59 @@ int scan_u32(sfcnl_ctx ctx, const uint32_t *in, uint32_t *out, int64_t n, uint32
 // Fills n u32 words with a value (a kernel, so it can sit inside a captured graph).
 int fill_u32(sfcnl_ctx ctx, uint32_t *p, int64_t n, uint32_t v);
 
+// ---- batched systems ----
+// Several independent systems laid out one after another from padded bases
+// that are multiples of 64 particles (padding particles are NaN). All pointers
+// are device pointers; a default-constructed table means one system.
+struct SegTable {
+    int nsys = 0;
+    const uint16_t *sc_sys = nullptr;  // per super-cluster: its system
+    const uint32_t *pbase = nullptr;   // nsys + 1 padded particle bases
+    const uint32_t *count = nullptr;   // nsys real particle counts
+    const float *edge = nullptr;       // nsys key-box edges (features)
+    uint4 *roots = nullptr;            // nsys root records, written by the octree build
+    __host__ __device__ bool on() const { return sc_sys != nullptr; }
+};
+
+}  // namespace sfcnl
+
+// A batch of independent systems (batch.hip). Input particles are the
+// systems concatenated (system s at in_off[s]); the padded layout puts system
+// s at pbase[s], a multiple of 64, followed by NaN padding up to pbase[s+1].
+struct sfcnl_batch_s {
+    int device;
+    int nsys;
+    int64_t n_in, n_pad;
+    int64_t *h_in_off;   // nsys + 1
+    int64_t *h_pbase;    // nsys + 1
+    float *h_box;        // 6 per system
+    // device tables
+    uint16_t *d_sc_sys;      // n_pad / 64
+    uint32_t *d_pbase;       // nsys + 1
+    uint32_t *d_count;       // nsys
+    uint32_t *d_in_off;      // nsys + 1
+    float *d_edge;           // nsys: largest box side
+    float *d_lo, *d_scale;   // 3 per system: key quantisation
+    uint4 *d_roots;          // nsys
+    uint32_t *d_sys_moved;   // nsys: particles moved in the last round
+    uint32_t *h_sys_moved;   // pinned mirror
+    hipStream_t stream;      // capture stream (default priority)
+    hipEvent_t ev_in, ev_out;
+};
+
+namespace sfcnl {
+
+inline SegTable seg_of(const sfcnl_batch_s *b) {
+    SegTable t;
+    t.nsys = b->nsys;
+    t.sc_sys = b->d_sc_sys;
+    t.pbase = b->d_pbase;
+    t.count = b->d_count;
+    t.edge = b->d_edge;
+    t.roots = b->d_roots;
+    return t;
+}
+
 // ---- pieces of build_nlist (octree.hip, traverse.hip) ----
 struct Octree {
     int64_t n;
@@ -117,9 +170,26 @@ struct Octree {
     void *scan_tmp;
 };
 
-void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket);
+void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket, int nsys = 1);
 int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x, const float *y,
-                 const float *z, const float *h, const float4 *cluster_box);
+                 const float *z, const float *h, const float4 *cluster_box, const SegTable &seg);
+
+// build_nlist without argument checks; `readback` waits for the stream and
+// reports capacity and input errors (otherwise the flags stay on the device).
+size_t nlist_ws_bytes(int64_t n, const sfcnl_nlist_opts &o, int nsys);
+int nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *keys, const float *x, const float *y, const float *z,
+                     const float *h, const float *bbox, const sfcnl_nlist_opts &o, void *ws, size_t ws_bytes,
+                     uint32_t *sc_info, uint32_t *pool, size_t pool_bytes, const SegTable &seg, bool readback,
+                     size_t *used_bytes, int64_t *max_nj);
+int clusters_impl(sfcnl_ctx ctx, int64_t n, const float *x, const float *y, const float *z, const float *h,
+                  float *bbox, const SegTable &seg);
+int pass_impl(sfcnl_ctx ctx, int64_t n, int compress, const uint32_t *sc_info, const uint32_t *pool, const float *x,
+              const float *y, const float *z, const float *h, const float *m, float *rho, int32_t *nnb,
+              const SegTable &seg);
+int features_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *keys, const float *h, const int32_t *nnb,
+                  const float *bbox, float box_edge, int target, uint16_t *feat, const SegTable &seg);
+// reads the status block into pinned memory (kStWords words) and waits
+int read_status(sfcnl_ctx ctx);
 
 }  // namespace sfcnl
 

@@ -333,8 +333,7 @@ __global__ __launch_bounds__(256) void k_mlp_init(uint64_t seed, float *__restri
 //        closest to h
 //   6 log2(edge_0 / h) - L0 (where h falls between levels)
 //   7 log(target / 100)
-__device__ __forceinline__ uint32_t lower_bound_key(const uint64_t *keys, uint32_t n, uint64_t v) {
-    uint32_t lo = 0, hi = n;
+__device__ __forceinline__ uint32_t lower_bound_key(const uint64_t *keys, uint32_t lo, uint32_t hi, uint64_t v) {
     while (lo < hi) {
         const uint32_t mid = lo + (hi - lo) / 2;
         if (keys[mid] < v)
@@ -348,13 +347,25 @@ __device__ __forceinline__ uint32_t lower_bound_key(const uint64_t *keys, uint32
 __global__ __launch_bounds__(256) void k_features(int64_t n, const uint64_t *__restrict__ keys,
                                                   const float *__restrict__ h, const int32_t *__restrict__ nnb,
                                                   const float4 *__restrict__ bbox, float edge0, int target,
-                                                  uint16_t *__restrict__ feat) {
+                                                  uint16_t *__restrict__ feat, SegTable seg) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
+    // key searches stay inside the particle's own system
+    uint32_t klo = 0, khi = (uint32_t)n;
+    if (seg.on()) {
+        const int sy = seg.sc_sys[i / kScSize];
+        klo = seg.pbase[sy];
+        khi = klo + seg.count[sy];
+        edge0 = seg.edge[sy];
+        if ((uint32_t)i >= khi) {  // padding
+            *reinterpret_cast<uint4 *>(feat + i * kIn) = make_uint4(0u, 0u, 0u, 0u);
+            return;
+        }
+    }
     const float hi = h[i];
     const float lt = logf((float)target);
     float f[kIn];
-    f[0] = logf((float)nnb[i] + 1.0f) - lt;
+    f[0] = nnb ? logf((float)nnb[i] + 1.0f) - lt : 0.0f;  // no count yet: 0
     const int64_t c = i / kCs;
     const float4 lo1 = bbox[2 * c], hi1 = bbox[2 * c + 1];
     const float d1 = sqrtf((hi1.x - lo1.x) * (hi1.x - lo1.x) + (hi1.y - lo1.y) * (hi1.y - lo1.y) +
@@ -383,8 +394,8 @@ __global__ __launch_bounds__(256) void k_features(int64_t n, const uint64_t *__r
         const int L = L0 + d;
         const int shift = 3 * (21 - L);
         const uint64_t pre = key >> shift;
-        const uint32_t a = lower_bound_key(keys, (uint32_t)n, pre << shift);
-        const uint32_t b = lower_bound_key(keys, (uint32_t)n, (pre + 1) << shift);
+        const uint32_t a = lower_bound_key(keys, klo, khi, pre << shift);
+        const uint32_t b = lower_bound_key(keys, klo, khi, (pre + 1) << shift);
         f[4 + d] = logf(1.0f + (float)(b - a)) - lt;
     }
     f[6] = lev - (float)L0;
@@ -465,17 +476,22 @@ extern "C" int sfcnl_mlp_adam(sfcnl_ctx ctx, float *d_params, const float *d_gra
     return SFCNL_OK;
 }
 
+int sfcnl::features_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_h, const int32_t *d_nnb,
+                         const float *d_bbox, float box_edge, int target, uint16_t *d_feat, const SegTable &seg) {
+    k_features<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, d_keys, d_h, d_nnb,
+                                                            reinterpret_cast<const float4 *>(d_bbox), box_edge,
+                                                            target, d_feat, seg);
+    SFCNL_LAUNCHED(ctx);
+    return SFCNL_OK;
+}
+
 extern "C" int sfcnl_hseed_features(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_h,
                                     const int32_t *d_nnb, const float *d_bbox, float box_edge, int target,
                                     uint16_t *d_feat) {
     if (!ctx) return SFCNL_E_ARG;
     if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "sfcnl_hseed_features: n out of range");
     if (n == 0) return SFCNL_OK;
-    if (!d_keys || !d_h || !d_nnb || !d_bbox || !d_feat || !(box_edge > 0.0f) || target < 1)
+    if (!d_keys || !d_h || !d_bbox || !d_feat || !(box_edge > 0.0f) || target < 1)
         return set_err(ctx, SFCNL_E_ARG, "sfcnl_hseed_features: bad argument");
-    k_features<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, d_keys, d_h, d_nnb,
-                                                            reinterpret_cast<const float4 *>(d_bbox), box_edge,
-                                                            target, d_feat);
-    SFCNL_LAUNCHED(ctx);
-    return SFCNL_OK;
+    return features_impl(ctx, n, d_keys, d_h, d_nnb, d_bbox, box_edge, target, d_feat, SegTable{});
 }

@@ -70,9 +70,16 @@ __device__ __forceinline__ uint32_t nibbles_of(uint32_t v) { return (32u - (uint
 __global__ __launch_bounds__(256) void k_cluster_bbox(int64_t n, const float *__restrict__ x,
                                                       const float *__restrict__ y, const float *__restrict__ z,
                                                       const float *__restrict__ h, float4 *__restrict__ bbox,
-                                                      uint32_t *status) {
+                                                      uint32_t *status, SegTable seg) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= (n + kCs - 1) / kCs) return;
+    // batched systems: particles from pend on are padding (NaN, ignored by
+    // fminf / fmaxf and never checked)
+    int64_t pend = n;
+    if (seg.on()) {
+        const int sy = seg.sc_sys[c / kSub];
+        pend = (int64_t)seg.pbase[sy] + seg.count[sy];
+    }
     float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
     float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
     uint32_t bad = 0;
@@ -81,8 +88,9 @@ __global__ __launch_bounds__(256) void k_cluster_bbox(int64_t n, const float *__
         int64_t p = c * kCs + k;
         if (p < n) {
             float px = x[p], py = y[p], pz = z[p], ph = h[p];
-            if (!(isfinite(px) && isfinite(py) && isfinite(pz))) bad |= 1u;
-            if (!(isfinite(ph) && ph > 0.0f)) bad |= 2u;
+            const bool pad = p >= pend;
+            if (!pad && !(isfinite(px) && isfinite(py) && isfinite(pz))) bad |= 1u;
+            if (!pad && !(isfinite(ph) && ph > 0.0f)) bad |= 2u;
             lo.x = fminf(lo.x, px);
             lo.y = fminf(lo.y, py);
             lo.z = fminf(lo.z, pz);
@@ -109,6 +117,7 @@ struct TravArgs {
     const float4 *cs_box;  // octree child slots (slot 0 = root)
     const uint4 *cs_rec;
     uint32_t nslots;       // capacity of the slot arrays
+    SegTable seg;          // batched systems (empty for one system)
     uint32_t *list_j;
     uint8_t *list_m;
     uint32_t *sc_nj, *sc_words;
@@ -146,7 +155,16 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
     // slot}; a node is pushed only after its box passed the test
     uint4 *stack = s_stack[w];
     int sp = 0;
-    if (lane == 0) stack[0] = a.cs_rec[0];  // root
+    // the tree of this super-cluster's system; list entries are cluster
+    // indices relative to the system's first cluster
+    uint32_t jbase = 0;
+    if (a.seg.on()) {
+        const int sy = a.seg.sc_sys[s];
+        jbase = a.seg.pbase[sy] / kCs;
+        if (lane == 0) stack[0] = a.seg.roots[sy];
+    } else {
+        if (lane == 0) stack[0] = a.cs_rec[0];  // root
+    }
     sp = 1;
     wave_sync();
 
@@ -229,12 +247,13 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                         }
                     }
                     if (mask) {
+                        const uint32_t jl_idx = cjv - jbase;
                         if (nj < a.cap && lane == 0) {
-                            out_j[nj] = cjv;
+                            out_j[nj] = jl_idx;
                             out_m[nj] = (uint8_t)mask;
                         }
-                        const uint32_t v = cjv - prevj;
-                        prevj = cjv;
+                        const uint32_t v = jl_idx - prevj;
+                        prevj = jl_idx;
                         blk_nib += v == 1u ? 0u : (v <= 9u ? 1u : 1u + nibbles_of(v));
                         if (++blk_cnt == 64u) {
                             seg_words += 2u + (blk_nib + 7u) / 8u;
@@ -305,15 +324,15 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
     const uint32_t nj = a.sc_nj[s];
     const uint32_t off = a.sc_off[s];
     const uint32_t words = a.sc_off[s + 1] - off;
+    // a list that could not be stored is recorded as empty (the status block
+    // reports it), so that a pass launched regardless never reads past the pool
+    const bool fits = nj <= a.cap && (uint64_t)off + words <= a.pool_words;
     if (lane == 0) {
         a.sc_info[2 * s] = off;
-        a.sc_info[2 * s + 1] = nj;
+        a.sc_info[2 * s + 1] = fits ? nj : 0u;
+        if (nj <= a.cap && !fits) atomicOr(&a.status[kStPoolOverflow], 1u);
     }
-    if (nj > a.cap) return;
-    if ((uint64_t)off + words > a.pool_words) {
-        if (lane == 0) atomicOr(&a.status[kStPoolOverflow], 1u);
-        return;
-    }
+    if (!fits) return;
     const uint32_t *lj = a.list_j + (size_t)s * a.cap;
     const uint8_t *lm = a.list_m + (size_t)s * a.cap;
     uint32_t *out = a.pool + off;
@@ -386,9 +405,9 @@ struct NlistWs {
     void *scan_tmp;
 };
 
-void carve_nlist(Carver &cv, NlistWs &ws, int64_t n, const sfcnl_nlist_opts &o) {
+void carve_nlist(Carver &cv, NlistWs &ws, int64_t n, const sfcnl_nlist_opts &o, int nsys = 1) {
     const uint32_t nsc = (uint32_t)((n + kScSize - 1) / kScSize);
-    octree_carve(cv, ws.tree, n, o.leaf_bucket);
+    octree_carve(cv, ws.tree, n, o.leaf_bucket, nsys);
     ws.list_j = cv.take<uint32_t>((size_t)nsc * o.max_j_per_sc);
     ws.list_m = cv.take<uint8_t>((size_t)nsc * o.max_j_per_sc);
     ws.sc_nj = cv.take<uint32_t>(nsc);
@@ -412,6 +431,18 @@ int check_opts(sfcnl_ctx ctx, const sfcnl_nlist_opts *o) {
 
 using namespace sfcnl;
 
+int sfcnl::clusters_impl(sfcnl_ctx ctx, int64_t n, const float *x, const float *y, const float *z, const float *h,
+                         float *bbox, const SegTable &seg) {
+    if (n == 0) return SFCNL_OK;
+    const int64_t nclu = (n + kCs - 1) / kCs;
+    prof_mark(ctx, kStageClusters, false);
+    k_cluster_bbox<<<blocks_for(nclu, 256), 256, 0, ctx->stream>>>(n, x, y, z, h, reinterpret_cast<float4 *>(bbox),
+                                                                   ctx->d_status, seg);
+    SFCNL_LAUNCHED(ctx);
+    prof_mark(ctx, kStageClusters, true);
+    return SFCNL_OK;
+}
+
 extern "C" int build_clusters(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y, const float *d_z,
                               const float *d_h, int cluster_size, float *d_bbox_out) {
     if (!ctx) return SFCNL_E_ARG;
@@ -419,53 +450,46 @@ extern "C" int build_clusters(sfcnl_ctx ctx, int64_t n, const float *d_x, const 
     if (cluster_size != kCs) return set_err(ctx, SFCNL_E_ARG, "build_clusters: cluster_size %d not supported", cluster_size);
     if (n == 0) return SFCNL_OK;
     if (!d_x || !d_y || !d_z || !d_h || !d_bbox_out) return set_err(ctx, SFCNL_E_ARG, "build_clusters: null pointer");
-    const int64_t nclu = (n + kCs - 1) / kCs;
-    prof_mark(ctx, kStageClusters, false);
-    k_cluster_bbox<<<blocks_for(nclu, 256), 256, 0, ctx->stream>>>(n, d_x, d_y, d_z, d_h,
-                                                                   reinterpret_cast<float4 *>(d_bbox_out), ctx->d_status);
-    SFCNL_LAUNCHED(ctx);
-    prof_mark(ctx, kStageClusters, true);
-    return SFCNL_OK;
+    return clusters_impl(ctx, n, d_x, d_y, d_z, d_h, d_bbox_out, SegTable{});
+}
+
+size_t sfcnl::nlist_ws_bytes(int64_t n, const sfcnl_nlist_opts &o, int nsys) {
+    Carver cv{nullptr, 0};
+    NlistWs ws;
+    carve_nlist(cv, ws, n, o, nsys);
+    return align_up(cv.used, 256) + 256;
 }
 
 extern "C" int build_nlist_workspace(int64_t n, const sfcnl_nlist_opts *opts, size_t *ws_bytes) {
     if (n < 0 || !ws_bytes || !opts || check_opts(nullptr, opts)) return SFCNL_E_ARG;
-    Carver cv{nullptr, 0};
-    NlistWs ws;
-    carve_nlist(cv, ws, n, *opts);
-    *ws_bytes = align_up(cv.used, 256) + 256;
+    *ws_bytes = nlist_ws_bytes(n, *opts, 1);
     return SFCNL_OK;
 }
 
-extern "C" int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_x, const float *d_y,
-                           const float *d_z, const float *d_h, const float *d_bbox, const sfcnl_nlist_opts *opts,
-                           void *d_ws, size_t ws_bytes, uint32_t *d_sc_info, uint32_t *d_pool, size_t pool_bytes,
-                           size_t *h_used_bytes, int64_t *h_max_nj) {
-    if (!ctx) return SFCNL_E_ARG;
-    int rc = check_opts(ctx, opts);
-    if (rc) return rc;
-    if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "build_nlist: n out of range");
-    if (!h_used_bytes || !h_max_nj) return set_err(ctx, SFCNL_E_ARG, "build_nlist: null result pointer");
-    *h_used_bytes = 0;
-    *h_max_nj = 0;
-    if (n == 0) return SFCNL_OK;
-    if (!d_keys || !d_x || !d_y || !d_z || !d_h || !d_bbox || !d_ws || !d_sc_info || (!d_pool && pool_bytes))
-        return set_err(ctx, SFCNL_E_ARG, "build_nlist: null pointer");
-    size_t need;
-    build_nlist_workspace(n, opts, &need);
-    if (ws_bytes < need) return set_err(ctx, SFCNL_E_ARG, "build_nlist: workspace %zu < %zu bytes", ws_bytes, need);
+int sfcnl::read_status(sfcnl_ctx ctx) {
+    SFCNL_HIP(ctx, hipMemcpyAsync(ctx->h_status, ctx->d_status, kStWords * sizeof(uint32_t), hipMemcpyDeviceToHost,
+                                  ctx->stream));
+    SFCNL_HIP(ctx, hipStreamSynchronize(ctx->stream));
+    return SFCNL_OK;
+}
 
+int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_x, const float *d_y,
+                            const float *d_z, const float *d_h, const float *d_bbox, const sfcnl_nlist_opts &o,
+                            void *d_ws, size_t ws_bytes, uint32_t *d_sc_info, uint32_t *d_pool, size_t pool_bytes,
+                            const SegTable &seg, bool readback, size_t *h_used_bytes, int64_t *h_max_nj) {
+    const int nsys = seg.on() ? seg.nsys : 1;
     Carver cv{reinterpret_cast<char *>(d_ws), 0};
     NlistWs ws;
-    carve_nlist(cv, ws, n, *opts);
+    carve_nlist(cv, ws, n, o, nsys);
+    if (cv.used > ws_bytes) return set_err(ctx, SFCNL_E_ARG, "build_nlist: workspace %zu < %zu bytes", ws_bytes, cv.used);
     const uint32_t nsc = (uint32_t)((n + kScSize - 1) / kScSize);
     const uint32_t nclu = (uint32_t)((n + kCs - 1) / kCs);
     hipStream_t st = ctx->stream;
 
-    rc = fill_u32(ctx, ctx->d_status + kStPoolOverflow, kStWords - kStPoolOverflow, 0);
+    int rc = fill_u32(ctx, ctx->d_status + kStPoolOverflow, kStWords - kStPoolOverflow, 0);
     if (rc) return rc;
     prof_mark(ctx, kStageOctree, false);
-    rc = octree_build(ctx, ws.tree, d_keys, d_x, d_y, d_z, d_h, reinterpret_cast<const float4 *>(d_bbox));
+    rc = octree_build(ctx, ws.tree, d_keys, d_x, d_y, d_z, d_h, reinterpret_cast<const float4 *>(d_bbox), seg);
     if (rc) return rc;
     prof_mark(ctx, kStageOctree, true);
 
@@ -473,8 +497,8 @@ extern "C" int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, con
     ta.n = n;
     ta.nsc = nsc;
     ta.nclu = nclu;
-    ta.cap = (uint32_t)opts->max_j_per_sc;
-    ta.compress = opts->compress;
+    ta.cap = (uint32_t)o.max_j_per_sc;
+    ta.compress = o.compress;
     ta.x = d_x;
     ta.y = d_y;
     ta.z = d_z;
@@ -483,6 +507,7 @@ extern "C" int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, con
     ta.cs_box = ws.tree.cs_box;
     ta.cs_rec = ws.tree.cs_rec;
     ta.nslots = ws.tree.node_cap;
+    ta.seg = seg;
     ta.list_j = ws.list_j;
     ta.list_m = ws.list_m;
     ta.sc_nj = ws.sc_nj;
@@ -500,7 +525,7 @@ extern "C" int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, con
     EncArgs ea;
     ea.nsc = nsc;
     ea.cap = ta.cap;
-    ea.compress = opts->compress;
+    ea.compress = o.compress;
     ea.list_j = ws.list_j;
     ea.list_m = ws.list_m;
     ea.sc_nj = ws.sc_nj;
@@ -514,9 +539,10 @@ extern "C" int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, con
     prof_mark(ctx, kStageEncode, true);
     k_finish<<<1, 1, 0, st>>>(ws.sc_off + nsc, ctx->d_status);
     SFCNL_LAUNCHED(ctx);
+    if (!readback) return SFCNL_OK;
 
-    SFCNL_HIP(ctx, hipMemcpyAsync(ctx->h_status, ctx->d_status, kStWords * sizeof(uint32_t), hipMemcpyDeviceToHost, st));
-    SFCNL_HIP(ctx, hipStreamSynchronize(st));
+    rc = read_status(ctx);
+    if (rc) return rc;
     const uint32_t *hs = ctx->h_status;
     *h_used_bytes = (size_t)hs[kStTotalLo] * 4;
     *h_max_nj = hs[kStMaxNj];
@@ -529,8 +555,26 @@ extern "C" int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, con
     if (hs[kStTree]) return set_err(ctx, SFCNL_E_HIP, "internal error: octree invariant broken (0x%x)", hs[kStTree]);
     if (hs[kStScratch])
         return set_err(ctx, SFCNL_E_CAPACITY, "a super-cluster lists %u j-clusters > max_j_per_sc %d", hs[kStMaxNj],
-                       opts->max_j_per_sc);
+                       o.max_j_per_sc);
     if (hs[kStPoolOverflow])
         return set_err(ctx, SFCNL_E_CAPACITY, "pool of %zu bytes < %zu needed", pool_bytes, *h_used_bytes);
     return SFCNL_OK;
+}
+
+extern "C" int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_x, const float *d_y,
+                           const float *d_z, const float *d_h, const float *d_bbox, const sfcnl_nlist_opts *opts,
+                           void *d_ws, size_t ws_bytes, uint32_t *d_sc_info, uint32_t *d_pool, size_t pool_bytes,
+                           size_t *h_used_bytes, int64_t *h_max_nj) {
+    if (!ctx) return SFCNL_E_ARG;
+    int rc = check_opts(ctx, opts);
+    if (rc) return rc;
+    if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "build_nlist: n out of range");
+    if (!h_used_bytes || !h_max_nj) return set_err(ctx, SFCNL_E_ARG, "build_nlist: null result pointer");
+    *h_used_bytes = 0;
+    *h_max_nj = 0;
+    if (n == 0) return SFCNL_OK;
+    if (!d_keys || !d_x || !d_y || !d_z || !d_h || !d_bbox || !d_ws || !d_sc_info || (!d_pool && pool_bytes))
+        return set_err(ctx, SFCNL_E_ARG, "build_nlist: null pointer");
+    return nlist_build_impl(ctx, n, d_keys, d_x, d_y, d_z, d_h, d_bbox, *opts, d_ws, ws_bytes, d_sc_info, d_pool,
+                            pool_bytes, SegTable{}, true, h_used_bytes, h_max_nj);
 }

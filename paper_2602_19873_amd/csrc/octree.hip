@@ -36,13 +36,33 @@ __device__ __forceinline__ uint32_t node_count(const uint32_t *d_nnodes, uint32_
     return nn < cap ? nn : cap;
 }
 
+// Real particle range [lo, hi) of the system holding particle p (the whole
+// array for one system); the padding after hi belongs to no node.
+__device__ __forceinline__ void seg_range(const SegTable &seg, int64_t p, int64_t n, int64_t &lo, int64_t &hi) {
+    if (seg.on()) {
+        const int sy = seg.sc_sys[p / kScSize];
+        lo = seg.pbase[sy];
+        hi = lo + seg.count[sy];
+    } else {
+        lo = 0;
+        hi = n;
+    }
+}
+
 __global__ __launch_bounds__(256) void k_digits(const uint64_t *__restrict__ keys, int64_t n, int bucket,
-                                                int8_t *__restrict__ cdig, int8_t *__restrict__ lam) {
+                                                int8_t *__restrict__ cdig, int8_t *__restrict__ lam, SegTable seg) {
     int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
+    int64_t lo, hi;
+    seg_range(seg, p, n, lo, hi);  // systems never share a cell: each starts its own root
+    if (p >= hi) {  // padding: starts no node (cdig >= every leaf level)
+        cdig[p] = 127;
+        lam[p] = -1;
+        return;
+    }
     uint64_t k = keys[p];
-    cdig[p] = (int8_t)(p == 0 ? -1 : sfc_common_digits(keys[p - 1], k));
-    lam[p] = (int8_t)(p + bucket < n ? sfc_common_digits(k, keys[p + bucket]) : -1);
+    cdig[p] = (int8_t)(p == lo ? -1 : sfc_common_digits(keys[p - 1], k));
+    lam[p] = (int8_t)(p + bucket < hi ? sfc_common_digits(k, keys[p + bucket]) : -1);
 }
 
 __global__ __launch_bounds__(256) void k_leaf_level(const int8_t *__restrict__ cdig, const int8_t *__restrict__ lam,
@@ -89,18 +109,20 @@ __global__ __launch_bounds__(256) void k_node_range(const uint64_t *__restrict__
                                                     const uint32_t *__restrict__ d_nnodes, uint32_t cap,
                                                     const uint32_t *__restrict__ nfirst,
                                                     const uint8_t *__restrict__ nlevel, uint32_t *__restrict__ nend,
-                                                    uint32_t *__restrict__ nesc, uint32_t *status) {
+                                                    uint32_t *__restrict__ nesc, uint32_t *status, SegTable seg) {
     const uint32_t nn = node_count(d_nnodes, cap);
     uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k == 0 && *d_nnodes > cap) atomicOr(&status[kStTree], 1u);
     if (k >= nn) return;
     uint32_t f = nfirst[k];
     int L = nlevel[k];
-    uint32_t end = (uint32_t)n;
+    int64_t slo, shi;
+    seg_range(seg, f, n, slo, shi);
+    uint32_t end = (uint32_t)shi;  // a root spans its whole system
     if (L > 0) {
         const int shift = 3 * (kMaxLevel - L);
         const uint64_t pre = keys[f] >> shift;
-        uint32_t lo = f + 1, hi = (uint32_t)n;
+        uint32_t lo = f + 1, hi = (uint32_t)shi;
         while (lo < hi) {
             uint32_t mid = lo + (hi - lo) / 2;
             if ((keys[mid] >> shift) == pre)
@@ -247,14 +269,30 @@ __global__ __launch_bounds__(256) void k_child_slots(const uint32_t *__restrict_
     }
 }
 
+// Root record of every system (the level-0 node at its first particle).
+__global__ void k_roots(SegTable seg, const uint32_t *__restrict__ node_at, const uint32_t *__restrict__ nfirst,
+                        const uint32_t *__restrict__ nend, const uint8_t *__restrict__ nnchild,
+                        const uint32_t *__restrict__ cbase, const uint32_t *__restrict__ d_nnodes, uint32_t cap) {
+    const int sy = blockIdx.x * blockDim.x + threadIdx.x;
+    if (sy >= seg.nsys) return;
+    const uint32_t nn = node_count(d_nnodes, cap);
+    const uint32_t p = seg.pbase[sy];
+    uint4 r = make_uint4(p, p, 0u, 0u);  // empty system: no super-cluster ever reads it
+    if (seg.count[sy] > 0) {
+        const uint32_t k = node_at[p];
+        if (k < nn) r = make_uint4(nfirst[k], nend[k], nnchild[k], 1u + cbase[k]);
+    }
+    seg.roots[sy] = r;
+}
+
 }  // namespace
 
-static size_t node_capacity(int64_t n, int bucket) {
+static size_t node_capacity(int64_t n, int bucket, int nsys) {
     // heavy cells of one level are disjoint and hold > bucket particles each;
     // levels 0..20 can be heavy and every node is a heavy cell or its child
-    int64_t heavy = 21 * (n / (bucket + 1) + 1);
+    int64_t heavy = 21 * (n / (bucket + 1) + nsys);
     int64_t cap = 9 * heavy + 2;
-    int64_t lim = 22 * n + 2;
+    int64_t lim = 22 * n + 2 * nsys;
     return (size_t)(cap < lim ? cap : lim);
 }
 
@@ -270,10 +308,10 @@ static int box_levels(int64_t n, int64_t *sizes) {
     return nl;
 }
 
-void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket) {
+void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket, int nsys) {
     t.n = n;
     t.bucket = bucket;
-    size_t nc = node_capacity(n, bucket);
+    size_t nc = node_capacity(n, bucket, nsys);
     t.node_cap = (uint32_t)nc;
     t.cdig = cv.take<int8_t>((size_t)n);
     t.lam = cv.take<int8_t>((size_t)n);
@@ -298,27 +336,27 @@ void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket) {
 }
 
 int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x, const float *y, const float *z,
-                 const float *h, const float4 *cluster_box) {
+                 const float *h, const float4 *cluster_box, const SegTable &seg) {
     const int64_t n = t.n;
     const int B = t.bucket;
     if (B < 1 || B > kMaxBucket) return set_err(ctx, SFCNL_E_ARG, "octree: bucket %d out of range", B);
     hipStream_t st = ctx->stream;
     const unsigned gp = blocks_for(n, 256);
-    k_digits<<<gp, 256, 0, st>>>(keys, n, B, t.cdig, t.lam);
+    k_digits<<<gp, 256, 0, st>>>(keys, n, B, t.cdig, t.lam, seg);
     SFCNL_LAUNCHED(ctx);
     uint32_t *cnt = t.node_at;  // counts, scanned in place
     k_leaf_level<<<gp, 256, 0, st>>>(t.cdig, t.lam, n, B, t.lleaf, cnt);
     SFCNL_LAUNCHED(ctx);
     int rc = scan_u32(ctx, cnt, t.node_at, n, t.d_nnodes, t.scan_tmp);
     if (rc) return rc;
-    const uint32_t cap = (uint32_t)node_capacity(n, B);
+    const uint32_t cap = t.node_cap;
     k_emit_nodes<<<gp, 256, 0, st>>>(t.cdig, t.lleaf, t.node_at, n, cap, t.nfirst, t.nlevel, t.nleaf);
     SFCNL_LAUNCHED(ctx);
     // the node count is only known on the device: launch for the proven upper
     // bound; threads past the count return at once
     const unsigned gn = blocks_for((int64_t)cap, 256);
     k_node_range<<<gn, 256, 0, st>>>(keys, n, t.node_at, t.d_nnodes, cap, t.nfirst, t.nlevel, t.nend, t.nesc,
-                                     ctx->d_status);
+                                     ctx->d_status, seg);
     SFCNL_LAUNCHED(ctx);
     k_children<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nleaf, t.nesc, t.nchild, t.nnchild, ctx->d_status);
     SFCNL_LAUNCHED(ctx);
@@ -346,6 +384,11 @@ int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x,
     k_child_slots<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nfirst, t.nend, t.nchild, t.nnchild, t.cbase, t.nbox,
                                       t.cs_box, t.cs_rec);
     SFCNL_LAUNCHED(ctx);
+    if (seg.on()) {
+        k_roots<<<blocks_for(seg.nsys, 64), 64, 0, st>>>(seg, t.node_at, t.nfirst, t.nend, t.nnchild, t.cbase,
+                                                         t.d_nnodes, cap);
+        SFCNL_LAUNCHED(ctx);
+    }
     return SFCNL_OK;
 }
 

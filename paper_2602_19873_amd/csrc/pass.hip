@@ -64,6 +64,7 @@ struct PassArgs {
     const float *x, *y, *z, *h, *m;
     float *rho;
     int32_t *nnb;
+    SegTable seg;  // batched systems: list indices are relative to the system's first cluster
 };
 
 template <bool kCompress, bool kMass, bool kCount>
@@ -101,6 +102,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
     const uint32_t own_c0 = s * kSub;
     const uint32_t off = a.sc_info[2 * s], nj = a.sc_info[2 * s + 1];
     const uint8_t *mbytes = reinterpret_cast<const uint8_t *>(a.pool + off);
+    const uint32_t jbase = a.seg.on() ? a.seg.pbase[a.seg.sc_sys[s]] / kCs : 0u;
     uint32_t p = off + (nj + 3u) / 4u;
     uint32_t prevj = 0xFFFFFFFFu;
     for (uint32_t b0 = 0; b0 < nj; b0 += kWave) {
@@ -113,6 +115,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
         }
         const uint32_t mv = (uint32_t)lane < cnt ? mbytes[b0 + lane] : 0u;
         prevj = sfc_readlane(jv, (int)cnt - 1);
+        jv += jbase;
         // software pipeline: the next entry's j-particles load while the
         // current entry's tiles run
         uint32_t cj = sfc_readlane(jv, 0);
@@ -232,17 +235,11 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
 
 using namespace sfcnl;
 
-extern "C" int nlist_pass(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, const uint32_t *d_sc_info,
-                          const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z,
-                          const float *d_h, const float *d_m, float *d_rho, int32_t *d_nnb) {
-    if (!ctx) return SFCNL_E_ARG;
-    if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: n out of range");
-    if (cluster_size != kCs) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: cluster_size %d not supported", cluster_size);
-    if (compress != 0 && compress != 1) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: compress must be 0 or 1");
-    if (n == 0) return SFCNL_OK;
-    if (!d_sc_info || !d_pool || !d_x || !d_y || !d_z || !d_h || !d_rho)
-        return set_err(ctx, SFCNL_E_ARG, "nlist_pass: null pointer");
-    PassArgs a{n, (uint32_t)((n + kScSize - 1) / kScSize), d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb};
+int sfcnl::pass_impl(sfcnl_ctx ctx, int64_t n, int compress, const uint32_t *d_sc_info, const uint32_t *d_pool,
+                     const float *d_x, const float *d_y, const float *d_z, const float *d_h, const float *d_m,
+                     float *d_rho, int32_t *d_nnb, const SegTable &seg) {
+    PassArgs a{n, (uint32_t)((n + kScSize - 1) / kScSize), d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb,
+               seg};
     const unsigned g = blocks_for(a.nsc, kWavesPerBlock);
     hipStream_t st = ctx->stream;
     const bool hm = d_m != nullptr, hc = d_nnb != nullptr;
@@ -265,6 +262,19 @@ extern "C" int nlist_pass(sfcnl_ctx ctx, int64_t n, int cluster_size, int compre
     SFCNL_LAUNCHED(ctx);
     prof_mark(ctx, kStagePass, true);
     return SFCNL_OK;
+}
+
+extern "C" int nlist_pass(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, const uint32_t *d_sc_info,
+                          const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z,
+                          const float *d_h, const float *d_m, float *d_rho, int32_t *d_nnb) {
+    if (!ctx) return SFCNL_E_ARG;
+    if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: n out of range");
+    if (cluster_size != kCs) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: cluster_size %d not supported", cluster_size);
+    if (compress != 0 && compress != 1) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: compress must be 0 or 1");
+    if (n == 0) return SFCNL_OK;
+    if (!d_sc_info || !d_pool || !d_x || !d_y || !d_z || !d_h || !d_rho)
+        return set_err(ctx, SFCNL_E_ARG, "nlist_pass: null pointer");
+    return pass_impl(ctx, n, compress, d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb, SegTable{});
 }
 
 extern "C" int nlist_decode(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, const uint32_t *d_sc_info,

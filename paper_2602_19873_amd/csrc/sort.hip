@@ -89,8 +89,35 @@ constexpr int kWavesPerBlock = kThreads / kWave;
 constexpr int kRadix = 256;
 constexpr int kPasses = 8;
 
-__global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ keys, int64_t n, int shift,
-                                                   uint32_t ntiles, uint32_t *__restrict__ hist) {
+// System of input particle i: the last s with off[s] <= i (off has nsys + 1
+// entries, off[0] = 0).
+__device__ __forceinline__ uint32_t system_of(uint32_t i, const uint32_t *__restrict__ off, int nsys) {
+    int lo = 0, hi = nsys;  // off[lo] <= i < off[hi]
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= i)
+            lo = mid;
+        else
+            hi = mid;
+    }
+    return (uint32_t)lo;
+}
+
+// Digit of an element: 8 bits of its key, or (batched systems) 8 bits of the
+// system its original index belongs to.
+struct DigitOf {
+    int shift;
+    const uint32_t *sys_off;  // null: key digit
+    int nsys;
+    __device__ __forceinline__ uint32_t operator()(uint64_t key, uint32_t val) const {
+        if (sys_off) return (system_of(val, sys_off, nsys) >> shift) & 255u;
+        return (uint32_t)(key >> shift) & 255u;
+    }
+};
+
+__global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ keys, const uint32_t *__restrict__ vals,
+                                                   int64_t n, DigitOf dg, uint32_t ntiles,
+                                                   uint32_t *__restrict__ hist) {
     __shared__ uint32_t s_h[kRadix];
     const int t = threadIdx.x;
     s_h[t] = 0;
@@ -99,7 +126,7 @@ __global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ 
 #pragma unroll
     for (int k = 0; k < kItems; k++) {
         int64_t i = base + k * kThreads + t;
-        if (i < n) atomicAdd(&s_h[(uint32_t)(keys[i] >> shift) & 255u], 1u);
+        if (i < n) atomicAdd(&s_h[dg(dg.sys_off ? 0ull : keys[i], dg.sys_off ? vals[i] : 0u)], 1u);
     }
     __syncthreads();
     hist[(size_t)t * ntiles + blockIdx.x] = s_h[t];
@@ -144,7 +171,7 @@ __global__ __launch_bounds__(kThreads) void k_digit_scan(uint32_t *__restrict__ 
 
 __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict__ kin, const uint32_t *__restrict__ vin,
                                                       uint64_t *__restrict__ kout, uint32_t *__restrict__ vout,
-                                                      int64_t n, int shift, uint32_t ntiles,
+                                                      int64_t n, DigitOf dg, uint32_t ntiles,
                                                       const uint32_t *__restrict__ hist,
                                                       const uint32_t *__restrict__ digit_tot) {
     __shared__ uint64_t s_keys[kTile];
@@ -170,7 +197,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
         bool valid = li < tile_n;
         key[k] = valid ? kin[base + li] : 0ull;
         val[k] = valid ? vin[base + li] : 0u;
-        uint32_t d = (uint32_t)(key[k] >> shift) & 255u;
+        uint32_t d = valid ? dg(key[k], val[k]) : 0u;
         uint64_t m = sfc_ballot(valid);
 #pragma unroll
         for (int b = 0; b < 8; b++) {
@@ -220,7 +247,7 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
     for (int k = 0; k < kItems; k++) {
         int li = w * (kItems * kWave) + k * kWave + lane;
         if (li < tile_n) {
-            uint32_t d = (uint32_t)(key[k] >> shift) & 255u;
+            uint32_t d = dg(key[k], val[k]);
             uint32_t lp = s_cnt[w][d] + lrank[k];
             s_keys[lp] = key[k];
             s_vals[lp] = val[k];
@@ -232,10 +259,11 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
         int lp = k * kThreads + t;
         if (lp < tile_n) {
             uint64_t kk = s_keys[lp];
-            uint32_t d = (uint32_t)(kk >> shift) & 255u;
+            uint32_t vv = s_vals[lp];
+            uint32_t d = dg(kk, vv);
             uint32_t gp = s_gbase[d] + (uint32_t)lp;
             kout[gp] = kk;
-            vout[gp] = s_vals[lp];
+            vout[gp] = vv;
         }
     }
 }
@@ -246,18 +274,64 @@ struct GatherArgs {
     int nf;
 };
 
-__global__ __launch_bounds__(256) void k_gather(int64_t n, const uint32_t *__restrict__ perm, GatherArgs a,
-                                                uint32_t *status) {
+// out[f][i] = in[f][perm[i]] for i < n_out, perm[i] < n_in; with `pad`, the
+// index 0xFFFFFFFF marks a padding slot that gets NaN.
+__global__ __launch_bounds__(256) void k_gather(int64_t n_out, int64_t n_in, const uint32_t *__restrict__ perm,
+                                                GatherArgs a, bool pad, uint32_t *status) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    if (i >= n_out) return;
     uint32_t p = perm[i];
-    if (p >= (uint64_t)n) {  // not a permutation of [0, n): report, never read outside
+    if (pad && p == 0xFFFFFFFFu) {
+#pragma unroll
+        for (int f = 0; f < 8; f++)
+            if (f < a.nf) a.out[f][i] = __builtin_nanf("");
+        return;
+    }
+    if (p >= (uint64_t)n_in) {  // not a permutation of [0, n): report, never read outside
         atomicOr(&status[kStInputErr], 4u);
         p = 0;
     }
 #pragma unroll
     for (int f = 0; f < 8; f++)
         if (f < a.nf) a.out[f][i] = a.in[f][p];
+}
+
+// Keys of batched systems: particle i of the concatenated input uses its own
+// system's box.
+__global__ __launch_bounds__(256) void k_batch_keys(int64_t n, const float *__restrict__ x,
+                                                    const float *__restrict__ y, const float *__restrict__ z,
+                                                    const uint32_t *__restrict__ in_off, int nsys,
+                                                    const float *__restrict__ lo, const float *__restrict__ sc,
+                                                    uint64_t *__restrict__ keys, uint32_t *__restrict__ idx,
+                                                    uint32_t *status) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const uint32_t sy = system_of((uint32_t)i, in_off, nsys);
+    float px = x[i], py = y[i], pz = z[i];
+    if (!(isfinite(px) && isfinite(py) && isfinite(pz))) atomicOr(&status[kStInputErr], 1u);
+    keys[i] = hilbert_key(quantise(px, lo[3 * sy], sc[3 * sy]), quantise(py, lo[3 * sy + 1], sc[3 * sy + 1]),
+                          quantise(pz, lo[3 * sy + 2], sc[3 * sy + 2]));
+    idx[i] = (uint32_t)i;
+}
+
+// Spreads the (system, key)-sorted input into the padded layout: slot q of
+// system s holds its (q - pbase[s])-th particle, or padding (key all ones,
+// index 0xFFFFFFFF).
+__global__ __launch_bounds__(256) void k_batch_pad(int64_t n_pad, const uint64_t *__restrict__ ks,
+                                                   const uint32_t *__restrict__ vs, SegTable seg,
+                                                   const uint32_t *__restrict__ in_off, uint64_t *__restrict__ keys,
+                                                   uint32_t *__restrict__ perm) {
+    int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (q >= n_pad) return;
+    const int sy = seg.sc_sys[q / kScSize];
+    const uint32_t local = (uint32_t)q - seg.pbase[sy];
+    if (local < seg.count[sy]) {
+        keys[q] = ks[in_off[sy] + local];
+        perm[q] = vs[in_off[sy] + local];
+    } else {
+        keys[q] = ~0ull;
+        perm[q] = 0xFFFFFFFFu;
+    }
 }
 
 struct SortWs {
@@ -274,6 +348,20 @@ size_t carve_sort(Carver &cv, SortWs &s, int64_t n) {
     s.hist = cv.take<uint32_t>((size_t)kRadix * ntiles);
     s.dtot = cv.take<uint32_t>(kRadix);
     return cv.used;
+}
+
+// One stable counting pass: (ka, va) -> (kb, vb) by the digit dg.
+int radix_pass(sfcnl_ctx ctx, const SortWs &s, const uint64_t *ka, const uint32_t *va, uint64_t *kb, uint32_t *vb,
+               int64_t n, DigitOf dg) {
+    hipStream_t st = ctx->stream;
+    const uint32_t ntiles = blocks_for(n, kTile);
+    k_hist<<<ntiles, kThreads, 0, st>>>(ka, va, n, dg, ntiles, s.hist);
+    SFCNL_LAUNCHED(ctx);
+    k_digit_scan<<<kRadix, kThreads, 0, st>>>(s.hist, ntiles, s.dtot);
+    SFCNL_LAUNCHED(ctx);
+    k_scatter<<<ntiles, kThreads, 0, st>>>(ka, va, kb, vb, n, dg, ntiles, s.hist, s.dtot);
+    SFCNL_LAUNCHED(ctx);
+    return SFCNL_OK;
 }
 
 float box_scale(float lo, float hi) { return (float)(2097152.0 / ((double)hi - (double)lo)); }
@@ -318,17 +406,11 @@ extern "C" int sfc_sort(sfcnl_ctx ctx, int64_t n, const float *d_x, const float 
     SFCNL_LAUNCHED(ctx);
     prof_mark(ctx, kStageKeys, true);
     prof_mark(ctx, kStageSort, false);
-    const uint32_t ntiles = blocks_for(n, kTile);
     uint64_t *ka = d_keys_out, *kb = s.ktmp;
     uint32_t *va = d_perm_out, *vb = s.vtmp;
     for (int pass = 0; pass < kPasses; pass++) {
-        int shift = 8 * pass;
-        k_hist<<<ntiles, kThreads, 0, st>>>(ka, n, shift, ntiles, s.hist);
-        SFCNL_LAUNCHED(ctx);
-        k_digit_scan<<<kRadix, kThreads, 0, st>>>(s.hist, ntiles, s.dtot);
-        SFCNL_LAUNCHED(ctx);
-        k_scatter<<<ntiles, kThreads, 0, st>>>(ka, va, kb, vb, n, shift, ntiles, s.hist, s.dtot);
-        SFCNL_LAUNCHED(ctx);
+        int rc = radix_pass(ctx, s, ka, va, kb, vb, n, DigitOf{8 * pass, nullptr, 0});
+        if (rc) return rc;
         uint64_t *tk = ka;
         ka = kb;
         kb = tk;
@@ -356,7 +438,111 @@ extern "C" int sfc_gather(sfcnl_ctx ctx, int64_t n, const uint32_t *d_perm, int 
         a.out[f] = h_out[f];
     }
     prof_mark(ctx, kStageGather, false);
-    k_gather<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, d_perm, a, ctx->d_status);
+    k_gather<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, n, d_perm, a, false, ctx->d_status);
+    SFCNL_LAUNCHED(ctx);
+    prof_mark(ctx, kStageGather, true);
+    return SFCNL_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Batched systems: keys in each system's own box, a stable sort by (system,
+// key) -- the key passes, then one or two passes on the system of the
+// original index -- and the spread into the padded layout.
+// ---------------------------------------------------------------------------
+
+namespace {
+
+struct BatchSortWs {
+    SortWs s;
+    uint64_t *k2;
+    uint32_t *v2;
+};
+
+size_t carve_batch_sort(Carver &cv, BatchSortWs &w, int64_t n_in) {
+    carve_sort(cv, w.s, n_in);
+    w.k2 = cv.take<uint64_t>((size_t)n_in);
+    w.v2 = cv.take<uint32_t>((size_t)n_in);
+    return cv.used;
+}
+
+}  // namespace
+
+extern "C" int sfcnl_batch_sort_workspace(sfcnl_batch b, size_t *ws_bytes) {
+    if (!b || !ws_bytes) return SFCNL_E_ARG;
+    Carver cv{nullptr, 0};
+    BatchSortWs w;
+    *ws_bytes = align_up(carve_batch_sort(cv, w, b->n_in), 256) + 256;
+    return SFCNL_OK;
+}
+
+extern "C" int sfcnl_batch_sort(sfcnl_ctx ctx, sfcnl_batch b, const float *d_x, const float *d_y, const float *d_z,
+                                uint64_t *d_keys_out, uint32_t *d_perm_out, void *d_ws, size_t ws_bytes) {
+    if (!ctx) return SFCNL_E_ARG;
+    if (!b) return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_sort: null batch");
+    if (b->device != ctx->device) return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_sort: batch on another device");
+    if (b->n_pad == 0) return SFCNL_OK;
+    if (!d_keys_out || !d_perm_out || ((!d_x || !d_y || !d_z || !d_ws) && b->n_in))
+        return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_sort: null pointer");
+    size_t need;
+    sfcnl_batch_sort_workspace(b, &need);
+    if (ws_bytes < need)
+        return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_sort: workspace %zu bytes < %zu needed", ws_bytes, need);
+    const int64_t n = b->n_in;
+    const SegTable seg = seg_of(b);
+    hipStream_t st = ctx->stream;
+    if (n == 0) {  // only padding
+        k_batch_pad<<<blocks_for(b->n_pad, 256), 256, 0, st>>>(b->n_pad, nullptr, nullptr, seg, b->d_in_off,
+                                                               d_keys_out, d_perm_out);
+        SFCNL_LAUNCHED(ctx);
+        return SFCNL_OK;
+    }
+    Carver cv{reinterpret_cast<char *>(d_ws), 0};
+    BatchSortWs w;
+    carve_batch_sort(cv, w, n);
+    prof_mark(ctx, kStageKeys, false);
+    k_batch_keys<<<blocks_for(n, 256), 256, 0, st>>>(n, d_x, d_y, d_z, b->d_in_off, b->nsys, b->d_lo, b->d_scale,
+                                                     w.k2, w.v2, ctx->d_status);
+    SFCNL_LAUNCHED(ctx);
+    prof_mark(ctx, kStageKeys, true);
+    prof_mark(ctx, kStageSort, false);
+    uint64_t *ka = w.k2, *kb = w.s.ktmp;
+    uint32_t *va = w.v2, *vb = w.s.vtmp;
+    const int sys_passes = b->nsys <= 1 ? 0 : (b->nsys <= 256 ? 1 : 2);
+    for (int pass = 0; pass < kPasses + sys_passes; pass++) {
+        const DigitOf dg = pass < kPasses ? DigitOf{8 * pass, nullptr, 0}
+                                          : DigitOf{8 * (pass - kPasses), b->d_in_off, b->nsys};
+        int rc = radix_pass(ctx, w.s, ka, va, kb, vb, n, dg);
+        if (rc) return rc;
+        uint64_t *tk = ka;
+        ka = kb;
+        kb = tk;
+        uint32_t *tv = va;
+        va = vb;
+        vb = tv;
+    }
+    k_batch_pad<<<blocks_for(b->n_pad, 256), 256, 0, st>>>(b->n_pad, ka, va, seg, b->d_in_off, d_keys_out,
+                                                           d_perm_out);
+    SFCNL_LAUNCHED(ctx);
+    prof_mark(ctx, kStageSort, true);
+    return SFCNL_OK;
+}
+
+extern "C" int sfcnl_batch_gather(sfcnl_ctx ctx, sfcnl_batch b, const uint32_t *d_perm, int nfields,
+                                  const float *const *h_in, float *const *h_out) {
+    if (!ctx) return SFCNL_E_ARG;
+    if (!b || nfields < 1 || nfields > 8 || !h_in || !h_out)
+        return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_gather: bad arguments");
+    if (b->n_pad == 0) return SFCNL_OK;
+    if (!d_perm) return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_gather: null perm");
+    GatherArgs a{};
+    a.nf = nfields;
+    for (int f = 0; f < nfields; f++) {
+        if ((!h_in[f] && b->n_in) || !h_out[f]) return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_gather: null field %d", f);
+        a.in[f] = h_in[f];
+        a.out[f] = h_out[f];
+    }
+    prof_mark(ctx, kStageGather, false);
+    k_gather<<<blocks_for(b->n_pad, 256), 256, 0, ctx->stream>>>(b->n_pad, b->n_in, d_perm, a, true, ctx->d_status);
     SFCNL_LAUNCHED(ctx);
     prof_mark(ctx, kStageGather, true);
     return SFCNL_OK;

@@ -33,12 +33,17 @@ def sorted_system(ctx, s, h=None):
     return keys, xs, ys, zs, hs
 
 
-def training_pairs(ctx, s, target: int, h_prev: np.ndarray, max_iters: int = 64):
-    """(features int16 bf16 bits [n, 8], targets float32 [n]) for one system."""
+def training_pairs(ctx, s, target: int, h_prev: np.ndarray, max_iters: int = 64, before_first: bool = False):
+    """(features int16 bf16 bits [n, 8], targets float32 [n]) for one system.
+    before_first: features without a count (the seed applied before the
+    first round), so no list is built at h_prev."""
     keys, xs, ys, zs, hs = sorted_system(ctx, s, h_prev)
     bbox = build_clusters(ctx, xs, ys, zs, hs)
-    nl = build_nlist(ctx, keys, xs, ys, zs, hs, bbox)
-    _, nnb = nlist_pass(ctx, nl, xs, ys, zs, hs)
+    if before_first:
+        nnb = None
+    else:
+        nl = build_nlist(ctx, keys, xs, ys, zs, hs, bbox)
+        _, nnb = nlist_pass(ctx, nl, xs, ys, zs, hs)
     feat = hseed_features(ctx, keys, hs, nnb, bbox, box_edge(s.box), target)
     hc = hs.clone()
     res = h_iterate(ctx, keys, xs, ys, zs, hc, target=target, tol=1, max_iters=max_iters)
@@ -60,6 +65,25 @@ def training_set(ctx, n_total: int = 1 << 20, targets=(50, 100, 150, 200), sprea
         rng = np.random.default_rng(seed * 1000 + k)
         hp = (s.h * np.exp(rng.uniform(-math.log(spread), math.log(spread), s.n))).astype(np.float32)
         f, d = training_pairs(ctx, s, T, hp)
+        feats.append(f)
+        ds.append(d)
+    return torch.cat(feats), torch.cat(ds)
+
+
+def mixed_training_set(ctx, target: int = 150, count: int = 16, lo: float = 1e4, hi: float = 2e5,
+                       spread: float = 2.0, seed: int = 11, before_first: bool = True):
+    """Pairs from the batch generators (uniform cube and Plummer sphere,
+    alternating; sizes log-uniform in [lo, hi]) with seeds disjoint from the
+    benchmark batch's; the starting radius is the generator's mean-density
+    radius times a log-uniform factor in [1/spread, spread]."""
+    feats, ds = [], []
+    for k in range(count):
+        rng = np.random.default_rng(seed * 7919 + k)
+        nk = int(round(10.0 ** rng.uniform(math.log10(lo), math.log10(hi))))
+        gseed = seed * 100003 + k
+        s = workloads.uniform_global(nk, gseed, target) if k % 2 == 0 else workloads.plummer(nk, gseed, target=target)
+        hp = (s.h * np.exp(rng.uniform(-math.log(spread), math.log(spread), s.n))).astype(np.float32)
+        f, d = training_pairs(ctx, s, target, hp, before_first=before_first)
         feats.append(f)
         ds.append(d)
     return torch.cat(feats), torch.cat(ds)

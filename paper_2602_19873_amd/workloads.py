@@ -33,7 +33,7 @@ SPHERE_BOX = (-1.0, 1.0, -1.0, 1.0, -1.0, 1.0)
 
 def radius_for_neighbours(n: int, target: float = 200.0, volume: float = 1.0) -> float:
     """Radius whose sphere holds ``target`` particles at mean density n/volume."""
-    return (3.0 * target * volume / (4.0 * math.pi * n)) ** (1.0 / 3.0)
+    return (3.0 * target * volume / (4.0 * math.pi * max(n, 1))) ** (1.0 / 3.0)
 
 
 @dataclass

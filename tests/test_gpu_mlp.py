@@ -116,18 +116,24 @@ def test_init_is_deterministic(env):
     assert w1max <= np.sqrt(6 / 8) and 0.4 < w1std < 0.6, (w1max, w1std)
 
 
-def test_features_match_oracle(env):
+@pytest.mark.parametrize("with_counts", [True, False])
+def test_features_match_oracle(env, with_counts):
     sf, ctx, torch = env
     from paper_2602_19873_amd import hseed
     s = workloads.evrard_sphere(40000, 81, target=100)
     keys, xs, ys, zs, hs = hseed.sorted_system(ctx, s)
     bbox = sf.build_clusters(ctx, xs, ys, zs, hs)
-    nl = sf.build_nlist(ctx, keys, xs, ys, zs, hs, bbox)
-    _, nnb = sf.nlist_pass(ctx, nl, xs, ys, zs, hs)
+    nnb = None
+    if with_counts:
+        nl = sf.build_nlist(ctx, keys, xs, ys, zs, hs, bbox)
+        _, nnb = sf.nlist_pass(ctx, nl, xs, ys, zs, hs)
     feat = sf.hseed_features(ctx, keys, hs, nnb, bbox, hseed.box_edge(s.box), 100)
     got = _bits_to_f64(feat.cpu().numpy()).reshape(-1, 8)
-    ref = oracle.hseed_features(keys.cpu().numpy().view(np.uint64), hs.cpu().numpy(), nnb.cpu().numpy(),
-                                bbox.cpu().numpy(), hseed.box_edge(s.box), 100)
+    ref = oracle.hseed_features(keys.cpu().numpy().view(np.uint64), hs.cpu().numpy(),
+                                None if nnb is None else nnb.cpu().numpy(), bbox.cpu().numpy(),
+                                hseed.box_edge(s.box), 100)
+    if not with_counts:
+        assert np.all(got[:, 0] == 0.0) and np.all(ref[:, 0] == 0.0)
     refq = _bits_to_f64(_bf16_bits(ref)).reshape(-1, 8)
     # equal up to one bf16 step, except where FP32 and FP64 pick different
     # levels (log2 at a half-integer): allow a tiny fraction of rows
