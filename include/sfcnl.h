@@ -87,22 +87,26 @@ int sfc_gather(sfcnl_ctx ctx, int64_t n, const uint32_t *d_perm, int nfields, co
 /* ---- 2. Clusters (Sec. II-A) ---------------------------------------------
  * Cluster c holds SFC-ordered particles [cs*c, min(cs*c + cs, n)). For each
  * cluster: d_bbox_out[8c .. 8c+7] = {lo.x, lo.y, lo.z, max h, hi.x, hi.y,
- * hi.z, 0} (exact FP32 min / max). cluster_size must be 8. Inputs must be in
- * SFC order. Also checks inputs (latched as SFCNL_E_INPUT). */
+ * hi.z, 0} (exact FP32 min / max). cluster_size is 4, 8 or 16 (the paper uses
+ * 8 on wave64 hardware, Sec. II-D; the cluster overhead grows with the size,
+ * Sec. III-A). Inputs must be in SFC order. Also checks inputs (latched as
+ * SFCNL_E_INPUT). */
 int build_clusters(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y, const float *d_z,
                    const float *d_h, int cluster_size, float *d_bbox_out);
 
 /* ---- 3. Neighbour list (Sec. II-A, II-B, II-C) ---------------------------
  * Pair set: (i, j) with i != j and d2 < f32(max(h_i, h_j)^2), where
  * dx = f32(x_j - x_i) (likewise y, z) and d2 = fma(dz, dz, fma(dy, dy, dx*dx)).
- * Super-cluster s = particles [64 s, 64 s + 64) = i-clusters 8 s .. 8 s + 7.
- * Its list holds every j-cluster containing a j paired with some i of s, in
- * ascending order, each with an 8-bit mask whose bit c is set iff some i of
- * i-cluster 8 s + c has a pair in the j-cluster.
+ * Super-cluster s = particles [64 s, 64 s + 64) = the S = 64 / cs i-clusters
+ * S s .. S s + S - 1 (cs = cluster size). Its list holds every j-cluster (cs
+ * particles) containing a j paired with some i of s, in ascending order, each
+ * with an S-bit mask whose bit c is set iff some i of i-cluster S s + c has a
+ * pair in the j-cluster.
  *
  * Output layout (all little-endian 32-bit words):
  *   d_sc_info [n_sc][2] u32: {word offset into the pool, n_j}, n_sc = ceil(n / 64).
- *   pool at that offset: n_j mask bytes, padded to 4 bytes; then
+ *   pool at that offset: n_j masks of 1 byte (2 bytes, little-endian, for
+ *     cs = 4), padded to 4 bytes; then
  *     compress == 0: n_j u32 j-cluster indices;
  *     compress == 1: per block of 64 index differences (the first from -1):
  *       u64 bitmask (bit k set iff difference k is not 1), then one info
@@ -114,7 +118,7 @@ int build_clusters(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y,
  *
  * Inputs: SFC-ordered d_keys (from sfc_sort), positions, radii, and the
  * cluster boxes of build_clusters. opts:
- *   cluster_size  must be 8.
+ *   cluster_size  4, 8 or 16 (the size given to build_clusters).
  *   compress      0 or 1.
  *   leaf_bucket   octree leaves hold at most this many particles (8..256).
  *   max_j_per_sc  capacity of the per-super-cluster staging list.
@@ -239,9 +243,11 @@ int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const floa
  * inputs and hidden activations to bfloat16 (nearest even) and use the bf16
  * matrix cores with FP32 accumulation; the back-propagated errors are rounded
  * to bf16 before entering matrix products (bias gradients are not).
- *   sfcnl_hseed_features: d_feat [n][8] bf16 for SFC-ordered d_keys, d_h,
- *     d_nnb and cluster boxes d_bbox; box_edge as above; d_nnb NULL means no
- *     count yet (feature 0 = 0).
+ *   sfcnl_hseed_features: d_feat [n][8] bf16 for SFC-ordered d_keys,
+ *     positions, d_h and d_nnb; the boxes are those of 8 consecutive
+ *     particles and of the 64-particle super-cluster whatever the list's
+ *     cluster size; box_edge as above; d_nnb NULL means no count yet
+ *     (feature 0 = 0).
  *   sfcnl_mlp_init: deterministic He-uniform initialisation from `seed`
  *     (splitmix64 counter stream), zero biases.
  *   sfcnl_mlp_infer: d_out[i] = MLP(d_feat[i]) - feature0 / 3.
@@ -253,8 +259,9 @@ int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const floa
  *     step t >= 1) on params with moments d_m, d_v. */
 #define SFCNL_MLP_NPARAM 4801
 #define SFCNL_HSEED_NFEAT 8
-int sfcnl_hseed_features(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_h, const int32_t *d_nnb,
-                         const float *d_bbox, float box_edge, int target, uint16_t *d_feat);
+int sfcnl_hseed_features(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_x, const float *d_y,
+                         const float *d_z, const float *d_h, const int32_t *d_nnb, float box_edge, int target,
+                         uint16_t *d_feat);
 int sfcnl_mlp_init(sfcnl_ctx ctx, uint64_t seed, float *d_params);
 int sfcnl_mlp_infer(sfcnl_ctx ctx, const float *d_params, int64_t n, const uint16_t *d_feat, float *d_out);
 int sfcnl_mlp_grad_workspace(int64_t batch, size_t *ws_bytes);
@@ -276,7 +283,7 @@ int sfcnl_mlp_adam(sfcnl_ctx ctx, float *d_params, const float *d_grad, float *d
  * system s at pbase[s] (a multiple of 64) and fills up to pbase[s+1] with
  * padding: key all ones, permutation entry 0xFFFFFFFF, fields NaN. Outputs for
  * padding slots are unspecified. Every array below named "padded" has n_padded
- * entries (d_bbox: 8 floats per 8 padded particles).
+ * entries (d_bbox: 8 floats per cluster of padded particles).
  *
  *   sfcnl_batch_create: nsys in [1, SFCNL_BATCH_MAX_SYSTEMS]; h_counts[s] >= 0
  *     particles of system s; h_boxes 6 floats per system (xlo, xhi, ylo, yhi,
@@ -319,14 +326,14 @@ int sfcnl_batch_gather(sfcnl_ctx ctx, sfcnl_batch b, const uint32_t *d_perm, int
                        float *const *h_out);
 int sfcnl_batch_nlist_workspace(sfcnl_batch b, const sfcnl_nlist_opts *opts, size_t *ws_bytes);
 int sfcnl_batch_build_clusters(sfcnl_ctx ctx, sfcnl_batch b, const float *d_x, const float *d_y, const float *d_z,
-                               const float *d_h, float *d_bbox_out);
+                               const float *d_h, int cluster_size, float *d_bbox_out);
 int sfcnl_batch_build_nlist(sfcnl_ctx ctx, sfcnl_batch b, const uint64_t *d_keys, const float *d_x,
                             const float *d_y, const float *d_z, const float *d_h, const float *d_bbox,
                             const sfcnl_nlist_opts *opts, void *d_ws, size_t ws_bytes, uint32_t *d_sc_info,
                             uint32_t *d_pool, size_t pool_bytes, size_t *h_used_bytes, int64_t *h_max_nj);
-int sfcnl_batch_pass(sfcnl_ctx ctx, sfcnl_batch b, int compress, const uint32_t *d_sc_info, const uint32_t *d_pool,
-                     const float *d_x, const float *d_y, const float *d_z, const float *d_h, const float *d_m,
-                     float *d_rho, int32_t *d_nnb);
+int sfcnl_batch_pass(sfcnl_ctx ctx, sfcnl_batch b, int cluster_size, int compress, const uint32_t *d_sc_info,
+                     const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z, const float *d_h,
+                     const float *d_m, float *d_rho, int32_t *d_nnb);
 int sfcnl_batch_h_iterate(sfcnl_ctx ctx, sfcnl_batch b, const uint64_t *d_keys, const float *d_x, const float *d_y,
                           const float *d_z, float *d_h, float *d_bracket, const float *d_m,
                           const sfcnl_nlist_opts *nl_opts, const sfcnl_hiter_opts *it_opts, float *d_bbox,

@@ -131,6 +131,8 @@ def build_clusters(ctx: Context, x, y, z, h, cluster_size: int = CLUSTER_SIZE, b
     n = x.numel()
     nc = (n + cluster_size - 1) // cluster_size
     bbox = ctx.empty((max(nc, 1), 8), torch.float32) if bbox is None else bbox
+    if bbox.numel() < 8 * nc:
+        raise ValueError("bbox holds %d boxes, %d clusters need them" % (bbox.numel() // 8, nc))
     ctx.check(ctx.lib.build_clusters(ctx.handle, n, _ptr(x), _ptr(y), _ptr(z), _ptr(h), cluster_size, _ptr(bbox)))
     return bbox
 
@@ -246,17 +248,19 @@ def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, m
               compress: bool = True, leaf_bucket: int = 128, max_j_per_sc: int = 512, bracket=None, bbox=None,
               ws=None, pool=None, sc_info=None, rho=None, nnb=None, raise_noconv: bool = False,
               resume: bool = False, mlp_params=None, box_edge: float = 0.0, seed_scratch=None,
-              seed_mode: int = _lib.SEED_AFTER_FIRST):
+              seed_mode: int = _lib.SEED_AFTER_FIRST, cluster_size: int = CLUSTER_SIZE):
     """Iterates the SFC-ordered radii h (updated in place) to target +- tol
     own-radius neighbours (sfcnl_h_iterate). With mlp_params the first round's
     update comes from the learned seed. Grows list buffers and resumes when
     the library reports them too small."""
     n = x.numel()
     nsc = (n + SC_SIZE - 1) // SC_SIZE
-    nc = (n + CLUSTER_SIZE - 1) // CLUSTER_SIZE
+    nc = (n + cluster_size - 1) // cluster_size
     e = ctx.empty
     bracket = e(max(2 * n, 2), torch.float32) if bracket is None else bracket
     bbox = e((max(nc, 1), 8), torch.float32) if bbox is None else bbox
+    if bbox.numel() < 8 * nc:
+        raise ValueError("bbox holds %d boxes, %d clusters need them" % (bbox.numel() // 8, nc))
     sc_info = e((max(nsc, 1), 2), torch.int32) if sc_info is None else sc_info
     pool = e(max(1024, 6 * n), torch.int32) if pool is None else pool
     rho = e(max(n, 1), torch.float32) if rho is None else rho
@@ -272,12 +276,12 @@ def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, m
     total, moved, resume = 0, 0, int(bool(resume))
     while True:
         if total >= max_iters:
-            nl = NeighbourList(n, CLUSTER_SIZE, bool(compress), sc_info[:nsc], pool, 0, 0)
+            nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, 0, 0)
             return HIterResult(total, n, False, nl, rho, nnb, moved)
-        need = build_nlist_workspace(n, CLUSTER_SIZE, compress, leaf_bucket, max_j_per_sc)
+        need = build_nlist_workspace(n, cluster_size, compress, leaf_bucket, max_j_per_sc)
         if ws is None or ws.numel() < need:
             ws = e(max(need, 1), torch.uint8)
-        no = _opts(CLUSTER_SIZE, compress, leaf_bucket, max_j_per_sc)
+        no = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc)
         io = _lib.HiterOpts(target, tol, max_iters - total, resume)
         st = _lib.HiterStats()
         seed_arg = C.byref(hs) if (hs is not None and total == 0) else None
@@ -296,7 +300,7 @@ def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, m
                 pool = e(st.used_bytes // 4 + 1024, torch.int32)
             resume = 1
             continue
-        nl = NeighbourList(n, CLUSTER_SIZE, bool(compress), sc_info[:nsc], pool, st.used_bytes, st.max_nj)
+        nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, st.used_bytes, st.max_nj)
         nl.ws, nl.max_j_per_sc = ws, max_j_per_sc
         if rc == _lib.E_NOCONV and not raise_noconv:
             return HIterResult(total, st.unconverged, False, nl, rho, nnb, moved)
@@ -311,11 +315,12 @@ def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, m
 MLP_NPARAM = _lib.MLP_NPARAM
 
 
-def hseed_features(ctx: Context, keys, h, nnb, bbox, box_edge: float, target: int, feat=None):
+def hseed_features(ctx: Context, keys, x, y, z, h, nnb, box_edge: float, target: int, feat=None):
+    """Seed features (bf16 bits, [n, 8]); nnb None: no count yet."""
     n = h.numel()
     feat = ctx.empty((max(n, 1), _lib.HSEED_NFEAT), torch.int16) if feat is None else feat
-    ctx.check(ctx.lib.sfcnl_hseed_features(ctx.handle, n, _ptr(keys), _ptr(h), _ptr(nnb), _ptr(bbox), box_edge,
-                                           target, _ptr(feat)))
+    ctx.check(ctx.lib.sfcnl_hseed_features(ctx.handle, n, _ptr(keys), _ptr(x), _ptr(y), _ptr(z), _ptr(h), _ptr(nnb),
+                                           box_edge, target, _ptr(feat)))
     return feat
 
 
@@ -393,11 +398,12 @@ class Pipeline:
     sfc_sort -> sfc_gather -> build_clusters -> build_nlist -> nlist_pass."""
 
     def __init__(self, ctx: Context, n: int, box, compress: bool = True, leaf_bucket: int = 128,
-                 max_j_per_sc: int = 512, with_mass: bool = False):
+                 max_j_per_sc: int = 512, with_mass: bool = False, cluster_size: int = CLUSTER_SIZE):
         self.ctx, self.n, self.box = ctx, n, tuple(float(v) for v in box)
         self.compress, self.leaf_bucket, self.max_j_per_sc = compress, leaf_bucket, max_j_per_sc
+        self.cluster_size = cluster_size
         nsc = (n + SC_SIZE - 1) // SC_SIZE
-        nc = (n + CLUSTER_SIZE - 1) // CLUSTER_SIZE
+        nc = (n + cluster_size - 1) // cluster_size
         e = ctx.empty
         self.keys, self.perm = e(max(n, 1), torch.int64), e(max(n, 1), torch.int32)
         self.sort_ws = e(max(sfc_sort_workspace(n), 1), torch.uint8)
@@ -406,7 +412,7 @@ class Pipeline:
         self.bbox = e((max(nc, 1), 8), torch.float32)
         self.sc_info = e((max(nsc, 1), 2), torch.int32)
         self.pool = e(max(1024, 6 * n), torch.int32)
-        self.ws = e(max(build_nlist_workspace(n, CLUSTER_SIZE, compress, leaf_bucket, max_j_per_sc), 1), torch.uint8)
+        self.ws = e(max(build_nlist_workspace(n, cluster_size, compress, leaf_bucket, max_j_per_sc), 1), torch.uint8)
         self.rho, self.nnb = e(max(n, 1), torch.float32), e(max(n, 1), torch.int32)
         self.nl = None
 
@@ -418,9 +424,9 @@ class Pipeline:
         sfc_gather(ctx, self.perm, fields, outs)
         xs, ys, zs, hs = outs[:4]
         ms = outs[4] if m is not None else None
-        build_clusters(ctx, xs, ys, zs, hs, CLUSTER_SIZE, self.bbox)
+        build_clusters(ctx, xs, ys, zs, hs, self.cluster_size, self.bbox)
         nl = build_nlist(ctx, self.keys, xs, ys, zs, hs, self.bbox, self.compress, self.leaf_bucket,
-                         self.max_j_per_sc, pool=self.pool, ws=self.ws, sc_info=self.sc_info)
+                         self.max_j_per_sc, self.cluster_size, pool=self.pool, ws=self.ws, sc_info=self.sc_info)
         if nl.pool is not self.pool or nl.ws is not self.ws:  # grown on a retry: keep the larger buffers
             self.pool, self.ws, self.max_j_per_sc = nl.pool, nl.ws, nl.max_j_per_sc
         self.nl = nl
@@ -501,32 +507,36 @@ def batch_gather(ctx: Context, b: Batch, perm, fields, outs=None):
     return outs
 
 
-def batch_build_clusters(ctx: Context, b: Batch, x, y, z, h, bbox=None):
-    nc = (b.n_pad + CLUSTER_SIZE - 1) // CLUSTER_SIZE
+def batch_build_clusters(ctx: Context, b: Batch, x, y, z, h, bbox=None, cluster_size: int = CLUSTER_SIZE):
+    nc = (b.n_pad + cluster_size - 1) // cluster_size
     bbox = ctx.empty((max(nc, 1), 8), torch.float32) if bbox is None else bbox
+    if bbox.numel() < 8 * nc:
+        raise ValueError("bbox holds %d boxes, %d clusters need them" % (bbox.numel() // 8, nc))
     ctx.check(ctx.lib.sfcnl_batch_build_clusters(ctx.handle, b.handle, _ptr(x), _ptr(y), _ptr(z), _ptr(h),
-                                                 _ptr(bbox)))
+                                                 cluster_size, _ptr(bbox)))
     return bbox
 
 
-def batch_nlist_workspace(b: Batch, compress=True, leaf_bucket=128, max_j_per_sc=512) -> int:
+def batch_nlist_workspace(b: Batch, compress=True, leaf_bucket=128, max_j_per_sc=512,
+                          cluster_size: int = CLUSTER_SIZE) -> int:
     out = C.c_size_t()
-    o = _opts(CLUSTER_SIZE, compress, leaf_bucket, max_j_per_sc)
+    o = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc)
     if _lib.load().sfcnl_batch_nlist_workspace(b.handle, C.byref(o), C.byref(out)) != 0:
         raise SfcnlError(_lib.E_ARG, "sfcnl_batch_nlist_workspace")
     return out.value
 
 
 def batch_build_nlist(ctx: Context, b: Batch, keys, x, y, z, h, bbox, compress: bool = True, leaf_bucket: int = 128,
-                      max_j_per_sc: int = 512, pool=None, ws=None, sc_info=None, grow: bool = True):
+                      max_j_per_sc: int = 512, pool=None, ws=None, sc_info=None, grow: bool = True,
+                      cluster_size: int = CLUSTER_SIZE):
     """The padded batch's list (one pool, sc_info per padded super-cluster)."""
     n = b.n_pad
     nsc = n // SC_SIZE
     sc_info = ctx.empty((max(nsc, 1), 2), torch.int32) if sc_info is None else sc_info
     pool = ctx.empty(max(1024, 5 * n), torch.int32) if pool is None else pool
     while True:
-        o = _opts(CLUSTER_SIZE, compress, leaf_bucket, max_j_per_sc)
-        need = batch_nlist_workspace(b, compress, leaf_bucket, max_j_per_sc)
+        o = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc)
+        need = batch_nlist_workspace(b, compress, leaf_bucket, max_j_per_sc, cluster_size)
         if ws is None or ws.numel() < need:
             ws = ctx.empty(max(need, 1), torch.uint8)
         used, maxnj = C.c_size_t(), C.c_int64()
@@ -540,7 +550,7 @@ def batch_build_nlist(ctx: Context, b: Batch, keys, x, y, z, h, bbox, compress: 
                 pool = ctx.empty(used.value // 4 + 1024, torch.int32)
             continue
         ctx.check(rc)
-        nl = NeighbourList(n, CLUSTER_SIZE, bool(compress), sc_info[:nsc], pool, used.value, maxnj.value)
+        nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, used.value, maxnj.value)
         nl.ws, nl.max_j_per_sc = ws, max_j_per_sc
         return nl
 
@@ -549,8 +559,9 @@ def batch_pass(ctx: Context, b: Batch, nl: NeighbourList, x, y, z, h, m=None, rh
     n = b.n_pad
     rho = ctx.empty(max(n, 1), torch.float32) if rho is None else rho
     nnb = ctx.empty(max(n, 1), torch.int32) if nnb is None else nnb
-    ctx.check(ctx.lib.sfcnl_batch_pass(ctx.handle, b.handle, int(nl.compress), _ptr(nl.sc_info), _ptr(nl.pool),
-                                       _ptr(x), _ptr(y), _ptr(z), _ptr(h), _ptr(m), _ptr(rho), _ptr(nnb)))
+    ctx.check(ctx.lib.sfcnl_batch_pass(ctx.handle, b.handle, nl.cluster_size, int(nl.compress), _ptr(nl.sc_info),
+                                       _ptr(nl.pool), _ptr(x), _ptr(y), _ptr(z), _ptr(h), _ptr(m), _ptr(rho),
+                                       _ptr(nnb)))
     return rho, nnb
 
 
@@ -572,14 +583,14 @@ class BatchIterResult:
 def batch_h_iterate(ctx: Context, b: Batch, keys, x, y, z, h, target: int = 100, tol: int = 1, max_iters: int = 64,
                     m=None, compress: bool = True, leaf_bucket: int = 128, max_j_per_sc: int = 512,
                     use_graph: bool = True, mlp_params=None, seed_mode: int = _lib.SEED_AFTER_FIRST,
-                    bufs: dict | None = None):
+                    bufs: dict | None = None, cluster_size: int = CLUSTER_SIZE):
     """sfcnl_batch_h_iterate on padded SFC-ordered arrays (h updated in
     place). `bufs` (a dict, filled on first use) keeps every buffer for reuse
     across calls; buffers grow and the run resumes on SFCNL_E_CAPACITY."""
     import numpy as np
     n = b.n_pad
     nsc = n // SC_SIZE
-    nc = n // CLUSTER_SIZE
+    nc = n // cluster_size
     e = ctx.empty
     B = {} if bufs is None else bufs
     if "bracket" not in B:
@@ -590,6 +601,8 @@ def batch_h_iterate(ctx: Context, b: Batch, keys, x, y, z, h, target: int = 100,
         B["rho"] = e(max(n, 1), torch.float32)
         B["nnb"] = e(max(n, 1), torch.int32)
     B.setdefault("max_j", max_j_per_sc)
+    if B["bbox"].numel() < 8 * nc:  # a smaller cluster size needs more boxes
+        B["bbox"] = e((max(nc, 1), 8), torch.float32)
     hs = None
     if mlp_params is not None:
         if "feat" not in B:
@@ -600,10 +613,10 @@ def batch_h_iterate(ctx: Context, b: Batch, keys, x, y, z, h, target: int = 100,
     total, moved, resume = 0, 0, 0
     while True:
         mj = B["max_j"]
-        need = batch_nlist_workspace(b, compress, leaf_bucket, mj)
+        need = batch_nlist_workspace(b, compress, leaf_bucket, mj, cluster_size)
         if "ws" not in B or B["ws"].numel() < need:
             B["ws"] = e(max(need, 1), torch.uint8)
-        no = _opts(CLUSTER_SIZE, compress, leaf_bucket, mj)
+        no = _opts(cluster_size, compress, leaf_bucket, mj)
         io = _lib.HiterOpts(target, tol, max(max_iters - total, 1), resume)
         st = _lib.HiterStats()
         r = np.zeros(b.nsys, dtype=np.int32)

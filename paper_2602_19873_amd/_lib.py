@@ -103,7 +103,7 @@ def load():
     lib.sfcnl_h_iterate.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, C.POINTER(NlistOpts), C.POINTER(HiterOpts),
                                     vp, vp, sz, vp, vp, sz, vp, vp, C.POINTER(HSeed), C.POINTER(HiterStats)]
     lib.sfcnl_h_iterate.restype = i32
-    lib.sfcnl_hseed_features.argtypes = [vp, i64, vp, vp, vp, vp, C.c_float, i32, vp]
+    lib.sfcnl_hseed_features.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, C.c_float, i32, vp]
     lib.sfcnl_hseed_features.restype = i32
     lib.sfcnl_mlp_init.argtypes = [vp, C.c_uint64, vp]
     lib.sfcnl_mlp_init.restype = i32
@@ -134,12 +134,12 @@ def load():
     lib.sfcnl_batch_gather.restype = i32
     lib.sfcnl_batch_nlist_workspace.argtypes = [vp, C.POINTER(NlistOpts), C.POINTER(sz)]
     lib.sfcnl_batch_nlist_workspace.restype = i32
-    lib.sfcnl_batch_build_clusters.argtypes = [vp, vp, vp, vp, vp, vp, vp]
+    lib.sfcnl_batch_build_clusters.argtypes = [vp, vp, vp, vp, vp, vp, i32, vp]
     lib.sfcnl_batch_build_clusters.restype = i32
     lib.sfcnl_batch_build_nlist.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(NlistOpts), vp, sz, vp, vp,
                                             sz, C.POINTER(sz), P64]
     lib.sfcnl_batch_build_nlist.restype = i32
-    lib.sfcnl_batch_pass.argtypes = [vp, vp, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.sfcnl_batch_pass.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.sfcnl_batch_pass.restype = i32
     lib.sfcnl_batch_h_iterate.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(NlistOpts),
                                           C.POINTER(HiterOpts), vp, vp, sz, vp, vp, sz, vp, vp, C.POINTER(HSeed),

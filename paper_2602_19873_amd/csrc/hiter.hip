@@ -126,10 +126,8 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
         k_bracket_init<<<blocks_for(n, 256), 256, 0, strm>>>(n, br);
         SFCNL_LAUNCHED(ctx);
         if (seed && seed->mode == SFCNL_SEED_BEFORE_FIRST) {
-            int rc = build_clusters(ctx, n, d_x, d_y, d_z, d_h, nl_opts->cluster_size, d_bbox);
-            if (rc) return rc;
-            rc = features_impl(ctx, n, d_keys, d_h, nullptr, d_bbox, seed->box_edge, it_opts->target, seed->d_feat,
-                               SegTable{});
+            int rc = features_impl(ctx, n, d_keys, d_x, d_y, d_z, d_h, nullptr, seed->box_edge, it_opts->target,
+                                   seed->d_feat, SegTable{});
             if (rc) return rc;
             rc = sfcnl_mlp_infer(ctx, seed->d_params, n, seed->d_feat, seed->d_delta);
             if (rc) return rc;
@@ -148,7 +146,7 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
         if (rc) return rc;
         const float *proposal = nullptr;
         if (seed && seed->mode == SFCNL_SEED_AFTER_FIRST && it == 0) {  // learned step from the first counts
-            rc = sfcnl_hseed_features(ctx, n, d_keys, d_h, d_nnb, d_bbox, seed->box_edge, it_opts->target,
+            rc = sfcnl_hseed_features(ctx, n, d_keys, d_x, d_y, d_z, d_h, d_nnb, seed->box_edge, it_opts->target,
                                       seed->d_feat);
             if (rc) return rc;
             rc = sfcnl_mlp_infer(ctx, seed->d_params, n, seed->d_feat, seed->d_delta);
@@ -202,16 +200,17 @@ struct RoundArgs {
 int enqueue_round(sfcnl_ctx ctx, const RoundArgs &r, const sfcnl_hseed *seed) {
     const SegTable seg = seg_of(r.b);
     const int64_t n = r.b->n_pad;
-    int rc = clusters_impl(ctx, n, r.x, r.y, r.z, r.h, r.bbox, seg);
+    int rc = clusters_impl(ctx, n, r.x, r.y, r.z, r.h, r.nl->cluster_size, r.bbox, seg);
     if (rc) return rc;
     rc = nlist_build_impl(ctx, n, r.keys, r.x, r.y, r.z, r.h, r.bbox, *r.nl, r.ws, r.ws_bytes, r.sc_info, r.pool,
                           r.pool_bytes, seg, false, nullptr, nullptr);
     if (rc) return rc;
-    rc = pass_impl(ctx, n, r.nl->compress, r.sc_info, r.pool, r.x, r.y, r.z, r.h, r.m, r.rho, r.nnb, seg);
+    rc = pass_impl(ctx, n, r.nl->cluster_size, r.nl->compress, r.sc_info, r.pool, r.x, r.y, r.z, r.h, r.m, r.rho,
+                   r.nnb, seg);
     if (rc) return rc;
     const float *proposal = nullptr;
     if (seed) {
-        rc = features_impl(ctx, n, r.keys, r.h, r.nnb, r.bbox, 1.0f, r.it->target, seed->d_feat, seg);
+        rc = features_impl(ctx, n, r.keys, r.x, r.y, r.z, r.h, r.nnb, 1.0f, r.it->target, seed->d_feat, seg);
         if (rc) return rc;
         rc = sfcnl_mlp_infer(ctx, seed->d_params, n, seed->d_feat, seed->d_delta);
         if (rc) return rc;
@@ -307,9 +306,8 @@ extern "C" int sfcnl_batch_h_iterate(sfcnl_ctx ctx, sfcnl_batch b, const uint64_
         SFCNL_LAUNCHED(ctx);
         if (seed && seed->mode == SFCNL_SEED_BEFORE_FIRST) {
             const SegTable seg = seg_of(b);
-            int rc = clusters_impl(ctx, b->n_pad, d_x, d_y, d_z, d_h, d_bbox, seg);
-            if (rc) return rc;
-            rc = features_impl(ctx, b->n_pad, d_keys, d_h, nullptr, d_bbox, 1.0f, it_opts->target, seed->d_feat, seg);
+            int rc = features_impl(ctx, b->n_pad, d_keys, d_x, d_y, d_z, d_h, nullptr, 1.0f, it_opts->target,
+                                   seed->d_feat, seg);
             if (rc) return rc;
             rc = sfcnl_mlp_infer(ctx, seed->d_params, b->n_pad, seed->d_feat, seed->d_delta);
             if (rc) return rc;

@@ -13,8 +13,7 @@ namespace sfcnl {
 
 constexpr int kWave = 64;
 constexpr int kScSize = SFCNL_SC_SIZE;   // particles per super-cluster
-constexpr int kCs = 8;                   // particles per cluster
-constexpr int kSub = kScSize / kCs;      // i-clusters per super-cluster
+constexpr int kCs = 8;                   // default particles per cluster
 constexpr int kMaxBoxLevels = 12;        // 8^12 clusters > 2^31 particles
 
 // Status block words (device, mirrored into pinned host memory).
@@ -149,6 +148,7 @@ inline SegTable seg_of(const sfcnl_batch_s *b) {
 struct Octree {
     int64_t n;
     int bucket;
+    int cs;             // cluster size of the boxes the node boxes are built from
     uint32_t node_cap;  // capacity of the per-node and child-slot arrays
     // per particle
     int8_t *cdig;      // common 3-bit digits with the previous key (-1 for particle 0)
@@ -170,7 +170,7 @@ struct Octree {
     void *scan_tmp;
 };
 
-void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket, int nsys = 1);
+void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket, int nsys, int cs);
 int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x, const float *y,
                  const float *z, const float *h, const float4 *cluster_box, const SegTable &seg);
 
@@ -181,13 +181,14 @@ int nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *keys, const float
                      const float *h, const float *bbox, const sfcnl_nlist_opts &o, void *ws, size_t ws_bytes,
                      uint32_t *sc_info, uint32_t *pool, size_t pool_bytes, const SegTable &seg, bool readback,
                      size_t *used_bytes, int64_t *max_nj);
-int clusters_impl(sfcnl_ctx ctx, int64_t n, const float *x, const float *y, const float *z, const float *h,
+int clusters_impl(sfcnl_ctx ctx, int64_t n, const float *x, const float *y, const float *z, const float *h, int cs,
                   float *bbox, const SegTable &seg);
-int pass_impl(sfcnl_ctx ctx, int64_t n, int compress, const uint32_t *sc_info, const uint32_t *pool, const float *x,
-              const float *y, const float *z, const float *h, const float *m, float *rho, int32_t *nnb,
+int pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, const uint32_t *sc_info, const uint32_t *pool,
+              const float *x, const float *y, const float *z, const float *h, const float *m, float *rho, int32_t *nnb,
               const SegTable &seg);
-int features_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *keys, const float *h, const int32_t *nnb,
-                  const float *bbox, float box_edge, int target, uint16_t *feat, const SegTable &seg);
+int features_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *keys, const float *x, const float *y, const float *z,
+                  const float *h, const int32_t *nnb, float box_edge, int target, uint16_t *feat,
+                  const SegTable &seg);
 // reads the status block into pinned memory (kStWords words) and waits
 int read_status(sfcnl_ctx ctx);
 

@@ -344,12 +344,36 @@ __device__ __forceinline__ uint32_t lower_bound_key(const uint64_t *keys, uint32
     return lo;
 }
 
+__device__ __forceinline__ float wave_min(float v, int from, int to) {
+    for (int d = from; d < to; d <<= 1) v = fminf(v, __shfl_xor(v, d, 64));
+    return v;
+}
+__device__ __forceinline__ float wave_max(float v, int from, int to) {
+    for (int d = from; d < to; d <<= 1) v = fmaxf(v, __shfl_xor(v, d, 64));
+    return v;
+}
+
+__device__ __forceinline__ float diag(float lx, float ly, float lz, float hx, float hy, float hz) {
+    return sqrtf((hx - lx) * (hx - lx) + (hy - ly) * (hy - ly) + (hz - lz) * (hz - lz));
+}
+
+// One wavefront = one 64-particle super-cluster (blocks of 256 start at
+// multiples of 64): the 8-particle cluster box and the super-cluster box come
+// from min / max over lane groups; absent particles are NaN, which fminf and
+// fmaxf ignore.
 __global__ __launch_bounds__(256) void k_features(int64_t n, const uint64_t *__restrict__ keys,
-                                                  const float *__restrict__ h, const int32_t *__restrict__ nnb,
-                                                  const float4 *__restrict__ bbox, float edge0, int target,
+                                                  const float *__restrict__ x, const float *__restrict__ y,
+                                                  const float *__restrict__ z, const float *__restrict__ h,
+                                                  const int32_t *__restrict__ nnb, float edge0, int target,
                                                   uint16_t *__restrict__ feat, SegTable seg) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
+    const bool in = i < n;
+    const float px = in ? x[i] : NAN, py = in ? y[i] : NAN, pz = in ? z[i] : NAN;
+    float clx = wave_min(px, 1, 8), cly = wave_min(py, 1, 8), clz = wave_min(pz, 1, 8);
+    float chx = wave_max(px, 1, 8), chy = wave_max(py, 1, 8), chz = wave_max(pz, 1, 8);
+    const float slx = wave_min(clx, 8, 64), sly = wave_min(cly, 8, 64), slz = wave_min(clz, 8, 64);
+    const float shx = wave_max(chx, 8, 64), shy = wave_max(chy, 8, 64), shz = wave_max(chz, 8, 64);
+    if (!in) return;
     // key searches stay inside the particle's own system
     uint32_t klo = 0, khi = (uint32_t)n;
     if (seg.on()) {
@@ -366,25 +390,8 @@ __global__ __launch_bounds__(256) void k_features(int64_t n, const uint64_t *__r
     const float lt = logf((float)target);
     float f[kIn];
     f[0] = nnb ? logf((float)nnb[i] + 1.0f) - lt : 0.0f;  // no count yet: 0
-    const int64_t c = i / kCs;
-    const float4 lo1 = bbox[2 * c], hi1 = bbox[2 * c + 1];
-    const float d1 = sqrtf((hi1.x - lo1.x) * (hi1.x - lo1.x) + (hi1.y - lo1.y) * (hi1.y - lo1.y) +
-                           (hi1.z - lo1.z) * (hi1.z - lo1.z));
-    f[1] = logf(fmaxf(d1 / hi, 1e-3f));
-    const int64_t nclu = (n + kCs - 1) / kCs;
-    float4 slo = lo1, shi = hi1;
-    for (int64_t k = (c / kSub) * kSub; k < (c / kSub) * kSub + kSub && k < nclu; k++) {
-        const float4 a = bbox[2 * k], b = bbox[2 * k + 1];
-        slo.x = fminf(slo.x, a.x);
-        slo.y = fminf(slo.y, a.y);
-        slo.z = fminf(slo.z, a.z);
-        shi.x = fmaxf(shi.x, b.x);
-        shi.y = fmaxf(shi.y, b.y);
-        shi.z = fmaxf(shi.z, b.z);
-    }
-    const float d2 = sqrtf((shi.x - slo.x) * (shi.x - slo.x) + (shi.y - slo.y) * (shi.y - slo.y) +
-                           (shi.z - slo.z) * (shi.z - slo.z));
-    f[2] = logf(fmaxf(d2 / hi, 1e-3f));
+    f[1] = logf(fmaxf(diag(clx, cly, clz, chx, chy, chz) / hi, 1e-3f));
+    f[2] = logf(fmaxf(diag(slx, sly, slz, shx, shy, shz) / hi, 1e-3f));
     const float lev = log2f(edge0 / hi);
     int L0 = (int)rintf(lev);
     L0 = L0 < 2 ? 2 : (L0 > 20 ? 20 : L0);
@@ -476,22 +483,22 @@ extern "C" int sfcnl_mlp_adam(sfcnl_ctx ctx, float *d_params, const float *d_gra
     return SFCNL_OK;
 }
 
-int sfcnl::features_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_h, const int32_t *d_nnb,
-                         const float *d_bbox, float box_edge, int target, uint16_t *d_feat, const SegTable &seg) {
-    k_features<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, d_keys, d_h, d_nnb,
-                                                            reinterpret_cast<const float4 *>(d_bbox), box_edge,
-                                                            target, d_feat, seg);
+int sfcnl::features_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_x, const float *d_y,
+                         const float *d_z, const float *d_h, const int32_t *d_nnb, float box_edge, int target,
+                         uint16_t *d_feat, const SegTable &seg) {
+    k_features<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, d_keys, d_x, d_y, d_z, d_h, d_nnb, box_edge, target,
+                                                            d_feat, seg);
     SFCNL_LAUNCHED(ctx);
     return SFCNL_OK;
 }
 
-extern "C" int sfcnl_hseed_features(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_h,
-                                    const int32_t *d_nnb, const float *d_bbox, float box_edge, int target,
-                                    uint16_t *d_feat) {
+extern "C" int sfcnl_hseed_features(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_x,
+                                    const float *d_y, const float *d_z, const float *d_h, const int32_t *d_nnb,
+                                    float box_edge, int target, uint16_t *d_feat) {
     if (!ctx) return SFCNL_E_ARG;
     if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "sfcnl_hseed_features: n out of range");
     if (n == 0) return SFCNL_OK;
-    if (!d_keys || !d_h || !d_bbox || !d_feat || !(box_edge > 0.0f) || target < 1)
+    if (!d_keys || !d_x || !d_y || !d_z || !d_h || !d_feat || !(box_edge > 0.0f) || target < 1)
         return set_err(ctx, SFCNL_E_ARG, "sfcnl_hseed_features: bad argument");
-    return features_impl(ctx, n, d_keys, d_h, d_nnb, d_bbox, box_edge, target, d_feat, SegTable{});
+    return features_impl(ctx, n, d_keys, d_x, d_y, d_z, d_h, d_nnb, box_edge, target, d_feat, SegTable{});
 }

@@ -70,23 +70,23 @@ __device__ __forceinline__ uint32_t nibbles_of(uint32_t v) { return (32u - (uint
 __global__ __launch_bounds__(256) void k_cluster_bbox(int64_t n, const float *__restrict__ x,
                                                       const float *__restrict__ y, const float *__restrict__ z,
                                                       const float *__restrict__ h, float4 *__restrict__ bbox,
-                                                      uint32_t *status, SegTable seg) {
+                                                      uint32_t *status, SegTable seg, int cs) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= (n + kCs - 1) / kCs) return;
+    if (c >= (n + cs - 1) / cs) return;
     // batched systems: particles from pend on are padding (NaN, ignored by
     // fminf / fmaxf and never checked)
     int64_t pend = n;
     if (seg.on()) {
-        const int sy = seg.sc_sys[c / kSub];
+        const int sy = seg.sc_sys[c * cs / kScSize];
         pend = (int64_t)seg.pbase[sy] + seg.count[sy];
     }
     float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
     float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
     uint32_t bad = 0;
 #pragma unroll
-    for (int k = 0; k < kCs; k++) {
-        int64_t p = c * kCs + k;
-        if (p < n) {
+    for (int k = 0; k < 16; k++) {
+        int64_t p = c * cs + k;
+        if (k < cs && p < n) {
             float px = x[p], py = y[p], pz = z[p], ph = h[p];
             const bool pad = p >= pend;
             if (!pad && !(isfinite(px) && isfinite(py) && isfinite(pz))) bad |= 1u;
@@ -118,38 +118,112 @@ struct TravArgs {
     const uint4 *cs_rec;
     uint32_t nslots;       // capacity of the slot arrays
     SegTable seg;          // batched systems (empty for one system)
-    uint32_t *list_j;
-    uint8_t *list_m;
+    uint32_t *list_j;      // staging: cap entries per super-cluster
+    uint16_t *list_m;
     uint32_t *sc_nj, *sc_words;
     uint32_t *status;
 };
 
+// Lane roles of a super-cluster's wavefront for cluster size CS (64 / CS
+// i-clusters per super-cluster):
+//   CS = 8:  lane (il, jl) = (lane / 8, lane % 8); register k holds i-particle
+//            8k + il (i-cluster k); one step is one 8x8 cluster pair.
+//   CS = 4:  lane (q, il, jl) = (lane / 16, lane / 4 % 4, lane % 4); register
+//            k holds i-particle 16k + lane / 4 (i-cluster 4k + q); one step is
+//            four 4x4 pairs (i-clusters 4k .. 4k + 3 against one j-cluster).
+//   CS = 16: lane (il, jq) = (lane / 4, lane % 4); register k holds
+//            i-particle 16k + il (i-cluster k); a 16x16 pair takes four steps
+//            (j-particles 4t + jq).
+// Leaf box tests pair i-cluster boxes with the 64 / CS j-cluster boxes of a
+// 64-particle candidate run, lane l taking j-cluster l % (64 / CS).
+template <int CS>
+struct Shape {
+    static constexpr int kNsub = kScSize / CS;
+    static constexpr int kNreg = CS == 8 ? 8 : 4;
+    static constexpr int kMaskBytes = kNsub > 8 ? 2 : 1;
+    __device__ static int ipart(int k, int lane) { return CS == 8 ? 8 * k + (lane >> 3) : 16 * k + (lane >> 2); }
+};
+
+__device__ __forceinline__ void box_union(float4 &lo, float4 &hi, float4 blo, float4 bhi) {
+    lo.x = fminf(lo.x, blo.x);
+    lo.y = fminf(lo.y, blo.y);
+    lo.z = fminf(lo.z, blo.z);
+    lo.w = fmaxf(lo.w, blo.w);
+    hi.x = fmaxf(hi.x, bhi.x);
+    hi.y = fmaxf(hi.y, bhi.y);
+    hi.z = fmaxf(hi.z, bhi.z);
+}
+
+// Bits 0, 16, 32 and 48 of x gathered into bits 0..3 (the products of the
+// other bit pairs land on distinct positions below 48 or above 63).
+__device__ __forceinline__ uint32_t pack4_16(uint64_t x) {
+    return (uint32_t)(((x & 0x0001000100010001ull) * 0x0001000200040008ull) >> 48) & 0xFu;
+}
+// Bits 0, 4, 8 and 12 of x gathered into bits 0..3.
+__device__ __forceinline__ uint32_t pack4_4(uint32_t x) { return (((x & 0x1111u) * 0x1248u) >> 12) & 0xFu; }
+
+template <int CS>
 __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
+    using S = Shape<CS>;
+    constexpr int kNsub = S::kNsub, kNreg = S::kNreg;
     __shared__ uint4 s_stack[kWavesPerBlock][kStackCap];
     const int lane = sfc_lane();
     const int w = threadIdx.x / kWave;
     const uint32_t s = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
     if (s >= a.nsc) return;
-    const int il = lane >> 3, jl = lane & 7;
     const int64_t n = a.n;
-    // i particles: lane holds particle il of every i-cluster c; absent ones
-    // are put far away so that no test accepts them
-    float ix[kSub], iy[kSub], iz[kSub], ih2[kSub];
+    // i particles; absent ones are put far away so that no test accepts them
+    float ix[kNreg], iy[kNreg], iz[kNreg], ih2[kNreg];
 #pragma unroll
-    for (int c = 0; c < kSub; c++) {
-        int64_t i = (int64_t)s * kScSize + c * kCs + il;
-        bool v = i < n;
-        ix[c] = v ? a.x[i] : kFar;
-        iy[c] = v ? a.y[i] : kFar;
-        iz[c] = v ? a.z[i] : kFar;
-        float hh = v ? a.h[i] : 0.0f;
-        ih2[c] = hh * hh;
+    for (int k = 0; k < kNreg; k++) {
+        const int64_t i = (int64_t)s * kScSize + S::ipart(k, lane);
+        const bool v = i < n;
+        ix[k] = v ? a.x[i] : kFar;
+        iy[k] = v ? a.y[i] : kFar;
+        iz[k] = v ? a.z[i] : kFar;
+        const float hh = v ? a.h[i] : 0.0f;
+        ih2[k] = hh * hh;
     }
-    // i-cluster il's box (lanes with the same il hold the same box)
-    const uint32_t ic = s * kSub + il;
-    const bool icv = ic < a.nclu;
-    const float4 clo = icv ? a.bbox[2 * ic] : make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
-    const float4 chi = icv ? a.bbox[2 * ic + 1] : make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+    const uint32_t own_c0 = s * kNsub;  // first i-cluster of this super-cluster
+    const float4 empty_lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
+    const float4 empty_hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+    auto cbox = [&](uint32_t c, float4 &lo, float4 &hi) {
+        if (c < a.nclu) {
+            lo = a.bbox[2 * (size_t)c];
+            hi = a.bbox[2 * (size_t)c + 1];
+        } else {
+            lo = empty_lo;
+            hi = empty_hi;
+        }
+    };
+    // node tests: lane group g = lane / 8 tests the children against the box
+    // of super-cluster particles [8g, 8g + 8) (for CS = 16 of its i-cluster)
+    float4 glo, ghi;
+    {
+        const int g = lane >> 3;
+        if (CS == 8) {
+            cbox(own_c0 + g, glo, ghi);
+        } else if (CS == 4) {
+            float4 l2, h2;
+            cbox(own_c0 + 2 * g, glo, ghi);
+            cbox(own_c0 + 2 * g + 1, l2, h2);
+            box_union(glo, ghi, l2, h2);
+        } else {
+            cbox(own_c0 + (g >> 1), glo, ghi);
+        }
+    }
+    // leaf tests: the i-cluster boxes this lane pairs with its j-cluster
+    constexpr int kIbox = CS == 4 ? 4 : 1;
+    float4 ilo[kIbox], ihi[kIbox];
+#pragma unroll
+    for (int t = 0; t < kIbox; t++) {
+        const uint32_t ic = CS == 8 ? (lane >> 3) : (CS == 4 ? (lane >> 4) + 4 * t : ((lane >> 2) & 3));
+        cbox(own_c0 + ic, ilo[t], ihi[t]);
+        if (CS == 16 && lane >= 16) {
+            ilo[t] = empty_lo;
+            ihi[t] = empty_hi;
+        }
+    }
 
     // stack of node records {first, end, child count (0 = leaf), first child
     // slot}; a node is pushed only after its box passed the test
@@ -160,7 +234,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
     uint32_t jbase = 0;
     if (a.seg.on()) {
         const int sy = a.seg.sc_sys[s];
-        jbase = a.seg.pbase[sy] / kCs;
+        jbase = a.seg.pbase[sy] / CS;
         if (lane == 0) stack[0] = a.seg.roots[sy];
     } else {
         if (lane == 0) stack[0] = a.cs_rec[0];  // root
@@ -171,9 +245,8 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
     int64_t last = -1;  // highest j-cluster already tested
     uint32_t nj = 0, prevj = 0xFFFFFFFFu, blk_cnt = 0, blk_nib = 0, seg_words = 0;
     uint32_t *out_j = a.list_j + (size_t)s * a.cap;
-    uint8_t *out_m = a.list_m + (size_t)s * a.cap;
+    uint16_t *out_m = a.list_m + (size_t)s * a.cap;
 
-    const uint32_t own_c0 = s * kSub;  // first i-cluster of this super-cluster
     while (sp > 0) {
         sp--;
         const uint4 rv = stack[sp];
@@ -186,71 +259,146 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
             break;
         }
         if (nchild == 0) {
-            int64_t c0 = nfirst / kCs;
-            const int64_t c1 = (nend - 1) / kCs;
+            int64_t c0 = nfirst / CS;
+            const int64_t c1 = (nend - 1) / CS;
             if (c0 <= last) c0 = last + 1;
-            // j-particles of the (up to) 8 candidate clusters cb .. cb+7 are
-            // 64 consecutive particles: one coalesced load, lane l holding
-            // particle l of the run; absent ones are put far away. The next
-            // batch of the leaf is loaded while this one is tested.
+            // j-particles of the candidate clusters cb .. cb + 64/CS - 1 are 64
+            // consecutive particles: one coalesced load, lane l holding
+            // particle l of the run; absent ones are put far away. Lane l also
+            // loads the box of candidate cluster cb + l % (64/CS). The next
+            // run of the leaf is loaded while this one is tested.
             float px, py, pz, ph, nx, ny, nz, nh;
             float4 blo, bhi, nlo, nhi;
             auto load_batch = [&](int64_t cb, float &x_, float &y_, float &z_, float &h_, float4 &lo_, float4 &hi_) {
-                const int64_t pj = cb * kCs + lane;
-                const bool pv = pj < n && cb + il <= c1;
+                const int64_t pj = cb * CS + lane;
+                const bool pv = pj < n && cb + lane / CS <= c1;
                 x_ = pv ? a.x[pj] : kFar;
                 y_ = pv ? a.y[pj] : kFar;
                 z_ = pv ? a.z[pj] : kFar;
                 h_ = pv ? a.h[pj] : 0.0f;
-                const int64_t cj = cb + jl;
+                const int64_t cj = cb + (lane & (kNsub - 1));
                 if (cj <= c1) {
                     lo_ = a.bbox[2 * cj];
                     hi_ = a.bbox[2 * cj + 1];
                 } else {
-                    lo_ = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
-                    hi_ = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+                    lo_ = empty_lo;
+                    hi_ = empty_hi;
                 }
             };
             if (c0 <= c1) load_batch(c0, nx, ny, nz, nh, nlo, nhi);
-            for (int64_t cb = c0; cb <= c1; cb += 8) {
+            for (int64_t cb = c0; cb <= c1; cb += kNsub) {
                 px = nx; py = ny; pz = nz; ph = nh; blo = nlo; bhi = nhi;
-                if (cb + 8 <= c1) load_batch(cb + 8, nx, ny, nz, nh, nlo, nhi);
+                if (cb + kNsub <= c1) load_batch(cb + kNsub, nx, ny, nz, nh, nlo, nhi);
                 const float ph2 = ph * ph;
-                // i-cluster il box against candidate cluster cb + jl box
-                const bool hit = icv && boxes_near(clo, chi, blo, bhi);
-                const uint64_t bal = sfc_ballot(hit);
-                uint32_t anyj = byte_or(bal);
+                // box tests -> per candidate j-cluster jc its i-cluster mask
+                uint64_t bal[kIbox];
+                uint32_t anyj;
+#pragma unroll
+                for (int t = 0; t < kIbox; t++) bal[t] = sfc_ballot(boxes_near(ilo[t], ihi[t], blo, bhi));
+                if (CS == 8) {
+                    anyj = byte_or(bal[0]);
+                } else if (CS == 4) {
+                    const uint64_t o = bal[0] | bal[1] | bal[2] | bal[3];
+                    anyj = (uint32_t)((o | (o >> 16) | (o >> 32) | (o >> 48)) & 0xFFFFu);
+                } else {
+                    const uint32_t o = (uint32_t)bal[0];
+                    anyj = (o | (o >> 4) | (o >> 8) | (o >> 12)) & 0xFu;
+                }
                 while (anyj) {
                     const int jc = __ffs(anyj) - 1;
                     anyj &= anyj - 1u;
-                    // bit c of cmask = bit (8c + jc) of the ballot
-                    const uint32_t cmask =
-                        (uint32_t)((((bal >> jc) & 0x0101010101010101ull) * 0x0102040810204080ull) >> 56);
+                    uint32_t cmask;
+                    if (CS == 8) {
+                        // bit c of cmask = bit (8c + jc) of the ballot
+                        cmask = (uint32_t)((((bal[0] >> jc) & 0x0101010101010101ull) * 0x0102040810204080ull) >> 56);
+                    } else if (CS == 4) {
+                        // ballot t, lane 16g + jc: i-cluster g + 4t
+                        cmask = pack4_16(bal[0] >> jc) | (pack4_16(bal[1] >> jc) << 4) |
+                                (pack4_16(bal[2] >> jc) << 8) | (pack4_16(bal[3] >> jc) << 12);
+                    } else {
+                        // lane 4c + jc: i-cluster c
+                        cmask = pack4_4((uint32_t)bal[0] >> jc);
+                    }
                     const uint32_t cjv = (uint32_t)(cb + jc);
-                    const int src = jc * kCs + jl;
-                    const float xj = __shfl(px, src, 64), yj = __shfl(py, src, 64), zj = __shfl(pz, src, 64);
-                    const float hj2 = __shfl(ph2, src, 64);
                     // the j-cluster is one of our own i-clusters: exclude i == j
-                    const int self_c = (cjv >= own_c0 && cjv < own_c0 + kSub) ? (int)(cjv - own_c0) : -1;
+                    const int self_c = (cjv >= own_c0 && cjv < own_c0 + kNsub) ? (int)(cjv - own_c0) : -1;
                     uint32_t mask = 0;
+                    if (CS == 8) {
+                        const int jl = lane & 7, il = lane >> 3;
+                        const int src = jc * CS + jl;
+                        const float xj = __shfl(px, src, 64), yj = __shfl(py, src, 64), zj = __shfl(pz, src, 64);
+                        const float hj2 = __shfl(ph2, src, 64);
 #pragma unroll
-                    for (int c = 0; c < kSub; c++) {
-                        if ((cmask >> c) & 1u) {
-                            const float dx = xj - ix[c];
-                            const float dy = yj - iy[c];
-                            const float dz = zj - iz[c];
-                            const float dxx = dx * dx;
-                            const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                            bool pr = d2 < fmaxf(ih2[c], hj2);
-                            if (c == self_c) pr = pr && il != jl;
-                            if (sfc_ballot(pr)) mask |= 1u << c;
+                        for (int c = 0; c < kNreg; c++) {
+                            if ((cmask >> c) & 1u) {
+                                const float dx = xj - ix[c];
+                                const float dy = yj - iy[c];
+                                const float dz = zj - iz[c];
+                                const float dxx = dx * dx;
+                                const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
+                                bool pr = d2 < fmaxf(ih2[c], hj2);
+                                if (c == self_c) pr = pr && il != jl;
+                                if (sfc_ballot(pr)) mask |= 1u << c;
+                            }
+                        }
+                    } else if (CS == 4) {
+                        const int jl = lane & 3, il = (lane >> 2) & 3, q = lane >> 4;
+                        const int src = jc * CS + jl;
+                        const float xj = __shfl(px, src, 64), yj = __shfl(py, src, 64), zj = __shfl(pz, src, 64);
+                        const float hj2 = __shfl(ph2, src, 64);
+#pragma unroll
+                        for (int k = 0; k < kNreg; k++) {
+                            if ((cmask >> (4 * k)) & 0xFu) {
+                                const float dx = xj - ix[k];
+                                const float dy = yj - iy[k];
+                                const float dz = zj - iz[k];
+                                const float dxx = dx * dx;
+                                const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
+                                bool pr = d2 < fmaxf(ih2[k], hj2);
+                                if (4 * k + q == self_c) pr = pr && il != jl;
+                                const uint64_t b = sfc_ballot(pr);
+                                const uint32_t g = (uint32_t)((b & 0xFFFFull) != 0) |
+                                                   ((uint32_t)(((b >> 16) & 0xFFFFull) != 0) << 1) |
+                                                   ((uint32_t)(((b >> 32) & 0xFFFFull) != 0) << 2) |
+                                                   ((uint32_t)((b >> 48) != 0) << 3);
+                                mask |= g << (4 * k);
+                            }
+                        }
+                    } else {
+                        const int jq = lane & 3, il = lane >> 2;
+                        float xj[4], yj[4], zj[4], hj2[4];
+#pragma unroll
+                        for (int t = 0; t < 4; t++) {
+                            const int src = jc * CS + 4 * t + jq;
+                            xj[t] = __shfl(px, src, 64);
+                            yj[t] = __shfl(py, src, 64);
+                            zj[t] = __shfl(pz, src, 64);
+                            hj2[t] = __shfl(ph2, src, 64);
+                        }
+#pragma unroll
+                        for (int c = 0; c < kNreg; c++) {
+                            if ((cmask >> c) & 1u) {
+                                bool pr = false;
+#pragma unroll
+                                for (int t = 0; t < 4; t++) {
+                                    const float dx = xj[t] - ix[c];
+                                    const float dy = yj[t] - iy[c];
+                                    const float dz = zj[t] - iz[c];
+                                    const float dxx = dx * dx;
+                                    const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
+                                    bool p = d2 < fmaxf(ih2[c], hj2[t]);
+                                    if (c == self_c) p = p && il != 4 * t + jq;
+                                    pr = pr || p;
+                                }
+                                if (sfc_ballot(pr)) mask |= 1u << c;
+                            }
                         }
                     }
                     if (mask) {
                         const uint32_t jl_idx = cjv - jbase;
                         if (nj < a.cap && lane == 0) {
                             out_j[nj] = jl_idx;
-                            out_m[nj] = (uint8_t)mask;
+                            out_m[nj] = (uint16_t)mask;
                         }
                         const uint32_t v = jl_idx - prevj;
                         prevj = jl_idx;
@@ -266,7 +414,8 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
             }
             if (c1 > last) last = c1;
         } else {
-            // lane (il, jl): child jl of the node against i-cluster il's box
+            // lane (g, jl): child jl of the node against lane group g's box
+            const int jl = lane & 7;
             const bool act = jl < (int)nchild;
             const uint32_t slot = cslot + (uint32_t)jl;
             bool hit = false;
@@ -274,7 +423,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
             if (act) {
                 const float4 lo = a.cs_box[2 * (size_t)slot], hi = a.cs_box[2 * (size_t)slot + 1];
                 crec = a.cs_rec[slot];
-                hit = icv && boxes_near(clo, chi, lo, hi);
+                hit = boxes_near(glo, ghi, lo, hi);
             }
             const uint32_t keep = byte_or(sfc_ballot(hit));
             const int cnt = __popc(keep);
@@ -292,7 +441,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
     }
     if (blk_cnt) seg_words += 2u + (blk_nib + 7u) / 8u;
     if (lane == 0) {
-        const uint32_t mwords = (nj + 3u) / 4u;
+        const uint32_t mwords = (nj * S::kMaskBytes + 3u) / 4u;
         a.sc_nj[s] = nj;
         a.sc_words[s] = mwords + (a.compress ? seg_words : nj);
         atomicMax(&a.status[kStMaxNj], nj);
@@ -306,8 +455,9 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
 struct EncArgs {
     uint32_t nsc, cap;
     int compress;
+    int mask_bytes;  // 2 for 16 i-clusters per super-cluster, else 1
     const uint32_t *list_j;
-    const uint8_t *list_m;
+    const uint16_t *list_m;
     const uint32_t *sc_nj, *sc_off;  // sc_off has nsc + 1 entries
     uint32_t *sc_info;
     uint32_t *pool;
@@ -334,15 +484,23 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
     }
     if (!fits) return;
     const uint32_t *lj = a.list_j + (size_t)s * a.cap;
-    const uint8_t *lm = a.list_m + (size_t)s * a.cap;
+    const uint16_t *lm = a.list_m + (size_t)s * a.cap;
     uint32_t *out = a.pool + off;
-    const uint32_t mwords = (nj + 3u) / 4u;
+    const uint32_t mwords = (nj * (uint32_t)a.mask_bytes + 3u) / 4u;
     for (uint32_t q = lane; q < mwords; q += kWave) {
         uint32_t word = 0;
+        if (a.mask_bytes == 1) {
 #pragma unroll
-        for (int b = 0; b < 4; b++) {
-            uint32_t e = 4 * q + b;
-            if (e < nj) word |= (uint32_t)lm[e] << (8 * b);
+            for (int b = 0; b < 4; b++) {
+                uint32_t e = 4 * q + b;
+                if (e < nj) word |= (uint32_t)(lm[e] & 0xFFu) << (8 * b);
+            }
+        } else {
+#pragma unroll
+            for (int b = 0; b < 2; b++) {
+                uint32_t e = 2 * q + b;
+                if (e < nj) word |= (uint32_t)lm[e] << (16 * b);
+            }
         }
         out[q] = word;
     }
@@ -400,16 +558,16 @@ __global__ void k_finish(const uint32_t *total, uint32_t *status) { status[kStTo
 struct NlistWs {
     Octree tree;
     uint32_t *list_j;
-    uint8_t *list_m;
+    uint16_t *list_m;
     uint32_t *sc_nj, *sc_words, *sc_off;
     void *scan_tmp;
 };
 
 void carve_nlist(Carver &cv, NlistWs &ws, int64_t n, const sfcnl_nlist_opts &o, int nsys = 1) {
     const uint32_t nsc = (uint32_t)((n + kScSize - 1) / kScSize);
-    octree_carve(cv, ws.tree, n, o.leaf_bucket, nsys);
+    octree_carve(cv, ws.tree, n, o.leaf_bucket, nsys, o.cluster_size);
     ws.list_j = cv.take<uint32_t>((size_t)nsc * o.max_j_per_sc);
-    ws.list_m = cv.take<uint8_t>((size_t)nsc * o.max_j_per_sc);
+    ws.list_m = cv.take<uint16_t>((size_t)nsc * o.max_j_per_sc);
     ws.sc_nj = cv.take<uint32_t>(nsc);
     ws.sc_words = cv.take<uint32_t>(nsc);
     ws.sc_off = cv.take<uint32_t>((size_t)nsc + 1);
@@ -418,7 +576,8 @@ void carve_nlist(Carver &cv, NlistWs &ws, int64_t n, const sfcnl_nlist_opts &o, 
 
 int check_opts(sfcnl_ctx ctx, const sfcnl_nlist_opts *o) {
     if (!o) return set_err(ctx, SFCNL_E_ARG, "null options");
-    if (o->cluster_size != kCs) return set_err(ctx, SFCNL_E_ARG, "cluster_size %d not supported (8)", o->cluster_size);
+    if (o->cluster_size != 4 && o->cluster_size != 8 && o->cluster_size != 16)
+        return set_err(ctx, SFCNL_E_ARG, "cluster_size %d not supported (4, 8, 16)", o->cluster_size);
     if (o->compress != 0 && o->compress != 1) return set_err(ctx, SFCNL_E_ARG, "compress must be 0 or 1");
     if (o->leaf_bucket < 8 || o->leaf_bucket > 256)
         return set_err(ctx, SFCNL_E_ARG, "leaf_bucket %d outside [8, 256]", o->leaf_bucket);
@@ -432,12 +591,12 @@ int check_opts(sfcnl_ctx ctx, const sfcnl_nlist_opts *o) {
 using namespace sfcnl;
 
 int sfcnl::clusters_impl(sfcnl_ctx ctx, int64_t n, const float *x, const float *y, const float *z, const float *h,
-                         float *bbox, const SegTable &seg) {
+                         int cs, float *bbox, const SegTable &seg) {
     if (n == 0) return SFCNL_OK;
-    const int64_t nclu = (n + kCs - 1) / kCs;
+    const int64_t nclu = (n + cs - 1) / cs;
     prof_mark(ctx, kStageClusters, false);
     k_cluster_bbox<<<blocks_for(nclu, 256), 256, 0, ctx->stream>>>(n, x, y, z, h, reinterpret_cast<float4 *>(bbox),
-                                                                   ctx->d_status, seg);
+                                                                   ctx->d_status, seg, cs);
     SFCNL_LAUNCHED(ctx);
     prof_mark(ctx, kStageClusters, true);
     return SFCNL_OK;
@@ -447,10 +606,11 @@ extern "C" int build_clusters(sfcnl_ctx ctx, int64_t n, const float *d_x, const 
                               const float *d_h, int cluster_size, float *d_bbox_out) {
     if (!ctx) return SFCNL_E_ARG;
     if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "build_clusters: n out of range");
-    if (cluster_size != kCs) return set_err(ctx, SFCNL_E_ARG, "build_clusters: cluster_size %d not supported", cluster_size);
+    if (cluster_size != 4 && cluster_size != 8 && cluster_size != 16)
+        return set_err(ctx, SFCNL_E_ARG, "build_clusters: cluster_size %d not supported (4, 8, 16)", cluster_size);
     if (n == 0) return SFCNL_OK;
     if (!d_x || !d_y || !d_z || !d_h || !d_bbox_out) return set_err(ctx, SFCNL_E_ARG, "build_clusters: null pointer");
-    return clusters_impl(ctx, n, d_x, d_y, d_z, d_h, d_bbox_out, SegTable{});
+    return clusters_impl(ctx, n, d_x, d_y, d_z, d_h, cluster_size, d_bbox_out, SegTable{});
 }
 
 size_t sfcnl::nlist_ws_bytes(int64_t n, const sfcnl_nlist_opts &o, int nsys) {
@@ -483,7 +643,8 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     carve_nlist(cv, ws, n, o, nsys);
     if (cv.used > ws_bytes) return set_err(ctx, SFCNL_E_ARG, "build_nlist: workspace %zu < %zu bytes", ws_bytes, cv.used);
     const uint32_t nsc = (uint32_t)((n + kScSize - 1) / kScSize);
-    const uint32_t nclu = (uint32_t)((n + kCs - 1) / kCs);
+    const int cs = o.cluster_size;
+    const uint32_t nclu = (uint32_t)((n + cs - 1) / cs);
     hipStream_t st = ctx->stream;
 
     int rc = fill_u32(ctx, ctx->d_status + kStPoolOverflow, kStWords - kStPoolOverflow, 0);
@@ -515,7 +676,12 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     ta.status = ctx->d_status;
     const unsigned gb = blocks_for(nsc, kWavesPerBlock);
     prof_mark(ctx, kStageTraverse, false);
-    k_traverse<<<gb, 256, 0, st>>>(ta);
+    if (cs == 4)
+        k_traverse<4><<<gb, 256, 0, st>>>(ta);
+    else if (cs == 16)
+        k_traverse<16><<<gb, 256, 0, st>>>(ta);
+    else
+        k_traverse<8><<<gb, 256, 0, st>>>(ta);
     SFCNL_LAUNCHED(ctx);
     prof_mark(ctx, kStageTraverse, true);
     prof_mark(ctx, kStageEncode, false);
@@ -526,6 +692,7 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     ea.nsc = nsc;
     ea.cap = ta.cap;
     ea.compress = o.compress;
+    ea.mask_bytes = cs == 4 ? 2 : 1;
     ea.list_j = ws.list_j;
     ea.list_m = ws.list_m;
     ea.sc_nj = ws.sc_nj;

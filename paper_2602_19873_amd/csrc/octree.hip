@@ -183,8 +183,9 @@ __global__ __launch_bounds__(256) void k_box_level(const float4 *__restrict__ be
 }
 
 struct BoxLevels {
-    const float4 *lvl[kMaxBoxLevels + 1];  // lvl[0] = cluster boxes (8 particles each)
+    const float4 *lvl[kMaxBoxLevels + 1];  // lvl[0] = cluster boxes (cs particles each)
     int nlvl;
+    int cshift;  // log2 of the cluster size
 };
 
 __global__ __launch_bounds__(256) void k_node_box(const uint32_t *__restrict__ d_nnodes, uint32_t cap,
@@ -199,17 +200,18 @@ __global__ __launch_bounds__(256) void k_node_box(const uint32_t *__restrict__ d
     float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
     float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
     // ragged particles at both ends
-    while (a < b && (a & 7u)) {
+    const uint64_t cm = (1u << L.cshift) - 1u;
+    while (a < b && (a & cm)) {
         add_box(lo, hi, make_float4(x[a], y[a], z[a], h[a]), make_float4(x[a], y[a], z[a], 0.0f));
         a++;
     }
-    while (b > a && (b & 7u)) {
+    while (b > a && (b & cm)) {
         b--;
         add_box(lo, hi, make_float4(x[b], y[b], z[b], h[b]), make_float4(x[b], y[b], z[b], 0.0f));
     }
-    // [a, b) is now empty or whole clusters (both ends multiples of 8)
-    a >>= 3;
-    b >>= 3;
+    // [a, b) is now empty or whole clusters (both ends multiples of cs)
+    a >>= L.cshift;
+    b >>= L.cshift;
     // whole groups, coarsening one level at a time
     for (int l = 0; l < L.nlvl && a < b; l++) {
         const float4 *bx = L.lvl[l];
@@ -298,8 +300,8 @@ static size_t node_capacity(int64_t n, int bucket, int nsys) {
 
 // Sizes of the box hierarchy above the cluster boxes: level 1 groups 8
 // clusters, level 2 groups 8 of those, ... until one box remains.
-static int box_levels(int64_t n, int64_t *sizes) {
-    int64_t m = (n + kCs - 1) / kCs;
+static int box_levels(int64_t n, int cs, int64_t *sizes) {
+    int64_t m = (n + cs - 1) / cs;
     int nl = 0;
     while (m > 1 && nl < kMaxBoxLevels) {
         m = (m + 7) / 8;
@@ -308,9 +310,10 @@ static int box_levels(int64_t n, int64_t *sizes) {
     return nl;
 }
 
-void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket, int nsys) {
+void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket, int nsys, int cs) {
     t.n = n;
     t.bucket = bucket;
+    t.cs = cs;
     size_t nc = node_capacity(n, bucket, nsys);
     t.node_cap = (uint32_t)nc;
     t.cdig = cv.take<int8_t>((size_t)n);
@@ -329,7 +332,7 @@ void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket, int nsys) {
     t.cs_box = cv.take<float4>(2 * nc);
     t.cs_rec = cv.take<uint4>(nc);
     int64_t sizes[kMaxBoxLevels];
-    t.nboxlvl = box_levels(n, sizes);
+    t.nboxlvl = box_levels(n, cs, sizes);
     for (int l = 0; l < t.nboxlvl; l++) t.boxlvl[l] = cv.take<float4>(2 * (size_t)sizes[l]);
     t.d_nnodes = cv.take<uint32_t>(4);
     t.scan_tmp = cv.take<char>(scan_tmp_bytes((int64_t)nc > n + 1 ? (int64_t)nc : n + 1));
@@ -362,11 +365,12 @@ int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x,
     SFCNL_LAUNCHED(ctx);
     // box hierarchy over the cluster boxes, then exact node boxes
     int64_t sizes[kMaxBoxLevels];
-    const int nl = box_levels(n, sizes);
+    const int nl = box_levels(n, t.cs, sizes);
     BoxLevels L;
     L.lvl[0] = cluster_box;
     L.nlvl = nl + 1;
-    int64_t below = (n + kCs - 1) / kCs;
+    L.cshift = t.cs == 4 ? 2 : (t.cs == 16 ? 4 : 3);
+    int64_t below = (n + t.cs - 1) / t.cs;
     for (int l = 0; l < nl; l++) {
         k_box_level<<<blocks_for(sizes[l], 256), 256, 0, st>>>(L.lvl[l], below, t.boxlvl[l], sizes[l]);
         SFCNL_LAUNCHED(ctx);

@@ -67,44 +67,98 @@ struct PassArgs {
     SegTable seg;  // batched systems: list indices are relative to the system's first cluster
 };
 
-template <bool kCompress, bool kMass, bool kCount>
+// i-particle held in register k by a lane (the traversal's lane roles):
+// CS = 8: 8k + lane / 8; CS = 4 and 16: 16k + lane / 4.
+template <int CS>
+__device__ __forceinline__ int ipart(int k, int lane) {
+    return CS == 8 ? 8 * k + (lane >> 3) : 16 * k + (lane >> 2);
+}
+
+// One particle pair of a tile: the own-radius test, then m_j times the
+// halved M4 shape 1/2 - 3q^2 + 3q^3 (q < 1/2) or (1-q)^3, summed.
+template <bool kMass>
+__device__ __forceinline__ void tile_pair(float xj, float yj, float zj, float mj, float xi, float yi, float zi,
+                                          float h2, float hinv, bool self_pair, float &acc, int &cnt) {
+    const float dx = xj - xi;
+    const float dy = yj - yi;
+    const float dz = zj - zi;
+    const float dxx = dx * dx;
+    const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
+    const bool in = d2 < h2 && !self_pair;
+    if (sfc_ballot(in)) {
+        const float q = __builtin_amdgcn_sqrtf(d2) * hinv;
+        const float t1 = q - 1.0f;
+        const float q2 = q * q;
+        const float inner = __builtin_fmaf(3.0f * q2, t1, 0.5f);
+        const float outer = -(t1 * t1) * t1;
+        const float wq = q < 0.5f ? inner : outer;
+        const float nacc = __builtin_fmaf(kMass ? mj : 1.0f, wq, acc);
+        acc = in ? nacc : acc;
+        cnt += in ? 1 : 0;
+    }
+}
+
+// Lane roles for cluster size CS (64 / CS i-clusters per super-cluster):
+//   CS = 8:  lane (il, jl) = (lane / 8, lane % 8) takes j-particle jl of the
+//            listed j-cluster against i-particle il of every set i-cluster;
+//   CS = 4:  lane (q, il, jl) = (lane / 16, lane / 4 % 4, lane % 4) takes
+//            j-particle jl against i-particle il of i-clusters 4k + q;
+//   CS = 16: lane (il, jq) = (lane / 4, lane % 4) takes j-particles 4t + jq
+//            (t = 0..3) against i-particle il of every set i-cluster.
+template <int CS, bool kCompress, bool kMass, bool kCount>
 __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
+    constexpr int kNsub = kScSize / CS;
+    constexpr int kNreg = CS == 8 ? 8 : 4;
+    constexpr int kNj = CS == 16 ? 4 : 1;     // j-particles per lane and entry
+    constexpr int kGroup = CS == 8 ? 8 : 4;   // lanes sharing an i-particle
     const int lane = sfc_lane();
     const int w = threadIdx.x / kWave;
     const uint32_t s = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
     if (s >= a.nsc) return;
-    const int il = lane >> 3, jl = lane & 7;
     const int64_t n = a.n;
+    const int jl = lane & (kGroup - 1);
 
-    // i particles: lane holds particle il of every i-cluster c; absent ones
-    // get a negative squared radius so that no pair is accepted
-    float ix[kSub], iy[kSub], iz[kSub], ih2[kSub], ihinv[kSub];
+    // i particles; absent ones get a negative squared radius so that no pair
+    // is accepted
+    float ix[kNreg], iy[kNreg], iz[kNreg], ih2[kNreg], ihinv[kNreg];
 #pragma unroll
-    for (int c = 0; c < kSub; c++) {
-        const int64_t i = (int64_t)s * kScSize + c * kCs + il;
+    for (int k = 0; k < kNreg; k++) {
+        const int64_t i = (int64_t)s * kScSize + ipart<CS>(k, lane);
         const bool v = i < n;
-        ix[c] = v ? a.x[i] : 0.0f;
-        iy[c] = v ? a.y[i] : 0.0f;
-        iz[c] = v ? a.z[i] : 0.0f;
+        ix[k] = v ? a.x[i] : 0.0f;
+        iy[k] = v ? a.y[i] : 0.0f;
+        iz[k] = v ? a.z[i] : 0.0f;
         const float hh = v ? a.h[i] : 1.0f;
-        ih2[c] = v ? hh * hh : -1.0f;
-        ihinv[c] = 1.0f / hh;
+        ih2[k] = v ? hh * hh : -1.0f;
+        ihinv[k] = 1.0f / hh;
     }
-    // acc[c] sums m_j f(q)/2 with f the spline shape (f(0) = 1)
-    float acc[kSub];
-    int cnt_nb[kSub];
+    // acc[k] sums m_j f(q)/2 with f the spline shape (f(0) = 1)
+    float acc[kNreg];
+    int cnt_nb[kNreg];
 #pragma unroll
-    for (int c = 0; c < kSub; c++) {
-        acc[c] = 0.0f;
-        cnt_nb[c] = 0;
+    for (int k = 0; k < kNreg; k++) {
+        acc[k] = 0.0f;
+        cnt_nb[k] = 0;
     }
 
-    const uint32_t own_c0 = s * kSub;
+    const uint32_t own_c0 = s * kNsub;
     const uint32_t off = a.sc_info[2 * s], nj = a.sc_info[2 * s + 1];
     const uint8_t *mbytes = reinterpret_cast<const uint8_t *>(a.pool + off);
-    const uint32_t jbase = a.seg.on() ? a.seg.pbase[a.seg.sc_sys[s]] / kCs : 0u;
-    uint32_t p = off + (nj + 3u) / 4u;
+    const uint16_t *mshorts = reinterpret_cast<const uint16_t *>(a.pool + off);
+    const uint32_t jbase = a.seg.on() ? a.seg.pbase[a.seg.sc_sys[s]] / CS : 0u;
+    uint32_t p = off + (nj * (CS == 4 ? 2u : 1u) + 3u) / 4u;
     uint32_t prevj = 0xFFFFFFFFu;
+    auto load_j = [&](uint32_t cj, float (&xj)[kNj], float (&yj)[kNj], float (&zj)[kNj], float (&mj)[kNj]) {
+#pragma unroll
+        for (int t = 0; t < kNj; t++) {
+            const int64_t jp = (int64_t)cj * CS + (CS == 16 ? 4 * t + jl : jl);
+            const bool vj = jp < n;
+            xj[t] = vj ? a.x[jp] : kFar;
+            yj[t] = vj ? a.y[jp] : kFar;
+            zj[t] = vj ? a.z[jp] : kFar;
+            mj[t] = kMass ? (vj ? a.m[jp] : 0.0f) : 1.0f;
+        }
+    };
     for (uint32_t b0 = 0; b0 < nj; b0 += kWave) {
         const uint32_t cnt = nj - b0 < (uint32_t)kWave ? nj - b0 : (uint32_t)kWave;
         uint32_t jv;
@@ -113,81 +167,77 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
         } else {
             jv = (uint32_t)lane < cnt ? a.pool[p + b0 + lane] : 0u;
         }
-        const uint32_t mv = (uint32_t)lane < cnt ? mbytes[b0 + lane] : 0u;
+        uint32_t mv = 0u;
+        if ((uint32_t)lane < cnt) mv = CS == 4 ? (uint32_t)mshorts[b0 + lane] : (uint32_t)mbytes[b0 + lane];
         prevj = sfc_readlane(jv, (int)cnt - 1);
         jv += jbase;
         // software pipeline: the next entry's j-particles load while the
         // current entry's tiles run
         uint32_t cj = sfc_readlane(jv, 0);
-        int64_t jp = (int64_t)cj * kCs + jl;
-        float xj, yj, zj, mj;
-        {
-            const bool vj = jp < n;
-            xj = vj ? a.x[jp] : kFar;
-            yj = vj ? a.y[jp] : kFar;
-            zj = vj ? a.z[jp] : kFar;
-            mj = kMass ? (vj ? a.m[jp] : 0.0f) : 1.0f;
-        }
+        float xj[kNj], yj[kNj], zj[kNj], mj[kNj];
+        load_j(cj, xj, yj, zj, mj);
         for (uint32_t e = 0; e < cnt; e++) {
             const uint32_t mk = sfc_readlane(mv, (int)e);
             const uint32_t ccur = cj;
-            const float cx = xj, cy = yj, cz = zj, cm = mj;
+            float cx[kNj], cy[kNj], cz[kNj], cm[kNj];
+#pragma unroll
+            for (int t = 0; t < kNj; t++) {
+                cx[t] = xj[t];
+                cy[t] = yj[t];
+                cz[t] = zj[t];
+                cm[t] = mj[t];
+            }
             if (e + 1 < cnt) {
                 cj = sfc_readlane(jv, (int)e + 1);
-                jp = (int64_t)cj * kCs + jl;
-                const bool vj = jp < n;
-                xj = vj ? a.x[jp] : kFar;
-                yj = vj ? a.y[jp] : kFar;
-                zj = vj ? a.z[jp] : kFar;
-                mj = kMass ? (vj ? a.m[jp] : 0.0f) : 1.0f;
+                load_j(cj, xj, yj, zj, mj);
             }
             // the j-cluster is one of our own i-clusters: exclude i == j
-            const int self_c = (ccur >= own_c0 && ccur < own_c0 + kSub) ? (int)(ccur - own_c0) : -1;
+            const int self_c = (ccur >= own_c0 && ccur < own_c0 + kNsub) ? (int)(ccur - own_c0) : -1;
+            if (CS == 8) {
+                const int il = lane >> 3;
 #pragma unroll
-            for (int c = 0; c < kSub; c++) {
-                if ((mk >> c) & 1u) {
-                    const float dx = cx - ix[c];
-                    const float dy = cy - iy[c];
-                    const float dz = cz - iz[c];
-                    const float dxx = dx * dx;
-                    const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                    bool in = d2 < ih2[c];
-                    if (c == self_c) in = in && il != jl;
-                    if (sfc_ballot(in)) {
-                        // M4 spline with support h, halved: 1/2 - 3q^2 + 3q^3
-                        // below q = 1/2, (1-q)^3 above
-                        const float q = __builtin_amdgcn_sqrtf(d2) * ihinv[c];
-                        const float t1 = q - 1.0f;
-                        const float q2 = q * q;
-                        const float inner = __builtin_fmaf(3.0f * q2, t1, 0.5f);
-                        const float outer = -(t1 * t1) * t1;
-                        const float wq = q < 0.5f ? inner : outer;
-                        const float nacc = __builtin_fmaf(cm, wq, acc[c]);
-                        acc[c] = in ? nacc : acc[c];
-                        cnt_nb[c] += in ? 1 : 0;
+                for (int c = 0; c < kNreg; c++)
+                    if ((mk >> c) & 1u)
+                        tile_pair<kMass>(cx[0], cy[0], cz[0], cm[0], ix[c], iy[c], iz[c], ih2[c], ihinv[c],
+                                         c == self_c && il == jl, acc[c], cnt_nb[c]);
+            } else if (CS == 4) {
+                const int il = (lane >> 2) & 3, q = lane >> 4;
+#pragma unroll
+                for (int k = 0; k < kNreg; k++)
+                    if ((mk >> (4 * k)) & 0xFu)
+                        tile_pair<kMass>(cx[0], cy[0], cz[0], cm[0], ix[k], iy[k], iz[k], ih2[k], ihinv[k],
+                                         4 * k + q == self_c && il == jl, acc[k], cnt_nb[k]);
+            } else {
+                const int il = lane >> 2;
+#pragma unroll
+                for (int c = 0; c < kNreg; c++)
+                    if ((mk >> c) & 1u) {
+#pragma unroll
+                        for (int t = 0; t < 4; t++)
+                            tile_pair<kMass>(cx[t], cy[t], cz[t], cm[t], ix[c], iy[c], iz[c], ih2[c], ihinv[c],
+                                             c == self_c && il == 4 * t + jl, acc[c], cnt_nb[c]);
                     }
-                }
             }
         }
     }
-    // sum the 8 partials of each i-particle (lanes differing in jl)
+    // sum the partials of each i-particle (the kGroup lanes sharing it)
 #pragma unroll
-    for (int c = 0; c < kSub; c++) {
+    for (int k = 0; k < kNreg; k++) {
 #pragma unroll
-        for (int d = 1; d < 8; d <<= 1) {
-            acc[c] += __shfl_xor(acc[c], d, 64);
-            if (kCount) cnt_nb[c] += __shfl_xor(cnt_nb[c], d, 64);
+        for (int d = 1; d < kGroup; d <<= 1) {
+            acc[k] += __shfl_xor(acc[k], d, 64);
+            if (kCount) cnt_nb[k] += __shfl_xor(cnt_nb[k], d, 64);
         }
     }
-    // lane (il, jl) stores particle il of i-cluster jl
+    // lane stores register jl (its group has kGroup lanes, one per register)
     float r = acc[0];
     int nb = cnt_nb[0];
 #pragma unroll
-    for (int c = 1; c < kSub; c++) {
-        r = jl == c ? acc[c] : r;
-        nb = jl == c ? cnt_nb[c] : nb;
+    for (int k = 1; k < kNreg; k++) {
+        r = jl == k ? acc[k] : r;
+        nb = jl == k ? cnt_nb[k] : nb;
     }
-    const int64_t io = (int64_t)s * kScSize + jl * kCs + il;
+    const int64_t io = (int64_t)s * kScSize + ipart<CS>(jl, lane);
     if (io < n) {
         const float hh = a.h[io];
         const float hinv = 1.0f / hh;
@@ -200,6 +250,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
 
 struct DecodeArgs {
     uint32_t nsc;
+    int mask_bytes;
     const uint32_t *sc_info, *pool, *offsets;
     uint32_t *j;
     uint16_t *mask;
@@ -212,7 +263,8 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
     if (s >= a.nsc) return;
     const uint32_t off = a.sc_info[2 * s], nj = a.sc_info[2 * s + 1];
     const uint8_t *mbytes = reinterpret_cast<const uint8_t *>(a.pool + off);
-    uint32_t p = off + (nj + 3u) / 4u;
+    const uint16_t *mshorts = reinterpret_cast<const uint16_t *>(a.pool + off);
+    uint32_t p = off + (nj * (uint32_t)a.mask_bytes + 3u) / 4u;
     uint32_t prevj = 0xFFFFFFFFu;
     const uint32_t o = a.offsets[s];
     for (uint32_t b0 = 0; b0 < nj; b0 += kWave) {
@@ -225,8 +277,22 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
         prevj = sfc_readlane(jv, (int)cnt - 1);
         if ((uint32_t)lane < cnt) {
             a.j[o + b0 + lane] = jv;
-            a.mask[o + b0 + lane] = mbytes[b0 + lane];
+            a.mask[o + b0 + lane] = a.mask_bytes == 2 ? mshorts[b0 + lane] : (uint16_t)mbytes[b0 + lane];
         }
+    }
+}
+
+template <int CS>
+void launch_pass(int variant, unsigned g, hipStream_t st, const PassArgs &a) {
+    switch (variant) {
+        case 7: k_pass<CS, true, true, true><<<g, 256, 0, st>>>(a); break;
+        case 6: k_pass<CS, true, true, false><<<g, 256, 0, st>>>(a); break;
+        case 5: k_pass<CS, true, false, true><<<g, 256, 0, st>>>(a); break;
+        case 4: k_pass<CS, true, false, false><<<g, 256, 0, st>>>(a); break;
+        case 3: k_pass<CS, false, true, true><<<g, 256, 0, st>>>(a); break;
+        case 2: k_pass<CS, false, true, false><<<g, 256, 0, st>>>(a); break;
+        case 1: k_pass<CS, false, false, true><<<g, 256, 0, st>>>(a); break;
+        default: k_pass<CS, false, false, false><<<g, 256, 0, st>>>(a); break;
     }
 }
 
@@ -235,57 +301,53 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
 
 using namespace sfcnl;
 
-int sfcnl::pass_impl(sfcnl_ctx ctx, int64_t n, int compress, const uint32_t *d_sc_info, const uint32_t *d_pool,
-                     const float *d_x, const float *d_y, const float *d_z, const float *d_h, const float *d_m,
-                     float *d_rho, int32_t *d_nnb, const SegTable &seg) {
+int sfcnl::pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, const uint32_t *d_sc_info,
+                     const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z, const float *d_h,
+                     const float *d_m, float *d_rho, int32_t *d_nnb, const SegTable &seg) {
     PassArgs a{n, (uint32_t)((n + kScSize - 1) / kScSize), d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb,
                seg};
     const unsigned g = blocks_for(a.nsc, kWavesPerBlock);
     hipStream_t st = ctx->stream;
-    const bool hm = d_m != nullptr, hc = d_nnb != nullptr;
-#define SFCNL_PASS(C, M, K) k_pass<C, M, K><<<g, 256, 0, st>>>(a)
+    const int variant = (compress ? 4 : 0) | (d_m ? 2 : 0) | (d_nnb ? 1 : 0);
     prof_mark(ctx, kStagePass, false);
-    if (compress) {
-        if (hm) {
-            if (hc) SFCNL_PASS(true, true, true); else SFCNL_PASS(true, true, false);
-        } else {
-            if (hc) SFCNL_PASS(true, false, true); else SFCNL_PASS(true, false, false);
-        }
-    } else {
-        if (hm) {
-            if (hc) SFCNL_PASS(false, true, true); else SFCNL_PASS(false, true, false);
-        } else {
-            if (hc) SFCNL_PASS(false, false, true); else SFCNL_PASS(false, false, false);
-        }
-    }
-#undef SFCNL_PASS
+    if (cs == 4)
+        launch_pass<4>(variant, g, st, a);
+    else if (cs == 16)
+        launch_pass<16>(variant, g, st, a);
+    else
+        launch_pass<8>(variant, g, st, a);
     SFCNL_LAUNCHED(ctx);
     prof_mark(ctx, kStagePass, true);
     return SFCNL_OK;
 }
+
+static bool cs_ok(int cs) { return cs == 4 || cs == 8 || cs == 16; }
 
 extern "C" int nlist_pass(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, const uint32_t *d_sc_info,
                           const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z,
                           const float *d_h, const float *d_m, float *d_rho, int32_t *d_nnb) {
     if (!ctx) return SFCNL_E_ARG;
     if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: n out of range");
-    if (cluster_size != kCs) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: cluster_size %d not supported", cluster_size);
+    if (!cs_ok(cluster_size)) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: cluster_size %d not supported", cluster_size);
     if (compress != 0 && compress != 1) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: compress must be 0 or 1");
     if (n == 0) return SFCNL_OK;
     if (!d_sc_info || !d_pool || !d_x || !d_y || !d_z || !d_h || !d_rho)
         return set_err(ctx, SFCNL_E_ARG, "nlist_pass: null pointer");
-    return pass_impl(ctx, n, compress, d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb, SegTable{});
+    return pass_impl(ctx, n, cluster_size, compress, d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb,
+                     SegTable{});
 }
 
 extern "C" int nlist_decode(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, const uint32_t *d_sc_info,
                             const uint32_t *d_pool, const uint32_t *d_offsets, uint32_t *d_j, uint16_t *d_mask) {
     if (!ctx) return SFCNL_E_ARG;
     if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "nlist_decode: n out of range");
-    if (cluster_size != kCs) return set_err(ctx, SFCNL_E_ARG, "nlist_decode: cluster_size %d not supported", cluster_size);
+    if (!cs_ok(cluster_size))
+        return set_err(ctx, SFCNL_E_ARG, "nlist_decode: cluster_size %d not supported", cluster_size);
     if (n == 0) return SFCNL_OK;
     if (!d_sc_info || !d_pool || !d_offsets || !d_j || !d_mask)
         return set_err(ctx, SFCNL_E_ARG, "nlist_decode: null pointer");
-    DecodeArgs a{(uint32_t)((n + kScSize - 1) / kScSize), d_sc_info, d_pool, d_offsets, d_j, d_mask};
+    DecodeArgs a{(uint32_t)((n + kScSize - 1) / kScSize), cluster_size == 4 ? 2 : 1, d_sc_info, d_pool, d_offsets,
+                 d_j, d_mask};
     const unsigned g = blocks_for(a.nsc, kWavesPerBlock);
     if (compress)
         k_decode<true><<<g, 256, 0, ctx->stream>>>(a);

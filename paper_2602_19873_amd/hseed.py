@@ -38,13 +38,13 @@ def training_pairs(ctx, s, target: int, h_prev: np.ndarray, max_iters: int = 64,
     before_first: features without a count (the seed applied before the
     first round), so no list is built at h_prev."""
     keys, xs, ys, zs, hs = sorted_system(ctx, s, h_prev)
-    bbox = build_clusters(ctx, xs, ys, zs, hs)
     if before_first:
         nnb = None
     else:
+        bbox = build_clusters(ctx, xs, ys, zs, hs)
         nl = build_nlist(ctx, keys, xs, ys, zs, hs, bbox)
         _, nnb = nlist_pass(ctx, nl, xs, ys, zs, hs)
-    feat = hseed_features(ctx, keys, hs, nnb, bbox, box_edge(s.box), target)
+    feat = hseed_features(ctx, keys, xs, ys, zs, hs, nnb, box_edge(s.box), target)
     hc = hs.clone()
     res = h_iterate(ctx, keys, xs, ys, zs, hc, target=target, tol=1, max_iters=max_iters)
     if not res.converged:

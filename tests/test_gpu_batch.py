@@ -95,7 +95,8 @@ def _batch_arrays(sf, ctx, torch, b, systems):
     return keys, xs, ys, zs, hs
 
 
-def test_list_density_counts_match_single(env):
+@pytest.mark.parametrize("cs", [8, 4, 16])
+def test_list_density_counts_match_single(env, cs):
     sf, ctx, torch = env
     systems = _systems(SIZES, 150, 600)
     b = _batch(sf, ctx, systems)
@@ -104,8 +105,9 @@ def test_list_density_counts_match_single(env):
     for s, sy in enumerate(systems):
         lo, hi = int(b.pbase[s]), int(b.pbase[s + 1])
         assert np.all(np.isnan(hp[lo + sy.n:hi]))
-    bbox = sf.batch_build_clusters(ctx, b, xs, ys, zs, hs)
-    nl = sf.batch_build_nlist(ctx, b, keys, xs, ys, zs, hs, bbox, pool=ctx.empty(1024, torch.int32))
+    bbox = sf.batch_build_clusters(ctx, b, xs, ys, zs, hs, cluster_size=cs)
+    nl = sf.batch_build_nlist(ctx, b, keys, xs, ys, zs, hs, bbox, pool=ctx.empty(1024, torch.int32),
+                              cluster_size=cs)
     rho, nnb = sf.batch_pass(ctx, b, nl, xs, ys, zs, hs)
     info = nl.sc_info.cpu().numpy().view(np.uint32)
     pool = nl.pool.cpu().numpy().view(np.uint32)
@@ -117,9 +119,9 @@ def test_list_density_counts_match_single(env):
         lo = int(b.pbase[s])
         c0, c1 = b.sc_range(s)
         k1, x1, y1, z1, h1 = _single(sf, ctx, torch, sy)
-        bb1 = sf.build_clusters(ctx, x1, y1, z1, h1)
-        np.testing.assert_array_equal(bbox.cpu().numpy()[lo // 8: lo // 8 + bb1.shape[0]], bb1.cpu().numpy())
-        nl1 = sf.build_nlist(ctx, k1, x1, y1, z1, h1, bb1)
+        bb1 = sf.build_clusters(ctx, x1, y1, z1, h1, cs)
+        np.testing.assert_array_equal(bbox.cpu().numpy()[lo // cs: lo // cs + bb1.shape[0]], bb1.cpu().numpy())
+        nl1 = sf.build_nlist(ctx, k1, x1, y1, z1, h1, bb1, cluster_size=cs)
         r1, n1 = sf.nlist_pass(ctx, nl1, x1, y1, z1, h1)
         i1 = nl1.sc_info.cpu().numpy().view(np.uint32)
         np.testing.assert_array_equal(info[c0:c1, 1], i1[:, 1])
@@ -130,7 +132,7 @@ def test_list_density_counts_match_single(env):
         total_words += words
         np.testing.assert_array_equal(rho_h[lo:lo + sy.n], r1.cpu().numpy())
         np.testing.assert_array_equal(nnb_h[lo:lo + sy.n], n1.cpu().numpy())
-        if sy.n <= 20000:  # the oracle's counts for the same radii
+        if sy.n <= 20000 and cs == 8:  # the oracle's counts for the same radii
             _, cnt = oracle.density(x1.cpu().numpy(), y1.cpu().numpy(), z1.cpu().numpy(), h1.cpu().numpy(), None,
                                     "grid")
             np.testing.assert_array_equal(n1.cpu().numpy(), cnt)

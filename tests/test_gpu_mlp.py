@@ -127,7 +127,7 @@ def test_features_match_oracle(env, with_counts):
     if with_counts:
         nl = sf.build_nlist(ctx, keys, xs, ys, zs, hs, bbox)
         _, nnb = sf.nlist_pass(ctx, nl, xs, ys, zs, hs)
-    feat = sf.hseed_features(ctx, keys, hs, nnb, bbox, hseed.box_edge(s.box), 100)
+    feat = sf.hseed_features(ctx, keys, xs, ys, zs, hs, nnb, hseed.box_edge(s.box), 100)
     got = _bits_to_f64(feat.cpu().numpy()).reshape(-1, 8)
     ref = oracle.hseed_features(keys.cpu().numpy().view(np.uint64), hs.cpu().numpy(),
                                 None if nnb is None else nnb.cpu().numpy(), bbox.cpu().numpy(),

@@ -41,12 +41,12 @@ def _u32(t):
     return t.cpu().numpy().view(np.uint32)
 
 
-def _run(env, s, compress=True, leaf_bucket=64, max_j=512, mass=None):
+def _run(env, s, compress=True, leaf_bucket=64, max_j=512, mass=None, cs=8):
     sf, ctx, torch = env
-    _say("case %s n=%d compress=%d bucket=%d" % (s.name, s.n, compress, leaf_bucket))
+    _say("case %s n=%d compress=%d bucket=%d cs=%d" % (s.name, s.n, compress, leaf_bucket, cs))
     x, y, z, h = (_dev(torch, a) for a in (s.x, s.y, s.z, s.h))
     m = None if mass is None else _dev(torch, mass)
-    pipe = sf.Pipeline(ctx, s.n, s.box, compress, leaf_bucket, max_j, with_mass=mass is not None)
+    pipe = sf.Pipeline(ctx, s.n, s.box, compress, leaf_bucket, max_j, with_mass=mass is not None, cluster_size=cs)
     nl = pipe.step(x, y, z, h, m)
     torch.cuda.synchronize()
     out = dict(keys=pipe.keys.cpu().numpy().view(np.uint64), perm=_u32(pipe.perm),
@@ -57,13 +57,13 @@ def _run(env, s, compress=True, leaf_bucket=64, max_j=512, mass=None):
     return out
 
 
-def _compare(s, g, compress=True, mass=None, method="grid"):
-    ref = oracle.pipeline(s.x, s.y, s.z, s.h, s.box, mass, 8, compress, method)
+def _compare(s, g, compress=True, mass=None, method="grid", cs=8):
+    ref = oracle.pipeline(s.x, s.y, s.z, s.h, s.box, mass, cs, compress, method)
     np.testing.assert_array_equal(g["keys"], ref["sorted_keys"])
     np.testing.assert_array_equal(g["perm"], ref["perm"])
     np.testing.assert_array_equal(g["x"], ref["x"])
     np.testing.assert_array_equal(g["h"], ref["h"])
-    np.testing.assert_array_equal(g["bbox"], oracle.cluster_bboxes(ref["x"], ref["y"], ref["z"], ref["h"], 8))
+    np.testing.assert_array_equal(g["bbox"], oracle.cluster_bboxes(ref["x"], ref["y"], ref["z"], ref["h"], cs))
     np.testing.assert_array_equal(g["sc_info"], ref["sc_info"])
     np.testing.assert_array_equal(g["pool"], ref["pool"])
     np.testing.assert_array_equal(g["nnb"], ref["nnb"])
@@ -152,6 +152,66 @@ def test_device_decoder_matches_oracle_list(env):
         g = _run(env, s, compress)
         offs, j, m = sf.nlist_decode(ctx, g["nl"])
         ref = oracle.pipeline(s.x, s.y, s.z, s.h, s.box, None, 8, compress)
+        np.testing.assert_array_equal(offs, ref["offs"])
+        np.testing.assert_array_equal(j, ref["j"])
+        np.testing.assert_array_equal(m, ref["mask"])
+
+
+# Cluster sizes 4 and 16 (64 / cs i-clusters per super-cluster, masks of 16
+# and 4 bits): the same oracle comparisons as for size 8.
+CS_OTHER = [4, 16]
+
+
+@pytest.mark.parametrize("cs", CS_OTHER)
+@pytest.mark.parametrize("compress", [True, False])
+def test_cluster_size_uniform_32k(env, cs, compress):
+    s = workloads.make_config("uniform_32k")
+    _compare(s, _run(env, s, compress, cs=cs), compress, cs=cs)
+
+
+@pytest.mark.parametrize("cs", CS_OTHER)
+@pytest.mark.parametrize("n", [1, 5, 17, 63, 65, 1000, 4099])
+def test_cluster_size_small_and_ragged(env, cs, n):
+    s = workloads.uniform_varied(n, 2000 + n, target=40.0)
+    _compare(s, _run(env, s, cs=cs), cs=cs)
+
+
+@pytest.mark.parametrize("cs", CS_OTHER)
+def test_cluster_size_varied_masses_plummer(env, cs):
+    rng = np.random.default_rng(15)
+    s = workloads.uniform_varied(20000, 16, target=60.0)
+    s.h = (s.h * np.exp(rng.uniform(-1.2, 1.2, s.n))).astype(np.float32)
+    m = rng.uniform(0.1, 3.0, s.n).astype(np.float32)
+    _compare(s, _run(env, s, mass=m, cs=cs), mass=m, cs=cs)
+    p = workloads.plummer(30000, 23, target=150.0)
+    _compare(p, _run(env, p, leaf_bucket=128, cs=cs), cs=cs)
+
+
+@pytest.mark.parametrize("cs", CS_OTHER)
+def test_cluster_size_ties_and_lattice(env, cs):
+    rng = np.random.default_rng(19)
+    n = 2000
+    base = rng.random((3, 30)).astype(np.float32)
+    pick = rng.integers(0, 30, n)
+    s = workloads.ParticleSystem("ties", base[0][pick].copy(), base[1][pick].copy(), base[2][pick].copy(),
+                                 np.full(n, 0.05, np.float32), None, workloads.UNIT_BOX)
+    _compare(s, _run(env, s, cs=cs), cs=cs)
+    a = 0.125
+    g = np.arange(8, dtype=np.float32) * np.float32(a)
+    X, Y, Z = np.meshgrid(g, g, g, indexing="ij")
+    lat = workloads.ParticleSystem("lattice", X.ravel().copy(), Y.ravel().copy(), Z.ravel().copy(),
+                                   np.full(X.size, 0.13, np.float32), None, workloads.UNIT_BOX)
+    _compare(lat, _run(env, lat, cs=cs), method="brute", cs=cs)
+
+
+@pytest.mark.parametrize("cs", CS_OTHER)
+def test_cluster_size_decoder(env, cs):
+    sf, ctx, torch = env
+    s = workloads.uniform_varied(9000, 45, target=120.0)
+    for compress in (True, False):
+        g = _run(env, s, compress, cs=cs)
+        offs, j, m = sf.nlist_decode(ctx, g["nl"])
+        ref = oracle.pipeline(s.x, s.y, s.z, s.h, s.box, None, cs, compress)
         np.testing.assert_array_equal(offs, ref["offs"])
         np.testing.assert_array_equal(j, ref["j"])
         np.testing.assert_array_equal(m, ref["mask"])
