@@ -211,13 +211,14 @@ def run_batch(args, sf, torch, ctx):
         return rounds, nnbs
 
     batch_bufs = {}
-    tuned = {"leaf_bucket": 128}
+    tuned = {"leaf_bucket": 128, "cluster_size": 8}
 
     def batched(seeded, use_graph=True):
         hb.copy_(h0b)
         kw = dict(mlp_params=params, seed_mode=sf.SEED_BEFORE_FIRST) if seeded else {}
         res = sf.batch_h_iterate(ctx, b, keys, xs, ys, zs, hb, target=T, tol=1, max_iters=64, use_graph=use_graph,
-                                 leaf_bucket=tuned["leaf_bucket"], bufs=batch_bufs, **kw)
+                                 leaf_bucket=tuned["leaf_bucket"], cluster_size=tuned["cluster_size"],
+                                 bufs=batch_bufs, **kw)
         if not res.converged:
             raise RuntimeError("batch did not converge")
         return res.sys_rounds.tolist(), [res.nnb[real]]
@@ -242,7 +243,7 @@ def run_batch(args, sf, torch, ctx):
     plain = timed(plain_per_system, False)
     log("batched seeded iteration: warm-up run, then leaf-bucket autotune at the converged radii")
     batched(True)
-    tuned = autotune.tune_batch(ctx, b, keys, xs, ys, zs, hb, tag="batch%d_t%d" % (b.nsys, T))
+    tuned = autotune.tune_batch(ctx, b, keys, xs, ys, zs, hb, tag="batch%d_t%d" % (b.nsys, T), use_cache=False)
     log("autotune: %s" % tuned)
     log("batched seeded iteration (graph)")
     best = timed(batched, True)
@@ -256,8 +257,8 @@ def run_batch(args, sf, torch, ctx):
            "warmup": args.warmup, "ms_per_step": best["ms"], "higher_is_better": True, "scaling": "weak",
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "batch_%d_uniform_plummer" % b.nsys, "n_total": ntot, "n_padded": b.n_pad,
-                      "sizes": "log-uniform [1e4, 1e6]", "target": T, "tol": 1, "cluster_size": 8,
-                      "leaf_bucket": tuned["leaf_bucket"]},
+                      "sizes": "log-uniform [1e4, 1e6]", "target": T, "tol": 1,
+                      "cluster_size": tuned["cluster_size"], "leaf_bucket": tuned["leaf_bucket"]},
            "batched_seeded_graph": best, "plain_per_system": plain, "batched_plain_graph": bplain,
            "seeded_per_system": sseed, "speedup_vs_plain_per_system": plain["ms"] / best["ms"],
            "autotune": tuned, "seed_training": {"pairs": int(feat.shape[0]), "seconds": train_s,

@@ -1,11 +1,14 @@
 """Launch-shape autotuner for the batched path.
 
-Picks the octree leaf bucket (particles per leaf, the one free shape of the
-list build: small buckets test more node boxes, large ones more candidate
-j-clusters) by timing one list build plus pass of the whole batch for each
-candidate on the batch's own stream order, with the radii the caller passes.
-Results are cached in a JSON file keyed by (GPU architecture, padded-size
-bucket, workload tag), so a later run on the same kind of batch reuses them.
+Picks the cluster size (4, 8 or 16: the tile each exact test and each pass
+step covers; smaller clusters waste fewer pair evaluations, larger ones list
+fewer entries, Sec. III-A) and the octree leaf bucket (particles per leaf:
+small buckets test more node boxes, large ones more candidate j-clusters) by
+timing one cluster-box build, list build and pass of the whole batch for each
+candidate, with the radii the caller passes. The list, and so every result,
+is the same for all candidates. Results are cached in a JSON file keyed by
+(GPU architecture, padded-size bucket, workload tag), so a later run on the
+same kind of batch reuses them.
 """
 from __future__ import annotations
 
@@ -17,7 +20,9 @@ import torch
 
 from . import batch_build_clusters, batch_build_nlist, batch_pass
 
-CANDIDATES = (32, 64, 128, 256)
+CLUSTER_SIZES = (4, 8, 16)
+BUCKETS = (32, 64, 128, 256)
+CANDIDATES = tuple((cs, b) for cs in CLUSTER_SIZES for b in BUCKETS)
 
 
 def default_cache_path() -> str:
@@ -40,7 +45,8 @@ def _load(path):
 
 def tune_batch(ctx, b, keys, x, y, z, h, tag: str = "", candidates=CANDIDATES, reps: int = 3,
                cache_path: str | None = None, use_cache: bool = True) -> dict:
-    """Returns {"leaf_bucket": best, "ms": {bucket: median ms}, "cached": bool}."""
+    """Returns {"cluster_size": cs, "leaf_bucket": bucket, "ms": {"cs<cs>_b<bucket>": median ms},
+    "cached": bool}."""
     path = cache_path or default_cache_path()
     key = cache_key(b.n_pad, tag)
     db = _load(path) if use_cache else {}
@@ -51,26 +57,29 @@ def tune_batch(ctx, b, keys, x, y, z, h, tag: str = "", candidates=CANDIDATES, r
     st = ctx.stream
     times = {}
     bufs = {}
-    for cand in candidates:
+    for cs, bucket in candidates:
         ms = []
         for _ in range(reps + 1):
             e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
             e0.record(st)
-            bbox = batch_build_clusters(ctx, b, x, y, z, h, bufs.get("bbox"))
-            nl = batch_build_nlist(ctx, b, keys, x, y, z, h, bbox, leaf_bucket=cand, pool=bufs.get("pool"),
+            bbox = batch_build_clusters(ctx, b, x, y, z, h, bufs.get("bbox"), cluster_size=cs)
+            nl = batch_build_nlist(ctx, b, keys, x, y, z, h, bbox, leaf_bucket=bucket, pool=bufs.get("pool"),
                                    ws=bufs.get("ws"), sc_info=bufs.get("sc_info"),
-                                   max_j_per_sc=bufs.get("max_j", 512))
+                                   max_j_per_sc=bufs.get("max_j", 512), cluster_size=cs)
             rho, nnb = batch_pass(ctx, b, nl, x, y, z, h, rho=bufs.get("rho"), nnb=bufs.get("nnb"))
             e1.record(st)
             e1.synchronize()
             ms.append(e0.elapsed_time(e1))
-            bufs.update(bbox=bbox, pool=nl.pool, sc_info=nl.sc_info, max_j=nl.max_j_per_sc, rho=rho, nnb=nnb)
+            bufs.update(pool=nl.pool, sc_info=nl.sc_info, max_j=nl.max_j_per_sc, rho=rho, nnb=nnb)
+            if bufs.get("bbox") is None or bbox.numel() > bufs["bbox"].numel():
+                bufs["bbox"] = bbox
             if nl.ws is not None and (bufs.get("ws") is None or nl.ws.numel() > bufs["ws"].numel()):
                 bufs["ws"] = nl.ws
         ms = sorted(ms[1:])  # the first call sizes the buffers
-        times[cand] = ms[len(ms) // 2]
+        times[(cs, bucket)] = ms[len(ms) // 2]
     best = min(times, key=times.get)
-    out = {"leaf_bucket": int(best), "ms": {str(k): round(v, 4) for k, v in times.items()}}
+    out = {"cluster_size": int(best[0]), "leaf_bucket": int(best[1]),
+           "ms": {"cs%d_b%d" % k: round(v, 4) for k, v in times.items()}}
     if use_cache:
         db = _load(path)
         db[key] = out
