@@ -122,6 +122,10 @@ int build_clusters(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y,
  *   compress      0 or 1.
  *   leaf_bucket   octree leaves hold at most this many particles (8..256).
  *   max_j_per_sc  capacity of the per-super-cluster staging list.
+ *   half          0: the full list above; 1: the half list, which keeps only
+ *                 the pairs with j > i (the symmetric option of Sec. II-D,
+ *                 each pair stored once): masks count only such pairs, and a
+ *                 super-cluster lists no j-cluster that ends before it.
  * Workspace: at least build_nlist_workspace(n, opts) bytes.
  * Returns SFCNL_OK, or SFCNL_E_CAPACITY when the pool (pool_bytes) or the
  * staging list is too small: then *h_used_bytes is the pool size needed and
@@ -134,6 +138,7 @@ typedef struct {
     int compress;
     int leaf_bucket;
     int max_j_per_sc;
+    int half;
 } sfcnl_nlist_opts;
 
 int build_nlist_workspace(int64_t n, const sfcnl_nlist_opts *opts, size_t *ws_bytes);
@@ -143,14 +148,18 @@ int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d
                 size_t *h_used_bytes, int64_t *h_max_nj);
 
 /* ---- 4. Neighbour pass (Sec. II-A, Sec. II-D Listing 1) ------------------
- * Decompresses each super-cluster's list and evaluates every 8x8 particle
+ * Decompresses each super-cluster's list and evaluates every cs x cs particle
  * tile of a listed (j-cluster, set mask bit) pair:
  *   rho_i = m_i W(0, h_i) + sum_{j != i, d2 < f32(h_i^2)} m_j W(r_ij, h_i)
  *   nnb_i = number of such j,
  * W the M4 cubic spline of compact support h (3-D norm 8 / (pi h^3)), in
  * FP32. d_m == NULL means unit masses; d_nnb may be NULL. Outputs in SFC
- * order. */
-int nlist_pass(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, const uint32_t *d_sc_info,
+ * order. cluster_size and compress as given to build_nlist; half = 1 for a
+ * half list (built with opts->half): each stored pair then feeds both
+ * particles (Sec. II-D's symmetric evaluation), added with atomics, so the
+ * last bits of rho may differ from run to run (nnb stays exact). A full list
+ * must be passed with half = 0. */
+int nlist_pass(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, int half, const uint32_t *d_sc_info,
                const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z,
                const float *d_h, const float *d_m, float *d_rho, int32_t *d_nnb);
 
@@ -331,7 +340,7 @@ int sfcnl_batch_build_nlist(sfcnl_ctx ctx, sfcnl_batch b, const uint64_t *d_keys
                             const float *d_y, const float *d_z, const float *d_h, const float *d_bbox,
                             const sfcnl_nlist_opts *opts, void *d_ws, size_t ws_bytes, uint32_t *d_sc_info,
                             uint32_t *d_pool, size_t pool_bytes, size_t *h_used_bytes, int64_t *h_max_nj);
-int sfcnl_batch_pass(sfcnl_ctx ctx, sfcnl_batch b, int cluster_size, int compress, const uint32_t *d_sc_info,
+int sfcnl_batch_pass(sfcnl_ctx ctx, sfcnl_batch b, int cluster_size, int compress, int half, const uint32_t *d_sc_info,
                      const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z, const float *d_h,
                      const float *d_m, float *d_rho, int32_t *d_nnb);
 int sfcnl_batch_h_iterate(sfcnl_ctx ctx, sfcnl_batch b, const uint64_t *d_keys, const float *d_x, const float *d_y,

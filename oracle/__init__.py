@@ -68,7 +68,7 @@ def _load():
         lib.orc_pairs_csr.restype = None
         lib.orc_pairs_csr.argtypes = [C.c_int64, f32p, f32p, f32p, f32p, C.c_int, i64p, C.c_void_p]
         lib.orc_cluster_list.restype = C.c_int
-        lib.orc_cluster_list.argtypes = [C.c_int64, f32p, f32p, f32p, f32p, C.c_int, C.c_int, C.c_int64,
+        lib.orc_cluster_list.argtypes = [C.c_int64, f32p, f32p, f32p, f32p, C.c_int, C.c_int, C.c_int, C.c_int64,
                                          C.c_void_p, C.c_int64, C.POINTER(C.c_void_p),
                                          C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]
         lib.orc_free.restype = None
@@ -162,9 +162,11 @@ def max_degree(x, y, z, h, method: str = "grid") -> int:
     return int(_load().orc_max_degree(x.shape[0], x, y, z, h, 1 if method == "grid" else 0))
 
 
-def cluster_list(x, y, z, h, cs: int = 8, method: str = "grid", sc_ids=None):
+def cluster_list(x, y, z, h, cs: int = 8, method: str = "grid", sc_ids=None, half: bool = False):
     """Cluster-pair list of Sec. II-A: per selected super-cluster the
-    ascending j-cluster indices and their i-cluster bitmasks.
+    ascending j-cluster indices and their i-cluster bitmasks. half: only
+    pairs with j > i count (each pair of P stored once, Sec. II-D's symmetric
+    option).
 
     Returns (offs[nsel+1] int64, j uint32, mask uint16)."""
     x, y, z, h = _f32(x), _f32(y), _f32(z), _f32(h)
@@ -181,7 +183,8 @@ def cluster_list(x, y, z, h, cs: int = 8, method: str = "grid", sc_ids=None):
         nsel = ids.shape[0]
         ids_ptr = ids.ctypes.data
     po, pj, pm = C.c_void_p(), C.c_void_p(), C.c_void_p()
-    rc = lib.orc_cluster_list(n, x, y, z, h, cs, g, nsel, ids_ptr, md, C.byref(po), C.byref(pj), C.byref(pm))
+    rc = lib.orc_cluster_list(n, x, y, z, h, cs, int(bool(half)), g, nsel, ids_ptr, md, C.byref(po), C.byref(pj),
+                              C.byref(pm))
     if rc != 0:
         raise MemoryError("oracle cluster list")
     offs = np.ctypeslib.as_array(C.cast(po, C.POINTER(C.c_int64)), shape=(nsel + 1,)).copy()
@@ -280,14 +283,15 @@ def density(x, y, z, h, m=None, method: str = "grid"):
 # The whole path on one system
 # --------------------------------------------------------------------------
 
-def pipeline(x, y, z, h, box, m=None, cs: int = 8, compress: bool = True, method: str = "grid"):
+def pipeline(x, y, z, h, box, m=None, cs: int = 8, compress: bool = True, method: str = "grid",
+             half: bool = False):
     """Hilbert keys -> stable order -> SFC-ordered arrays -> cluster list ->
     encoding -> density, all in SFC order. Returns a dict."""
     keys = hilbert_keys(x, y, z, box)
     perm = sfc_order(keys)
     xs, ys, zs, hs = (np.asarray(a)[perm] for a in (x, y, z, h))
     ms = None if m is None else np.asarray(m)[perm]
-    offs, jj, mm = cluster_list(xs, ys, zs, hs, cs, method)
+    offs, jj, mm = cluster_list(xs, ys, zs, hs, cs, method, half=half)
     info, pool = encode_all(offs, jj, mm, cs, compress)
     rho, nnb = density(xs, ys, zs, hs, ms, method)
     return dict(keys=keys, perm=perm, sorted_keys=keys[perm], x=xs, y=ys, z=zs, h=hs, m=ms,

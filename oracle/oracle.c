@@ -295,7 +295,9 @@ void orc_pairs_csr(int64_t n, const float *x, const float *y, const float *z, co
  * cs-sized runs inside it (bit c of a mask = i-cluster c of the super-cluster).
  * Its list holds every j-cluster that contains a j with (i, j) in P for some i
  * of the super-cluster, ascending, with bit c set iff such an i lies in
- * i-cluster c. */
+ * i-cluster c. The half list (the symmetric option of Sec. II-D: each pair
+ * stored once) counts only pairs with j > i, so every pair of P appears in
+ * exactly one super-cluster's list, under its smaller index. */
 typedef struct {
     int64_t count;
     uint32_t *j;
@@ -303,7 +305,7 @@ typedef struct {
 } orc_sc_list;
 
 static void sc_list_one(const orc_grid *g, int use_grid, int64_t n, const float *x, const float *y,
-                        const float *z, const float *h, int cs, int64_t s, uint16_t *marks,
+                        const float *z, const float *h, int cs, int half, int64_t s, uint16_t *marks,
                         int64_t *touched, int64_t **nbp, int64_t *nbcap, orc_sc_list *out)
 {
     int64_t nt = 0;
@@ -319,6 +321,7 @@ static void sc_list_one(const orc_grid *g, int use_grid, int64_t n, const float 
         }
         const int64_t *nb = *nbp;
         for (int64_t k = 0; k < cnt; k++) {
+            if (half && nb[k] <= i) continue;
             int64_t cj = nb[k] / cs;
             if (marks[cj] == 0) touched[nt++] = cj;
             marks[cj] |= (uint16_t)(1u << c);
@@ -340,7 +343,7 @@ static void sc_list_one(const orc_grid *g, int use_grid, int64_t n, const float 
  * per-thread neighbour buffer, which grows on demand. Results are returned as CSR over the
  * selection: *out_offs (nsel+1), *out_j, *out_mask, malloc'ed here and
  * released with orc_free. Returns 0, or -1 on allocation failure. */
-int orc_cluster_list(int64_t n, const float *x, const float *y, const float *z, const float *h, int cs,
+int orc_cluster_list(int64_t n, const float *x, const float *y, const float *z, const float *h, int cs, int half,
                      int use_grid, int64_t nsel, const int64_t *sc_ids, int64_t max_degree,
                      int64_t **out_offs, uint32_t **out_j, uint16_t **out_mask)
 {
@@ -359,7 +362,7 @@ int orc_cluster_list(int64_t n, const float *x, const float *y, const float *z, 
 #pragma omp for schedule(dynamic, 4)
         for (int64_t k = 0; k < nsel; k++) {
             int64_t s = sc_ids ? sc_ids[k] : k;
-            sc_list_one(&g, use_grid, n, x, y, z, h, cs, s, marks, touched, &nb, &cap, &lists[k]);
+            sc_list_one(&g, use_grid, n, x, y, z, h, cs, half, s, marks, touched, &nb, &cap, &lists[k]);
         }
         free(marks);
         free(touched);

@@ -146,6 +146,7 @@ class NeighbourList:
     pool: torch.Tensor        # int32 view of u32 words
     used_bytes: int
     max_nj: int
+    half: bool = False        # only pairs with j > i (each pair once)
 
     @property
     def n_sc(self) -> int:
@@ -155,13 +156,14 @@ class NeighbourList:
         return (self.used_bytes + 8 * self.n_sc) / max(self.n, 1)
 
 
-def _opts(cluster_size, compress, leaf_bucket, max_j_per_sc):
-    return _lib.NlistOpts(cluster_size, int(bool(compress)), leaf_bucket, max_j_per_sc)
+def _opts(cluster_size, compress, leaf_bucket, max_j_per_sc, half=False):
+    return _lib.NlistOpts(cluster_size, int(bool(compress)), leaf_bucket, max_j_per_sc, int(bool(half)))
 
 
-def build_nlist_workspace(n, cluster_size=CLUSTER_SIZE, compress=True, leaf_bucket=128, max_j_per_sc=512) -> int:
+def build_nlist_workspace(n, cluster_size=CLUSTER_SIZE, compress=True, leaf_bucket=128, max_j_per_sc=512,
+                          half=False) -> int:
     b = C.c_size_t()
-    o = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc)
+    o = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc, half)
     if _lib.load().build_nlist_workspace(n, C.byref(o), C.byref(b)) != 0:
         raise SfcnlError(_lib.E_ARG, "build_nlist_workspace")
     return b.value
@@ -169,18 +171,18 @@ def build_nlist_workspace(n, cluster_size=CLUSTER_SIZE, compress=True, leaf_buck
 
 def build_nlist(ctx: Context, keys, x, y, z, h, bbox, compress: bool = True, leaf_bucket: int = 128,
                 max_j_per_sc: int = 512, cluster_size: int = CLUSTER_SIZE, pool=None, ws=None, sc_info=None,
-                grow: bool = True):
-    """Builds the compressed cluster-pair list. Grows the staging list and the
-    pool and retries when the library reports they are too small (unless
-    grow=False, which raises)."""
+                grow: bool = True, half: bool = False):
+    """Builds the compressed cluster-pair list (half: each pair once, j > i).
+    Grows the staging list and the pool and retries when the library reports
+    they are too small (unless grow=False, which raises)."""
     n = x.numel()
     nsc = (n + SC_SIZE - 1) // SC_SIZE
     sc_info = ctx.empty((max(nsc, 1), 2), torch.int32) if sc_info is None else sc_info
     if pool is None:
         pool = ctx.empty(max(1024, 5 * n), torch.int32)
     while True:
-        o = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc)
-        need = build_nlist_workspace(n, cluster_size, compress, leaf_bucket, max_j_per_sc)
+        o = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc, half)
+        need = build_nlist_workspace(n, cluster_size, compress, leaf_bucket, max_j_per_sc, half)
         if ws is None or ws.numel() < need:
             ws = ctx.empty(max(need, 1), torch.uint8)
         used = C.c_size_t()
@@ -195,7 +197,8 @@ def build_nlist(ctx: Context, keys, x, y, z, h, bbox, compress: bool = True, lea
                 pool = ctx.empty(used.value // 4 + 1024, torch.int32)
             continue
         ctx.check(rc)
-        nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, used.value, maxnj.value)
+        nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, used.value, maxnj.value,
+                           bool(half))
         nl.ws = ws
         nl.max_j_per_sc = max_j_per_sc
         return nl
@@ -207,8 +210,8 @@ def nlist_pass(ctx: Context, nl: NeighbourList, x, y, z, h, m=None, rho=None, nn
     rho = ctx.empty(n, torch.float32) if rho is None else rho
     if want_counts and nnb is None:
         nnb = ctx.empty(n, torch.int32)
-    ctx.check(ctx.lib.nlist_pass(ctx.handle, n, nl.cluster_size, int(nl.compress), _ptr(nl.sc_info), _ptr(nl.pool),
-                                 _ptr(x), _ptr(y), _ptr(z), _ptr(h), _ptr(m), _ptr(rho),
+    ctx.check(ctx.lib.nlist_pass(ctx.handle, n, nl.cluster_size, int(nl.compress), int(nl.half), _ptr(nl.sc_info),
+                                 _ptr(nl.pool), _ptr(x), _ptr(y), _ptr(z), _ptr(h), _ptr(m), _ptr(rho),
                                  _ptr(nnb) if want_counts else None))
     return rho, nnb
 
@@ -248,7 +251,7 @@ def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, m
               compress: bool = True, leaf_bucket: int = 128, max_j_per_sc: int = 512, bracket=None, bbox=None,
               ws=None, pool=None, sc_info=None, rho=None, nnb=None, raise_noconv: bool = False,
               resume: bool = False, mlp_params=None, box_edge: float = 0.0, seed_scratch=None,
-              seed_mode: int = _lib.SEED_AFTER_FIRST, cluster_size: int = CLUSTER_SIZE):
+              seed_mode: int = _lib.SEED_AFTER_FIRST, cluster_size: int = CLUSTER_SIZE, half: bool = False):
     """Iterates the SFC-ordered radii h (updated in place) to target +- tol
     own-radius neighbours (sfcnl_h_iterate). With mlp_params the first round's
     update comes from the learned seed. Grows list buffers and resumes when
@@ -276,12 +279,12 @@ def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, m
     total, moved, resume = 0, 0, int(bool(resume))
     while True:
         if total >= max_iters:
-            nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, 0, 0)
+            nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, 0, 0, bool(half))
             return HIterResult(total, n, False, nl, rho, nnb, moved)
-        need = build_nlist_workspace(n, cluster_size, compress, leaf_bucket, max_j_per_sc)
+        need = build_nlist_workspace(n, cluster_size, compress, leaf_bucket, max_j_per_sc, half)
         if ws is None or ws.numel() < need:
             ws = e(max(need, 1), torch.uint8)
-        no = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc)
+        no = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc, half)
         io = _lib.HiterOpts(target, tol, max_iters - total, resume)
         st = _lib.HiterStats()
         seed_arg = C.byref(hs) if (hs is not None and total == 0) else None
@@ -300,7 +303,8 @@ def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, m
                 pool = e(st.used_bytes // 4 + 1024, torch.int32)
             resume = 1
             continue
-        nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, st.used_bytes, st.max_nj)
+        nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, st.used_bytes, st.max_nj,
+                           bool(half))
         nl.ws, nl.max_j_per_sc = ws, max_j_per_sc
         if rc == _lib.E_NOCONV and not raise_noconv:
             return HIterResult(total, st.unconverged, False, nl, rho, nnb, moved)
@@ -398,10 +402,11 @@ class Pipeline:
     sfc_sort -> sfc_gather -> build_clusters -> build_nlist -> nlist_pass."""
 
     def __init__(self, ctx: Context, n: int, box, compress: bool = True, leaf_bucket: int = 128,
-                 max_j_per_sc: int = 512, with_mass: bool = False, cluster_size: int = CLUSTER_SIZE):
+                 max_j_per_sc: int = 512, with_mass: bool = False, cluster_size: int = CLUSTER_SIZE,
+                 half: bool = False):
         self.ctx, self.n, self.box = ctx, n, tuple(float(v) for v in box)
         self.compress, self.leaf_bucket, self.max_j_per_sc = compress, leaf_bucket, max_j_per_sc
-        self.cluster_size = cluster_size
+        self.cluster_size, self.half = cluster_size, half
         nsc = (n + SC_SIZE - 1) // SC_SIZE
         nc = (n + cluster_size - 1) // cluster_size
         e = ctx.empty
@@ -426,7 +431,8 @@ class Pipeline:
         ms = outs[4] if m is not None else None
         build_clusters(ctx, xs, ys, zs, hs, self.cluster_size, self.bbox)
         nl = build_nlist(ctx, self.keys, xs, ys, zs, hs, self.bbox, self.compress, self.leaf_bucket,
-                         self.max_j_per_sc, self.cluster_size, pool=self.pool, ws=self.ws, sc_info=self.sc_info)
+                         self.max_j_per_sc, self.cluster_size, pool=self.pool, ws=self.ws, sc_info=self.sc_info,
+                         half=self.half)
         if nl.pool is not self.pool or nl.ws is not self.ws:  # grown on a retry: keep the larger buffers
             self.pool, self.ws, self.max_j_per_sc = nl.pool, nl.ws, nl.max_j_per_sc
         self.nl = nl
@@ -518,9 +524,9 @@ def batch_build_clusters(ctx: Context, b: Batch, x, y, z, h, bbox=None, cluster_
 
 
 def batch_nlist_workspace(b: Batch, compress=True, leaf_bucket=128, max_j_per_sc=512,
-                          cluster_size: int = CLUSTER_SIZE) -> int:
+                          cluster_size: int = CLUSTER_SIZE, half: bool = False) -> int:
     out = C.c_size_t()
-    o = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc)
+    o = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc, half)
     if _lib.load().sfcnl_batch_nlist_workspace(b.handle, C.byref(o), C.byref(out)) != 0:
         raise SfcnlError(_lib.E_ARG, "sfcnl_batch_nlist_workspace")
     return out.value
@@ -528,15 +534,15 @@ def batch_nlist_workspace(b: Batch, compress=True, leaf_bucket=128, max_j_per_sc
 
 def batch_build_nlist(ctx: Context, b: Batch, keys, x, y, z, h, bbox, compress: bool = True, leaf_bucket: int = 128,
                       max_j_per_sc: int = 512, pool=None, ws=None, sc_info=None, grow: bool = True,
-                      cluster_size: int = CLUSTER_SIZE):
+                      cluster_size: int = CLUSTER_SIZE, half: bool = False):
     """The padded batch's list (one pool, sc_info per padded super-cluster)."""
     n = b.n_pad
     nsc = n // SC_SIZE
     sc_info = ctx.empty((max(nsc, 1), 2), torch.int32) if sc_info is None else sc_info
     pool = ctx.empty(max(1024, 5 * n), torch.int32) if pool is None else pool
     while True:
-        o = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc)
-        need = batch_nlist_workspace(b, compress, leaf_bucket, max_j_per_sc, cluster_size)
+        o = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc, half)
+        need = batch_nlist_workspace(b, compress, leaf_bucket, max_j_per_sc, cluster_size, half)
         if ws is None or ws.numel() < need:
             ws = ctx.empty(max(need, 1), torch.uint8)
         used, maxnj = C.c_size_t(), C.c_int64()
@@ -550,7 +556,8 @@ def batch_build_nlist(ctx: Context, b: Batch, keys, x, y, z, h, bbox, compress: 
                 pool = ctx.empty(used.value // 4 + 1024, torch.int32)
             continue
         ctx.check(rc)
-        nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, used.value, maxnj.value)
+        nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, used.value, maxnj.value,
+                           bool(half))
         nl.ws, nl.max_j_per_sc = ws, max_j_per_sc
         return nl
 
@@ -559,7 +566,8 @@ def batch_pass(ctx: Context, b: Batch, nl: NeighbourList, x, y, z, h, m=None, rh
     n = b.n_pad
     rho = ctx.empty(max(n, 1), torch.float32) if rho is None else rho
     nnb = ctx.empty(max(n, 1), torch.int32) if nnb is None else nnb
-    ctx.check(ctx.lib.sfcnl_batch_pass(ctx.handle, b.handle, nl.cluster_size, int(nl.compress), _ptr(nl.sc_info),
+    ctx.check(ctx.lib.sfcnl_batch_pass(ctx.handle, b.handle, nl.cluster_size, int(nl.compress), int(nl.half),
+                                       _ptr(nl.sc_info),
                                        _ptr(nl.pool), _ptr(x), _ptr(y), _ptr(z), _ptr(h), _ptr(m), _ptr(rho),
                                        _ptr(nnb)))
     return rho, nnb
@@ -583,7 +591,7 @@ class BatchIterResult:
 def batch_h_iterate(ctx: Context, b: Batch, keys, x, y, z, h, target: int = 100, tol: int = 1, max_iters: int = 64,
                     m=None, compress: bool = True, leaf_bucket: int = 128, max_j_per_sc: int = 512,
                     use_graph: bool = True, mlp_params=None, seed_mode: int = _lib.SEED_AFTER_FIRST,
-                    bufs: dict | None = None, cluster_size: int = CLUSTER_SIZE):
+                    bufs: dict | None = None, cluster_size: int = CLUSTER_SIZE, half: bool = False):
     """sfcnl_batch_h_iterate on padded SFC-ordered arrays (h updated in
     place). `bufs` (a dict, filled on first use) keeps every buffer for reuse
     across calls; buffers grow and the run resumes on SFCNL_E_CAPACITY."""
@@ -613,10 +621,10 @@ def batch_h_iterate(ctx: Context, b: Batch, keys, x, y, z, h, target: int = 100,
     total, moved, resume = 0, 0, 0
     while True:
         mj = B["max_j"]
-        need = batch_nlist_workspace(b, compress, leaf_bucket, mj, cluster_size)
+        need = batch_nlist_workspace(b, compress, leaf_bucket, mj, cluster_size, half)
         if "ws" not in B or B["ws"].numel() < need:
             B["ws"] = e(max(need, 1), torch.uint8)
-        no = _opts(cluster_size, compress, leaf_bucket, mj)
+        no = _opts(cluster_size, compress, leaf_bucket, mj, half)
         io = _lib.HiterOpts(target, tol, max(max_iters - total, 1), resume)
         st = _lib.HiterStats()
         r = np.zeros(b.nsys, dtype=np.int32)

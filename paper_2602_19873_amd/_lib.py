@@ -38,7 +38,7 @@ STAGES = ["keys", "sort", "gather", "clusters", "octree", "traverse", "encode", 
 
 class NlistOpts(C.Structure):
     _fields_ = [("cluster_size", C.c_int), ("compress", C.c_int), ("leaf_bucket", C.c_int),
-                ("max_j_per_sc", C.c_int)]
+                ("max_j_per_sc", C.c_int), ("half", C.c_int)]
 
 
 class HiterOpts(C.Structure):
@@ -96,7 +96,7 @@ def load():
     lib.build_nlist.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, C.POINTER(NlistOpts), vp, sz, vp, vp, sz,
                                 C.POINTER(sz), C.POINTER(i64)]
     lib.build_nlist.restype = i32
-    lib.nlist_pass.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.nlist_pass.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.nlist_pass.restype = i32
     lib.nlist_decode.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp]
     lib.nlist_decode.restype = i32
@@ -139,7 +139,7 @@ def load():
     lib.sfcnl_batch_build_nlist.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(NlistOpts), vp, sz, vp, vp,
                                             sz, C.POINTER(sz), P64]
     lib.sfcnl_batch_build_nlist.restype = i32
-    lib.sfcnl_batch_pass.argtypes = [vp, vp, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    lib.sfcnl_batch_pass.argtypes = [vp, vp, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.sfcnl_batch_pass.restype = i32
     lib.sfcnl_batch_h_iterate.argtypes = [vp, vp, vp, vp, vp, vp, vp, vp, vp, C.POINTER(NlistOpts),
                                           C.POINTER(HiterOpts), vp, vp, sz, vp, vp, sz, vp, vp, C.POINTER(HSeed),

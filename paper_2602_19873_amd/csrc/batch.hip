@@ -205,7 +205,7 @@ extern "C" int sfcnl_batch_build_nlist(sfcnl_ctx ctx, sfcnl_batch b, const uint6
                             d_pool, pool_bytes, seg_of(b), true, h_used_bytes, h_max_nj);
 }
 
-extern "C" int sfcnl_batch_pass(sfcnl_ctx ctx, sfcnl_batch b, int cluster_size, int compress,
+extern "C" int sfcnl_batch_pass(sfcnl_ctx ctx, sfcnl_batch b, int cluster_size, int compress, int half,
                                 const uint32_t *d_sc_info, const uint32_t *d_pool, const float *d_x, const float *d_y,
                                 const float *d_z, const float *d_h, const float *d_m, float *d_rho, int32_t *d_nnb) {
     if (!ctx) return SFCNL_E_ARG;
@@ -214,9 +214,10 @@ extern "C" int sfcnl_batch_pass(sfcnl_ctx ctx, sfcnl_batch b, int cluster_size, 
     if (cluster_size != 4 && cluster_size != 8 && cluster_size != 16)
         return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_pass: cluster_size %d not supported", cluster_size);
     if (compress != 0 && compress != 1) return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_pass: compress must be 0 or 1");
+    if (half != 0 && half != 1) return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_pass: half must be 0 or 1");
     if (b->n_pad == 0) return SFCNL_OK;
     if (!d_sc_info || !d_pool || !d_x || !d_y || !d_z || !d_h || !d_rho)
         return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_pass: null pointer");
-    return pass_impl(ctx, b->n_pad, cluster_size, compress, d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb,
+    return pass_impl(ctx, b->n_pad, cluster_size, compress, half, d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb,
                      seg_of(b));
 }

@@ -141,8 +141,8 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
         rc = build_nlist(ctx, n, d_keys, d_x, d_y, d_z, d_h, d_bbox, nl_opts, d_ws, ws_bytes, d_sc_info, d_pool,
                          pool_bytes, &S.used_bytes, &S.max_nj);
         if (rc) return rc;
-        rc = nlist_pass(ctx, n, nl_opts->cluster_size, nl_opts->compress, d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m,
-                        d_rho, d_nnb);
+        rc = nlist_pass(ctx, n, nl_opts->cluster_size, nl_opts->compress, nl_opts->half, d_sc_info, d_pool, d_x, d_y,
+                        d_z, d_h, d_m, d_rho, d_nnb);
         if (rc) return rc;
         const float *proposal = nullptr;
         if (seed && seed->mode == SFCNL_SEED_AFTER_FIRST && it == 0) {  // learned step from the first counts
@@ -205,8 +205,8 @@ int enqueue_round(sfcnl_ctx ctx, const RoundArgs &r, const sfcnl_hseed *seed) {
     rc = nlist_build_impl(ctx, n, r.keys, r.x, r.y, r.z, r.h, r.bbox, *r.nl, r.ws, r.ws_bytes, r.sc_info, r.pool,
                           r.pool_bytes, seg, false, nullptr, nullptr);
     if (rc) return rc;
-    rc = pass_impl(ctx, n, r.nl->cluster_size, r.nl->compress, r.sc_info, r.pool, r.x, r.y, r.z, r.h, r.m, r.rho,
-                   r.nnb, seg);
+    rc = pass_impl(ctx, n, r.nl->cluster_size, r.nl->compress, r.nl->half, r.sc_info, r.pool, r.x, r.y, r.z, r.h,
+                   r.m, r.rho, r.nnb, seg);
     if (rc) return rc;
     const float *proposal = nullptr;
     if (seed) {

@@ -183,7 +183,7 @@ int nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *keys, const float
                      size_t *used_bytes, int64_t *max_nj);
 int clusters_impl(sfcnl_ctx ctx, int64_t n, const float *x, const float *y, const float *z, const float *h, int cs,
                   float *bbox, const SegTable &seg);
-int pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, const uint32_t *sc_info, const uint32_t *pool,
+int pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, int half, const uint32_t *sc_info, const uint32_t *pool,
               const float *x, const float *y, const float *z, const float *h, const float *m, float *rho, int32_t *nnb,
               const SegTable &seg);
 int features_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *keys, const float *x, const float *y, const float *z,

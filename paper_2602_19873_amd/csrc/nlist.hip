@@ -118,6 +118,7 @@ struct TravArgs {
     const uint4 *cs_rec;
     uint32_t nslots;       // capacity of the slot arrays
     SegTable seg;          // batched systems (empty for one system)
+    int half;              // list only pairs with j > i
     uint32_t *list_j;      // staging: cap entries per super-cluster
     uint16_t *list_m;
     uint32_t *sc_nj, *sc_words;
@@ -185,6 +186,8 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
         ih2[k] = hh * hh;
     }
     const uint32_t own_c0 = s * kNsub;  // first i-cluster of this super-cluster
+    const uint32_t own_p0 = s * kScSize;  // and its first particle
+    const bool half = a.half != 0;
     const float4 empty_lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
     const float4 empty_hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
     auto cbox = [&](uint32_t c, float4 &lo, float4 &hi) {
@@ -262,6 +265,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
             int64_t c0 = nfirst / CS;
             const int64_t c1 = (nend - 1) / CS;
             if (c0 <= last) c0 = last + 1;
+            if (half && c0 < (int64_t)own_c0) c0 = own_c0;  // j-clusters wholly before i: no j > i
             // j-particles of the candidate clusters cb .. cb + 64/CS - 1 are 64
             // consecutive particles: one coalesced load, lane l holding
             // particle l of the run; absent ones are put far away. Lane l also
@@ -321,7 +325,11 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                     }
                     const uint32_t cjv = (uint32_t)(cb + jc);
                     // the j-cluster is one of our own i-clusters: exclude i == j
+                    // (full list) or keep only j > i (half list)
                     const int self_c = (cjv >= own_c0 && cjv < own_c0 + kNsub) ? (int)(cjv - own_c0) : -1;
+                    auto keep = [&](int ci, int ipos, int jpos) {
+                        return half ? (ci < self_c || (ci == self_c && jpos > ipos)) : (ci != self_c || jpos != ipos);
+                    };
                     uint32_t mask = 0;
                     if (CS == 8) {
                         const int jl = lane & 7, il = lane >> 3;
@@ -337,7 +345,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                                 const float dxx = dx * dx;
                                 const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
                                 bool pr = d2 < fmaxf(ih2[c], hj2);
-                                if (c == self_c) pr = pr && il != jl;
+                                if (self_c >= 0) pr = pr && keep(c, il, jl);
                                 if (sfc_ballot(pr)) mask |= 1u << c;
                             }
                         }
@@ -355,7 +363,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                                 const float dxx = dx * dx;
                                 const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
                                 bool pr = d2 < fmaxf(ih2[k], hj2);
-                                if (4 * k + q == self_c) pr = pr && il != jl;
+                                if (self_c >= 0) pr = pr && keep(4 * k + q, il, jl);
                                 const uint64_t b = sfc_ballot(pr);
                                 const uint32_t g = (uint32_t)((b & 0xFFFFull) != 0) |
                                                    ((uint32_t)(((b >> 16) & 0xFFFFull) != 0) << 1) |
@@ -387,7 +395,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                                     const float dxx = dx * dx;
                                     const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
                                     bool p = d2 < fmaxf(ih2[c], hj2[t]);
-                                    if (c == self_c) p = p && il != 4 * t + jq;
+                                    if (self_c >= 0) p = p && keep(c, il, 4 * t + jq);
                                     pr = pr || p;
                                 }
                                 if (sfc_ballot(pr)) mask |= 1u << c;
@@ -423,7 +431,8 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
             if (act) {
                 const float4 lo = a.cs_box[2 * (size_t)slot], hi = a.cs_box[2 * (size_t)slot + 1];
                 crec = a.cs_rec[slot];
-                hit = boxes_near(glo, ghi, lo, hi);
+                // a half list never needs a node that ends before the super-cluster
+                hit = boxes_near(glo, ghi, lo, hi) && (!half || crec.y > own_p0);
             }
             const uint32_t keep = byte_or(sfc_ballot(hit));
             const int cnt = __popc(keep);
@@ -579,6 +588,7 @@ int check_opts(sfcnl_ctx ctx, const sfcnl_nlist_opts *o) {
     if (o->cluster_size != 4 && o->cluster_size != 8 && o->cluster_size != 16)
         return set_err(ctx, SFCNL_E_ARG, "cluster_size %d not supported (4, 8, 16)", o->cluster_size);
     if (o->compress != 0 && o->compress != 1) return set_err(ctx, SFCNL_E_ARG, "compress must be 0 or 1");
+    if (o->half != 0 && o->half != 1) return set_err(ctx, SFCNL_E_ARG, "half must be 0 or 1");
     if (o->leaf_bucket < 8 || o->leaf_bucket > 256)
         return set_err(ctx, SFCNL_E_ARG, "leaf_bucket %d outside [8, 256]", o->leaf_bucket);
     if (o->max_j_per_sc < 1) return set_err(ctx, SFCNL_E_ARG, "max_j_per_sc must be positive");
@@ -669,6 +679,7 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     ta.cs_rec = ws.tree.cs_rec;
     ta.nslots = ws.tree.node_cap;
     ta.seg = seg;
+    ta.half = o.half;
     ta.list_j = ws.list_j;
     ta.list_m = ws.list_m;
     ta.sc_nj = ws.sc_nj;

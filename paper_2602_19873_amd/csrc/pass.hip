@@ -248,6 +248,212 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
     }
 }
 
+// ---------------------------------------------------------------------------
+// Half list: every stored pair (i, j), j > i, is evaluated once and feeds both
+// particles: rho_i gets m_j W(r, h_i) when d2 < h_i^2 and rho_j gets m_i
+// W(r, h_j) when d2 < h_j^2 (the symmetric evaluation of Sec. II-D). Shape
+// sums (times masses) and counts are added atomically to rho and nnb, which
+// start at zero; the j side is first reduced over the lanes that share a
+// j-particle. k_pass_finalize then applies each particle's normalisation and
+// self term. Float atomics make the summation order, and so the last bits of
+// rho, vary from run to run; the counts are exact.
+// ---------------------------------------------------------------------------
+
+__device__ __forceinline__ float half_shape(float q) {
+    // M4 spline shape halved: 1/2 - 3q^2 + 3q^3 below q = 1/2, (1-q)^3 above
+    const float t1 = q - 1.0f;
+    const float q2 = q * q;
+    const float inner = __builtin_fmaf(3.0f * q2, t1, 0.5f);
+    const float outer = -(t1 * t1) * t1;
+    return q < 0.5f ? inner : outer;
+}
+
+template <int CS>
+__device__ __forceinline__ void half_pair(float xj, float yj, float zj, float mj, float hj2, float hjinv, float xi,
+                                          float yi, float zi, float mi, float hi2, float hiinv, bool keep,
+                                          float &acc_i, int &cnt_i, float &acc_j, int &cnt_j) {
+    const float dx = xj - xi;
+    const float dy = yj - yi;
+    const float dz = zj - zi;
+    const float dxx = dx * dx;
+    const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
+    const bool ini = keep && d2 < hi2;
+    const bool inj = keep && d2 < hj2;
+    if (sfc_ballot(ini || inj)) {
+        const float r = __builtin_amdgcn_sqrtf(d2);
+        const float wi = half_shape(r * hiinv);
+        const float wj = half_shape(r * hjinv);
+        const float ni = __builtin_fmaf(mj, wi, acc_i);
+        const float nj = __builtin_fmaf(mi, wj, acc_j);
+        acc_i = ini ? ni : acc_i;
+        cnt_i += ini ? 1 : 0;
+        acc_j = inj ? nj : acc_j;
+        cnt_j += inj ? 1 : 0;
+    }
+}
+
+template <int CS, bool kCompress, bool kMass, bool kCount>
+__global__ __launch_bounds__(256) void k_pass_half(PassArgs a) {
+    constexpr int kNsub = kScSize / CS;
+    constexpr int kNreg = CS == 8 ? 8 : 4;
+    constexpr int kNj = CS == 16 ? 4 : 1;
+    constexpr int kGroup = CS == 8 ? 8 : 4;   // lanes sharing an i-particle = low lane bits
+    const int lane = sfc_lane();
+    const int w = threadIdx.x / kWave;
+    const uint32_t s = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
+    if (s >= a.nsc) return;
+    const int64_t n = a.n;
+    const int jl = lane & (kGroup - 1);
+
+    // i particles; absent ones are put far away (every distance overflows)
+    float ix[kNreg], iy[kNreg], iz[kNreg], ih2[kNreg], ihinv[kNreg], im[kNreg];
+#pragma unroll
+    for (int k = 0; k < kNreg; k++) {
+        const int64_t i = (int64_t)s * kScSize + ipart<CS>(k, lane);
+        const bool v = i < n;
+        ix[k] = v ? a.x[i] : kFar;
+        iy[k] = v ? a.y[i] : kFar;
+        iz[k] = v ? a.z[i] : kFar;
+        const float hh = v ? a.h[i] : 1.0f;
+        ih2[k] = v ? hh * hh : -1.0f;
+        ihinv[k] = 1.0f / hh;
+        im[k] = kMass ? (v ? a.m[i] : 0.0f) : 1.0f;
+    }
+    float acc[kNreg];
+    int cnt_nb[kNreg];
+#pragma unroll
+    for (int k = 0; k < kNreg; k++) {
+        acc[k] = 0.0f;
+        cnt_nb[k] = 0;
+    }
+
+    const uint32_t own_c0 = s * kNsub;
+    const uint32_t off = a.sc_info[2 * s], nj = a.sc_info[2 * s + 1];
+    const uint8_t *mbytes = reinterpret_cast<const uint8_t *>(a.pool + off);
+    const uint16_t *mshorts = reinterpret_cast<const uint16_t *>(a.pool + off);
+    const uint32_t jbase = a.seg.on() ? a.seg.pbase[a.seg.sc_sys[s]] / CS : 0u;
+    uint32_t p = off + (nj * (CS == 4 ? 2u : 1u) + 3u) / 4u;
+    uint32_t prevj = 0xFFFFFFFFu;
+    for (uint32_t b0 = 0; b0 < nj; b0 += kWave) {
+        const uint32_t cnt = nj - b0 < (uint32_t)kWave ? nj - b0 : (uint32_t)kWave;
+        uint32_t jv;
+        if (kCompress) {
+            jv = decode_segment(a.pool, p, cnt, prevj);
+        } else {
+            jv = (uint32_t)lane < cnt ? a.pool[p + b0 + lane] : 0u;
+        }
+        uint32_t mv = 0u;
+        if ((uint32_t)lane < cnt) mv = CS == 4 ? (uint32_t)mshorts[b0 + lane] : (uint32_t)mbytes[b0 + lane];
+        prevj = sfc_readlane(jv, (int)cnt - 1);
+        jv += jbase;
+        for (uint32_t e = 0; e < cnt; e++) {
+            const uint32_t mk = sfc_readlane(mv, (int)e);
+            const uint32_t cj = sfc_readlane(jv, (int)e);
+            float xj[kNj], yj[kNj], zj[kNj], mj[kNj], hj2[kNj], hjinv[kNj], accj[kNj];
+            int cntj[kNj];
+            int64_t jp[kNj];
+#pragma unroll
+            for (int t = 0; t < kNj; t++) {
+                jp[t] = (int64_t)cj * CS + (CS == 16 ? 4 * t + jl : jl);
+                const bool vj = jp[t] < n;
+                xj[t] = vj ? a.x[jp[t]] : kFar;
+                yj[t] = vj ? a.y[jp[t]] : kFar;
+                zj[t] = vj ? a.z[jp[t]] : kFar;
+                mj[t] = kMass ? (vj ? a.m[jp[t]] : 0.0f) : 1.0f;
+                const float hh = vj ? a.h[jp[t]] : 1.0f;
+                hj2[t] = vj ? hh * hh : -1.0f;
+                hjinv[t] = 1.0f / hh;
+                accj[t] = 0.0f;
+                cntj[t] = 0;
+            }
+            // inside the super-cluster only j > i counts
+            const int self_c = (cj >= own_c0 && cj < own_c0 + kNsub) ? (int)(cj - own_c0) : -1;
+            auto keep = [&](int ci, int ipos, int jpos) {
+                return self_c < 0 || ci < self_c || (ci == self_c && jpos > ipos);
+            };
+            if (CS == 8) {
+                const int il = lane >> 3;
+#pragma unroll
+                for (int c = 0; c < kNreg; c++)
+                    if ((mk >> c) & 1u)
+                        half_pair<CS>(xj[0], yj[0], zj[0], mj[0], hj2[0], hjinv[0], ix[c], iy[c], iz[c], im[c],
+                                      ih2[c], ihinv[c], keep(c, il, jl), acc[c], cnt_nb[c], accj[0], cntj[0]);
+            } else if (CS == 4) {
+                const int il = (lane >> 2) & 3, q = lane >> 4;
+#pragma unroll
+                for (int k = 0; k < kNreg; k++)
+                    if ((mk >> (4 * k)) & 0xFu)
+                        half_pair<CS>(xj[0], yj[0], zj[0], mj[0], hj2[0], hjinv[0], ix[k], iy[k], iz[k], im[k],
+                                      ih2[k], ihinv[k], keep(4 * k + q, il, jl), acc[k], cnt_nb[k], accj[0],
+                                      cntj[0]);
+            } else {
+                const int il = lane >> 2;
+#pragma unroll
+                for (int c = 0; c < kNreg; c++)
+                    if ((mk >> c) & 1u) {
+#pragma unroll
+                        for (int t = 0; t < 4; t++)
+                            half_pair<CS>(xj[t], yj[t], zj[t], mj[t], hj2[t], hjinv[t], ix[c], iy[c], iz[c], im[c],
+                                          ih2[c], ihinv[c], keep(c, il, 4 * t + jl), acc[c], cnt_nb[c], accj[t],
+                                          cntj[t]);
+                    }
+            }
+            // j side: sum over the lanes sharing each j-particle (the high lane
+            // bits), then one atomic per j-particle
+            bool any = false;
+#pragma unroll
+            for (int t = 0; t < kNj; t++) any = any || cntj[t] != 0;
+            if (sfc_ballot(any)) {
+#pragma unroll
+                for (int t = 0; t < kNj; t++) {
+#pragma unroll
+                    for (int d = kGroup; d < kWave; d <<= 1) {
+                        accj[t] += __shfl_xor(accj[t], d, 64);
+                        cntj[t] += __shfl_xor(cntj[t], d, 64);
+                    }
+                    if (lane < kGroup && cntj[t] != 0) {
+                        atomicAdd(&a.rho[jp[t]], accj[t]);
+                        if (kCount) atomicAdd(&a.nnb[jp[t]], cntj[t]);
+                    }
+                }
+            }
+        }
+    }
+    // i side: sum the partials of each i-particle (the kGroup lanes sharing
+    // it), then one atomic per particle
+#pragma unroll
+    for (int k = 0; k < kNreg; k++) {
+#pragma unroll
+        for (int d = 1; d < kGroup; d <<= 1) {
+            acc[k] += __shfl_xor(acc[k], d, 64);
+            cnt_nb[k] += __shfl_xor(cnt_nb[k], d, 64);
+        }
+    }
+    float r = acc[0];
+    int nb = cnt_nb[0];
+#pragma unroll
+    for (int k = 1; k < kNreg; k++) {
+        r = jl == k ? acc[k] : r;
+        nb = jl == k ? cnt_nb[k] : nb;
+    }
+    const int64_t io = (int64_t)s * kScSize + ipart<CS>(jl, lane);
+    if (io < n && nb != 0) {
+        atomicAdd(&a.rho[io], r);
+        if (kCount) atomicAdd(&a.nnb[io], nb);
+    }
+}
+
+// rho_i = 8 / (pi h_i^3) (m_i + 2 S_i), S_i the summed halved shapes.
+template <bool kMass>
+__global__ __launch_bounds__(256) void k_pass_finalize(int64_t n, const float *__restrict__ h,
+                                                       const float *__restrict__ m, float *__restrict__ rho) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    const float hinv = 1.0f / h[i];
+    const float norm = 2.5464790894703255f * hinv * hinv * hinv;  // 8 / pi
+    rho[i] = norm * __builtin_fmaf(2.0f, rho[i], kMass ? m[i] : 1.0f);
+}
+
 struct DecodeArgs {
     uint32_t nsc;
     int mask_bytes;
@@ -296,12 +502,26 @@ void launch_pass(int variant, unsigned g, hipStream_t st, const PassArgs &a) {
     }
 }
 
+template <int CS>
+void launch_pass_half(int variant, unsigned g, hipStream_t st, const PassArgs &a) {
+    switch (variant) {
+        case 7: k_pass_half<CS, true, true, true><<<g, 256, 0, st>>>(a); break;
+        case 6: k_pass_half<CS, true, true, false><<<g, 256, 0, st>>>(a); break;
+        case 5: k_pass_half<CS, true, false, true><<<g, 256, 0, st>>>(a); break;
+        case 4: k_pass_half<CS, true, false, false><<<g, 256, 0, st>>>(a); break;
+        case 3: k_pass_half<CS, false, true, true><<<g, 256, 0, st>>>(a); break;
+        case 2: k_pass_half<CS, false, true, false><<<g, 256, 0, st>>>(a); break;
+        case 1: k_pass_half<CS, false, false, true><<<g, 256, 0, st>>>(a); break;
+        default: k_pass_half<CS, false, false, false><<<g, 256, 0, st>>>(a); break;
+    }
+}
+
 }  // namespace
 }  // namespace sfcnl
 
 using namespace sfcnl;
 
-int sfcnl::pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, const uint32_t *d_sc_info,
+int sfcnl::pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, int half, const uint32_t *d_sc_info,
                      const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z, const float *d_h,
                      const float *d_m, float *d_rho, int32_t *d_nnb, const SegTable &seg) {
     PassArgs a{n, (uint32_t)((n + kScSize - 1) / kScSize), d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb,
@@ -310,12 +530,32 @@ int sfcnl::pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, const uint3
     hipStream_t st = ctx->stream;
     const int variant = (compress ? 4 : 0) | (d_m ? 2 : 0) | (d_nnb ? 1 : 0);
     prof_mark(ctx, kStagePass, false);
-    if (cs == 4)
+    if (half) {
+        // accumulators start at zero (fill kernels, so the call can sit in a graph)
+        int rc = fill_u32(ctx, reinterpret_cast<uint32_t *>(d_rho), n, 0u);
+        if (rc) return rc;
+        if (d_nnb) {
+            rc = fill_u32(ctx, reinterpret_cast<uint32_t *>(d_nnb), n, 0u);
+            if (rc) return rc;
+        }
+        if (cs == 4)
+            launch_pass_half<4>(variant, g, st, a);
+        else if (cs == 16)
+            launch_pass_half<16>(variant, g, st, a);
+        else
+            launch_pass_half<8>(variant, g, st, a);
+        SFCNL_LAUNCHED(ctx);
+        if (d_m)
+            k_pass_finalize<true><<<blocks_for(n, 256), 256, 0, st>>>(n, d_h, d_m, d_rho);
+        else
+            k_pass_finalize<false><<<blocks_for(n, 256), 256, 0, st>>>(n, d_h, d_m, d_rho);
+    } else if (cs == 4) {
         launch_pass<4>(variant, g, st, a);
-    else if (cs == 16)
+    } else if (cs == 16) {
         launch_pass<16>(variant, g, st, a);
-    else
+    } else {
         launch_pass<8>(variant, g, st, a);
+    }
     SFCNL_LAUNCHED(ctx);
     prof_mark(ctx, kStagePass, true);
     return SFCNL_OK;
@@ -323,17 +563,18 @@ int sfcnl::pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, const uint3
 
 static bool cs_ok(int cs) { return cs == 4 || cs == 8 || cs == 16; }
 
-extern "C" int nlist_pass(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, const uint32_t *d_sc_info,
-                          const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z,
-                          const float *d_h, const float *d_m, float *d_rho, int32_t *d_nnb) {
+extern "C" int nlist_pass(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, int half,
+                          const uint32_t *d_sc_info, const uint32_t *d_pool, const float *d_x, const float *d_y,
+                          const float *d_z, const float *d_h, const float *d_m, float *d_rho, int32_t *d_nnb) {
     if (!ctx) return SFCNL_E_ARG;
     if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: n out of range");
     if (!cs_ok(cluster_size)) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: cluster_size %d not supported", cluster_size);
     if (compress != 0 && compress != 1) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: compress must be 0 or 1");
+    if (half != 0 && half != 1) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: half must be 0 or 1");
     if (n == 0) return SFCNL_OK;
     if (!d_sc_info || !d_pool || !d_x || !d_y || !d_z || !d_h || !d_rho)
         return set_err(ctx, SFCNL_E_ARG, "nlist_pass: null pointer");
-    return pass_impl(ctx, n, cluster_size, compress, d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb,
+    return pass_impl(ctx, n, cluster_size, compress, half, d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb,
                      SegTable{});
 }
 

@@ -100,3 +100,19 @@ def test_capacity_growth_keeps_trajectory(env):
                       pool=torch.empty(64, dtype=torch.int32, device="cuda"))
     assert ra.converged and rb.converged and ra.iters == rb.iters
     assert torch.equal(h_a, h_b)
+
+
+def test_half_list_iteration_matches_full(env):
+    """Counts do not depend on the list form, so the half list gives the same
+    radii round by round."""
+    sf, ctx, torch = env
+    from paper_2602_19873_amd import hseed
+    s = workloads.uniform_varied(40000, 71, target=80)
+    s.h = (s.h * np.exp(np.random.default_rng(72).uniform(-0.7, 0.7, s.n))).astype(np.float32)
+    a = hseed.sorted_system(ctx, s)
+    b = tuple(t.clone() for t in a)
+    ra = sf.h_iterate(ctx, *a, target=80, tol=1)
+    rb = sf.h_iterate(ctx, *b, target=80, tol=1, half=True)
+    assert ra.converged and rb.converged and ra.iters == rb.iters
+    np.testing.assert_array_equal(a[4].cpu().numpy(), b[4].cpu().numpy())
+    np.testing.assert_array_equal(ra.nnb.cpu().numpy(), rb.nnb.cpu().numpy())

@@ -41,12 +41,13 @@ def _u32(t):
     return t.cpu().numpy().view(np.uint32)
 
 
-def _run(env, s, compress=True, leaf_bucket=64, max_j=512, mass=None, cs=8):
+def _run(env, s, compress=True, leaf_bucket=64, max_j=512, mass=None, cs=8, half=False):
     sf, ctx, torch = env
-    _say("case %s n=%d compress=%d bucket=%d cs=%d" % (s.name, s.n, compress, leaf_bucket, cs))
+    _say("case %s n=%d compress=%d bucket=%d cs=%d half=%d" % (s.name, s.n, compress, leaf_bucket, cs, half))
     x, y, z, h = (_dev(torch, a) for a in (s.x, s.y, s.z, s.h))
     m = None if mass is None else _dev(torch, mass)
-    pipe = sf.Pipeline(ctx, s.n, s.box, compress, leaf_bucket, max_j, with_mass=mass is not None, cluster_size=cs)
+    pipe = sf.Pipeline(ctx, s.n, s.box, compress, leaf_bucket, max_j, with_mass=mass is not None, cluster_size=cs,
+                       half=half)
     nl = pipe.step(x, y, z, h, m)
     torch.cuda.synchronize()
     out = dict(keys=pipe.keys.cpu().numpy().view(np.uint64), perm=_u32(pipe.perm),
@@ -57,8 +58,8 @@ def _run(env, s, compress=True, leaf_bucket=64, max_j=512, mass=None, cs=8):
     return out
 
 
-def _compare(s, g, compress=True, mass=None, method="grid", cs=8):
-    ref = oracle.pipeline(s.x, s.y, s.z, s.h, s.box, mass, cs, compress, method)
+def _compare(s, g, compress=True, mass=None, method="grid", cs=8, half=False):
+    ref = oracle.pipeline(s.x, s.y, s.z, s.h, s.box, mass, cs, compress, method, half=half)
     np.testing.assert_array_equal(g["keys"], ref["sorted_keys"])
     np.testing.assert_array_equal(g["perm"], ref["perm"])
     np.testing.assert_array_equal(g["x"], ref["x"])
@@ -215,6 +216,53 @@ def test_cluster_size_decoder(env, cs):
         np.testing.assert_array_equal(offs, ref["offs"])
         np.testing.assert_array_equal(j, ref["j"])
         np.testing.assert_array_equal(m, ref["mask"])
+
+
+# Half lists (each pair once, j > i; the pass feeds both particles of a pair
+# through atomics): list bytes bit-exact, counts exact, densities within the
+# tolerance.
+CS_ALL = [8, 4, 16]
+
+
+@pytest.mark.parametrize("cs", CS_ALL)
+@pytest.mark.parametrize("compress", [True, False])
+def test_half_uniform_32k(env, cs, compress):
+    s = workloads.make_config("uniform_32k")
+    _compare(s, _run(env, s, compress, cs=cs, half=True), compress, cs=cs, half=True)
+
+
+@pytest.mark.parametrize("cs", CS_ALL)
+@pytest.mark.parametrize("n", [1, 2, 9, 63, 65, 1000, 4099])
+def test_half_small_and_ragged(env, cs, n):
+    s = workloads.uniform_varied(n, 3000 + n, target=40.0)
+    _compare(s, _run(env, s, cs=cs, half=True), cs=cs, half=True)
+
+
+@pytest.mark.parametrize("cs", CS_ALL)
+def test_half_varied_masses_plummer_ties(env, cs):
+    rng = np.random.default_rng(25)
+    s = workloads.uniform_varied(20000, 26, target=60.0)
+    s.h = (s.h * np.exp(rng.uniform(-1.2, 1.2, s.n))).astype(np.float32)
+    m = rng.uniform(0.1, 3.0, s.n).astype(np.float32)
+    _compare(s, _run(env, s, mass=m, cs=cs, half=True), mass=m, cs=cs, half=True)
+    p = workloads.plummer(30000, 27, target=150.0)
+    _compare(p, _run(env, p, leaf_bucket=128, cs=cs, half=True), cs=cs, half=True)
+    n = 2000
+    base = rng.random((3, 30)).astype(np.float32)
+    pick = rng.integers(0, 30, n)
+    t = workloads.ParticleSystem("ties", base[0][pick].copy(), base[1][pick].copy(), base[2][pick].copy(),
+                                 np.full(n, 0.05, np.float32), None, workloads.UNIT_BOX)
+    _compare(t, _run(env, t, cs=cs, half=True), cs=cs, half=True)
+
+
+def test_half_matches_full_counts_and_density(env):
+    s = workloads.uniform_varied(50000, 28, target=120.0)
+    full = _run(env, s)
+    half = _run(env, s, half=True)
+    np.testing.assert_array_equal(half["nnb"], full["nnb"])
+    rel = np.abs(half["rho"].astype(np.float64) - full["rho"]) / full["rho"]
+    assert rel.max() <= RHO_RTOL
+    assert half["nl"].used_bytes < 0.62 * full["nl"].used_bytes
 
 
 def test_capacity_retry_gives_identical_list(env):

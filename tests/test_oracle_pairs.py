@@ -174,3 +174,44 @@ def test_degenerate_sizes():
             # every particle sees every other one: super-cluster 0 lists all clusters
             nc = (n + 7) // 8
             assert list(jj[offs[0]:offs[1]]) == list(range(nc))
+
+
+@pytest.mark.parametrize("cs", [4, 8, 16])
+def test_half_list_stores_each_pair_once(cs):
+    """The half list (j > i) recovers exactly the upper half of P, its masks
+    are exact for that half, and every entry is also in the full list with a
+    mask that contains the half mask."""
+    s = workloads.uniform_varied(700, 22, target=25.0)
+    keys = oracle.hilbert_keys(s.x, s.y, s.z, s.box)
+    p = oracle.sfc_order(keys)
+    x, y, z, h = s.x[p], s.y[p], s.z[p], s.h[p]
+    n = len(x)
+    ho, hj, hm = oracle.cluster_list(x, y, z, h, cs, "brute", half=True)
+    go, gj, gm = oracle.cluster_list(x, y, z, h, cs, "grid", half=True)
+    np.testing.assert_array_equal(ho, go)
+    np.testing.assert_array_equal(hj, gj)
+    np.testing.assert_array_equal(hm, gm)
+    po, pn = oracle.pairs_csr(x, y, z, h, "brute")
+    upper = {(i, int(j)) for i in range(n) for j in pn[po[i]:po[i + 1]] if j > i}
+    got = {(i, j) for (i, j) in _pairs_from_list(x, y, z, h, cs, ho, hj, hm) if j > i}
+    assert got == upper
+    # exact masks for the half: bit c iff some i of i-cluster c pairs with a
+    # larger j of the j-cluster
+    nsub = 64 // cs
+    for sc in range(len(ho) - 1):
+        for e in range(ho[sc], ho[sc + 1]):
+            cj = int(hj[e])
+            assert cj * cs + cs - 1 > 64 * sc  # never a j-cluster wholly before the super-cluster
+            for c in range(nsub):
+                ii = range(64 * sc + c * cs, min(n, 64 * sc + c * cs + cs))
+                hit = any(j > i and oracle.is_pair(x[i], y[i], z[i], h[i], x[j], y[j], z[j], h[j])
+                          for i in ii for j in range(cj * cs, min(n, cj * cs + cs)))
+                assert hit == bool((int(hm[e]) >> c) & 1)
+    fo, fj, fm = oracle.cluster_list(x, y, z, h, cs, "brute")
+    for sc in range(len(ho) - 1):
+        full = dict(zip(fj[fo[sc]:fo[sc + 1]].tolist(), fm[fo[sc]:fo[sc + 1]].tolist()))
+        for e in range(ho[sc], ho[sc + 1]):
+            fmask = full[int(hj[e])]
+            assert (int(hm[e]) & ~fmask) == 0
+    # about half the entries' pairs: the half list is the smaller one
+    assert len(hj) < len(fj)
