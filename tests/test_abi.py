@@ -52,7 +52,7 @@ def test_workspace_queries_are_host_only(lib):
     assert L.build_nlist_workspace(100000, ctypes.byref(o), ctypes.byref(b)) == 0
     assert b.value > 100000 // 64 * 512 * 5
     for bad in (_lib.NlistOpts(5, 1, 64, 512), _lib.NlistOpts(8, 2, 64, 512), _lib.NlistOpts(8, 1, 4, 512),
-                _lib.NlistOpts(8, 1, 64, 0)):
+                _lib.NlistOpts(8, 1, 64, 0), _lib.NlistOpts(8, 1, 64, 512, 2)):
         assert L.build_nlist_workspace(1000, ctypes.byref(bad), ctypes.byref(b)) == _lib.E_ARG
     assert L.sfc_sort_workspace(-1, ctypes.byref(b)) == _lib.E_ARG
 
@@ -62,5 +62,5 @@ def test_null_context_rejected(lib):
     L = _lib.load()
     assert L.sfcnl_sync(None) == _lib.E_ARG
     assert L.sfc_sort(None, 10, None, None, None, None, None, None, None, 0) == _lib.E_ARG
-    assert L.nlist_pass(None, 10, 8, 1, None, None, None, None, None, None, None, None, None) == _lib.E_ARG
+    assert L.nlist_pass(None, 10, 8, 1, 0, None, None, None, None, None, None, None, None, None) == _lib.E_ARG
     assert L.sfcnl_version().startswith(b"sfcnl")
