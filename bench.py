@@ -38,6 +38,7 @@ FLOPS_PER_TEST = 10     # dx, dy, dz (3); dx*dx (1); 2 fma (4); max of radii (1)
 # Counted tests and evaluations: 64 per set mask bit of the final list (the 8x8
 # tiles that establish the list in the build and that the pass evaluates).
 FLOPS_PER_PAIR = 17     # dx, dy, dz (3); d2 (5); sqrt (1); q (1); spline piece (5); m*W, += (2)
+FLOPS_PER_PAIR_HALF = 25  # one distance (9), then q, spline piece, m*W, += for both particles (2 x 8)
 
 
 def log(msg):
@@ -53,7 +54,8 @@ def list_stats(sf, ctx, nl):
     """Bytes per particle split, and the pair work the list fixes."""
     import numpy as np
     offs, j, m = sf.nlist_decode(ctx, nl)
-    pc = np.unpackbits(m.astype(np.uint8)[:, None], axis=1).sum() if m.size else 0
+    mm = m.astype(np.uint16)
+    pc = int(np.unpackbits(mm.view(np.uint8)).sum()) if m.size else 0
     nj = np.diff(offs)
     n = nl.n
     mask_bytes = float(((nj + 3) // 4 * 4).sum())
@@ -65,7 +67,8 @@ def list_stats(sf, ctx, nl):
         "entries": int(nj.sum()),
         "mean_nj": float(nj.mean()) if nj.size else 0.0,
         "max_nj": int(nj.max()) if nj.size else 0,
-        "tile_pairs": int(pc) * 64,        # 64 pair tests per set mask bit (8x8 tile)
+        "tile_pairs": int(pc) * nl.cluster_size ** 2,   # cs x cs pair tests per set mask bit
+        "half": bool(nl.half),
     }
 
 
@@ -274,6 +277,8 @@ def main():
     ap.add_argument("--workload", default="uniform_2m_varied")
     ap.add_argument("--compress", type=int, default=1)
     ap.add_argument("--leaf-bucket", type=int, default=128)
+    ap.add_argument("--cluster-size", type=int, default=8)
+    ap.add_argument("--half", type=int, default=0, help="1: half list (each pair once)")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after warm-up, copy this many MiB once (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -316,6 +321,7 @@ def main():
     x, y, z, h = (torch.from_numpy(a).to(dev) for a in (s.x, s.y, s.z, s.h))
     ctx = sf.Context(0)
     pipe = sf.Pipeline(ctx, n, s.box, compress=bool(args.compress), leaf_bucket=args.leaf_bucket,
+                       cluster_size=args.cluster_size, half=bool(args.half),
                        max_j_per_sc=512)
     for _ in range(max(args.warmup, 1)):
         pipe.step(x, y, z, h)
@@ -355,7 +361,8 @@ def main():
             tf = st["tile_pairs"] * FLOPS_PER_TEST / (avg * 1e-3) / 1e12
             d.update(bound="alu", achieved=tf, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s", frac=tf / FP32_PEAK_TFLOPS)
         elif name == "pass":
-            tf = st["tile_pairs"] * FLOPS_PER_PAIR / (avg * 1e-3) / 1e12
+            fl = FLOPS_PER_PAIR_HALF if args.half else FLOPS_PER_PAIR
+            tf = st["tile_pairs"] * fl / (avg * 1e-3) / 1e12
             d.update(bound="alu", achieved=tf, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s", frac=tf / FP32_PEAK_TFLOPS)
         stages[name] = d
     dom = max((k for k in stages if "bound" in stages[k]), key=lambda k: stages[k]["ms"])
@@ -370,8 +377,9 @@ def main():
         "metric": METRIC, "value": value, "unit": "Mparticles/s", "n_gpus": 1, "steps": args.steps,
         "warmup": args.warmup, "ms_per_step": ms_step, "higher_is_better": True, "scaling": "weak",
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
-        "config": {"workload": args.workload, "n": n, "cluster_size": 8, "super_cluster": 64,
+        "config": {"workload": args.workload, "n": n, "cluster_size": args.cluster_size, "super_cluster": 64,
                    "compress": bool(args.compress), "leaf_bucket": args.leaf_bucket, "radii": "r_c*U(0.8,1.2)",
+                   "list": "half (each pair once, j > i)" if args.half else "full",
                    "target_neighbours": 200},
         "bytes_per_particle": st["bytes_per_particle"],
         "list": st,
