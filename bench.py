@@ -205,7 +205,8 @@ def run_batch(args, sf, torch, ctx):
             if seeded:
                 kw.update(mlp_params=params, box_edge=hseed.box_edge(systems[k].box),
                           seed_mode=sf.SEED_BEFORE_FIRST)
-            res = sf.h_iterate(ctx, keys_k, x_k, y_k, z_k, h_k, target=T, tol=1, max_iters=64, **kw)
+            res = sf.h_iterate(ctx, keys_k, x_k, y_k, z_k, h_k, target=T, tol=1, max_iters=64, half=bool(args.half),
+                               **kw)
             single_bufs[k] = dict(ws=res.nl.ws, pool=res.nl.pool, max_j_per_sc=res.nl.max_j_per_sc)
             if not res.converged:
                 raise RuntimeError("system %d did not converge" % k)
@@ -221,7 +222,7 @@ def run_batch(args, sf, torch, ctx):
         kw = dict(mlp_params=params, seed_mode=sf.SEED_BEFORE_FIRST) if seeded else {}
         res = sf.batch_h_iterate(ctx, b, keys, xs, ys, zs, hb, target=T, tol=1, max_iters=64, use_graph=use_graph,
                                  leaf_bucket=tuned["leaf_bucket"], cluster_size=tuned["cluster_size"],
-                                 bufs=batch_bufs, **kw)
+                                 half=bool(args.half), bufs=batch_bufs, **kw)
         if not res.converged:
             raise RuntimeError("batch did not converge")
         return res.sys_rounds.tolist(), [res.nnb[real]]
@@ -246,7 +247,8 @@ def run_batch(args, sf, torch, ctx):
     plain = timed(plain_per_system, False)
     log("batched seeded iteration: warm-up run, then leaf-bucket autotune at the converged radii")
     batched(True)
-    tuned = autotune.tune_batch(ctx, b, keys, xs, ys, zs, hb, tag="batch%d_t%d" % (b.nsys, T), use_cache=False)
+    tuned = autotune.tune_batch(ctx, b, keys, xs, ys, zs, hb, tag="batch%d_t%d" % (b.nsys, T), use_cache=False,
+                                half=bool(args.half))
     log("autotune: %s" % tuned)
     log("batched seeded iteration (graph)")
     best = timed(batched, True)
@@ -261,7 +263,8 @@ def run_batch(args, sf, torch, ctx):
            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
            "config": {"workload": "batch_%d_uniform_plummer" % b.nsys, "n_total": ntot, "n_padded": b.n_pad,
                       "sizes": "log-uniform [1e4, 1e6]", "target": T, "tol": 1,
-                      "cluster_size": tuned["cluster_size"], "leaf_bucket": tuned["leaf_bucket"]},
+                      "cluster_size": tuned["cluster_size"], "leaf_bucket": tuned["leaf_bucket"],
+                      "list": "half (each pair once, j > i)" if args.half else "full"},
            "batched_seeded_graph": best, "plain_per_system": plain, "batched_plain_graph": bplain,
            "seeded_per_system": sseed, "speedup_vs_plain_per_system": plain["ms"] / best["ms"],
            "autotune": tuned, "seed_training": {"pairs": int(feat.shape[0]), "seconds": train_s,
@@ -278,7 +281,7 @@ def main():
     ap.add_argument("--compress", type=int, default=1)
     ap.add_argument("--leaf-bucket", type=int, default=128)
     ap.add_argument("--cluster-size", type=int, default=8)
-    ap.add_argument("--half", type=int, default=0, help="1: half list (each pair once)")
+    ap.add_argument("--half", type=int, default=1, help="1: half list (each pair once), 0: full list")
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after warm-up, copy this many MiB once (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")

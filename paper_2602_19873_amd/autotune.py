@@ -44,11 +44,11 @@ def _load(path):
 
 
 def tune_batch(ctx, b, keys, x, y, z, h, tag: str = "", candidates=CANDIDATES, reps: int = 3,
-               cache_path: str | None = None, use_cache: bool = True) -> dict:
+               cache_path: str | None = None, use_cache: bool = True, half: bool = False) -> dict:
     """Returns {"cluster_size": cs, "leaf_bucket": bucket, "ms": {"cs<cs>_b<bucket>": median ms},
     "cached": bool}."""
     path = cache_path or default_cache_path()
-    key = cache_key(b.n_pad, tag)
+    key = cache_key(b.n_pad, tag + ("_half" if half else ""))
     db = _load(path) if use_cache else {}
     if use_cache and key in db:
         out = dict(db[key])
@@ -65,7 +65,7 @@ def tune_batch(ctx, b, keys, x, y, z, h, tag: str = "", candidates=CANDIDATES, r
             bbox = batch_build_clusters(ctx, b, x, y, z, h, bufs.get("bbox"), cluster_size=cs)
             nl = batch_build_nlist(ctx, b, keys, x, y, z, h, bbox, leaf_bucket=bucket, pool=bufs.get("pool"),
                                    ws=bufs.get("ws"), sc_info=bufs.get("sc_info"),
-                                   max_j_per_sc=bufs.get("max_j", 512), cluster_size=cs)
+                                   max_j_per_sc=bufs.get("max_j", 512), cluster_size=cs, half=half)
             rho, nnb = batch_pass(ctx, b, nl, x, y, z, h, rho=bufs.get("rho"), nnb=bufs.get("nnb"))
             e1.record(st)
             e1.synchronize()

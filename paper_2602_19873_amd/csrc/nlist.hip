@@ -118,7 +118,6 @@ struct TravArgs {
     const uint4 *cs_rec;
     uint32_t nslots;       // capacity of the slot arrays
     SegTable seg;          // batched systems (empty for one system)
-    int half;              // list only pairs with j > i
     uint32_t *list_j;      // staging: cap entries per super-cluster
     uint16_t *list_m;
     uint32_t *sc_nj, *sc_words;
@@ -163,14 +162,15 @@ __device__ __forceinline__ uint32_t pack4_16(uint64_t x) {
 // Bits 0, 4, 8 and 12 of x gathered into bits 0..3.
 __device__ __forceinline__ uint32_t pack4_4(uint32_t x) { return (((x & 0x1111u) * 0x1248u) >> 12) & 0xFu; }
 
-template <int CS>
+template <int CS, bool kHalf>
 __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
     using S = Shape<CS>;
     constexpr int kNsub = S::kNsub, kNreg = S::kNreg;
     __shared__ uint4 s_stack[kWavesPerBlock][kStackCap];
     const int lane = sfc_lane();
     const int w = threadIdx.x / kWave;
-    const uint32_t s = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
+    // wave-uniform: keep the super-cluster index (and all derived from it) scalar
+    const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w));
     if (s >= a.nsc) return;
     const int64_t n = a.n;
     // i particles; absent ones are put far away so that no test accepts them
@@ -187,45 +187,32 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
     }
     const uint32_t own_c0 = s * kNsub;  // first i-cluster of this super-cluster
     const uint32_t own_p0 = s * kScSize;  // and its first particle
-    const bool half = a.half != 0;
+    constexpr bool half = kHalf;
     const float4 empty_lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
     const float4 empty_hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
-    auto cbox = [&](uint32_t c, float4 &lo, float4 &hi) {
-        if (c < a.nclu) {
-            lo = a.bbox[2 * (size_t)c];
-            hi = a.bbox[2 * (size_t)c + 1];
-        } else {
-            lo = empty_lo;
-            hi = empty_hi;
-        }
-    };
-    // node tests: lane group g = lane / 8 tests the children against the box
-    // of super-cluster particles [8g, 8g + 8) (for CS = 16 of its i-cluster)
-    float4 glo, ghi;
-    {
-        const int g = lane >> 3;
-        if (CS == 8) {
-            cbox(own_c0 + g, glo, ghi);
-        } else if (CS == 4) {
-            float4 l2, h2;
-            cbox(own_c0 + 2 * g, glo, ghi);
-            cbox(own_c0 + 2 * g + 1, l2, h2);
-            box_union(glo, ghi, l2, h2);
-        } else {
-            cbox(own_c0 + (g >> 1), glo, ghi);
-        }
-    }
     // leaf tests: the i-cluster boxes this lane pairs with its j-cluster
     constexpr int kIbox = CS == 4 ? 4 : 1;
     float4 ilo[kIbox], ihi[kIbox];
 #pragma unroll
     for (int t = 0; t < kIbox; t++) {
-        const uint32_t ic = CS == 8 ? (lane >> 3) : (CS == 4 ? (lane >> 4) + 4 * t : ((lane >> 2) & 3));
-        cbox(own_c0 + ic, ilo[t], ihi[t]);
-        if (CS == 16 && lane >= 16) {
-            ilo[t] = empty_lo;
-            ihi[t] = empty_hi;
-        }
+        const uint32_t ic = own_c0 + (CS == 8 ? (lane >> 3) : (CS == 4 ? (lane >> 4) + 4 * t : ((lane >> 2) & 3)));
+        const bool v = ic < a.nclu && (CS != 16 || lane < 16);
+        ilo[t] = v ? a.bbox[2 * (size_t)ic] : empty_lo;
+        ihi[t] = v ? a.bbox[2 * (size_t)ic + 1] : empty_hi;
+    }
+    // node tests: lane group g = lane / 8 tests the children against the box
+    // of super-cluster particles [8g, 8g + 8) (for CS = 16 of its i-cluster)
+    float4 glo, ghi;
+    if (CS == 8) {
+        glo = ilo[0];
+        ghi = ihi[0];
+    } else {
+        const int g = lane >> 3;
+        const uint32_t c0 = own_c0 + (CS == 4 ? 2 * g : (g >> 1));
+        const bool v0 = c0 < a.nclu;
+        glo = v0 ? a.bbox[2 * (size_t)c0] : empty_lo;
+        ghi = v0 ? a.bbox[2 * (size_t)c0 + 1] : empty_hi;
+        if (CS == 4 && c0 + 1 < a.nclu) box_union(glo, ghi, a.bbox[2 * (size_t)c0 + 2], a.bbox[2 * (size_t)c0 + 3]);
     }
 
     // stack of node records {first, end, child count (0 = leaf), first child
@@ -285,8 +272,8 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                     lo_ = a.bbox[2 * cj];
                     hi_ = a.bbox[2 * cj + 1];
                 } else {
-                    lo_ = empty_lo;
-                    hi_ = empty_hi;
+                    lo_ = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
+                    hi_ = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
                 }
             };
             if (c0 <= c1) load_batch(c0, nx, ny, nz, nh, nlo, nhi);
@@ -336,6 +323,8 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                         const int src = jc * CS + jl;
                         const float xj = __shfl(px, src, 64), yj = __shfl(py, src, 64), zj = __shfl(pz, src, 64);
                         const float hj2 = __shfl(ph2, src, 64);
+                        // the tile of the j-cluster with itself: i != j, or j > i for a half list
+                        const bool diag_ok = half ? jl > il : jl != il;
 #pragma unroll
                         for (int c = 0; c < kNreg; c++) {
                             if ((cmask >> c) & 1u) {
@@ -345,7 +334,11 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                                 const float dxx = dx * dx;
                                 const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
                                 bool pr = d2 < fmaxf(ih2[c], hj2);
-                                if (self_c >= 0) pr = pr && keep(c, il, jl);
+                                if (half) {  // inside the super-cluster: i-clusters up to the j-cluster only
+                                    if (self_c >= 0) pr = pr && (c < self_c || (c == self_c && diag_ok));
+                                } else if (c == self_c) {
+                                    pr = pr && diag_ok;
+                                }
                                 if (sfc_ballot(pr)) mask |= 1u << c;
                             }
                         }
@@ -395,7 +388,11 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                                     const float dxx = dx * dx;
                                     const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
                                     bool p = d2 < fmaxf(ih2[c], hj2[t]);
-                                    if (self_c >= 0) p = p && keep(c, il, 4 * t + jq);
+                                    if (half) {
+                                        if (self_c >= 0) p = p && (c < self_c || (c == self_c && 4 * t + jq > il));
+                                    } else if (c == self_c) {
+                                        p = p && 4 * t + jq != il;
+                                    }
                                     pr = pr || p;
                                 }
                                 if (sfc_ballot(pr)) mask |= 1u << c;
@@ -478,7 +475,8 @@ __global__ __launch_bounds__(256) void k_encode(EncArgs a) {
     __shared__ uint32_t s_seg[kWavesPerBlock][kSegCap];
     const int lane = sfc_lane();
     const int w = threadIdx.x / kWave;
-    const uint32_t s = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
+    // wave-uniform: keep the super-cluster index (and all derived from it) scalar
+    const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w));
     if (s >= a.nsc) return;
     const uint32_t nj = a.sc_nj[s];
     const uint32_t off = a.sc_off[s];
@@ -679,7 +677,6 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     ta.cs_rec = ws.tree.cs_rec;
     ta.nslots = ws.tree.node_cap;
     ta.seg = seg;
-    ta.half = o.half;
     ta.list_j = ws.list_j;
     ta.list_m = ws.list_m;
     ta.sc_nj = ws.sc_nj;
@@ -687,12 +684,13 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     ta.status = ctx->d_status;
     const unsigned gb = blocks_for(nsc, kWavesPerBlock);
     prof_mark(ctx, kStageTraverse, false);
-    if (cs == 4)
-        k_traverse<4><<<gb, 256, 0, st>>>(ta);
-    else if (cs == 16)
-        k_traverse<16><<<gb, 256, 0, st>>>(ta);
-    else
-        k_traverse<8><<<gb, 256, 0, st>>>(ta);
+    if (cs == 4) {
+        if (o.half) k_traverse<4, true><<<gb, 256, 0, st>>>(ta); else k_traverse<4, false><<<gb, 256, 0, st>>>(ta);
+    } else if (cs == 16) {
+        if (o.half) k_traverse<16, true><<<gb, 256, 0, st>>>(ta); else k_traverse<16, false><<<gb, 256, 0, st>>>(ta);
+    } else {
+        if (o.half) k_traverse<8, true><<<gb, 256, 0, st>>>(ta); else k_traverse<8, false><<<gb, 256, 0, st>>>(ta);
+    }
     SFCNL_LAUNCHED(ctx);
     prof_mark(ctx, kStageTraverse, true);
     prof_mark(ctx, kStageEncode, false);

@@ -113,7 +113,8 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
     constexpr int kGroup = CS == 8 ? 8 : 4;   // lanes sharing an i-particle
     const int lane = sfc_lane();
     const int w = threadIdx.x / kWave;
-    const uint32_t s = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
+    // wave-uniform: keep the super-cluster index (and all derived from it) scalar
+    const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w));
     if (s >= a.nsc) return;
     const int64_t n = a.n;
     const int jl = lane & (kGroup - 1);
@@ -292,24 +293,62 @@ __device__ __forceinline__ void half_pair(float xj, float yj, float zj, float mj
     }
 }
 
+// Cross-lane sums inside groups of 8 or 16 consecutive lanes with DPP
+// (quad swaps, then the mirrored half row, then the mirrored row): every lane
+// of a group ends with the group total.
+template <int CTRL>
+__device__ __forceinline__ float dpp_f(float v) {
+    return __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), CTRL, 0xF, 0xF, false));
+}
+template <int CTRL>
+__device__ __forceinline__ int dpp_i(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, 0xF, 0xF, false);
+}
+template <int kLanes>
+__device__ __forceinline__ void group_sum(float &f, int &c) {
+    f += dpp_f<0xB1>(f);  // quad_perm [1, 0, 3, 2]
+    c += dpp_i<0xB1>(c);
+    f += dpp_f<0x4E>(f);  // quad_perm [2, 3, 0, 1]
+    c += dpp_i<0x4E>(c);
+    f += dpp_f<0x141>(f);  // row_half_mirror
+    c += dpp_i<0x141>(c);
+    if (kLanes == 16) {
+        f += dpp_f<0x140>(f);  // row_mirror
+        c += dpp_i<0x140>(c);
+    }
+}
+
+// Lane roles of the symmetric pass (the i-particles in the low lane bits, so
+// that a j-particle's sum over the i side stays inside a DPP row):
+//   CS = 8:  lane = 8 jl + il; register k holds i-particle 8k + il;
+//   CS = 4:  lane = 16 jl + 4q + il; register k holds i-particle 16k + 4q + il
+//            (i-cluster 4k + q);
+//   CS = 16: lane = 16 jq + il; register k holds i-particle 16k + il; the
+//            lane takes j-particles 4t + jq.
+template <int CS>
+__device__ __forceinline__ int ipart_sym(int k, int lane) {
+    return CS == 8 ? 8 * k + (lane & 7) : 16 * k + (lane & 15);
+}
+
 template <int CS, bool kCompress, bool kMass, bool kCount>
 __global__ __launch_bounds__(256) void k_pass_half(PassArgs a) {
     constexpr int kNsub = kScSize / CS;
     constexpr int kNreg = CS == 8 ? 8 : 4;
     constexpr int kNj = CS == 16 ? 4 : 1;
-    constexpr int kGroup = CS == 8 ? 8 : 4;   // lanes sharing an i-particle = low lane bits
+    constexpr int kIL = CS == 8 ? 8 : 16;  // lanes per j-particle (the i side, low bits)
     const int lane = sfc_lane();
     const int w = threadIdx.x / kWave;
-    const uint32_t s = xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w;
+    // wave-uniform: keep the super-cluster index (and all derived from it) scalar
+    const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w));
     if (s >= a.nsc) return;
     const int64_t n = a.n;
-    const int jl = lane & (kGroup - 1);
+    const int jq = CS == 8 ? lane >> 3 : lane >> 4;  // j-particle slot of the lane
 
     // i particles; absent ones are put far away (every distance overflows)
     float ix[kNreg], iy[kNreg], iz[kNreg], ih2[kNreg], ihinv[kNreg], im[kNreg];
 #pragma unroll
     for (int k = 0; k < kNreg; k++) {
-        const int64_t i = (int64_t)s * kScSize + ipart<CS>(k, lane);
+        const int64_t i = (int64_t)s * kScSize + ipart_sym<CS>(k, lane);
         const bool v = i < n;
         ix[k] = v ? a.x[i] : kFar;
         iy[k] = v ? a.y[i] : kFar;
@@ -346,6 +385,22 @@ __global__ __launch_bounds__(256) void k_pass_half(PassArgs a) {
         if ((uint32_t)lane < cnt) mv = CS == 4 ? (uint32_t)mshorts[b0 + lane] : (uint32_t)mbytes[b0 + lane];
         prevj = sfc_readlane(jv, (int)cnt - 1);
         jv += jbase;
+        // software pipeline: the next entry's j-particles load while the
+        // current entry's tiles run
+        float nx[kNj], ny[kNj], nz[kNj], nm[kNj], nh[kNj];
+        auto load_j = [&](uint32_t cjn) {
+#pragma unroll
+            for (int t = 0; t < kNj; t++) {
+                const int64_t q = (int64_t)cjn * CS + (CS == 16 ? 4 * t + jq : jq);
+                const bool vj = q < n;
+                nx[t] = vj ? a.x[q] : kFar;
+                ny[t] = vj ? a.y[q] : kFar;
+                nz[t] = vj ? a.z[q] : kFar;
+                nm[t] = kMass ? (vj ? a.m[q] : 0.0f) : 1.0f;
+                nh[t] = vj ? a.h[q] : -1.0f;
+            }
+        };
+        load_j(sfc_readlane(jv, 0));
         for (uint32_t e = 0; e < cnt; e++) {
             const uint32_t mk = sfc_readlane(mv, (int)e);
             const uint32_t cj = sfc_readlane(jv, (int)e);
@@ -354,64 +409,60 @@ __global__ __launch_bounds__(256) void k_pass_half(PassArgs a) {
             int64_t jp[kNj];
 #pragma unroll
             for (int t = 0; t < kNj; t++) {
-                jp[t] = (int64_t)cj * CS + (CS == 16 ? 4 * t + jl : jl);
-                const bool vj = jp[t] < n;
-                xj[t] = vj ? a.x[jp[t]] : kFar;
-                yj[t] = vj ? a.y[jp[t]] : kFar;
-                zj[t] = vj ? a.z[jp[t]] : kFar;
-                mj[t] = kMass ? (vj ? a.m[jp[t]] : 0.0f) : 1.0f;
-                const float hh = vj ? a.h[jp[t]] : 1.0f;
-                hj2[t] = vj ? hh * hh : -1.0f;
-                hjinv[t] = 1.0f / hh;
+                jp[t] = (int64_t)cj * CS + (CS == 16 ? 4 * t + jq : jq);
+                xj[t] = nx[t];
+                yj[t] = ny[t];
+                zj[t] = nz[t];
+                mj[t] = nm[t];
+                const bool vj = nh[t] > 0.0f;  // absent: -1 (NaN padding never pairs)
+                hj2[t] = vj ? nh[t] * nh[t] : -1.0f;
+                hjinv[t] = vj ? 1.0f / nh[t] : 1.0f;
                 accj[t] = 0.0f;
                 cntj[t] = 0;
             }
+            if (e + 1 < cnt) load_j(sfc_readlane(jv, (int)e + 1));
             // inside the super-cluster only j > i counts
             const int self_c = (cj >= own_c0 && cj < own_c0 + kNsub) ? (int)(cj - own_c0) : -1;
             auto keep = [&](int ci, int ipos, int jpos) {
                 return self_c < 0 || ci < self_c || (ci == self_c && jpos > ipos);
             };
             if (CS == 8) {
-                const int il = lane >> 3;
+                const int il = lane & 7;
 #pragma unroll
                 for (int c = 0; c < kNreg; c++)
                     if ((mk >> c) & 1u)
                         half_pair<CS>(xj[0], yj[0], zj[0], mj[0], hj2[0], hjinv[0], ix[c], iy[c], iz[c], im[c],
-                                      ih2[c], ihinv[c], keep(c, il, jl), acc[c], cnt_nb[c], accj[0], cntj[0]);
+                                      ih2[c], ihinv[c], keep(c, il, jq), acc[c], cnt_nb[c], accj[0], cntj[0]);
             } else if (CS == 4) {
-                const int il = (lane >> 2) & 3, q = lane >> 4;
+                const int il = lane & 3, q = (lane >> 2) & 3;
 #pragma unroll
                 for (int k = 0; k < kNreg; k++)
                     if ((mk >> (4 * k)) & 0xFu)
                         half_pair<CS>(xj[0], yj[0], zj[0], mj[0], hj2[0], hjinv[0], ix[k], iy[k], iz[k], im[k],
-                                      ih2[k], ihinv[k], keep(4 * k + q, il, jl), acc[k], cnt_nb[k], accj[0],
+                                      ih2[k], ihinv[k], keep(4 * k + q, il, jq), acc[k], cnt_nb[k], accj[0],
                                       cntj[0]);
             } else {
-                const int il = lane >> 2;
+                const int il = lane & 15;
 #pragma unroll
                 for (int c = 0; c < kNreg; c++)
                     if ((mk >> c) & 1u) {
 #pragma unroll
                         for (int t = 0; t < 4; t++)
                             half_pair<CS>(xj[t], yj[t], zj[t], mj[t], hj2[t], hjinv[t], ix[c], iy[c], iz[c], im[c],
-                                          ih2[c], ihinv[c], keep(c, il, 4 * t + jl), acc[c], cnt_nb[c], accj[t],
+                                          ih2[c], ihinv[c], keep(c, il, 4 * t + jq), acc[c], cnt_nb[c], accj[t],
                                           cntj[t]);
                     }
             }
-            // j side: sum over the lanes sharing each j-particle (the high lane
-            // bits), then one atomic per j-particle
+            // j side: sum over the i lanes of each j-particle (one DPP row
+            // group), then one atomic per j-particle
             bool any = false;
 #pragma unroll
             for (int t = 0; t < kNj; t++) any = any || cntj[t] != 0;
             if (sfc_ballot(any)) {
 #pragma unroll
                 for (int t = 0; t < kNj; t++) {
-#pragma unroll
-                    for (int d = kGroup; d < kWave; d <<= 1) {
-                        accj[t] += __shfl_xor(accj[t], d, 64);
-                        cntj[t] += __shfl_xor(cntj[t], d, 64);
-                    }
-                    if (lane < kGroup && cntj[t] != 0) {
+                    group_sum<kIL>(accj[t], cntj[t]);
+                    if ((lane & (kIL - 1)) == 0 && cntj[t] != 0) {
                         atomicAdd(&a.rho[jp[t]], accj[t]);
                         if (kCount) atomicAdd(&a.nnb[jp[t]], cntj[t]);
                     }
@@ -419,12 +470,13 @@ __global__ __launch_bounds__(256) void k_pass_half(PassArgs a) {
             }
         }
     }
-    // i side: sum the partials of each i-particle (the kGroup lanes sharing
-    // it), then one atomic per particle
+    // i side: sum the partials of each i-particle over the j lanes (the high
+    // lane bits), then one atomic per particle; the lane with j slot k takes
+    // register k
 #pragma unroll
     for (int k = 0; k < kNreg; k++) {
 #pragma unroll
-        for (int d = 1; d < kGroup; d <<= 1) {
+        for (int d = kIL; d < kWave; d <<= 1) {
             acc[k] += __shfl_xor(acc[k], d, 64);
             cnt_nb[k] += __shfl_xor(cnt_nb[k], d, 64);
         }
@@ -433,10 +485,10 @@ __global__ __launch_bounds__(256) void k_pass_half(PassArgs a) {
     int nb = cnt_nb[0];
 #pragma unroll
     for (int k = 1; k < kNreg; k++) {
-        r = jl == k ? acc[k] : r;
-        nb = jl == k ? cnt_nb[k] : nb;
+        r = jq == k ? acc[k] : r;
+        nb = jq == k ? cnt_nb[k] : nb;
     }
-    const int64_t io = (int64_t)s * kScSize + ipart<CS>(jl, lane);
+    const int64_t io = (int64_t)s * kScSize + ipart_sym<CS>(jq, lane);
     if (io < n && nb != 0) {
         atomicAdd(&a.rho[io], r);
         if (kCount) atomicAdd(&a.nnb[io], nb);
