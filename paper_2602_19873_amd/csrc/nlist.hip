@@ -335,7 +335,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                                 const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
                                 bool pr = d2 < fmaxf(ih2[c], hj2);
                                 if (half) {  // inside the super-cluster: i-clusters up to the j-cluster only
-                                    if (self_c >= 0) pr = pr && (c < self_c || (c == self_c && diag_ok));
+                                    if (self_c >= 0) pr = pr && keep(c, il, jl);
                                 } else if (c == self_c) {
                                     pr = pr && diag_ok;
                                 }
