@@ -105,7 +105,7 @@ def read_traffic(kernel, n):
             if line.startswith("traffic "):
                 kv = dict(t.split("=", 1) for t in line.split()[1:])
                 rec[kv["kernel"]] = kv
-    kv = rec.get(kernel)
+    kv = rec.get(kernel.replace(" ", ""))
     if not kv or int(kv["n"]) != n:
         return None
     if kv["source_sha"] != source_sha(os.path.join(ROOT, "paper_2602_19873_amd", "csrc", kv["source"])):
@@ -370,7 +370,10 @@ def main():
         stages[name] = d
     dom = max((k for k in stages if "bound" in stages[k]), key=lambda k: stages[k]["ms"])
     dd = stages[dom]
-    kernel_of = {"traverse": ("k_traverse", "nlist.hip"), "pass": ("k_pass", "pass.hip")}
+    hb = "true" if args.half else "false"
+    kernel_of = {"traverse": ("k_traverse<%d, %s>" % (args.cluster_size, hb), "nlist.hip"),
+                 "pass": ("k_pass_half<%d, true, false, true>" % args.cluster_size if args.half
+                          else "k_pass<%d, true, false, true>" % args.cluster_size, "pass.hip")}
     traffic = read_traffic(kernel_of[dom][0], n) if dom in kernel_of else None
     roofline = {"kernel": kernel_of.get(dom, (dom,))[0], "bound": dd["bound"], "achieved": dd["achieved"],
                 "peak": dd["peak"], "unit": dd["unit"], "frac": dd["frac"], "traffic": traffic,
