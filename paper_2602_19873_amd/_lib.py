@@ -8,7 +8,8 @@ import ctypes as C
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libsfcnl.so")
+# SFCNL_LIB selects another build of the same library (for A/B timing)
+LIB_PATH = os.environ.get("SFCNL_LIB") or os.path.join(HERE, "libsfcnl.so")
 
 OK = 0
 E_ARG = -1

@@ -202,7 +202,7 @@ __device__ __forceinline__ int sfc_lane() { return (int)__lane_id(); }
 
 __device__ __forceinline__ uint64_t sfc_lt_mask() { return (1ull << sfc_lane()) - 1ull; }
 
-__device__ __forceinline__ uint64_t sfc_ballot(bool p) { return (uint64_t)__ballot(p); }
+__device__ __forceinline__ uint64_t sfc_ballot(bool p) { return __builtin_amdgcn_ballot_w64(p); }
 
 __device__ __forceinline__ int sfc_popc(uint64_t v) { return __popcll(v); }
 
