@@ -318,13 +318,15 @@ def test_repeat_is_deterministic(env):
 
 
 @pytest.mark.slow
-def test_uniform_2m_sampled(env):
-    """Full 2,097,152-particle workload in the benchmark's configuration:
-    exact lists for sampled super-clusters (oracle brute force over all
+@pytest.mark.parametrize("half", [True, False])
+def test_uniform_2m_sampled(env, half):
+    """Full 2,097,152-particle workload in the benchmark's configuration
+    (cluster size 8, leaf bucket 128, compressed; the benchmark times the half
+    list): exact lists for sampled super-clusters (oracle brute force over all
     particles), exact counts and densities for all particles (oracle cell list)."""
     sf, ctx, torch = env
     s = workloads.make_config("uniform_2m_varied")
-    g = _run(env, s)
+    g = _run(env, s, leaf_bucket=128, half=half)
     _say("gpu done; oracle keys and order")
     keys = oracle.hilbert_keys(s.x, s.y, s.z, s.box)
     perm = oracle.sfc_order(keys)
@@ -333,7 +335,7 @@ def test_uniform_2m_sampled(env):
     nsc = (s.n + 63) // 64
     ids = np.unique(np.concatenate([[0, nsc - 1], np.random.default_rng(1).integers(0, nsc, 14)]))
     _say("oracle brute-force lists for %d super-clusters" % len(ids))
-    so, sj, sm = oracle.cluster_list(xs, ys, zs, hs, 8, "brute", sc_ids=ids)
+    so, sj, sm = oracle.cluster_list(xs, ys, zs, hs, 8, "brute", sc_ids=ids, half=half)
     _say("compare lists, then oracle densities")
     info = g["sc_info"]
     for k, sc in enumerate(ids):
@@ -347,5 +349,6 @@ def test_uniform_2m_sampled(env):
     np.testing.assert_array_equal(g["nnb"], nnb)
     rel = np.abs(g["rho"].astype(np.float64) - rho) / rho
     assert rel.max() <= RHO_RTOL, rel.max()
-    # full (not half) list under max(h_i, h_j): ~190 j-clusters per super-cluster
-    assert g["nl"].bytes_per_particle() < 4.25
+    # under max(h_i, h_j): ~190 j-clusters per super-cluster in the full list,
+    # ~97 in the half list (each pair once)
+    assert g["nl"].bytes_per_particle() < (2.4 if half else 4.25)
