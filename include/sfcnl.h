@@ -184,7 +184,17 @@ int nlist_decode(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, const
  *                  (lo_i, hi_i), h' = (lo_i + hi_i) / 2 (or hi_i / 2 while
  *                  lo_i = 0, 2 lo_i while hi_i is unbounded).
  * Each round: build_clusters, build_nlist, nlist_pass, update; it stops when no
- * particle moved, after max_iters rounds, or on an error.
+ * particle moved, after max_iters rounds, or on an error. The first round of a
+ * call counts every particle with the requested list form; later rounds
+ * rebuild full lists only for the super-clusters where some radius moved in
+ * the previous round (n_i depends on h_i alone, so the other counts cannot
+ * change and the rounds, radii and counts are those of recounting
+ * everything), and a converged run that needed more than one round ends with
+ * one list build of every super-cluster in the requested form. The workspace
+ * is build_nlist_workspace(n, nl_opts) bytes. If only that closing build does
+ * not fit, SFCNL_E_CAPACITY comes back with h_stats->unconverged == 0: radii,
+ * d_rho and d_nnb are final and the list can be built with build_nlist after
+ * growing the buffers.
  * Arrays are in SFC order (sfc_sort + sfc_gather). d_h is updated in place.
  * d_bracket [2n] holds {lo_i, hi_i}; it is initialised to {0, +inf} unless
  * opts->resume is set, which continues an interrupted run (for instance after

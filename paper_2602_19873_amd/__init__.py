@@ -295,12 +295,19 @@ def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, m
         total += st.iters
         moved += st.moved
         if rc == _lib.E_CAPACITY:
-            # the round that overflowed did not update h (only completed
-            # rounds are counted): run it again with room
             if st.max_nj > max_j_per_sc:
                 max_j_per_sc = int(st.max_nj)
             if st.used_bytes > pool.numel() * 4:
                 pool = e(st.used_bytes // 4 + 1024, torch.int32)
+            if st.unconverged == 0 and st.iters > 0:
+                # converged, only the closing list of the final radii did not
+                # fit: build it with room (radii, rho and nnb are final)
+                build_clusters(ctx, x, y, z, h, cluster_size, bbox)
+                nl = build_nlist(ctx, keys, x, y, z, h, bbox, compress, leaf_bucket, max_j_per_sc, cluster_size,
+                                 pool=pool, ws=ws, sc_info=sc_info, half=half)
+                return HIterResult(total, 0, True, nl, rho, nnb, moved)
+            # the round that overflowed did not update h (only completed
+            # rounds are counted): run it again with room
             resume = 1
             continue
         nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, st.used_bytes, st.max_nj,
@@ -642,6 +649,14 @@ def batch_h_iterate(ctx: Context, b: Batch, keys, x, y, z, h, target: int = 100,
                 B["max_j"] = int(st.max_nj)
             if st.used_bytes > B["pool"].numel() * 4:
                 B["pool"] = e(st.used_bytes // 4 + 1024, torch.int32)
+            if st.unconverged == 0 and st.iters > 0:
+                # converged, only the closing list did not fit: build it with room
+                batch_build_clusters(ctx, b, x, y, z, h, B["bbox"], cluster_size)
+                nl = batch_build_nlist(ctx, b, keys, x, y, z, h, B["bbox"], compress, leaf_bucket, B["max_j"],
+                                       pool=B["pool"], ws=B["ws"], sc_info=B["sc_info"], cluster_size=cluster_size,
+                                       half=half)
+                B["pool"], B["max_j"] = nl.pool, nl.max_j_per_sc
+                return BatchIterResult(total, 0, True, rounds, moved, nl.used_bytes, B["rho"], B["nnb"])
             resume = 1
             continue
         conv = rc == 0

@@ -40,7 +40,7 @@ __global__ __launch_bounds__(256) void k_seed_apply(int64_t n, float *__restrict
 __global__ __launch_bounds__(256) void k_h_update(int64_t n, const int32_t *__restrict__ nnb, float *__restrict__ h,
                                                   float2 *__restrict__ br, int target, int tol,
                                                   const float *__restrict__ proposal, uint32_t *status, SegTable seg,
-                                                  uint32_t *sys_moved) {
+                                                  uint32_t *sys_moved, uint32_t *sc_active) {
     if (status[kStInputErr] | status[kStPoolOverflow] | status[kStScratch] | status[kStTree]) return;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool moved = false;
@@ -88,6 +88,9 @@ __global__ __launch_bounds__(256) void k_h_update(int64_t n, const int32_t *__re
         atomicAdd(&status[kStUnconverged], (uint32_t)sfc_popc(m));
         if (sys_moved) atomicAdd(&sys_moved[sy], (uint32_t)sfc_popc(m));
     }
+    // the next round recounts only super-clusters where a radius moved (a
+    // wave's 64 particles are one super-cluster)
+    if (sc_active && sfc_lane() == 0 && i < n) sc_active[i / kScSize] = m != 0;
 }
 
 }  // namespace
@@ -115,8 +118,13 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
         S.unconverged = 0;
         return SFCNL_OK;
     }
-    if (!d_keys || !d_x || !d_y || !d_z || !d_h || !d_bracket || !d_bbox || !d_rho || !d_nnb)
+    if (!d_keys || !d_x || !d_y || !d_z || !d_h || !d_bracket || !d_bbox || !d_rho || !d_nnb || !d_ws ||
+        !d_sc_info || (!d_pool && pool_bytes))
         return set_err(ctx, SFCNL_E_ARG, "sfcnl_h_iterate: null pointer");
+    size_t need;
+    if (build_nlist_workspace(n, nl_opts, &need) != SFCNL_OK)
+        return set_err(ctx, SFCNL_E_ARG, "sfcnl_h_iterate: bad list options");
+    if (ws_bytes < need) return set_err(ctx, SFCNL_E_ARG, "sfcnl_h_iterate: workspace %zu < %zu bytes", ws_bytes, need);
     if (seed && (!seed->d_params || !seed->d_feat || !seed->d_delta || !(seed->box_edge > 0.0f) ||
                  (seed->mode != SFCNL_SEED_AFTER_FIRST && seed->mode != SFCNL_SEED_BEFORE_FIRST)))
         return set_err(ctx, SFCNL_E_ARG, "sfcnl_h_iterate: incomplete seed");
@@ -135,17 +143,29 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
             SFCNL_LAUNCHED(ctx);
         }
     }
+    // The first round counts every particle with the requested list form;
+    // later rounds rebuild full lists only for super-clusters where a radius
+    // moved (the counts of the others cannot change: n_i depends on h_i only),
+    // and a converged run ends with one list build in the requested form.
+    sfcnl_nlist_opts it_nl = *nl_opts;
+    it_nl.half = 0;
+    uint32_t *act = nlist_ws_active(d_ws, n, it_nl, 1);
+    bool list_final = false;
     for (int it = 0; it < it_opts->max_iters; it++) {
-        int rc = build_clusters(ctx, n, d_x, d_y, d_z, d_h, nl_opts->cluster_size, d_bbox);
+        const bool first = it == 0;
+        const sfcnl_nlist_opts &o = first ? *nl_opts : it_nl;
+        const uint32_t *active = first ? nullptr : act;
+        int rc = clusters_impl(ctx, n, d_x, d_y, d_z, d_h, o.cluster_size, d_bbox, SegTable{});
         if (rc) return rc;
-        rc = build_nlist(ctx, n, d_keys, d_x, d_y, d_z, d_h, d_bbox, nl_opts, d_ws, ws_bytes, d_sc_info, d_pool,
-                         pool_bytes, &S.used_bytes, &S.max_nj);
+        rc = nlist_build_impl(ctx, n, d_keys, d_x, d_y, d_z, d_h, d_bbox, o, d_ws, ws_bytes, d_sc_info, d_pool,
+                              pool_bytes, SegTable{}, true, &S.used_bytes, &S.max_nj, active);
         if (rc) return rc;
-        rc = nlist_pass(ctx, n, nl_opts->cluster_size, nl_opts->compress, nl_opts->half, d_sc_info, d_pool, d_x, d_y,
-                        d_z, d_h, d_m, d_rho, d_nnb);
+        rc = pass_impl(ctx, n, o.cluster_size, o.compress, o.half, d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho,
+                       d_nnb, SegTable{}, active);
         if (rc) return rc;
+        list_final = first;
         const float *proposal = nullptr;
-        if (seed && seed->mode == SFCNL_SEED_AFTER_FIRST && it == 0) {  // learned step from the first counts
+        if (seed && seed->mode == SFCNL_SEED_AFTER_FIRST && first) {  // learned step from the first counts
             rc = sfcnl_hseed_features(ctx, n, d_keys, d_x, d_y, d_z, d_h, d_nnb, seed->box_edge, it_opts->target,
                                       seed->d_feat);
             if (rc) return rc;
@@ -156,7 +176,7 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
         rc = fill_u32(ctx, ctx->d_status + kStUnconverged, 1, 0);
         if (rc) return rc;
         k_h_update<<<blocks_for(n, 256), 256, 0, strm>>>(n, d_nnb, d_h, br, it_opts->target, it_opts->tol, proposal,
-                                                        ctx->d_status, SegTable{}, nullptr);
+                                                        ctx->d_status, SegTable{}, nullptr, act);
         SFCNL_LAUNCHED(ctx);
         SFCNL_HIP(ctx, hipMemcpyAsync(ctx->h_status + kStUnconverged, ctx->d_status + kStUnconverged,
                                       sizeof(uint32_t), hipMemcpyDeviceToHost, strm));
@@ -164,7 +184,16 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
         S.iters = it + 1;
         S.unconverged = ctx->h_status[kStUnconverged];
         S.moved += S.unconverged;
-        if (S.unconverged == 0) return SFCNL_OK;
+        if (S.unconverged == 0) {
+            if (!list_final) {  // the list of the final radii, every super-cluster, requested form
+                rc = clusters_impl(ctx, n, d_x, d_y, d_z, d_h, nl_opts->cluster_size, d_bbox, SegTable{});
+                if (rc) return rc;
+                rc = nlist_build_impl(ctx, n, d_keys, d_x, d_y, d_z, d_h, d_bbox, *nl_opts, d_ws, ws_bytes,
+                                      d_sc_info, d_pool, pool_bytes, SegTable{}, true, &S.used_bytes, &S.max_nj);
+                if (rc) return rc;
+            }
+            return SFCNL_OK;
+        }
     }
     return set_err(ctx, SFCNL_E_NOCONV, "sfcnl_h_iterate: %lld particles unconverged after %d rounds",
                    (long long)S.unconverged, it_opts->max_iters);
@@ -196,17 +225,20 @@ struct RoundArgs {
     int32_t *nnb;
 };
 
-// Enqueues one round on ctx->stream; `seed` adds the learned first step.
-int enqueue_round(sfcnl_ctx ctx, const RoundArgs &r, const sfcnl_hseed *seed) {
+// Enqueues one round on ctx->stream with list options `o`; `seed` adds the
+// learned first step; `active` (nullable) restricts the list build and the
+// pass to flagged super-clusters; `act_out` receives the next round's flags.
+int enqueue_round(sfcnl_ctx ctx, const RoundArgs &r, const sfcnl_nlist_opts &o, const sfcnl_hseed *seed,
+                  const uint32_t *active, uint32_t *act_out) {
     const SegTable seg = seg_of(r.b);
     const int64_t n = r.b->n_pad;
-    int rc = clusters_impl(ctx, n, r.x, r.y, r.z, r.h, r.nl->cluster_size, r.bbox, seg);
+    int rc = clusters_impl(ctx, n, r.x, r.y, r.z, r.h, o.cluster_size, r.bbox, seg);
     if (rc) return rc;
-    rc = nlist_build_impl(ctx, n, r.keys, r.x, r.y, r.z, r.h, r.bbox, *r.nl, r.ws, r.ws_bytes, r.sc_info, r.pool,
-                          r.pool_bytes, seg, false, nullptr, nullptr);
+    rc = nlist_build_impl(ctx, n, r.keys, r.x, r.y, r.z, r.h, r.bbox, o, r.ws, r.ws_bytes, r.sc_info, r.pool,
+                          r.pool_bytes, seg, false, nullptr, nullptr, active);
     if (rc) return rc;
-    rc = pass_impl(ctx, n, r.nl->cluster_size, r.nl->compress, r.nl->half, r.sc_info, r.pool, r.x, r.y, r.z, r.h,
-                   r.m, r.rho, r.nnb, seg);
+    rc = pass_impl(ctx, n, o.cluster_size, o.compress, o.half, r.sc_info, r.pool, r.x, r.y, r.z, r.h, r.m, r.rho,
+                   r.nnb, seg, active);
     if (rc) return rc;
     const float *proposal = nullptr;
     if (seed) {
@@ -221,7 +253,7 @@ int enqueue_round(sfcnl_ctx ctx, const RoundArgs &r, const sfcnl_hseed *seed) {
     rc = fill_u32(ctx, r.b->d_sys_moved, r.b->nsys, 0);
     if (rc) return rc;
     k_h_update<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, r.nnb, r.h, r.br, r.it->target, r.it->tol, proposal,
-                                                           ctx->d_status, seg, r.b->d_sys_moved);
+                                                           ctx->d_status, seg, r.b->d_sys_moved, act_out);
     SFCNL_LAUNCHED(ctx);
     SFCNL_HIP(ctx, hipMemcpyAsync(ctx->h_status, ctx->d_status, kStWords * sizeof(uint32_t), hipMemcpyDeviceToHost,
                                   ctx->stream));
@@ -315,15 +347,27 @@ extern "C" int sfcnl_batch_h_iterate(sfcnl_ctx ctx, sfcnl_batch b, const uint64_
             SFCNL_LAUNCHED(ctx);
         }
     }
+    // Round 0 counts every particle with the requested list form; later
+    // rounds rebuild full lists only for super-clusters where a radius moved
+    // (the same rounds, and so the same radii, as recounting everything); a
+    // converged run ends with one list build in the requested form.
+    sfcnl_nlist_opts it_nl = *nl_opts;
+    it_nl.half = 0;
+    uint32_t *act = nlist_ws_active(d_ws, b->n_pad, it_nl, b->nsys);
+    bool list_final = false;
     GraphHolder gh;
     std::vector<char> active((size_t)b->nsys, 1);
     for (int it = 0; it < it_opts->max_iters; it++) {
         const sfcnl_hseed *sd = (seed && seed->mode == SFCNL_SEED_AFTER_FIRST && it == 0) ? seed : nullptr;
-        if (use_graph && !sd) {
+        list_final = it == 0;
+        if (it == 0) {
+            int rc = enqueue_round(ctx, r, *nl_opts, sd, nullptr, act);
+            if (rc) return rc;
+        } else if (use_graph) {
             if (!gh.e) {
                 ctx->prof_slots = 0;  // no event records inside the graph
                 SFCNL_HIP(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-                int rc = enqueue_round(ctx, r, nullptr);
+                int rc = enqueue_round(ctx, r, it_nl, nullptr, act, act);
                 hipGraph_t g = nullptr;
                 hipError_t e = hipStreamEndCapture(st, &g);
                 gh.g = g;
@@ -334,7 +378,7 @@ extern "C" int sfcnl_batch_h_iterate(sfcnl_ctx ctx, sfcnl_batch b, const uint64_
             }
             SFCNL_HIP(ctx, hipGraphLaunch(gh.e, st));
         } else {
-            int rc = enqueue_round(ctx, r, sd);
+            int rc = enqueue_round(ctx, r, it_nl, nullptr, act, act);
             if (rc) return rc;
         }
         SFCNL_HIP(ctx, hipStreamSynchronize(st));
@@ -362,7 +406,17 @@ extern "C" int sfcnl_batch_h_iterate(sfcnl_ctx ctx, sfcnl_batch b, const uint64_
             for (int s = 0; s < b->nsys; s++)
                 if (it == 0 || active[s]) h_sys_rounds[s] = it + 1;
         for (int s = 0; s < b->nsys; s++) active[s] = b->h_sys_moved[s] != 0;
-        if (S.unconverged == 0) return SFCNL_OK;
+        if (S.unconverged == 0) {
+            if (!list_final) {  // the list of the final radii, every super-cluster, requested form
+                const SegTable seg = seg_of(b);
+                int rc = clusters_impl(ctx, b->n_pad, d_x, d_y, d_z, d_h, nl_opts->cluster_size, d_bbox, seg);
+                if (rc) return rc;
+                rc = nlist_build_impl(ctx, b->n_pad, d_keys, d_x, d_y, d_z, d_h, d_bbox, *nl_opts, d_ws, ws_bytes,
+                                      d_sc_info, d_pool, pool_bytes, seg, true, &S.used_bytes, &S.max_nj);
+                if (rc) return rc;
+            }
+            return SFCNL_OK;
+        }
     }
     return set_err(ctx, SFCNL_E_NOCONV, "sfcnl_batch_h_iterate: %lld particles unconverged after %d rounds",
                    (long long)S.unconverged, it_opts->max_iters);

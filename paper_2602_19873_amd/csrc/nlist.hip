@@ -118,6 +118,7 @@ struct TravArgs {
     const uint4 *cs_rec;
     uint32_t nslots;       // capacity of the slot arrays
     SegTable seg;          // batched systems (empty for one system)
+    const uint32_t *active;  // nullable: super-clusters with active[s] == 0 get an empty list
     uint32_t *list_j;      // staging: cap entries per super-cluster
     uint16_t *list_m;
     uint32_t *sc_nj, *sc_words;
@@ -172,6 +173,13 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
     // wave-uniform: keep the super-cluster index (and all derived from it) scalar
     const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w));
     if (s >= a.nsc) return;
+    if (a.active && !a.active[s]) {  // restricted rebuild: this super-cluster keeps no list
+        if (sfc_lane() == 0) {
+            a.sc_nj[s] = 0;
+            a.sc_words[s] = 0;
+        }
+        return;
+    }
     const int64_t n = a.n;
     // i particles; absent ones are put far away so that no test accepts them
     float ix[kNreg], iy[kNreg], iz[kNreg], ih2[kNreg];
@@ -567,6 +575,7 @@ struct NlistWs {
     uint32_t *list_j;
     uint16_t *list_m;
     uint32_t *sc_nj, *sc_words, *sc_off;
+    uint32_t *sc_active;  // per super-cluster flags for restricted rebuilds (h-iteration)
     void *scan_tmp;
 };
 
@@ -578,6 +587,7 @@ void carve_nlist(Carver &cv, NlistWs &ws, int64_t n, const sfcnl_nlist_opts &o, 
     ws.sc_nj = cv.take<uint32_t>(nsc);
     ws.sc_words = cv.take<uint32_t>(nsc);
     ws.sc_off = cv.take<uint32_t>((size_t)nsc + 1);
+    ws.sc_active = cv.take<uint32_t>(nsc);
     ws.scan_tmp = cv.take<char>(scan_tmp_bytes(nsc));
 }
 
@@ -641,10 +651,19 @@ int sfcnl::read_status(sfcnl_ctx ctx) {
     return SFCNL_OK;
 }
 
+uint32_t *sfcnl::nlist_ws_active(void *d_ws, int64_t n, const sfcnl_nlist_opts &o, int nsys) {
+    Carver cv{reinterpret_cast<char *>(d_ws), 0};
+    NlistWs ws;
+    carve_nlist(cv, ws, n, o, nsys);
+    return ws.sc_active;
+}
+
 int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_x, const float *d_y,
                             const float *d_z, const float *d_h, const float *d_bbox, const sfcnl_nlist_opts &o,
                             void *d_ws, size_t ws_bytes, uint32_t *d_sc_info, uint32_t *d_pool, size_t pool_bytes,
-                            const SegTable &seg, bool readback, size_t *h_used_bytes, int64_t *h_max_nj) {
+                            const SegTable &seg, bool readback, size_t *h_used_bytes, int64_t *h_max_nj,
+                            const uint32_t *active) {
+    if (active && o.half) return set_err(ctx, SFCNL_E_ARG, "build_nlist: a restricted rebuild needs the full list");
     const int nsys = seg.on() ? seg.nsys : 1;
     Carver cv{reinterpret_cast<char *>(d_ws), 0};
     NlistWs ws;
@@ -677,6 +696,7 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     ta.cs_rec = ws.tree.cs_rec;
     ta.nslots = ws.tree.node_cap;
     ta.seg = seg;
+    ta.active = active;
     ta.list_j = ws.list_j;
     ta.list_m = ws.list_m;
     ta.sc_nj = ws.sc_nj;

@@ -65,6 +65,7 @@ struct PassArgs {
     float *rho;
     int32_t *nnb;
     SegTable seg;  // batched systems: list indices are relative to the system's first cluster
+    const uint32_t *active;  // nullable: skip super-clusters with active[s] == 0 (full pass)
 };
 
 // i-particle held in register k by a lane (the traversal's lane roles):
@@ -115,7 +116,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
     const int w = threadIdx.x / kWave;
     // wave-uniform: keep the super-cluster index (and all derived from it) scalar
     const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w));
-    if (s >= a.nsc) return;
+    if (s >= a.nsc || (a.active && !a.active[s])) return;
     const int64_t n = a.n;
     const int jl = lane & (kGroup - 1);
 
@@ -575,9 +576,10 @@ using namespace sfcnl;
 
 int sfcnl::pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, int half, const uint32_t *d_sc_info,
                      const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z, const float *d_h,
-                     const float *d_m, float *d_rho, int32_t *d_nnb, const SegTable &seg) {
+                     const float *d_m, float *d_rho, int32_t *d_nnb, const SegTable &seg, const uint32_t *active) {
+    if (active && half) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: a restricted pass needs the full list");
     PassArgs a{n, (uint32_t)((n + kScSize - 1) / kScSize), d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb,
-               seg};
+               seg, active};
     const unsigned g = blocks_for(a.nsc, kWavesPerBlock);
     hipStream_t st = ctx->stream;
     const int variant = (compress ? 4 : 0) | (d_m ? 2 : 0) | (d_nnb ? 1 : 0);
