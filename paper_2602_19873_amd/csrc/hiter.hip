@@ -39,8 +39,9 @@ __global__ __launch_bounds__(256) void k_seed_apply(int64_t n, float *__restrict
 // particles are one super-cluster, hence one system).
 __global__ __launch_bounds__(256) void k_h_update(int64_t n, const int32_t *__restrict__ nnb, float *__restrict__ h,
                                                   float2 *__restrict__ br, int target, int tol,
-                                                  const float *__restrict__ proposal, uint32_t *status, SegTable seg,
-                                                  uint32_t *sys_moved, uint32_t *sc_active) {
+                                                  const float *__restrict__ proposal, const uint32_t *status,
+                                                  SegTable seg, uint32_t *sys_moved, uint32_t *sc_moved,
+                                                  uint8_t *p_moved) {
     if (status[kStInputErr] | status[kStPoolOverflow] | status[kStScratch] | status[kStTree]) return;
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     bool moved = false;
@@ -83,14 +84,15 @@ __global__ __launch_bounds__(256) void k_h_update(int64_t n, const int32_t *__re
             br[i] = b;
         }
     }
+    // per particle and per super-cluster (a wave's 64 particles are one
+    // super-cluster) what moved: the next round recounts only those; the
+    // total is a prefix sum over the super-clusters (no contended atomics)
+    if (i < n) p_moved[i] = moved ? 1 : 0;
     const uint64_t m = sfc_ballot(moved);
-    if (sfc_lane() == 0 && m) {
-        atomicAdd(&status[kStUnconverged], (uint32_t)sfc_popc(m));
-        if (sys_moved) atomicAdd(&sys_moved[sy], (uint32_t)sfc_popc(m));
+    if (sfc_lane() == 0 && i < n) {
+        sc_moved[i / kScSize] = (uint32_t)sfc_popc(m);
+        if (sys_moved && m) sys_moved[sy] = 1u;  // same value from every wave
     }
-    // the next round recounts only super-clusters where a radius moved (a
-    // wave's 64 particles are one super-cluster)
-    if (sc_active && sfc_lane() == 0 && i < n) sc_active[i / kScSize] = m != 0;
 }
 
 }  // namespace
@@ -149,19 +151,24 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
     // and a converged run ends with one list build in the requested form.
     sfcnl_nlist_opts it_nl = *nl_opts;
     it_nl.half = 0;
-    uint32_t *act = nlist_ws_active(d_ws, n, it_nl, 1);
+    const ActiveWs act = nlist_ws_active(d_ws, n, it_nl, 1);
+    const int64_t nsc = (n + kScSize - 1) / kScSize;
     bool list_final = false;
     for (int it = 0; it < it_opts->max_iters; it++) {
         const bool first = it == 0;
         const sfcnl_nlist_opts &o = first ? *nl_opts : it_nl;
-        const uint32_t *active = first ? nullptr : act;
-        int rc = clusters_impl(ctx, n, d_x, d_y, d_z, d_h, o.cluster_size, d_bbox, SegTable{});
-        if (rc) return rc;
+        int rc = SFCNL_OK;
+        if (first) {
+            rc = clusters_impl(ctx, n, d_x, d_y, d_z, d_h, o.cluster_size, d_bbox, SegTable{});
+            if (rc) return rc;
+        }
+        // later rounds: counting lists of the moved particles, same octree
         rc = nlist_build_impl(ctx, n, d_keys, d_x, d_y, d_z, d_h, d_bbox, o, d_ws, ws_bytes, d_sc_info, d_pool,
-                              pool_bytes, SegTable{}, true, &S.used_bytes, &S.max_nj, active);
+                              pool_bytes, SegTable{}, true, &S.used_bytes, &S.max_nj, first ? nullptr : act.sc,
+                              first ? nullptr : act.p, !first);
         if (rc) return rc;
         rc = pass_impl(ctx, n, o.cluster_size, o.compress, o.half, d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho,
-                       d_nnb, SegTable{}, active);
+                       d_nnb, SegTable{}, first ? nullptr : act.sc, first ? nullptr : act.p);
         if (rc) return rc;
         list_final = first;
         const float *proposal = nullptr;
@@ -173,11 +180,11 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
             if (rc) return rc;
             proposal = seed->d_delta;
         }
-        rc = fill_u32(ctx, ctx->d_status + kStUnconverged, 1, 0);
-        if (rc) return rc;
         k_h_update<<<blocks_for(n, 256), 256, 0, strm>>>(n, d_nnb, d_h, br, it_opts->target, it_opts->tol, proposal,
-                                                        ctx->d_status, SegTable{}, nullptr, act);
+                                                        ctx->d_status, SegTable{}, nullptr, act.sc, act.p);
         SFCNL_LAUNCHED(ctx);
+        rc = scan_u32(ctx, act.sc, act.scan, nsc, ctx->d_status + kStUnconverged, act.scan_tmp);
+        if (rc) return rc;
         SFCNL_HIP(ctx, hipMemcpyAsync(ctx->h_status + kStUnconverged, ctx->d_status + kStUnconverged,
                                       sizeof(uint32_t), hipMemcpyDeviceToHost, strm));
         SFCNL_HIP(ctx, hipStreamSynchronize(strm));
@@ -229,16 +236,20 @@ struct RoundArgs {
 // learned first step; `active` (nullable) restricts the list build and the
 // pass to flagged super-clusters; `act_out` receives the next round's flags.
 int enqueue_round(sfcnl_ctx ctx, const RoundArgs &r, const sfcnl_nlist_opts &o, const sfcnl_hseed *seed,
-                  const uint32_t *active, uint32_t *act_out) {
+                  bool restricted, const ActiveWs &act) {
     const SegTable seg = seg_of(r.b);
     const int64_t n = r.b->n_pad;
-    int rc = clusters_impl(ctx, n, r.x, r.y, r.z, r.h, o.cluster_size, r.bbox, seg);
-    if (rc) return rc;
+    int rc = SFCNL_OK;
+    if (!restricted) {
+        rc = clusters_impl(ctx, n, r.x, r.y, r.z, r.h, o.cluster_size, r.bbox, seg);
+        if (rc) return rc;
+    }
     rc = nlist_build_impl(ctx, n, r.keys, r.x, r.y, r.z, r.h, r.bbox, o, r.ws, r.ws_bytes, r.sc_info, r.pool,
-                          r.pool_bytes, seg, false, nullptr, nullptr, active);
+                          r.pool_bytes, seg, false, nullptr, nullptr, restricted ? act.sc : nullptr,
+                          restricted ? act.p : nullptr, restricted);
     if (rc) return rc;
     rc = pass_impl(ctx, n, o.cluster_size, o.compress, o.half, r.sc_info, r.pool, r.x, r.y, r.z, r.h, r.m, r.rho,
-                   r.nnb, seg, active);
+                   r.nnb, seg, restricted ? act.sc : nullptr, restricted ? act.p : nullptr);
     if (rc) return rc;
     const float *proposal = nullptr;
     if (seed) {
@@ -248,13 +259,13 @@ int enqueue_round(sfcnl_ctx ctx, const RoundArgs &r, const sfcnl_nlist_opts &o, 
         if (rc) return rc;
         proposal = seed->d_delta;
     }
-    rc = fill_u32(ctx, ctx->d_status + kStUnconverged, 1, 0);
-    if (rc) return rc;
     rc = fill_u32(ctx, r.b->d_sys_moved, r.b->nsys, 0);
     if (rc) return rc;
     k_h_update<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, r.nnb, r.h, r.br, r.it->target, r.it->tol, proposal,
-                                                           ctx->d_status, seg, r.b->d_sys_moved, act_out);
+                                                           ctx->d_status, seg, r.b->d_sys_moved, act.sc, act.p);
     SFCNL_LAUNCHED(ctx);
+    rc = scan_u32(ctx, act.sc, act.scan, n / kScSize, ctx->d_status + kStUnconverged, act.scan_tmp);
+    if (rc) return rc;
     SFCNL_HIP(ctx, hipMemcpyAsync(ctx->h_status, ctx->d_status, kStWords * sizeof(uint32_t), hipMemcpyDeviceToHost,
                                   ctx->stream));
     SFCNL_HIP(ctx, hipMemcpyAsync(r.b->h_sys_moved, r.b->d_sys_moved, r.b->nsys * sizeof(uint32_t),
@@ -353,7 +364,7 @@ extern "C" int sfcnl_batch_h_iterate(sfcnl_ctx ctx, sfcnl_batch b, const uint64_
     // converged run ends with one list build in the requested form.
     sfcnl_nlist_opts it_nl = *nl_opts;
     it_nl.half = 0;
-    uint32_t *act = nlist_ws_active(d_ws, b->n_pad, it_nl, b->nsys);
+    const ActiveWs act = nlist_ws_active(d_ws, b->n_pad, it_nl, b->nsys);
     bool list_final = false;
     GraphHolder gh;
     std::vector<char> active((size_t)b->nsys, 1);
@@ -361,13 +372,13 @@ extern "C" int sfcnl_batch_h_iterate(sfcnl_ctx ctx, sfcnl_batch b, const uint64_
         const sfcnl_hseed *sd = (seed && seed->mode == SFCNL_SEED_AFTER_FIRST && it == 0) ? seed : nullptr;
         list_final = it == 0;
         if (it == 0) {
-            int rc = enqueue_round(ctx, r, *nl_opts, sd, nullptr, act);
+            int rc = enqueue_round(ctx, r, *nl_opts, sd, false, act);
             if (rc) return rc;
         } else if (use_graph) {
             if (!gh.e) {
                 ctx->prof_slots = 0;  // no event records inside the graph
                 SFCNL_HIP(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-                int rc = enqueue_round(ctx, r, it_nl, nullptr, act, act);
+                int rc = enqueue_round(ctx, r, it_nl, nullptr, true, act);
                 hipGraph_t g = nullptr;
                 hipError_t e = hipStreamEndCapture(st, &g);
                 gh.g = g;
@@ -378,7 +389,7 @@ extern "C" int sfcnl_batch_h_iterate(sfcnl_ctx ctx, sfcnl_batch b, const uint64_
             }
             SFCNL_HIP(ctx, hipGraphLaunch(gh.e, st));
         } else {
-            int rc = enqueue_round(ctx, r, it_nl, nullptr, act, act);
+            int rc = enqueue_round(ctx, r, it_nl, nullptr, true, act);
             if (rc) return rc;
         }
         SFCNL_HIP(ctx, hipStreamSynchronize(st));

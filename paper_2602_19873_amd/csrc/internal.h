@@ -179,19 +179,30 @@ int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x,
 size_t nlist_ws_bytes(int64_t n, const sfcnl_nlist_opts &o, int nsys);
 // `active` (nullable, one flag per super-cluster): only super-clusters with a
 // nonzero flag get a list (full lists only); the others get an empty one.
+// `p_active` (nullable, one flag per particle): the lists count only the
+// flagged particles' own-radius pairs (d2 < h_i^2), so boxes need no radii;
+// `reuse_tree` keeps the octree of the previous build (same keys, bucket and
+// cluster size: its positions and ranges are still exact).
 int nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *keys, const float *x, const float *y, const float *z,
                      const float *h, const float *bbox, const sfcnl_nlist_opts &o, void *ws, size_t ws_bytes,
                      uint32_t *sc_info, uint32_t *pool, size_t pool_bytes, const SegTable &seg, bool readback,
-                     size_t *used_bytes, int64_t *max_nj, const uint32_t *active = nullptr);
-// the per-super-cluster flag array inside a build_nlist workspace
-uint32_t *nlist_ws_active(void *ws, int64_t n, const sfcnl_nlist_opts &o, int nsys);
+                     size_t *used_bytes, int64_t *max_nj, const uint32_t *active = nullptr,
+                     const uint8_t *p_active = nullptr, bool reuse_tree = false);
+// arrays for restricted rebuilds inside a build_nlist workspace
+struct ActiveWs {
+    uint32_t *sc;      // per super-cluster: particles that moved
+    uint32_t *scan;    // nsc + 1 words of scan output
+    uint8_t *p;        // per particle: moved
+    void *scan_tmp;
+};
+ActiveWs nlist_ws_active(void *ws, int64_t n, const sfcnl_nlist_opts &o, int nsys);
 int clusters_impl(sfcnl_ctx ctx, int64_t n, const float *x, const float *y, const float *z, const float *h, int cs,
                   float *bbox, const SegTable &seg);
 // `active` as for nlist_build_impl: the pass leaves rho and nnb of inactive
 // super-clusters unchanged (full lists only).
 int pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, int half, const uint32_t *sc_info, const uint32_t *pool,
               const float *x, const float *y, const float *z, const float *h, const float *m, float *rho, int32_t *nnb,
-              const SegTable &seg, const uint32_t *active = nullptr);
+              const SegTable &seg, const uint32_t *active = nullptr, const uint8_t *p_active = nullptr);
 int features_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *keys, const float *x, const float *y, const float *z,
                   const float *h, const int32_t *nnb, float box_edge, int target, uint16_t *feat,
                   const SegTable &seg);

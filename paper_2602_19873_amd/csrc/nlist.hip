@@ -119,6 +119,10 @@ struct TravArgs {
     uint32_t nslots;       // capacity of the slot arrays
     SegTable seg;          // batched systems (empty for one system)
     const uint32_t *active;  // nullable: super-clusters with active[s] == 0 get an empty list
+    // nullable: a counting list for the flagged particles only (own radius):
+    // pairs d2 < h_i^2 for i with p_active[i] != 0; node, cluster and j radii
+    // are ignored, so the octree's boxes need no refit when only radii change
+    const uint8_t *p_active;
     uint32_t *list_j;      // staging: cap entries per super-cluster
     uint16_t *list_m;
     uint32_t *sc_nj, *sc_words;
@@ -181,6 +185,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
         return;
     }
     const int64_t n = a.n;
+    const bool gather = a.p_active != nullptr;
     // i particles; absent ones are put far away so that no test accepts them
     float ix[kNreg], iy[kNreg], iz[kNreg], ih2[kNreg];
 #pragma unroll
@@ -190,7 +195,8 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
         ix[k] = v ? a.x[i] : kFar;
         iy[k] = v ? a.y[i] : kFar;
         iz[k] = v ? a.z[i] : kFar;
-        const float hh = v ? a.h[i] : 0.0f;
+        float hh = v ? a.h[i] : 0.0f;
+        if (gather && v && !a.p_active[i]) hh = 0.0f;  // counting list: flagged particles only
         ih2[k] = hh * hh;
     }
     const uint32_t own_c0 = s * kNsub;  // first i-cluster of this super-cluster
@@ -221,6 +227,35 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
         glo = v0 ? a.bbox[2 * (size_t)c0] : empty_lo;
         ghi = v0 ? a.bbox[2 * (size_t)c0 + 1] : empty_hi;
         if (CS == 4 && c0 + 1 < a.nclu) box_union(glo, ghi, a.bbox[2 * (size_t)c0 + 2], a.bbox[2 * (size_t)c0 + 3]);
+    }
+
+    if (gather) {
+        // radii of the boxes: the largest flagged radius inside, from the i
+        // registers (a radius 0 box passes no test)
+        __shared__ float s_hmax[kWavesPerBlock][kScSize];
+        float *hm = s_hmax[w];
+#pragma unroll
+        for (int k = 0; k < kNreg; k++) {
+            if ((CS == 8 ? (lane & 7) : (lane & 3)) == 0) hm[S::ipart(k, lane)] = __builtin_sqrtf(ih2[k]);
+        }
+        wave_sync();
+        auto rmax = [&](int p0, int cnt) {
+            float r = 0.0f;
+            for (int q = 0; q < cnt; q++) r = fmaxf(r, hm[p0 + q]);
+            return r;
+        };
+#pragma unroll
+        for (int t = 0; t < kIbox; t++) {
+            const int ic = CS == 8 ? (lane >> 3) : (CS == 4 ? (lane >> 4) + 4 * t : ((lane >> 2) & 3));
+            ilo[t].w = rmax(ic * CS, CS);
+        }
+        if (CS == 8)
+            glo.w = ilo[0].w;
+        else if (CS == 4)
+            glo.w = rmax(8 * (lane >> 3), 8);
+        else
+            glo.w = rmax(16 * (lane >> 4), 16);
+        wave_sync();
     }
 
     // stack of node records {first, end, child count (0 = leaf), first child
@@ -279,6 +314,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                 if (cj <= c1) {
                     lo_ = a.bbox[2 * cj];
                     hi_ = a.bbox[2 * cj + 1];
+                    if (gather) lo_.w = 0.0f;  // own radius only
                 } else {
                     lo_ = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
                     hi_ = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
@@ -341,7 +377,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                                 const float dz = zj - iz[c];
                                 const float dxx = dx * dx;
                                 const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                                bool pr = d2 < fmaxf(ih2[c], hj2);
+                                bool pr = d2 < (gather ? ih2[c] : fmaxf(ih2[c], hj2));
                                 if (half) {  // inside the super-cluster: i-clusters up to the j-cluster only
                                     if (self_c >= 0) pr = pr && keep(c, il, jl);
                                 } else if (c == self_c) {
@@ -363,7 +399,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                                 const float dz = zj - iz[k];
                                 const float dxx = dx * dx;
                                 const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                                bool pr = d2 < fmaxf(ih2[k], hj2);
+                                bool pr = d2 < (gather ? ih2[k] : fmaxf(ih2[k], hj2));
                                 if (self_c >= 0) pr = pr && keep(4 * k + q, il, jl);
                                 const uint64_t b = sfc_ballot(pr);
                                 const uint32_t g = (uint32_t)((b & 0xFFFFull) != 0) |
@@ -395,7 +431,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                                     const float dz = zj[t] - iz[c];
                                     const float dxx = dx * dx;
                                     const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                                    bool p = d2 < fmaxf(ih2[c], hj2[t]);
+                                    bool p = d2 < (gather ? ih2[c] : fmaxf(ih2[c], hj2[t]));
                                     if (half) {
                                         if (self_c >= 0) p = p && (c < self_c || (c == self_c && 4 * t + jq > il));
                                     } else if (c == self_c) {
@@ -434,7 +470,9 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
             bool hit = false;
             uint4 crec = make_uint4(0u, 0u, 0u, 0u);
             if (act) {
-                const float4 lo = a.cs_box[2 * (size_t)slot], hi = a.cs_box[2 * (size_t)slot + 1];
+                float4 lo = a.cs_box[2 * (size_t)slot];
+                const float4 hi = a.cs_box[2 * (size_t)slot + 1];
+                if (gather) lo.w = 0.0f;  // own radius only
                 crec = a.cs_rec[slot];
                 // a half list never needs a node that ends before the super-cluster
                 hit = boxes_near(glo, ghi, lo, hi) && (!half || crec.y > own_p0);
@@ -575,7 +613,9 @@ struct NlistWs {
     uint32_t *list_j;
     uint16_t *list_m;
     uint32_t *sc_nj, *sc_words, *sc_off;
-    uint32_t *sc_active;  // per super-cluster flags for restricted rebuilds (h-iteration)
+    uint32_t *sc_active;  // per super-cluster counts / flags for restricted rebuilds (h-iteration)
+    uint32_t *sc_scan;    // their prefix sum (nsc + 1)
+    uint8_t *p_active;    // per particle flags for restricted rebuilds
     void *scan_tmp;
 };
 
@@ -588,6 +628,8 @@ void carve_nlist(Carver &cv, NlistWs &ws, int64_t n, const sfcnl_nlist_opts &o, 
     ws.sc_words = cv.take<uint32_t>(nsc);
     ws.sc_off = cv.take<uint32_t>((size_t)nsc + 1);
     ws.sc_active = cv.take<uint32_t>(nsc);
+    ws.sc_scan = cv.take<uint32_t>((size_t)nsc + 1);
+    ws.p_active = cv.take<uint8_t>((size_t)n);
     ws.scan_tmp = cv.take<char>(scan_tmp_bytes(nsc));
 }
 
@@ -651,19 +693,20 @@ int sfcnl::read_status(sfcnl_ctx ctx) {
     return SFCNL_OK;
 }
 
-uint32_t *sfcnl::nlist_ws_active(void *d_ws, int64_t n, const sfcnl_nlist_opts &o, int nsys) {
+sfcnl::ActiveWs sfcnl::nlist_ws_active(void *d_ws, int64_t n, const sfcnl_nlist_opts &o, int nsys) {
     Carver cv{reinterpret_cast<char *>(d_ws), 0};
     NlistWs ws;
     carve_nlist(cv, ws, n, o, nsys);
-    return ws.sc_active;
+    return ActiveWs{ws.sc_active, ws.sc_scan, ws.p_active, ws.scan_tmp};
 }
 
 int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_x, const float *d_y,
                             const float *d_z, const float *d_h, const float *d_bbox, const sfcnl_nlist_opts &o,
                             void *d_ws, size_t ws_bytes, uint32_t *d_sc_info, uint32_t *d_pool, size_t pool_bytes,
                             const SegTable &seg, bool readback, size_t *h_used_bytes, int64_t *h_max_nj,
-                            const uint32_t *active) {
-    if (active && o.half) return set_err(ctx, SFCNL_E_ARG, "build_nlist: a restricted rebuild needs the full list");
+                            const uint32_t *active, const uint8_t *p_active, bool reuse_tree) {
+    if ((active || p_active) && o.half)
+        return set_err(ctx, SFCNL_E_ARG, "build_nlist: a restricted rebuild needs the full list");
     const int nsys = seg.on() ? seg.nsys : 1;
     Carver cv{reinterpret_cast<char *>(d_ws), 0};
     NlistWs ws;
@@ -676,10 +719,12 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
 
     int rc = fill_u32(ctx, ctx->d_status + kStPoolOverflow, kStWords - kStPoolOverflow, 0);
     if (rc) return rc;
-    prof_mark(ctx, kStageOctree, false);
-    rc = octree_build(ctx, ws.tree, d_keys, d_x, d_y, d_z, d_h, reinterpret_cast<const float4 *>(d_bbox), seg);
-    if (rc) return rc;
-    prof_mark(ctx, kStageOctree, true);
+    if (!reuse_tree) {  // else the tree of the previous build (same keys and bucket) serves
+        prof_mark(ctx, kStageOctree, false);
+        rc = octree_build(ctx, ws.tree, d_keys, d_x, d_y, d_z, d_h, reinterpret_cast<const float4 *>(d_bbox), seg);
+        if (rc) return rc;
+        prof_mark(ctx, kStageOctree, true);
+    }
 
     TravArgs ta;
     ta.n = n;
@@ -697,6 +742,7 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     ta.nslots = ws.tree.node_cap;
     ta.seg = seg;
     ta.active = active;
+    ta.p_active = p_active;
     ta.list_j = ws.list_j;
     ta.list_m = ws.list_m;
     ta.sc_nj = ws.sc_nj;

@@ -66,6 +66,7 @@ struct PassArgs {
     int32_t *nnb;
     SegTable seg;  // batched systems: list indices are relative to the system's first cluster
     const uint32_t *active;  // nullable: skip super-clusters with active[s] == 0 (full pass)
+    const uint8_t *p_active;  // nullable: write only particles with p_active[i] != 0 (full pass)
 };
 
 // i-particle held in register k by a lane (the traversal's lane roles):
@@ -240,7 +241,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
         nb = jl == k ? cnt_nb[k] : nb;
     }
     const int64_t io = (int64_t)s * kScSize + ipart<CS>(jl, lane);
-    if (io < n) {
+    if (io < n && (!a.p_active || a.p_active[io])) {
         const float hh = a.h[io];
         const float hinv = 1.0f / hh;
         const float mi = kMass ? a.m[io] : 1.0f;
@@ -576,10 +577,12 @@ using namespace sfcnl;
 
 int sfcnl::pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, int half, const uint32_t *d_sc_info,
                      const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z, const float *d_h,
-                     const float *d_m, float *d_rho, int32_t *d_nnb, const SegTable &seg, const uint32_t *active) {
-    if (active && half) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: a restricted pass needs the full list");
+                     const float *d_m, float *d_rho, int32_t *d_nnb, const SegTable &seg, const uint32_t *active,
+                     const uint8_t *p_active) {
+    if ((active || p_active) && half)
+        return set_err(ctx, SFCNL_E_ARG, "nlist_pass: a restricted pass needs the full list");
     PassArgs a{n, (uint32_t)((n + kScSize - 1) / kScSize), d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb,
-               seg, active};
+               seg, active, p_active};
     const unsigned g = blocks_for(a.nsc, kWavesPerBlock);
     hipStream_t st = ctx->stream;
     const int variant = (compress ? 4 : 0) | (d_m ? 2 : 0) | (d_nnb ? 1 : 0);
