@@ -312,9 +312,9 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                 h_ = pv ? a.h[pj] : 0.0f;
                 const int64_t cj = cb + (lane & (kNsub - 1));
                 if (cj <= c1) {
-                    lo_ = a.bbox[2 * cj];
+                    const float4 l = a.bbox[2 * cj];
+                    lo_ = make_float4(l.x, l.y, l.z, gather ? 0.0f : l.w);  // own radius only when counting
                     hi_ = a.bbox[2 * cj + 1];
-                    if (gather) lo_.w = 0.0f;  // own radius only
                 } else {
                     lo_ = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
                     hi_ = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
@@ -470,9 +470,9 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
             bool hit = false;
             uint4 crec = make_uint4(0u, 0u, 0u, 0u);
             if (act) {
-                float4 lo = a.cs_box[2 * (size_t)slot];
+                const float4 l = a.cs_box[2 * (size_t)slot];
+                const float4 lo = make_float4(l.x, l.y, l.z, gather ? 0.0f : l.w);  // own radius only when counting
                 const float4 hi = a.cs_box[2 * (size_t)slot + 1];
-                if (gather) lo.w = 0.0f;  // own radius only
                 crec = a.cs_rec[slot];
                 // a half list never needs a node that ends before the super-cluster
                 hit = boxes_near(glo, ghi, lo, hi) && (!half || crec.y > own_p0);
