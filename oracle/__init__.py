@@ -84,6 +84,9 @@ def _load():
         lib.orc_kernel_w.argtypes = [C.c_double, C.c_double]
         lib.orc_density.restype = None
         lib.orc_density.argtypes = [C.c_int64, f32p, f32p, f32p, f32p, C.c_void_p, C.c_int, f64p, i32p]
+        lib.orc_lj.restype = None
+        lib.orc_lj.argtypes = [C.c_int64, f32p, f32p, f32p, C.c_void_p, C.c_double, C.c_double, C.c_double,
+                               C.c_float, C.c_int, C.c_void_p, C.c_int64, f64p, f64p, f64p, i32p]
         lib.orc_num_threads.restype = C.c_int
         lib.orc_num_threads.argtypes = []
         _lib = lib
@@ -277,6 +280,34 @@ def density(x, y, z, h, m=None, method: str = "grid"):
     _load().orc_density(n, x, y, z, h, None if mm is None else mm.ctypes.data,
                         1 if method == "grid" else 0, rho, nnb)
     return rho[:n], nnb[:n]
+
+
+# --------------------------------------------------------------------------
+# Sec. III, Lennard-Jones benchmark: 12/6 Lennard-Jones + Coulomb forces of
+# the pairs inside an interaction cutoff shorter than the list cutoff (FP64)
+# --------------------------------------------------------------------------
+
+def lj(x, y, z, q=None, eps: float = 1.0, sigma: float = 1.0, coulomb: float = 0.0, r_cut: float = 1.0,
+       method: str = "grid", idx=None):
+    """Pair forces of U(r) = 4 eps ((sigma/r)^12 - (sigma/r)^6) + k q_i q_j / r
+    over the pairs j != i with d2 < f32(r_cut^2) (the FP32 pair formula).
+
+    Returns dict(f=(rows, 3) float64 forces on i, e=per-particle energy (half of
+    each pair's), scale=sum_j |F_ij| (for rounding bounds), nnb=pairs per
+    particle). ``idx`` restricts the rows to those particles."""
+    x, y, z = _f32(x), _f32(y), _f32(z)
+    n = x.shape[0]
+    qq = None if q is None else _f32(q)
+    ii = None if idx is None else np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+    rows = n if ii is None else ii.shape[0]
+    f = np.zeros((max(rows, 1), 3), np.float64)
+    e = np.zeros(max(rows, 1), np.float64)
+    sc = np.zeros(max(rows, 1), np.float64)
+    nnb = np.zeros(max(rows, 1), np.int32)
+    _load().orc_lj(n, x, y, z, None if qq is None else qq.ctypes.data, float(eps), float(sigma), float(coulomb),
+                   float(r_cut), 1 if method == "grid" else 0, None if ii is None else ii.ctypes.data, rows,
+                   f.reshape(-1), e, sc, nnb)
+    return dict(f=f[:rows], e=e[:rows], scale=sc[:rows], nnb=nnb[:rows])
 
 
 # --------------------------------------------------------------------------

@@ -18,6 +18,8 @@
  *     wavefront width (Sec. II-C).
  *   - SPH densities rho_i = sum_j m_j W(r_ij, h_i) and neighbour counts in
  *     FP64 (Sec. II-D, Listing 1).
+ *   - Lennard-Jones 12/6 + Coulomb forces of the pairs inside an interaction
+ *     cutoff shorter than the list cutoff (Sec. III, Lennard-Jones benchmark).
  *
  * Must be compiled with -ffp-contract=off: the FP32 pair test below spells
  * out every rounding step and no other contraction is allowed.
@@ -621,6 +623,91 @@ void orc_density(int64_t n, const float *x, const float *y, const float *z, cons
         if (nnb) nnb[i] = cnt;
     }
     if (use_grid) grid_free(&g);
+}
+
+/* ------------------------------------------------------------------------- */
+/* Lennard-Jones 12/6 + Coulomb pair forces (Sec. III, Lennard-Jones benchmark) */
+/* ------------------------------------------------------------------------- */
+
+/* The benchmark pass of Sec. III: every pair closer than the interaction
+ * cutoff r_c (fewer than the list cutoff, the Verlet buffer) feels the 12/6
+ * Lennard-Jones force plus the Coulomb force of the two charges. Which pairs
+ * interact is decided by the same FP32 test as everything else,
+ * d2 < f32(r_c^2); the force of an accepted pair is evaluated in FP64 from the
+ * exact differences of the FP32 coordinates:
+ *   U(r) = 4 eps ((sigma/r)^12 - (sigma/r)^6) + k q_i q_j / r
+ *   F_i  = sum_j -dU/dr (x_i - x_j)/r
+ *        = sum_j [24 eps (2 (sigma/r)^12 - (sigma/r)^6) / r^2 + k q_i q_j / r^3] (x_i - x_j)
+ *   E_i  = 1/2 sum_j U(r_ij)   (each pair's energy shared by its two particles)
+ * scale_i = sum_j |F_ij| (the size of the terms, for rounding-error bounds).
+ * q == NULL means no charges. idx (nullable, count nidx) restricts the output
+ * to those particles: row t of the outputs is particle idx[t]. */
+void orc_lj(int64_t n, const float *x, const float *y, const float *z, const float *q, double eps, double sigma,
+            double kc, float rc, int use_grid, const int64_t *idx, int64_t nidx, double *f, double *e,
+            double *scale, int32_t *nnb)
+{
+    float *hr = (float *)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
+    for (int64_t i = 0; i < n; i++) hr[i] = rc;
+    orc_grid g;
+    memset(&g, 0, sizeof g);
+    if (use_grid) grid_build(&g, n, x, y, z, hr);
+    int64_t rows = idx ? nidx : n;
+#pragma omp parallel for schedule(dynamic, 256)
+    for (int64_t t = 0; t < rows; t++) {
+        int64_t i = idx ? idx[t] : t;
+        double fx = 0.0, fy = 0.0, fz = 0.0, en = 0.0, sc = 0.0;
+        int32_t cnt = 0;
+        int64_t cx = 0, cy = 0, cz = 0, r0 = 0, r1 = 0;
+        if (use_grid) {
+            cx = grid_cell1(&g, 0, x[i]);
+            cy = grid_cell1(&g, 1, y[i]);
+            cz = grid_cell1(&g, 2, z[i]);
+            r0 = -1;
+            r1 = 1;
+        }
+        for (int64_t az = cz + r0; az <= cz + r1; az++) {
+            for (int64_t ay = cy + r0; ay <= cy + r1; ay++) {
+                for (int64_t ax = cx + r0; ax <= cx + r1; ax++) {
+                    int64_t k0 = 0, k1 = n;
+                    if (use_grid) {
+                        if (az < 0 || az >= g.dim[2] || ay < 0 || ay >= g.dim[1] || ax < 0 || ax >= g.dim[0])
+                            continue;
+                        int64_t c = (az * g.dim[1] + ay) * g.dim[0] + ax;
+                        k0 = g.start[c];
+                        k1 = g.start[c + 1];
+                    }
+                    for (int64_t k = k0; k < k1; k++) {
+                        int64_t j = use_grid ? g.idx[k] : k;
+                        if (j == i) continue;
+                        if (!orc_in_own_radius(x[i], y[i], z[i], rc, x[j], y[j], z[j])) continue;
+                        double dx = (double)x[i] - (double)x[j];
+                        double dy = (double)y[i] - (double)y[j];
+                        double dz = (double)z[i] - (double)z[j];
+                        double r2 = dx * dx + dy * dy + dz * dz;
+                        double r = sqrt(r2);
+                        double sr6 = pow(sigma / r, 6.0);
+                        double qq = q ? (double)q[i] * (double)q[j] : 0.0;
+                        /* -dU/dr divided by r */
+                        double fr = (24.0 * eps * (2.0 * sr6 * sr6 - sr6) + kc * qq / r) / r2;
+                        fx += fr * dx;
+                        fy += fr * dy;
+                        fz += fr * dz;
+                        en += 0.5 * (4.0 * eps * (sr6 * sr6 - sr6) + kc * qq / r);
+                        sc += fabs(fr) * r;
+                        cnt++;
+                    }
+                }
+            }
+        }
+        f[3 * t] = fx;
+        f[3 * t + 1] = fy;
+        f[3 * t + 2] = fz;
+        if (e) e[t] = en;
+        if (scale) scale[t] = sc;
+        if (nnb) nnb[t] = cnt;
+    }
+    if (use_grid) grid_free(&g);
+    free(hr);
 }
 
 int orc_num_threads(void)

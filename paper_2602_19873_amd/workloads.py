@@ -17,6 +17,10 @@ sphere whose density falls off as 1/r, Sec. IV):
 * ``plummer``          Plummer sphere (scale radius a), truncated at 10 a.
 * ``batch_systems``    64 systems of log-uniform size in [1e4, 1e6], half
                         uniform cubes and half Plummer spheres.
+* ``lj_lattice``       the Lennard-Jones benchmark box: a jittered simple
+                        cubic lattice of n_side^3 atoms in [0,1)^3 with
+                        rock-salt charges, list radius for ~200 neighbours
+                        and interaction cutoff for ~150.
 """
 from __future__ import annotations
 
@@ -46,6 +50,7 @@ class ParticleSystem:
     m: np.ndarray | None
     box: tuple
     meta: dict = field(default_factory=dict)
+    q: np.ndarray | None = None
 
     @property
     def n(self) -> int:
@@ -134,15 +139,43 @@ def batch_systems(count: int = 64, target: float = 150.0, lo: float = 1e4, hi: f
     return systems
 
 
+def lj_lattice(n_side: int, seed: int, jitter: float = 0.2, list_target: float = 200.0,
+               cut_target: float = 150.0) -> ParticleSystem:
+    """Near-uniform atoms for the Lennard-Jones benchmark (Sec. III: about 200
+    neighbours inside the list cutoff, 150 inside the interaction cutoff).
+
+    Atom (i, j, k) sits at ((i, j, k) + 1/2 + U(-jitter, jitter)^3) a with
+    a = 1/n_side, so no two atoms come closer than (1 - 2 jitter) a. Charges
+    alternate +-1/2 with the parity of i + j + k (rock salt, neutral for even
+    n_side). sigma = 0.9 a (reduced density 0.729), eps = 1, Coulomb prefactor
+    4 a (a charge pair at distance a has energy of order eps). h is the list
+    radius for every atom; meta holds the pass parameters."""
+    rng = np.random.default_rng(seed)
+    a = 1.0 / n_side
+    g = np.indices((n_side,) * 3).reshape(3, -1).astype(np.float64)
+    pos = (g + 0.5 + rng.uniform(-jitter, jitter, g.shape)) * a
+    n = pos.shape[1]
+    q = np.where(g.sum(axis=0).astype(np.int64) % 2 == 0, 0.5, -0.5)
+    r_list = radius_for_neighbours(n, list_target)
+    r_cut = radius_for_neighbours(n, cut_target)
+    return ParticleSystem("lj_lattice", _f32(pos[0]), _f32(pos[1]), _f32(pos[2]), _f32(np.full(n, r_list)), None,
+                          UNIT_BOX, {"seed": seed, "r_list": r_list, "r_cut": r_cut, "eps": 1.0, "sigma": 0.9 * a,
+                                     "coulomb": 4.0 * a, "spacing": a},
+                          q=_f32(q))
+
+
 # Named single-system workloads at their full sizes.
 CONFIGS = {
     "uniform_32k": dict(kind="uniform_global", n=32768, seed=SEED_BASE + 1),
     "uniform_2m_varied": dict(kind="uniform_varied", n=2097152, seed=SEED_BASE + 2),
     "evrard_8m": dict(kind="evrard_sphere", n=8388608, seed=SEED_BASE + 3),
+    "lj_4m": dict(kind="lj_lattice", n=160 ** 3, seed=SEED_BASE + 6),
 }
 
 
 def make(kind: str, n: int, seed: int, **kw) -> ParticleSystem:
+    if kind == "lj_lattice":
+        return lj_lattice(int(round(n ** (1.0 / 3.0))), seed, **kw)
     fn = {"uniform_global": uniform_global, "uniform_varied": uniform_varied,
           "evrard_sphere": evrard_sphere, "plummer": plummer}[kind]
     return fn(n, seed, **kw)
