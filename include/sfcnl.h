@@ -11,6 +11,8 @@
  *                   bitmasks, nibble compression (Sec. II-A, II-B, II-C)
  *   nlist_pass      decompress and compute the SPH density sum and neighbour
  *                   counts (Sec. II-A "neighbor pass", Sec. II-D, Listing 1)
+ *   nlist_pass_lj   the Lennard-Jones 12/6 + Coulomb force pass of the
+ *                   Sec. III benchmark (interaction cutoff inside the list's)
  *
  * Conventions shared by every call:
  *   - d_* arguments are device pointers, h_* arguments are host pointers. The
@@ -162,6 +164,32 @@ int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d
 int nlist_pass(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, int half, const uint32_t *d_sc_info,
                const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z,
                const float *d_h, const float *d_m, float *d_rho, int32_t *d_nnb);
+
+/* ---- 4b. Lennard-Jones 12/6 + Coulomb pass (Sec. III, Lennard-Jones benchmark)
+ * The benchmark pass of Sec. III with a Verlet buffer: the list is built once
+ * with a radius h_i >= r_cut for every particle (the list cutoff) and reused;
+ * the pass keeps only the pairs with d2 < f32(r_cut^2) (the interaction
+ * cutoff), decided by the pair formula of build_nlist. For those pairs
+ *   U(r) = 4 eps ((sigma/r)^12 - (sigma/r)^6) + coulomb q_i q_j / r
+ *   F_i  = sum_j [24 eps (2 (sigma/r)^12 - (sigma/r)^6) / r^2 + coulomb q_i q_j / r^3] (x_i - x_j)
+ *   E_i  = 1/2 sum_j U(r_ij)
+ * in FP32 (reciprocal and reciprocal square root at 1 ulp). Pairs within
+ * r_cut that the list does not hold (a list built with radii below r_cut)
+ * are not seen. Outputs in SFC order: d_fx, d_fy, d_fz forces, d_epot
+ * (nullable) per-particle energies. d_q == NULL means no charges (pure
+ * Lennard-Jones). cluster_size, compress and half as given to build_nlist; a
+ * half list feeds both particles of every stored pair (Newton's third law)
+ * through float atomics, so the last bits vary from run to run. Two particles
+ * at the same position give non-finite forces. */
+typedef struct {
+    float eps;      /* Lennard-Jones well depth, finite */
+    float sigma;    /* Lennard-Jones length, > 0 */
+    float coulomb;  /* Coulomb prefactor k, finite (ignored without charges) */
+    float r_cut;    /* interaction cutoff, > 0 */
+} sfcnl_lj_params;
+int nlist_pass_lj(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, int half, const uint32_t *d_sc_info,
+                  const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z, const float *d_q,
+                  const sfcnl_lj_params *params, float *d_fx, float *d_fy, float *d_fz, float *d_epot);
 
 /* Decodes the whole list on the device into flat arrays: super-cluster s's
  * entries go to [d_offsets[s], d_offsets[s] + n_j), with d_offsets the

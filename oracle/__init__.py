@@ -86,7 +86,7 @@ def _load():
         lib.orc_density.argtypes = [C.c_int64, f32p, f32p, f32p, f32p, C.c_void_p, C.c_int, f64p, i32p]
         lib.orc_lj.restype = None
         lib.orc_lj.argtypes = [C.c_int64, f32p, f32p, f32p, C.c_void_p, C.c_double, C.c_double, C.c_double,
-                               C.c_float, C.c_int, C.c_void_p, C.c_int64, f64p, f64p, f64p, i32p]
+                               C.c_float, C.c_int, C.c_void_p, C.c_int64, f64p, f64p, f64p, f64p, i32p]
         lib.orc_num_threads.restype = C.c_int
         lib.orc_num_threads.argtypes = []
         _lib = lib
@@ -293,8 +293,9 @@ def lj(x, y, z, q=None, eps: float = 1.0, sigma: float = 1.0, coulomb: float = 0
     over the pairs j != i with d2 < f32(r_cut^2) (the FP32 pair formula).
 
     Returns dict(f=(rows, 3) float64 forces on i, e=per-particle energy (half of
-    each pair's), scale=sum_j |F_ij| (for rounding bounds), nnb=pairs per
-    particle). ``idx`` restricts the rows to those particles."""
+    each pair's), scale=sum_j |F_ij| and escale=sum_j |U_ij| / 2 (for rounding
+    bounds), nnb=pairs per particle). ``idx`` restricts the rows to those
+    particles."""
     x, y, z = _f32(x), _f32(y), _f32(z)
     n = x.shape[0]
     qq = None if q is None else _f32(q)
@@ -303,11 +304,12 @@ def lj(x, y, z, q=None, eps: float = 1.0, sigma: float = 1.0, coulomb: float = 0
     f = np.zeros((max(rows, 1), 3), np.float64)
     e = np.zeros(max(rows, 1), np.float64)
     sc = np.zeros(max(rows, 1), np.float64)
+    esc = np.zeros(max(rows, 1), np.float64)
     nnb = np.zeros(max(rows, 1), np.int32)
     _load().orc_lj(n, x, y, z, None if qq is None else qq.ctypes.data, float(eps), float(sigma), float(coulomb),
                    float(r_cut), 1 if method == "grid" else 0, None if ii is None else ii.ctypes.data, rows,
-                   f.reshape(-1), e, sc, nnb)
-    return dict(f=f[:rows], e=e[:rows], scale=sc[:rows], nnb=nnb[:rows])
+                   f.reshape(-1), e, sc, esc, nnb)
+    return dict(f=f[:rows], e=e[:rows], scale=sc[:rows], escale=esc[:rows], nnb=nnb[:rows])
 
 
 # --------------------------------------------------------------------------

@@ -639,12 +639,13 @@ void orc_density(int64_t n, const float *x, const float *y, const float *z, cons
  *   F_i  = sum_j -dU/dr (x_i - x_j)/r
  *        = sum_j [24 eps (2 (sigma/r)^12 - (sigma/r)^6) / r^2 + k q_i q_j / r^3] (x_i - x_j)
  *   E_i  = 1/2 sum_j U(r_ij)   (each pair's energy shared by its two particles)
- * scale_i = sum_j |F_ij| (the size of the terms, for rounding-error bounds).
+ * scale_i = sum_j |F_ij| and escale_i = 1/2 sum_j |U(r_ij)| (the sizes of the
+ * terms, for rounding-error bounds).
  * q == NULL means no charges. idx (nullable, count nidx) restricts the output
  * to those particles: row t of the outputs is particle idx[t]. */
 void orc_lj(int64_t n, const float *x, const float *y, const float *z, const float *q, double eps, double sigma,
             double kc, float rc, int use_grid, const int64_t *idx, int64_t nidx, double *f, double *e,
-            double *scale, int32_t *nnb)
+            double *scale, double *escale, int32_t *nnb)
 {
     float *hr = (float *)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
     for (int64_t i = 0; i < n; i++) hr[i] = rc;
@@ -655,7 +656,7 @@ void orc_lj(int64_t n, const float *x, const float *y, const float *z, const flo
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t t = 0; t < rows; t++) {
         int64_t i = idx ? idx[t] : t;
-        double fx = 0.0, fy = 0.0, fz = 0.0, en = 0.0, sc = 0.0;
+        double fx = 0.0, fy = 0.0, fz = 0.0, en = 0.0, sc = 0.0, esc = 0.0;
         int32_t cnt = 0;
         int64_t cx = 0, cy = 0, cz = 0, r0 = 0, r1 = 0;
         if (use_grid) {
@@ -692,7 +693,9 @@ void orc_lj(int64_t n, const float *x, const float *y, const float *z, const flo
                         fx += fr * dx;
                         fy += fr * dy;
                         fz += fr * dz;
-                        en += 0.5 * (4.0 * eps * (sr6 * sr6 - sr6) + kc * qq / r);
+                        double u = 4.0 * eps * (sr6 * sr6 - sr6) + kc * qq / r;
+                        en += 0.5 * u;
+                        esc += 0.5 * fabs(u);
                         sc += fabs(fr) * r;
                         cnt++;
                     }
@@ -704,6 +707,7 @@ void orc_lj(int64_t n, const float *x, const float *y, const float *z, const flo
         f[3 * t + 2] = fz;
         if (e) e[t] = en;
         if (scale) scale[t] = sc;
+        if (escale) escale[t] = esc;
         if (nnb) nnb[t] = cnt;
     }
     if (use_grid) grid_free(&g);

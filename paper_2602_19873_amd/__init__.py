@@ -216,6 +216,27 @@ def nlist_pass(ctx: Context, nl: NeighbourList, x, y, z, h, m=None, rho=None, nn
     return rho, nnb
 
 
+def nlist_pass_lj(ctx: Context, nl: NeighbourList, x, y, z, q=None, eps: float = 1.0, sigma: float = 1.0,
+                  coulomb: float = 0.0, r_cut: float = 1.0, energy: bool = False, f=None, e=None):
+    """Lennard-Jones 12/6 + Coulomb forces over the listed pairs inside r_cut
+    (the list built at a radius >= r_cut). Returns (f (3, n) float32 rows fx,
+    fy, fz; e per-particle energy or None)."""
+    n = nl.n
+    for t, nm in ((x, "x"), (y, "y"), (z, "z")) + (((q, "q"),) if q is not None else ()):
+        _check_f32(t, n, nm)
+    f = ctx.empty((3, max(n, 1)), torch.float32) if f is None else f
+    if f.dtype != torch.float32 or not f.is_contiguous() or f.dim() != 2 or f.shape[0] != 3 or f.shape[1] < n:
+        raise ValueError("f must be a contiguous float32 (3, >= n) device tensor")
+    if energy and e is None:
+        e = ctx.empty(max(n, 1), torch.float32)
+    par = _lib.LjParams(float(eps), float(sigma), float(coulomb), float(r_cut))
+    ctx.check(ctx.lib.nlist_pass_lj(ctx.handle, n, nl.cluster_size, int(nl.compress), int(nl.half),
+                                    _ptr(nl.sc_info), _ptr(nl.pool), _ptr(x), _ptr(y), _ptr(z), _ptr(q),
+                                    C.byref(par), _ptr(f[0]), _ptr(f[1]), _ptr(f[2]),
+                                    _ptr(e) if energy else None))
+    return f[:, :n], (e[:n] if energy else None)
+
+
 def nlist_decode(ctx: Context, nl: NeighbourList):
     """Decodes the list on the device: (offsets int64 host, j uint32 numpy, mask uint16 numpy)."""
     import numpy as np

@@ -21,7 +21,7 @@ E_NOCONV = -5
 SYMBOLS = [
     "sfcnl_create", "sfcnl_destroy", "sfcnl_set_stream", "sfcnl_last_error", "sfcnl_sync", "sfcnl_version",
     "sfc_sort_workspace", "sfc_sort", "sfc_gather", "build_clusters", "build_nlist_workspace", "build_nlist",
-    "nlist_pass", "nlist_decode", "sfcnl_profile_begin", "sfcnl_profile_end", "sfcnl_h_iterate",
+    "nlist_pass", "nlist_pass_lj", "nlist_decode", "sfcnl_profile_begin", "sfcnl_profile_end", "sfcnl_h_iterate",
     "sfcnl_hseed_features", "sfcnl_mlp_init", "sfcnl_mlp_infer", "sfcnl_mlp_grad_workspace", "sfcnl_mlp_grad",
     "sfcnl_mlp_adam", "sfcnl_batch_create", "sfcnl_batch_destroy", "sfcnl_batch_layout", "sfcnl_batch_sort_workspace",
     "sfcnl_batch_sort", "sfcnl_batch_gather", "sfcnl_batch_nlist_workspace", "sfcnl_batch_build_clusters",
@@ -49,6 +49,10 @@ class HiterOpts(C.Structure):
 class HiterStats(C.Structure):
     _fields_ = [("iters", C.c_int), ("unconverged", C.c_int64), ("moved", C.c_int64), ("used_bytes", C.c_size_t),
                 ("max_nj", C.c_int64)]
+
+
+class LjParams(C.Structure):
+    _fields_ = [("eps", C.c_float), ("sigma", C.c_float), ("coulomb", C.c_float), ("r_cut", C.c_float)]
 
 
 class HSeed(C.Structure):
@@ -99,6 +103,8 @@ def load():
     lib.build_nlist.restype = i32
     lib.nlist_pass.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
     lib.nlist_pass.restype = i32
+    lib.nlist_pass_lj.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp, vp, vp, C.POINTER(LjParams), vp, vp, vp, vp]
+    lib.nlist_pass_lj.restype = i32
     lib.nlist_decode.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp]
     lib.nlist_decode.restype = i32
     lib.sfcnl_h_iterate.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, C.POINTER(NlistOpts), C.POINTER(HiterOpts),

@@ -63,4 +63,7 @@ def test_null_context_rejected(lib):
     assert L.sfcnl_sync(None) == _lib.E_ARG
     assert L.sfc_sort(None, 10, None, None, None, None, None, None, None, 0) == _lib.E_ARG
     assert L.nlist_pass(None, 10, 8, 1, 0, None, None, None, None, None, None, None, None, None) == _lib.E_ARG
+    par = _lib.LjParams(1.0, 0.01, 0.0, 0.05)
+    assert L.nlist_pass_lj(None, 10, 8, 1, 0, None, None, None, None, None, None, ctypes.byref(par), None, None,
+                           None, None) == _lib.E_ARG
     assert L.sfcnl_version().startswith(b"sfcnl")

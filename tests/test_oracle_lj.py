@@ -30,6 +30,7 @@ def test_two_body_minimum_and_zero_crossing():
     scale = 24.0 * 1.5 / r
     assert np.all(np.abs(out["f"]) <= 1e-12 * scale)
     np.testing.assert_allclose(out["e"], [-0.75, -0.75], rtol=1e-12)  # pair energy -eps, shared
+    np.testing.assert_allclose(out["escale"], [0.75, 0.75], rtol=1e-12)
     assert list(out["nnb"]) == [1, 1]
     # at r = sigma the Lennard-Jones energy is zero and the force repulsive
     out = oracle.lj(x, y, z, None, eps=1.5, sigma=r, r_cut=0.1)
@@ -108,7 +109,7 @@ def test_rows_subset():
     full = oracle.lj(x, y, z, q, **par)
     idx = np.array([0, 17, 499, 250])
     sub = oracle.lj(x, y, z, q, **par, idx=idx)
-    for k in ("f", "e", "scale", "nnb"):
+    for k in ("f", "e", "scale", "escale", "nnb"):
         np.testing.assert_array_equal(sub[k], full[k][idx])
 
 
