@@ -41,6 +41,14 @@ FLOPS_PER_PAIR = 17     # dx, dy, dz (3); d2 (5); sqrt (1); q (1); spline piece 
 FLOPS_PER_PAIR_HALF = 25  # one distance (9), then q, spline piece, m*W, += for both particles (2 x 8)
 
 
+# Lennard-Jones + Coulomb pass, per evaluated tile pair: dx, dy, dz (3); d2 (3);
+# cutoff compare (1); 1/r^2, (sigma^2/r^2)^3, 24 eps (2 s6 - 1) s6 / r^2 (7);
+# 1/r, k q_i q_j / r, fma into the force factor (4); select (1); three fma into
+# the force sums (3). The half list adds three products and three sums for j.
+LJ_FLOPS_PER_PAIR = 22
+LJ_FLOPS_PER_PAIR_HALF = 28
+
+
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
@@ -272,6 +280,97 @@ def run_batch(args, sf, torch, ctx):
     print(json.dumps(out), flush=True)
 
 
+def run_lj(args, sf, torch, ctx):
+    """The Lennard-Jones benchmark of Sec. III: a near-uniform box of 160^3
+    atoms, the list built once at the radius holding ~200 neighbours and the
+    12/6 Lennard-Jones + Coulomb forces evaluated inside the ~150-neighbour
+    cutoff (a Verlet buffer). Times the list build (keys to encode) and the
+    force pass separately for every cluster size, list form and compression;
+    the JSON line reports the configuration given by the flags."""
+    import numpy as np
+    from paper_2602_19873_amd import workloads
+    s = workloads.make_config("lj_4m", args.n or None)
+    n, mt = s.n, s.meta
+    log("lj: %s n=%d r_list=%.5f r_cut=%.5f" % (s.name, n, mt["r_list"], mt["r_cut"]))
+    dev = torch.device("cuda:0")
+    x, y, z, h, q = (torch.from_numpy(a).to(dev) for a in (s.x, s.y, s.z, s.h, s.q))
+    main_cfg = (args.cluster_size, bool(args.compress), bool(args.half))
+    cfgs = [(cs, c, hf) for cs in (8, 4, 16) for hf in (True, False) for c in (True, False)] if args.sweep else []
+    if main_cfg not in cfgs:
+        cfgs.append(main_cfg)
+    sweep, main = {}, None
+    for cs, comp, hf in cfgs:
+        pipe = sf.Pipeline(ctx, n, s.box, compress=comp, leaf_bucket=args.leaf_bucket, cluster_size=cs, half=hf,
+                           max_j_per_sc=512, with_mass=True)
+        for _ in range(max(args.warmup, 1)):
+            pipe.step(x, y, z, h, q, density=False)
+        torch.cuda.synchronize()
+        ctx.profile_begin(args.steps)
+        for _ in range(args.steps):
+            pipe.step(x, y, z, h, q, density=False)
+        prof_build = ctx.profile_end()
+        nl = pipe.nl
+        xs, ys, zs, _, qs = pipe.sorted
+        f = ctx.empty((3, n), torch.float32)
+        for _ in range(max(args.warmup, 1)):
+            sf.nlist_pass_lj(ctx, nl, xs, ys, zs, qs, mt["eps"], mt["sigma"], mt["coulomb"], mt["r_cut"], f=f)
+        torch.cuda.synchronize()
+        ctx.profile_begin(args.steps)
+        t0 = time.perf_counter()
+        for _ in range(args.steps):
+            sf.nlist_pass_lj(ctx, nl, xs, ys, zs, qs, mt["eps"], mt["sigma"], mt["coulomb"], mt["r_cut"], f=f)
+        torch.cuda.synchronize()
+        wall = (time.perf_counter() - t0) * 1e3 / args.steps
+        prof_pass = ctx.profile_end()
+        build_ms = sum(ms / c for k, (ms, c) in prof_build.items() if c and k != "pass")
+        pass_ms = prof_pass["pass"][0] / prof_pass["pass"][1]
+        st = list_stats(sf, ctx, nl)
+        fl = LJ_FLOPS_PER_PAIR_HALF if hf else LJ_FLOPS_PER_PAIR
+        tf = st["tile_pairs"] * fl / (pass_ms * 1e-3) / 1e12
+        key = "cs%d_%s_%s" % (cs, "half" if hf else "full", "nibble" if comp else "plain")
+        rec = {"build_ms": build_ms, "pass_ms": pass_ms, "pass_wall_ms": wall, "build_over_pass": build_ms / pass_ms,
+               "bytes_per_particle": st["bytes_per_particle"], "tile_pairs_per_particle": st["tile_pairs"] / n,
+               "pass_tflops": tf, "build_stages_ms": {k: ms / c for k, (ms, c) in prof_build.items() if c}}
+        sweep[key] = rec
+        log("%-22s build %.3f ms  pass %.3f ms  (%.2fx)  %.3f B/p  %.0f tile pairs/p  %.1f TFLOP/s"
+            % (key, build_ms, pass_ms, build_ms / pass_ms, st["bytes_per_particle"], st["tile_pairs"] / n, tf))
+        if (cs, comp, hf) == main_cfg:
+            main = (key, rec, st)
+        del pipe, nl, f
+        torch.cuda.empty_cache()
+    key, rec, st = main
+    cs, comp, hf = main_cfg
+    hb = "true" if hf else "false"
+    kern = "k_pass_lj%s<%d, %s, true, false>" % ("_half" if hf else "", cs, "true" if comp else "false")
+    out = {
+        "metric": "Lennard-Jones 12/6 + Coulomb force pass over the compressed cluster list, Mparticles/s",
+        "value": n / (rec["pass_ms"] * 1e-3) / 1e6, "unit": "Mparticles/s", "n_gpus": 1, "steps": args.steps,
+        "warmup": args.warmup, "ms_per_step": rec["pass_ms"], "higher_is_better": True, "scaling": "weak",
+        "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+        "config": {"workload": s.name, "n": n, "cluster_size": cs, "compress": comp, "leaf_bucket": args.leaf_bucket,
+                   "list": "half (each pair once, j > i)" if hf else "full", "list_neighbours": 200,
+                   "cutoff_neighbours": 150, "charges": "rock salt +-1/2", "energy": False},
+        "build_ms": rec["build_ms"], "build_over_pass": rec["build_over_pass"],
+        "bytes_per_particle": rec["bytes_per_particle"], "list": st,
+        "roofline": {"kernel": kern, "bound": "alu", "achieved": rec["pass_tflops"], "peak": FP32_PEAK_TFLOPS,
+                     "unit": "TFLOP/s", "frac": rec["pass_tflops"] / FP32_PEAK_TFLOPS, "traffic": None,
+                     "avg_ms": rec["pass_ms"]},
+        "sweep": sweep,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        oracle.build()
+        rows = np.arange(n)
+        t0 = time.perf_counter()
+        oracle.lj(s.x, s.y, s.z, s.q, mt["eps"], mt["sigma"], mt["coulomb"], mt["r_cut"], idx=rows)
+        dt = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": rows.size / dt / 1e6, "unit": "Mparticles/s", "cores": oracle.num_threads(),
+                               "kind": "oracle", "seconds": dt,
+                               "sample": "FP64 Lennard-Jones + Coulomb forces of all %d atoms of the box (cell "
+                                         "list, no list build), %.1f s" % (n, dt)}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -285,13 +384,15 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after warm-up, copy this many MiB once (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=["step", "hiter", "batch"], default="step")
+    ap.add_argument("--mode", choices=["step", "hiter", "batch", "lj"], default="step")
     ap.add_argument("--target", type=int, default=0, help="neighbour target (hiter 100, batch 150)")
     ap.add_argument("--nsys", type=int, default=64)
     ap.add_argument("--train-systems", type=int, default=16)
     ap.add_argument("--train-epochs", type=int, default=20)
     ap.add_argument("--seed-h", choices=["global", "analytic"], default="global")
     ap.add_argument("--n", type=int, default=0)
+    ap.add_argument("--sweep", type=int, default=1, help="lj mode: also time every cluster size, list form and "
+                                                          "compression (0: only the flagged configuration)")
     args = ap.parse_args()
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
@@ -304,10 +405,12 @@ def main():
     import torch
     import paper_2602_19873_amd as sf
 
-    if args.mode in ("hiter", "batch"):
+    if args.mode in ("hiter", "batch", "lj"):
         torch.cuda.set_device(0)
         ctx = sf.Context(0)
-        if args.mode == "hiter":
+        if args.mode == "lj":
+            run_lj(args, sf, torch, ctx)
+        elif args.mode == "hiter":
             args.target = args.target or 100
             run_hiter(args, sf, torch, ctx)
         else:

@@ -449,7 +449,8 @@ class Pipeline:
         self.rho, self.nnb = e(max(n, 1), torch.float32), e(max(n, 1), torch.int32)
         self.nl = None
 
-    def step(self, x, y, z, h, m=None, want_counts=True):
+    def step(self, x, y, z, h, m=None, want_counts=True, density=True):
+        """One pass of the path; density=False stops after the list build."""
         ctx, n = self.ctx, self.n
         sfc_sort(ctx, x, y, z, self.box, self.keys, self.perm, self.sort_ws)
         fields = [x, y, z, h] + ([m] if m is not None else [])
@@ -464,7 +465,8 @@ class Pipeline:
         if nl.pool is not self.pool or nl.ws is not self.ws:  # grown on a retry: keep the larger buffers
             self.pool, self.ws, self.max_j_per_sc = nl.pool, nl.ws, nl.max_j_per_sc
         self.nl = nl
-        nlist_pass(ctx, nl, xs, ys, zs, hs, ms, self.rho, self.nnb if want_counts else None, want_counts)
+        if density:
+            nlist_pass(ctx, nl, xs, ys, zs, hs, ms, self.rho, self.nnb if want_counts else None, want_counts)
         return nl
 
 
