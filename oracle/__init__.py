@@ -64,13 +64,13 @@ def _load():
         lib.orc_is_pair.restype = C.c_int
         lib.orc_is_pair.argtypes = [C.c_float] * 8
         lib.orc_max_degree.restype = C.c_int64
-        lib.orc_max_degree.argtypes = [C.c_int64, f32p, f32p, f32p, f32p, C.c_int]
+        lib.orc_max_degree.argtypes = [C.c_int64, f32p, f32p, f32p, f32p, C.c_int, f32p]
         lib.orc_pairs_csr.restype = None
-        lib.orc_pairs_csr.argtypes = [C.c_int64, f32p, f32p, f32p, f32p, C.c_int, i64p, C.c_void_p]
+        lib.orc_pairs_csr.argtypes = [C.c_int64, f32p, f32p, f32p, f32p, C.c_int, i64p, C.c_void_p, f32p]
         lib.orc_cluster_list.restype = C.c_int
         lib.orc_cluster_list.argtypes = [C.c_int64, f32p, f32p, f32p, f32p, C.c_int, C.c_int, C.c_int, C.c_int64,
                                          C.c_void_p, C.c_int64, C.POINTER(C.c_void_p),
-                                         C.POINTER(C.c_void_p), C.POINTER(C.c_void_p)]
+                                         C.POINTER(C.c_void_p), C.POINTER(C.c_void_p), f32p]
         lib.orc_free.restype = None
         lib.orc_free.argtypes = [C.c_void_p]
         lib.orc_encode_block_symbols.restype = C.c_int
@@ -83,10 +83,10 @@ def _load():
         lib.orc_kernel_w.restype = C.c_double
         lib.orc_kernel_w.argtypes = [C.c_double, C.c_double]
         lib.orc_density.restype = None
-        lib.orc_density.argtypes = [C.c_int64, f32p, f32p, f32p, f32p, C.c_void_p, C.c_int, f64p, i32p]
+        lib.orc_density.argtypes = [C.c_int64, f32p, f32p, f32p, f32p, C.c_void_p, C.c_int, f64p, i32p, f32p]
         lib.orc_lj.restype = None
         lib.orc_lj.argtypes = [C.c_int64, f32p, f32p, f32p, C.c_void_p, C.c_double, C.c_double, C.c_double,
-                               C.c_float, C.c_int, C.c_void_p, C.c_int64, f64p, f64p, f64p, f64p, i32p]
+                               C.c_float, C.c_int, C.c_void_p, C.c_int64, f64p, f64p, f64p, f64p, i32p, f32p]
         lib.orc_num_threads.restype = C.c_int
         lib.orc_num_threads.argtypes = []
         _lib = lib
@@ -95,6 +95,17 @@ def _load():
 
 def _f32(a):
     return np.ascontiguousarray(a, dtype=np.float32)
+
+
+def _per(period):
+    """Periods as 3 float32 (0 = open axis); None = all open (Sec. II-A:
+    periodic boundaries by minimum images, no shift vectors)."""
+    if period is None:
+        return np.zeros(3, np.float32)
+    p = _f32(period).reshape(-1)
+    if p.shape[0] != 3 or not np.all(np.isfinite(p)) or np.any(p < 0):
+        raise ValueError("period must be 3 finite values >= 0")
+    return p
 
 
 def num_threads() -> int:
@@ -147,29 +158,32 @@ def is_pair(xi, yi, zi, hi, xj, yj, zj, hj) -> bool:
     return bool(_load().orc_is_pair(xi, yi, zi, hi, xj, yj, zj, hj))
 
 
-def pairs_csr(x, y, z, h, method: str = "brute"):
-    """Pair set P as CSR (offs[n+1], nbr ascending per particle)."""
+def pairs_csr(x, y, z, h, method: str = "brute", period=None):
+    """Pair set P as CSR (offs[n+1], nbr ascending per particle); period: 3
+    lengths (0 = open axis) for periodic boundaries."""
     x, y, z, h = _f32(x), _f32(y), _f32(z), _f32(h)
     n = x.shape[0]
     g = 1 if method == "grid" else 0
+    per = _per(period)
     offs = np.zeros(n + 1, dtype=np.int64)
     lib = _load()
-    lib.orc_pairs_csr(n, x, y, z, h, g, offs, None)
+    lib.orc_pairs_csr(n, x, y, z, h, g, offs, None, per)
     nbr = np.zeros(max(1, int(offs[-1])), dtype=np.int64)
-    lib.orc_pairs_csr(n, x, y, z, h, g, offs, nbr.ctypes.data)
+    lib.orc_pairs_csr(n, x, y, z, h, g, offs, nbr.ctypes.data, per)
     return offs, nbr[: offs[-1]]
 
 
-def max_degree(x, y, z, h, method: str = "grid") -> int:
+def max_degree(x, y, z, h, method: str = "grid", period=None) -> int:
     x, y, z, h = _f32(x), _f32(y), _f32(z), _f32(h)
-    return int(_load().orc_max_degree(x.shape[0], x, y, z, h, 1 if method == "grid" else 0))
+    return int(_load().orc_max_degree(x.shape[0], x, y, z, h, 1 if method == "grid" else 0, _per(period)))
 
 
-def cluster_list(x, y, z, h, cs: int = 8, method: str = "grid", sc_ids=None, half: bool = False):
+def cluster_list(x, y, z, h, cs: int = 8, method: str = "grid", sc_ids=None, half: bool = False, period=None):
     """Cluster-pair list of Sec. II-A: per selected super-cluster the
     ascending j-cluster indices and their i-cluster bitmasks. half: only
     pairs with j > i count (each pair of P stored once, Sec. II-D's symmetric
-    option).
+    option). period: periodic axes (minimum images; one entry per j-cluster
+    whatever image its pairs use, Sec. II-A's list without shift vectors).
 
     Returns (offs[nsel+1] int64, j uint32, mask uint16)."""
     x, y, z, h = _f32(x), _f32(y), _f32(z), _f32(h)
@@ -187,7 +201,7 @@ def cluster_list(x, y, z, h, cs: int = 8, method: str = "grid", sc_ids=None, hal
         ids_ptr = ids.ctypes.data
     po, pj, pm = C.c_void_p(), C.c_void_p(), C.c_void_p()
     rc = lib.orc_cluster_list(n, x, y, z, h, cs, int(bool(half)), g, nsel, ids_ptr, md, C.byref(po), C.byref(pj),
-                              C.byref(pm))
+                              C.byref(pm), _per(period))
     if rc != 0:
         raise MemoryError("oracle cluster list")
     offs = np.ctypeslib.as_array(C.cast(po, C.POINTER(C.c_int64)), shape=(nsel + 1,)).copy()
@@ -269,16 +283,17 @@ def kernel_w(r: float, h: float) -> float:
     return float(_load().orc_kernel_w(r, h))
 
 
-def density(x, y, z, h, m=None, method: str = "grid"):
+def density(x, y, z, h, m=None, method: str = "grid", period=None):
     """(rho float64, nnb int32): gather density with support h_i and the
-    number of j != i inside h_i (decided by the FP32 pair formula)."""
+    number of j != i inside h_i (decided by the FP32 pair formula, minimum
+    images on periodic axes)."""
     x, y, z, h = _f32(x), _f32(y), _f32(z), _f32(h)
     n = x.shape[0]
     rho = np.zeros(max(n, 1), np.float64)
     nnb = np.zeros(max(n, 1), np.int32)
     mm = None if m is None else _f32(m)
     _load().orc_density(n, x, y, z, h, None if mm is None else mm.ctypes.data,
-                        1 if method == "grid" else 0, rho, nnb)
+                        1 if method == "grid" else 0, rho, nnb, _per(period))
     return rho[:n], nnb[:n]
 
 
@@ -288,7 +303,7 @@ def density(x, y, z, h, m=None, method: str = "grid"):
 # --------------------------------------------------------------------------
 
 def lj(x, y, z, q=None, eps: float = 1.0, sigma: float = 1.0, coulomb: float = 0.0, r_cut: float = 1.0,
-       method: str = "grid", idx=None):
+       method: str = "grid", idx=None, period=None):
     """Pair forces of U(r) = 4 eps ((sigma/r)^12 - (sigma/r)^6) + k q_i q_j / r
     over the pairs j != i with d2 < f32(r_cut^2) (the FP32 pair formula).
 
@@ -308,7 +323,7 @@ def lj(x, y, z, q=None, eps: float = 1.0, sigma: float = 1.0, coulomb: float = 0
     nnb = np.zeros(max(rows, 1), np.int32)
     _load().orc_lj(n, x, y, z, None if qq is None else qq.ctypes.data, float(eps), float(sigma), float(coulomb),
                    float(r_cut), 1 if method == "grid" else 0, None if ii is None else ii.ctypes.data, rows,
-                   f.reshape(-1), e, sc, esc, nnb)
+                   f.reshape(-1), e, sc, esc, nnb, _per(period))
     return dict(f=f[:rows], e=e[:rows], scale=sc[:rows], escale=esc[:rows], nnb=nnb[:rows])
 
 
@@ -317,16 +332,16 @@ def lj(x, y, z, q=None, eps: float = 1.0, sigma: float = 1.0, coulomb: float = 0
 # --------------------------------------------------------------------------
 
 def pipeline(x, y, z, h, box, m=None, cs: int = 8, compress: bool = True, method: str = "grid",
-             half: bool = False):
+             half: bool = False, period=None):
     """Hilbert keys -> stable order -> SFC-ordered arrays -> cluster list ->
     encoding -> density, all in SFC order. Returns a dict."""
     keys = hilbert_keys(x, y, z, box)
     perm = sfc_order(keys)
     xs, ys, zs, hs = (np.asarray(a)[perm] for a in (x, y, z, h))
     ms = None if m is None else np.asarray(m)[perm]
-    offs, jj, mm = cluster_list(xs, ys, zs, hs, cs, method, half=half)
+    offs, jj, mm = cluster_list(xs, ys, zs, hs, cs, method, half=half, period=period)
     info, pool = encode_all(offs, jj, mm, cs, compress)
-    rho, nnb = density(xs, ys, zs, hs, ms, method)
+    rho, nnb = density(xs, ys, zs, hs, ms, method, period=period)
     return dict(keys=keys, perm=perm, sorted_keys=keys[perm], x=xs, y=ys, z=zs, h=hs, m=ms,
                 offs=offs, j=jj, mask=mm, sc_info=info, pool=pool, rho=rho, nnb=nnb)
 

@@ -20,6 +20,8 @@
  *     FP64 (Sec. II-D, Listing 1).
  *   - Lennard-Jones 12/6 + Coulomb forces of the pairs inside an interaction
  *     cutoff shorter than the list cutoff (Sec. III, Lennard-Jones benchmark).
+ *   - Periodic boundaries without shift vectors: every distance test takes
+ *     the minimum image of each component on periodic axes (Sec. II-A).
  *
  * Must be compiled with -ffp-contract=off: the FP32 pair test below spells
  * out every rounding step and no other contraction is allowed.
@@ -107,29 +109,72 @@ void orc_hilbert_keys(int64_t n, const float *x, const float *y, const float *z,
 /* The FP32 pair test                                                         */
 /* ------------------------------------------------------------------------- */
 
-/* d2 = fma(dz, dz, fma(dy, dy, dx*dx)) with dx = f32(x_j - x_i) etc.;
- * the pair is in P iff d2 < f32(max(h_i, h_j)^2), strictly. */
-static float orc_d2(float xi, float yi, float zi, float xj, float yj, float zj)
+/* Periodic axes (Sec. II-A: periodic boundaries without shift vectors, the
+ * periodic distance of a pair computed whenever it is needed): per[a] > 0
+ * makes axis a periodic with length per[a], 0 leaves it open. A component
+ * difference d = f32(x_j - x_i) becomes its minimum image in FP32: d - L if
+ * d > f32(L/2), d + L if d < -f32(L/2). Positions lie within one period, so
+ * |d| < L and one step suffices. */
+static float orc_min_image(float d, float L)
 {
-    float dx = xj - xi;
-    float dy = yj - yi;
-    float dz = zj - zi;
+    if (L > 0.0f) {
+        float hl = 0.5f * L;
+        if (d > hl)
+            d = d - L;
+        else if (d < -hl)
+            d = d + L;
+    }
+    return d;
+}
+
+/* The same image choice on the exact FP64 difference of two FP32 coordinates,
+ * for the values computed on accepted pairs (their distance is below every
+ * radius, which is below L/2, so both rules pick the same image). */
+static double orc_diff64(float xj, float xi, float L)
+{
+    double d = (double)xj - (double)xi;
+    if (L > 0.0f) {
+        if (d > 0.5 * (double)L)
+            d -= (double)L;
+        else if (d < -0.5 * (double)L)
+            d += (double)L;
+    }
+    return d;
+}
+
+/* d2 = fma(dz, dz, fma(dy, dy, dx*dx)) with dx = f32(x_j - x_i) etc. (minimum
+ * images on periodic axes); the pair is in P iff d2 < f32(max(h_i, h_j)^2),
+ * strictly. */
+static float orc_d2(const float *per, float xi, float yi, float zi, float xj, float yj, float zj)
+{
+    float dx = orc_min_image(xj - xi, per[0]);
+    float dy = orc_min_image(yj - yi, per[1]);
+    float dz = orc_min_image(zj - zi, per[2]);
     float dxx = dx * dx;
     return fmaf(dz, dz, fmaf(dy, dy, dxx));
 }
 
-int orc_is_pair(float xi, float yi, float zi, float hi, float xj, float yj, float zj, float hj)
+static int is_pair_p(const float *per, float xi, float yi, float zi, float hi, float xj, float yj, float zj,
+                     float hj)
 {
-    float d2 = orc_d2(xi, yi, zi, xj, yj, zj);
+    float d2 = orc_d2(per, xi, yi, zi, xj, yj, zj);
     float r = hi > hj ? hi : hj;
     float r2 = r * r;
     return d2 < r2;
 }
 
-/* Own-radius (gather) test used by the density and the neighbour count. */
-static int orc_in_own_radius(float xi, float yi, float zi, float hi, float xj, float yj, float zj)
+static const float orc_open[3] = {0.0f, 0.0f, 0.0f};
+
+int orc_is_pair(float xi, float yi, float zi, float hi, float xj, float yj, float zj, float hj)
 {
-    float d2 = orc_d2(xi, yi, zi, xj, yj, zj);
+    return is_pair_p(orc_open, xi, yi, zi, hi, xj, yj, zj, hj);
+}
+
+/* Own-radius (gather) test used by the density and the neighbour count. */
+static int orc_in_own_radius(const float *per, float xi, float yi, float zi, float hi, float xj, float yj,
+                             float zj)
+{
+    float d2 = orc_d2(per, xi, yi, zi, xj, yj, zj);
     float r2 = hi * hi;
     return d2 < r2;
 }
@@ -139,22 +184,31 @@ static int orc_in_own_radius(float xi, float yi, float zi, float hi, float xj, f
 /* ------------------------------------------------------------------------- */
 
 typedef struct {
-    double lo[3], edge;
+    double lo[3], edge[3];
     int64_t dim[3];
+    float per[3];   /* periods (0: open axis) */
     int64_t *start; /* ncell + 1 */
     int64_t *idx;   /* particles sorted by cell */
 } orc_grid;
 
+static void grid_init(orc_grid *g, const float *period)
+{
+    memset(g, 0, sizeof *g);
+    for (int a = 0; a < 3; a++) g->per[a] = (period && period[a] > 0.0f) ? period[a] : 0.0f;
+}
+
 static int64_t grid_cell1(const orc_grid *g, int a, double v)
 {
-    int64_t c = (int64_t)floor((v - g->lo[a]) / g->edge);
+    int64_t c = (int64_t)floor((v - g->lo[a]) / g->edge[a]);
     if (c < 0) c = 0;
     if (c >= g->dim[a]) c = g->dim[a] - 1;
     return c;
 }
 
 /* Cells of edge >= max radius * (1 + 2^-20): every FP32-accepted pair lies in
- * adjacent cells, since FP32 rounding accepts pairs at most a few ulp beyond R. */
+ * adjacent cells, since FP32 rounding accepts pairs at most a few ulp beyond R.
+ * On a periodic axis the cells tile the period exactly (edge = L / dim), so a
+ * pair whose minimum image wraps lies in the first and last cells. */
 static void grid_build(orc_grid *g, int64_t n, const float *x, const float *y, const float *z,
                        const float *h)
 {
@@ -169,18 +223,28 @@ static void grid_build(orc_grid *g, int64_t n, const float *x, const float *y, c
         if (h[i] > hmax) hmax = h[i];
     }
     if (n == 0) { lo[0] = lo[1] = lo[2] = 0.0; hi[0] = hi[1] = hi[2] = 0.0; }
-    double edge = hmax * (1.0 + ldexp(1.0, -20));
+    double need = hmax * (1.0 + ldexp(1.0, -20));
+    double edge = need;
     double ext = 0.0;
     for (int a = 0; a < 3; a++) if (hi[a] - lo[a] > ext) ext = hi[a] - lo[a];
     /* keep the cell count near N: a coarser grid is still exact, just slower */
     double cap = ceil(cbrt((double)(n > 1 ? n : 1))) + 1.0;
     if (edge <= 0.0 || ext / edge > cap) edge = ext / cap;
     if (edge <= 0.0) edge = 1.0;
-    g->edge = edge;
     int64_t ncell = 1;
     for (int a = 0; a < 3; a++) {
         g->lo[a] = lo[a];
-        g->dim[a] = (int64_t)floor((hi[a] - lo[a]) / edge) + 1;
+        if (g->per[a] > 0.0f) {
+            double L = (double)g->per[a];
+            int64_t d = need > 0.0 ? (int64_t)floor(L / need) : (int64_t)cap;
+            if (d > (int64_t)cap) d = (int64_t)cap;
+            if (d < 1) d = 1;
+            g->dim[a] = d;
+            g->edge[a] = L / (double)d;
+        } else {
+            g->edge[a] = edge;
+            g->dim[a] = (int64_t)floor((hi[a] - lo[a]) / edge) + 1;
+        }
         ncell *= g->dim[a];
     }
     g->start = (int64_t *)calloc((size_t)ncell + 1, sizeof(int64_t));
@@ -206,6 +270,62 @@ static void grid_free(orc_grid *g)
     free(g->idx);
 }
 
+/* Cells along axis a next to cell c (c - 1, c, c + 1; wrapped on a periodic
+ * axis), each once. */
+static int axis_cells(const orc_grid *g, int a, int64_t c, int64_t *out)
+{
+    int k = 0;
+    for (int64_t dc = -1; dc <= 1; dc++) {
+        int64_t v = c + dc;
+        if (g->per[a] > 0.0f)
+            v = ((v % g->dim[a]) + g->dim[a]) % g->dim[a];
+        else if (v < 0 || v >= g->dim[a])
+            continue;
+        int dup = 0;
+        for (int t = 0; t < k; t++) dup |= out[t] == v;
+        if (!dup) out[k++] = v;
+    }
+    return k;
+}
+
+/* The cells that can hold a partner of a particle at (xi, yi, zi): the 3x3x3
+ * block around its cell (at most 27 cells). */
+static int cells_around(const orc_grid *g, float xi, float yi, float zi, int64_t *cells)
+{
+    int64_t cx[3], cy[3], cz[3];
+    int nx = axis_cells(g, 0, grid_cell1(g, 0, xi), cx);
+    int ny = axis_cells(g, 1, grid_cell1(g, 1, yi), cy);
+    int nz = axis_cells(g, 2, grid_cell1(g, 2, zi), cz);
+    int k = 0;
+    for (int iz = 0; iz < nz; iz++)
+        for (int iy = 0; iy < ny; iy++)
+            for (int ix = 0; ix < nx; ix++) cells[k++] = (cz[iz] * g->dim[1] + cy[iy]) * g->dim[0] + cx[ix];
+    return k;
+}
+
+/* Candidate range t of particle i: cell t of its block (grid) or all particles. */
+static int candidate_ranges(const orc_grid *g, int use_grid, int64_t n, float xi, float yi, float zi,
+                            int64_t *cells)
+{
+    if (!use_grid) {
+        cells[0] = -1;
+        return 1;
+    }
+    (void)n;
+    return cells_around(g, xi, yi, zi, cells);
+}
+
+static void range_of(const orc_grid *g, int64_t n, int64_t cell, int64_t *k0, int64_t *k1)
+{
+    if (cell < 0) {
+        *k0 = 0;
+        *k1 = n;
+    } else {
+        *k0 = g->start[cell];
+        *k1 = g->start[cell + 1];
+    }
+}
+
 static int cmp_i64(const void *a, const void *b)
 {
     int64_t x = *(const int64_t *)a, y = *(const int64_t *)b;
@@ -218,45 +338,30 @@ static int64_t neighbours_of(const orc_grid *g, int use_grid, int64_t n, const f
                              const float *z, const float *h, int64_t i, int64_t *out, int64_t cap)
 {
     int64_t cnt = 0;
-    if (!use_grid) {
-        for (int64_t j = 0; j < n; j++) {
+    int64_t cells[27];
+    int nc = candidate_ranges(g, use_grid, n, x[i], y[i], z[i], cells);
+    for (int t = 0; t < nc; t++) {
+        int64_t k0, k1;
+        range_of(g, n, cells[t], &k0, &k1);
+        for (int64_t k = k0; k < k1; k++) {
+            int64_t j = cells[t] < 0 ? k : g->idx[k];
             if (j == i) continue;
-            if (orc_is_pair(x[i], y[i], z[i], h[i], x[j], y[j], z[j], h[j])) {
+            if (is_pair_p(g->per, x[i], y[i], z[i], h[i], x[j], y[j], z[j], h[j])) {
                 if (cnt < cap) out[cnt] = j;
                 cnt++;
             }
         }
-        return cnt;
     }
-    int64_t cx = grid_cell1(g, 0, x[i]), cy = grid_cell1(g, 1, y[i]), cz = grid_cell1(g, 2, z[i]);
-    for (int64_t az = cz - 1; az <= cz + 1; az++) {
-        if (az < 0 || az >= g->dim[2]) continue;
-        for (int64_t ay = cy - 1; ay <= cy + 1; ay++) {
-            if (ay < 0 || ay >= g->dim[1]) continue;
-            for (int64_t ax = cx - 1; ax <= cx + 1; ax++) {
-                if (ax < 0 || ax >= g->dim[0]) continue;
-                int64_t c = (az * g->dim[1] + ay) * g->dim[0] + ax;
-                for (int64_t k = g->start[c]; k < g->start[c + 1]; k++) {
-                    int64_t j = g->idx[k];
-                    if (j == i) continue;
-                    if (orc_is_pair(x[i], y[i], z[i], h[i], x[j], y[j], z[j], h[j])) {
-                        if (cnt < cap) out[cnt] = j;
-                        cnt++;
-                    }
-                }
-            }
-        }
-    }
-    if (cnt <= cap) qsort(out, (size_t)cnt, sizeof(int64_t), cmp_i64);
+    if (cnt <= cap && cnt > 1) qsort(out, (size_t)cnt, sizeof(int64_t), cmp_i64);
     return cnt;
 }
 
 /* Maximum |P_i| over all i (to size buffers). */
 int64_t orc_max_degree(int64_t n, const float *x, const float *y, const float *z, const float *h,
-                       int use_grid)
+                       int use_grid, const float *period)
 {
     orc_grid g;
-    memset(&g, 0, sizeof g);
+    grid_init(&g, period);
     if (use_grid) grid_build(&g, n, x, y, z, h);
     int64_t mx = 0;
 #pragma omp parallel for schedule(dynamic, 256) reduction(max : mx)
@@ -269,12 +374,13 @@ int64_t orc_max_degree(int64_t n, const float *x, const float *y, const float *z
 }
 
 /* Pair set as CSR: offs[n+1], nbr[offs[i]..offs[i+1]) ascending.
- * Call with nbr == NULL to get the counts in offs only. */
+ * Call with nbr == NULL to get the counts in offs only. period: 3 floats
+ * (0 = open axis) or NULL (all open). */
 void orc_pairs_csr(int64_t n, const float *x, const float *y, const float *z, const float *h, int use_grid,
-                   int64_t *offs, int64_t *nbr)
+                   int64_t *offs, int64_t *nbr, const float *period)
 {
     orc_grid g;
-    memset(&g, 0, sizeof g);
+    grid_init(&g, period);
     if (use_grid) grid_build(&g, n, x, y, z, h);
     if (nbr == NULL) {
         offs[0] = 0;
@@ -347,11 +453,11 @@ static void sc_list_one(const orc_grid *g, int use_grid, int64_t n, const float 
  * released with orc_free. Returns 0, or -1 on allocation failure. */
 int orc_cluster_list(int64_t n, const float *x, const float *y, const float *z, const float *h, int cs, int half,
                      int use_grid, int64_t nsel, const int64_t *sc_ids, int64_t max_degree,
-                     int64_t **out_offs, uint32_t **out_j, uint16_t **out_mask)
+                     int64_t **out_offs, uint32_t **out_j, uint16_t **out_mask, const float *period)
 {
     int64_t nclu = (n + cs - 1) / cs;
     orc_grid g;
-    memset(&g, 0, sizeof g);
+    grid_init(&g, period);
     if (use_grid) grid_build(&g, n, x, y, z, h);
     orc_sc_list *lists = (orc_sc_list *)calloc((size_t)(nsel > 0 ? nsel : 1), sizeof(orc_sc_list));
     int64_t nbcap = max_degree > 0 ? max_degree : 1;
@@ -571,52 +677,36 @@ double orc_kernel_w(double r, double h)
 }
 
 /* rho_i = m_i W(0, h_i) + sum over j != i with d2 < f32(h_i^2) of m_j W(r_ij, h_i),
- * r_ij from the exact FP64 differences of the FP32 coordinates. The set of j
- * is decided by the same FP32 test as the pair set. nnb_i = size of that set.
- * m == NULL means unit masses. */
+ * r_ij from the exact FP64 differences of the FP32 coordinates (minimum
+ * images on periodic axes). The set of j is decided by the same FP32 test as
+ * the pair set. nnb_i = size of that set. m == NULL means unit masses. */
 void orc_density(int64_t n, const float *x, const float *y, const float *z, const float *h, const float *m,
-                 int use_grid, double *rho, int32_t *nnb)
+                 int use_grid, double *rho, int32_t *nnb, const float *period)
 {
     orc_grid g;
-    memset(&g, 0, sizeof g);
+    grid_init(&g, period);
     if (use_grid) grid_build(&g, n, x, y, z, h);
 #pragma omp parallel for schedule(dynamic, 256)
     for (int64_t i = 0; i < n; i++) {
         double mi = m ? (double)m[i] : 1.0;
         double acc = mi * orc_kernel_w(0.0, (double)h[i]);
         int32_t cnt = 0;
-        int64_t cx = 0, cy = 0, cz = 0, r0 = 0, r1 = 0;
-        if (use_grid) {
-            cx = grid_cell1(&g, 0, x[i]);
-            cy = grid_cell1(&g, 1, y[i]);
-            cz = grid_cell1(&g, 2, z[i]);
-            r0 = -1;
-            r1 = 1;
-        }
-        for (int64_t az = cz + r0; az <= cz + r1; az++) {
-            for (int64_t ay = cy + r0; ay <= cy + r1; ay++) {
-                for (int64_t ax = cx + r0; ax <= cx + r1; ax++) {
-                    int64_t k0 = 0, k1 = n;
-                    if (use_grid) {
-                        if (az < 0 || az >= g.dim[2] || ay < 0 || ay >= g.dim[1] || ax < 0 || ax >= g.dim[0])
-                            continue;
-                        int64_t c = (az * g.dim[1] + ay) * g.dim[0] + ax;
-                        k0 = g.start[c];
-                        k1 = g.start[c + 1];
-                    }
-                    for (int64_t k = k0; k < k1; k++) {
-                        int64_t j = use_grid ? g.idx[k] : k;
-                        if (j == i) continue;
-                        if (!orc_in_own_radius(x[i], y[i], z[i], h[i], x[j], y[j], z[j])) continue;
-                        double dx = (double)x[j] - (double)x[i];
-                        double dy = (double)y[j] - (double)y[i];
-                        double dz = (double)z[j] - (double)z[i];
-                        double r = sqrt(dx * dx + dy * dy + dz * dz);
-                        double mj = m ? (double)m[j] : 1.0;
-                        acc += mj * orc_kernel_w(r, (double)h[i]);
-                        cnt++;
-                    }
-                }
+        int64_t cells[27];
+        int nc = candidate_ranges(&g, use_grid, n, x[i], y[i], z[i], cells);
+        for (int t = 0; t < nc; t++) {
+            int64_t k0, k1;
+            range_of(&g, n, cells[t], &k0, &k1);
+            for (int64_t k = k0; k < k1; k++) {
+                int64_t j = cells[t] < 0 ? k : g.idx[k];
+                if (j == i) continue;
+                if (!orc_in_own_radius(g.per, x[i], y[i], z[i], h[i], x[j], y[j], z[j])) continue;
+                double dx = orc_diff64(x[j], x[i], g.per[0]);
+                double dy = orc_diff64(y[j], y[i], g.per[1]);
+                double dz = orc_diff64(z[j], z[i], g.per[2]);
+                double r = sqrt(dx * dx + dy * dy + dz * dz);
+                double mj = m ? (double)m[j] : 1.0;
+                acc += mj * orc_kernel_w(r, (double)h[i]);
+                cnt++;
             }
         }
         rho[i] = acc;
@@ -642,15 +732,16 @@ void orc_density(int64_t n, const float *x, const float *y, const float *z, cons
  * scale_i = sum_j |F_ij| and escale_i = 1/2 sum_j |U(r_ij)| (the sizes of the
  * terms, for rounding-error bounds).
  * q == NULL means no charges. idx (nullable, count nidx) restricts the output
- * to those particles: row t of the outputs is particle idx[t]. */
+ * to those particles: row t of the outputs is particle idx[t]. Periodic axes
+ * as for the pair set (minimum images). */
 void orc_lj(int64_t n, const float *x, const float *y, const float *z, const float *q, double eps, double sigma,
             double kc, float rc, int use_grid, const int64_t *idx, int64_t nidx, double *f, double *e,
-            double *scale, double *escale, int32_t *nnb)
+            double *scale, double *escale, int32_t *nnb, const float *period)
 {
     float *hr = (float *)malloc((size_t)(n > 0 ? n : 1) * sizeof(float));
     for (int64_t i = 0; i < n; i++) hr[i] = rc;
     orc_grid g;
-    memset(&g, 0, sizeof g);
+    grid_init(&g, period);
     if (use_grid) grid_build(&g, n, x, y, z, hr);
     int64_t rows = idx ? nidx : n;
 #pragma omp parallel for schedule(dynamic, 256)
@@ -658,48 +749,32 @@ void orc_lj(int64_t n, const float *x, const float *y, const float *z, const flo
         int64_t i = idx ? idx[t] : t;
         double fx = 0.0, fy = 0.0, fz = 0.0, en = 0.0, sc = 0.0, esc = 0.0;
         int32_t cnt = 0;
-        int64_t cx = 0, cy = 0, cz = 0, r0 = 0, r1 = 0;
-        if (use_grid) {
-            cx = grid_cell1(&g, 0, x[i]);
-            cy = grid_cell1(&g, 1, y[i]);
-            cz = grid_cell1(&g, 2, z[i]);
-            r0 = -1;
-            r1 = 1;
-        }
-        for (int64_t az = cz + r0; az <= cz + r1; az++) {
-            for (int64_t ay = cy + r0; ay <= cy + r1; ay++) {
-                for (int64_t ax = cx + r0; ax <= cx + r1; ax++) {
-                    int64_t k0 = 0, k1 = n;
-                    if (use_grid) {
-                        if (az < 0 || az >= g.dim[2] || ay < 0 || ay >= g.dim[1] || ax < 0 || ax >= g.dim[0])
-                            continue;
-                        int64_t c = (az * g.dim[1] + ay) * g.dim[0] + ax;
-                        k0 = g.start[c];
-                        k1 = g.start[c + 1];
-                    }
-                    for (int64_t k = k0; k < k1; k++) {
-                        int64_t j = use_grid ? g.idx[k] : k;
-                        if (j == i) continue;
-                        if (!orc_in_own_radius(x[i], y[i], z[i], rc, x[j], y[j], z[j])) continue;
-                        double dx = (double)x[i] - (double)x[j];
-                        double dy = (double)y[i] - (double)y[j];
-                        double dz = (double)z[i] - (double)z[j];
-                        double r2 = dx * dx + dy * dy + dz * dz;
-                        double r = sqrt(r2);
-                        double sr6 = pow(sigma / r, 6.0);
-                        double qq = q ? (double)q[i] * (double)q[j] : 0.0;
-                        /* -dU/dr divided by r */
-                        double fr = (24.0 * eps * (2.0 * sr6 * sr6 - sr6) + kc * qq / r) / r2;
-                        fx += fr * dx;
-                        fy += fr * dy;
-                        fz += fr * dz;
-                        double u = 4.0 * eps * (sr6 * sr6 - sr6) + kc * qq / r;
-                        en += 0.5 * u;
-                        esc += 0.5 * fabs(u);
-                        sc += fabs(fr) * r;
-                        cnt++;
-                    }
-                }
+        int64_t cells[27];
+        int nc = candidate_ranges(&g, use_grid, n, x[i], y[i], z[i], cells);
+        for (int u = 0; u < nc; u++) {
+            int64_t k0, k1;
+            range_of(&g, n, cells[u], &k0, &k1);
+            for (int64_t k = k0; k < k1; k++) {
+                int64_t j = cells[u] < 0 ? k : g.idx[k];
+                if (j == i) continue;
+                if (!orc_in_own_radius(g.per, x[i], y[i], z[i], rc, x[j], y[j], z[j])) continue;
+                double dx = -orc_diff64(x[j], x[i], g.per[0]);
+                double dy = -orc_diff64(y[j], y[i], g.per[1]);
+                double dz = -orc_diff64(z[j], z[i], g.per[2]);
+                double r2 = dx * dx + dy * dy + dz * dz;
+                double r = sqrt(r2);
+                double sr6 = pow(sigma / r, 6.0);
+                double qq = q ? (double)q[i] * (double)q[j] : 0.0;
+                /* -dU/dr divided by r */
+                double fr = (24.0 * eps * (2.0 * sr6 * sr6 - sr6) + kc * qq / r) / r2;
+                fx += fr * dx;
+                fy += fr * dy;
+                fz += fr * dz;
+                double u_ = 4.0 * eps * (sr6 * sr6 - sr6) + kc * qq / r;
+                en += 0.5 * u_;
+                esc += 0.5 * fabs(u_);
+                sc += fabs(fr) * r;
+                cnt++;
             }
         }
         f[3 * t] = fx;
