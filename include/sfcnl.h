@@ -128,6 +128,17 @@ int build_clusters(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y,
  *                 the pairs with j > i (the symmetric option of Sec. II-D,
  *                 each pair stored once): masks count only such pairs, and a
  *                 super-cluster lists no j-cluster that ends before it.
+ *   period        periodic boundaries without shift vectors (Sec. II-A):
+ *                 period[a] > 0 makes axis a periodic with that length, 0
+ *                 leaves it open (finite, >= 0). Every distance test then
+ *                 uses the minimum image of each periodic component in FP32,
+ *                 d - L if d > f32(L/2), d + L if d < -f32(L/2), before the
+ *                 pair formula; the list stores one entry per j-cluster, with
+ *                 no image index, and the passes recompute the image. The
+ *                 positions must span less than one period and every radius
+ *                 must stay below half of it (else SFCNL_E_INPUT, flag 8).
+ *                 Batched calls take open boundaries only. A zeroed field
+ *                 (the C default of an initialised struct) means open.
  * Workspace: at least build_nlist_workspace(n, opts) bytes.
  * Returns SFCNL_OK, or SFCNL_E_CAPACITY when the pool (pool_bytes) or the
  * staging list is too small: then *h_used_bytes is the pool size needed and
@@ -141,6 +152,7 @@ typedef struct {
     int leaf_bucket;
     int max_j_per_sc;
     int half;
+    float period[3];
 } sfcnl_nlist_opts;
 
 int build_nlist_workspace(int64_t n, const sfcnl_nlist_opts *opts, size_t *ws_bytes);
@@ -160,10 +172,11 @@ int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d
  * half list (built with opts->half): each stored pair then feeds both
  * particles (Sec. II-D's symmetric evaluation), added with atomics, so the
  * last bits of rho may differ from run to run (nnb stays exact). A full list
- * must be passed with half = 0. */
+ * must be passed with half = 0. h_period: host pointer to the 3 periods the
+ * list was built with (opts->period), or NULL for open boundaries. */
 int nlist_pass(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, int half, const uint32_t *d_sc_info,
                const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z,
-               const float *d_h, const float *d_m, float *d_rho, int32_t *d_nnb);
+               const float *d_h, const float *d_m, float *d_rho, int32_t *d_nnb, const float *h_period);
 
 /* ---- 4b. Lennard-Jones 12/6 + Coulomb pass (Sec. III, Lennard-Jones benchmark)
  * The benchmark pass of Sec. III with a Verlet buffer: the list is built once
@@ -180,7 +193,9 @@ int nlist_pass(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, int hal
  * Lennard-Jones). cluster_size, compress and half as given to build_nlist; a
  * half list feeds both particles of every stored pair (Newton's third law)
  * through float atomics, so the last bits vary from run to run. Two particles
- * at the same position give non-finite forces. */
+ * at the same position give non-finite forces. h_period: the 3 periods of the
+ * list (opts->period) or NULL for open boundaries; periodic pairs use their
+ * minimum images. */
 typedef struct {
     float eps;      /* Lennard-Jones well depth, finite */
     float sigma;    /* Lennard-Jones length, > 0 */
@@ -189,7 +204,8 @@ typedef struct {
 } sfcnl_lj_params;
 int nlist_pass_lj(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, int half, const uint32_t *d_sc_info,
                   const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z, const float *d_q,
-                  const sfcnl_lj_params *params, float *d_fx, float *d_fy, float *d_fz, float *d_epot);
+                  const sfcnl_lj_params *params, float *d_fx, float *d_fy, float *d_fz, float *d_epot,
+                  const float *h_period);
 
 /* Decodes the whole list on the device into flat arrays: super-cluster s's
  * entries go to [d_offsets[s], d_offsets[s] + n_j), with d_offsets the

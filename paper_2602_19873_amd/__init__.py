@@ -147,6 +147,7 @@ class NeighbourList:
     used_bytes: int
     max_nj: int
     half: bool = False        # only pairs with j > i (each pair once)
+    period: tuple = (0.0, 0.0, 0.0)  # periodic axes (0 = open), as built
 
     @property
     def n_sc(self) -> int:
@@ -156,8 +157,25 @@ class NeighbourList:
         return (self.used_bytes + 8 * self.n_sc) / max(self.n, 1)
 
 
-def _opts(cluster_size, compress, leaf_bucket, max_j_per_sc, half=False):
-    return _lib.NlistOpts(cluster_size, int(bool(compress)), leaf_bucket, max_j_per_sc, int(bool(half)))
+def _period(period):
+    """Periods as a tuple of 3 floats (0 = open axis); None = all open."""
+    if period is None:
+        return (0.0, 0.0, 0.0)
+    p = tuple(float(v) for v in period)
+    if len(p) != 3:
+        raise ValueError("period needs 3 values (0 = open axis)")
+    return p
+
+
+def _period_arg(period):
+    """Host pointer argument for the passes: NULL when every axis is open."""
+    p = _period(period)
+    return None if not any(p) else (C.c_float * 3)(*p)
+
+
+def _opts(cluster_size, compress, leaf_bucket, max_j_per_sc, half=False, period=None):
+    return _lib.NlistOpts(cluster_size, int(bool(compress)), leaf_bucket, max_j_per_sc, int(bool(half)),
+                          (C.c_float * 3)(*_period(period)))
 
 
 def build_nlist_workspace(n, cluster_size=CLUSTER_SIZE, compress=True, leaf_bucket=128, max_j_per_sc=512,
@@ -171,17 +189,18 @@ def build_nlist_workspace(n, cluster_size=CLUSTER_SIZE, compress=True, leaf_buck
 
 def build_nlist(ctx: Context, keys, x, y, z, h, bbox, compress: bool = True, leaf_bucket: int = 128,
                 max_j_per_sc: int = 512, cluster_size: int = CLUSTER_SIZE, pool=None, ws=None, sc_info=None,
-                grow: bool = True, half: bool = False):
-    """Builds the compressed cluster-pair list (half: each pair once, j > i).
-    Grows the staging list and the pool and retries when the library reports
-    they are too small (unless grow=False, which raises)."""
+                grow: bool = True, half: bool = False, period=None):
+    """Builds the compressed cluster-pair list (half: each pair once, j > i;
+    period: 3 lengths, 0 = open axis, for periodic boundaries by minimum
+    images). Grows the staging list and the pool and retries when the library
+    reports they are too small (unless grow=False, which raises)."""
     n = x.numel()
     nsc = (n + SC_SIZE - 1) // SC_SIZE
     sc_info = ctx.empty((max(nsc, 1), 2), torch.int32) if sc_info is None else sc_info
     if pool is None:
         pool = ctx.empty(max(1024, 5 * n), torch.int32)
     while True:
-        o = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc, half)
+        o = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc, half, period)
         need = build_nlist_workspace(n, cluster_size, compress, leaf_bucket, max_j_per_sc, half)
         if ws is None or ws.numel() < need:
             ws = ctx.empty(max(need, 1), torch.uint8)
@@ -198,7 +217,7 @@ def build_nlist(ctx: Context, keys, x, y, z, h, bbox, compress: bool = True, lea
             continue
         ctx.check(rc)
         nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, used.value, maxnj.value,
-                           bool(half))
+                           bool(half), _period(period))
         nl.ws = ws
         nl.max_j_per_sc = max_j_per_sc
         return nl
@@ -212,7 +231,7 @@ def nlist_pass(ctx: Context, nl: NeighbourList, x, y, z, h, m=None, rho=None, nn
         nnb = ctx.empty(n, torch.int32)
     ctx.check(ctx.lib.nlist_pass(ctx.handle, n, nl.cluster_size, int(nl.compress), int(nl.half), _ptr(nl.sc_info),
                                  _ptr(nl.pool), _ptr(x), _ptr(y), _ptr(z), _ptr(h), _ptr(m), _ptr(rho),
-                                 _ptr(nnb) if want_counts else None))
+                                 _ptr(nnb) if want_counts else None, _period_arg(nl.period)))
     return rho, nnb
 
 
@@ -233,7 +252,7 @@ def nlist_pass_lj(ctx: Context, nl: NeighbourList, x, y, z, q=None, eps: float =
     ctx.check(ctx.lib.nlist_pass_lj(ctx.handle, n, nl.cluster_size, int(nl.compress), int(nl.half),
                                     _ptr(nl.sc_info), _ptr(nl.pool), _ptr(x), _ptr(y), _ptr(z), _ptr(q),
                                     C.byref(par), _ptr(f[0]), _ptr(f[1]), _ptr(f[2]),
-                                    _ptr(e) if energy else None))
+                                    _ptr(e) if energy else None, _period_arg(nl.period)))
     return f[:, :n], (e[:n] if energy else None)
 
 
@@ -272,7 +291,8 @@ def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, m
               compress: bool = True, leaf_bucket: int = 128, max_j_per_sc: int = 512, bracket=None, bbox=None,
               ws=None, pool=None, sc_info=None, rho=None, nnb=None, raise_noconv: bool = False,
               resume: bool = False, mlp_params=None, box_edge: float = 0.0, seed_scratch=None,
-              seed_mode: int = _lib.SEED_AFTER_FIRST, cluster_size: int = CLUSTER_SIZE, half: bool = False):
+              seed_mode: int = _lib.SEED_AFTER_FIRST, cluster_size: int = CLUSTER_SIZE, half: bool = False,
+              period=None):
     """Iterates the SFC-ordered radii h (updated in place) to target +- tol
     own-radius neighbours (sfcnl_h_iterate). With mlp_params the first round's
     update comes from the learned seed. Grows list buffers and resumes when
@@ -300,12 +320,13 @@ def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, m
     total, moved, resume = 0, 0, int(bool(resume))
     while True:
         if total >= max_iters:
-            nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, 0, 0, bool(half))
+            nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, 0, 0, bool(half),
+                               _period(period))
             return HIterResult(total, n, False, nl, rho, nnb, moved)
         need = build_nlist_workspace(n, cluster_size, compress, leaf_bucket, max_j_per_sc, half)
         if ws is None or ws.numel() < need:
             ws = e(max(need, 1), torch.uint8)
-        no = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc, half)
+        no = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc, half, period)
         io = _lib.HiterOpts(target, tol, max_iters - total, resume)
         st = _lib.HiterStats()
         seed_arg = C.byref(hs) if (hs is not None and total == 0) else None
@@ -325,14 +346,14 @@ def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, m
                 # fit: build it with room (radii, rho and nnb are final)
                 build_clusters(ctx, x, y, z, h, cluster_size, bbox)
                 nl = build_nlist(ctx, keys, x, y, z, h, bbox, compress, leaf_bucket, max_j_per_sc, cluster_size,
-                                 pool=pool, ws=ws, sc_info=sc_info, half=half)
+                                 pool=pool, ws=ws, sc_info=sc_info, half=half, period=period)
                 return HIterResult(total, 0, True, nl, rho, nnb, moved)
             # the round that overflowed did not update h (only completed
             # rounds are counted): run it again with room
             resume = 1
             continue
         nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, st.used_bytes, st.max_nj,
-                           bool(half))
+                           bool(half), _period(period))
         nl.ws, nl.max_j_per_sc = ws, max_j_per_sc
         if rc == _lib.E_NOCONV and not raise_noconv:
             return HIterResult(total, st.unconverged, False, nl, rho, nnb, moved)
@@ -431,8 +452,9 @@ class Pipeline:
 
     def __init__(self, ctx: Context, n: int, box, compress: bool = True, leaf_bucket: int = 128,
                  max_j_per_sc: int = 512, with_mass: bool = False, cluster_size: int = CLUSTER_SIZE,
-                 half: bool = False):
+                 half: bool = False, period=None):
         self.ctx, self.n, self.box = ctx, n, tuple(float(v) for v in box)
+        self.period = _period(period)
         self.compress, self.leaf_bucket, self.max_j_per_sc = compress, leaf_bucket, max_j_per_sc
         self.cluster_size, self.half = cluster_size, half
         nsc = (n + SC_SIZE - 1) // SC_SIZE
@@ -461,7 +483,7 @@ class Pipeline:
         build_clusters(ctx, xs, ys, zs, hs, self.cluster_size, self.bbox)
         nl = build_nlist(ctx, self.keys, xs, ys, zs, hs, self.bbox, self.compress, self.leaf_bucket,
                          self.max_j_per_sc, self.cluster_size, pool=self.pool, ws=self.ws, sc_info=self.sc_info,
-                         half=self.half)
+                         half=self.half, period=self.period)
         if nl.pool is not self.pool or nl.ws is not self.ws:  # grown on a retry: keep the larger buffers
             self.pool, self.ws, self.max_j_per_sc = nl.pool, nl.ws, nl.max_j_per_sc
         self.nl = nl

@@ -39,7 +39,7 @@ STAGES = ["keys", "sort", "gather", "clusters", "octree", "traverse", "encode", 
 
 class NlistOpts(C.Structure):
     _fields_ = [("cluster_size", C.c_int), ("compress", C.c_int), ("leaf_bucket", C.c_int),
-                ("max_j_per_sc", C.c_int), ("half", C.c_int)]
+                ("max_j_per_sc", C.c_int), ("half", C.c_int), ("period", C.c_float * 3)]
 
 
 class HiterOpts(C.Structure):
@@ -101,9 +101,11 @@ def load():
     lib.build_nlist.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, C.POINTER(NlistOpts), vp, sz, vp, vp, sz,
                                 C.POINTER(sz), C.POINTER(i64)]
     lib.build_nlist.restype = i32
-    lib.nlist_pass.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+    f3 = C.POINTER(C.c_float)
+    lib.nlist_pass.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, f3]
     lib.nlist_pass.restype = i32
-    lib.nlist_pass_lj.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp, vp, vp, C.POINTER(LjParams), vp, vp, vp, vp]
+    lib.nlist_pass_lj.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp, vp, vp, C.POINTER(LjParams), vp, vp, vp, vp,
+                                  f3]
     lib.nlist_pass_lj.restype = i32
     lib.nlist_decode.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp]
     lib.nlist_decode.restype = i32

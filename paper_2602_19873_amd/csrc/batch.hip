@@ -219,5 +219,5 @@ extern "C" int sfcnl_batch_pass(sfcnl_ctx ctx, sfcnl_batch b, int cluster_size, 
     if (!d_sc_info || !d_pool || !d_x || !d_y || !d_z || !d_h || !d_rho)
         return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_pass: null pointer");
     return pass_impl(ctx, b->n_pad, cluster_size, compress, half, d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb,
-                     seg_of(b));
+                     seg_of(b), Period{});
 }

@@ -2,6 +2,8 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <cmath>
+
 #include "internal.h"
 
 namespace sfcnl {
@@ -14,6 +16,26 @@ int set_err(sfcnl_ctx ctx, int code, const char *fmt, ...) {
         va_end(ap);
     }
     return code;
+}
+
+bool period_ok(const float *period) {
+    if (!period) return true;
+    for (int a = 0; a < 3; a++)
+        if (!(period[a] >= 0.0f) || !std::isfinite(period[a])) return false;
+    return true;
+}
+
+Period make_period(const float *period) {
+    Period p;
+    if (!period) return p;
+    for (int a = 0; a < 3; a++) {
+        if (period[a] > 0.0f) {
+            p.L[a] = period[a];
+            p.hL[a] = 0.5f * period[a];
+            if (p.hL[a] < p.hmin) p.hmin = p.hL[a];
+        }
+    }
+    return p;
 }
 
 }  // namespace sfcnl
@@ -119,7 +141,8 @@ extern "C" int sfcnl_sync(sfcnl_ctx ctx) {
     if (e) {
         int rc = fill_u32(ctx, ctx->d_status + kStInputErr, 1, 0);
         if (rc) return rc;
-        return set_err(ctx, SFCNL_E_INPUT, "input error flags 0x%x (1: non-finite position, 2: bad radius, 4: bad permutation)", e);
+        return set_err(ctx, SFCNL_E_INPUT, "input error flags 0x%x (1: non-finite position, 2: bad radius, 4: bad permutation, 8: positions span a "
+                       "period or a radius reaches half of it)", e);
     }
     return SFCNL_OK;
 }

@@ -168,7 +168,7 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
                               first ? nullptr : act.p, !first);
         if (rc) return rc;
         rc = pass_impl(ctx, n, o.cluster_size, o.compress, o.half, d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho,
-                       d_nnb, SegTable{}, first ? nullptr : act.sc, first ? nullptr : act.p);
+                       d_nnb, SegTable{}, make_period(o.period), first ? nullptr : act.sc, first ? nullptr : act.p);
         if (rc) return rc;
         list_final = first;
         const float *proposal = nullptr;
@@ -249,7 +249,7 @@ int enqueue_round(sfcnl_ctx ctx, const RoundArgs &r, const sfcnl_nlist_opts &o, 
                           restricted ? act.p : nullptr, restricted);
     if (rc) return rc;
     rc = pass_impl(ctx, n, o.cluster_size, o.compress, o.half, r.sc_info, r.pool, r.x, r.y, r.z, r.h, r.m, r.rho,
-                   r.nnb, seg, restricted ? act.sc : nullptr, restricted ? act.p : nullptr);
+                   r.nnb, seg, Period{}, restricted ? act.sc : nullptr, restricted ? act.p : nullptr);
     if (rc) return rc;
     const float *proposal = nullptr;
     if (seed) {
@@ -400,7 +400,8 @@ extern "C" int sfcnl_batch_h_iterate(sfcnl_ctx ctx, sfcnl_batch b, const uint64_
             const uint32_t e = hs[kStInputErr];
             int rc = fill_u32(ctx, ctx->d_status + kStInputErr, 1, 0);
             if (rc) return rc;
-            return set_err(ctx, SFCNL_E_INPUT, "input error flags 0x%x (1: non-finite position, 2: bad radius)", e);
+            return set_err(ctx, SFCNL_E_INPUT, "input error flags 0x%x (1: non-finite position, 2: bad radius, 8: positions span a "
+                                   "period or a radius reaches half of it)", e);
         }
         if (hs[kStTree]) return set_err(ctx, SFCNL_E_HIP, "internal error: octree invariant broken (0x%x)", hs[kStTree]);
         if (hs[kStScratch])

@@ -18,7 +18,7 @@ constexpr int kMaxBoxLevels = 12;        // 8^12 clusters > 2^31 particles
 
 // Status block words (device, mirrored into pinned host memory).
 enum StatusWord : int {
-    kStInputErr = 0,     // bit 0: non-finite coordinate, bit 1: bad radius
+    kStInputErr = 0,     // bit 0: non-finite coordinate, bit 1: bad radius, bit 3: period violated
     kStPoolOverflow = 1, // set if the pool is too small
     kStMaxNj = 2,        // largest list length (atomicMax)
     kStTotalLo = 3,      // total pool words (exclusive scan total)
@@ -104,6 +104,27 @@ struct SegTable {
     uint4 *roots = nullptr;            // nsys root records, written by the octree build
     __host__ __device__ bool on() const { return sc_sys != nullptr; }
 };
+
+// Periodic axes (Sec. II-A: periodic boundaries without shift vectors, the
+// periodic distance of a pair computed whenever it is needed). L[a] is the
+// period of axis a, +inf for an open axis, hL[a] = f32(L[a] / 2). A component
+// difference d becomes its minimum image: d - L if d > L/2, d + L if d < -L/2
+// (with L = +inf it stays d). Positions must lie within one period and radii
+// below hmin, the smallest half period, so one image is the only candidate.
+struct Period {
+    float L[3] = {INFINITY, INFINITY, INFINITY};
+    float hL[3] = {INFINITY, INFINITY, INFINITY};
+    float hmin = INFINITY;
+    __host__ __device__ bool on() const { return hmin < INFINITY; }
+};
+// period: 3 lengths (0 = open axis) or nullptr (all open); the caller has
+// checked them (finite, >= 0)
+Period make_period(const float *period);
+bool period_ok(const float *period);
+
+__device__ __forceinline__ float min_image(float d, float L, float hL) {
+    return d > hL ? d - L : (d < -hL ? d + L : d);
+}
 
 }  // namespace sfcnl
 
@@ -202,7 +223,8 @@ int clusters_impl(sfcnl_ctx ctx, int64_t n, const float *x, const float *y, cons
 // super-clusters unchanged (full lists only).
 int pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, int half, const uint32_t *sc_info, const uint32_t *pool,
               const float *x, const float *y, const float *z, const float *h, const float *m, float *rho, int32_t *nnb,
-              const SegTable &seg, const uint32_t *active = nullptr, const uint8_t *p_active = nullptr);
+              const SegTable &seg, const Period &per, const uint32_t *active = nullptr,
+              const uint8_t *p_active = nullptr);
 int features_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *keys, const float *x, const float *y, const float *z,
                   const float *h, const int32_t *nnb, float box_edge, int target, uint16_t *feat,
                   const SegTable &seg);

@@ -37,7 +37,18 @@ struct LjArgs {
     float eps4;   // 4 eps
     float kc;     // Coulomb prefactor
     float *fx, *fy, *fz, *ep;
+    Period per;   // periodic axes (used by the kPbc kernels)
 };
+
+// minimum images of a pair's components on periodic axes
+template <bool kPbc>
+__device__ __forceinline__ void wrap3(float &dx, float &dy, float &dz, const Period &p) {
+    if (kPbc) {
+        dx = min_image(dx, p.L[0], p.hL[0]);
+        dy = min_image(dy, p.L[1], p.hL[1]);
+        dz = min_image(dz, p.L[2], p.hL[2]);
+    }
+}
 
 // fr = -(dU/dr) / r of one pair at squared distance d2, and (kE) the pair
 // energy U; kqq = coulomb * q_i * q_j.
@@ -57,13 +68,14 @@ __device__ __forceinline__ void lj_factor(float d2, float kqq, const LjArgs &a, 
 
 // One pair of a full-list tile. g accumulates fr * (x_j - x_i) (the force on
 // i is its negative), ge the pair energies.
-template <bool kQ, bool kE>
+template <bool kQ, bool kE, bool kPbc>
 __device__ __forceinline__ void lj_tile(float xj, float yj, float zj, float qj, float xi, float yi, float zi,
                                         float kqi, bool self_pair, const LjArgs &a, float &gx, float &gy, float &gz,
                                         float &ge) {
-    const float dx = xj - xi;
-    const float dy = yj - yi;
-    const float dz = zj - zi;
+    float dx = xj - xi;
+    float dy = yj - yi;
+    float dz = zj - zi;
+    wrap3<kPbc>(dx, dy, dz, a.per);
     const float dxx = dx * dx;
     const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
     const bool in = d2 < a.rc2 && !self_pair;
@@ -78,7 +90,7 @@ __device__ __forceinline__ void lj_tile(float xj, float yj, float zj, float qj, 
     }
 }
 
-template <int CS, bool kCompress, bool kQ, bool kE>
+template <int CS, bool kCompress, bool kQ, bool kE, bool kPbc>
 __global__ __launch_bounds__(256) void k_pass_lj(LjArgs a) {
     constexpr int kNsub = kScSize / CS;
     constexpr int kNreg = CS == 8 ? 8 : 4;
@@ -157,14 +169,14 @@ __global__ __launch_bounds__(256) void k_pass_lj(LjArgs a) {
 #pragma unroll
                 for (int c = 0; c < kNreg; c++)
                     if ((mk >> c) & 1u)
-                        lj_tile<kQ, kE>(cx[0], cy[0], cz[0], cq[0], ix[c], iy[c], iz[c], ikq[c],
+                        lj_tile<kQ, kE, kPbc>(cx[0], cy[0], cz[0], cq[0], ix[c], iy[c], iz[c], ikq[c],
                                         c == self_c && il == jl, a, gx[c], gy[c], gz[c], ge[c]);
             } else if (CS == 4) {
                 const int il = (lane >> 2) & 3, q = lane >> 4;
 #pragma unroll
                 for (int k = 0; k < kNreg; k++)
                     if ((mk >> (4 * k)) & 0xFu)
-                        lj_tile<kQ, kE>(cx[0], cy[0], cz[0], cq[0], ix[k], iy[k], iz[k], ikq[k],
+                        lj_tile<kQ, kE, kPbc>(cx[0], cy[0], cz[0], cq[0], ix[k], iy[k], iz[k], ikq[k],
                                         4 * k + q == self_c && il == jl, a, gx[k], gy[k], gz[k], ge[k]);
             } else {
                 const int il = lane >> 2;
@@ -173,7 +185,7 @@ __global__ __launch_bounds__(256) void k_pass_lj(LjArgs a) {
                     if ((mk >> c) & 1u) {
 #pragma unroll
                         for (int t = 0; t < 4; t++)
-                            lj_tile<kQ, kE>(cx[t], cy[t], cz[t], cq[t], ix[c], iy[c], iz[c], ikq[c],
+                            lj_tile<kQ, kE, kPbc>(cx[t], cy[t], cz[t], cq[t], ix[c], iy[c], iz[c], ikq[c],
                                             c == self_c && il == 4 * t + jl, a, gx[c], gy[c], gz[c], ge[c]);
                     }
             }
@@ -208,7 +220,7 @@ __global__ __launch_bounds__(256) void k_pass_lj(LjArgs a) {
     }
 }
 
-template <int CS, bool kCompress, bool kQ, bool kE>
+template <int CS, bool kCompress, bool kQ, bool kE, bool kPbc>
 __global__ __launch_bounds__(256) void k_pass_lj_half(LjArgs a) {
     constexpr int kNsub = kScSize / CS;
     constexpr int kNreg = CS == 8 ? 8 : 4;
@@ -289,9 +301,10 @@ __global__ __launch_bounds__(256) void k_pass_lj_half(LjArgs a) {
             for (int t = 0; t < kNj; t++) jm[t] = 0;
             // one pair: g (i side) and h (j side) accumulate fr * (x_j - x_i)
             auto pair = [&](int t, int k, bool kp) {
-                const float dx = xj[t] - ix[k];
-                const float dy = yj[t] - iy[k];
-                const float dz = zj[t] - iz[k];
+                float dx = xj[t] - ix[k];
+                float dy = yj[t] - iy[k];
+                float dz = zj[t] - iz[k];
+                wrap3<kPbc>(dx, dy, dz, a.per);
                 const float dxx = dx * dx;
                 const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
                 const bool in = kp && d2 < a.rc2;
@@ -387,10 +400,10 @@ __global__ __launch_bounds__(256) void k_pass_lj_half(LjArgs a) {
     }
 }
 
-template <int CS, bool kHalf>
+template <int CS, bool kHalf, bool kPbc>
 void launch_lj(int variant, unsigned g, hipStream_t st, const LjArgs &a) {
 #define SFCNL_LJ(C, Q, E) \
-    (kHalf ? k_pass_lj_half<CS, C, Q, E> : k_pass_lj<CS, C, Q, E>)<<<g, 256, 0, st>>>(a)
+    (kHalf ? k_pass_lj_half<CS, C, Q, E, kPbc> : k_pass_lj<CS, C, Q, E, kPbc>)<<<g, 256, 0, st>>>(a)
     switch (variant) {
         case 7: SFCNL_LJ(true, true, true); break;
         case 6: SFCNL_LJ(true, true, false); break;
@@ -404,6 +417,24 @@ void launch_lj(int variant, unsigned g, hipStream_t st, const LjArgs &a) {
 #undef SFCNL_LJ
 }
 
+template <bool kPbc>
+void launch_lj_any(int cs, int half, int variant, unsigned g, hipStream_t st, const LjArgs &a) {
+    if (half) {
+        if (cs == 4)
+            launch_lj<4, true, kPbc>(variant, g, st, a);
+        else if (cs == 16)
+            launch_lj<16, true, kPbc>(variant, g, st, a);
+        else
+            launch_lj<8, true, kPbc>(variant, g, st, a);
+    } else if (cs == 4) {
+        launch_lj<4, false, kPbc>(variant, g, st, a);
+    } else if (cs == 16) {
+        launch_lj<16, false, kPbc>(variant, g, st, a);
+    } else {
+        launch_lj<8, false, kPbc>(variant, g, st, a);
+    }
+}
+
 }  // namespace
 }  // namespace sfcnl
 
@@ -412,7 +443,7 @@ using namespace sfcnl;
 extern "C" int nlist_pass_lj(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, int half,
                              const uint32_t *d_sc_info, const uint32_t *d_pool, const float *d_x, const float *d_y,
                              const float *d_z, const float *d_q, const sfcnl_lj_params *params, float *d_fx,
-                             float *d_fy, float *d_fz, float *d_epot) {
+                             float *d_fy, float *d_fz, float *d_epot, const float *h_period) {
     if (!ctx) return SFCNL_E_ARG;
     if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "nlist_pass_lj: n out of range");
     if (cluster_size != 4 && cluster_size != 8 && cluster_size != 16)
@@ -424,12 +455,13 @@ extern "C" int nlist_pass_lj(sfcnl_ctx ctx, int64_t n, int cluster_size, int com
     if (!(pr.r_cut > 0.0f) || !std::isfinite(pr.r_cut) || !(pr.sigma > 0.0f) || !std::isfinite(pr.sigma) ||
         !std::isfinite(pr.eps) || !std::isfinite(pr.coulomb))
         return set_err(ctx, SFCNL_E_ARG, "nlist_pass_lj: parameters must be finite, sigma and r_cut > 0");
+    if (!period_ok(h_period)) return set_err(ctx, SFCNL_E_ARG, "nlist_pass_lj: period must be 3 finite values >= 0");
     if (n == 0) return SFCNL_OK;
     if (!d_sc_info || !d_pool || !d_x || !d_y || !d_z || !d_fx || !d_fy || !d_fz)
         return set_err(ctx, SFCNL_E_ARG, "nlist_pass_lj: null pointer");
     LjArgs a{n, (uint32_t)((n + kScSize - 1) / kScSize), d_sc_info, d_pool, d_x, d_y, d_z, d_q,
              pr.r_cut * pr.r_cut, pr.sigma * pr.sigma, 24.0f * pr.eps, 4.0f * pr.eps, pr.coulomb,
-             d_fx, d_fy, d_fz, d_epot};
+             d_fx, d_fy, d_fz, d_epot, make_period(h_period)};
     const unsigned g = blocks_for(a.nsc, kWavesPerBlock);
     hipStream_t st = ctx->stream;
     const int variant = (compress ? 4 : 0) | (d_q ? 2 : 0) | (d_epot ? 1 : 0);
@@ -442,19 +474,11 @@ extern "C" int nlist_pass_lj(sfcnl_ctx ctx, int64_t n, int cluster_size, int com
             const int rc = fill_u32(ctx, reinterpret_cast<uint32_t *>(o), n, 0u);
             if (rc) return rc;
         }
-        if (cluster_size == 4)
-            launch_lj<4, true>(variant, g, st, a);
-        else if (cluster_size == 16)
-            launch_lj<16, true>(variant, g, st, a);
-        else
-            launch_lj<8, true>(variant, g, st, a);
-    } else if (cluster_size == 4) {
-        launch_lj<4, false>(variant, g, st, a);
-    } else if (cluster_size == 16) {
-        launch_lj<16, false>(variant, g, st, a);
-    } else {
-        launch_lj<8, false>(variant, g, st, a);
     }
+    if (a.per.on())
+        launch_lj_any<true>(cluster_size, half, variant, g, st, a);
+    else
+        launch_lj_any<false>(cluster_size, half, variant, g, st, a);
     SFCNL_LAUNCHED(ctx);
     prof_mark(ctx, kStagePass, true);
     return SFCNL_OK;

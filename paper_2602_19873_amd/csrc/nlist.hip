@@ -39,12 +39,26 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Gap along one axis between two boxes, from d1 = blo - ahi and d2 = alo - bhi
+// (the separations of the direct images). On a periodic axis the gap is also
+// taken to the images one period away, min(d1, d2) + L; both boxes lie within
+// one period, so no other image is closer. Every step rounds monotonically, so
+// the gap never exceeds the |d| of a particle pair across the boxes after its
+// minimum image is taken.
+template <bool kPbc>
+__device__ __forceinline__ float axis_gap(float d1, float d2, float L) {
+    const float g = fmaxf(fmaxf(d1, d2), 0.0f);
+    if (!kPbc) return g;
+    return fminf(g, fmaxf(fminf(d1, d2) + L, 0.0f));
+}
+
 // Boxes carry .w of lo = largest radius inside. True if some particle pair
 // across the two boxes could satisfy d2 < max(h_i, h_j)^2.
-__device__ __forceinline__ bool boxes_near(float4 alo, float4 ahi, float4 blo, float4 bhi) {
-    float gx = fmaxf(fmaxf(blo.x - ahi.x, alo.x - bhi.x), 0.0f);
-    float gy = fmaxf(fmaxf(blo.y - ahi.y, alo.y - bhi.y), 0.0f);
-    float gz = fmaxf(fmaxf(blo.z - ahi.z, alo.z - bhi.z), 0.0f);
+template <bool kPbc = false>
+__device__ __forceinline__ bool boxes_near(float4 alo, float4 ahi, float4 blo, float4 bhi, const Period &per = Period{}) {
+    float gx = axis_gap<kPbc>(blo.x - ahi.x, alo.x - bhi.x, per.L[0]);
+    float gy = axis_gap<kPbc>(blo.y - ahi.y, alo.y - bhi.y, per.L[1]);
+    float gz = axis_gap<kPbc>(blo.z - ahi.z, alo.z - bhi.z, per.L[2]);
     float gxx = gx * gx;
     float d2 = __builtin_fmaf(gz, gz, __builtin_fmaf(gy, gy, gxx));
     float ra = alo.w * alo.w, rb = blo.w * blo.w;
@@ -118,6 +132,7 @@ struct TravArgs {
     const uint4 *cs_rec;
     uint32_t nslots;       // capacity of the slot arrays
     SegTable seg;          // batched systems (empty for one system)
+    Period per;            // periodic axes (used by the kPbc kernels)
     const uint32_t *active;  // nullable: super-clusters with active[s] == 0 get an empty list
     // nullable: a counting list for the flagged particles only (own radius):
     // pairs d2 < h_i^2 for i with p_active[i] != 0; node, cluster and j radii
@@ -167,7 +182,7 @@ __device__ __forceinline__ uint32_t pack4_16(uint64_t x) {
 // Bits 0, 4, 8 and 12 of x gathered into bits 0..3.
 __device__ __forceinline__ uint32_t pack4_4(uint32_t x) { return (((x & 0x1111u) * 0x1248u) >> 12) & 0xFu; }
 
-template <int CS, bool kHalf>
+template <int CS, bool kHalf, bool kPbc>
 __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
     using S = Shape<CS>;
     constexpr int kNsub = S::kNsub, kNreg = S::kNreg;
@@ -188,6 +203,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
     const bool gather = a.p_active != nullptr;
     // i particles; absent ones are put far away so that no test accepts them
     float ix[kNreg], iy[kNreg], iz[kNreg], ih2[kNreg];
+    bool big = false;  // a radius reaches half a period
 #pragma unroll
     for (int k = 0; k < kNreg; k++) {
         const int64_t i = (int64_t)s * kScSize + S::ipart(k, lane);
@@ -196,11 +212,19 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
         iy[k] = v ? a.y[i] : kFar;
         iz[k] = v ? a.z[i] : kFar;
         float hh = v ? a.h[i] : 0.0f;
+        if (kPbc) big = big || !(hh < a.per.hmin);
         if (gather && v && !a.p_active[i]) hh = 0.0f;  // counting list: flagged particles only
         ih2[k] = hh * hh;
     }
+    if (kPbc && sfc_ballot(big) && lane == 0) atomicOr(&a.status[kStInputErr], 8u);
     const uint32_t own_c0 = s * kNsub;  // first i-cluster of this super-cluster
     const uint32_t own_p0 = s * kScSize;  // and its first particle
+    // minimum images of a pair's components on periodic axes
+    auto wrap = [&](float &dx, float &dy, float &dz) {
+        dx = min_image(dx, a.per.L[0], a.per.hL[0]);
+        dy = min_image(dy, a.per.L[1], a.per.hL[1]);
+        dz = min_image(dz, a.per.L[2], a.per.hL[2]);
+    };
     constexpr bool half = kHalf;
     const float4 empty_lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
     const float4 empty_hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
@@ -329,7 +353,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                 uint64_t bal[kIbox];
                 uint32_t anyj;
 #pragma unroll
-                for (int t = 0; t < kIbox; t++) bal[t] = sfc_ballot(boxes_near(ilo[t], ihi[t], blo, bhi));
+                for (int t = 0; t < kIbox; t++) bal[t] = sfc_ballot(boxes_near<kPbc>(ilo[t], ihi[t], blo, bhi, a.per));
                 if (CS == 8) {
                     anyj = byte_or(bal[0]);
                 } else if (CS == 4) {
@@ -372,9 +396,10 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
 #pragma unroll
                         for (int c = 0; c < kNreg; c++) {
                             if ((cmask >> c) & 1u) {
-                                const float dx = xj - ix[c];
-                                const float dy = yj - iy[c];
-                                const float dz = zj - iz[c];
+                                float dx = xj - ix[c];
+                                float dy = yj - iy[c];
+                                float dz = zj - iz[c];
+                                if (kPbc) wrap(dx, dy, dz);
                                 const float dxx = dx * dx;
                                 const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
                                 bool pr = d2 < (gather ? ih2[c] : fmaxf(ih2[c], hj2));
@@ -394,9 +419,10 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
 #pragma unroll
                         for (int k = 0; k < kNreg; k++) {
                             if ((cmask >> (4 * k)) & 0xFu) {
-                                const float dx = xj - ix[k];
-                                const float dy = yj - iy[k];
-                                const float dz = zj - iz[k];
+                                float dx = xj - ix[k];
+                                float dy = yj - iy[k];
+                                float dz = zj - iz[k];
+                                if (kPbc) wrap(dx, dy, dz);
                                 const float dxx = dx * dx;
                                 const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
                                 bool pr = d2 < (gather ? ih2[k] : fmaxf(ih2[k], hj2));
@@ -426,9 +452,10 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                                 bool pr = false;
 #pragma unroll
                                 for (int t = 0; t < 4; t++) {
-                                    const float dx = xj[t] - ix[c];
-                                    const float dy = yj[t] - iy[c];
-                                    const float dz = zj[t] - iz[c];
+                                    float dx = xj[t] - ix[c];
+                                    float dy = yj[t] - iy[c];
+                                    float dz = zj[t] - iz[c];
+                                    if (kPbc) wrap(dx, dy, dz);
                                     const float dxx = dx * dx;
                                     const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
                                     bool p = d2 < (gather ? ih2[c] : fmaxf(ih2[c], hj2[t]));
@@ -475,7 +502,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                 const float4 hi = a.cs_box[2 * (size_t)slot + 1];
                 crec = a.cs_rec[slot];
                 // a half list never needs a node that ends before the super-cluster
-                hit = boxes_near(glo, ghi, lo, hi) && (!half || crec.y > own_p0);
+                hit = boxes_near<kPbc>(glo, ghi, lo, hi, a.per) && (!half || crec.y > own_p0);
             }
             const uint32_t keep = byte_or(sfc_ballot(hit));
             const int cnt = __popc(keep);
@@ -633,6 +660,25 @@ void carve_nlist(Carver &cv, NlistWs &ws, int64_t n, const sfcnl_nlist_opts &o, 
     ws.scan_tmp = cv.take<char>(scan_tmp_bytes(nsc));
 }
 
+template <bool kPbc>
+void launch_traverse(int cs, int half, unsigned gb, hipStream_t st, const TravArgs &ta) {
+    if (cs == 4) {
+        if (half) k_traverse<4, true, kPbc><<<gb, 256, 0, st>>>(ta); else k_traverse<4, false, kPbc><<<gb, 256, 0, st>>>(ta);
+    } else if (cs == 16) {
+        if (half) k_traverse<16, true, kPbc><<<gb, 256, 0, st>>>(ta); else k_traverse<16, false, kPbc><<<gb, 256, 0, st>>>(ta);
+    } else {
+        if (half) k_traverse<8, true, kPbc><<<gb, 256, 0, st>>>(ta); else k_traverse<8, false, kPbc><<<gb, 256, 0, st>>>(ta);
+    }
+}
+
+// Periodic axes: the particles must span less than one period (the root box
+// of the octree holds the exact extent).
+__global__ void k_check_span(const float4 *__restrict__ root_box, Period per, uint32_t *status) {
+    const float4 lo = root_box[0], hi = root_box[1];
+    const bool bad = !(hi.x - lo.x < per.L[0]) || !(hi.y - lo.y < per.L[1]) || !(hi.z - lo.z < per.L[2]);
+    if (bad) atomicOr(&status[kStInputErr], 8u);
+}
+
 int check_opts(sfcnl_ctx ctx, const sfcnl_nlist_opts *o) {
     if (!o) return set_err(ctx, SFCNL_E_ARG, "null options");
     if (o->cluster_size != 4 && o->cluster_size != 8 && o->cluster_size != 16)
@@ -642,6 +688,7 @@ int check_opts(sfcnl_ctx ctx, const sfcnl_nlist_opts *o) {
     if (o->leaf_bucket < 8 || o->leaf_bucket > 256)
         return set_err(ctx, SFCNL_E_ARG, "leaf_bucket %d outside [8, 256]", o->leaf_bucket);
     if (o->max_j_per_sc < 1) return set_err(ctx, SFCNL_E_ARG, "max_j_per_sc must be positive");
+    if (!period_ok(o->period)) return set_err(ctx, SFCNL_E_ARG, "period must be 3 finite values >= 0");
     return SFCNL_OK;
 }
 
@@ -707,6 +754,8 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
                             const uint32_t *active, const uint8_t *p_active, bool reuse_tree) {
     if ((active || p_active) && o.half)
         return set_err(ctx, SFCNL_E_ARG, "build_nlist: a restricted rebuild needs the full list");
+    const Period per = make_period(o.period);
+    if (per.on() && seg.on()) return set_err(ctx, SFCNL_E_ARG, "batched lists take open boundaries only");
     const int nsys = seg.on() ? seg.nsys : 1;
     Carver cv{reinterpret_cast<char *>(d_ws), 0};
     NlistWs ws;
@@ -723,6 +772,10 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
         prof_mark(ctx, kStageOctree, false);
         rc = octree_build(ctx, ws.tree, d_keys, d_x, d_y, d_z, d_h, reinterpret_cast<const float4 *>(d_bbox), seg);
         if (rc) return rc;
+        if (per.on()) {
+            k_check_span<<<1, 1, 0, st>>>(ws.tree.cs_box, per, ctx->d_status);
+            SFCNL_LAUNCHED(ctx);
+        }
         prof_mark(ctx, kStageOctree, true);
     }
 
@@ -741,6 +794,7 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     ta.cs_rec = ws.tree.cs_rec;
     ta.nslots = ws.tree.node_cap;
     ta.seg = seg;
+    ta.per = per;
     ta.active = active;
     ta.p_active = p_active;
     ta.list_j = ws.list_j;
@@ -750,13 +804,10 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     ta.status = ctx->d_status;
     const unsigned gb = blocks_for(nsc, kWavesPerBlock);
     prof_mark(ctx, kStageTraverse, false);
-    if (cs == 4) {
-        if (o.half) k_traverse<4, true><<<gb, 256, 0, st>>>(ta); else k_traverse<4, false><<<gb, 256, 0, st>>>(ta);
-    } else if (cs == 16) {
-        if (o.half) k_traverse<16, true><<<gb, 256, 0, st>>>(ta); else k_traverse<16, false><<<gb, 256, 0, st>>>(ta);
-    } else {
-        if (o.half) k_traverse<8, true><<<gb, 256, 0, st>>>(ta); else k_traverse<8, false><<<gb, 256, 0, st>>>(ta);
-    }
+    if (per.on())
+        launch_traverse<true>(cs, o.half, gb, st, ta);
+    else
+        launch_traverse<false>(cs, o.half, gb, st, ta);
     SFCNL_LAUNCHED(ctx);
     prof_mark(ctx, kStageTraverse, true);
     prof_mark(ctx, kStageEncode, false);
@@ -792,7 +843,9 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
         uint32_t e = hs[kStInputErr];
         rc = fill_u32(ctx, ctx->d_status + kStInputErr, 1, 0);
         if (rc) return rc;
-        return set_err(ctx, SFCNL_E_INPUT, "input error flags 0x%x (1: non-finite position, 2: bad radius, 4: bad permutation)", e);
+        return set_err(ctx, SFCNL_E_INPUT,
+                       "input error flags 0x%x (1: non-finite position, 2: bad radius, 4: bad permutation, "
+                       "8: positions span a period or a radius reaches half of it)", e);
     }
     if (hs[kStTree]) return set_err(ctx, SFCNL_E_HIP, "internal error: octree invariant broken (0x%x)", hs[kStTree]);
     if (hs[kStScratch])

@@ -24,18 +24,25 @@ struct PassArgs {
     float *rho;
     int32_t *nnb;
     SegTable seg;  // batched systems: list indices are relative to the system's first cluster
+    Period per;    // periodic axes (used by the kPbc kernels)
     const uint32_t *active;  // nullable: skip super-clusters with active[s] == 0 (full pass)
     const uint8_t *p_active;  // nullable: write only particles with p_active[i] != 0 (full pass)
 };
 
 // One particle pair of a tile: the own-radius test, then m_j times the
 // halved M4 shape 1/2 - 3q^2 + 3q^3 (q < 1/2) or (1-q)^3, summed.
-template <bool kMass>
+template <bool kMass, bool kPbc>
 __device__ __forceinline__ void tile_pair(float xj, float yj, float zj, float mj, float xi, float yi, float zi,
-                                          float h2, float hinv, bool self_pair, float &acc, int &cnt) {
-    const float dx = xj - xi;
-    const float dy = yj - yi;
-    const float dz = zj - zi;
+                                          float h2, float hinv, bool self_pair, float &acc, int &cnt,
+                                          const Period &per) {
+    float dx = xj - xi;
+    float dy = yj - yi;
+    float dz = zj - zi;
+    if (kPbc) {  // minimum images on periodic axes
+        dx = min_image(dx, per.L[0], per.hL[0]);
+        dy = min_image(dy, per.L[1], per.hL[1]);
+        dz = min_image(dz, per.L[2], per.hL[2]);
+    }
     const float dxx = dx * dx;
     const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
     const bool in = d2 < h2 && !self_pair;
@@ -59,7 +66,7 @@ __device__ __forceinline__ void tile_pair(float xj, float yj, float zj, float mj
 //            j-particle jl against i-particle il of i-clusters 4k + q;
 //   CS = 16: lane (il, jq) = (lane / 4, lane % 4) takes j-particles 4t + jq
 //            (t = 0..3) against i-particle il of every set i-cluster.
-template <int CS, bool kCompress, bool kMass, bool kCount>
+template <int CS, bool kCompress, bool kMass, bool kCount, bool kPbc>
 __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
     constexpr int kNsub = kScSize / CS;
     constexpr int kNreg = CS == 8 ? 8 : 4;
@@ -153,15 +160,15 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
 #pragma unroll
                 for (int c = 0; c < kNreg; c++)
                     if ((mk >> c) & 1u)
-                        tile_pair<kMass>(cx[0], cy[0], cz[0], cm[0], ix[c], iy[c], iz[c], ih2[c], ihinv[c],
-                                         c == self_c && il == jl, acc[c], cnt_nb[c]);
+                        tile_pair<kMass, kPbc>(cx[0], cy[0], cz[0], cm[0], ix[c], iy[c], iz[c], ih2[c], ihinv[c],
+                                         c == self_c && il == jl, acc[c], cnt_nb[c], a.per);
             } else if (CS == 4) {
                 const int il = (lane >> 2) & 3, q = lane >> 4;
 #pragma unroll
                 for (int k = 0; k < kNreg; k++)
                     if ((mk >> (4 * k)) & 0xFu)
-                        tile_pair<kMass>(cx[0], cy[0], cz[0], cm[0], ix[k], iy[k], iz[k], ih2[k], ihinv[k],
-                                         4 * k + q == self_c && il == jl, acc[k], cnt_nb[k]);
+                        tile_pair<kMass, kPbc>(cx[0], cy[0], cz[0], cm[0], ix[k], iy[k], iz[k], ih2[k], ihinv[k],
+                                         4 * k + q == self_c && il == jl, acc[k], cnt_nb[k], a.per);
             } else {
                 const int il = lane >> 2;
 #pragma unroll
@@ -169,8 +176,8 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
                     if ((mk >> c) & 1u) {
 #pragma unroll
                         for (int t = 0; t < 4; t++)
-                            tile_pair<kMass>(cx[t], cy[t], cz[t], cm[t], ix[c], iy[c], iz[c], ih2[c], ihinv[c],
-                                             c == self_c && il == 4 * t + jl, acc[c], cnt_nb[c]);
+                            tile_pair<kMass, kPbc>(cx[t], cy[t], cz[t], cm[t], ix[c], iy[c], iz[c], ih2[c], ihinv[c],
+                                             c == self_c && il == 4 * t + jl, acc[c], cnt_nb[c], a.per);
                     }
             }
         }
@@ -223,13 +230,18 @@ __device__ __forceinline__ float half_shape(float q) {
     return q < 0.5f ? inner : outer;
 }
 
-template <int CS>
+template <int CS, bool kPbc>
 __device__ __forceinline__ void half_pair(float xj, float yj, float zj, float mj, float hj2, float hjinv, float xi,
                                           float yi, float zi, float mi, float hi2, float hiinv, bool keep,
-                                          float &acc_i, int &cnt_i, float &acc_j, int &cnt_j) {
-    const float dx = xj - xi;
-    const float dy = yj - yi;
-    const float dz = zj - zi;
+                                          float &acc_i, int &cnt_i, float &acc_j, int &cnt_j, const Period &per) {
+    float dx = xj - xi;
+    float dy = yj - yi;
+    float dz = zj - zi;
+    if (kPbc) {  // minimum images on periodic axes
+        dx = min_image(dx, per.L[0], per.hL[0]);
+        dy = min_image(dy, per.L[1], per.hL[1]);
+        dz = min_image(dz, per.L[2], per.hL[2]);
+    }
     const float dxx = dx * dx;
     const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
     const bool ini = keep && d2 < hi2;
@@ -247,7 +259,7 @@ __device__ __forceinline__ void half_pair(float xj, float yj, float zj, float mj
     }
 }
 
-template <int CS, bool kCompress, bool kMass, bool kCount>
+template <int CS, bool kCompress, bool kMass, bool kCount, bool kPbc>
 __global__ __launch_bounds__(256) void k_pass_half(PassArgs a) {
     constexpr int kNsub = kScSize / CS;
     constexpr int kNreg = CS == 8 ? 8 : 4;
@@ -348,16 +360,16 @@ __global__ __launch_bounds__(256) void k_pass_half(PassArgs a) {
 #pragma unroll
                 for (int c = 0; c < kNreg; c++)
                     if ((mk >> c) & 1u)
-                        half_pair<CS>(xj[0], yj[0], zj[0], mj[0], hj2[0], hjinv[0], ix[c], iy[c], iz[c], im[c],
-                                      ih2[c], ihinv[c], keep(c, il, jq), acc[c], cnt_nb[c], accj[0], cntj[0]);
+                        half_pair<CS, kPbc>(xj[0], yj[0], zj[0], mj[0], hj2[0], hjinv[0], ix[c], iy[c], iz[c], im[c],
+                                      ih2[c], ihinv[c], keep(c, il, jq), acc[c], cnt_nb[c], accj[0], cntj[0], a.per);
             } else if (CS == 4) {
                 const int il = lane & 3, q = (lane >> 2) & 3;
 #pragma unroll
                 for (int k = 0; k < kNreg; k++)
                     if ((mk >> (4 * k)) & 0xFu)
-                        half_pair<CS>(xj[0], yj[0], zj[0], mj[0], hj2[0], hjinv[0], ix[k], iy[k], iz[k], im[k],
+                        half_pair<CS, kPbc>(xj[0], yj[0], zj[0], mj[0], hj2[0], hjinv[0], ix[k], iy[k], iz[k], im[k],
                                       ih2[k], ihinv[k], keep(4 * k + q, il, jq), acc[k], cnt_nb[k], accj[0],
-                                      cntj[0]);
+                                      cntj[0], a.per);
             } else {
                 const int il = lane & 15;
 #pragma unroll
@@ -365,9 +377,9 @@ __global__ __launch_bounds__(256) void k_pass_half(PassArgs a) {
                     if ((mk >> c) & 1u) {
 #pragma unroll
                         for (int t = 0; t < 4; t++)
-                            half_pair<CS>(xj[t], yj[t], zj[t], mj[t], hj2[t], hjinv[t], ix[c], iy[c], iz[c], im[c],
+                            half_pair<CS, kPbc>(xj[t], yj[t], zj[t], mj[t], hj2[t], hjinv[t], ix[c], iy[c], iz[c], im[c],
                                           ih2[c], ihinv[c], keep(c, il, 4 * t + jq), acc[c], cnt_nb[c], accj[t],
-                                          cntj[t]);
+                                          cntj[t], a.per);
                     }
             }
             // j side: sum over the i lanes of each j-particle (one DPP row
@@ -457,31 +469,49 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
     }
 }
 
-template <int CS>
+template <int CS, bool kPbc>
 void launch_pass(int variant, unsigned g, hipStream_t st, const PassArgs &a) {
     switch (variant) {
-        case 7: k_pass<CS, true, true, true><<<g, 256, 0, st>>>(a); break;
-        case 6: k_pass<CS, true, true, false><<<g, 256, 0, st>>>(a); break;
-        case 5: k_pass<CS, true, false, true><<<g, 256, 0, st>>>(a); break;
-        case 4: k_pass<CS, true, false, false><<<g, 256, 0, st>>>(a); break;
-        case 3: k_pass<CS, false, true, true><<<g, 256, 0, st>>>(a); break;
-        case 2: k_pass<CS, false, true, false><<<g, 256, 0, st>>>(a); break;
-        case 1: k_pass<CS, false, false, true><<<g, 256, 0, st>>>(a); break;
-        default: k_pass<CS, false, false, false><<<g, 256, 0, st>>>(a); break;
+        case 7: k_pass<CS, true, true, true, kPbc><<<g, 256, 0, st>>>(a); break;
+        case 6: k_pass<CS, true, true, false, kPbc><<<g, 256, 0, st>>>(a); break;
+        case 5: k_pass<CS, true, false, true, kPbc><<<g, 256, 0, st>>>(a); break;
+        case 4: k_pass<CS, true, false, false, kPbc><<<g, 256, 0, st>>>(a); break;
+        case 3: k_pass<CS, false, true, true, kPbc><<<g, 256, 0, st>>>(a); break;
+        case 2: k_pass<CS, false, true, false, kPbc><<<g, 256, 0, st>>>(a); break;
+        case 1: k_pass<CS, false, false, true, kPbc><<<g, 256, 0, st>>>(a); break;
+        default: k_pass<CS, false, false, false, kPbc><<<g, 256, 0, st>>>(a); break;
     }
 }
 
-template <int CS>
+template <int CS, bool kPbc>
 void launch_pass_half(int variant, unsigned g, hipStream_t st, const PassArgs &a) {
     switch (variant) {
-        case 7: k_pass_half<CS, true, true, true><<<g, 256, 0, st>>>(a); break;
-        case 6: k_pass_half<CS, true, true, false><<<g, 256, 0, st>>>(a); break;
-        case 5: k_pass_half<CS, true, false, true><<<g, 256, 0, st>>>(a); break;
-        case 4: k_pass_half<CS, true, false, false><<<g, 256, 0, st>>>(a); break;
-        case 3: k_pass_half<CS, false, true, true><<<g, 256, 0, st>>>(a); break;
-        case 2: k_pass_half<CS, false, true, false><<<g, 256, 0, st>>>(a); break;
-        case 1: k_pass_half<CS, false, false, true><<<g, 256, 0, st>>>(a); break;
-        default: k_pass_half<CS, false, false, false><<<g, 256, 0, st>>>(a); break;
+        case 7: k_pass_half<CS, true, true, true, kPbc><<<g, 256, 0, st>>>(a); break;
+        case 6: k_pass_half<CS, true, true, false, kPbc><<<g, 256, 0, st>>>(a); break;
+        case 5: k_pass_half<CS, true, false, true, kPbc><<<g, 256, 0, st>>>(a); break;
+        case 4: k_pass_half<CS, true, false, false, kPbc><<<g, 256, 0, st>>>(a); break;
+        case 3: k_pass_half<CS, false, true, true, kPbc><<<g, 256, 0, st>>>(a); break;
+        case 2: k_pass_half<CS, false, true, false, kPbc><<<g, 256, 0, st>>>(a); break;
+        case 1: k_pass_half<CS, false, false, true, kPbc><<<g, 256, 0, st>>>(a); break;
+        default: k_pass_half<CS, false, false, false, kPbc><<<g, 256, 0, st>>>(a); break;
+    }
+}
+
+template <bool kPbc>
+void launch_any(int cs, bool half, int variant, unsigned g, hipStream_t st, const PassArgs &a) {
+    if (half) {
+        if (cs == 4)
+            launch_pass_half<4, kPbc>(variant, g, st, a);
+        else if (cs == 16)
+            launch_pass_half<16, kPbc>(variant, g, st, a);
+        else
+            launch_pass_half<8, kPbc>(variant, g, st, a);
+    } else if (cs == 4) {
+        launch_pass<4, kPbc>(variant, g, st, a);
+    } else if (cs == 16) {
+        launch_pass<16, kPbc>(variant, g, st, a);
+    } else {
+        launch_pass<8, kPbc>(variant, g, st, a);
     }
 }
 
@@ -492,12 +522,12 @@ using namespace sfcnl;
 
 int sfcnl::pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, int half, const uint32_t *d_sc_info,
                      const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z, const float *d_h,
-                     const float *d_m, float *d_rho, int32_t *d_nnb, const SegTable &seg, const uint32_t *active,
-                     const uint8_t *p_active) {
+                     const float *d_m, float *d_rho, int32_t *d_nnb, const SegTable &seg, const Period &per,
+                     const uint32_t *active, const uint8_t *p_active) {
     if ((active || p_active) && half)
         return set_err(ctx, SFCNL_E_ARG, "nlist_pass: a restricted pass needs the full list");
     PassArgs a{n, (uint32_t)((n + kScSize - 1) / kScSize), d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb,
-               seg, active, p_active};
+               seg, per, active, p_active};
     const unsigned g = blocks_for(a.nsc, kWavesPerBlock);
     hipStream_t st = ctx->stream;
     const int variant = (compress ? 4 : 0) | (d_m ? 2 : 0) | (d_nnb ? 1 : 0);
@@ -510,25 +540,19 @@ int sfcnl::pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, int half, c
             rc = fill_u32(ctx, reinterpret_cast<uint32_t *>(d_nnb), n, 0u);
             if (rc) return rc;
         }
-        if (cs == 4)
-            launch_pass_half<4>(variant, g, st, a);
-        else if (cs == 16)
-            launch_pass_half<16>(variant, g, st, a);
-        else
-            launch_pass_half<8>(variant, g, st, a);
-        SFCNL_LAUNCHED(ctx);
+    }
+    if (per.on())
+        launch_any<true>(cs, half, variant, g, st, a);
+    else
+        launch_any<false>(cs, half, variant, g, st, a);
+    SFCNL_LAUNCHED(ctx);
+    if (half) {
         if (d_m)
             k_pass_finalize<true><<<blocks_for(n, 256), 256, 0, st>>>(n, d_h, d_m, d_rho);
         else
             k_pass_finalize<false><<<blocks_for(n, 256), 256, 0, st>>>(n, d_h, d_m, d_rho);
-    } else if (cs == 4) {
-        launch_pass<4>(variant, g, st, a);
-    } else if (cs == 16) {
-        launch_pass<16>(variant, g, st, a);
-    } else {
-        launch_pass<8>(variant, g, st, a);
+        SFCNL_LAUNCHED(ctx);
     }
-    SFCNL_LAUNCHED(ctx);
     prof_mark(ctx, kStagePass, true);
     return SFCNL_OK;
 }
@@ -537,17 +561,19 @@ static bool cs_ok(int cs) { return cs == 4 || cs == 8 || cs == 16; }
 
 extern "C" int nlist_pass(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, int half,
                           const uint32_t *d_sc_info, const uint32_t *d_pool, const float *d_x, const float *d_y,
-                          const float *d_z, const float *d_h, const float *d_m, float *d_rho, int32_t *d_nnb) {
+                          const float *d_z, const float *d_h, const float *d_m, float *d_rho, int32_t *d_nnb,
+                          const float *h_period) {
     if (!ctx) return SFCNL_E_ARG;
     if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: n out of range");
     if (!cs_ok(cluster_size)) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: cluster_size %d not supported", cluster_size);
     if (compress != 0 && compress != 1) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: compress must be 0 or 1");
     if (half != 0 && half != 1) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: half must be 0 or 1");
+    if (!period_ok(h_period)) return set_err(ctx, SFCNL_E_ARG, "nlist_pass: period must be 3 finite values >= 0");
     if (n == 0) return SFCNL_OK;
     if (!d_sc_info || !d_pool || !d_x || !d_y || !d_z || !d_h || !d_rho)
         return set_err(ctx, SFCNL_E_ARG, "nlist_pass: null pointer");
     return pass_impl(ctx, n, cluster_size, compress, half, d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb,
-                     SegTable{});
+                     SegTable{}, make_period(h_period));
 }
 
 extern "C" int nlist_decode(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, const uint32_t *d_sc_info,

@@ -52,9 +52,13 @@ def test_workspace_queries_are_host_only(lib):
     assert L.build_nlist_workspace(100000, ctypes.byref(o), ctypes.byref(b)) == 0
     assert b.value > 100000 // 64 * 512 * 5
     for bad in (_lib.NlistOpts(5, 1, 64, 512), _lib.NlistOpts(8, 2, 64, 512), _lib.NlistOpts(8, 1, 4, 512),
-                _lib.NlistOpts(8, 1, 64, 0), _lib.NlistOpts(8, 1, 64, 512, 2)):
+                _lib.NlistOpts(8, 1, 64, 0), _lib.NlistOpts(8, 1, 64, 512, 2),
+                _lib.NlistOpts(8, 1, 64, 512, 0, (ctypes.c_float * 3)(1.0, -1.0, 0.0)),
+                _lib.NlistOpts(8, 1, 64, 512, 0, (ctypes.c_float * 3)(float("inf"), 0.0, 0.0))):
         assert L.build_nlist_workspace(1000, ctypes.byref(bad), ctypes.byref(b)) == _lib.E_ARG
     assert L.sfc_sort_workspace(-1, ctypes.byref(b)) == _lib.E_ARG
+    ok = _lib.NlistOpts(8, 1, 64, 512, 1, (ctypes.c_float * 3)(1.0, 0.0, 2.5))
+    assert L.build_nlist_workspace(1000, ctypes.byref(ok), ctypes.byref(b)) == 0
 
 
 def test_null_context_rejected(lib):
@@ -62,8 +66,8 @@ def test_null_context_rejected(lib):
     L = _lib.load()
     assert L.sfcnl_sync(None) == _lib.E_ARG
     assert L.sfc_sort(None, 10, None, None, None, None, None, None, None, 0) == _lib.E_ARG
-    assert L.nlist_pass(None, 10, 8, 1, 0, None, None, None, None, None, None, None, None, None) == _lib.E_ARG
+    assert L.nlist_pass(None, 10, 8, 1, 0, None, None, None, None, None, None, None, None, None, None) == _lib.E_ARG
     par = _lib.LjParams(1.0, 0.01, 0.0, 0.05)
     assert L.nlist_pass_lj(None, 10, 8, 1, 0, None, None, None, None, None, None, ctypes.byref(par), None, None,
-                           None, None) == _lib.E_ARG
+                           None, None, None) == _lib.E_ARG
     assert L.sfcnl_version().startswith(b"sfcnl")
