@@ -295,13 +295,14 @@ def run_lj(args, sf, torch, ctx):
     dev = torch.device("cuda:0")
     x, y, z, h, q = (torch.from_numpy(a).to(dev) for a in (s.x, s.y, s.z, s.h, s.q))
     main_cfg = (args.cluster_size, bool(args.compress), bool(args.half))
+    period = (1.0, 1.0, 1.0) if args.periodic else None  # the lattice fills the unit box
     cfgs = [(cs, c, hf) for cs in (8, 4, 16) for hf in (True, False) for c in (True, False)] if args.sweep else []
     if main_cfg not in cfgs:
         cfgs.append(main_cfg)
     sweep, main = {}, None
     for cs, comp, hf in cfgs:
         pipe = sf.Pipeline(ctx, n, s.box, compress=comp, leaf_bucket=args.leaf_bucket, cluster_size=cs, half=hf,
-                           max_j_per_sc=512, with_mass=True)
+                           max_j_per_sc=512, with_mass=True, period=period)
         for _ in range(max(args.warmup, 1)):
             pipe.step(x, y, z, h, q, density=False)
         torch.cuda.synchronize()
@@ -349,7 +350,8 @@ def run_lj(args, sf, torch, ctx):
         "vs_baseline": None, "dtype": "f32", "data": "synthetic",
         "config": {"workload": s.name, "n": n, "cluster_size": cs, "compress": comp, "leaf_bucket": args.leaf_bucket,
                    "list": "half (each pair once, j > i)" if hf else "full", "list_neighbours": 200,
-                   "cutoff_neighbours": 150, "charges": "rock salt +-1/2", "energy": False},
+                   "cutoff_neighbours": 150, "charges": "rock salt +-1/2", "energy": False,
+                   "boundaries": "periodic (minimum images)" if period else "open"},
         "build_ms": rec["build_ms"], "build_over_pass": rec["build_over_pass"],
         "bytes_per_particle": rec["bytes_per_particle"], "list": st,
         "roofline": {"kernel": kern, "bound": "alu", "achieved": rec["pass_tflops"], "peak": FP32_PEAK_TFLOPS,
@@ -368,6 +370,10 @@ def run_lj(args, sf, torch, ctx):
                                "kind": "oracle", "seconds": dt,
                                "sample": "FP64 Lennard-Jones + Coulomb forces of all %d atoms of the box (cell "
                                          "list, no list build), %.1f s" % (n, dt)}
+        if period:
+            t0 = time.perf_counter()
+            oracle.lj(s.x, s.y, s.z, s.q, mt["eps"], mt["sigma"], mt["coulomb"], mt["r_cut"], period=period)
+            out["cpu_baseline"]["periodic_seconds"] = time.perf_counter() - t0
     print(json.dumps(out), flush=True)
 
 
@@ -391,6 +397,7 @@ def main():
     ap.add_argument("--train-epochs", type=int, default=20)
     ap.add_argument("--seed-h", choices=["global", "analytic"], default="global")
     ap.add_argument("--n", type=int, default=0)
+    ap.add_argument("--periodic", type=int, default=0, help="lj mode: periodic box (the lattice fills it)")
     ap.add_argument("--sweep", type=int, default=1, help="lj mode: also time every cluster size, list form and "
                                                           "compression (0: only the flagged configuration)")
     args = ap.parse_args()

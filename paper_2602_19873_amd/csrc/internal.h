@@ -122,8 +122,10 @@ struct Period {
 Period make_period(const float *period);
 bool period_ok(const float *period);
 
+// d - L for d > L/2 and d + L for d < -L/2, as one subtraction of L with d's
+// sign (the same FP32 operation either way).
 __device__ __forceinline__ float min_image(float d, float L, float hL) {
-    return d > hL ? d - L : (d < -hL ? d + L : d);
+    return fabsf(d) > hL ? d - copysignf(L, d) : d;
 }
 
 }  // namespace sfcnl
@@ -262,6 +264,18 @@ __device__ __forceinline__ uint32_t sfc_incl_scan(uint32_t v) {
         if (l >= d) v += t;
     }
     return v;
+}
+
+// Minimum images of a pair's components on periodic axes, skipped for the
+// whole wave when no lane's component exceeds half its period (then none
+// changes): only tiles that straddle a periodic face pay for the selects.
+__device__ __forceinline__ void wave_min_image(float &dx, float &dy, float &dz, const sfcnl::Period &p) {
+    const bool far = fabsf(dx) > p.hL[0] || fabsf(dy) > p.hL[1] || fabsf(dz) > p.hL[2];
+    if (sfc_ballot(far)) {
+        dx = sfcnl::min_image(dx, p.L[0], p.hL[0]);
+        dy = sfcnl::min_image(dy, p.L[1], p.hL[1]);
+        dz = sfcnl::min_image(dz, p.L[2], p.hL[2]);
+    }
 }
 
 // Common leading 3-bit digits of two 63-bit keys (21 if equal).

@@ -43,11 +43,7 @@ struct LjArgs {
 // minimum images of a pair's components on periodic axes
 template <bool kPbc>
 __device__ __forceinline__ void wrap3(float &dx, float &dy, float &dz, const Period &p) {
-    if (kPbc) {
-        dx = min_image(dx, p.L[0], p.hL[0]);
-        dy = min_image(dy, p.L[1], p.hL[1]);
-        dz = min_image(dz, p.L[2], p.hL[2]);
-    }
+    if (kPbc) wave_min_image(dx, dy, dz, p);
 }
 
 // fr = -(dU/dr) / r of one pair at squared distance d2, and (kE) the pair

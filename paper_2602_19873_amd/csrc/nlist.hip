@@ -54,8 +54,8 @@ __device__ __forceinline__ float axis_gap(float d1, float d2, float L) {
 
 // Boxes carry .w of lo = largest radius inside. True if some particle pair
 // across the two boxes could satisfy d2 < max(h_i, h_j)^2.
-template <bool kPbc = false>
-__device__ __forceinline__ bool boxes_near(float4 alo, float4 ahi, float4 blo, float4 bhi, const Period &per = Period{}) {
+template <bool kPbc>
+__device__ __forceinline__ bool boxes_near_p(float4 alo, float4 ahi, float4 blo, float4 bhi, const Period &per) {
     float gx = axis_gap<kPbc>(blo.x - ahi.x, alo.x - bhi.x, per.L[0]);
     float gy = axis_gap<kPbc>(blo.y - ahi.y, alo.y - bhi.y, per.L[1]);
     float gz = axis_gap<kPbc>(blo.z - ahi.z, alo.z - bhi.z, per.L[2]);
@@ -63,6 +63,12 @@ __device__ __forceinline__ bool boxes_near(float4 alo, float4 ahi, float4 blo, f
     float d2 = __builtin_fmaf(gz, gz, __builtin_fmaf(gy, gy, gxx));
     float ra = alo.w * alo.w, rb = blo.w * blo.w;
     return d2 < fmaxf(ra, rb);
+}
+// per is wave-uniform: super-clusters that need no wrapping take the open test
+template <bool kPbc = false>
+__device__ __forceinline__ bool boxes_near(float4 alo, float4 ahi, float4 blo, float4 bhi, const Period &per = Period{}) {
+    if (kPbc && per.on()) return boxes_near_p<true>(alo, ahi, blo, bhi, per);
+    return boxes_near_p<false>(alo, ahi, blo, bhi, per);
 }
 
 // Position for absent particles: any distance to it overflows to +inf.
@@ -219,12 +225,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
     if (kPbc && sfc_ballot(big) && lane == 0) atomicOr(&a.status[kStInputErr], 8u);
     const uint32_t own_c0 = s * kNsub;  // first i-cluster of this super-cluster
     const uint32_t own_p0 = s * kScSize;  // and its first particle
-    // minimum images of a pair's components on periodic axes
-    auto wrap = [&](float &dx, float &dy, float &dz) {
-        dx = min_image(dx, a.per.L[0], a.per.hL[0]);
-        dy = min_image(dy, a.per.L[1], a.per.hL[1]);
-        dz = min_image(dz, a.per.L[2], a.per.hL[2]);
-    };
+
     constexpr bool half = kHalf;
     const float4 empty_lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
     const float4 empty_hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
@@ -281,6 +282,44 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
             glo.w = rmax(16 * (lane >> 4), 16);
         wave_sync();
     }
+
+    // Periodic axes: a pair can take an image one period away only if the
+    // super-cluster lies within the largest search radius R of the far face
+    // of the particles' span (a direct difference above L - R). Otherwise
+    // every minimum image is the direct one and the super-cluster runs the
+    // open-boundary tests; the margin on R keeps the decision on the safe side
+    // of FP32 rounding, so no accepted pair changes.
+    bool wraps = false;
+    if (kPbc) {
+        float slo[3] = {glo.x, glo.y, glo.z}, shi[3] = {ghi.x, ghi.y, ghi.z};
+        float r = glo.w;  // full build: replaced by the largest radius of all
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) {
+#pragma unroll
+            for (int t = 0; t < 3; t++) {
+                slo[t] = fminf(slo[t], __shfl_xor(slo[t], d, 64));
+                shi[t] = fmaxf(shi[t], __shfl_xor(shi[t], d, 64));
+            }
+            r = fmaxf(r, __shfl_xor(r, d, 64));
+        }
+        const float4 rlo = a.cs_box[0], rhi = a.cs_box[1];  // root box: the particles' span
+        if (!gather) r = fmaxf(r, rlo.w);  // pairs use max(h_i, h_j)
+        const float plo[3] = {rlo.x, rlo.y, rlo.z}, phi[3] = {rhi.x, rhi.y, rhi.z};
+        bool w_lane = false;
+#pragma unroll
+        for (int t = 0; t < 3; t++) {
+            if (a.per.L[t] < INFINITY) {
+                const float reach = a.per.L[t] - 1.0001f * r - 1e-5f * a.per.L[t];
+                w_lane = w_lane || !(phi[t] - slo[t] <= reach) || !(shi[t] - plo[t] <= reach);
+            }
+        }
+        wraps = sfc_ballot(w_lane) != 0;
+    }
+    const Period per = wraps ? a.per : Period{};
+    // minimum images of a pair's components on periodic axes
+    auto wrap = [&](float &dx, float &dy, float &dz) {
+        if (wraps) wave_min_image(dx, dy, dz, a.per);
+    };
 
     // stack of node records {first, end, child count (0 = leaf), first child
     // slot}; a node is pushed only after its box passed the test
@@ -353,7 +392,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                 uint64_t bal[kIbox];
                 uint32_t anyj;
 #pragma unroll
-                for (int t = 0; t < kIbox; t++) bal[t] = sfc_ballot(boxes_near<kPbc>(ilo[t], ihi[t], blo, bhi, a.per));
+                for (int t = 0; t < kIbox; t++) bal[t] = sfc_ballot(boxes_near<kPbc>(ilo[t], ihi[t], blo, bhi, per));
                 if (CS == 8) {
                     anyj = byte_or(bal[0]);
                 } else if (CS == 4) {
@@ -502,7 +541,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                 const float4 hi = a.cs_box[2 * (size_t)slot + 1];
                 crec = a.cs_rec[slot];
                 // a half list never needs a node that ends before the super-cluster
-                hit = boxes_near<kPbc>(glo, ghi, lo, hi, a.per) && (!half || crec.y > own_p0);
+                hit = boxes_near<kPbc>(glo, ghi, lo, hi, per) && (!half || crec.y > own_p0);
             }
             const uint32_t keep = byte_or(sfc_ballot(hit));
             const int cnt = __popc(keep);

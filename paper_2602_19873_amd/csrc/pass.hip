@@ -38,11 +38,7 @@ __device__ __forceinline__ void tile_pair(float xj, float yj, float zj, float mj
     float dx = xj - xi;
     float dy = yj - yi;
     float dz = zj - zi;
-    if (kPbc) {  // minimum images on periodic axes
-        dx = min_image(dx, per.L[0], per.hL[0]);
-        dy = min_image(dy, per.L[1], per.hL[1]);
-        dz = min_image(dz, per.L[2], per.hL[2]);
-    }
+    if (kPbc) wave_min_image(dx, dy, dz, per);  // minimum images on periodic axes
     const float dxx = dx * dx;
     const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
     const bool in = d2 < h2 && !self_pair;
@@ -237,11 +233,7 @@ __device__ __forceinline__ void half_pair(float xj, float yj, float zj, float mj
     float dx = xj - xi;
     float dy = yj - yi;
     float dz = zj - zi;
-    if (kPbc) {  // minimum images on periodic axes
-        dx = min_image(dx, per.L[0], per.hL[0]);
-        dy = min_image(dy, per.L[1], per.hL[1]);
-        dz = min_image(dz, per.L[2], per.hL[2]);
-    }
+    if (kPbc) wave_min_image(dx, dy, dz, per);  // minimum images on periodic axes
     const float dxx = dx * dx;
     const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
     const bool ini = keep && d2 < hi2;
