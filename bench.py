@@ -142,7 +142,8 @@ def run_hiter(args, sf, torch, ctx):
         hw.copy_(h0)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        res = sf.h_iterate(ctx, keys, xs, ys, zs, hw, target=T, tol=1, max_iters=64, half=bool(args.half), **bufs)
+        res = sf.h_iterate(ctx, keys, xs, ys, zs, hw, target=T, tol=1, max_iters=64, half=bool(args.half),
+                           recount=args.recount, **bufs)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
         bufs = dict(ws=res.nl.ws, pool=res.nl.pool, max_j_per_sc=res.nl.max_j_per_sc)
@@ -214,7 +215,7 @@ def run_batch(args, sf, torch, ctx):
                 kw.update(mlp_params=params, box_edge=hseed.box_edge(systems[k].box),
                           seed_mode=sf.SEED_BEFORE_FIRST)
             res = sf.h_iterate(ctx, keys_k, x_k, y_k, z_k, h_k, target=T, tol=1, max_iters=64, half=bool(args.half),
-                               **kw)
+                               recount=args.recount, **kw)
             single_bufs[k] = dict(ws=res.nl.ws, pool=res.nl.pool, max_j_per_sc=res.nl.max_j_per_sc)
             if not res.converged:
                 raise RuntimeError("system %d did not converge" % k)
@@ -230,7 +231,7 @@ def run_batch(args, sf, torch, ctx):
         kw = dict(mlp_params=params, seed_mode=sf.SEED_BEFORE_FIRST) if seeded else {}
         res = sf.batch_h_iterate(ctx, b, keys, xs, ys, zs, hb, target=T, tol=1, max_iters=64, use_graph=use_graph,
                                  leaf_bucket=tuned["leaf_bucket"], cluster_size=tuned["cluster_size"],
-                                 half=bool(args.half), bufs=batch_bufs, **kw)
+                                 half=bool(args.half), bufs=batch_bufs, recount=args.recount, **kw)
         if not res.converged:
             raise RuntimeError("batch did not converge")
         return res.sys_rounds.tolist(), [res.nnb[real]]
@@ -397,6 +398,8 @@ def main():
     ap.add_argument("--train-epochs", type=int, default=20)
     ap.add_argument("--seed-h", choices=["global", "analytic"], default="global")
     ap.add_argument("--n", type=int, default=0)
+    ap.add_argument("--recount", type=int, default=0, help="hiter/batch: rounds after the first recount by "
+                                                            "0 automatic choice, 1 lists, 2 one wave per moved particle")
     ap.add_argument("--periodic", type=int, default=0, help="lj mode: periodic box (the lattice fills it)")
     ap.add_argument("--sweep", type=int, default=1, help="lj mode: also time every cluster size, list form and "
                                                           "compression (0: only the flagged configuration)")

@@ -230,11 +230,17 @@ int nlist_decode(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, const
  * Each round: build_clusters, build_nlist, nlist_pass, update; it stops when no
  * particle moved, after max_iters rounds, or on an error. The first round of a
  * call counts every particle with the requested list form; later rounds
- * rebuild full lists only for the super-clusters where some radius moved in
- * the previous round (n_i depends on h_i alone, so the other counts cannot
- * change and the rounds, radii and counts are those of recounting
- * everything), and a converged run that needed more than one round ends with
- * one list build of every super-cluster in the requested form. The workspace
+ * recount only the particles whose radius moved in the previous round (n_i
+ * depends on h_i alone, so the other counts cannot change and the rounds,
+ * radii and counts are those of recounting everything), and a converged run
+ * that needed more than one round ends with one list build of every
+ * super-cluster in the requested form. A later round recounts either through
+ * full lists of the super-clusters holding a moved particle (each octree walk
+ * shared by up to 64 particles) or, when few moved, with one wavefront per
+ * moved particle walking the octree with its own sphere and no list;
+ * opts->recount chooses: 0 by the number moved (at most n / 4 + 64: per
+ * particle), 1 lists, 2 per particle. Counts and radii are the same either
+ * way; densities differ in summation order only. The workspace
  * is build_nlist_workspace(n, nl_opts) bytes. If only that closing build does
  * not fit, SFCNL_E_CAPACITY comes back with h_stats->unconverged == 0: radii,
  * d_rho and d_nnb are final and the list can be built with build_nlist after
@@ -251,6 +257,7 @@ typedef struct {
     int tol;
     int max_iters;
     int resume;
+    int recount;  /* 0 automatic, 1 lists, 2 one wavefront per moved particle */
 } sfcnl_hiter_opts;
 
 /* Optional learned step (see section 6), used when `seed` is not NULL:

@@ -292,7 +292,7 @@ def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, m
               ws=None, pool=None, sc_info=None, rho=None, nnb=None, raise_noconv: bool = False,
               resume: bool = False, mlp_params=None, box_edge: float = 0.0, seed_scratch=None,
               seed_mode: int = _lib.SEED_AFTER_FIRST, cluster_size: int = CLUSTER_SIZE, half: bool = False,
-              period=None):
+              period=None, recount: int = 0):
     """Iterates the SFC-ordered radii h (updated in place) to target +- tol
     own-radius neighbours (sfcnl_h_iterate). With mlp_params the first round's
     update comes from the learned seed. Grows list buffers and resumes when
@@ -327,7 +327,7 @@ def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, m
         if ws is None or ws.numel() < need:
             ws = e(max(need, 1), torch.uint8)
         no = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc, half, period)
-        io = _lib.HiterOpts(target, tol, max_iters - total, resume)
+        io = _lib.HiterOpts(target, tol, max_iters - total, resume, int(recount))
         st = _lib.HiterStats()
         seed_arg = C.byref(hs) if (hs is not None and total == 0) else None
         rc = ctx.lib.sfcnl_h_iterate(ctx.handle, n, _ptr(keys), _ptr(x), _ptr(y), _ptr(z), _ptr(h), _ptr(bracket),
@@ -643,10 +643,12 @@ class BatchIterResult:
 def batch_h_iterate(ctx: Context, b: Batch, keys, x, y, z, h, target: int = 100, tol: int = 1, max_iters: int = 64,
                     m=None, compress: bool = True, leaf_bucket: int = 128, max_j_per_sc: int = 512,
                     use_graph: bool = True, mlp_params=None, seed_mode: int = _lib.SEED_AFTER_FIRST,
-                    bufs: dict | None = None, cluster_size: int = CLUSTER_SIZE, half: bool = False):
+                    bufs: dict | None = None, cluster_size: int = CLUSTER_SIZE, half: bool = False,
+                    recount: int = 0):
     """sfcnl_batch_h_iterate on padded SFC-ordered arrays (h updated in
     place). `bufs` (a dict, filled on first use) keeps every buffer for reuse
-    across calls; buffers grow and the run resumes on SFCNL_E_CAPACITY."""
+    across calls; buffers grow and the run resumes on SFCNL_E_CAPACITY.
+    recount: 0 automatic, 1 lists, 2 one wavefront per moved particle."""
     import numpy as np
     n = b.n_pad
     nsc = n // SC_SIZE
@@ -677,7 +679,7 @@ def batch_h_iterate(ctx: Context, b: Batch, keys, x, y, z, h, target: int = 100,
         if "ws" not in B or B["ws"].numel() < need:
             B["ws"] = e(max(need, 1), torch.uint8)
         no = _opts(cluster_size, compress, leaf_bucket, mj, half)
-        io = _lib.HiterOpts(target, tol, max(max_iters - total, 1), resume)
+        io = _lib.HiterOpts(target, tol, max(max_iters - total, 1), resume, int(recount))
         st = _lib.HiterStats()
         r = np.zeros(b.nsys, dtype=np.int32)
         seed_arg = C.byref(hs) if (hs is not None and total == 0) else None

@@ -43,7 +43,8 @@ class NlistOpts(C.Structure):
 
 
 class HiterOpts(C.Structure):
-    _fields_ = [("target", C.c_int), ("tol", C.c_int), ("max_iters", C.c_int), ("resume", C.c_int)]
+    _fields_ = [("target", C.c_int), ("tol", C.c_int), ("max_iters", C.c_int), ("resume", C.c_int),
+                ("recount", C.c_int)]
 
 
 class HiterStats(C.Structure):

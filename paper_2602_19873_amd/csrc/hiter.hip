@@ -95,6 +95,23 @@ __global__ __launch_bounds__(256) void k_h_update(int64_t n, const int32_t *__re
     }
 }
 
+// The moved total for the host's status read (the next round's list build
+// clears the status block; the total itself stays in the scan output).
+__global__ void k_publish_total(const uint32_t *total, uint32_t *status) { status[kStUnconverged] = *total; }
+
+// Rounds after the first recount the moved particles one wavefront each
+// (count_moved_impl) when they are at most this many; above it, building the
+// lists of their super-clusters shares each walk among up to 64 particles.
+// Measured on the 1/r sphere and the 64-system batch: the per-particle walk
+// wins up to about a quarter of the particles.
+uint32_t count_path_limit(int64_t n) { return (uint32_t)(n / 4 + 64); }
+
+// Grid of the per-particle recount: up to 8192 wavefronts.
+unsigned count_blocks(uint32_t total) {
+    const uint32_t b = (total + 3u) / 4u;
+    return b < 1u ? 1u : (b > 2048u ? 2048u : b);
+}
+
 }  // namespace
 }  // namespace sfcnl
 
@@ -116,6 +133,8 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
     if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "sfcnl_h_iterate: n out of range");
     if (it_opts->target < 1 || it_opts->tol < 0 || it_opts->max_iters < 1)
         return set_err(ctx, SFCNL_E_ARG, "sfcnl_h_iterate: target >= 1, tol >= 0, max_iters >= 1 required");
+    if (it_opts->recount < 0 || it_opts->recount > 2)
+        return set_err(ctx, SFCNL_E_ARG, "sfcnl_h_iterate: recount must be 0, 1 or 2");
     if (n == 0) {
         S.unconverged = 0;
         return SFCNL_OK;
@@ -162,14 +181,24 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
             rc = clusters_impl(ctx, n, d_x, d_y, d_z, d_h, o.cluster_size, d_bbox, SegTable{});
             if (rc) return rc;
         }
-        // later rounds: counting lists of the moved particles, same octree
-        rc = nlist_build_impl(ctx, n, d_keys, d_x, d_y, d_z, d_h, d_bbox, o, d_ws, ws_bytes, d_sc_info, d_pool,
-                              pool_bytes, SegTable{}, true, &S.used_bytes, &S.max_nj, first ? nullptr : act.sc,
-                              first ? nullptr : act.p, !first);
-        if (rc) return rc;
-        rc = pass_impl(ctx, n, o.cluster_size, o.compress, o.half, d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho,
-                       d_nnb, SegTable{}, make_period(o.period), first ? nullptr : act.sc, first ? nullptr : act.p);
-        if (rc) return rc;
+        const bool per_particle = it_opts->recount == 2 ||
+                                  (it_opts->recount == 0 && S.unconverged <= count_path_limit(n));
+        if (!first && per_particle) {
+            // few moved: one wavefront per moved particle on the last octree
+            rc = count_moved_impl(ctx, n, act, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb, SegTable{},
+                                  make_period(o.period), nullptr, 0, count_blocks((uint32_t)S.unconverged));
+            if (rc) return rc;
+        } else {
+            // later rounds: counting lists of the moved particles, same octree
+            rc = nlist_build_impl(ctx, n, d_keys, d_x, d_y, d_z, d_h, d_bbox, o, d_ws, ws_bytes, d_sc_info, d_pool,
+                                  pool_bytes, SegTable{}, true, &S.used_bytes, &S.max_nj, first ? nullptr : act.sc,
+                                  first ? nullptr : act.p, !first);
+            if (rc) return rc;
+            rc = pass_impl(ctx, n, o.cluster_size, o.compress, o.half, d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m,
+                           d_rho, d_nnb, SegTable{}, make_period(o.period), first ? nullptr : act.sc,
+                           first ? nullptr : act.p);
+            if (rc) return rc;
+        }
         list_final = first;
         const float *proposal = nullptr;
         if (seed && seed->mode == SFCNL_SEED_AFTER_FIRST && first) {  // learned step from the first counts
@@ -183,8 +212,10 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
         k_h_update<<<blocks_for(n, 256), 256, 0, strm>>>(n, d_nnb, d_h, br, it_opts->target, it_opts->tol, proposal,
                                                         ctx->d_status, SegTable{}, nullptr, act.sc, act.p);
         SFCNL_LAUNCHED(ctx);
-        rc = scan_u32(ctx, act.sc, act.scan, nsc, ctx->d_status + kStUnconverged, act.scan_tmp);
+        rc = scan_u32(ctx, act.sc, act.scan, nsc, act.scan + nsc, act.scan_tmp);
         if (rc) return rc;
+        k_publish_total<<<1, 1, 0, strm>>>(act.scan + nsc, ctx->d_status);
+        SFCNL_LAUNCHED(ctx);
         SFCNL_HIP(ctx, hipMemcpyAsync(ctx->h_status + kStUnconverged, ctx->d_status + kStUnconverged,
                                       sizeof(uint32_t), hipMemcpyDeviceToHost, strm));
         SFCNL_HIP(ctx, hipStreamSynchronize(strm));
@@ -244,13 +275,25 @@ int enqueue_round(sfcnl_ctx ctx, const RoundArgs &r, const sfcnl_nlist_opts &o, 
         rc = clusters_impl(ctx, n, r.x, r.y, r.z, r.h, o.cluster_size, r.bbox, seg);
         if (rc) return rc;
     }
+    // restricted rounds hold both recounts; the moved total (left in the scan
+    // output by the previous round) selects one on the device: the lists of
+    // the moved particles' super-clusters, or one wavefront per moved particle
+    const uint32_t *gate = restricted ? act.scan + n / kScSize : nullptr;
+    // recount 1: lists only (the per-particle path runs for a zero total,
+    // where it has nothing to do); 2: per particle only
+    const uint32_t limit = r.it->recount == 1 ? 0u : (r.it->recount == 2 ? 0xFFFFFFFFu : count_path_limit(n));
     rc = nlist_build_impl(ctx, n, r.keys, r.x, r.y, r.z, r.h, r.bbox, o, r.ws, r.ws_bytes, r.sc_info, r.pool,
                           r.pool_bytes, seg, false, nullptr, nullptr, restricted ? act.sc : nullptr,
-                          restricted ? act.p : nullptr, restricted);
+                          restricted ? act.p : nullptr, restricted, gate, limit);
     if (rc) return rc;
     rc = pass_impl(ctx, n, o.cluster_size, o.compress, o.half, r.sc_info, r.pool, r.x, r.y, r.z, r.h, r.m, r.rho,
-                   r.nnb, seg, Period{}, restricted ? act.sc : nullptr, restricted ? act.p : nullptr);
+                   r.nnb, seg, Period{}, restricted ? act.sc : nullptr, restricted ? act.p : nullptr, gate, limit);
     if (rc) return rc;
+    if (restricted) {
+        rc = count_moved_impl(ctx, n, act, r.x, r.y, r.z, r.h, r.m, r.rho, r.nnb, seg, Period{}, gate, limit,
+                              count_blocks(r.it->recount == 2 ? 8192u : limit));
+        if (rc) return rc;
+    }
     const float *proposal = nullptr;
     if (seed) {
         rc = features_impl(ctx, n, r.keys, r.x, r.y, r.z, r.h, r.nnb, 1.0f, r.it->target, seed->d_feat, seg);
@@ -264,8 +307,10 @@ int enqueue_round(sfcnl_ctx ctx, const RoundArgs &r, const sfcnl_nlist_opts &o, 
     k_h_update<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, r.nnb, r.h, r.br, r.it->target, r.it->tol, proposal,
                                                            ctx->d_status, seg, r.b->d_sys_moved, act.sc, act.p);
     SFCNL_LAUNCHED(ctx);
-    rc = scan_u32(ctx, act.sc, act.scan, n / kScSize, ctx->d_status + kStUnconverged, act.scan_tmp);
+    rc = scan_u32(ctx, act.sc, act.scan, n / kScSize, act.scan + n / kScSize, act.scan_tmp);
     if (rc) return rc;
+    k_publish_total<<<1, 1, 0, ctx->stream>>>(act.scan + n / kScSize, ctx->d_status);
+    SFCNL_LAUNCHED(ctx);
     SFCNL_HIP(ctx, hipMemcpyAsync(ctx->h_status, ctx->d_status, kStWords * sizeof(uint32_t), hipMemcpyDeviceToHost,
                                   ctx->stream));
     SFCNL_HIP(ctx, hipMemcpyAsync(r.b->h_sys_moved, r.b->d_sys_moved, r.b->nsys * sizeof(uint32_t),
@@ -324,6 +369,8 @@ extern "C" int sfcnl_batch_h_iterate(sfcnl_ctx ctx, sfcnl_batch b, const uint64_
         for (int s = 0; s < b->nsys; s++) h_sys_rounds[s] = 0;
     if (it_opts->target < 1 || it_opts->tol < 0 || it_opts->max_iters < 1)
         return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_h_iterate: target >= 1, tol >= 0, max_iters >= 1 required");
+    if (it_opts->recount < 0 || it_opts->recount > 2)
+        return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_h_iterate: recount must be 0, 1 or 2");
     size_t need;
     if (sfcnl_batch_nlist_workspace(b, nl_opts, &need))
         return set_err(ctx, SFCNL_E_ARG, "sfcnl_batch_h_iterate: bad list options");

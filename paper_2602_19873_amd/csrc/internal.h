@@ -206,18 +206,34 @@ size_t nlist_ws_bytes(int64_t n, const sfcnl_nlist_opts &o, int nsys);
 // flagged particles' own-radius pairs (d2 < h_i^2), so boxes need no radii;
 // `reuse_tree` keeps the octree of the previous build (same keys, bucket and
 // cluster size: its positions and ranges are still exact).
+// `gate` (device word, nullable): when *gate <= gate_max every super-cluster
+// gets an empty list (the moved particles are recounted by count_moved_impl).
 int nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *keys, const float *x, const float *y, const float *z,
                      const float *h, const float *bbox, const sfcnl_nlist_opts &o, void *ws, size_t ws_bytes,
                      uint32_t *sc_info, uint32_t *pool, size_t pool_bytes, const SegTable &seg, bool readback,
                      size_t *used_bytes, int64_t *max_nj, const uint32_t *active = nullptr,
-                     const uint8_t *p_active = nullptr, bool reuse_tree = false);
+                     const uint8_t *p_active = nullptr, bool reuse_tree = false, const uint32_t *gate = nullptr,
+                     uint32_t gate_max = 0);
 // arrays for restricted rebuilds inside a build_nlist workspace
 struct ActiveWs {
     uint32_t *sc;      // per super-cluster: particles that moved
-    uint32_t *scan;    // nsc + 1 words of scan output
+    uint32_t *scan;    // nsc + 1 words: exclusive prefix sum, then the total
     uint8_t *p;        // per particle: moved
     void *scan_tmp;
+    uint32_t *plist;   // n words: the moved particles, in order
+    const float4 *cs_box;  // the octree's child slots (boxes and records)
+    const uint4 *cs_rec;
+    uint32_t nslots;
 };
+// Recount of the moved particles without a list (h-iteration rounds after the
+// first): compacts act.p into act.plist, then one wavefront per listed
+// particle walks the octree of the last full build with the particle's own
+// sphere and writes rho and nnb as the restricted pass would. With `gate`
+// (device word, nullable) both kernels run only if *gate <= gate_max; the
+// per-particle kernel grid is `blocks` workgroups of 4 waves.
+int count_moved_impl(sfcnl_ctx ctx, int64_t n, const ActiveWs &act, const float *x, const float *y, const float *z,
+                     const float *h, const float *m, float *rho, int32_t *nnb, const SegTable &seg, const Period &per,
+                     const uint32_t *gate, uint32_t gate_max, unsigned blocks);
 ActiveWs nlist_ws_active(void *ws, int64_t n, const sfcnl_nlist_opts &o, int nsys);
 int clusters_impl(sfcnl_ctx ctx, int64_t n, const float *x, const float *y, const float *z, const float *h, int cs,
                   float *bbox, const SegTable &seg);
@@ -226,7 +242,7 @@ int clusters_impl(sfcnl_ctx ctx, int64_t n, const float *x, const float *y, cons
 int pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, int half, const uint32_t *sc_info, const uint32_t *pool,
               const float *x, const float *y, const float *z, const float *h, const float *m, float *rho, int32_t *nnb,
               const SegTable &seg, const Period &per, const uint32_t *active = nullptr,
-              const uint8_t *p_active = nullptr);
+              const uint8_t *p_active = nullptr, const uint32_t *gate = nullptr, uint32_t gate_max = 0);
 int features_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *keys, const float *x, const float *y, const float *z,
                   const float *h, const int32_t *nnb, float box_edge, int target, uint16_t *feat,
                   const SegTable &seg);
@@ -264,6 +280,19 @@ __device__ __forceinline__ uint32_t sfc_incl_scan(uint32_t v) {
         if (l >= d) v += t;
     }
     return v;
+}
+
+// Gap along one axis between two boxes (or a point and a box), from
+// d1 = blo - ahi and d2 = alo - bhi (the separations of the direct images). On
+// a periodic axis the gap is also taken to the images one period away,
+// min(d1, d2) + L; both lie within one period, so no other image is closer.
+// Every step rounds monotonically, so the gap never exceeds the |d| of a
+// particle pair across the two after its minimum image is taken.
+template <bool kPbc>
+__device__ __forceinline__ float axis_gap(float d1, float d2, float L) {
+    const float g = fmaxf(fmaxf(d1, d2), 0.0f);
+    if (!kPbc) return g;
+    return fminf(g, fmaxf(fminf(d1, d2) + L, 0.0f));
 }
 
 // Minimum images of a pair's components on periodic axes, skipped for the

@@ -39,19 +39,6 @@ __device__ __forceinline__ void wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
-// Gap along one axis between two boxes, from d1 = blo - ahi and d2 = alo - bhi
-// (the separations of the direct images). On a periodic axis the gap is also
-// taken to the images one period away, min(d1, d2) + L; both boxes lie within
-// one period, so no other image is closer. Every step rounds monotonically, so
-// the gap never exceeds the |d| of a particle pair across the boxes after its
-// minimum image is taken.
-template <bool kPbc>
-__device__ __forceinline__ float axis_gap(float d1, float d2, float L) {
-    const float g = fmaxf(fmaxf(d1, d2), 0.0f);
-    if (!kPbc) return g;
-    return fminf(g, fmaxf(fminf(d1, d2) + L, 0.0f));
-}
-
 // Boxes carry .w of lo = largest radius inside. True if some particle pair
 // across the two boxes could satisfy d2 < max(h_i, h_j)^2.
 template <bool kPbc>
@@ -144,6 +131,8 @@ struct TravArgs {
     // pairs d2 < h_i^2 for i with p_active[i] != 0; node, cluster and j radii
     // are ignored, so the octree's boxes need no refit when only radii change
     const uint8_t *p_active;
+    const uint32_t *gate;  // nullable: every list empty when *gate <= gate_max
+    uint32_t gate_max;
     uint32_t *list_j;      // staging: cap entries per super-cluster
     uint16_t *list_m;
     uint32_t *sc_nj, *sc_words;
@@ -198,7 +187,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
     // wave-uniform: keep the super-cluster index (and all derived from it) scalar
     const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w));
     if (s >= a.nsc) return;
-    if (a.active && !a.active[s]) {  // restricted rebuild: this super-cluster keeps no list
+    if ((a.active && !a.active[s]) || (a.gate && *a.gate <= a.gate_max)) {  // no list for this super-cluster
         if (sfc_lane() == 0) {
             a.sc_nj[s] = 0;
             a.sc_words[s] = 0;
@@ -683,6 +672,7 @@ struct NlistWs {
     uint32_t *sc_scan;    // their prefix sum (nsc + 1)
     uint8_t *p_active;    // per particle flags for restricted rebuilds
     void *scan_tmp;
+    uint32_t *plist;      // the flagged particles, compacted
 };
 
 void carve_nlist(Carver &cv, NlistWs &ws, int64_t n, const sfcnl_nlist_opts &o, int nsys = 1) {
@@ -697,6 +687,7 @@ void carve_nlist(Carver &cv, NlistWs &ws, int64_t n, const sfcnl_nlist_opts &o, 
     ws.sc_scan = cv.take<uint32_t>((size_t)nsc + 1);
     ws.p_active = cv.take<uint8_t>((size_t)n);
     ws.scan_tmp = cv.take<char>(scan_tmp_bytes(nsc));
+    ws.plist = cv.take<uint32_t>((size_t)n);
 }
 
 template <bool kPbc>
@@ -783,14 +774,16 @@ sfcnl::ActiveWs sfcnl::nlist_ws_active(void *d_ws, int64_t n, const sfcnl_nlist_
     Carver cv{reinterpret_cast<char *>(d_ws), 0};
     NlistWs ws;
     carve_nlist(cv, ws, n, o, nsys);
-    return ActiveWs{ws.sc_active, ws.sc_scan, ws.p_active, ws.scan_tmp};
+    return ActiveWs{ws.sc_active, ws.sc_scan, ws.p_active, ws.scan_tmp, ws.plist, ws.tree.cs_box, ws.tree.cs_rec,
+                    ws.tree.node_cap};
 }
 
 int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_x, const float *d_y,
                             const float *d_z, const float *d_h, const float *d_bbox, const sfcnl_nlist_opts &o,
                             void *d_ws, size_t ws_bytes, uint32_t *d_sc_info, uint32_t *d_pool, size_t pool_bytes,
                             const SegTable &seg, bool readback, size_t *h_used_bytes, int64_t *h_max_nj,
-                            const uint32_t *active, const uint8_t *p_active, bool reuse_tree) {
+                            const uint32_t *active, const uint8_t *p_active, bool reuse_tree, const uint32_t *gate,
+                            uint32_t gate_max) {
     if ((active || p_active) && o.half)
         return set_err(ctx, SFCNL_E_ARG, "build_nlist: a restricted rebuild needs the full list");
     const Period per = make_period(o.period);
@@ -836,6 +829,8 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     ta.per = per;
     ta.active = active;
     ta.p_active = p_active;
+    ta.gate = gate;
+    ta.gate_max = gate_max;
     ta.list_j = ws.list_j;
     ta.list_m = ws.list_m;
     ta.sc_nj = ws.sc_nj;

@@ -27,6 +27,8 @@ struct PassArgs {
     Period per;    // periodic axes (used by the kPbc kernels)
     const uint32_t *active;  // nullable: skip super-clusters with active[s] == 0 (full pass)
     const uint8_t *p_active;  // nullable: write only particles with p_active[i] != 0 (full pass)
+    const uint32_t *gate;     // nullable: nothing to do when *gate <= gate_max
+    uint32_t gate_max;
 };
 
 // One particle pair of a tile: the own-radius test, then m_j times the
@@ -72,7 +74,7 @@ __global__ __launch_bounds__(256) void k_pass(PassArgs a) {
     const int w = threadIdx.x / kWave;
     // wave-uniform: keep the super-cluster index (and all derived from it) scalar
     const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w));
-    if (s >= a.nsc || (a.active && !a.active[s])) return;
+    if (s >= a.nsc || (a.active && !a.active[s]) || (a.gate && *a.gate <= a.gate_max)) return;
     const int64_t n = a.n;
     const int jl = lane & (kGroup - 1);
 
@@ -515,11 +517,11 @@ using namespace sfcnl;
 int sfcnl::pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, int half, const uint32_t *d_sc_info,
                      const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z, const float *d_h,
                      const float *d_m, float *d_rho, int32_t *d_nnb, const SegTable &seg, const Period &per,
-                     const uint32_t *active, const uint8_t *p_active) {
-    if ((active || p_active) && half)
+                     const uint32_t *active, const uint8_t *p_active, const uint32_t *gate, uint32_t gate_max) {
+    if ((active || p_active || gate) && half)
         return set_err(ctx, SFCNL_E_ARG, "nlist_pass: a restricted pass needs the full list");
     PassArgs a{n, (uint32_t)((n + kScSize - 1) / kScSize), d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb,
-               seg, per, active, p_active};
+               seg, per, active, p_active, gate, gate_max};
     const unsigned g = blocks_for(a.nsc, kWavesPerBlock);
     hipStream_t st = ctx->stream;
     const int variant = (compress ? 4 : 0) | (d_m ? 2 : 0) | (d_nnb ? 1 : 0);

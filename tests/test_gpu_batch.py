@@ -151,14 +151,14 @@ def _perturbed(systems, seed, spread=2.0):
     return systems
 
 
-@pytest.mark.parametrize("use_graph", [True, False])
-def test_h_iterate_matches_single(env, use_graph):
+@pytest.mark.parametrize("use_graph,recount", [(True, 0), (False, 0), (True, 1), (True, 2)])
+def test_h_iterate_matches_single(env, use_graph, recount):
     sf, ctx, torch = env
     T = 60
     systems = _perturbed(_systems(SIZES_IT, T, 700), 701)
     b = _batch(sf, ctx, systems)
     keys, xs, ys, zs, hs = _batch_arrays(sf, ctx, torch, b, systems)
-    res = sf.batch_h_iterate(ctx, b, keys, xs, ys, zs, hs, target=T, tol=1, use_graph=use_graph)
+    res = sf.batch_h_iterate(ctx, b, keys, xs, ys, zs, hs, target=T, tol=1, use_graph=use_graph, recount=recount)
     _say("batch: %d rounds, per system %s" % (res.iters, res.sys_rounds.tolist()))
     assert res.converged and res.unconverged == 0
     hb, nb = hs.cpu().numpy(), res.nnb.cpu().numpy()

@@ -116,3 +116,30 @@ def test_half_list_iteration_matches_full(env):
     assert ra.converged and rb.converged and ra.iters == rb.iters
     np.testing.assert_array_equal(a[4].cpu().numpy(), b[4].cpu().numpy())
     np.testing.assert_array_equal(ra.nnb.cpu().numpy(), rb.nnb.cpu().numpy())
+
+
+@pytest.mark.parametrize("kind", ["sphere", "plummer"])
+def test_recount_paths_agree(env, kind):
+    """Rounds after the first recount the moved particles through lists or
+    one wavefront per particle: same rounds, radii and counts either way,
+    densities equal up to summation order."""
+    sf, ctx, torch = env
+    T = 100
+    s = workloads.evrard_sphere(40000, 75, target=T) if kind == "sphere" else workloads.plummer(40000, 76, target=T)
+    keys, xs, ys, zs, hs = _sorted_inputs(env, s)
+    h0 = hs.clone()
+    out = {}
+    for mode in (1, 2, 0):
+        hs.copy_(h0)
+        res = sf.h_iterate(ctx, keys, xs, ys, zs, hs, target=T, tol=1, max_iters=64, recount=mode)
+        torch.cuda.synchronize()
+        _say("recount=%d: converged=%s rounds=%d" % (mode, res.converged, res.iters))
+        assert res.converged
+        out[mode] = (res.iters, hs.cpu().numpy().copy(), res.nnb.cpu().numpy()[: s.n].copy(),
+                     res.rho.cpu().numpy()[: s.n].astype(np.float64))
+    for mode in (2, 0):
+        assert out[mode][0] == out[1][0]
+        np.testing.assert_array_equal(out[mode][1], out[1][1])
+        np.testing.assert_array_equal(out[mode][2], out[1][2])
+        np.testing.assert_allclose(out[mode][3], out[1][3], rtol=2e-6, atol=0)
+    _check_final((xs.cpu().numpy(), ys.cpu().numpy(), zs.cpu().numpy(), out[2][1]), res, T, 1)
