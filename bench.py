@@ -343,7 +343,8 @@ def run_lj(args, sf, torch, ctx):
     key, rec, st = main
     cs, comp, hf = main_cfg
     hb = "true" if hf else "false"
-    kern = "k_pass_lj%s<%d, %s, true, false>" % ("_half" if hf else "", cs, "true" if comp else "false")
+    kern = "k_pass_lj%s<%d, %s, true, false, %s>" % ("_half" if hf else "", cs, "true" if comp else "false",
+                                                     "true" if period else "false")
     out = {
         "metric": "Lennard-Jones 12/6 + Coulomb force pass over the compressed cluster list, Mparticles/s",
         "value": n / (rec["pass_ms"] * 1e-3) / 1e6, "unit": "Mparticles/s", "n_gpus": 1, "steps": args.steps,
@@ -484,9 +485,9 @@ def main():
     dom = max((k for k in stages if "bound" in stages[k]), key=lambda k: stages[k]["ms"])
     dd = stages[dom]
     hb = "true" if args.half else "false"
-    kernel_of = {"traverse": ("k_traverse<%d, %s>" % (args.cluster_size, hb), "nlist.hip"),
-                 "pass": ("k_pass_half<%d, true, false, true>" % args.cluster_size if args.half
-                          else "k_pass<%d, true, false, true>" % args.cluster_size, "pass.hip")}
+    kernel_of = {"traverse": ("k_traverse<%d, %s, false>" % (args.cluster_size, hb), "nlist.hip"),
+                 "pass": ("k_pass_half<%d, true, false, true, false>" % args.cluster_size if args.half
+                          else "k_pass<%d, true, false, true, false>" % args.cluster_size, "pass.hip")}
     traffic = read_traffic(kernel_of[dom][0], n) if dom in kernel_of else None
     roofline = {"kernel": kernel_of.get(dom, (dom,))[0], "bound": dd["bound"], "achieved": dd["achieved"],
                 "peak": dd["peak"], "unit": dd["unit"], "frac": dd["frac"], "traffic": traffic,
