@@ -80,6 +80,10 @@ def _load():
         lib.orc_encode_sc.argtypes = [C.c_int64, u32p, u16p, C.c_int, C.c_int, C.c_void_p]
         lib.orc_decode_sc.restype = C.c_int64
         lib.orc_decode_sc.argtypes = [u32p, C.c_int64, C.c_int, C.c_int, u32p, u16p]
+        lib.orc_encode_row.restype = C.c_int64
+        lib.orc_encode_row.argtypes = [C.c_int64, u32p, C.c_int, C.c_void_p]
+        lib.orc_decode_row.restype = C.c_int64
+        lib.orc_decode_row.argtypes = [u32p, C.c_int64, C.c_int, u32p]
         lib.orc_kernel_w.restype = C.c_double
         lib.orc_kernel_w.argtypes = [C.c_double, C.c_double]
         lib.orc_density.restype = None
@@ -255,6 +259,49 @@ def decode_sc(words, nj: int, cs: int = 8, compress: bool = True):
     if used < 0:
         raise ValueError("malformed stream")
     return j[:nj], m[:nj], int(used)
+
+
+def encode_row(j, compress: bool = True) -> np.ndarray:
+    """Word stream of one 1x1 row (the paper's future-work combination of the
+    compression with a full neighbour list, Sec. V): the ascending indices as
+    the index stream of a super-cluster list, with no masks."""
+    j = np.ascontiguousarray(j, dtype=np.uint32)
+    lib = _load()
+    nw = lib.orc_encode_row(j.shape[0], j, int(compress), None)
+    if nw < 0:
+        raise ValueError("row not strictly ascending")
+    out = np.zeros(max(int(nw), 1), dtype=np.uint32)
+    lib.orc_encode_row(j.shape[0], j, int(compress), out.ctypes.data)
+    return out[: int(nw)]
+
+
+def decode_row(words, nj: int, compress: bool = True):
+    w = np.ascontiguousarray(words, dtype=np.uint32)
+    if w.shape[0] == 0:
+        w = np.zeros(1, np.uint32)
+    j = np.zeros(max(nj, 1), np.uint32)
+    used = _load().orc_decode_row(w, nj, int(compress), j)
+    if used < 0:
+        raise ValueError("malformed stream")
+    return j[:nj], int(used)
+
+
+def row_list(x, y, z, h, compress: bool = True, method: str = "grid", period=None):
+    """The compressed 1x1 list: per particle its ascending neighbours in P
+    (j != i, d2 < max(h_i, h_j)^2), rows laid out in particle order.
+    Returns (info (n x 2 uint32: word offset, count), pool uint32)."""
+    offs, nbr = pairs_csr(x, y, z, h, method, period=period)
+    n = offs.shape[0] - 1
+    info = np.zeros((n, 2), dtype=np.uint32)
+    parts, pos = [], 0
+    for i in range(n):
+        a, b = int(offs[i]), int(offs[i + 1])
+        words = encode_row(nbr[a:b].astype(np.uint32), compress) if b > a else np.zeros(0, np.uint32)
+        info[i] = (pos, b - a)
+        parts.append(words)
+        pos += words.shape[0]
+    pool = np.concatenate(parts) if parts else np.zeros(0, np.uint32)
+    return info, pool
 
 
 def encode_all(offs, j, mask, cs: int = 8, compress: bool = True):

@@ -554,29 +554,15 @@ int orc_encode_block_symbols(const uint32_t *v, int count, uint8_t *bits, uint8_
  *     padded to 4 bytes. */
 static int64_t mask_bytes_per_entry(int cs) { return (64 / cs == 16) ? 2 : 1; }
 
-int64_t orc_encode_sc(int64_t nj, const uint32_t *j, const uint16_t *mask, int cs, int compress,
-                      uint32_t *out /* may be NULL to size */)
+/* The index stream of a list: raw u32 indices, or the differences (from -1)
+ * in nibble segments of up to 64 values. */
+static int64_t encode_values(int64_t nj, const uint32_t *j, int compress, uint32_t *out /* may be NULL */)
 {
-    int64_t mb = mask_bytes_per_entry(cs);
-    int64_t mwords = (nj * mb + 3) / 4;
     int64_t w = 0;
-    if (out) {
-        memset(out, 0, (size_t)mwords * 4);
-        uint8_t *mbytes = (uint8_t *)out;
-        for (int64_t k = 0; k < nj; k++) {
-            if (mb == 2) {
-                mbytes[2 * k] = (uint8_t)(mask[k] & 0xFF);
-                mbytes[2 * k + 1] = (uint8_t)(mask[k] >> 8);
-            } else {
-                mbytes[k] = (uint8_t)mask[k];
-            }
-        }
-    }
-    w = mwords;
     if (!compress) {
         if (out)
-            for (int64_t k = 0; k < nj; k++) out[w + k] = j[k];
-        return w + nj;
+            for (int64_t k = 0; k < nj; k++) out[k] = j[k];
+        return nj;
     }
     uint32_t v[64];
     uint8_t bits[64], info[64], data[64 * 8];
@@ -609,20 +595,45 @@ int64_t orc_encode_sc(int64_t nj, const uint32_t *j, const uint16_t *mask, int c
     return w;
 }
 
-/* Inverse of orc_encode_sc. Returns words consumed, or -1 on a malformed
- * stream. */
-int64_t orc_decode_sc(const uint32_t *in, int64_t nj, int cs, int compress, uint32_t *j, uint16_t *mask)
+int64_t orc_encode_sc(int64_t nj, const uint32_t *j, const uint16_t *mask, int cs, int compress,
+                      uint32_t *out /* may be NULL to size */)
 {
     int64_t mb = mask_bytes_per_entry(cs);
     int64_t mwords = (nj * mb + 3) / 4;
-    const uint8_t *mbytes = (const uint8_t *)in;
-    for (int64_t k = 0; k < nj; k++)
-        mask[k] = mb == 2 ? (uint16_t)(mbytes[2 * k] | (mbytes[2 * k + 1] << 8)) : mbytes[k];
-    int64_t w = mwords;
-    if (!compress) {
-        for (int64_t k = 0; k < nj; k++) j[k] = in[w + k];
-        return w + nj;
+    if (out) {
+        memset(out, 0, (size_t)mwords * 4);
+        uint8_t *mbytes = (uint8_t *)out;
+        for (int64_t k = 0; k < nj; k++) {
+            if (mb == 2) {
+                mbytes[2 * k] = (uint8_t)(mask[k] & 0xFF);
+                mbytes[2 * k + 1] = (uint8_t)(mask[k] >> 8);
+            } else {
+                mbytes[k] = (uint8_t)mask[k];
+            }
+        }
     }
+    int64_t vw = encode_values(nj, j, compress, out ? out + mwords : NULL);
+    return vw < 0 ? -1 : mwords + vw;
+}
+
+/* One row of the 1x1 list (the combination of the compression with a full
+ * neighbour list that the paper names as future work, Sec. V): particle i's
+ * ascending neighbour indices, encoded as the index stream of a super-cluster
+ * list without masks. */
+int64_t orc_encode_row(int64_t nj, const uint32_t *j, int compress, uint32_t *out /* may be NULL to size */)
+{
+    return encode_values(nj, j, compress, out);
+}
+
+/* Inverse of orc_encode_sc. Returns words consumed, or -1 on a malformed
+ * stream. */
+static int64_t decode_values(const uint32_t *in, int64_t nj, int compress, uint32_t *j)
+{
+    if (!compress) {
+        for (int64_t k = 0; k < nj; k++) j[k] = in[k];
+        return nj;
+    }
+    int64_t w = 0;
     uint32_t prev = 0xFFFFFFFFu;
     for (int64_t b0 = 0; b0 < nj; b0 += 64) {
         int cnt = (int)(nj - b0 < 64 ? nj - b0 : 64);
@@ -654,6 +665,22 @@ int64_t orc_decode_sc(const uint32_t *in, int64_t nj, int cs, int compress, uint
         w += 2 + (td + 7) / 8;
     }
     return w;
+}
+
+int64_t orc_decode_sc(const uint32_t *in, int64_t nj, int cs, int compress, uint32_t *j, uint16_t *mask)
+{
+    int64_t mb = mask_bytes_per_entry(cs);
+    int64_t mwords = (nj * mb + 3) / 4;
+    const uint8_t *mbytes = (const uint8_t *)in;
+    for (int64_t k = 0; k < nj; k++)
+        mask[k] = mb == 2 ? (uint16_t)(mbytes[2 * k] | (mbytes[2 * k + 1] << 8)) : mbytes[k];
+    int64_t vw = decode_values(in + mwords, nj, compress, j);
+    return vw < 0 ? -1 : mwords + vw;
+}
+
+int64_t orc_decode_row(const uint32_t *in, int64_t nj, int compress, uint32_t *j)
+{
+    return decode_values(in, nj, compress, j);
 }
 
 /* ------------------------------------------------------------------------- */
