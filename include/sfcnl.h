@@ -13,6 +13,8 @@
  *                   counts (Sec. II-A "neighbor pass", Sec. II-D, Listing 1)
  *   nlist_pass_lj   the Lennard-Jones 12/6 + Coulomb force pass of the
  *                   Sec. III benchmark (interaction cutoff inside the list's)
+ *   build_rows      the compressed 1x1 list derived from a cluster list, and
+ *   rows_pass       its density pass (the paper's future work, Sec. V)
  *
  * Conventions shared by every call:
  *   - d_* arguments are device pointers, h_* arguments are host pointers. The
@@ -206,6 +208,32 @@ int nlist_pass_lj(sfcnl_ctx ctx, int64_t n, int cluster_size, int compress, int 
                   const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z, const float *d_q,
                   const sfcnl_lj_params *params, float *d_fx, float *d_fy, float *d_fz, float *d_epot,
                   const float *h_period);
+
+/* ---- 4c. Compressed 1x1 list (the paper's future work, Sec. V) -----------
+ * The combination of the index compression with a full neighbour list: row i
+ * holds particle i's neighbours in the pair set (j != i,
+ * d2 < f32(max(h_i, h_j)^2), minimum images on periodic axes) in ascending
+ * order, encoded as the index stream of a super-cluster list without masks
+ * (differences from -1 in 64-value nibble segments, or raw u32 indices when
+ * compress = 0). Rows follow each other in particle order; d_row_info [n][2]
+ * u32 holds {word offset, count} per particle (caller-owned, like the pool).
+ * build_rows derives the rows from a FULL cluster list (build_nlist with
+ * half = 0) of the same positions and radii, given with its cluster size and
+ * encoding; h_period as given to that build (NULL: open). The workspace is
+ * build_rows_workspace(n) bytes. Waits for the stream; returns
+ * SFCNL_E_CAPACITY with *h_used_bytes = the pool size needed when pool_bytes
+ * is too small (rows that did not fit are recorded empty; a retry with room
+ * gives the identical rows). rows_pass computes the density and counts of
+ * nlist_pass from the rows (the own-radius subset of each row), one wavefront
+ * per particle, in FP32. */
+int build_rows_workspace(int64_t n, size_t *ws_bytes);
+int build_rows(sfcnl_ctx ctx, int64_t n, int cluster_size, int list_compress, const uint32_t *d_sc_info,
+               const uint32_t *d_pool, const float *d_x, const float *d_y, const float *d_z, const float *d_h,
+               int compress, const float *h_period, void *d_ws, size_t ws_bytes, uint32_t *d_row_info,
+               uint32_t *d_row_pool, size_t pool_bytes, size_t *h_used_bytes);
+int rows_pass(sfcnl_ctx ctx, int64_t n, int compress, const uint32_t *d_row_info, const uint32_t *d_row_pool,
+              const float *d_x, const float *d_y, const float *d_z, const float *d_h, const float *d_m,
+              float *d_rho, int32_t *d_nnb, const float *h_period);
 
 /* Decodes the whole list on the device into flat arrays: super-cluster s's
  * entries go to [d_offsets[s], d_offsets[s] + n_j), with d_offsets the

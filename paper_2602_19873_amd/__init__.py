@@ -256,6 +256,70 @@ def nlist_pass_lj(ctx: Context, nl: NeighbourList, x, y, z, q=None, eps: float =
     return f[:, :n], (e[:n] if energy else None)
 
 
+@dataclass
+class RowList:
+    """Compressed 1x1 list (build_rows): per particle its neighbours in order."""
+    n: int
+    compress: bool
+    row_info: torch.Tensor   # (n, 2) int32 view of u32 {word offset, count}
+    pool: torch.Tensor       # int32 view of u32 words
+    used_bytes: int
+    period: tuple = (0.0, 0.0, 0.0)
+
+    def bytes_per_particle(self) -> float:
+        return (self.used_bytes + 8 * self.n) / max(self.n, 1)
+
+
+def build_rows_workspace(n: int) -> int:
+    b = C.c_size_t()
+    if _lib.load().build_rows_workspace(n, C.byref(b)) != 0:
+        raise SfcnlError(_lib.E_ARG, "build_rows_workspace")
+    return b.value
+
+
+def build_rows(ctx: Context, nl: NeighbourList, x, y, z, h, compress: bool = True, pool=None, ws=None,
+               row_info=None, grow: bool = True) -> RowList:
+    """The compressed 1x1 list from a full cluster list `nl` of the same
+    SFC-ordered positions and radii. Grows the pool and retries when it is
+    too small (unless grow=False, which raises)."""
+    if nl.half:
+        raise ValueError("build_rows needs a full cluster list (half=False)")
+    n = nl.n
+    for t, nm in ((x, "x"), (y, "y"), (z, "z"), (h, "h")):
+        _check_f32(t, n, nm)
+    need = build_rows_workspace(n)
+    if ws is None or ws.numel() < need:
+        ws = ctx.empty(max(need, 1), torch.uint8)
+    if row_info is None:
+        row_info = ctx.empty((max(n, 1), 2), torch.int32)
+    if pool is None:
+        pool = ctx.empty(max(1024, (40 if compress else 320) * n), torch.int32)
+    while True:
+        used = C.c_size_t()
+        rc = ctx.lib.build_rows(ctx.handle, n, nl.cluster_size, int(nl.compress), _ptr(nl.sc_info), _ptr(nl.pool),
+                                _ptr(x), _ptr(y), _ptr(z), _ptr(h), int(bool(compress)), _period_arg(nl.period),
+                                _ptr(ws), ws.numel(), _ptr(row_info), _ptr(pool), pool.numel() * 4, C.byref(used))
+        if rc == _lib.E_CAPACITY and grow:
+            pool = ctx.empty(used.value // 4 + 1024, torch.int32)
+            continue
+        ctx.check(rc)
+        rl = RowList(n, bool(compress), row_info[:n], pool, used.value, nl.period)
+        rl.ws = ws
+        return rl
+
+
+def rows_pass(ctx: Context, rl: RowList, x, y, z, h, m=None, rho=None, nnb=None, want_counts: bool = True):
+    """SPH density (and neighbour counts) from the compressed 1x1 list."""
+    n = rl.n
+    rho = ctx.empty(max(n, 1), torch.float32) if rho is None else rho
+    if want_counts and nnb is None:
+        nnb = ctx.empty(max(n, 1), torch.int32)
+    ctx.check(ctx.lib.rows_pass(ctx.handle, n, int(rl.compress), _ptr(rl.row_info), _ptr(rl.pool), _ptr(x), _ptr(y),
+                                _ptr(z), _ptr(h), _ptr(m), _ptr(rho), _ptr(nnb) if want_counts else None,
+                                _period_arg(rl.period)))
+    return rho[:n], (nnb[:n] if want_counts else None)
+
+
 def nlist_decode(ctx: Context, nl: NeighbourList):
     """Decodes the list on the device: (offsets int64 host, j uint32 numpy, mask uint16 numpy)."""
     import numpy as np

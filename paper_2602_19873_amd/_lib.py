@@ -21,7 +21,7 @@ E_NOCONV = -5
 SYMBOLS = [
     "sfcnl_create", "sfcnl_destroy", "sfcnl_set_stream", "sfcnl_last_error", "sfcnl_sync", "sfcnl_version",
     "sfc_sort_workspace", "sfc_sort", "sfc_gather", "build_clusters", "build_nlist_workspace", "build_nlist",
-    "nlist_pass", "nlist_pass_lj", "nlist_decode", "sfcnl_profile_begin", "sfcnl_profile_end", "sfcnl_h_iterate",
+    "nlist_pass", "nlist_pass_lj", "build_rows_workspace", "build_rows", "rows_pass", "nlist_decode", "sfcnl_profile_begin", "sfcnl_profile_end", "sfcnl_h_iterate",
     "sfcnl_hseed_features", "sfcnl_mlp_init", "sfcnl_mlp_infer", "sfcnl_mlp_grad_workspace", "sfcnl_mlp_grad",
     "sfcnl_mlp_adam", "sfcnl_batch_create", "sfcnl_batch_destroy", "sfcnl_batch_layout", "sfcnl_batch_sort_workspace",
     "sfcnl_batch_sort", "sfcnl_batch_gather", "sfcnl_batch_nlist_workspace", "sfcnl_batch_build_clusters",
@@ -108,6 +108,13 @@ def load():
     lib.nlist_pass_lj.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp, vp, vp, C.POINTER(LjParams), vp, vp, vp, vp,
                                   f3]
     lib.nlist_pass_lj.restype = i32
+    lib.build_rows_workspace.argtypes = [i64, C.POINTER(C.c_size_t)]
+    lib.build_rows_workspace.restype = i32
+    lib.build_rows.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp, vp, i32, f3, vp, C.c_size_t, vp, vp,
+                               C.c_size_t, C.POINTER(C.c_size_t)]
+    lib.build_rows.restype = i32
+    lib.rows_pass.argtypes = [vp, i64, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, f3]
+    lib.rows_pass.restype = i32
     lib.nlist_decode.argtypes = [vp, i64, i32, i32, vp, vp, vp, vp, vp]
     lib.nlist_decode.restype = i32
     lib.sfcnl_h_iterate.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, vp, C.POINTER(NlistOpts), C.POINTER(HiterOpts),

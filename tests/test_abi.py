@@ -71,3 +71,15 @@ def test_null_context_rejected(lib):
     assert L.nlist_pass_lj(None, 10, 8, 1, 0, None, None, None, None, None, None, ctypes.byref(par), None, None,
                            None, None, None) == _lib.E_ARG
     assert L.sfcnl_version().startswith(b"sfcnl")
+
+
+def test_rows_calls_are_checked(lib):
+    from paper_2602_19873_amd import _lib
+    L = _lib.load()
+    b = ctypes.c_size_t()
+    assert L.build_rows_workspace(1000, ctypes.byref(b)) == 0 and b.value >= 8 * 1000
+    assert L.build_rows_workspace(-1, ctypes.byref(b)) == _lib.E_ARG
+    used = ctypes.c_size_t()
+    assert L.build_rows(None, 10, 8, 1, None, None, None, None, None, None, 1, None, None, 0, None, None, 0,
+                        ctypes.byref(used)) == _lib.E_ARG
+    assert L.rows_pass(None, 10, 1, None, None, None, None, None, None, None, None, None, None) == _lib.E_ARG
