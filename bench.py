@@ -379,6 +379,69 @@ def run_lj(args, sf, torch, ctx):
     print(json.dumps(out), flush=True)
 
 
+def run_rows(args, sf, torch, ctx):
+    """The compressed 1x1 list (the paper's future-work combination of the
+    index compression with a full neighbour list) against the cluster lists
+    on the benchmark workload: list sizes, build times and density-pass times
+    of the full and half cluster lists and of the rows (compressed and raw)."""
+    s = make_workload(args.workload)
+    n = s.n
+    dev = torch.device("cuda:0")
+    x, y, z, h = (torch.from_numpy(a).to(dev) for a in (s.x, s.y, s.z, s.h))
+    log("rows: %s n=%d" % (s.name, n))
+    res = {}
+
+    def timed(fn, steps):
+        for _ in range(max(args.warmup, 1)):
+            fn()
+        torch.cuda.synchronize()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(ctx.stream)
+        for _ in range(steps):
+            fn()
+        e1.record(ctx.stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / steps
+
+    cs = args.cluster_size
+    for half in (True, False):
+        pipe = sf.Pipeline(ctx, n, s.box, compress=True, leaf_bucket=args.leaf_bucket, cluster_size=cs, half=half)
+        build = timed(lambda: pipe.step(x, y, z, h, density=False), args.steps)
+        xs, ys, zs, hs = pipe.sorted[:4]
+        nl = pipe.nl
+        ps = timed(lambda: sf.nlist_pass(ctx, nl, xs, ys, zs, hs, rho=pipe.rho, nnb=pipe.nnb), args.steps)
+        key = "cluster_%s" % ("half" if half else "full")
+        res[key] = {"bytes_per_particle": nl.bytes_per_particle(), "build_ms": build, "pass_ms": ps}
+        log("%-14s %.3f B/p  build %.3f ms  pass %.3f ms" % (key, nl.bytes_per_particle(), build, ps))
+        if not half:
+            for comp in (True, False):
+                box = {}
+
+                def mk():
+                    box["rl"] = sf.build_rows(ctx, nl, xs, ys, zs, hs, compress=comp, pool=box.get("pool"),
+                                              ws=box.get("ws"))
+                    box["pool"], box["ws"] = box["rl"].pool, box["rl"].ws
+                rb = timed(mk, args.steps)
+                rl = box["rl"]
+                rp = timed(lambda: sf.rows_pass(ctx, rl, xs, ys, zs, hs, rho=pipe.rho, nnb=pipe.nnb), args.steps)
+                key = "rows_%s" % ("nibble" if comp else "raw")
+                res[key] = {"bytes_per_particle": rl.bytes_per_particle(), "rows_from_cluster_list_ms": rb,
+                            "build_ms": build + rb, "pass_ms": rp}
+                log("%-14s %.3f B/p  rows %.3f ms (+ cluster build)  pass %.3f ms" % (key, rl.bytes_per_particle(),
+                                                                                    rb, rp))
+                del box
+        del pipe, nl
+        torch.cuda.empty_cache()
+    best = res["rows_nibble"]
+    out = {"metric": "compressed 1x1 list: density pass Mparticles/s (and list bytes/particle)",
+           "value": n / (best["pass_ms"] * 1e-3) / 1e6, "unit": "Mparticles/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": best["pass_ms"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": args.workload, "n": n, "cluster_size": cs, "leaf_bucket": args.leaf_bucket},
+           "lists": res}
+    print(json.dumps(out), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -392,7 +455,7 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after warm-up, copy this many MiB once (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--mode", choices=["step", "hiter", "batch", "lj"], default="step")
+    ap.add_argument("--mode", choices=["step", "hiter", "batch", "lj", "rows"], default="step")
     ap.add_argument("--target", type=int, default=0, help="neighbour target (hiter 100, batch 150)")
     ap.add_argument("--nsys", type=int, default=64)
     ap.add_argument("--train-systems", type=int, default=16)
@@ -416,11 +479,13 @@ def main():
     import torch
     import paper_2602_19873_amd as sf
 
-    if args.mode in ("hiter", "batch", "lj"):
+    if args.mode in ("hiter", "batch", "lj", "rows"):
         torch.cuda.set_device(0)
         ctx = sf.Context(0)
         if args.mode == "lj":
             run_lj(args, sf, torch, ctx)
+        elif args.mode == "rows":
+            run_rows(args, sf, torch, ctx)
         elif args.mode == "hiter":
             args.target = args.target or 100
             run_hiter(args, sf, torch, ctx)
