@@ -87,7 +87,7 @@ __device__ __forceinline__ void lj_tile(float xj, float yj, float zj, float qj, 
 }
 
 template <int CS, bool kCompress, bool kQ, bool kE, bool kPbc>
-__global__ __launch_bounds__(256) void k_pass_lj(LjArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_pass_lj(LjArgs a) {
     constexpr int kNsub = kScSize / CS;
     constexpr int kNreg = CS == 8 ? 8 : 4;
     constexpr int kNj = CS == 16 ? 4 : 1;
@@ -217,7 +217,7 @@ __global__ __launch_bounds__(256) void k_pass_lj(LjArgs a) {
 }
 
 template <int CS, bool kCompress, bool kQ, bool kE, bool kPbc>
-__global__ __launch_bounds__(256) void k_pass_lj_half(LjArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_pass_lj_half(LjArgs a) {
     constexpr int kNsub = kScSize / CS;
     constexpr int kNreg = CS == 8 ? 8 : 4;
     constexpr int kNj = CS == 16 ? 4 : 1;
