@@ -376,7 +376,9 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
             for (int64_t cb = c0; cb <= c1; cb += kNsub) {
                 px = nx; py = ny; pz = nz; ph = nh; blo = nlo; bhi = nhi;
                 if (cb + kNsub <= c1) load_batch(cb + kNsub, nx, ny, nz, nh, nlo, nhi);
-                const float ph2 = ph * ph;
+                // counting lists use the i radius only: a zero j radius makes
+                // max(h_i^2, h_j^2) = h_i^2 without a select per tile
+                const float ph2 = gather ? 0.0f : ph * ph;
                 // box tests -> per candidate j-cluster jc its i-cluster mask
                 uint64_t bal[kIbox];
                 uint32_t anyj;
@@ -414,29 +416,46 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                         return half ? (ci < self_c || (ci == self_c && jpos > ipos)) : (ci != self_c || jpos != ipos);
                     };
                     uint32_t mask = 0;
+                    // max(h_i^2, h_j^2) as a compare and select (fmaxf would
+                    // re-canonicalise both operands on every tile)
+                    auto rmax2 = [](float u, float v) { return u > v ? u : v; };
                     if (CS == 8) {
                         const int jl = lane & 7, il = lane >> 3;
                         const int src = jc * CS + jl;
                         const float xj = __shfl(px, src, 64), yj = __shfl(py, src, 64), zj = __shfl(pz, src, 64);
                         const float hj2 = __shfl(ph2, src, 64);
-                        // the tile of the j-cluster with itself: i != j, or j > i for a half list
-                        const bool diag_ok = half ? jl > il : jl != il;
+                        if (self_c < 0) {  // another super-cluster's j-cluster: the plain test
 #pragma unroll
-                        for (int c = 0; c < kNreg; c++) {
-                            if ((cmask >> c) & 1u) {
-                                float dx = xj - ix[c];
-                                float dy = yj - iy[c];
-                                float dz = zj - iz[c];
-                                if (kPbc) wrap(dx, dy, dz);
-                                const float dxx = dx * dx;
-                                const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                                bool pr = d2 < (gather ? ih2[c] : fmaxf(ih2[c], hj2));
-                                if (half) {  // inside the super-cluster: i-clusters up to the j-cluster only
-                                    if (self_c >= 0) pr = pr && keep(c, il, jl);
-                                } else if (c == self_c) {
-                                    pr = pr && diag_ok;
+                            for (int c = 0; c < kNreg; c++) {
+                                if ((cmask >> c) & 1u) {
+                                    float dx = xj - ix[c];
+                                    float dy = yj - iy[c];
+                                    float dz = zj - iz[c];
+                                    if (kPbc) wrap(dx, dy, dz);
+                                    const float dxx = dx * dx;
+                                    const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
+                                    if (sfc_ballot(d2 < rmax2(ih2[c], hj2))) mask |= 1u << c;
                                 }
-                                if (sfc_ballot(pr)) mask |= 1u << c;
+                            }
+                        } else {
+                            // the tile of the j-cluster with itself: i != j, or j > i for a half list
+                            const bool diag_ok = half ? jl > il : jl != il;
+#pragma unroll
+                            for (int c = 0; c < kNreg; c++) {
+                                if ((cmask >> c) & 1u) {
+                                    float dx = xj - ix[c];
+                                    float dy = yj - iy[c];
+                                    float dz = zj - iz[c];
+                                    if (kPbc) wrap(dx, dy, dz);
+                                    const float dxx = dx * dx;
+                                    const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
+                                    bool pr = d2 < rmax2(ih2[c], hj2);
+                                    if (half)  // inside the super-cluster: i-clusters up to the j-cluster only
+                                        pr = pr && keep(c, il, jl);
+                                    else if (c == self_c)
+                                        pr = pr && diag_ok;
+                                    if (sfc_ballot(pr)) mask |= 1u << c;
+                                }
                             }
                         }
                     } else if (CS == 4) {
@@ -453,7 +472,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                                 if (kPbc) wrap(dx, dy, dz);
                                 const float dxx = dx * dx;
                                 const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                                bool pr = d2 < (gather ? ih2[k] : fmaxf(ih2[k], hj2));
+                                bool pr = d2 < rmax2(ih2[k], hj2);
                                 if (self_c >= 0) pr = pr && keep(4 * k + q, il, jl);
                                 const uint64_t b = sfc_ballot(pr);
                                 const uint32_t g = (uint32_t)((b & 0xFFFFull) != 0) |
@@ -486,11 +505,12 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                                     if (kPbc) wrap(dx, dy, dz);
                                     const float dxx = dx * dx;
                                     const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                                    bool p = d2 < (gather ? ih2[c] : fmaxf(ih2[c], hj2[t]));
-                                    if (half) {
-                                        if (self_c >= 0) p = p && (c < self_c || (c == self_c && 4 * t + jq > il));
-                                    } else if (c == self_c) {
-                                        p = p && 4 * t + jq != il;
+                                    bool p = d2 < rmax2(ih2[c], hj2[t]);
+                                    if (self_c >= 0) {
+                                        if (half)
+                                            p = p && (c < self_c || (c == self_c && 4 * t + jq > il));
+                                        else if (c == self_c)
+                                            p = p && 4 * t + jq != il;
                                     }
                                     pr = pr || p;
                                 }
