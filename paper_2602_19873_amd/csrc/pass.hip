@@ -31,8 +31,24 @@ struct PassArgs {
     uint32_t gate_max;
 };
 
-// One particle pair of a tile: the own-radius test, then m_j times the
-// halved M4 shape 1/2 - 3q^2 + 3q^3 (q < 1/2) or (1-q)^3, summed.
+// Halved M4 shape written as two clamped cubes: with t = sat(1 - q) and
+// u = sat(1/2 - q) (sat clamps to [0, 1]), t^3 - 4 u^3 equals 1/2 - 3q^2 + 3q^3
+// below q = 1/2, (1-q)^3 up to q = 1 and zero beyond, so a pair outside the
+// radius adds exactly nothing and the sum needs no select. Adds m f(q)/2 to
+// acc for q = r hinv.
+template <bool kMass>
+__device__ __forceinline__ float add_shape(float acc, float m, float r, float hinv) {
+    const float t = __builtin_amdgcn_fmed3f(__builtin_fmaf(-r, hinv, 1.0f), 0.0f, 1.0f);
+    const float u = __builtin_amdgcn_fmed3f(__builtin_fmaf(-r, hinv, 0.5f), 0.0f, 1.0f);
+    const float t2 = t * t;
+    const float u2m = -4.0f * (u * u);
+    if (!kMass) return __builtin_fmaf(u2m, u, __builtin_fmaf(t2, t, acc));
+    return __builtin_fmaf(m, __builtin_fmaf(u2m, u, t2 * t), acc);
+}
+
+// One particle pair of a tile: the own-radius test (the self pair excluded)
+// counts and adds m_j f(q)/2. Folding the self pair into the test measured
+// faster here than masking it off around the call.
 template <bool kMass, bool kPbc>
 __device__ __forceinline__ void tile_pair(float xj, float yj, float zj, float mj, float xi, float yi, float zi,
                                           float h2, float hinv, bool self_pair, float &acc, int &cnt,
@@ -45,13 +61,7 @@ __device__ __forceinline__ void tile_pair(float xj, float yj, float zj, float mj
     const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
     const bool in = d2 < h2 && !self_pair;
     if (sfc_ballot(in)) {
-        const float q = __builtin_amdgcn_sqrtf(d2) * hinv;
-        const float t1 = q - 1.0f;
-        const float q2 = q * q;
-        const float inner = __builtin_fmaf(3.0f * q2, t1, 0.5f);
-        const float outer = -(t1 * t1) * t1;
-        const float wq = q < 0.5f ? inner : outer;
-        const float nacc = __builtin_fmaf(kMass ? mj : 1.0f, wq, acc);
+        const float nacc = add_shape<kMass>(acc, mj, __builtin_amdgcn_sqrtf(d2), hinv);
         acc = in ? nacc : acc;
         cnt += in ? 1 : 0;
     }
@@ -162,14 +172,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
                 for (int c = 0; c < kNreg; c++)
                     if ((mk >> c) & 1u)
                         tile_pair<kMass, kPbc>(cx[0], cy[0], cz[0], cm[0], ix[c], iy[c], iz[c], ih2[c], ihinv[c],
-                                         c == self_c && il == jl, acc[c], cnt_nb[c], a.per);
+                                               c == self_c && il == jl, acc[c], cnt_nb[c], a.per);
             } else if (CS == 4) {
                 const int il = (lane >> 2) & 3, q = lane >> 4;
 #pragma unroll
                 for (int k = 0; k < kNreg; k++)
                     if ((mk >> (4 * k)) & 0xFu)
                         tile_pair<kMass, kPbc>(cx[0], cy[0], cz[0], cm[0], ix[k], iy[k], iz[k], ih2[k], ihinv[k],
-                                         4 * k + q == self_c && il == jl, acc[k], cnt_nb[k], a.per);
+                                               4 * k + q == self_c && il == jl, acc[k], cnt_nb[k], a.per);
             } else {
                 const int il = lane >> 2;
 #pragma unroll
@@ -177,8 +187,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
                     if ((mk >> c) & 1u) {
 #pragma unroll
                         for (int t = 0; t < 4; t++)
-                            tile_pair<kMass, kPbc>(cx[t], cy[t], cz[t], cm[t], ix[c], iy[c], iz[c], ih2[c], ihinv[c],
-                                             c == self_c && il == 4 * t + jl, acc[c], cnt_nb[c], a.per);
+                                tile_pair<kMass, kPbc>(cx[t], cy[t], cz[t], cm[t], ix[c], iy[c], iz[c], ih2[c],
+                                                       ihinv[c], c == self_c && il == 4 * t + jl, acc[c], cnt_nb[c], a.per);
                     }
             }
         }
@@ -222,38 +232,24 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 // rho, vary from run to run; the counts are exact.
 // ---------------------------------------------------------------------------
 
-__device__ __forceinline__ float half_shape(float q) {
-    // M4 spline shape halved: 1/2 - 3q^2 + 3q^3 below q = 1/2, (1-q)^3 above
-    const float t1 = q - 1.0f;
-    const float q2 = q * q;
-    const float inner = __builtin_fmaf(3.0f * q2, t1, 0.5f);
-    const float outer = -(t1 * t1) * t1;
-    return q < 0.5f ? inner : outer;
-}
-
-template <int CS, bool kPbc>
+// One stored pair feeding both particles: own-radius counts on either side
+// and the two shape sums (zero outside each radius). The caller masks pairs
+// that the half list does not hold off.
+template <bool kMass, bool kPbc>
 __device__ __forceinline__ void half_pair(float xj, float yj, float zj, float mj, float hj2, float hjinv, float xi,
-                                          float yi, float zi, float mi, float hi2, float hiinv, bool keep,
-                                          float &acc_i, int &cnt_i, float &acc_j, int &cnt_j, const Period &per) {
+                                          float yi, float zi, float mi, float hi2, float hiinv, float &acc_i,
+                                          int &cnt_i, float &acc_j, int &cnt_j, const Period &per) {
     float dx = xj - xi;
     float dy = yj - yi;
     float dz = zj - zi;
     if (kPbc) wave_min_image(dx, dy, dz, per);  // minimum images on periodic axes
     const float dxx = dx * dx;
     const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-    const bool ini = keep && d2 < hi2;
-    const bool inj = keep && d2 < hj2;
-    if (sfc_ballot(ini || inj)) {
-        const float r = __builtin_amdgcn_sqrtf(d2);
-        const float wi = half_shape(r * hiinv);
-        const float wj = half_shape(r * hjinv);
-        const float ni = __builtin_fmaf(mj, wi, acc_i);
-        const float nj = __builtin_fmaf(mi, wj, acc_j);
-        acc_i = ini ? ni : acc_i;
-        cnt_i += ini ? 1 : 0;
-        acc_j = inj ? nj : acc_j;
-        cnt_j += inj ? 1 : 0;
-    }
+    cnt_i += d2 < hi2 ? 1 : 0;
+    cnt_j += d2 < hj2 ? 1 : 0;
+    const float r = __builtin_amdgcn_sqrtf(d2);
+    acc_i = add_shape<kMass>(acc_i, mj, r, hiinv);
+    acc_j = add_shape<kMass>(acc_j, mi, r, hjinv);
 }
 
 template <int CS, bool kCompress, bool kMass, bool kCount, bool kPbc>
@@ -342,7 +338,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
                 mj[t] = nm[t];
                 const bool vj = nh[t] > 0.0f;  // absent: -1 (NaN padding never pairs)
                 hj2[t] = vj ? nh[t] * nh[t] : -1.0f;
-                hjinv[t] = vj ? 1.0f / nh[t] : 1.0f;
+                hjinv[t] = vj ? __builtin_amdgcn_rcpf(nh[t]) : 1.0f;
                 accj[t] = 0.0f;
                 cntj[t] = 0;
             }
@@ -356,17 +352,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
                 const int il = lane & 7;
 #pragma unroll
                 for (int c = 0; c < kNreg; c++)
-                    if ((mk >> c) & 1u)
-                        half_pair<CS, kPbc>(xj[0], yj[0], zj[0], mj[0], hj2[0], hjinv[0], ix[c], iy[c], iz[c], im[c],
-                                      ih2[c], ihinv[c], keep(c, il, jq), acc[c], cnt_nb[c], accj[0], cntj[0], a.per);
+                    if (((mk >> c) & 1u) && keep(c, il, jq))
+                        half_pair<kMass, kPbc>(xj[0], yj[0], zj[0], mj[0], hj2[0], hjinv[0], ix[c], iy[c], iz[c],
+                                               im[c], ih2[c], ihinv[c], acc[c], cnt_nb[c], accj[0], cntj[0], a.per);
             } else if (CS == 4) {
                 const int il = lane & 3, q = (lane >> 2) & 3;
 #pragma unroll
                 for (int k = 0; k < kNreg; k++)
-                    if ((mk >> (4 * k)) & 0xFu)
-                        half_pair<CS, kPbc>(xj[0], yj[0], zj[0], mj[0], hj2[0], hjinv[0], ix[k], iy[k], iz[k], im[k],
-                                      ih2[k], ihinv[k], keep(4 * k + q, il, jq), acc[k], cnt_nb[k], accj[0],
-                                      cntj[0], a.per);
+                    if (((mk >> (4 * k)) & 0xFu) && keep(4 * k + q, il, jq))
+                        half_pair<kMass, kPbc>(xj[0], yj[0], zj[0], mj[0], hj2[0], hjinv[0], ix[k], iy[k], iz[k],
+                                               im[k], ih2[k], ihinv[k], acc[k], cnt_nb[k], accj[0], cntj[0], a.per);
             } else {
                 const int il = lane & 15;
 #pragma unroll
@@ -374,9 +369,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
                     if ((mk >> c) & 1u) {
 #pragma unroll
                         for (int t = 0; t < 4; t++)
-                            half_pair<CS, kPbc>(xj[t], yj[t], zj[t], mj[t], hj2[t], hjinv[t], ix[c], iy[c], iz[c], im[c],
-                                          ih2[c], ihinv[c], keep(c, il, 4 * t + jq), acc[c], cnt_nb[c], accj[t],
-                                          cntj[t], a.per);
+                            if (keep(c, il, 4 * t + jq))
+                                half_pair<kMass, kPbc>(xj[t], yj[t], zj[t], mj[t], hj2[t], hjinv[t], ix[c], iy[c],
+                                                       iz[c], im[c], ih2[c], ihinv[c], acc[c], cnt_nb[c], accj[t],
+                                                       cntj[t], a.per);
                     }
             }
             // j side: sum over the i lanes of each j-particle (one DPP row
