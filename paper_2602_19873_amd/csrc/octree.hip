@@ -65,25 +65,42 @@ __global__ __launch_bounds__(256) void k_digits(const uint64_t *__restrict__ key
     lam[p] = (int8_t)(p + bucket < hi ? sfc_common_digits(k, keys[p + bucket]) : -1);
 }
 
+// Leaf level of particle p: one more than the largest lam over the bucket + 1
+// windows [p - bucket, p]. The maximum over that sliding window comes from a
+// doubling table in LDS: after the step of width d, entry k holds the largest
+// of the d values from k on, and two overlapping runs of the largest width
+// d <= bucket + 1 cover the window.
 __global__ __launch_bounds__(256) void k_leaf_level(const int8_t *__restrict__ cdig, const int8_t *__restrict__ lam,
                                                     int64_t n, int bucket, int8_t *__restrict__ lleaf,
                                                     uint32_t *__restrict__ cnt) {
-    __shared__ int8_t s_lam[256 + kMaxBucket];
+    constexpr int kSpan = 256 + kMaxBucket;
+    __shared__ int8_t s_tab[2][kSpan];
+    const int len = 256 + bucket;
     const int64_t b0 = (int64_t)blockIdx.x * 256;
-    for (int k = threadIdx.x; k < 256 + bucket; k += 256) {
-        int64_t a = b0 - bucket + k;
-        s_lam[k] = (a >= 0 && a < n) ? lam[a] : (int8_t)-1;
+    for (int k = threadIdx.x; k < len; k += 256) {
+        const int64_t a = b0 - bucket + k;
+        s_tab[0][k] = (a >= 0 && a < n) ? lam[a] : (int8_t)-1;
     }
     __syncthreads();
-    int64_t p = b0 + threadIdx.x;
-    if (p >= n) return;
-    int m = -1;
-    for (int k = 0; k <= bucket; k++) {
-        int v = s_lam[threadIdx.x + k];  // window start a = p - bucket + k
-        m = v > m ? v : m;
+    const int win = bucket + 1;
+    int d = 1, cur = 0;
+    while (2 * d <= win) {
+        // entries k with k + 2d <= len are exact; the rest are never read
+        for (int k = threadIdx.x; k < len; k += 256) {
+            const int u = s_tab[cur][k];
+            const int v = k + d < len ? s_tab[cur][k + d] : -1;
+            s_tab[cur ^ 1][k] = (int8_t)(u > v ? u : v);
+        }
+        __syncthreads();
+        cur ^= 1;
+        d *= 2;
     }
-    int L = m + 1 < kMaxLevel ? m + 1 : kMaxLevel;
-    int c = cdig[p];
+    const int64_t p = b0 + threadIdx.x;
+    if (p >= n) return;
+    const int u = s_tab[cur][threadIdx.x], v = s_tab[cur][threadIdx.x + win - d];
+    const int m = u > v ? u : v;
+    const int L = m + 1 < kMaxLevel ? m + 1 : kMaxLevel;
+    const int c = cdig[p];
     lleaf[p] = (int8_t)L;
     cnt[p] = c < L ? (uint32_t)(L - c) : 0u;
 }
