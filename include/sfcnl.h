@@ -4,7 +4,8 @@
  * C ABI of the GPU library. The operations follow "GPU-Native Compressed
  * Neighbor Lists with a Space-Filling-Curve Data Layout":
  *   sfc_sort        Hilbert keys and SFC order of the particles (Sec. II-A)
- *   sfc_gather      particle fields into SFC order (Sec. II-A, II-C)
+ *   sfc_gather      particle fields into SFC order (Sec. II-A, II-C); the
+ *                   sfc_gather_ws form stages them through a workspace
  *   build_clusters  fixed-size clusters of SFC-consecutive particles and their
  *                   bounding boxes (Sec. II-A)
  *   build_nlist     octree traversal, cluster-pair list with per-i-cluster
@@ -87,6 +88,16 @@ int sfc_sort(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y, const
  * h_in / h_out are host arrays of device pointers; out must not alias in. */
 int sfc_gather(sfcnl_ctx ctx, int64_t n, const uint32_t *d_perm, int nfields, const float *const *h_in,
                float *const *h_out);
+
+/* The same gather staged through a workspace: up to four fields at a time are
+ * first packed into 16-byte records in input order (one coalesced pass), so
+ * that every particle's fields arrive with one random read instead of one per
+ * field. Results are identical to sfc_gather, bit for bit.
+ *   d_ws / ws_bytes: at least sfc_gather_workspace(n) bytes (16 n + 256), any
+ *   alignment; reused from one call to the next. */
+int sfc_gather_workspace(int64_t n, size_t *ws_bytes);
+int sfc_gather_ws(sfcnl_ctx ctx, int64_t n, const uint32_t *d_perm, int nfields, const float *const *h_in,
+                  float *const *h_out, void *d_ws, size_t ws_bytes);
 
 /* ---- 2. Clusters (Sec. II-A) ---------------------------------------------
  * Cluster c holds SFC-ordered particles [cs*c, min(cs*c + cs, n)). For each

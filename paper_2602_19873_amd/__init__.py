@@ -19,7 +19,7 @@ import torch
 
 from . import _lib
 
-__all__ = ["Context", "NeighbourList", "SfcnlError", "sfc_sort", "sfc_gather", "build_clusters",
+__all__ = ["Context", "NeighbourList", "SfcnlError", "sfc_sort", "sfc_gather", "sfc_gather_workspace", "build_clusters",
            "build_nlist", "nlist_pass", "nlist_decode", "h_iterate", "HIterResult", "Pipeline", "SC_SIZE",
            "CLUSTER_SIZE", "hseed_features", "mlp_init", "mlp_infer", "mlp_grad", "mlp_adam", "mlp_train",
            "MLP_NPARAM", "Batch", "batch_create", "batch_sort", "batch_gather", "batch_build_clusters",
@@ -114,7 +114,18 @@ def sfc_sort(ctx: Context, x, y, z, box, keys=None, perm=None, ws=None):
     return keys, perm
 
 
-def sfc_gather(ctx: Context, perm, fields, outs=None):
+def sfc_gather_workspace(n: int) -> int:
+    """Bytes of workspace sfc_gather needs to stage its reads (16 n + 256)."""
+    b = C.c_size_t()
+    if _lib.load().sfc_gather_workspace(int(n), C.byref(b)) != 0:
+        raise SfcnlError(_lib.E_ARG, "sfc_gather_workspace")
+    return b.value
+
+
+def sfc_gather(ctx: Context, perm, fields, outs=None, ws=None):
+    """out[f][k] = fields[f][perm[k]]. With ws (a uint8 tensor of at least
+    sfc_gather_workspace(n) bytes) the fields are staged four at a time into
+    16-byte records, one random read per particle (sfc_gather_ws)."""
     n = perm.numel()
     nf = len(fields)
     outs = [torch.empty_like(f) for f in fields] if outs is None else outs
@@ -122,7 +133,10 @@ def sfc_gather(ctx: Context, perm, fields, outs=None):
         _check_f32(f, n, "field")
     ins = (C.c_void_p * nf)(*[f.data_ptr() for f in fields])
     ous = (C.c_void_p * nf)(*[o.data_ptr() for o in outs])
-    ctx.check(ctx.lib.sfc_gather(ctx.handle, n, _ptr(perm), nf, ins, ous))
+    if ws is None:
+        ctx.check(ctx.lib.sfc_gather(ctx.handle, n, _ptr(perm), nf, ins, ous))
+    else:
+        ctx.check(ctx.lib.sfc_gather_ws(ctx.handle, n, _ptr(perm), nf, ins, ous, _ptr(ws), ws.numel()))
     return outs
 
 
@@ -526,6 +540,7 @@ class Pipeline:
         e = ctx.empty
         self.keys, self.perm = e(max(n, 1), torch.int64), e(max(n, 1), torch.int32)
         self.sort_ws = e(max(sfc_sort_workspace(n), 1), torch.uint8)
+        self.gather_ws = e(max(sfc_gather_workspace(n), 1), torch.uint8)
         nf = 5 if with_mass else 4
         self.sorted = [e(max(n, 1), torch.float32) for _ in range(nf)]
         self.bbox = e((max(nc, 1), 8), torch.float32)
@@ -541,7 +556,7 @@ class Pipeline:
         sfc_sort(ctx, x, y, z, self.box, self.keys, self.perm, self.sort_ws)
         fields = [x, y, z, h] + ([m] if m is not None else [])
         outs = self.sorted[:len(fields)]
-        sfc_gather(ctx, self.perm, fields, outs)
+        sfc_gather(ctx, self.perm, fields, outs, ws=self.gather_ws)
         xs, ys, zs, hs = outs[:4]
         ms = outs[4] if m is not None else None
         build_clusters(ctx, xs, ys, zs, hs, self.cluster_size, self.bbox)

@@ -20,7 +20,7 @@ E_NOCONV = -5
 
 SYMBOLS = [
     "sfcnl_create", "sfcnl_destroy", "sfcnl_set_stream", "sfcnl_last_error", "sfcnl_sync", "sfcnl_version",
-    "sfc_sort_workspace", "sfc_sort", "sfc_gather", "build_clusters", "build_nlist_workspace", "build_nlist",
+    "sfc_sort_workspace", "sfc_sort", "sfc_gather", "sfc_gather_workspace", "sfc_gather_ws", "build_clusters", "build_nlist_workspace", "build_nlist",
     "nlist_pass", "nlist_pass_lj", "build_rows_workspace", "build_rows", "rows_pass", "nlist_decode", "sfcnl_profile_begin", "sfcnl_profile_end", "sfcnl_h_iterate",
     "sfcnl_hseed_features", "sfcnl_mlp_init", "sfcnl_mlp_infer", "sfcnl_mlp_grad_workspace", "sfcnl_mlp_grad",
     "sfcnl_mlp_adam", "sfcnl_batch_create", "sfcnl_batch_destroy", "sfcnl_batch_layout", "sfcnl_batch_sort_workspace",
@@ -95,6 +95,10 @@ def load():
     lib.sfc_sort.restype = i32
     lib.sfc_gather.argtypes = [vp, i64, vp, i32, C.POINTER(vp), C.POINTER(vp)]
     lib.sfc_gather.restype = i32
+    lib.sfc_gather_workspace.argtypes = [i64, C.POINTER(sz)]
+    lib.sfc_gather_workspace.restype = i32
+    lib.sfc_gather_ws.argtypes = [vp, i64, vp, i32, C.POINTER(vp), C.POINTER(vp), vp, sz]
+    lib.sfc_gather_ws.restype = i32
     lib.build_clusters.argtypes = [vp, i64, vp, vp, vp, vp, i32, vp]
     lib.build_clusters.restype = i32
     lib.build_nlist_workspace.argtypes = [i64, C.POINTER(NlistOpts), C.POINTER(sz)]

@@ -296,6 +296,42 @@ __global__ __launch_bounds__(256) void k_gather(int64_t n_out, int64_t n_in, con
         if (f < a.nf) a.out[f][i] = a.in[f][p];
 }
 
+// Staged gather: up to four fields packed into 16-byte records in input order
+// (coalesced), then one random 16-byte read per particle instead of one per
+// field.
+struct Pack4 {
+    const float *in[4];
+    float *out[4];
+    int nf;
+};
+
+__global__ __launch_bounds__(256) void k_pack4(int64_t n, Pack4 a, float4 *__restrict__ rec) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    float4 r;
+    r.x = a.in[0][i];
+    r.y = a.nf > 1 ? a.in[1][i] : 0.0f;
+    r.z = a.nf > 2 ? a.in[2][i] : 0.0f;
+    r.w = a.nf > 3 ? a.in[3][i] : 0.0f;
+    rec[i] = r;
+}
+
+__global__ __launch_bounds__(256) void k_gather4(int64_t n, const uint32_t *__restrict__ perm,
+                                                 const float4 *__restrict__ rec, Pack4 a, uint32_t *status) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    uint32_t p = perm[i];
+    if (p >= (uint64_t)n) {  // not a permutation of [0, n): report, never read outside
+        atomicOr(&status[kStInputErr], 4u);
+        p = 0;
+    }
+    const float4 r = rec[p];
+    a.out[0][i] = r.x;
+    if (a.nf > 1) a.out[1][i] = r.y;
+    if (a.nf > 2) a.out[2][i] = r.z;
+    if (a.nf > 3) a.out[3][i] = r.w;
+}
+
 // Keys of batched systems: particle i of the concatenated input uses its own
 // system's box.
 __global__ __launch_bounds__(256) void k_batch_keys(int64_t n, const float *__restrict__ x,
@@ -440,6 +476,57 @@ extern "C" int sfc_gather(sfcnl_ctx ctx, int64_t n, const uint32_t *d_perm, int 
     prof_mark(ctx, kStageGather, false);
     k_gather<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(n, n, d_perm, a, false, ctx->d_status);
     SFCNL_LAUNCHED(ctx);
+    prof_mark(ctx, kStageGather, true);
+    return SFCNL_OK;
+}
+
+extern "C" int sfc_gather_workspace(int64_t n, size_t *ws_bytes) {
+    if (n < 0 || !ws_bytes) return SFCNL_E_ARG;
+    *ws_bytes = align_up((size_t)n * sizeof(float4), 256) + 256;
+    return SFCNL_OK;
+}
+
+extern "C" int sfc_gather_ws(sfcnl_ctx ctx, int64_t n, const uint32_t *d_perm, int nfields, const float *const *h_in,
+                             float *const *h_out, void *d_ws, size_t ws_bytes) {
+    if (!ctx) return SFCNL_E_ARG;
+    if (n < 0 || n >= (int64_t(1) << 31) || nfields < 1 || nfields > 8 || !h_in || !h_out)
+        return set_err(ctx, SFCNL_E_ARG, "sfc_gather_ws: bad arguments");
+    if (n == 0) return SFCNL_OK;
+    if (!d_perm || !d_ws) return set_err(ctx, SFCNL_E_ARG, "sfc_gather_ws: null perm or workspace");
+    size_t need;
+    sfc_gather_workspace(n, &need);
+    if (ws_bytes < need)
+        return set_err(ctx, SFCNL_E_ARG, "sfc_gather_ws: workspace %zu bytes < %zu needed", ws_bytes, need);
+    for (int f = 0; f < nfields; f++)
+        if (!h_in[f] || !h_out[f]) return set_err(ctx, SFCNL_E_ARG, "sfc_gather_ws: null field %d", f);
+    // records start at the first 256-byte boundary of the workspace (the
+    // size includes that slack)
+    float4 *rec = reinterpret_cast<float4 *>(align_up(reinterpret_cast<uintptr_t>(d_ws), 256));
+    hipStream_t st = ctx->stream;
+    const unsigned g = blocks_for(n, 256);
+    prof_mark(ctx, kStageGather, false);
+    for (int f0 = 0; f0 < nfields; f0 += 4) {
+        const int nf = nfields - f0 < 4 ? nfields - f0 : 4;
+        if (nf == 1) {  // a single field gains nothing from staging
+            GatherArgs a{};
+            a.nf = 1;
+            a.in[0] = h_in[f0];
+            a.out[0] = h_out[f0];
+            k_gather<<<g, 256, 0, st>>>(n, n, d_perm, a, false, ctx->d_status);
+            SFCNL_LAUNCHED(ctx);
+            continue;
+        }
+        Pack4 a{};
+        a.nf = nf;
+        for (int f = 0; f < nf; f++) {
+            a.in[f] = h_in[f0 + f];
+            a.out[f] = h_out[f0 + f];
+        }
+        k_pack4<<<g, 256, 0, st>>>(n, a, rec);
+        SFCNL_LAUNCHED(ctx);
+        k_gather4<<<g, 256, 0, st>>>(n, d_perm, rec, a, ctx->d_status);
+        SFCNL_LAUNCHED(ctx);
+    }
     prof_mark(ctx, kStageGather, true);
     return SFCNL_OK;
 }
