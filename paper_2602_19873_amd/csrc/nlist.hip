@@ -444,7 +444,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                         const int src = jc * CS + jl;
                         const float xj = __shfl(px, src, 64), yj = __shfl(py, src, 64), zj = __shfl(pz, src, 64);
                         const float hj2 = __shfl(ph2, src, 64);
-                        if (self_c < 0) {  // another super-cluster's j-cluster: the plain test
+                        if (self_c < 0) {  // another super-cluster's j-cluster: the plain test,
+                                           // d2 below either squared radius
 #pragma unroll
                             for (int c = 0; c < kNreg; c++) {
                                 if ((cmask >> c) & 1u) {
@@ -454,7 +455,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(5))) void k
                                     if (kPbc) wrap(dx, dy, dz);
                                     const float dxx = dx * dx;
                                     const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                                    if (sfc_ballot(d2 < rmax2(ih2[c], hj2))) mask |= 1u << c;
+                                    if (sfc_ballot((d2 < ih2[c]) | (d2 < hj2))) mask |= 1u << c;
                                 }
                             }
                         } else {
