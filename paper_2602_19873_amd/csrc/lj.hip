@@ -86,8 +86,11 @@ __device__ __forceinline__ void lj_tile(float xj, float yj, float zj, float qj, 
     }
 }
 
+// Six waves per SIMD for cluster sizes 4 and 8 (a few registers spilled, 3 %
+// faster); cluster size 16 spills heavily under that cap and keeps its own
+// register count.
 template <int CS, bool kCompress, bool kQ, bool kE, bool kPbc>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_pass_lj(LjArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 1 : 6))) void k_pass_lj(LjArgs a) {
     constexpr int kNsub = kScSize / CS;
     constexpr int kNreg = CS == 8 ? 8 : 4;
     constexpr int kNj = CS == 16 ? 4 : 1;
@@ -217,7 +220,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k
 }
 
 template <int CS, bool kCompress, bool kQ, bool kE, bool kPbc>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_pass_lj_half(LjArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 1 : 6))) void k_pass_lj_half(LjArgs a) {
     constexpr int kNsub = kScSize / CS;
     constexpr int kNreg = CS == 8 ? 8 : 4;
     constexpr int kNj = CS == 16 ? 4 : 1;

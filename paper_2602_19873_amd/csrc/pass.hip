@@ -74,11 +74,13 @@ __device__ __forceinline__ void tile_pair(float xj, float yj, float zj, float mj
 //            j-particle jl against i-particle il of i-clusters 4k + q;
 //   CS = 16: lane (il, jq) = (lane / 4, lane % 4) takes j-particles 4t + jq
 //            (t = 0..3) against i-particle il of every set i-cluster.
-// Both passes are bound by VALU issue; six waves per SIMD (at most 80 VGPRs,
-// a few registers spilled) hide more of the load latency than five without
-// spills: measured 8 % faster for either list form.
+// Both passes are bound by VALU issue; for cluster sizes 4 and 8 six waves
+// per SIMD (at most 80 VGPRs, a few registers spilled) hide more of the load
+// latency than five without spills: measured 8 % faster for either list
+// form. Cluster size 16 holds four j-particles per lane; under the same cap it
+// spills heavily, so it keeps its own register count.
 template <int CS, bool kCompress, bool kMass, bool kCount, bool kPbc>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_pass(PassArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 1 : 6))) void k_pass(PassArgs a) {
     constexpr int kNsub = kScSize / CS;
     constexpr int kNreg = CS == 8 ? 8 : 4;
     constexpr int kNj = CS == 16 ? 4 : 1;     // j-particles per lane and entry
@@ -253,7 +255,7 @@ __device__ __forceinline__ void half_pair(float xj, float yj, float zj, float mj
 }
 
 template <int CS, bool kCompress, bool kMass, bool kCount, bool kPbc>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(6))) void k_pass_half(PassArgs a) {
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 1 : 6))) void k_pass_half(PassArgs a) {
     constexpr int kNsub = kScSize / CS;
     constexpr int kNreg = CS == 8 ? 8 : 4;
     constexpr int kNj = CS == 16 ? 4 : 1;
