@@ -22,7 +22,8 @@
  *     caller owns every buffer; the library only borrows them for the call.
  *   - Work is enqueued on the context's HIP stream. Calls return as soon as
  *     the work is enqueued, except build_nlist, which waits for its own
- *     kernels to read back list size and error flags.
+ *     kernels to read back list size and error flags (build_nlist_async and
+ *     build_nlist_result split that wait off).
  *   - Every call returns an sfcnl status (0 on success, negative on failure)
  *     and never throws. sfcnl_last_error() gives a text for the last failure
  *     on that context.
@@ -173,6 +174,21 @@ int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d
                 const float *d_z, const float *d_h, const float *d_bbox, const sfcnl_nlist_opts *opts,
                 void *d_ws, size_t ws_bytes, uint32_t *d_sc_info, uint32_t *d_pool, size_t pool_bytes,
                 size_t *h_used_bytes, int64_t *h_max_nj);
+
+/* The same build without the wait: build_nlist_async returns once the work
+ * is enqueued, so that a pass (or the next step's work) can be enqueued behind
+ * it at once, and build_nlist_result waits until the build's status has
+ * reached the host (not for work enqueued after the build) and returns what
+ * build_nlist would have returned, with the same *h_used_bytes and *h_max_nj.
+ * One build may be pending per context; build_nlist_result without one is
+ * SFCNL_E_ARG. A list that does not fit is recorded as empty in sc_info, so a
+ * pass enqueued before the result stays inside the pool; on SFCNL_E_CAPACITY
+ * the build (and such a pass) must be redone with the sizes reported. The
+ * buffers must stay untouched until the result call. */
+int build_nlist_async(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_x, const float *d_y,
+                      const float *d_z, const float *d_h, const float *d_bbox, const sfcnl_nlist_opts *opts,
+                      void *d_ws, size_t ws_bytes, uint32_t *d_sc_info, uint32_t *d_pool, size_t pool_bytes);
+int build_nlist_result(sfcnl_ctx ctx, size_t *h_used_bytes, int64_t *h_max_nj);
 
 /* ---- 4. Neighbour pass (Sec. II-A, Sec. II-D Listing 1) ------------------
  * Decompresses each super-cluster's list and evaluates every cs x cs particle

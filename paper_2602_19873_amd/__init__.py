@@ -162,6 +162,7 @@ class NeighbourList:
     max_nj: int
     half: bool = False        # only pairs with j > i (each pair once)
     period: tuple = (0.0, 0.0, 0.0)  # periodic axes (0 = open), as built
+    pending: bool = False     # built by build_nlist_async: sizes unknown until build_nlist_finish
 
     @property
     def n_sc(self) -> int:
@@ -235,6 +236,41 @@ def build_nlist(ctx: Context, keys, x, y, z, h, bbox, compress: bool = True, lea
         nl.ws = ws
         nl.max_j_per_sc = max_j_per_sc
         return nl
+
+
+def build_nlist_async(ctx: Context, keys, x, y, z, h, bbox, pool, ws, sc_info, compress: bool = True,
+                      leaf_bucket: int = 128, max_j_per_sc: int = 512, cluster_size: int = CLUSTER_SIZE,
+                      half: bool = False, period=None):
+    """Enqueues the list build without waiting (build_nlist_async). The list
+    can be passed at once; build_nlist_finish then reports its sizes and
+    errors. Buffers are the caller's (no growth here)."""
+    n = x.numel()
+    nsc = (n + SC_SIZE - 1) // SC_SIZE
+    o = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc, half, period)
+    ctx.check(ctx.lib.build_nlist_async(ctx.handle, n, _ptr(keys), _ptr(x), _ptr(y), _ptr(z), _ptr(h), _ptr(bbox),
+                                        C.byref(o), _ptr(ws), ws.numel(), _ptr(sc_info), _ptr(pool),
+                                        pool.numel() * 4))
+    nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, -1, -1, bool(half), _period(period),
+                       pending=True)
+    nl.ws = ws
+    nl.max_j_per_sc = max_j_per_sc
+    return nl
+
+
+def build_nlist_finish(ctx: Context, nl: NeighbourList) -> bool:
+    """Waits for the pending build's status (build_nlist_result) and fills in
+    its sizes. True when the list is complete; False when the pool or the
+    staging list was too small (nl.used_bytes / nl.max_nj then give the sizes
+    needed, and the build and any pass over it must be redone); raises on
+    every other error."""
+    used = C.c_size_t()
+    maxnj = C.c_int64()
+    rc = ctx.lib.build_nlist_result(ctx.handle, C.byref(used), C.byref(maxnj))
+    nl.used_bytes, nl.max_nj, nl.pending = used.value, maxnj.value, False
+    if rc == _lib.E_CAPACITY:
+        return False
+    ctx.check(rc)
+    return True
 
 
 def nlist_pass(ctx: Context, nl: NeighbourList, x, y, z, h, m=None, rho=None, nnb=None, want_counts=True):
@@ -551,7 +587,10 @@ class Pipeline:
         self.nl = None
 
     def step(self, x, y, z, h, m=None, want_counts=True, density=True):
-        """One pass of the path; density=False stops after the list build."""
+        """One pass of the path; density=False stops after the list build.
+        Once a build has fixed the buffer sizes, later steps enqueue the pass
+        right behind the build and check the build's status afterwards
+        (build_nlist_async), redoing both if the list outgrew its buffers."""
         ctx, n = self.ctx, self.n
         sfc_sort(ctx, x, y, z, self.box, self.keys, self.perm, self.sort_ws)
         fields = [x, y, z, h] + ([m] if m is not None else [])
@@ -560,6 +599,14 @@ class Pipeline:
         xs, ys, zs, hs = outs[:4]
         ms = outs[4] if m is not None else None
         build_clusters(ctx, xs, ys, zs, hs, self.cluster_size, self.bbox)
+        if self.nl is not None and density:
+            nl = build_nlist_async(ctx, self.keys, xs, ys, zs, hs, self.bbox, self.pool, self.ws, self.sc_info,
+                                   self.compress, self.leaf_bucket, self.max_j_per_sc, self.cluster_size,
+                                   self.half, self.period)
+            nlist_pass(ctx, nl, xs, ys, zs, hs, ms, self.rho, self.nnb if want_counts else None, want_counts)
+            if build_nlist_finish(ctx, nl):
+                self.nl = nl
+                return nl
         nl = build_nlist(ctx, self.keys, xs, ys, zs, hs, self.bbox, self.compress, self.leaf_bucket,
                          self.max_j_per_sc, self.cluster_size, pool=self.pool, ws=self.ws, sc_info=self.sc_info,
                          half=self.half, period=self.period)

@@ -20,7 +20,8 @@ E_NOCONV = -5
 
 SYMBOLS = [
     "sfcnl_create", "sfcnl_destroy", "sfcnl_set_stream", "sfcnl_last_error", "sfcnl_sync", "sfcnl_version",
-    "sfc_sort_workspace", "sfc_sort", "sfc_gather", "sfc_gather_workspace", "sfc_gather_ws", "build_clusters", "build_nlist_workspace", "build_nlist",
+    "sfc_sort_workspace", "sfc_sort", "sfc_gather", "sfc_gather_workspace", "sfc_gather_ws", "build_clusters",
+    "build_nlist_workspace", "build_nlist", "build_nlist_async", "build_nlist_result",
     "nlist_pass", "nlist_pass_lj", "build_rows_workspace", "build_rows", "rows_pass", "nlist_decode", "sfcnl_profile_begin", "sfcnl_profile_end", "sfcnl_h_iterate",
     "sfcnl_hseed_features", "sfcnl_mlp_init", "sfcnl_mlp_infer", "sfcnl_mlp_grad_workspace", "sfcnl_mlp_grad",
     "sfcnl_mlp_adam", "sfcnl_batch_create", "sfcnl_batch_destroy", "sfcnl_batch_layout", "sfcnl_batch_sort_workspace",
@@ -106,6 +107,10 @@ def load():
     lib.build_nlist.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, C.POINTER(NlistOpts), vp, sz, vp, vp, sz,
                                 C.POINTER(sz), C.POINTER(i64)]
     lib.build_nlist.restype = i32
+    lib.build_nlist_async.argtypes = [vp, i64, vp, vp, vp, vp, vp, vp, C.POINTER(NlistOpts), vp, sz, vp, vp, sz]
+    lib.build_nlist_async.restype = i32
+    lib.build_nlist_result.argtypes = [vp, C.POINTER(sz), C.POINTER(i64)]
+    lib.build_nlist_result.restype = i32
     f3 = C.POINTER(C.c_float)
     lib.nlist_pass.argtypes = [vp, i64, i32, i32, i32, vp, vp, vp, vp, vp, vp, vp, vp, vp, f3]
     lib.nlist_pass.restype = i32

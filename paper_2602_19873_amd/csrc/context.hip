@@ -65,7 +65,22 @@ extern "C" int sfcnl_create(sfcnl_ctx *out, int device, void *stream) {
         return SFCNL_E_HIP;
     }
     memset(c->h_status, 0, kStWords * sizeof(uint32_t));
+    if (hipHostMalloc((void **)&c->h_pend, kStWords * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+        (void)hipHostFree(c->h_status);
+        (void)hipFree(c->d_status);
+        free(c);
+        return SFCNL_E_HIP;
+    }
+    if (hipEventCreateWithFlags(&c->ev_pend, hipEventDisableTiming) != hipSuccess) {
+        (void)hipHostFree(c->h_pend);
+        (void)hipHostFree(c->h_status);
+        (void)hipFree(c->d_status);
+        free(c);
+        return SFCNL_E_HIP;
+    }
     if (fill_u32(c, c->d_status, kStWords, 0) != SFCNL_OK || hipStreamSynchronize(c->stream) != hipSuccess) {
+        (void)hipEventDestroy(c->ev_pend);
+        (void)hipHostFree(c->h_pend);
         (void)hipHostFree(c->h_status);
         (void)hipFree(c->d_status);
         free(c);
@@ -120,6 +135,8 @@ extern "C" void sfcnl_destroy(sfcnl_ctx ctx) {
     if (!ctx) return;
     prof_release(ctx);
     (void)hipStreamSynchronize(ctx->stream);
+    (void)hipEventDestroy(ctx->ev_pend);
+    (void)hipHostFree(ctx->h_pend);
     (void)hipHostFree(ctx->h_status);
     (void)hipFree(ctx->d_status);
     free(ctx);

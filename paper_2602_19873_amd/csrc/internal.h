@@ -36,6 +36,13 @@ struct sfcnl_ctx_s {
     uint32_t *d_status;
     uint32_t *h_status;
     char err[512];
+    // build_nlist_async: status block copied behind the build, the event
+    // that marks the copy, and what the result call needs for its messages
+    uint32_t *h_pend;
+    hipEvent_t ev_pend;
+    int pend;
+    size_t pend_pool_bytes;
+    int pend_max_j;
     // stage timing (sfcnl_profile_begin / _end)
     int prof_slots;
     int prof_used[SFCNL_NSTAGE];
@@ -248,6 +255,9 @@ int features_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *keys, const float *x
                   const SegTable &seg);
 // reads the status block into pinned memory (kStWords words) and waits
 int read_status(sfcnl_ctx ctx);
+// build_nlist's sizes and errors from a copied status block (hs)
+int nlist_status(sfcnl_ctx ctx, const uint32_t *hs, size_t pool_bytes, int max_j_per_sc, size_t *h_used_bytes,
+                 int64_t *h_max_nj);
 
 }  // namespace sfcnl
 

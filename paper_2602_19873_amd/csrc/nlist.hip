@@ -18,6 +18,8 @@
 // The list is staged per super-cluster, its encoded size is computed on the
 // fly, a prefix sum places the super-clusters in order, and a second kernel
 // writes masks and nibble segments.
+#include <cstring>
+
 #include "internal.h"
 
 namespace sfcnl {
@@ -901,7 +903,13 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
 
     rc = read_status(ctx);
     if (rc) return rc;
-    const uint32_t *hs = ctx->h_status;
+    return nlist_status(ctx, ctx->h_status, pool_bytes, o.max_j_per_sc, h_used_bytes, h_max_nj);
+}
+
+// Sizes and errors of a build from its copied status block.
+int sfcnl::nlist_status(sfcnl_ctx ctx, const uint32_t *hs, size_t pool_bytes, int max_j_per_sc,
+                        size_t *h_used_bytes, int64_t *h_max_nj) {
+    int rc;
     *h_used_bytes = (size_t)hs[kStTotalLo] * 4;
     *h_max_nj = hs[kStMaxNj];
     if (hs[kStInputErr]) {
@@ -915,7 +923,7 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     if (hs[kStTree]) return set_err(ctx, SFCNL_E_HIP, "internal error: octree invariant broken (0x%x)", hs[kStTree]);
     if (hs[kStScratch])
         return set_err(ctx, SFCNL_E_CAPACITY, "a super-cluster lists %u j-clusters > max_j_per_sc %d", hs[kStMaxNj],
-                       o.max_j_per_sc);
+                       max_j_per_sc);
     if (hs[kStPoolOverflow])
         return set_err(ctx, SFCNL_E_CAPACITY, "pool of %zu bytes < %zu needed", pool_bytes, *h_used_bytes);
     return SFCNL_OK;
@@ -937,4 +945,44 @@ extern "C" int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, con
         return set_err(ctx, SFCNL_E_ARG, "build_nlist: null pointer");
     return nlist_build_impl(ctx, n, d_keys, d_x, d_y, d_z, d_h, d_bbox, *opts, d_ws, ws_bytes, d_sc_info, d_pool,
                             pool_bytes, SegTable{}, true, h_used_bytes, h_max_nj);
+}
+
+extern "C" int build_nlist_async(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_x,
+                                 const float *d_y, const float *d_z, const float *d_h, const float *d_bbox,
+                                 const sfcnl_nlist_opts *opts, void *d_ws, size_t ws_bytes, uint32_t *d_sc_info,
+                                 uint32_t *d_pool, size_t pool_bytes) {
+    if (!ctx) return SFCNL_E_ARG;
+    ctx->pend = 0;
+    int rc = check_opts(ctx, opts);
+    if (rc) return rc;
+    if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "build_nlist_async: n out of range");
+    if (n > 0 && (!d_keys || !d_x || !d_y || !d_z || !d_h || !d_bbox || !d_ws || !d_sc_info || (!d_pool && pool_bytes)))
+        return set_err(ctx, SFCNL_E_ARG, "build_nlist_async: null pointer");
+    if (n > 0) {
+        size_t used;
+        int64_t maxnj;
+        rc = nlist_build_impl(ctx, n, d_keys, d_x, d_y, d_z, d_h, d_bbox, *opts, d_ws, ws_bytes, d_sc_info, d_pool,
+                              pool_bytes, SegTable{}, false, &used, &maxnj);
+        if (rc) return rc;
+        SFCNL_HIP(ctx, hipMemcpyAsync(ctx->h_pend, ctx->d_status, kStWords * sizeof(uint32_t),
+                                      hipMemcpyDeviceToHost, ctx->stream));
+    } else {
+        memset(ctx->h_pend, 0, kStWords * sizeof(uint32_t));
+    }
+    SFCNL_HIP(ctx, hipEventRecord(ctx->ev_pend, ctx->stream));
+    ctx->pend = 1;
+    ctx->pend_pool_bytes = pool_bytes;
+    ctx->pend_max_j = opts->max_j_per_sc;
+    return SFCNL_OK;
+}
+
+extern "C" int build_nlist_result(sfcnl_ctx ctx, size_t *h_used_bytes, int64_t *h_max_nj) {
+    if (!ctx) return SFCNL_E_ARG;
+    if (!h_used_bytes || !h_max_nj) return set_err(ctx, SFCNL_E_ARG, "build_nlist_result: null result pointer");
+    *h_used_bytes = 0;
+    *h_max_nj = 0;
+    if (!ctx->pend) return set_err(ctx, SFCNL_E_ARG, "build_nlist_result: no build_nlist_async pending");
+    ctx->pend = 0;
+    SFCNL_HIP(ctx, hipEventSynchronize(ctx->ev_pend));
+    return nlist_status(ctx, ctx->h_pend, ctx->pend_pool_bytes, ctx->pend_max_j, h_used_bytes, h_max_nj);
 }
