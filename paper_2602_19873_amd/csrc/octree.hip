@@ -199,6 +199,37 @@ __global__ __launch_bounds__(256) void k_box_level(const float4 *__restrict__ be
     above[2 * b + 1] = hi;
 }
 
+// Two levels in one launch: each thread forms one box of the level above
+// `below` (as k_box_level), and the block's first 32 threads then join each
+// 8 of those from LDS into the next level (a block covers 256 boxes of the
+// middle level, so 32 of the top one; boxes past the end are empty and join
+// as no-ops).
+__global__ __launch_bounds__(256) void k_box_level2(const float4 *__restrict__ below, int64_t nbelow,
+                                                    float4 *__restrict__ mid, int64_t nmid,
+                                                    float4 *__restrict__ above, int64_t nabove) {
+    __shared__ float4 s_lo[256], s_hi[256];
+    const int t = threadIdx.x;
+    const int64_t b = (int64_t)blockIdx.x * 256 + t;
+    float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
+    float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+    if (b < nmid) {
+        for (int64_t c = 8 * b; c < 8 * b + 8 && c < nbelow; c++) add_box(lo, hi, below[2 * c], below[2 * c + 1]);
+        mid[2 * b] = lo;
+        mid[2 * b + 1] = hi;
+    }
+    s_lo[t] = lo;
+    s_hi[t] = hi;
+    __syncthreads();
+    const int64_t a = (int64_t)blockIdx.x * 32 + t;
+    if (t < 32 && a < nabove) {
+        float4 l2 = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
+        float4 h2 = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+        for (int k = 0; k < 8; k++) add_box(l2, h2, s_lo[8 * t + k], s_hi[8 * t + k]);
+        above[2 * a] = l2;
+        above[2 * a + 1] = h2;
+    }
+}
+
 struct BoxLevels {
     const float4 *lvl[kMaxBoxLevels + 1];  // lvl[0] = cluster boxes (cs particles each)
     int nlvl;
@@ -388,11 +419,22 @@ int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x,
     L.nlvl = nl + 1;
     L.cshift = t.cs == 4 ? 2 : (t.cs == 16 ? 4 : 3);
     int64_t below = (n + t.cs - 1) / t.cs;
-    for (int l = 0; l < nl; l++) {
-        k_box_level<<<blocks_for(sizes[l], 256), 256, 0, st>>>(L.lvl[l], below, t.boxlvl[l], sizes[l]);
-        SFCNL_LAUNCHED(ctx);
-        L.lvl[l + 1] = t.boxlvl[l];
-        below = sizes[l];
+    for (int l = 0; l < nl;) {
+        if (l + 1 < nl) {  // two levels per launch
+            k_box_level2<<<blocks_for(sizes[l], 256), 256, 0, st>>>(L.lvl[l], below, t.boxlvl[l], sizes[l],
+                                                                    t.boxlvl[l + 1], sizes[l + 1]);
+            SFCNL_LAUNCHED(ctx);
+            L.lvl[l + 1] = t.boxlvl[l];
+            L.lvl[l + 2] = t.boxlvl[l + 1];
+            below = sizes[l + 1];
+            l += 2;
+        } else {
+            k_box_level<<<blocks_for(sizes[l], 256), 256, 0, st>>>(L.lvl[l], below, t.boxlvl[l], sizes[l]);
+            SFCNL_LAUNCHED(ctx);
+            L.lvl[l + 1] = t.boxlvl[l];
+            below = sizes[l];
+            l += 1;
+        }
     }
     k_node_box<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nfirst, t.nend, x, y, z, h, L, t.nbox);
     SFCNL_LAUNCHED(ctx);
