@@ -95,3 +95,16 @@ def test_result_without_pending_build_is_an_argument_error(env):
     import ctypes as C
     used, maxnj = C.c_size_t(), C.c_int64()
     assert ctx.lib.build_nlist_result(ctx.handle, C.byref(used), C.byref(maxnj)) == -1
+
+
+def test_async_build_of_nothing(env):
+    sf, ctx, torch = env
+    import ctypes as C
+    from paper_2602_19873_amd import _lib
+    o = sf._opts(8, True, 128, 512, False, None)
+    assert ctx.lib.build_nlist_async(ctx.handle, 0, None, None, None, None, None, None, C.byref(o), None, 0,
+                                     None, None, 0) == 0
+    used, maxnj = C.c_size_t(7), C.c_int64(7)
+    assert ctx.lib.build_nlist_result(ctx.handle, C.byref(used), C.byref(maxnj)) == 0
+    assert used.value == 0 and maxnj.value == 0
+    assert ctx.lib.build_nlist_result(ctx.handle, C.byref(used), C.byref(maxnj)) == _lib.E_ARG

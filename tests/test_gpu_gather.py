@@ -58,3 +58,11 @@ def test_staged_gather_reports_bad_perm_and_small_workspace(env):
     with pytest.raises(sf.SfcnlError) as ei:
         sf.sfc_gather(ctx, torch.arange(n, dtype=torch.int32, device="cuda"), [x, x.clone()], ws=ws[:100])
     assert ei.value.code == -1
+
+
+def test_staged_gather_of_nothing(env):
+    sf, ctx, torch = env
+    import ctypes as C
+    ins = (C.c_void_p * 1)(None)
+    outs = (C.c_void_p * 1)(None)
+    assert ctx.lib.sfc_gather_ws(ctx.handle, 0, None, 1, ins, outs, None, 0) == 0
