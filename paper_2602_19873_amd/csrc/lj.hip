@@ -26,6 +26,9 @@ using namespace passk;
 
 constexpr float kAway = 1.0e38f;
 
+// One wavefront (one super-cluster) per block, as for the density passes.
+constexpr int kLjWaves = 1;
+
 struct LjArgs {
     int64_t n;
     uint32_t nsc;
@@ -90,14 +93,14 @@ __device__ __forceinline__ void lj_tile(float xj, float yj, float zj, float qj, 
 // faster); cluster size 16 spills heavily under that cap and keeps its own
 // register count.
 template <int CS, bool kCompress, bool kQ, bool kE, bool kPbc>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 1 : 6))) void k_pass_lj(LjArgs a) {
+__global__ __launch_bounds__(kWave * kLjWaves) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 1 : 6))) void k_pass_lj(LjArgs a) {
     constexpr int kNsub = kScSize / CS;
     constexpr int kNreg = CS == 8 ? 8 : 4;
     constexpr int kNj = CS == 16 ? 4 : 1;
     constexpr int kGroup = CS == 8 ? 8 : 4;
     const int lane = sfc_lane();
     const int w = threadIdx.x / kWave;
-    const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w));
+    const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(blockIdx.x, gridDim.x) * kLjWaves + w));
     if (s >= a.nsc) return;
     const int64_t n = a.n;
     const int jl = lane & (kGroup - 1);
@@ -220,14 +223,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 
 }
 
 template <int CS, bool kCompress, bool kQ, bool kE, bool kPbc>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 1 : 6))) void k_pass_lj_half(LjArgs a) {
+__global__ __launch_bounds__(kWave * kLjWaves) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 1 : 6))) void k_pass_lj_half(LjArgs a) {
     constexpr int kNsub = kScSize / CS;
     constexpr int kNreg = CS == 8 ? 8 : 4;
     constexpr int kNj = CS == 16 ? 4 : 1;
     constexpr int kIL = CS == 8 ? 8 : 16;  // lanes per j-particle (the i side, low bits)
     const int lane = sfc_lane();
     const int w = threadIdx.x / kWave;
-    const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w));
+    const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(blockIdx.x, gridDim.x) * kLjWaves + w));
     if (s >= a.nsc) return;
     const int64_t n = a.n;
     const int jq = CS == 8 ? lane >> 3 : lane >> 4;
@@ -402,7 +405,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 
 template <int CS, bool kHalf, bool kPbc>
 void launch_lj(int variant, unsigned g, hipStream_t st, const LjArgs &a) {
 #define SFCNL_LJ(C, Q, E) \
-    (kHalf ? k_pass_lj_half<CS, C, Q, E, kPbc> : k_pass_lj<CS, C, Q, E, kPbc>)<<<g, 256, 0, st>>>(a)
+    (kHalf ? k_pass_lj_half<CS, C, Q, E, kPbc> : k_pass_lj<CS, C, Q, E, kPbc>)<<<g, kWave * kLjWaves, 0, st>>>(a)
     switch (variant) {
         case 7: SFCNL_LJ(true, true, true); break;
         case 6: SFCNL_LJ(true, true, false); break;
@@ -461,7 +464,7 @@ extern "C" int nlist_pass_lj(sfcnl_ctx ctx, int64_t n, int cluster_size, int com
     LjArgs a{n, (uint32_t)((n + kScSize - 1) / kScSize), d_sc_info, d_pool, d_x, d_y, d_z, d_q,
              pr.r_cut * pr.r_cut, pr.sigma * pr.sigma, 24.0f * pr.eps, 4.0f * pr.eps, pr.coulomb,
              d_fx, d_fy, d_fz, d_epot, make_period(h_period)};
-    const unsigned g = blocks_for(a.nsc, kWavesPerBlock);
+    const unsigned g = blocks_for(a.nsc, kLjWaves);
     hipStream_t st = ctx->stream;
     const int variant = (compress ? 4 : 0) | (d_q ? 2 : 0) | (d_epot ? 1 : 0);
     prof_mark(ctx, kStagePass, false);
