@@ -1,8 +1,8 @@
-// Neighbour pass (Sec. II-A "neighbor pass", Sec. II-D Listing 1): decode a
-// super-cluster's compressed list 64 entries at a time (Sec. II-B, "set the
-// output to one where the bitmask is zero", info nibbles, data nibbles), then
-// evaluate one 8x8 particle tile per (j-cluster, set mask bit) on one
-// wavefront and accumulate the SPH density and the neighbour count.
+// Neighbour pass (Sec. II-A, Sec. II-D Listing 1): decode a super-cluster's
+// compressed list 64 entries at a time (Sec. II-B: lanes whose bitmask bit is
+// clear take difference 1, the others read an info nibble and then any data
+// nibbles), then evaluate one 8x8 particle tile per (j-cluster, set mask bit)
+// on one wavefront and accumulate the SPH density and the neighbour count.
 //
 // Lane (il, jl) = (lane / 8, lane % 8) keeps i-particle il of every i-cluster
 // in registers and loads j-particle jl of the current j-cluster, so a tile is
@@ -285,7 +285,9 @@ __global__ __launch_bounds__(kWave * kPassWaves) __attribute__((amdgpu_waves_per
         const float hh = v ? a.h[i] : 1.0f;
         ih2[k] = v ? hh * hh : -1.0f;
         ihinv[k] = 1.0f / hh;
-        im[k] = kMass ? (v ? a.m[i] : 0.0f) : 1.0f;
+        // a batch's padding particles (index < n, NaN radius and mass) get a
+        // zero mass: their shape is zero, but 0 * NaN would not be
+        im[k] = kMass ? ((v && hh > 0.0f) ? a.m[i] : 0.0f) : 1.0f;
     }
     float acc[kNreg];
     int cnt_nb[kNreg];
@@ -325,8 +327,8 @@ __global__ __launch_bounds__(kWave * kPassWaves) __attribute__((amdgpu_waves_per
                 nx[t] = vj ? a.x[q] : kFar;
                 ny[t] = vj ? a.y[q] : kFar;
                 nz[t] = vj ? a.z[q] : kFar;
-                nm[t] = kMass ? (vj ? a.m[q] : 0.0f) : 1.0f;
                 nh[t] = vj ? a.h[q] : -1.0f;
+                nm[t] = kMass ? ((vj && nh[t] > 0.0f) ? a.m[q] : 0.0f) : 1.0f;
             }
         };
         load_j(sfc_readlane(jv, 0));

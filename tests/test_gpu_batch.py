@@ -44,6 +44,9 @@ def _systems(sizes, target, seed0):
 # uneven sizes: an empty system, one below a super-cluster, ragged tails,
 # several thousand particles (many octree levels)
 SIZES = [3000, 0, 37, 20000, 64, 9001, 1, 15000]
+# systems whose list words and densities are also checked against the oracle
+# (one uniform, one Plummer)
+ORACLE_SYS = (0, 5)
 # for the iteration every system must hold more than target + 1 particles
 SIZES_IT = [3000, 0, 300, 20000, 129, 9001, 15000]
 
@@ -139,7 +142,57 @@ def test_list_density_counts_match_single(env, cs, half):
             _, cnt = oracle.density(x1.cpu().numpy(), y1.cpu().numpy(), z1.cpu().numpy(), h1.cpu().numpy(), None,
                                     "grid")
             np.testing.assert_array_equal(n1.cpu().numpy(), cnt)
+        if s in ORACLE_SYS:  # the batch's own words and densities against the oracle
+            xa, ya, za, ha = (t.cpu().numpy() for t in (x1, y1, z1, h1))
+            offs, jj, mm = oracle.cluster_list(xa, ya, za, ha, cs, "grid", half=half)
+            oinfo, opool = oracle.encode_all(offs, jj, mm, cs, True)
+            np.testing.assert_array_equal(info[c0:c1, 1], oinfo[:, 1])
+            np.testing.assert_array_equal(info[c0:c1, 0] - base, oinfo[:, 0])
+            np.testing.assert_array_equal(pool[base:base + words], opool)
+            orho, ocnt = oracle.density(xa, ya, za, ha, None, "grid")
+            np.testing.assert_array_equal(nnb_h[lo:lo + sy.n], ocnt)
+            rel = np.abs(rho_h[lo:lo + sy.n].astype(np.float64) - orho) / orho
+            assert rel.max() <= 1e-5, (s, rel.max())
     assert nl.used_bytes == 4 * total_words
+
+
+@pytest.mark.parametrize("cs", [4, 8, 16])
+def test_half_pass_masses(env, cs):
+    """Non-unit masses through the batched symmetric pass: system sizes not
+    divisible by the cluster size leave NaN padding in the last clusters,
+    which must add nothing (rho of every real particle finite and equal to
+    the single-system half pass and to the oracle)."""
+    sf, ctx, torch = env
+    sizes = [3001, 37, 9005, 1, 4099]
+    systems = _systems(sizes, 150, 650)
+    rng = np.random.default_rng(651)
+    for sy in systems:
+        sy.m = rng.uniform(0.5, 2.0, sy.n).astype(np.float32)
+    b = _batch(sf, ctx, systems)
+    keys, perm = sf.batch_sort(ctx, b, *(_concat(torch, systems, f) for f in "xyz"))
+    xs, ys, zs, hs, ms = sf.batch_gather(ctx, b, perm, [_concat(torch, systems, f) for f in "xyzhm"])
+    assert np.all(np.isnan(ms.cpu().numpy()[int(b.pbase[0]) + sizes[0]:int(b.pbase[1])]))
+    bbox = sf.batch_build_clusters(ctx, b, xs, ys, zs, hs, cluster_size=cs)
+    nl = sf.batch_build_nlist(ctx, b, keys, xs, ys, zs, hs, bbox, pool=ctx.empty(1024, torch.int32),
+                              cluster_size=cs, half=True)
+    rho, nnb = sf.batch_pass(ctx, b, nl, xs, ys, zs, hs, m=ms)
+    rho_h, nnb_h = rho.cpu().numpy(), nnb.cpu().numpy()
+    for s, sy in enumerate(systems):
+        lo = int(b.pbase[s])
+        got = rho_h[lo:lo + sy.n]
+        assert np.all(np.isfinite(got)), s
+        k1, p1 = sf.sfc_sort(ctx, *(torch.from_numpy(a).cuda() for a in (sy.x, sy.y, sy.z)), sy.box)
+        x1, y1, z1, h1, m1 = sf.sfc_gather(ctx, p1, [torch.from_numpy(a).cuda() for a in (sy.x, sy.y, sy.z, sy.h,
+                                                                                          sy.m)])
+        bb1 = sf.build_clusters(ctx, x1, y1, z1, h1, cs)
+        nl1 = sf.build_nlist(ctx, k1, x1, y1, z1, h1, bb1, cluster_size=cs, half=True)
+        r1, n1 = sf.nlist_pass(ctx, nl1, x1, y1, z1, h1, m=m1)
+        np.testing.assert_allclose(got, r1.cpu().numpy(), rtol=2e-6, atol=0)
+        np.testing.assert_array_equal(nnb_h[lo:lo + sy.n], n1.cpu().numpy())
+        orho, ocnt = oracle.density(*(t.cpu().numpy() for t in (x1, y1, z1, h1, m1)), "grid")
+        np.testing.assert_array_equal(nnb_h[lo:lo + sy.n], ocnt)
+        rel = np.abs(got.astype(np.float64) - orho) / orho
+        assert rel.max() <= 1e-5, (s, rel.max())
 
 
 def _perturbed(systems, seed, spread=2.0):
