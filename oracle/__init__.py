@@ -93,6 +93,8 @@ def _load():
                                C.c_float, C.c_int, C.c_void_p, C.c_int64, f64p, f64p, f64p, f64p, i32p, f32p]
         lib.orc_num_threads.restype = C.c_int
         lib.orc_num_threads.argtypes = []
+        lib.orc_set_num_threads.restype = None
+        lib.orc_set_num_threads.argtypes = [C.c_int]
         _lib = lib
         return lib
 
@@ -114,6 +116,11 @@ def _per(period):
 
 def num_threads() -> int:
     return int(_load().orc_num_threads())
+
+
+def set_num_threads(k: int) -> None:
+    """OpenMP threads of the following oracle calls."""
+    _load().orc_set_num_threads(int(k))
 
 
 # --------------------------------------------------------------------------
@@ -399,36 +406,48 @@ def pipeline(x, y, z, h, box, m=None, cs: int = 8, compress: bool = True, method
 # rebuilds its list every step with per-particle radii, Sec. IV)
 # --------------------------------------------------------------------------
 
+def h_step(h, cnt, lo, hi, target: int, tol: int):
+    """One round of the rule for every particle, given its radius h, its
+    own-radius count cnt and its bracket [lo, hi] (lo = 0 and hi = inf while
+    open). A particle with |cnt - target| <= tol keeps everything. Otherwise
+    its bracket narrows first (lo = max(lo, h) when too few, hi = min(hi, h)
+    when too many); the proposal is 2h for cnt = 0, else h (target/cnt)^(1/3)
+    clamped to [h/2, 2h]; a proposal not strictly inside (lo, hi) becomes the
+    midpoint, or 2 lo while hi is open, or hi/2 while lo is open. FP64.
+    Returns (h_new float64, lo, hi, moved)."""
+    hc = np.asarray(h, dtype=np.float64)
+    cnt = np.asarray(cnt, dtype=np.int64)
+    lo = np.array(lo, dtype=np.float64, copy=True)
+    hi = np.array(hi, dtype=np.float64, copy=True)
+    dev = cnt - target
+    move = np.abs(dev) > tol
+    few = move & (dev < 0)
+    many = move & (dev > 0)
+    lo[few] = np.maximum(lo[few], hc[few])
+    hi[many] = np.minimum(hi[many], hc[many])
+    with np.errstate(divide="ignore"):
+        hn = np.where(cnt == 0, 2.0 * hc, hc * np.cbrt(target / np.maximum(cnt, 1)))
+    hn = np.where(cnt == 0, hn, np.clip(hn, 0.5 * hc, 2.0 * hc))
+    out = ~((hn > lo) & (hn < hi))
+    mid = np.where(np.isinf(hi), 2.0 * lo, np.where(lo == 0.0, 0.5 * hi, 0.5 * (lo + hi)))
+    hn = np.where(out, mid, hn)
+    return np.where(move, hn, hc), lo, hi, move
+
+
 def h_iterate(x, y, z, h0, target: int, tol: int = 1, max_iters: int = 64, method: str = "grid"):
-    """Plain reference of the rule: a particle with |n - target| <= tol keeps
-    its h; otherwise its bracket narrows (lower bound if too few neighbours,
-    upper if too many) and h moves to 2h (n = 0) or h (target/n)^(1/3) clamped
-    to [h/2, 2h], replaced by the bracket midpoint (or the doubled lower /
-    halved upper bound while one side is open) when outside the bracket.
-    Update arithmetic in FP64, h stored in FP32, counts from density().
-    Returns (h, rounds, unconverged)."""
+    """Plain reference of the rule: h_step() on the counts of density() each
+    round until every particle is within target +- tol; h is stored in FP32
+    between rounds. Returns (h, rounds, unconverged)."""
     h = np.ascontiguousarray(h0, dtype=np.float32).copy()
     n = h.shape[0]
     lo = np.zeros(n)
     hi = np.full(n, np.inf)
     for it in range(max_iters):
         _, cnt = density(x, y, z, h, None, method)
-        dev = cnt.astype(np.int64) - target
-        move = np.abs(dev) > tol
+        hn, lo, hi, move = h_step(h, cnt, lo, hi, target, tol)
         if not move.any():
             return h, it + 1, 0
-        hc = h.astype(np.float64)
-        few = move & (dev < 0)
-        many = move & (dev > 0)
-        lo[few] = np.maximum(lo[few], hc[few])
-        hi[many] = np.minimum(hi[many], hc[many])
-        with np.errstate(divide="ignore"):
-            hn = np.where(cnt == 0, 2.0 * hc, hc * np.cbrt(target / np.maximum(cnt, 1)))
-        hn = np.where(cnt == 0, hn, np.clip(hn, 0.5 * hc, 2.0 * hc))
-        out = ~((hn > lo) & (hn < hi))
-        mid = np.where(np.isinf(hi), 2.0 * lo, np.where(lo == 0.0, 0.5 * hi, 0.5 * (lo + hi)))
-        hn = np.where(out, mid, hn)
-        h = np.where(move, hn, hc).astype(np.float32)
+        h = hn.astype(np.float32)
     _, cnt = density(x, y, z, h, None, method)
     return h, max_iters, int((np.abs(cnt.astype(np.int64) - target) > tol).sum())
 
@@ -518,14 +537,16 @@ def adam_step(p, g, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
     return p - lr * mh / (np.sqrt(vh) + eps), m, v
 
 
-def hseed_features(keys_sorted, h, nnb, bbox, edge0: float, target: int):
+def hseed_features(keys_sorted, h, nnb, bbox, edge0: float, target: int, level=None):
     """Features of the learned seed for SFC-ordered particles (float64, before
     rounding to bf16): log((n+1)/T); log(max(cluster box diagonal / h, 1e-3));
     the same for the 64-particle super-cluster box; log((1 + occupancy)/T) of
     the particle's Hilbert-key cell at levels L0-1, L0, L0+1 with
     L0 = clamp(round(log2(edge0 / h)), 2, 20); log2(edge0 / h) - L0;
     log(T / 100). With nnb None (no count yet: the seed applied before the
-    first round) the first feature is 0."""
+    first round) the first feature is 0. ``level`` (optional, one integer per
+    particle) replaces L0, for checks where FP32 and FP64 round log2(edge0 / h)
+    to different levels."""
     keys = np.asarray(keys_sorted, dtype=np.uint64)
     h = np.asarray(h, dtype=np.float64)
     n = h.shape[0]
@@ -544,6 +565,8 @@ def hseed_features(keys_sorted, h, nnb, bbox, edge0: float, target: int):
     f[:, 2] = np.log(np.maximum(sdiag[c // 8] / h, 1e-3))
     lev = np.log2(edge0 / h)
     L0 = np.clip(np.rint(lev), 2, 20).astype(np.int64)
+    if level is not None:
+        L0 = np.asarray(level, dtype=np.int64)
     for d in (-1, 0, 1):
         L = L0 + d
         shift = (3 * (21 - L)).astype(np.uint64)

@@ -824,3 +824,13 @@ int orc_num_threads(void)
     return 1;
 #endif
 }
+
+/* Threads for the following parallel loops (timing at one thread). */
+void orc_set_num_threads(int k)
+{
+#ifdef _OPENMP
+    if (k > 0) omp_set_num_threads(k);
+#else
+    (void)k;
+#endif
+}
