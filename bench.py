@@ -33,10 +33,13 @@ BYTES_PER_PARTICLE = {
     "sort": 8 * (12 + 12) + 8,     # 8 digit passes: read + write key/index; one histogram read
     "gather": 4 + 4 * (4 + 4),     # read perm; read + write x, y, z, h
     "clusters": 16 + 4,            # read x, y, z, h; write 32 B per 8-particle cluster
+    "octree": 8 + 4,               # read the sorted keys and the cluster boxes (nodes are ~1/16 of that)
+    "traverse": 16,                # read x, y, z, h of the own super-cluster (j-data from L2)
+    "pass": 16 + 8,                # read x, y, z, h; write rho, nnb (plus the list, counted per byte)
 }
-FLOPS_PER_TEST = 10     # dx, dy, dz (3); dx*dx (1); 2 fma (4); max of radii (1); compare (1)
 # Counted tests and evaluations: 64 per set mask bit of the final list (the 8x8
 # tiles that establish the list in the build and that the pass evaluates).
+FLOPS_PER_TEST = 9      # dx, dy, dz (3); dx*dx (1); two fma (4); compares are not counted
 FLOPS_PER_PAIR = 17     # dx, dy, dz (3); d2 (5); sqrt (1); q (1); spline piece (5); m*W, += (2)
 FLOPS_PER_PAIR_HALF = 25  # one distance (9), then q, spline piece, m*W, += for both particles (2 x 8)
 
@@ -80,19 +83,47 @@ def list_stats(sf, ctx, nl):
     }
 
 
-def cpu_baseline(s):
-    """The oracle, as it stands, on the timed workload itself: keys, stable
-    order, cell-list cluster list, encoding, FP64 density."""
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
+
+
+def cpu_baseline(s, runs=3, one_thread_n=262144):
+    """The oracle, as it stands, on the timed workload itself (keys, stable
+    order, cell-list cluster list, encoding, FP64 density): the median of
+    `runs` runs on all host threads, and one run on one thread over a bounded
+    sample of the same generator (same neighbour count, fewer particles)."""
+    import statistics
     import oracle
+    from paper_2602_19873_amd import workloads
     oracle.build()
+    nthreads = oracle.num_threads()
+    ts = []
+    for _ in range(runs):
+        t0 = time.perf_counter()
+        oracle.pipeline(s.x, s.y, s.z, s.h, s.box)
+        ts.append(time.perf_counter() - t0)
+    dt = statistics.median(ts)
+    small = workloads.uniform_varied(one_thread_n, workloads.SEED_BASE + 2, target=200.0)
+    oracle.set_num_threads(1)
     t0 = time.perf_counter()
-    oracle.pipeline(s.x, s.y, s.z, s.h, s.box)
-    dt = time.perf_counter() - t0
-    return {"value": s.n / dt / 1e6, "unit": "Mparticles/s", "cores": oracle.num_threads(), "kind": "oracle",
-            "sample": "the full timed workload (%s, N=%d), one run of the whole oracle path: Hilbert keys, "
-                      "stable sort, cell-list cluster list, nibble encoding, FP64 density; %.1f s"
-                      % (s.name, s.n, dt),
-            "seconds": dt}
+    oracle.pipeline(small.x, small.y, small.z, small.h, small.box)
+    dt1 = time.perf_counter() - t0
+    oracle.set_num_threads(nthreads)
+    return {"value": s.n / dt / 1e6, "unit": "Mparticles/s", "cores": nthreads, "kind": "oracle",
+            "sample": "the full timed workload (%s, N=%d): the whole oracle path (Hilbert keys, stable sort, "
+                      "cell-list cluster list, nibble encoding, FP64 density), median of %d runs on %d threads "
+                      "(%.1f s); one thread: the same generator at N=%d"
+                      % (s.name, s.n, runs, nthreads, dt, one_thread_n),
+            "seconds": dt, "runs_s": ts, "cpu_model": cpu_model(), "nproc": os.cpu_count(),
+            "one_thread": {"value": one_thread_n / dt1 / 1e6, "unit": "Mparticles/s", "n": one_thread_n,
+                           "seconds": dt1}}
 
 
 def source_sha(path):
@@ -101,43 +132,82 @@ def source_sha(path):
         return hashlib.sha1(f.read()).hexdigest()[:12]
 
 
-def read_traffic(kernel, n):
-    """HBM bytes per launch of `kernel` from the committed counter summary, or
-    None if there is none or the kernel's source changed since it was taken."""
+# Kernels of each stage of a step (for the counter-byte figures).
+STAGE_KERNELS = {
+    "keys": ["k_keys"],
+    "sort": ["k_hist", "k_digit_scan", "k_scatter"],
+    "gather": ["k_pack4", "k_gather4"],
+    "clusters": ["k_cluster_bbox"],
+    "octree": ["k_digits", "k_leaf_level", "k_emit_nodes", "k_node_range", "k_children", "k_box_level2",
+               "k_node_box", "k_child_count", "k_child_slots"],
+}
+
+
+def read_counters(n):
+    """HBM bytes per launch of each kernel from the committed counter summary
+    (lines `traffic kernel=... source=... source_sha=... n=... bytes_per_launch=...
+    launches_per_step=...`); a kernel whose source changed since the counters
+    were taken is left out."""
     path = os.path.join(ROOT, "profiles", "counters_uniform_2m.txt")
+    out = {}
     if not os.path.exists(path):
-        return None
-    rec = {}
+        return out
     with open(path) as f:
         for line in f:
-            if line.startswith("traffic "):
-                kv = dict(t.split("=", 1) for t in line.split()[1:])
-                rec[kv["kernel"]] = kv
-    kv = rec.get(kernel.replace(" ", ""))
-    if not kv or int(kv["n"]) != n:
-        return None
-    if kv["source_sha"] != source_sha(os.path.join(ROOT, "paper_2602_19873_amd", "csrc", kv["source"])):
-        return None
-    return float(kv["bytes_per_launch"])
+            if not line.startswith("traffic "):
+                continue
+            kv = dict(t.split("=", 1) for t in line.split()[1:])
+            if int(kv["n"]) != n:
+                continue
+            src = os.path.join(ROOT, "paper_2602_19873_amd", "csrc", kv["source"])
+            if not os.path.exists(src) or kv["source_sha"] != source_sha(src):
+                continue
+            out[kv["kernel"]] = (float(kv["bytes_per_launch"]), float(kv.get("launches_per_step", "1")))
+    return out
 
 
-def run_hiter(args, sf, torch, ctx):
-    """Time to drive every particle of the 1/r sphere to target +- 1 own-radius
-    neighbours from the plain starting guess (one global mean-density radius),
-    by list rebuilds. Positions are fixed, so the SFC order is computed once
-    outside the timed region."""
+def read_traffic(kernel, n):
+    """HBM bytes per launch of `kernel` (None if not measured for its current source)."""
+    rec = read_counters(n).get(kernel.replace(" ", ""))
+    return None if rec is None else rec[0]
+
+
+def _hiter_system(args, name):
+    """The 8,388,608-particle 1/r sphere from the plain global mean-density
+    radius (or the analytic-density seed), or the uniform generator of the
+    2M benchmark at the same size with starting radii off by a log-uniform
+    factor in [1/spread, spread] (the learned seed's training distribution)."""
+    import math
+    import numpy as np
     from paper_2602_19873_amd import workloads
     T = args.target
-    s = workloads.evrard_sphere(args.n or 8388608, workloads.SEED_BASE + 3, target=T, seed_h=args.seed_h)
-    n = s.n
-    log("h-iteration: %s n=%d target=%d seed=%s" % (s.name, n, T, args.seed_h))
+    n = args.n or 8388608
+    if name == "sphere":
+        return workloads.evrard_sphere(n, workloads.SEED_BASE + 3, target=T, seed_h=args.seed_h)
+    s = workloads.uniform_varied(n, workloads.SEED_BASE + 4, target=T)
+    rng = np.random.default_rng(workloads.SEED_BASE + 5)
+    sp = args.train_spread
+    s.h = (s.h * np.exp(rng.uniform(-math.log(sp), math.log(sp), n))).astype(np.float32)
+    s.name = "uniform_varied_8m_spread%g" % sp
+    return s
+
+
+def _time_hiter(args, sf, torch, ctx, s, params=None):
+    """Median time of `steps` runs of the iteration from the starting radii;
+    the SFC order is computed once outside the timed region (positions are
+    fixed)."""
+    from paper_2602_19873_amd import hseed
+    T = args.target
     dev = torch.device("cuda:0")
     x, y, z, h = (torch.from_numpy(a).to(dev) for a in (s.x, s.y, s.z, s.h))
     keys, perm = sf.sfc_sort(ctx, x, y, z, s.box)
     xs, ys, zs, h0 = sf.sfc_gather(ctx, perm, [x, y, z, h])
+    del x, y, z, h, perm
     hw = torch.empty_like(h0)
     bufs = {}
-    times, rounds = [], []
+    if params is not None:
+        bufs.update(mlp_params=params, box_edge=hseed.box_edge(s.box))
+    times, res = [], None
     for rep in range(args.warmup + args.steps):
         hw.copy_(h0)
         torch.cuda.synchronize()
@@ -146,18 +216,69 @@ def run_hiter(args, sf, torch, ctx):
                            recount=args.recount, **bufs)
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
-        bufs = dict(ws=res.nl.ws, pool=res.nl.pool, max_j_per_sc=res.nl.max_j_per_sc)
+        bufs.update(ws=res.nl.ws, pool=res.nl.pool, max_j_per_sc=res.nl.max_j_per_sc)
         if rep >= args.warmup:
             times.append(dt)
-            rounds.append(res.iters)
-        log("rep %d: %d rounds, %.1f ms, converged=%s" % (rep, res.iters, dt * 1e3, res.converged))
+        log("  rep %d: %d rounds (mean %.2f), %.1f ms, converged=%s" % (rep, res.iters, res.mean_rounds(), dt * 1e3,
+                                                                      res.converged))
+    if not res.converged:
+        raise RuntimeError("%s did not converge" % s.name)
     t = sorted(times)[len(times) // 2]
+    worst = int((res.nnb[:s.n].long() - T).abs().max().item())
+    out = {"ms": t * 1e3, "mparticles_per_s": s.n / t / 1e6, "rounds": res.iters,
+           "mean_rounds": res.mean_rounds(), "ms_per_round": t * 1e3 / res.iters, "max_abs_dev": worst}
+    del keys, xs, ys, zs, h0, hw, res, bufs
+    torch.cuda.empty_cache()
+    return out
+
+
+def run_hiter(args, sf, torch, ctx):
+    """Time to drive every particle to target +- 1 own-radius neighbours by
+    list rebuilds: the 1/r sphere from the plain starting guess, and with
+    --mlp 1 also the learned seed (trained on converged pairs of the 2M
+    benchmark's generator at 1,048,576 particles; training is a one-off
+    outside the timed region) against the plain rule, on the sphere and on
+    the training generator at the same size."""
+    from paper_2602_19873_amd import hseed
+    T = args.target
+    names = ("sphere", "uniform") if args.mlp else ("sphere",)
+    params, train = None, None
+    if args.mlp:
+        log("training the seed on %d pairs of the uniform generator (spread x%g)" % (args.train_n, args.train_spread))
+        t0 = time.perf_counter()
+        feat, d = hseed.training_set(ctx, n_total=args.train_n, targets=(T,), spread=args.train_spread)
+        params, losses = sf.mlp_train(ctx, feat, d, epochs=args.train_epochs, batch=4096)
+        torch.cuda.synchronize()
+        train = {"pairs": int(feat.shape[0]), "seconds": time.perf_counter() - t0, "loss_first": losses[0],
+                 "loss_last": losses[-1], "target_variance": float(torch.var(d).item()),
+                 "generator": "uniform, r_c U(0.8, 1.2), start x e^U(-ln s, ln s), s = %g" % args.train_spread}
+        log("trained: loss %.4f -> %.4f (variance %.4f) in %.1f s" % (losses[0], losses[-1],
+                                                                      train["target_variance"], train["seconds"]))
+        del feat, d
+    results = {}
+    for name in names:
+        s = _hiter_system(args, name)
+        log("h-iteration: %s n=%d target=%d" % (s.name, s.n, T))
+        log(" plain rule")
+        r = {"plain": _time_hiter(args, sf, torch, ctx, s)}
+        if params is not None:
+            log(" learned seed")
+            r["seeded"] = _time_hiter(args, sf, torch, ctx, s, params)
+            r["speedup"] = r["plain"]["ms"] / r["seeded"]["ms"]
+        r["workload"] = s.name
+        r["n"] = s.n
+        results[name] = r
+    main = results["sphere"]["seeded" if args.mlp else "plain"]
     out = {"metric": "h-iteration to target +- 1 neighbours, Mparticles/s (N / time to convergence)",
-           "value": n / t / 1e6, "unit": "Mparticles/s", "n_gpus": 1, "steps": args.steps, "warmup": args.warmup,
-           "ms_to_converge": t * 1e3, "rounds": rounds[0], "ms_per_round": t * 1e3 / rounds[0],
-           "higher_is_better": True, "dtype": "f32", "data": "synthetic",
-           "config": {"workload": s.name, "n": n, "target": T, "tol": 1, "seed_h": args.seed_h,
-                      "cluster_size": 8, "list": "half (each pair once, j > i)" if args.half else "full"}}
+           "value": main["mparticles_per_s"], "unit": "Mparticles/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": main["ms"], "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": results["sphere"]["workload"], "n": results["sphere"]["n"], "target": T, "tol": 1,
+                      "seed_h": args.seed_h, "cluster_size": 8, "learned_seed": bool(args.mlp),
+                      "list": "half (each pair once, j > i)" if args.half else "full"},
+           "systems": results}
+    if train:
+        out["seed_training"] = train
     print(json.dumps(out), flush=True)
 
 
@@ -455,12 +576,16 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after warm-up, copy this many MiB once (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 32k and 8M build + pass figures")
     ap.add_argument("--mode", choices=["step", "hiter", "batch", "lj", "rows"], default="step")
     ap.add_argument("--target", type=int, default=0, help="neighbour target (hiter 100, batch 150)")
     ap.add_argument("--nsys", type=int, default=64)
     ap.add_argument("--train-systems", type=int, default=16)
     ap.add_argument("--train-epochs", type=int, default=20)
     ap.add_argument("--seed-h", choices=["global", "analytic"], default="global")
+    ap.add_argument("--mlp", type=int, default=0, help="hiter mode: also train and time the learned seed")
+    ap.add_argument("--train-n", type=int, default=1 << 20, help="hiter --mlp: training particles")
+    ap.add_argument("--train-spread", type=float, default=4.0, help="hiter --mlp: starting-radius spread")
     ap.add_argument("--n", type=int, default=0)
     ap.add_argument("--recount", type=int, default=0, help="hiter/batch: rounds after the first recount by "
                                                             "0 automatic choice, 1 lists, 2 one wave per moved particle")
@@ -471,8 +596,8 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU: the path runs on a single MI355X; multi-GPU sharding is "
-              "described in DESIGN.md and not built", file=sys.stderr)
+        print("bench.py measures one GPU only: the path runs on a single MI355X and no multi-GPU "
+              "sharding is built", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
@@ -495,68 +620,138 @@ def main():
         ctx.close()
         return
 
-    s = make_workload(args.workload)
-    n = s.n
-    log("workload %s n=%d" % (args.workload, n))
     torch.cuda.set_device(0)
+    ctx = sf.Context(0)
+    run_step(args, sf, torch, ctx)
+    ctx.close()
+
+
+def time_steps(sf, torch, ctx, s, args, steps, warmup, copy_probe=0):
+    """Times `steps` whole-path steps (keys to density pass) of system s on the
+    library's stream; returns (ms per step, per-stage event times, list
+    statistics)."""
     dev = torch.device("cuda:0")
     x, y, z, h = (torch.from_numpy(a).to(dev) for a in (s.x, s.y, s.z, s.h))
-    ctx = sf.Context(0)
-    pipe = sf.Pipeline(ctx, n, s.box, compress=bool(args.compress), leaf_bucket=args.leaf_bucket,
-                       cluster_size=args.cluster_size, half=bool(args.half),
-                       max_j_per_sc=512)
-    for _ in range(max(args.warmup, 1)):
+    pipe = sf.Pipeline(ctx, s.n, s.box, compress=bool(args.compress), leaf_bucket=args.leaf_bucket,
+                       cluster_size=args.cluster_size, half=bool(args.half), max_j_per_sc=512)
+    for _ in range(max(warmup, 1)):
         pipe.step(x, y, z, h)
     torch.cuda.synchronize()
-    log("warmup done")
-    if args.copy_probe:
-        src = torch.empty(args.copy_probe << 20, dtype=torch.uint8, device=dev)
+    if copy_probe:
+        src = torch.empty(copy_probe << 20, dtype=torch.uint8, device=dev)
         dst = torch.empty_like(src)
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
-        log("copy probe: %d MiB" % args.copy_probe)
-
-    ctx.profile_begin(args.steps)
+        log("copy probe: %d MiB" % copy_probe)
+    ctx.profile_begin(steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    for _ in range(args.steps):
+    for _ in range(steps):
         pipe.step(x, y, z, h)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     prof = ctx.profile_end()
-    ms_step = (t1 - t0) * 1e3 / args.steps
-    value = n / (ms_step * 1e-3) / 1e6
-    log("timed %d steps: %.3f ms/step" % (args.steps, ms_step))
-
     st = list_stats(sf, ctx, pipe.nl)
+    del pipe, x, y, z, h
+    torch.cuda.empty_cache()
+    return (t1 - t0) * 1e3 / steps, prof, st
+
+
+def stage_table(prof, st, n, half, counters):
+    """Per stage: event time, the algorithmic rate against its bound, the
+    stage's lower-bound time max(bytes / HBM peak, flops / FP32 peak), and
+    (where the committed counters cover every kernel of the stage) the HBM
+    bytes the counters saw per step as a fraction of the HBM peak."""
     stages = {}
     for name, (ms, calls) in prof.items():
         if calls == 0:
             continue
         avg = ms / calls
         d = {"ms": avg}
-        if name in BYTES_PER_PARTICLE:
-            gbs = BYTES_PER_PARTICLE[name] * n / (avg * 1e-3) / 1e9
-            d.update(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS)
-        elif name == "traverse":
-            tf = st["tile_pairs"] * FLOPS_PER_TEST / (avg * 1e-3) / 1e12
-            d.update(bound="alu", achieved=tf, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s", frac=tf / FP32_PEAK_TFLOPS)
+        byts = BYTES_PER_PARTICLE.get(name, 0) * n
+        flops = 0.0
+        if name == "traverse":
+            flops = st["tile_pairs"] * FLOPS_PER_TEST
+            byts += 6.0 * st["entries"]  # staging list entries written
         elif name == "pass":
-            fl = FLOPS_PER_PAIR_HALF if args.half else FLOPS_PER_PAIR
-            tf = st["tile_pairs"] * fl / (avg * 1e-3) / 1e12
+            flops = st["tile_pairs"] * (FLOPS_PER_PAIR_HALF if half else FLOPS_PER_PAIR)
+            byts += st["bytes_per_particle"] * n
+        elif name == "encode":
+            byts = 6.0 * st["entries"] + st["bytes_per_particle"] * n
+        if flops:
+            tf = flops / (avg * 1e-3) / 1e12
             d.update(bound="alu", achieved=tf, peak=FP32_PEAK_TFLOPS, unit="TFLOP/s", frac=tf / FP32_PEAK_TFLOPS)
+        elif name in BYTES_PER_PARTICLE or name == "encode":
+            gbs = byts / (avg * 1e-3) / 1e9
+            d.update(bound="hbm", achieved=gbs, peak=HBM_PEAK_GBS, unit="GB/s", frac=gbs / HBM_PEAK_GBS)
+        d["bound_ms"] = max(byts / (HBM_PEAK_GBS * 1e9), flops / (FP32_PEAK_TFLOPS * 1e12)) * 1e3
+        ks = STAGE_KERNELS.get(name)
+        if ks and all(k in counters for k in ks):
+            cb = sum(counters[k][0] * counters[k][1] for k in ks)
+            d["counter_bytes"] = cb
+            d["counter_frac"] = cb / (avg * 1e-3) / (HBM_PEAK_GBS * 1e9)
         stages[name] = d
+    return stages
+
+
+def extra_config(sf, torch, ctx, args, name):
+    """Build + pass throughput of another configuration: the 32,768-particle
+    uniform system with one global radius, or the 8,388,608-particle 1/r
+    sphere at radii iterated to 100 +- 1 neighbours (from the analytic-density
+    seed, untimed), both in the launch configuration of the main run."""
+    from paper_2602_19873_amd import workloads
+    if name == "uniform_32k":
+        s = workloads.make_config("uniform_32k")
+        note = "h = r_c for all"
+    else:
+        s = workloads.evrard_sphere(8388608, workloads.SEED_BASE + 3, target=100, seed_h="analytic")
+        dev = torch.device("cuda:0")
+        x, y, z, h = (torch.from_numpy(a).to(dev) for a in (s.x, s.y, s.z, s.h))
+        keys, perm = sf.sfc_sort(ctx, x, y, z, s.box)
+        xs, ys, zs, hs = sf.sfc_gather(ctx, perm, [x, y, z, h])
+        res = sf.h_iterate(ctx, keys, xs, ys, zs, hs, target=100, tol=1, max_iters=64)
+        if not res.converged:
+            raise RuntimeError("sphere did not converge")
+        s.x, s.y, s.z, s.h = (t.cpu().numpy() for t in (xs, ys, zs, hs))
+        note = "radii iterated to 100 +- 1 (%d rounds from the analytic seed)" % res.iters
+        del keys, perm, x, y, z, h, xs, ys, zs, hs, res
+        torch.cuda.empty_cache()
+    steps = max(5, args.steps // 2)
+    ms, prof, st = time_steps(sf, torch, ctx, s, args, steps, args.warmup)
+    build = sum(v[0] / v[1] for k, v in prof.items() if v[1] and k != "pass")
+    pas = prof["pass"][0] / prof["pass"][1] if prof.get("pass", (0, 0))[1] else 0.0
+    log("%s: n=%d %.3f ms/step (build %.3f, pass %.3f) %.3f B/p" % (name, s.n, ms, build, pas,
+                                                                    st["bytes_per_particle"]))
+    return {"n": s.n, "radii": note, "ms_per_step": ms, "mparticles_per_s": s.n / (ms * 1e-3) / 1e6,
+            "build_ms": build, "pass_ms": pas, "mparticles_per_s_events": s.n / ((build + pas) * 1e-3) / 1e6,
+            "bytes_per_particle": st["bytes_per_particle"], "mean_nj": st["mean_nj"],
+            "tile_pairs_per_particle": st["tile_pairs"] / s.n}
+
+
+def run_step(args, sf, torch, ctx):
+    s = make_workload(args.workload)
+    n = s.n
+    log("workload %s n=%d" % (args.workload, n))
+    ms_step, prof, st = time_steps(sf, torch, ctx, s, args, args.steps, args.warmup, args.copy_probe)
+    value = n / (ms_step * 1e-3) / 1e6
+    log("timed %d steps: %.3f ms/step" % (args.steps, ms_step))
+    counters = read_counters(n)
+    stages = stage_table(prof, st, n, bool(args.half), counters)
     dom = max((k for k in stages if "bound" in stages[k]), key=lambda k: stages[k]["ms"])
     dd = stages[dom]
     hb = "true" if args.half else "false"
-    kernel_of = {"traverse": ("k_traverse<%d, %s, false>" % (args.cluster_size, hb), "nlist.hip"),
-                 "pass": ("k_pass_half<%d, true, false, true, false>" % args.cluster_size if args.half
-                          else "k_pass<%d, true, false, true, false>" % args.cluster_size, "pass.hip")}
-    traffic = read_traffic(kernel_of[dom][0], n) if dom in kernel_of else None
-    roofline = {"kernel": kernel_of.get(dom, (dom,))[0], "bound": dd["bound"], "achieved": dd["achieved"],
+    kernel_of = {"traverse": "k_traverse<%d,%s,false>" % (args.cluster_size, hb),
+                 "pass": ("k_pass_half<%d,true,false,true,false>" % args.cluster_size if args.half
+                          else "k_pass<%d,true,false,true,false>" % args.cluster_size)}
+    kern = kernel_of.get(dom, dom)
+    traffic = counters[kern][0] if kern in counters else None
+    roofline = {"kernel": kern, "bound": dd["bound"], "achieved": dd["achieved"],
                 "peak": dd["peak"], "unit": dd["unit"], "frac": dd["frac"], "traffic": traffic,
                 "avg_ms": dd["ms"]}
+    bound_sum = sum(v["bound_ms"] for v in stages.values())
+    additive = {"sum_stage_bound_ms": bound_sum, "measured_ms": ms_step, "frac": bound_sum / ms_step,
+                "note": "sum over stages of max(bytes / 8 TB/s, flops / 157.3 TFLOP/s), over the measured step"}
 
     out = {
         "metric": METRIC, "value": value, "unit": "Mparticles/s", "n_gpus": 1, "steps": args.steps,
@@ -571,11 +766,13 @@ def main():
         "stages_ms": {k: v["ms"] for k, v in stages.items()},
         "stages": stages,
         "roofline": roofline,
+        "roofline_additive": additive,
     }
+    if not args.no_extra:
+        out["configs"] = {name: extra_config(sf, torch, ctx, args, name) for name in ("uniform_32k", "evrard_8m")}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) on %d particles" % n)
         out["cpu_baseline"] = cpu_baseline(s)
-    ctx.close()
     print(json.dumps(out), flush=True)
 
 

@@ -143,3 +143,56 @@ def test_recount_paths_agree(env, kind):
         np.testing.assert_array_equal(out[mode][2], out[1][2])
         np.testing.assert_allclose(out[mode][3], out[1][3], rtol=2e-6, atol=0)
     _check_final((xs.cpu().numpy(), ys.cpu().numpy(), zs.cpu().numpy(), out[2][1]), res, T, 1)
+
+
+@pytest.mark.slow
+def test_sphere_8m_plain_and_seeded(env):
+    """The 8,388,608-particle 1/r sphere (Sec. IV's Evrard density profile)
+    from the plain global mean-density radius to 100 +- 1 neighbours, once
+    with the plain rule and once with the learned seed trained on 1,048,576
+    converged pairs of the 2M benchmark's generator (the learned-seed
+    configuration). For both, the oracle's cell list at the GPU's final
+    radii finds every count within 100 +- 1 and equal to the GPU's, and
+    densities within 1e-5; the final lists of sampled super-clusters (the
+    densest, at the centre, among them) equal the oracle's."""
+    sf, ctx, torch = env
+    from paper_2602_19873_amd import hseed
+    T = 100
+    _say("training set: 1M pairs of the uniform generator")
+    feat, d = hseed.training_set(ctx, n_total=1 << 20, targets=(T,), spread=4.0)
+    params, losses = sf.mlp_train(ctx, feat, d, epochs=10, batch=4096)
+    _say("loss %.4f -> %.4f" % (losses[0], losses[-1]))
+    del feat, d
+    s = workloads.evrard_sphere(8388608, workloads.SEED_BASE + 3, target=T)
+    keys, xs, ys, zs, hs = _sorted_inputs(env, s)
+    h0 = hs.clone()
+    xa, ya, za = (t.cpu().numpy() for t in (xs, ys, zs))
+    nsc = (s.n + 63) // 64
+    rounds = {}
+    for seeded in (False, True):
+        hs.copy_(h0)
+        kw = dict(mlp_params=params, box_edge=hseed.box_edge(s.box)) if seeded else {}
+        res = sf.h_iterate(ctx, keys, xs, ys, zs, hs, target=T, tol=1, max_iters=64, **kw)
+        torch.cuda.synchronize()
+        _say("%s: converged=%s rounds=%d mean %.2f" % ("seeded" if seeded else "plain", res.converged, res.iters,
+                                                      res.mean_rounds()))
+        assert res.converged and res.unconverged == 0
+        rounds[seeded] = (res.iters, res.mean_rounds())
+        hf = hs.cpu().numpy()
+        rho, cnt = oracle.density(xa, ya, za, hf, None, "grid")
+        assert np.all(np.abs(cnt - T) <= 1)
+        np.testing.assert_array_equal(res.nnb.cpu().numpy()[: s.n], cnt)
+        rel = np.abs(res.rho.cpu().numpy()[: s.n].astype(np.float64) - rho) / rho
+        assert rel.max() <= 1e-5, rel.max()
+        # sampled final lists: the centre (largest lists) and random ones
+        info = res.nl.sc_info.cpu().numpy().view(np.uint32)
+        pool = res.nl.pool.cpu().numpy().view(np.uint32)
+        big = np.argsort(info[:, 1])[-4:]
+        ids = np.unique(np.concatenate([big, [0, nsc - 1], np.random.default_rng(3).integers(0, nsc, 10)]))
+        so, sj, sm = oracle.cluster_list(xa, ya, za, hf, 8, "grid", sc_ids=ids)
+        for k, sc in enumerate(ids):
+            words = pool[info[sc, 0]:]
+            exp = oracle.encode_sc(sj[so[k]:so[k + 1]], sm[so[k]:so[k + 1]])
+            assert info[sc, 1] == so[k + 1] - so[k]
+            np.testing.assert_array_equal(words[:exp.shape[0]], exp)
+    _say("rounds plain %s, seeded %s" % (rounds[False], rounds[True]))
