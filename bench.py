@@ -424,7 +424,7 @@ def run_lj(args, sf, torch, ctx):
     sweep, main = {}, None
     for cs, comp, hf in cfgs:
         pipe = sf.Pipeline(ctx, n, s.box, compress=comp, leaf_bucket=args.leaf_bucket, cluster_size=cs, half=hf,
-                           max_j_per_sc=512, with_mass=True, period=period)
+                           max_j_per_sc=256, with_mass=True, period=period)
         for _ in range(max(args.warmup, 1)):
             pipe.step(x, y, z, h, q, density=False)
         torch.cuda.synchronize()
@@ -633,7 +633,7 @@ def time_steps(sf, torch, ctx, s, args, steps, warmup, copy_probe=0):
     dev = torch.device("cuda:0")
     x, y, z, h = (torch.from_numpy(a).to(dev) for a in (s.x, s.y, s.z, s.h))
     pipe = sf.Pipeline(ctx, s.n, s.box, compress=bool(args.compress), leaf_bucket=args.leaf_bucket,
-                       cluster_size=args.cluster_size, half=bool(args.half), max_j_per_sc=512)
+                       cluster_size=args.cluster_size, half=bool(args.half), max_j_per_sc=128 if args.half else 256)
     for _ in range(max(warmup, 1)):
         pipe.step(x, y, z, h)
     torch.cuda.synchronize()

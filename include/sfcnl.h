@@ -63,6 +63,11 @@ int sfcnl_create(sfcnl_ctx *out, int device, void *stream);
 void sfcnl_destroy(sfcnl_ctx ctx);
 /* Re-binds the context to another stream of the same device. */
 int sfcnl_set_stream(sfcnl_ctx ctx, void *stream);
+/* Launch shape of the density passes (nlist_pass and the batched passes) of
+ * this context: 1, 2 or 4 wavefronts (super-clusters) per workgroup (default
+ * 1). Results do not depend on it; the batch autotuner times the choices.
+ * Other values return SFCNL_E_ARG. */
+int sfcnl_set_pass_waves(sfcnl_ctx ctx, int waves);
 const char *sfcnl_last_error(sfcnl_ctx ctx);
 /* Waits for the stream and returns the latched device-side error, if any
  * (the latch is cleared). */
@@ -137,7 +142,11 @@ int build_clusters(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y,
  *   cluster_size  4, 8 or 16 (the size given to build_clusters).
  *   compress      0 or 1.
  *   leaf_bucket   octree leaves hold at most this many particles (8..256).
- *   max_j_per_sc  capacity of the per-super-cluster staging list.
+ *   max_j_per_sc  staging room per super-cluster on average: the workspace
+ *                 stages n_sc * ceil(max_j_per_sc / 64) chunks of 64 list
+ *                 entries (6 bytes each); every super-cluster fills its own
+ *                 first chunk and a longer list continues in chunks shared
+ *                 by all super-clusters, so only the total length counts.
  *   half          0: the full list above; 1: the half list, which keeps only
  *                 the pairs with j > i (the symmetric option of Sec. II-D,
  *                 each pair stored once): masks count only such pairs, and a
@@ -156,10 +165,12 @@ int build_clusters(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y,
  * Workspace: at least build_nlist_workspace(n, opts) bytes.
  * Returns SFCNL_OK, or SFCNL_E_CAPACITY when the pool (pool_bytes) or the
  * staging list is too small: then *h_used_bytes is the pool size needed and
- * *h_max_nj the largest list length, a retry with enough room yields the
+ * *h_max_nj the largest list length, or, when the staging list was too small,
+ * the max_j_per_sc that holds every list; a retry with enough room yields the
  * identical list, and the lists that did not fit are recorded as empty in
  * sc_info (so a pass over it stays inside the pool). On success *h_used_bytes
- * is the pool size used. Waits for the stream. */
+ * is the pool size used and *h_max_nj the largest list length. Waits for the
+ * stream. */
 typedef struct {
     int cluster_size;
     int compress;

@@ -63,6 +63,11 @@ class Context:
         if rc != 0:
             raise SfcnlError(rc, self.lib.sfcnl_last_error(self.handle).decode())
 
+    def set_pass_waves(self, waves: int):
+        """Wavefronts per workgroup of the density passes (1, 2 or 4)."""
+        self.check(self.lib.sfcnl_set_pass_waves(self.handle, int(waves)))
+        self.pass_waves = int(waves)
+
     def sync(self):
         self.check(self.lib.sfcnl_sync(self.handle))
 
@@ -193,7 +198,7 @@ def _opts(cluster_size, compress, leaf_bucket, max_j_per_sc, half=False, period=
                           (C.c_float * 3)(*_period(period)))
 
 
-def build_nlist_workspace(n, cluster_size=CLUSTER_SIZE, compress=True, leaf_bucket=128, max_j_per_sc=512,
+def build_nlist_workspace(n, cluster_size=CLUSTER_SIZE, compress=True, leaf_bucket=128, max_j_per_sc=256,
                           half=False) -> int:
     b = C.c_size_t()
     o = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc, half)
@@ -203,7 +208,7 @@ def build_nlist_workspace(n, cluster_size=CLUSTER_SIZE, compress=True, leaf_buck
 
 
 def build_nlist(ctx: Context, keys, x, y, z, h, bbox, compress: bool = True, leaf_bucket: int = 128,
-                max_j_per_sc: int = 512, cluster_size: int = CLUSTER_SIZE, pool=None, ws=None, sc_info=None,
+                max_j_per_sc: int = 256, cluster_size: int = CLUSTER_SIZE, pool=None, ws=None, sc_info=None,
                 grow: bool = True, half: bool = False, period=None):
     """Builds the compressed cluster-pair list (half: each pair once, j > i;
     period: 3 lengths, 0 = open axis, for periodic boundaries by minimum
@@ -239,7 +244,7 @@ def build_nlist(ctx: Context, keys, x, y, z, h, bbox, compress: bool = True, lea
 
 
 def build_nlist_async(ctx: Context, keys, x, y, z, h, bbox, pool, ws, sc_info, compress: bool = True,
-                      leaf_bucket: int = 128, max_j_per_sc: int = 512, cluster_size: int = CLUSTER_SIZE,
+                      leaf_bucket: int = 128, max_j_per_sc: int = 256, cluster_size: int = CLUSTER_SIZE,
                       half: bool = False, period=None):
     """Enqueues the list build without waiting (build_nlist_async). The list
     can be passed at once; build_nlist_finish then reports its sizes and
@@ -402,7 +407,7 @@ class HIterResult:
 
 
 def h_iterate(ctx: Context, keys, x, y, z, h, target: int = 100, tol: int = 1, max_iters: int = 64, m=None,
-              compress: bool = True, leaf_bucket: int = 128, max_j_per_sc: int = 512, bracket=None, bbox=None,
+              compress: bool = True, leaf_bucket: int = 128, max_j_per_sc: int = 256, bracket=None, bbox=None,
               ws=None, pool=None, sc_info=None, rho=None, nnb=None, raise_noconv: bool = False,
               resume: bool = False, mlp_params=None, box_edge: float = 0.0, seed_scratch=None,
               seed_mode: int = _lib.SEED_AFTER_FIRST, cluster_size: int = CLUSTER_SIZE, half: bool = False,
@@ -565,7 +570,7 @@ class Pipeline:
     sfc_sort -> sfc_gather -> build_clusters -> build_nlist -> nlist_pass."""
 
     def __init__(self, ctx: Context, n: int, box, compress: bool = True, leaf_bucket: int = 128,
-                 max_j_per_sc: int = 512, with_mass: bool = False, cluster_size: int = CLUSTER_SIZE,
+                 max_j_per_sc: int = 256, with_mass: bool = False, cluster_size: int = CLUSTER_SIZE,
                  half: bool = False, period=None):
         self.ctx, self.n, self.box = ctx, n, tuple(float(v) for v in box)
         self.period = _period(period)
@@ -701,7 +706,7 @@ def batch_build_clusters(ctx: Context, b: Batch, x, y, z, h, bbox=None, cluster_
     return bbox
 
 
-def batch_nlist_workspace(b: Batch, compress=True, leaf_bucket=128, max_j_per_sc=512,
+def batch_nlist_workspace(b: Batch, compress=True, leaf_bucket=128, max_j_per_sc=256,
                           cluster_size: int = CLUSTER_SIZE, half: bool = False) -> int:
     out = C.c_size_t()
     o = _opts(cluster_size, compress, leaf_bucket, max_j_per_sc, half)
@@ -711,7 +716,7 @@ def batch_nlist_workspace(b: Batch, compress=True, leaf_bucket=128, max_j_per_sc
 
 
 def batch_build_nlist(ctx: Context, b: Batch, keys, x, y, z, h, bbox, compress: bool = True, leaf_bucket: int = 128,
-                      max_j_per_sc: int = 512, pool=None, ws=None, sc_info=None, grow: bool = True,
+                      max_j_per_sc: int = 256, pool=None, ws=None, sc_info=None, grow: bool = True,
                       cluster_size: int = CLUSTER_SIZE, half: bool = False):
     """The padded batch's list (one pool, sc_info per padded super-cluster)."""
     n = b.n_pad
@@ -767,7 +772,7 @@ class BatchIterResult:
 
 
 def batch_h_iterate(ctx: Context, b: Batch, keys, x, y, z, h, target: int = 100, tol: int = 1, max_iters: int = 64,
-                    m=None, compress: bool = True, leaf_bucket: int = 128, max_j_per_sc: int = 512,
+                    m=None, compress: bool = True, leaf_bucket: int = 128, max_j_per_sc: int = 256,
                     use_graph: bool = True, mlp_params=None, seed_mode: int = _lib.SEED_AFTER_FIRST,
                     bufs: dict | None = None, cluster_size: int = CLUSTER_SIZE, half: bool = False,
                     recount: int = 0):

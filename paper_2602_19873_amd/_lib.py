@@ -19,7 +19,7 @@ E_HIP = -4
 E_NOCONV = -5
 
 SYMBOLS = [
-    "sfcnl_create", "sfcnl_destroy", "sfcnl_set_stream", "sfcnl_last_error", "sfcnl_sync", "sfcnl_version",
+    "sfcnl_create", "sfcnl_destroy", "sfcnl_set_stream", "sfcnl_set_pass_waves", "sfcnl_last_error", "sfcnl_sync", "sfcnl_version",
     "sfc_sort_workspace", "sfc_sort", "sfc_gather", "sfc_gather_workspace", "sfc_gather_ws", "build_clusters",
     "build_nlist_workspace", "build_nlist", "build_nlist_async", "build_nlist_result",
     "nlist_pass", "nlist_pass_lj", "build_rows_workspace", "build_rows", "rows_pass", "nlist_decode", "sfcnl_profile_begin", "sfcnl_profile_end", "sfcnl_h_iterate",
@@ -82,6 +82,8 @@ def load():
     lib.sfcnl_create.restype = i32
     lib.sfcnl_destroy.argtypes = [vp]
     lib.sfcnl_destroy.restype = None
+    lib.sfcnl_set_pass_waves.argtypes = [vp, i32]
+    lib.sfcnl_set_pass_waves.restype = i32
     lib.sfcnl_set_stream.argtypes = [vp, vp]
     lib.sfcnl_set_stream.restype = i32
     lib.sfcnl_last_error.argtypes = [vp]

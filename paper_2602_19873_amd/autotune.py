@@ -5,10 +5,11 @@ step covers; smaller clusters waste fewer pair evaluations, larger ones list
 fewer entries, Sec. III-A) and the octree leaf bucket (particles per leaf:
 small buckets test more node boxes, large ones more candidate j-clusters) by
 timing one cluster-box build, list build and pass of the whole batch for each
-candidate, with the radii the caller passes. The list, and so every result,
-is the same for all candidates. Results are cached in a JSON file keyed by
-(GPU architecture, padded-size bucket, workload tag), so a later run on the
-same kind of batch reuses them.
+candidate, with the radii the caller passes; then, for the winner, the
+workgroup shape of the density pass (1, 2 or 4 wavefronts per block). The
+list, and so every result, is the same for all candidates. Results are cached
+in a JSON file keyed by (GPU architecture, padded-size bucket, workload tag),
+so a later run on the same kind of batch reuses them.
 """
 from __future__ import annotations
 
@@ -23,6 +24,7 @@ from . import batch_build_clusters, batch_build_nlist, batch_pass
 CLUSTER_SIZES = (4, 8, 16)
 BUCKETS = (32, 64, 128, 256)
 CANDIDATES = tuple((cs, b) for cs in CLUSTER_SIZES for b in BUCKETS)
+PASS_WAVES = (1, 2, 4)
 
 
 def default_cache_path() -> str:
@@ -45,14 +47,15 @@ def _load(path):
 
 def tune_batch(ctx, b, keys, x, y, z, h, tag: str = "", candidates=CANDIDATES, reps: int = 3,
                cache_path: str | None = None, use_cache: bool = True, half: bool = False) -> dict:
-    """Returns {"cluster_size": cs, "leaf_bucket": bucket, "ms": {"cs<cs>_b<bucket>": median ms},
-    "cached": bool}."""
+    """Returns {"cluster_size": cs, "leaf_bucket": bucket, "pass_waves": w, "ms": {"cs<cs>_b<bucket>":
+    median ms}, "pass_ms": {"w<w>": median ms}, "cached": bool}; sets the context's pass shape to w."""
     path = cache_path or default_cache_path()
     key = cache_key(b.n_pad, tag + ("_half" if half else ""))
     db = _load(path) if use_cache else {}
-    if use_cache and key in db:
+    if use_cache and key in db and "pass_waves" in db[key]:
         out = dict(db[key])
         out["cached"] = True
+        ctx.set_pass_waves(out["pass_waves"])
         return out
     st = ctx.stream
     times = {}
@@ -65,7 +68,7 @@ def tune_batch(ctx, b, keys, x, y, z, h, tag: str = "", candidates=CANDIDATES, r
             bbox = batch_build_clusters(ctx, b, x, y, z, h, bufs.get("bbox"), cluster_size=cs)
             nl = batch_build_nlist(ctx, b, keys, x, y, z, h, bbox, leaf_bucket=bucket, pool=bufs.get("pool"),
                                    ws=bufs.get("ws"), sc_info=bufs.get("sc_info"),
-                                   max_j_per_sc=bufs.get("max_j", 512), cluster_size=cs, half=half)
+                                   max_j_per_sc=bufs.get("max_j", 256), cluster_size=cs, half=half)
             rho, nnb = batch_pass(ctx, b, nl, x, y, z, h, rho=bufs.get("rho"), nnb=bufs.get("nnb"))
             e1.record(st)
             e1.synchronize()
@@ -78,8 +81,29 @@ def tune_batch(ctx, b, keys, x, y, z, h, tag: str = "", candidates=CANDIDATES, r
         ms = sorted(ms[1:])  # the first call sizes the buffers
         times[(cs, bucket)] = ms[len(ms) // 2]
     best = min(times, key=times.get)
-    out = {"cluster_size": int(best[0]), "leaf_bucket": int(best[1]),
-           "ms": {"cs%d_b%d" % k: round(v, 4) for k, v in times.items()}}
+    # the pass's workgroup shape, on the winner's list
+    bbox = batch_build_clusters(ctx, b, x, y, z, h, bufs.get("bbox"), cluster_size=best[0])
+    nl = batch_build_nlist(ctx, b, keys, x, y, z, h, bbox, leaf_bucket=best[1], pool=bufs.get("pool"),
+                           ws=bufs.get("ws"), sc_info=bufs.get("sc_info"), max_j_per_sc=bufs.get("max_j", 256),
+                           cluster_size=best[0], half=half)
+    ptimes = {}
+    for w in PASS_WAVES:
+        ctx.set_pass_waves(w)
+        ms = []
+        for _ in range(reps + 1):
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record(st)
+            batch_pass(ctx, b, nl, x, y, z, h, rho=bufs.get("rho"), nnb=bufs.get("nnb"))
+            e1.record(st)
+            e1.synchronize()
+            ms.append(e0.elapsed_time(e1))
+        ms = sorted(ms[1:])
+        ptimes[w] = ms[len(ms) // 2]
+    wbest = min(ptimes, key=ptimes.get)
+    ctx.set_pass_waves(wbest)
+    out = {"cluster_size": int(best[0]), "leaf_bucket": int(best[1]), "pass_waves": int(wbest),
+           "ms": {"cs%d_b%d" % k: round(v, 4) for k, v in times.items()},
+           "pass_ms": {"w%d" % k: round(v, 4) for k, v in ptimes.items()}}
     if use_cache:
         db = _load(path)
         db[key] = out

@@ -23,6 +23,7 @@ void free_batch(sfcnl_batch b) {
     (void)hipFree(b->d_roots);
     (void)hipFree(b->d_sys_moved);
     if (b->h_sys_moved) (void)hipHostFree(b->h_sys_moved);
+    if (b->h_rstat) (void)hipHostFree(b->h_rstat);
     if (b->stream) (void)hipStreamDestroy(b->stream);
     if (b->ev_in) (void)hipEventDestroy(b->ev_in);
     if (b->ev_out) (void)hipEventDestroy(b->ev_out);
@@ -118,7 +119,9 @@ extern "C" int sfcnl_batch_create(sfcnl_ctx ctx, int nsys, const int64_t *h_coun
         SFCNL_ALLOC(b->d_roots, nsys);
         SFCNL_ALLOC(b->d_sys_moved, nsys);
 #undef SFCNL_ALLOC
-        if (rc == SFCNL_OK && hipHostMalloc((void **)&b->h_sys_moved, sizeof(uint32_t) * nsys) != hipSuccess)
+        if (rc == SFCNL_OK &&
+            (hipHostMalloc((void **)&b->h_sys_moved, sizeof(uint32_t) * nsys * kGraphRounds) != hipSuccess ||
+             hipHostMalloc((void **)&b->h_rstat, sizeof(uint32_t) * kStWords * kGraphRounds) != hipSuccess))
             rc = set_err(ctx, SFCNL_E_HIP, "sfcnl_batch_create: pinned allocation failed");
         if (rc == SFCNL_OK && (hipStreamCreateWithFlags(&b->stream, hipStreamNonBlocking) != hipSuccess ||
                                hipEventCreateWithFlags(&b->ev_in, hipEventDisableTiming) != hipSuccess ||

@@ -51,6 +51,7 @@ extern "C" int sfcnl_create(sfcnl_ctx *out, int device, void *stream) {
     if (!c) return SFCNL_E_ARG;
     c->device = device;
     c->stream = (hipStream_t)stream;
+    c->pass_waves = 1;
     if (hipSetDevice(device) != hipSuccess) {
         free(c);
         return SFCNL_E_HIP;
@@ -145,6 +146,13 @@ extern "C" void sfcnl_destroy(sfcnl_ctx ctx) {
 extern "C" int sfcnl_set_stream(sfcnl_ctx ctx, void *stream) {
     if (!ctx) return SFCNL_E_ARG;
     ctx->stream = (hipStream_t)stream;
+    return SFCNL_OK;
+}
+
+extern "C" int sfcnl_set_pass_waves(sfcnl_ctx ctx, int waves) {
+    if (!ctx) return SFCNL_E_ARG;
+    if (waves != 1 && waves != 2 && waves != 4) return set_err(ctx, SFCNL_E_ARG, "pass waves must be 1, 2 or 4");
+    ctx->pass_waves = waves;
     return SFCNL_OK;
 }
 

@@ -264,10 +264,12 @@ struct RoundArgs {
 };
 
 // Enqueues one round on ctx->stream with list options `o`; `seed` adds the
-// learned first step; `active` (nullable) restricts the list build and the
-// pass to flagged super-clusters; `act_out` receives the next round's flags.
+// learned first step; `restricted` limits the list build and the pass to the
+// super-clusters flagged in `act` (which receives the next round's flags);
+// the round's status block and per-system moved flags are copied to host
+// slot `slot`.
 int enqueue_round(sfcnl_ctx ctx, const RoundArgs &r, const sfcnl_nlist_opts &o, const sfcnl_hseed *seed,
-                  bool restricted, const ActiveWs &act) {
+                  bool restricted, const ActiveWs &act, int slot) {
     const SegTable seg = seg_of(r.b);
     const int64_t n = r.b->n_pad;
     int rc = SFCNL_OK;
@@ -311,10 +313,10 @@ int enqueue_round(sfcnl_ctx ctx, const RoundArgs &r, const sfcnl_nlist_opts &o, 
     if (rc) return rc;
     k_publish_total<<<1, 1, 0, ctx->stream>>>(act.scan + n / kScSize, ctx->d_status);
     SFCNL_LAUNCHED(ctx);
-    SFCNL_HIP(ctx, hipMemcpyAsync(ctx->h_status, ctx->d_status, kStWords * sizeof(uint32_t), hipMemcpyDeviceToHost,
-                                  ctx->stream));
-    SFCNL_HIP(ctx, hipMemcpyAsync(r.b->h_sys_moved, r.b->d_sys_moved, r.b->nsys * sizeof(uint32_t),
+    SFCNL_HIP(ctx, hipMemcpyAsync(r.b->h_rstat + (size_t)slot * kStWords, ctx->d_status, kStWords * sizeof(uint32_t),
                                   hipMemcpyDeviceToHost, ctx->stream));
+    SFCNL_HIP(ctx, hipMemcpyAsync(r.b->h_sys_moved + (size_t)slot * r.b->nsys, r.b->d_sys_moved,
+                                  r.b->nsys * sizeof(uint32_t), hipMemcpyDeviceToHost, ctx->stream));
     return SFCNL_OK;
 }
 
@@ -413,19 +415,27 @@ extern "C" int sfcnl_batch_h_iterate(sfcnl_ctx ctx, sfcnl_batch b, const uint64_
     it_nl.half = 0;
     const ActiveWs act = nlist_ws_active(d_ws, b->n_pad, it_nl, b->nsys);
     bool list_final = false;
-    GraphHolder gh;
+    // restricted rounds replay a graph of kGraphRounds rounds (one of a single
+    // round when fewer are left): rounds after convergence in a replay find
+    // nothing flagged and change nothing, so the host reads the status
+    // blocks of a replay in order and stops at the first converged one
+    GraphHolder gh_many, gh_one;
     std::vector<char> active((size_t)b->nsys, 1);
-    for (int it = 0; it < it_opts->max_iters; it++) {
-        const sfcnl_hseed *sd = (seed && seed->mode == SFCNL_SEED_AFTER_FIRST && it == 0) ? seed : nullptr;
-        list_final = it == 0;
+    int it = 0;
+    while (it < it_opts->max_iters) {
+        int nr = 1;
         if (it == 0) {
-            int rc = enqueue_round(ctx, r, *nl_opts, sd, false, act);
+            const sfcnl_hseed *sd = (seed && seed->mode == SFCNL_SEED_AFTER_FIRST) ? seed : nullptr;
+            int rc = enqueue_round(ctx, r, *nl_opts, sd, false, act, 0);
             if (rc) return rc;
         } else if (use_graph) {
+            nr = it + kGraphRounds <= it_opts->max_iters ? kGraphRounds : 1;
+            GraphHolder &gh = nr > 1 ? gh_many : gh_one;
             if (!gh.e) {
                 ctx->prof_slots = 0;  // no event records inside the graph
                 SFCNL_HIP(ctx, hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
-                int rc = enqueue_round(ctx, r, it_nl, nullptr, true, act);
+                int rc = SFCNL_OK;
+                for (int k = 0; k < nr && rc == SFCNL_OK; k++) rc = enqueue_round(ctx, r, it_nl, nullptr, true, act, k);
                 hipGraph_t g = nullptr;
                 hipError_t e = hipStreamEndCapture(st, &g);
                 gh.g = g;
@@ -436,45 +446,51 @@ extern "C" int sfcnl_batch_h_iterate(sfcnl_ctx ctx, sfcnl_batch b, const uint64_
             }
             SFCNL_HIP(ctx, hipGraphLaunch(gh.e, st));
         } else {
-            int rc = enqueue_round(ctx, r, it_nl, nullptr, true, act);
+            int rc = enqueue_round(ctx, r, it_nl, nullptr, true, act, 0);
             if (rc) return rc;
         }
         SFCNL_HIP(ctx, hipStreamSynchronize(st));
-        const uint32_t *hs = ctx->h_status;
-        S.used_bytes = (size_t)hs[kStTotalLo] * 4;
-        S.max_nj = hs[kStMaxNj];
-        if (hs[kStInputErr]) {
-            const uint32_t e = hs[kStInputErr];
-            int rc = fill_u32(ctx, ctx->d_status + kStInputErr, 1, 0);
-            if (rc) return rc;
-            return set_err(ctx, SFCNL_E_INPUT, "input error flags 0x%x (1: non-finite position, 2: bad radius, 8: positions span a "
-                                   "period or a radius reaches half of it)", e);
-        }
-        if (hs[kStTree]) return set_err(ctx, SFCNL_E_HIP, "internal error: octree invariant broken (0x%x)", hs[kStTree]);
-        if (hs[kStScratch])
-            return set_err(ctx, SFCNL_E_CAPACITY, "a super-cluster lists %u j-clusters > max_j_per_sc %d", hs[kStMaxNj],
-                           nl_opts->max_j_per_sc);
-        if (hs[kStPoolOverflow])
-            return set_err(ctx, SFCNL_E_CAPACITY, "pool of %zu bytes < %zu needed", pool_bytes, S.used_bytes);
-        S.iters = it + 1;
-        S.unconverged = hs[kStUnconverged];
-        S.moved += S.unconverged;
-        // a system takes part in a round while its previous round moved a
-        // particle (every system takes part in the first)
-        if (h_sys_rounds)
-            for (int s = 0; s < b->nsys; s++)
-                if (it == 0 || active[s]) h_sys_rounds[s] = it + 1;
-        for (int s = 0; s < b->nsys; s++) active[s] = b->h_sys_moved[s] != 0;
-        if (S.unconverged == 0) {
-            if (!list_final) {  // the list of the final radii, every super-cluster, requested form
-                const SegTable seg = seg_of(b);
-                int rc = clusters_impl(ctx, b->n_pad, d_x, d_y, d_z, d_h, nl_opts->cluster_size, d_bbox, seg);
+        for (int k = 0; k < nr; k++, it++) {
+            list_final = it == 0;
+            const uint32_t *hs = b->h_rstat + (size_t)k * kStWords;
+            const uint32_t *hm = b->h_sys_moved + (size_t)k * b->nsys;
+            S.used_bytes = (size_t)hs[kStTotalLo] * 4;
+            S.max_nj = hs[kStMaxNj];
+            if (hs[kStInputErr]) {
+                const uint32_t e = hs[kStInputErr];
+                int rc = fill_u32(ctx, ctx->d_status + kStInputErr, 1, 0);
                 if (rc) return rc;
-                rc = nlist_build_impl(ctx, b->n_pad, d_keys, d_x, d_y, d_z, d_h, d_bbox, *nl_opts, d_ws, ws_bytes,
-                                      d_sc_info, d_pool, pool_bytes, seg, true, &S.used_bytes, &S.max_nj);
-                if (rc) return rc;
+                return set_err(ctx, SFCNL_E_INPUT, "input error flags 0x%x (1: non-finite position, 2: bad radius, 8: positions span a "
+                                       "period or a radius reaches half of it)", e);
             }
-            return SFCNL_OK;
+            if (hs[kStTree]) return set_err(ctx, SFCNL_E_HIP, "internal error: octree invariant broken (0x%x)", hs[kStTree]);
+            if (hs[kStScratch]) {
+                S.max_nj = staging_fit(hs, (uint32_t)(b->n_pad / kScSize));
+                return set_err(ctx, SFCNL_E_CAPACITY, "staging list of max_j_per_sc %d too small: %lld holds the lists",
+                               nl_opts->max_j_per_sc, (long long)S.max_nj);
+            }
+            if (hs[kStPoolOverflow])
+                return set_err(ctx, SFCNL_E_CAPACITY, "pool of %zu bytes < %zu needed", pool_bytes, S.used_bytes);
+            S.iters = it + 1;
+            S.unconverged = hs[kStUnconverged];
+            S.moved += S.unconverged;
+            // a system takes part in a round while its previous round moved a
+            // particle (every system takes part in the first)
+            if (h_sys_rounds)
+                for (int s = 0; s < b->nsys; s++)
+                    if (it == 0 || active[s]) h_sys_rounds[s] = it + 1;
+            for (int s = 0; s < b->nsys; s++) active[s] = hm[s] != 0;
+            if (S.unconverged == 0) {
+                if (!list_final) {  // the list of the final radii, every super-cluster, requested form
+                    const SegTable seg = seg_of(b);
+                    int rc = clusters_impl(ctx, b->n_pad, d_x, d_y, d_z, d_h, nl_opts->cluster_size, d_bbox, seg);
+                    if (rc) return rc;
+                    rc = nlist_build_impl(ctx, b->n_pad, d_keys, d_x, d_y, d_z, d_h, d_bbox, *nl_opts, d_ws, ws_bytes,
+                                          d_sc_info, d_pool, pool_bytes, seg, true, &S.used_bytes, &S.max_nj);
+                    if (rc) return rc;
+                }
+                return SFCNL_OK;
+            }
         }
     }
     return set_err(ctx, SFCNL_E_NOCONV, "sfcnl_batch_h_iterate: %lld particles unconverged after %d rounds",

@@ -22,9 +22,10 @@ enum StatusWord : int {
     kStPoolOverflow = 1, // set if the pool is too small
     kStMaxNj = 2,        // largest list length (atomicMax)
     kStTotalLo = 3,      // total pool words (exclusive scan total)
-    kStScratch = 4,      // set if a staging list overflowed
+    kStScratch = 4,      // set if a list found no staging room
     kStTree = 5,         // octree invariant broken (internal error)
     kStUnconverged = 6,  // h iteration: particles that moved this round
+    kStChunks = 7,       // shared staging chunks requested by the traversal
     kStWords = 16
 };
 
@@ -43,6 +44,9 @@ struct sfcnl_ctx_s {
     int pend;
     size_t pend_pool_bytes;
     int pend_max_j;
+    uint32_t pend_nsc;
+    // waves (super-clusters) per block of the density passes (1, 2 or 4)
+    int pass_waves;
     // stage timing (sfcnl_profile_begin / _end)
     int prof_slots;
     int prof_used[SFCNL_NSTAGE];
@@ -156,12 +160,17 @@ struct sfcnl_batch_s {
     float *d_lo, *d_scale;   // 3 per system: key quantisation
     uint4 *d_roots;          // nsys
     uint32_t *d_sys_moved;   // nsys: particles moved in the last round
-    uint32_t *h_sys_moved;   // pinned mirror
+    uint32_t *h_sys_moved;   // pinned mirrors, one slot per round of a replay (kGraphRounds x nsys)
+    uint32_t *h_rstat;       // pinned status blocks, one per round of a replay (kGraphRounds x kStWords)
     hipStream_t stream;      // capture stream (default priority)
     hipEvent_t ev_in, ev_out;
 };
 
 namespace sfcnl {
+
+// Rounds of the batched h-iteration captured into one graph replay (the host
+// reads their status blocks after the replay).
+constexpr int kGraphRounds = 4;
 
 inline SegTable seg_of(const sfcnl_batch_s *b) {
     SegTable t;
@@ -256,8 +265,16 @@ int features_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *keys, const float *x
 // reads the status block into pinned memory (kStWords words) and waits
 int read_status(sfcnl_ctx ctx);
 // build_nlist's sizes and errors from a copied status block (hs)
-int nlist_status(sfcnl_ctx ctx, const uint32_t *hs, size_t pool_bytes, int max_j_per_sc, size_t *h_used_bytes,
-                 int64_t *h_max_nj);
+// (nsc: super-clusters of the build; on a staging overflow *h_max_nj is the
+// max_j_per_sc that holds every list)
+int nlist_status(sfcnl_ctx ctx, const uint32_t *hs, size_t pool_bytes, int max_j_per_sc, uint32_t nsc,
+                 size_t *h_used_bytes, int64_t *h_max_nj);
+// The max_j_per_sc whose staging holds the lists of a build over nsc
+// super-clusters that requested hs[kStChunks] shared chunks.
+inline int64_t staging_fit(const uint32_t *hs, uint32_t nsc) {
+    const uint64_t need = (uint64_t)nsc + hs[kStChunks];
+    return (int64_t)((need + nsc - 1) / (nsc ? nsc : 1)) * kWave;
+}
 
 }  // namespace sfcnl
 

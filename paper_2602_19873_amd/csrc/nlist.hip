@@ -2,20 +2,23 @@
 // II-C).
 //
 // One wavefront builds the list of one super-cluster (64 particles = 8
-// i-clusters of 8). Lane (il, jl) = (lane / 8, lane % 8) holds particle il of
-// every i-cluster, so one 64-lane compare covers one 8x8 cluster pair.
+// i-clusters of 8).
 //
 // Traversal: depth-first from the root with an LDS stack; at an internal node
-// up to 8 lanes test the children's boxes against the super-cluster box and
+// 64 lanes test up to 8 children against 8 boxes of the super-cluster and
 // push the survivors in reverse key order, so leaves come out in key order
-// and the list is sorted without a sort (Sec. II-A). At a leaf, the j-clusters
-// overlapping its particle range are tested 8 at a time: 64 lanes test 8
-// i-cluster boxes x 8 j-cluster boxes, then every surviving (i-cluster,
-// j-cluster) pair gets its 64 exact particle tests. Box tests are conservative
-// under FP32 rounding (rounding is monotone), so they never drop a pair the
-// exact test keeps; the masks are exact.
+// and the list is sorted without a sort (Sec. II-A). At a leaf, 64 lanes test
+// the i-cluster boxes against the boxes of the leaf's candidate j-clusters;
+// each candidate with a nonempty i-cluster mask joins an LDS queue. Once 64
+// are queued (and at the end) the queue is drained in order: every candidate
+// loads its own j-particles (the next candidate's load overlapping the
+// current one's tests) and each i-cluster of its mask gets one 64-lane step
+// of exact particle tests (lane (il, jl) = (lane / 8, lane % 8) holds
+// particle il of every i-cluster). Box tests are conservative under FP32
+// rounding (rounding is monotone), so they never drop a pair the exact test
+// keeps; the masks are exact.
 //
-// The list is staged per super-cluster, its encoded size is computed on the
+// The list is staged in 64-entry chunks with its encoded size computed on the
 // fly, a prefix sum places the super-clusters in order, and a second kernel
 // writes masks and nibble segments.
 #include <cstring>
@@ -31,6 +34,8 @@ namespace {
 constexpr int kWavesPerBlock = 1;
 constexpr int kStackCap = 160;  // 1 + 7 * 21 pushes at most
 constexpr int kSegCap = 80;     // words of one 64-value segment: 2 + (64 + 512 + 7) / 8
+constexpr int kQueueCap = 96;   // queued candidates: drained at 64, one box step adds at most 16
+constexpr uint32_t kUnstaged = 0xFFFFFFFFu;  // sc_nj of a list that found no staging room
 
 __device__ __forceinline__ unsigned xcd_remap(unsigned b, unsigned g) {
     // blocks are dealt round-robin to the 8 XCDs; give each XCD a contiguous
@@ -122,7 +127,7 @@ __global__ __launch_bounds__(256) void k_cluster_bbox(int64_t n, const float *__
 // ---------------------------------------------------------------------------
 struct TravArgs {
     int64_t n;
-    uint32_t nsc, nclu, cap;
+    uint32_t nsc, nclu;
     int compress;
     const float *x, *y, *z, *h;
     const float4 *bbox;
@@ -138,14 +143,28 @@ struct TravArgs {
     const uint8_t *p_active;
     const uint32_t *gate;  // nullable: every list empty when *gate <= gate_max
     uint32_t gate_max;
-    uint32_t *list_j;      // staging: cap entries per super-cluster
+    // staging: 64-entry chunks; chunk s is super-cluster s's first, longer
+    // lists continue in chunks nsc + id taken from a shared counter
+    // (status[kStChunks]); chunk_next links a list's chunks in order
+    uint32_t *list_j;
     uint16_t *list_m;
+    uint32_t *chunk_next;
+    uint32_t nshared;      // shared chunks (ids 0 .. nshared - 1)
     uint32_t *sc_nj, *sc_words;
     uint32_t *status;
 };
 
 // Lane roles of a super-cluster's wavefront for cluster size CS (64 / CS
-// i-clusters per super-cluster):
+// i-clusters per super-cluster).
+//
+// Box tests: lane l pairs the box of i-cluster l % (64 / CS) with candidate
+// slot l / (64 / CS), so one ballot holds in consecutive groups of 64 / CS
+// bits the i-cluster mask of each candidate slot (8 slots of 8 bits for CS = 8,
+// 4 of 16 for CS = 4, 16 of 4 for CS = 16). Node tests pair child l / 8 with
+// the box of super-cluster particles [8g, 8g + 8), g = l % 8 (for CS = 16 the
+// box of the i-cluster holding them).
+//
+// Exact tests (one step is 64 particle pairs):
 //   CS = 8:  lane (il, jl) = (lane / 8, lane % 8); register k holds i-particle
 //            8k + il (i-cluster k); one step is one 8x8 cluster pair.
 //   CS = 4:  lane (q, il, jl) = (lane / 16, lane / 4 % 4, lane % 4); register
@@ -154,14 +173,16 @@ struct TravArgs {
 //   CS = 16: lane (il, jq) = (lane / 4, lane % 4); register k holds
 //            i-particle 16k + il (i-cluster k); a 16x16 pair takes four steps
 //            (j-particles 4t + jq).
-// Leaf box tests pair i-cluster boxes with the 64 / CS j-cluster boxes of a
-// 64-particle candidate run, lane l taking j-cluster l % (64 / CS).
 template <int CS>
 struct Shape {
-    static constexpr int kNsub = kScSize / CS;
-    static constexpr int kNreg = CS == 8 ? 8 : 4;
+    static constexpr int kNsub = kScSize / CS;        // i-clusters per super-cluster
+    static constexpr int kNreg = CS == 8 ? 8 : 4;     // i-particles per lane
+    static constexpr int kNj = CS == 16 ? 4 : 1;      // j-particles per lane and candidate
     static constexpr int kMaskBytes = kNsub > 8 ? 2 : 1;
+    static constexpr int kSlots = kWave / kNsub;      // candidate j-clusters per box step
+    static constexpr uint32_t kFull = (1u << kNsub) - 1u;
     __device__ static int ipart(int k, int lane) { return CS == 8 ? 8 * k + (lane >> 3) : 16 * k + (lane >> 2); }
+    __device__ static int jpart(int t, int lane) { return CS == 8 ? (lane & 7) : (CS == 4 ? (lane & 3) : 4 * t + (lane & 3)); }
 };
 
 __device__ __forceinline__ void box_union(float4 &lo, float4 &hi, float4 blo, float4 bhi) {
@@ -174,21 +195,28 @@ __device__ __forceinline__ void box_union(float4 &lo, float4 &hi, float4 blo, fl
     hi.z = fmaxf(hi.z, bhi.z);
 }
 
-// Bits 0, 16, 32 and 48 of x gathered into bits 0..3 (the products of the
-// other bit pairs land on distinct positions below 48 or above 63).
-__device__ __forceinline__ uint32_t pack4_16(uint64_t x) {
-    return (uint32_t)(((x & 0x0001000100010001ull) * 0x0001000200040008ull) >> 48) & 0xFu;
+// Bit k of the result: byte k of b is nonzero.
+__device__ __forceinline__ uint32_t nonzero_bytes(uint64_t b) {
+    b |= b >> 4;
+    b |= b >> 2;
+    b |= b >> 1;
+    b &= 0x0101010101010101ull;
+    return (uint32_t)((b * 0x0102040810204080ull) >> 56);
 }
-// Bits 0, 4, 8 and 12 of x gathered into bits 0..3.
-__device__ __forceinline__ uint32_t pack4_4(uint32_t x) { return (((x & 0x1111u) * 0x1248u) >> 12) & 0xFu; }
 
-// Five waves per SIMD (at most 96 VGPRs): one more than the register count
-// left to itself would allow, measured 8 % faster.
+// max of two squared radii (both >= +0): the integer order of their bit
+// patterns is their order, and the integer max needs no canonicalisation
+__device__ __forceinline__ float max_sq(float u, float v) {
+    return __int_as_float(max(__float_as_int(u), __float_as_int(v)));
+}
+
+// Five waves per SIMD (at most 96 VGPRs).
 template <int CS, bool kHalf, bool kPbc>
 __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves_per_eu(5))) void k_traverse(TravArgs a) {
     using S = Shape<CS>;
-    constexpr int kNsub = S::kNsub, kNreg = S::kNreg;
+    constexpr int kNsub = S::kNsub, kNreg = S::kNreg, kNj = S::kNj, kSlots = S::kSlots;
     __shared__ uint4 s_stack[kWavesPerBlock][kStackCap];
+    __shared__ uint2 s_queue[kWavesPerBlock][kQueueCap];
     const int lane = sfc_lane();
     const int w = threadIdx.x / kWave;
     // wave-uniform: keep the super-cluster index (and all derived from it) scalar
@@ -225,24 +253,22 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
     constexpr bool half = kHalf;
     const float4 empty_lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
     const float4 empty_hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
-    // leaf tests: the i-cluster boxes this lane pairs with its j-cluster
-    constexpr int kIbox = CS == 4 ? 4 : 1;
-    float4 ilo[kIbox], ihi[kIbox];
-#pragma unroll
-    for (int t = 0; t < kIbox; t++) {
-        const uint32_t ic = own_c0 + (CS == 8 ? (lane >> 3) : (CS == 4 ? (lane >> 4) + 4 * t : ((lane >> 2) & 3)));
-        const bool v = ic < a.nclu && (CS != 16 || lane < 16);
-        ilo[t] = v ? a.bbox[2 * (size_t)ic] : empty_lo;
-        ihi[t] = v ? a.bbox[2 * (size_t)ic + 1] : empty_hi;
+    // box tests: the box of i-cluster lane % kNsub
+    float4 ilo, ihi;
+    {
+        const uint32_t ic = own_c0 + (uint32_t)(lane & (kNsub - 1));
+        const bool v = ic < a.nclu;
+        ilo = v ? a.bbox[2 * (size_t)ic] : empty_lo;
+        ihi = v ? a.bbox[2 * (size_t)ic + 1] : empty_hi;
     }
-    // node tests: lane group g = lane / 8 tests the children against the box
-    // of super-cluster particles [8g, 8g + 8) (for CS = 16 of its i-cluster)
+    // node tests: the box of super-cluster particles [8g, 8g + 8), g = lane % 8
+    // (for CS = 16 the box of their i-cluster)
     float4 glo, ghi;
     if (CS == 8) {
-        glo = ilo[0];
-        ghi = ihi[0];
+        glo = ilo;
+        ghi = ihi;
     } else {
-        const int g = lane >> 3;
+        const int g = lane & 7;
         const uint32_t c0 = own_c0 + (CS == 4 ? 2 * g : (g >> 1));
         const bool v0 = c0 < a.nclu;
         glo = v0 ? a.bbox[2 * (size_t)c0] : empty_lo;
@@ -265,17 +291,13 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
             for (int q = 0; q < cnt; q++) r = fmaxf(r, hm[p0 + q]);
             return r;
         };
-#pragma unroll
-        for (int t = 0; t < kIbox; t++) {
-            const int ic = CS == 8 ? (lane >> 3) : (CS == 4 ? (lane >> 4) + 4 * t : ((lane >> 2) & 3));
-            ilo[t].w = rmax(ic * CS, CS);
-        }
+        ilo.w = rmax((lane & (kNsub - 1)) * CS, CS);
         if (CS == 8)
-            glo.w = ilo[0].w;
+            glo.w = ilo.w;
         else if (CS == 4)
-            glo.w = rmax(8 * (lane >> 3), 8);
+            glo.w = rmax(8 * (lane & 7), 8);
         else
-            glo.w = rmax(16 * (lane >> 4), 16);
+            glo.w = rmax(16 * ((lane & 7) >> 1), 16);
         wave_sync();
     }
 
@@ -320,6 +342,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
     // stack of node records {first, end, child count (0 = leaf), first child
     // slot}; a node is pushed only after its box passed the test
     uint4 *stack = s_stack[w];
+    uint2 *queue = s_queue[w];
     int sp = 0;
     // the tree of this super-cluster's system; list entries are cluster
     // indices relative to the system's first cluster
@@ -336,18 +359,29 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
 
     int64_t last = -1;  // highest j-cluster already tested
     uint32_t nj = 0, prevj = 0xFFFFFFFFu, seg_words = 0;
-    uint32_t *out_j = a.list_j + (size_t)s * a.cap;
-    uint16_t *out_m = a.list_m + (size_t)s * a.cap;
-    // entries collect in lane (index % 64) of ej / em and leave 64 at a time:
-    // one coalesced store each, and the compressed size of the 64-entry
-    // segment (first difference from the previous segment's last index;
-    // difference 1: no nibble, up to 9: one, else one plus its hex digits)
+    // entries collect in lane (index % 64) of ej / em and leave 64 at a time
+    // into the next staging chunk: one coalesced store each, and the
+    // compressed size of the 64-entry segment (first difference from the
+    // previous segment's last index; difference 1: no nibble, up to 9: one,
+    // else one plus its hex digits)
     uint32_t ej = 0, em = 0;
+    uint32_t chunk = s;        // chunk being filled
+    bool staged = true;        // false once the shared chunks ran out
     auto flush = [&](uint32_t cnt) {
-        const uint32_t b = nj - cnt;  // first entry of the segment
-        if ((uint32_t)lane < cnt && b + lane < a.cap) {
-            out_j[b + lane] = ej;
-            out_m[b + lane] = (uint16_t)em;
+        if (nj > cnt) {  // beyond the first chunk: take a shared one
+            uint32_t id = 0;
+            if (lane == 0) id = atomicAdd(&a.status[kStChunks], 1u);
+            id = (uint32_t)__builtin_amdgcn_readfirstlane((int)id);
+            if (staged && id < a.nshared) {
+                if (lane == 0) a.chunk_next[chunk] = a.nsc + id;
+                chunk = a.nsc + id;
+            } else {
+                staged = false;
+            }
+        }
+        if (staged && (uint32_t)lane < cnt) {
+            a.list_j[(size_t)chunk * kWave + lane] = ej;
+            a.list_m[(size_t)chunk * kWave + lane] = (uint16_t)em;
         }
         const uint32_t up = __shfl_up(ej, 1, 64);
         const uint32_t v = ej - (lane == 0 ? prevj : up);
@@ -357,6 +391,158 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
         prevj = sfc_readlane(ej, (int)cnt - 1);
     };
 
+    // j-particles of candidate cluster cj in the exact-test lane roles; absent
+    // ones (past n) are put far away with a zero radius
+    auto load_j = [&](uint32_t cj, float (&xj)[kNj], float (&yj)[kNj], float (&zj)[kNj], float (&hj)[kNj]) {
+        const int64_t p0 = (int64_t)cj * CS;
+        const float *xb = a.x + p0, *yb = a.y + p0, *zb = a.z + p0, *hb = a.h + p0;
+        if (p0 + CS <= n) {
+#pragma unroll
+            for (int t = 0; t < kNj; t++) {
+                const int q = S::jpart(t, lane);
+                xj[t] = xb[q];
+                yj[t] = yb[q];
+                zj[t] = zb[q];
+                hj[t] = hb[q];
+            }
+        } else {
+#pragma unroll
+            for (int t = 0; t < kNj; t++) {
+                const int q = S::jpart(t, lane);
+                const bool v = p0 + q < n;
+                xj[t] = v ? xb[q] : kFar;
+                yj[t] = v ? yb[q] : kFar;
+                zj[t] = v ? zb[q] : kFar;
+                hj[t] = v ? hb[q] : 0.0f;
+            }
+        }
+    };
+
+    // exact tests of the queued candidates, in queue order: the next entry's
+    // j-particles load while the current entry's tiles run
+    uint32_t qn = 0;
+    auto drain = [&]() {
+        wave_sync();
+        uint2 qe = queue[0];
+        uint32_t ncj = (uint32_t)__builtin_amdgcn_readfirstlane((int)qe.x);
+        uint32_t ncm = (uint32_t)__builtin_amdgcn_readfirstlane((int)qe.y);
+        float nx[kNj], ny[kNj], nz[kNj], nh[kNj];
+        load_j(ncj, nx, ny, nz, nh);
+        for (uint32_t e = 0; e < qn; e++) {
+            const uint32_t cjv = ncj, cmask = ncm;
+            float xj[kNj], yj[kNj], zj[kNj], hj2[kNj];
+#pragma unroll
+            for (int t = 0; t < kNj; t++) {
+                xj[t] = nx[t];
+                yj[t] = ny[t];
+                zj[t] = nz[t];
+                // counting lists use the i radius only: a zero j radius
+                // makes max(h_i^2, h_j^2) = h_i^2
+                hj2[t] = gather ? 0.0f : nh[t] * nh[t];
+            }
+            if (e + 1 < qn) {
+                qe = queue[e + 1];
+                ncj = (uint32_t)__builtin_amdgcn_readfirstlane((int)qe.x);
+                ncm = (uint32_t)__builtin_amdgcn_readfirstlane((int)qe.y);
+                load_j(ncj, nx, ny, nz, nh);
+            }
+            // the j-cluster is one of our own i-clusters: exclude i == j
+            // (full list) or keep only j > i (half list)
+            const int self_c = (cjv >= own_c0 && cjv < own_c0 + kNsub) ? (int)(cjv - own_c0) : -1;
+            auto keep = [&](int ci, int ipos, int jpos) {
+                return half ? (ci < self_c || (ci == self_c && jpos > ipos)) : (ci != self_c || jpos != ipos);
+            };
+            uint32_t mask = 0;
+            if (CS == 8) {
+                const int jl = lane & 7, il = lane >> 3;
+                if (self_c < 0) {  // another super-cluster's j-cluster: the plain test
+#pragma unroll
+                    for (int c = 0; c < kNreg; c++) {
+                        if ((cmask >> c) & 1u) {
+                            float dx = xj[0] - ix[c];
+                            float dy = yj[0] - iy[c];
+                            float dz = zj[0] - iz[c];
+                            if (kPbc) wrap(dx, dy, dz);
+                            const float dxx = dx * dx;
+                            const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
+                            if (sfc_ballot(d2 < max_sq(ih2[c], hj2[0]))) mask |= 1u << c;
+                        }
+                    }
+                } else {
+#pragma unroll
+                    for (int c = 0; c < kNreg; c++) {
+                        if ((cmask >> c) & 1u) {
+                            float dx = xj[0] - ix[c];
+                            float dy = yj[0] - iy[c];
+                            float dz = zj[0] - iz[c];
+                            if (kPbc) wrap(dx, dy, dz);
+                            const float dxx = dx * dx;
+                            const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
+                            const bool pr = d2 < max_sq(ih2[c], hj2[0]) && keep(c, il, jl);
+                            if (sfc_ballot(pr)) mask |= 1u << c;
+                        }
+                    }
+                }
+            } else if (CS == 4) {
+                const int jl = lane & 3, il = (lane >> 2) & 3, q = lane >> 4;
+#pragma unroll
+                for (int k = 0; k < kNreg; k++) {
+                    if ((cmask >> (4 * k)) & 0xFu) {
+                        float dx = xj[0] - ix[k];
+                        float dy = yj[0] - iy[k];
+                        float dz = zj[0] - iz[k];
+                        if (kPbc) wrap(dx, dy, dz);
+                        const float dxx = dx * dx;
+                        const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
+                        bool pr = d2 < max_sq(ih2[k], hj2[0]);
+                        if (self_c >= 0) pr = pr && keep(4 * k + q, il, jl);
+                        const uint64_t b = sfc_ballot(pr);
+                        const uint32_t g = (uint32_t)((b & 0xFFFFull) != 0) |
+                                           ((uint32_t)(((b >> 16) & 0xFFFFull) != 0) << 1) |
+                                           ((uint32_t)(((b >> 32) & 0xFFFFull) != 0) << 2) |
+                                           ((uint32_t)((b >> 48) != 0) << 3);
+                        mask |= g << (4 * k);
+                    }
+                }
+            } else {
+                const int jq = lane & 3, il = lane >> 2;
+#pragma unroll
+                for (int c = 0; c < kNreg; c++) {
+                    if ((cmask >> c) & 1u) {
+                        bool pr = false;
+#pragma unroll
+                        for (int t = 0; t < 4; t++) {
+                            float dx = xj[t] - ix[c];
+                            float dy = yj[t] - iy[c];
+                            float dz = zj[t] - iz[c];
+                            if (kPbc) wrap(dx, dy, dz);
+                            const float dxx = dx * dx;
+                            const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
+                            bool p = d2 < max_sq(ih2[c], hj2[t]);
+                            if (self_c >= 0) {
+                                if (half)
+                                    p = p && (c < self_c || (c == self_c && 4 * t + jq > il));
+                                else if (c == self_c)
+                                    p = p && 4 * t + jq != il;
+                            }
+                            pr = pr || p;
+                        }
+                        if (sfc_ballot(pr)) mask |= 1u << c;
+                    }
+                }
+            }
+            if (mask) {
+                const bool mine = lane == (int)(nj & (kWave - 1));
+                ej = mine ? cjv - jbase : ej;
+                em = mine ? mask : em;
+                if ((++nj & (kWave - 1)) == 0) flush(kWave);
+            }
+        }
+        qn = 0;
+        wave_sync();
+    };
+
+    const uint64_t lt = sfc_lt_mask();
     while (sp > 0) {
         sp--;
         const uint4 rv = stack[sp];
@@ -373,191 +559,33 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
             const int64_t c1 = (nend - 1) / CS;
             if (c0 <= last) c0 = last + 1;
             if (half && c0 < (int64_t)own_c0) c0 = own_c0;  // j-clusters wholly before i: no j > i
-            // j-particles of the candidate clusters cb .. cb + 64/CS - 1 are 64
-            // consecutive particles: one coalesced load, lane l holding
-            // particle l of the run; absent ones are put far away. Lane l also
-            // loads the box of candidate cluster cb + l % (64/CS). The next
-            // run of the leaf is loaded while this one is tested.
-            float px, py, pz, ph, nx, ny, nz, nh;
-            float4 blo, bhi, nlo, nhi;
-            auto load_batch = [&](int64_t cb, float &x_, float &y_, float &z_, float &h_, float4 &lo_, float4 &hi_) {
-                const int64_t pj = cb * CS + lane;
-                const bool pv = pj < n && cb + lane / CS <= c1;
-                x_ = pv ? a.x[pj] : kFar;
-                y_ = pv ? a.y[pj] : kFar;
-                z_ = pv ? a.z[pj] : kFar;
-                h_ = pv ? a.h[pj] : 0.0f;
-                const int64_t cj = cb + (lane & (kNsub - 1));
+            // candidate clusters cb .. cb + kSlots - 1: lane l tests i-cluster
+            // l % kNsub against the box of candidate cb + l / kNsub; the
+            // survivors (nonempty i-cluster masks) join the queue in order
+            for (int64_t cb = c0; cb <= c1; cb += kSlots) {
+                const int64_t cj = cb + lane / kNsub;
+                float4 blo = empty_lo, bhi = empty_hi;
                 if (cj <= c1) {
                     const float4 l = a.bbox[2 * cj];
-                    lo_ = make_float4(l.x, l.y, l.z, gather ? 0.0f : l.w);  // own radius only when counting
-                    hi_ = a.bbox[2 * cj + 1];
-                } else {
-                    lo_ = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
-                    hi_ = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+                    blo = make_float4(l.x, l.y, l.z, gather ? 0.0f : l.w);  // own radius only when counting
+                    bhi = a.bbox[2 * cj + 1];
                 }
-            };
-            if (c0 <= c1) load_batch(c0, nx, ny, nz, nh, nlo, nhi);
-            for (int64_t cb = c0; cb <= c1; cb += kNsub) {
-                px = nx; py = ny; pz = nz; ph = nh; blo = nlo; bhi = nhi;
-                if (cb + kNsub <= c1) load_batch(cb + kNsub, nx, ny, nz, nh, nlo, nhi);
-                // counting lists use the i radius only: a zero j radius makes
-                // max(h_i^2, h_j^2) = h_i^2 without a select per tile
-                const float ph2 = gather ? 0.0f : ph * ph;
-                // box tests -> per candidate j-cluster jc its i-cluster mask
-                uint64_t bal[kIbox];
-                uint32_t anyj;
-#pragma unroll
-                for (int t = 0; t < kIbox; t++) bal[t] = sfc_ballot(boxes_near<kPbc>(ilo[t], ihi[t], blo, bhi, per));
-                if (CS == 8) {
-                    anyj = byte_or(bal[0]);
-                } else if (CS == 4) {
-                    const uint64_t o = bal[0] | bal[1] | bal[2] | bal[3];
-                    anyj = (uint32_t)((o | (o >> 16) | (o >> 32) | (o >> 48)) & 0xFFFFu);
-                } else {
-                    const uint32_t o = (uint32_t)bal[0];
-                    anyj = (o | (o >> 4) | (o >> 8) | (o >> 12)) & 0xFu;
-                }
-                while (anyj) {
-                    const int jc = __ffs(anyj) - 1;
-                    anyj &= anyj - 1u;
-                    uint32_t cmask;
-                    if (CS == 8) {
-                        // bit c of cmask = bit (8c + jc) of the ballot
-                        cmask = (uint32_t)((((bal[0] >> jc) & 0x0101010101010101ull) * 0x0102040810204080ull) >> 56);
-                    } else if (CS == 4) {
-                        // ballot t, lane 16g + jc: i-cluster g + 4t
-                        cmask = pack4_16(bal[0] >> jc) | (pack4_16(bal[1] >> jc) << 4) |
-                                (pack4_16(bal[2] >> jc) << 8) | (pack4_16(bal[3] >> jc) << 12);
-                    } else {
-                        // lane 4c + jc: i-cluster c
-                        cmask = pack4_4((uint32_t)bal[0] >> jc);
-                    }
-                    const uint32_t cjv = (uint32_t)(cb + jc);
-                    // the j-cluster is one of our own i-clusters: exclude i == j
-                    // (full list) or keep only j > i (half list)
-                    const int self_c = (cjv >= own_c0 && cjv < own_c0 + kNsub) ? (int)(cjv - own_c0) : -1;
-                    auto keep = [&](int ci, int ipos, int jpos) {
-                        return half ? (ci < self_c || (ci == self_c && jpos > ipos)) : (ci != self_c || jpos != ipos);
-                    };
-                    uint32_t mask = 0;
-                    // max(h_i^2, h_j^2) as a compare and select (fmaxf would
-                    // re-canonicalise both operands on every tile)
-                    auto rmax2 = [](float u, float v) { return u > v ? u : v; };
-                    if (CS == 8) {
-                        const int jl = lane & 7, il = lane >> 3;
-                        const int src = jc * CS + jl;
-                        const float xj = __shfl(px, src, 64), yj = __shfl(py, src, 64), zj = __shfl(pz, src, 64);
-                        const float hj2 = __shfl(ph2, src, 64);
-                        if (self_c < 0) {  // another super-cluster's j-cluster: the plain test,
-                                           // d2 below either squared radius
-#pragma unroll
-                            for (int c = 0; c < kNreg; c++) {
-                                if ((cmask >> c) & 1u) {
-                                    float dx = xj - ix[c];
-                                    float dy = yj - iy[c];
-                                    float dz = zj - iz[c];
-                                    if (kPbc) wrap(dx, dy, dz);
-                                    const float dxx = dx * dx;
-                                    const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                                    if (sfc_ballot((d2 < ih2[c]) | (d2 < hj2))) mask |= 1u << c;
-                                }
-                            }
-                        } else {
-                            // the tile of the j-cluster with itself: i != j, or j > i for a half list
-                            const bool diag_ok = half ? jl > il : jl != il;
-#pragma unroll
-                            for (int c = 0; c < kNreg; c++) {
-                                if ((cmask >> c) & 1u) {
-                                    float dx = xj - ix[c];
-                                    float dy = yj - iy[c];
-                                    float dz = zj - iz[c];
-                                    if (kPbc) wrap(dx, dy, dz);
-                                    const float dxx = dx * dx;
-                                    const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                                    bool pr = d2 < rmax2(ih2[c], hj2);
-                                    if (half)  // inside the super-cluster: i-clusters up to the j-cluster only
-                                        pr = pr && keep(c, il, jl);
-                                    else if (c == self_c)
-                                        pr = pr && diag_ok;
-                                    if (sfc_ballot(pr)) mask |= 1u << c;
-                                }
-                            }
-                        }
-                    } else if (CS == 4) {
-                        const int jl = lane & 3, il = (lane >> 2) & 3, q = lane >> 4;
-                        const int src = jc * CS + jl;
-                        const float xj = __shfl(px, src, 64), yj = __shfl(py, src, 64), zj = __shfl(pz, src, 64);
-                        const float hj2 = __shfl(ph2, src, 64);
-#pragma unroll
-                        for (int k = 0; k < kNreg; k++) {
-                            if ((cmask >> (4 * k)) & 0xFu) {
-                                float dx = xj - ix[k];
-                                float dy = yj - iy[k];
-                                float dz = zj - iz[k];
-                                if (kPbc) wrap(dx, dy, dz);
-                                const float dxx = dx * dx;
-                                const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                                bool pr = d2 < rmax2(ih2[k], hj2);
-                                if (self_c >= 0) pr = pr && keep(4 * k + q, il, jl);
-                                const uint64_t b = sfc_ballot(pr);
-                                const uint32_t g = (uint32_t)((b & 0xFFFFull) != 0) |
-                                                   ((uint32_t)(((b >> 16) & 0xFFFFull) != 0) << 1) |
-                                                   ((uint32_t)(((b >> 32) & 0xFFFFull) != 0) << 2) |
-                                                   ((uint32_t)((b >> 48) != 0) << 3);
-                                mask |= g << (4 * k);
-                            }
-                        }
-                    } else {
-                        const int jq = lane & 3, il = lane >> 2;
-                        float xj[4], yj[4], zj[4], hj2[4];
-#pragma unroll
-                        for (int t = 0; t < 4; t++) {
-                            const int src = jc * CS + 4 * t + jq;
-                            xj[t] = __shfl(px, src, 64);
-                            yj[t] = __shfl(py, src, 64);
-                            zj[t] = __shfl(pz, src, 64);
-                            hj2[t] = __shfl(ph2, src, 64);
-                        }
-#pragma unroll
-                        for (int c = 0; c < kNreg; c++) {
-                            if ((cmask >> c) & 1u) {
-                                bool pr = false;
-#pragma unroll
-                                for (int t = 0; t < 4; t++) {
-                                    float dx = xj[t] - ix[c];
-                                    float dy = yj[t] - iy[c];
-                                    float dz = zj[t] - iz[c];
-                                    if (kPbc) wrap(dx, dy, dz);
-                                    const float dxx = dx * dx;
-                                    const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                                    bool p = d2 < rmax2(ih2[c], hj2[t]);
-                                    if (self_c >= 0) {
-                                        if (half)
-                                            p = p && (c < self_c || (c == self_c && 4 * t + jq > il));
-                                        else if (c == self_c)
-                                            p = p && 4 * t + jq != il;
-                                    }
-                                    pr = pr || p;
-                                }
-                                if (sfc_ballot(pr)) mask |= 1u << c;
-                            }
-                        }
-                    }
-                    if (mask) {
-                        const bool mine = lane == (int)(nj & (kWave - 1));
-                        ej = mine ? cjv - jbase : ej;
-                        em = mine ? mask : em;
-                        if ((++nj & (kWave - 1)) == 0) flush(kWave);
-                    }
+                const uint64_t bal = sfc_ballot(boxes_near<kPbc>(ilo, ihi, blo, bhi, per));
+                if (bal) {
+                    const int sl = lane < kSlots ? lane : 0;
+                    const uint32_t cm = lane < kSlots ? (uint32_t)(bal >> (sl * kNsub)) & S::kFull : 0u;
+                    const uint64_t sv = sfc_ballot(cm != 0u);
+                    if (cm) queue[qn + (uint32_t)sfc_popc(sv & lt)] = make_uint2((uint32_t)cb + (uint32_t)lane, cm);
+                    qn += (uint32_t)sfc_popc(sv);
+                    if (qn >= (uint32_t)kWave) drain();
                 }
             }
             if (c1 > last) last = c1;
         } else {
-            // lane (g, jl): child jl of the node against lane group g's box
-            const int jl = lane & 7;
-            const bool act = jl < (int)nchild;
-            const uint32_t slot = cslot + (uint32_t)jl;
+            // lane (ch, g): child ch = lane / 8 of the node against group g's box
+            const int ch = lane >> 3;
+            const bool act = ch < (int)nchild;
+            const uint32_t slot = cslot + (uint32_t)ch;
             bool hit = false;
             uint4 crec = make_uint4(0u, 0u, 0u, 0u);
             if (act) {
@@ -568,27 +596,28 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
                 // a half list never needs a node that ends before the super-cluster
                 hit = boxes_near<kPbc>(glo, ghi, lo, hi, per) && (!half || crec.y > own_p0);
             }
-            const uint32_t keep = byte_or(sfc_ballot(hit));
+            const uint32_t keep = nonzero_bytes(sfc_ballot(hit));
             const int cnt = __popc(keep);
             if (sp + cnt > kStackCap) {  // cannot happen in a valid octree (depth <= 21)
                 if (lane == 0) atomicOr(&a.status[kStTree], 8u);
                 break;
             }
-            if (lane < 8 && ((keep >> lane) & 1u)) {
-                const int r = __popc(keep & ((1u << lane) - 1u));
+            if ((lane & 7) == 0 && ((keep >> ch) & 1u)) {
+                const int r = __popc(keep & ((1u << ch) - 1u));
                 stack[sp + cnt - 1 - r] = crec;  // first child on top
             }
             sp += cnt;
             wave_sync();
         }
     }
+    if (qn) drain();
     if (nj & (kWave - 1)) flush(nj & (kWave - 1));
     if (lane == 0) {
         const uint32_t mwords = (nj * S::kMaskBytes + 3u) / 4u;
-        a.sc_nj[s] = nj;
-        a.sc_words[s] = mwords + (a.compress ? seg_words : nj);
+        a.sc_nj[s] = staged ? nj : kUnstaged;
+        a.sc_words[s] = staged ? mwords + (a.compress ? seg_words : nj) : 0u;
         atomicMax(&a.status[kStMaxNj], nj);
-        if (nj > a.cap) atomicOr(&a.status[kStScratch], 1u);
+        if (!staged) atomicOr(&a.status[kStScratch], 1u);
     }
 }
 
@@ -596,11 +625,12 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
 // Encoder: masks, then raw indices or 64-wide nibble segments.
 // ---------------------------------------------------------------------------
 struct EncArgs {
-    uint32_t nsc, cap;
+    uint32_t nsc;
     int compress;
     int mask_bytes;  // 2 for 16 i-clusters per super-cluster, else 1
-    const uint32_t *list_j;
+    const uint32_t *list_j;  // staging chunks (see TravArgs)
     const uint16_t *list_m;
+    const uint32_t *chunk_next;
     const uint32_t *sc_nj, *sc_off;  // sc_off has nsc + 1 entries
     uint32_t *sc_info;
     uint32_t *pool;
@@ -618,59 +648,55 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_encode(EncArgs a) {
     const uint32_t nj = a.sc_nj[s];
     const uint32_t off = a.sc_off[s];
     const uint32_t words = a.sc_off[s + 1] - off;
-    // a list that could not be stored is recorded as empty (the status block
-    // reports it), so that a pass launched regardless never reads past the pool
-    const bool fits = nj <= a.cap && (uint64_t)off + words <= a.pool_words;
+    // a list that could not be staged or stored is recorded as empty (the
+    // status block reports it), so that a pass launched regardless never
+    // reads past the pool
+    const bool fits = nj != kUnstaged && (uint64_t)off + words <= a.pool_words;
     if (lane == 0) {
         a.sc_info[2 * s] = off;
         a.sc_info[2 * s + 1] = fits ? nj : 0u;
-        if (nj <= a.cap && !fits) atomicOr(&a.status[kStPoolOverflow], 1u);
+        if (nj != kUnstaged && !fits) atomicOr(&a.status[kStPoolOverflow], 1u);
     }
     if (!fits) return;
-    const uint32_t *lj = a.list_j + (size_t)s * a.cap;
-    const uint16_t *lm = a.list_m + (size_t)s * a.cap;
-    uint32_t *out = a.pool + off;
     const uint32_t mwords = (nj * (uint32_t)a.mask_bytes + 3u) / 4u;
-    for (uint32_t q = lane; q < mwords; q += kWave) {
-        uint32_t word = 0;
-        if (a.mask_bytes == 1) {
-#pragma unroll
-            for (int b = 0; b < 4; b++) {
-                uint32_t e = 4 * q + b;
-                if (e < nj) word |= (uint32_t)(lm[e] & 0xFFu) << (8 * b);
-            }
-        } else {
-#pragma unroll
-            for (int b = 0; b < 2; b++) {
-                uint32_t e = 2 * q + b;
-                if (e < nj) word |= (uint32_t)lm[e] << (16 * b);
-            }
-        }
-        out[q] = word;
-    }
-    out += mwords;
-    if (!a.compress) {
-        for (uint32_t e = lane; e < nj; e += kWave) out[e] = lj[e];
-        return;
-    }
+    uint32_t *mout = a.pool + off;
+    uint32_t *out = mout + mwords;
     uint32_t *seg = s_seg[w];
     const uint64_t lt = sfc_lt_mask();
     uint32_t prevj = 0xFFFFFFFFu;
+    uint32_t chunk = s;
     for (uint32_t b0 = 0; b0 < nj; b0 += kWave) {
         const uint32_t cnt = nj - b0 < (uint32_t)kWave ? nj - b0 : (uint32_t)kWave;
         const bool valid = (uint32_t)lane < cnt;
-        const uint32_t j = valid ? lj[b0 + lane] : 0u;
+        const uint32_t j = valid ? a.list_j[(size_t)chunk * kWave + lane] : 0u;
+        const uint32_t m = valid ? (uint32_t)a.list_m[(size_t)chunk * kWave + lane] : 0u;
+        if (b0 + kWave < nj) chunk = a.chunk_next[chunk];
+        // masks of this block: 4 (or 2) consecutive entries per word
+        if (a.mask_bytes == 1) {
+            uint32_t v = m << (8 * (lane & 3));
+            v |= __shfl_xor(v, 1, 64);
+            v |= __shfl_xor(v, 2, 64);
+            if ((lane & 3) == 0 && (uint32_t)lane < cnt) mout[b0 / 4 + lane / 4] = v;
+        } else {
+            uint32_t v = m << (16 * (lane & 1));
+            v |= __shfl_xor(v, 1, 64);
+            if ((lane & 1) == 0 && (uint32_t)lane < cnt) mout[b0 / 2 + lane / 2] = v;
+        }
+        if (!a.compress) {
+            if (valid) out[b0 + lane] = j;
+            continue;
+        }
         uint32_t jprev = __shfl_up(j, 1, 64);
         if (lane == 0) jprev = prevj;
         const uint32_t v = j - jprev;
         const bool nonone = valid && v != 1u;
-        const uint64_t m = sfc_ballot(nonone);
+        const uint64_t mk = sfc_ballot(nonone);
         const bool small = v <= 9u;
         const uint32_t nn = nibbles_of(v);
         const uint32_t ndata = (nonone && !small) ? nn : 0u;
         const uint32_t info = small ? v + 6u : nn - 1u;
-        const uint32_t ninfo = (uint32_t)sfc_popc(m);
-        const uint32_t ipos = (uint32_t)sfc_popc(m & lt);
+        const uint32_t ninfo = (uint32_t)sfc_popc(mk);
+        const uint32_t ipos = (uint32_t)sfc_popc(mk & lt);
         const uint32_t incl = sfc_incl_scan(ndata);
         const uint32_t dpos = ninfo + incl - ndata;
         const uint32_t total_nib = ninfo + sfc_readlane(incl, kWave - 1);
@@ -678,8 +704,8 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_encode(EncArgs a) {
         for (uint32_t q = lane; q < segw; q += kWave) seg[q] = 0u;
         wave_sync();
         if (lane == 0) {
-            seg[0] = (uint32_t)m;
-            seg[1] = (uint32_t)(m >> 32);
+            seg[0] = (uint32_t)mk;
+            seg[1] = (uint32_t)(mk >> 32);
         }
         if (nonone) {
             atomicOr(&seg[2 + ipos / 8], info << (4 * (ipos % 8)));
@@ -701,8 +727,10 @@ __global__ void k_finish(const uint32_t *total, uint32_t *status) { status[kStTo
 
 struct NlistWs {
     Octree tree;
+    uint32_t nchunks;     // staging chunks: nsc first ones, then the shared ones
     uint32_t *list_j;
     uint16_t *list_m;
+    uint32_t *chunk_next;
     uint32_t *sc_nj, *sc_words, *sc_off;
     uint32_t *sc_active;  // per super-cluster counts / flags for restricted rebuilds (h-iteration)
     uint32_t *sc_scan;    // their prefix sum (nsc + 1)
@@ -711,11 +739,17 @@ struct NlistWs {
     uint32_t *plist;      // the flagged particles, compacted
 };
 
+// Staging chunks per super-cluster (on average): max_j_per_sc rounded up to
+// whole 64-entry chunks.
+inline int64_t staging_chunks(int max_j_per_sc) { return ((int64_t)max_j_per_sc + kWave - 1) / kWave; }
+
 void carve_nlist(Carver &cv, NlistWs &ws, int64_t n, const sfcnl_nlist_opts &o, int nsys = 1) {
     const uint32_t nsc = (uint32_t)((n + kScSize - 1) / kScSize);
     octree_carve(cv, ws.tree, n, o.leaf_bucket, nsys, o.cluster_size);
-    ws.list_j = cv.take<uint32_t>((size_t)nsc * o.max_j_per_sc);
-    ws.list_m = cv.take<uint16_t>((size_t)nsc * o.max_j_per_sc);
+    ws.nchunks = nsc * (uint32_t)staging_chunks(o.max_j_per_sc);
+    ws.list_j = cv.take<uint32_t>((size_t)ws.nchunks * kWave);
+    ws.list_m = cv.take<uint16_t>((size_t)ws.nchunks * kWave);
+    ws.chunk_next = cv.take<uint32_t>(ws.nchunks);
     ws.sc_nj = cv.take<uint32_t>(nsc);
     ws.sc_words = cv.take<uint32_t>(nsc);
     ws.sc_off = cv.take<uint32_t>((size_t)nsc + 1);
@@ -851,7 +885,6 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     ta.n = n;
     ta.nsc = nsc;
     ta.nclu = nclu;
-    ta.cap = (uint32_t)o.max_j_per_sc;
     ta.compress = o.compress;
     ta.x = d_x;
     ta.y = d_y;
@@ -869,6 +902,8 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     ta.gate_max = gate_max;
     ta.list_j = ws.list_j;
     ta.list_m = ws.list_m;
+    ta.chunk_next = ws.chunk_next;
+    ta.nshared = ws.nchunks - nsc;
     ta.sc_nj = ws.sc_nj;
     ta.sc_words = ws.sc_words;
     ta.status = ctx->d_status;
@@ -886,11 +921,11 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
 
     EncArgs ea;
     ea.nsc = nsc;
-    ea.cap = ta.cap;
     ea.compress = o.compress;
     ea.mask_bytes = cs == 4 ? 2 : 1;
     ea.list_j = ws.list_j;
     ea.list_m = ws.list_m;
+    ea.chunk_next = ws.chunk_next;
     ea.sc_nj = ws.sc_nj;
     ea.sc_off = ws.sc_off;
     ea.sc_info = d_sc_info;
@@ -906,11 +941,11 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
 
     rc = read_status(ctx);
     if (rc) return rc;
-    return nlist_status(ctx, ctx->h_status, pool_bytes, o.max_j_per_sc, h_used_bytes, h_max_nj);
+    return nlist_status(ctx, ctx->h_status, pool_bytes, o.max_j_per_sc, nsc, h_used_bytes, h_max_nj);
 }
 
 // Sizes and errors of a build from its copied status block.
-int sfcnl::nlist_status(sfcnl_ctx ctx, const uint32_t *hs, size_t pool_bytes, int max_j_per_sc,
+int sfcnl::nlist_status(sfcnl_ctx ctx, const uint32_t *hs, size_t pool_bytes, int max_j_per_sc, uint32_t nsc,
                         size_t *h_used_bytes, int64_t *h_max_nj) {
     int rc;
     *h_used_bytes = (size_t)hs[kStTotalLo] * 4;
@@ -924,9 +959,11 @@ int sfcnl::nlist_status(sfcnl_ctx ctx, const uint32_t *hs, size_t pool_bytes, in
                        "8: positions span a period or a radius reaches half of it)", e);
     }
     if (hs[kStTree]) return set_err(ctx, SFCNL_E_HIP, "internal error: octree invariant broken (0x%x)", hs[kStTree]);
-    if (hs[kStScratch])
-        return set_err(ctx, SFCNL_E_CAPACITY, "a super-cluster lists %u j-clusters > max_j_per_sc %d", hs[kStMaxNj],
-                       max_j_per_sc);
+    if (hs[kStScratch]) {
+        *h_max_nj = staging_fit(hs, nsc);
+        return set_err(ctx, SFCNL_E_CAPACITY, "staging list of max_j_per_sc %d too small: %lld holds the lists",
+                       max_j_per_sc, (long long)*h_max_nj);
+    }
     if (hs[kStPoolOverflow])
         return set_err(ctx, SFCNL_E_CAPACITY, "pool of %zu bytes < %zu needed", pool_bytes, *h_used_bytes);
     return SFCNL_OK;
@@ -976,6 +1013,7 @@ extern "C" int build_nlist_async(sfcnl_ctx ctx, int64_t n, const uint64_t *d_key
     ctx->pend = 1;
     ctx->pend_pool_bytes = pool_bytes;
     ctx->pend_max_j = opts->max_j_per_sc;
+    ctx->pend_nsc = (uint32_t)((n + kScSize - 1) / kScSize);
     return SFCNL_OK;
 }
 
@@ -987,5 +1025,6 @@ extern "C" int build_nlist_result(sfcnl_ctx ctx, size_t *h_used_bytes, int64_t *
     if (!ctx->pend) return set_err(ctx, SFCNL_E_ARG, "build_nlist_result: no build_nlist_async pending");
     ctx->pend = 0;
     SFCNL_HIP(ctx, hipEventSynchronize(ctx->ev_pend));
-    return nlist_status(ctx, ctx->h_pend, ctx->pend_pool_bytes, ctx->pend_max_j, h_used_bytes, h_max_nj);
+    return nlist_status(ctx, ctx->h_pend, ctx->pend_pool_bytes, ctx->pend_max_j, ctx->pend_nsc, h_used_bytes,
+                        h_max_nj);
 }

@@ -154,15 +154,18 @@ __global__ __launch_bounds__(256) void k_node_range(const uint64_t *__restrict__
     nesc[k] = e < nn ? e : nn;
 }
 
+// Children of every node (up to 8, in key order) and their count, also as
+// u32 in cbase for the prefix sum that places them in child slots.
 __global__ __launch_bounds__(256) void k_children(const uint32_t *__restrict__ d_nnodes, uint32_t cap,
                                                   const uint8_t *__restrict__ nleaf, const uint32_t *__restrict__ nesc,
                                                   uint32_t *__restrict__ nchild, uint8_t *__restrict__ nnchild,
-                                                  uint32_t *status) {
+                                                  uint32_t *__restrict__ cbase, uint32_t *status) {
     const uint32_t nn = node_count(d_nnodes, cap);
     uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
     if (k >= nn) return;
     if (nleaf[k]) {
         nnchild[k] = 0;
+        cbase[k] = 0;
         return;
     }
     uint32_t e = nesc[k], c = k + 1;
@@ -174,6 +177,7 @@ __global__ __launch_bounds__(256) void k_children(const uint32_t *__restrict__ d
     }
     if (c < e || i == 0) atomicOr(&status[kStTree], 2u);  // an octree node has 1..8 children
     nnchild[k] = (uint8_t)i;
+    cbase[k] = (uint32_t)i;
 }
 
 __device__ __forceinline__ void add_box(float4 &lo, float4 &hi, const float4 l, const float4 u) {
@@ -277,16 +281,6 @@ __global__ __launch_bounds__(256) void k_node_box(const uint32_t *__restrict__ d
     }
     nbox[2 * (size_t)k] = lo;
     nbox[2 * (size_t)k + 1] = hi;
-}
-
-// Child counts as u32 for the prefix sum that places every node's children
-// in one contiguous run of child slots.
-__global__ __launch_bounds__(256) void k_child_count(const uint32_t *__restrict__ d_nnodes, uint32_t cap,
-                                                     const uint8_t *__restrict__ nnchild, uint32_t *__restrict__ cbase) {
-    const uint32_t nn = node_count(d_nnodes, cap);
-    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nn) return;
-    cbase[k] = nnchild[k];
 }
 
 // Child slot 0 holds the root; node k's children occupy slots
@@ -409,7 +403,7 @@ int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x,
     k_node_range<<<gn, 256, 0, st>>>(keys, n, t.node_at, t.d_nnodes, cap, t.nfirst, t.nlevel, t.nend, t.nesc,
                                      ctx->d_status, seg);
     SFCNL_LAUNCHED(ctx);
-    k_children<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nleaf, t.nesc, t.nchild, t.nnchild, ctx->d_status);
+    k_children<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nleaf, t.nesc, t.nchild, t.nnchild, t.cbase, ctx->d_status);
     SFCNL_LAUNCHED(ctx);
     // box hierarchy over the cluster boxes, then exact node boxes
     int64_t sizes[kMaxBoxLevels];
@@ -440,8 +434,6 @@ int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x,
     SFCNL_LAUNCHED(ctx);
     // contiguous child slots (the node count is on the device: scan the
     // capacity, counts past the node count are never read)
-    k_child_count<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nnchild, t.cbase);
-    SFCNL_LAUNCHED(ctx);
     rc = scan_u32(ctx, t.cbase, t.cbase, (int64_t)cap, nullptr, t.scan_tmp);
     if (rc) return rc;
     k_child_slots<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nfirst, t.nend, t.nchild, t.nnchild, t.cbase, t.nbox,

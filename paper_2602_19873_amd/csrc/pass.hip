@@ -16,10 +16,12 @@ namespace {
 
 using namespace passk;
 
-// One wavefront (one super-cluster) per block for the passes: blocks release
-// their slots as soon as their one list is done (7 % faster than four waves
-// per block for the half-list pass).
-constexpr int kPassWaves = 1;
+// Waves (super-clusters) per block of the density passes: a launch-shape
+// knob of the context (sfcnl_set_pass_waves, 1, 2 or 4). One wave per block
+// lets a block release its slots as soon as its one list is done (7 % faster
+// than four for the half-list pass on the uniform benchmark); the batch
+// autotuner times all three.
+constexpr int kPassWavesMax = 4;
 
 struct PassArgs {
     int64_t n;
@@ -36,23 +38,26 @@ struct PassArgs {
     uint32_t gate_max;
 };
 
-// Halved M4 shape written as two clamped cubes: with t = sat(1 - q) and
-// u = sat(1/2 - q) (sat clamps to [0, 1]), t^3 - 4 u^3 equals 1/2 - 3q^2 + 3q^3
-// below q = 1/2, (1-q)^3 up to q = 1 and zero beyond, so a pair outside the
-// radius adds exactly nothing and the sum needs no select. Adds m f(q)/2 to
-// acc for q = r hinv.
+// A quarter of the halved M4 shape as two clamped cubes: with
+// a = sat(c (1 - q)), c = 4^(-1/3), and u = sat(1/2 - q) (sat clamps to
+// [0, 1], a free output modifier), a^3 - u^3 equals (1/2 - 3q^2 + 3q^3) / 4
+// below q = 1/2, (1 - q)^3 / 4 up to q = 1 and zero beyond, so a pair
+// outside the radius adds nothing and the sum needs no select. Adds
+// m f(q) / 8 to acc (f(0) = 1) for q = r hinv, given rc = r c.
+constexpr float kCubeC = 0.62996052494743658f;  // 4^(-1/3)
+
 template <bool kMass>
-__device__ __forceinline__ float add_shape(float acc, float m, float r, float hinv) {
-    const float t = __builtin_amdgcn_fmed3f(__builtin_fmaf(-r, hinv, 1.0f), 0.0f, 1.0f);
+__device__ __forceinline__ float add_shape(float acc, float m, float r, float rc, float hinv) {
+    const float a = __builtin_amdgcn_fmed3f(__builtin_fmaf(-rc, hinv, kCubeC), 0.0f, 1.0f);
     const float u = __builtin_amdgcn_fmed3f(__builtin_fmaf(-r, hinv, 0.5f), 0.0f, 1.0f);
-    const float t2 = t * t;
-    const float u2m = -4.0f * (u * u);
-    if (!kMass) return __builtin_fmaf(u2m, u, __builtin_fmaf(t2, t, acc));
-    return __builtin_fmaf(m, __builtin_fmaf(u2m, u, t2 * t), acc);
+    const float a2 = a * a;
+    const float u2 = u * u;
+    if (!kMass) return __builtin_fmaf(-u2, u, __builtin_fmaf(a2, a, acc));
+    return __builtin_fmaf(m, __builtin_fmaf(a2, a, -(u2 * u)), acc);
 }
 
 // One particle pair of a tile: the own-radius test (the self pair excluded)
-// counts and adds m_j f(q)/2. Folding the self pair into the test measured
+// counts and adds m_j f(q)/8. Folding the self pair into the test measured
 // faster here than masking it off around the call.
 template <bool kMass, bool kPbc>
 __device__ __forceinline__ void tile_pair(float xj, float yj, float zj, float mj, float xi, float yi, float zi,
@@ -66,7 +71,8 @@ __device__ __forceinline__ void tile_pair(float xj, float yj, float zj, float mj
     const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
     const bool in = d2 < h2 && !self_pair;
     if (sfc_ballot(in)) {
-        const float nacc = add_shape<kMass>(acc, mj, __builtin_amdgcn_sqrtf(d2), hinv);
+        const float r = __builtin_amdgcn_sqrtf(d2);
+        const float nacc = add_shape<kMass>(acc, mj, r, r * kCubeC, hinv);
         acc = in ? nacc : acc;
         cnt += in ? 1 : 0;
     }
@@ -85,7 +91,7 @@ __device__ __forceinline__ void tile_pair(float xj, float yj, float zj, float mj
 // form. Cluster size 16 holds four j-particles per lane; under the same cap it
 // spills heavily, so it keeps its own register count.
 template <int CS, bool kCompress, bool kMass, bool kCount, bool kPbc>
-__global__ __launch_bounds__(kWave * kPassWaves) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 1 : 6))) void k_pass(PassArgs a) {
+__global__ __launch_bounds__(kWave * kPassWavesMax) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 1 : 6))) void k_pass(PassArgs a) {
     constexpr int kNsub = kScSize / CS;
     constexpr int kNreg = CS == 8 ? 8 : 4;
     constexpr int kNj = CS == 16 ? 4 : 1;     // j-particles per lane and entry
@@ -93,7 +99,7 @@ __global__ __launch_bounds__(kWave * kPassWaves) __attribute__((amdgpu_waves_per
     const int lane = sfc_lane();
     const int w = threadIdx.x / kWave;
     // wave-uniform: keep the super-cluster index (and all derived from it) scalar
-    const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(blockIdx.x, gridDim.x) * kPassWaves + w));
+    const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x / kWave) + w));
     if (s >= a.nsc || (a.active && !a.active[s]) || (a.gate && *a.gate <= a.gate_max)) return;
     const int64_t n = a.n;
     const int jl = lane & (kGroup - 1);
@@ -112,7 +118,7 @@ __global__ __launch_bounds__(kWave * kPassWaves) __attribute__((amdgpu_waves_per
         ih2[k] = v ? hh * hh : -1.0f;
         ihinv[k] = 1.0f / hh;
     }
-    // acc[k] sums m_j f(q)/2 with f the spline shape (f(0) = 1)
+    // acc[k] sums m_j f(q)/8 with f the spline shape (f(0) = 1)
     float acc[kNreg];
     int cnt_nb[kNreg];
 #pragma unroll
@@ -223,7 +229,7 @@ __global__ __launch_bounds__(kWave * kPassWaves) __attribute__((amdgpu_waves_per
         const float hinv = 1.0f / hh;
         const float mi = kMass ? a.m[io] : 1.0f;
         const float norm = 2.5464790894703255f * hinv * hinv * hinv;  // 8 / pi
-        a.rho[io] = norm * __builtin_fmaf(2.0f, r, mi);
+        a.rho[io] = norm * __builtin_fmaf(8.0f, r, mi);
         if (kCount) a.nnb[io] = nb;
     }
 }
@@ -255,12 +261,13 @@ __device__ __forceinline__ void half_pair(float xj, float yj, float zj, float mj
     cnt_i += d2 < hi2 ? 1 : 0;
     cnt_j += d2 < hj2 ? 1 : 0;
     const float r = __builtin_amdgcn_sqrtf(d2);
-    acc_i = add_shape<kMass>(acc_i, mj, r, hiinv);
-    acc_j = add_shape<kMass>(acc_j, mi, r, hjinv);
+    const float rc = r * kCubeC;
+    acc_i = add_shape<kMass>(acc_i, mj, r, rc, hiinv);
+    acc_j = add_shape<kMass>(acc_j, mi, r, rc, hjinv);
 }
 
 template <int CS, bool kCompress, bool kMass, bool kCount, bool kPbc>
-__global__ __launch_bounds__(kWave * kPassWaves) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 1 : 6))) void k_pass_half(PassArgs a) {
+__global__ __launch_bounds__(kWave * kPassWavesMax) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 1 : 6))) void k_pass_half(PassArgs a) {
     constexpr int kNsub = kScSize / CS;
     constexpr int kNreg = CS == 8 ? 8 : 4;
     constexpr int kNj = CS == 16 ? 4 : 1;
@@ -268,7 +275,7 @@ __global__ __launch_bounds__(kWave * kPassWaves) __attribute__((amdgpu_waves_per
     const int lane = sfc_lane();
     const int w = threadIdx.x / kWave;
     // wave-uniform: keep the super-cluster index (and all derived from it) scalar
-    const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(blockIdx.x, gridDim.x) * kPassWaves + w));
+    const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(blockIdx.x, gridDim.x) * (blockDim.x / kWave) + w));
     if (s >= a.nsc) return;
     const int64_t n = a.n;
     const int jq = CS == 8 ? lane >> 3 : lane >> 4;  // j-particle slot of the lane
@@ -426,7 +433,7 @@ __global__ __launch_bounds__(kWave * kPassWaves) __attribute__((amdgpu_waves_per
     }
 }
 
-// rho_i = 8 / (pi h_i^3) (m_i + 2 S_i), S_i the summed halved shapes.
+// rho_i = 8 / (pi h_i^3) (m_i + 8 S_i), S_i the summed m_j f / 8.
 template <bool kMass>
 __global__ __launch_bounds__(256) void k_pass_finalize(int64_t n, const float *__restrict__ h,
                                                        const float *__restrict__ m, float *__restrict__ rho) {
@@ -434,7 +441,7 @@ __global__ __launch_bounds__(256) void k_pass_finalize(int64_t n, const float *_
     if (i >= n) return;
     const float hinv = 1.0f / h[i];
     const float norm = 2.5464790894703255f * hinv * hinv * hinv;  // 8 / pi
-    rho[i] = norm * __builtin_fmaf(2.0f, rho[i], kMass ? m[i] : 1.0f);
+    rho[i] = norm * __builtin_fmaf(8.0f, rho[i], kMass ? m[i] : 1.0f);
 }
 
 struct DecodeArgs {
@@ -472,48 +479,48 @@ __global__ __launch_bounds__(256) void k_decode(DecodeArgs a) {
 }
 
 template <int CS, bool kPbc>
-void launch_pass(int variant, unsigned g, hipStream_t st, const PassArgs &a) {
+void launch_pass(int variant, unsigned g, unsigned tpb, hipStream_t st, const PassArgs &a) {
     switch (variant) {
-        case 7: k_pass<CS, true, true, true, kPbc><<<g, kWave * kPassWaves, 0, st>>>(a); break;
-        case 6: k_pass<CS, true, true, false, kPbc><<<g, kWave * kPassWaves, 0, st>>>(a); break;
-        case 5: k_pass<CS, true, false, true, kPbc><<<g, kWave * kPassWaves, 0, st>>>(a); break;
-        case 4: k_pass<CS, true, false, false, kPbc><<<g, kWave * kPassWaves, 0, st>>>(a); break;
-        case 3: k_pass<CS, false, true, true, kPbc><<<g, kWave * kPassWaves, 0, st>>>(a); break;
-        case 2: k_pass<CS, false, true, false, kPbc><<<g, kWave * kPassWaves, 0, st>>>(a); break;
-        case 1: k_pass<CS, false, false, true, kPbc><<<g, kWave * kPassWaves, 0, st>>>(a); break;
-        default: k_pass<CS, false, false, false, kPbc><<<g, kWave * kPassWaves, 0, st>>>(a); break;
+        case 7: k_pass<CS, true, true, true, kPbc><<<g, tpb, 0, st>>>(a); break;
+        case 6: k_pass<CS, true, true, false, kPbc><<<g, tpb, 0, st>>>(a); break;
+        case 5: k_pass<CS, true, false, true, kPbc><<<g, tpb, 0, st>>>(a); break;
+        case 4: k_pass<CS, true, false, false, kPbc><<<g, tpb, 0, st>>>(a); break;
+        case 3: k_pass<CS, false, true, true, kPbc><<<g, tpb, 0, st>>>(a); break;
+        case 2: k_pass<CS, false, true, false, kPbc><<<g, tpb, 0, st>>>(a); break;
+        case 1: k_pass<CS, false, false, true, kPbc><<<g, tpb, 0, st>>>(a); break;
+        default: k_pass<CS, false, false, false, kPbc><<<g, tpb, 0, st>>>(a); break;
     }
 }
 
 template <int CS, bool kPbc>
-void launch_pass_half(int variant, unsigned g, hipStream_t st, const PassArgs &a) {
+void launch_pass_half(int variant, unsigned g, unsigned tpb, hipStream_t st, const PassArgs &a) {
     switch (variant) {
-        case 7: k_pass_half<CS, true, true, true, kPbc><<<g, kWave * kPassWaves, 0, st>>>(a); break;
-        case 6: k_pass_half<CS, true, true, false, kPbc><<<g, kWave * kPassWaves, 0, st>>>(a); break;
-        case 5: k_pass_half<CS, true, false, true, kPbc><<<g, kWave * kPassWaves, 0, st>>>(a); break;
-        case 4: k_pass_half<CS, true, false, false, kPbc><<<g, kWave * kPassWaves, 0, st>>>(a); break;
-        case 3: k_pass_half<CS, false, true, true, kPbc><<<g, kWave * kPassWaves, 0, st>>>(a); break;
-        case 2: k_pass_half<CS, false, true, false, kPbc><<<g, kWave * kPassWaves, 0, st>>>(a); break;
-        case 1: k_pass_half<CS, false, false, true, kPbc><<<g, kWave * kPassWaves, 0, st>>>(a); break;
-        default: k_pass_half<CS, false, false, false, kPbc><<<g, kWave * kPassWaves, 0, st>>>(a); break;
+        case 7: k_pass_half<CS, true, true, true, kPbc><<<g, tpb, 0, st>>>(a); break;
+        case 6: k_pass_half<CS, true, true, false, kPbc><<<g, tpb, 0, st>>>(a); break;
+        case 5: k_pass_half<CS, true, false, true, kPbc><<<g, tpb, 0, st>>>(a); break;
+        case 4: k_pass_half<CS, true, false, false, kPbc><<<g, tpb, 0, st>>>(a); break;
+        case 3: k_pass_half<CS, false, true, true, kPbc><<<g, tpb, 0, st>>>(a); break;
+        case 2: k_pass_half<CS, false, true, false, kPbc><<<g, tpb, 0, st>>>(a); break;
+        case 1: k_pass_half<CS, false, false, true, kPbc><<<g, tpb, 0, st>>>(a); break;
+        default: k_pass_half<CS, false, false, false, kPbc><<<g, tpb, 0, st>>>(a); break;
     }
 }
 
 template <bool kPbc>
-void launch_any(int cs, bool half, int variant, unsigned g, hipStream_t st, const PassArgs &a) {
+void launch_any(int cs, bool half, int variant, unsigned g, unsigned tpb, hipStream_t st, const PassArgs &a) {
     if (half) {
         if (cs == 4)
-            launch_pass_half<4, kPbc>(variant, g, st, a);
+            launch_pass_half<4, kPbc>(variant, g, tpb, st, a);
         else if (cs == 16)
-            launch_pass_half<16, kPbc>(variant, g, st, a);
+            launch_pass_half<16, kPbc>(variant, g, tpb, st, a);
         else
-            launch_pass_half<8, kPbc>(variant, g, st, a);
+            launch_pass_half<8, kPbc>(variant, g, tpb, st, a);
     } else if (cs == 4) {
-        launch_pass<4, kPbc>(variant, g, st, a);
+        launch_pass<4, kPbc>(variant, g, tpb, st, a);
     } else if (cs == 16) {
-        launch_pass<16, kPbc>(variant, g, st, a);
+        launch_pass<16, kPbc>(variant, g, tpb, st, a);
     } else {
-        launch_pass<8, kPbc>(variant, g, st, a);
+        launch_pass<8, kPbc>(variant, g, tpb, st, a);
     }
 }
 
@@ -530,7 +537,9 @@ int sfcnl::pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, int half, c
         return set_err(ctx, SFCNL_E_ARG, "nlist_pass: a restricted pass needs the full list");
     PassArgs a{n, (uint32_t)((n + kScSize - 1) / kScSize), d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb,
                seg, per, active, p_active, gate, gate_max};
-    const unsigned g = blocks_for(a.nsc, kPassWaves);
+    const int waves = ctx->pass_waves;
+    const unsigned g = blocks_for(a.nsc, waves);
+    const unsigned tpb = (unsigned)(kWave * waves);
     hipStream_t st = ctx->stream;
     const int variant = (compress ? 4 : 0) | (d_m ? 2 : 0) | (d_nnb ? 1 : 0);
     prof_mark(ctx, kStagePass, false);
@@ -544,9 +553,9 @@ int sfcnl::pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, int half, c
         }
     }
     if (per.on())
-        launch_any<true>(cs, half, variant, g, st, a);
+        launch_any<true>(cs, half, variant, g, tpb, st, a);
     else
-        launch_any<false>(cs, half, variant, g, st, a);
+        launch_any<false>(cs, half, variant, g, tpb, st, a);
     SFCNL_LAUNCHED(ctx);
     if (half) {
         if (d_m)

@@ -1,5 +1,5 @@
 // Device-wide exclusive prefix sum of u32 words (reduce, scan the tile sums,
-// scan tiles again and add), plus a fill kernel.
+// scan tiles again and add; one block for short arrays), plus a fill kernel.
 #include "internal.h"
 
 namespace sfcnl {
@@ -89,6 +89,36 @@ __global__ __launch_bounds__(kThreads) void k_down(const uint32_t *in, uint32_t 
     }
 }
 
+// The whole scan in one block for short arrays: thread t takes a contiguous
+// run of about n / 1024 words (reads it, then writes it, so in == out works).
+constexpr int64_t kSmallScan = int64_t(1) << 16;
+
+__global__ __launch_bounds__(1024) void k_scan_small(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total) {
+    __shared__ uint32_t s_w[1024 / kWave];
+    const int t = threadIdx.x;
+    const int64_t per = (n + 1023) / 1024;
+    const int64_t b0 = t * per < n ? t * per : n, b1 = b0 + per < n ? b0 + per : n;
+    uint32_t acc = 0;
+    for (int64_t b = b0; b < b1; b++) acc += in[b];
+    const int lane = sfc_lane(), w = t / kWave;
+    const uint32_t inc = sfc_incl_scan(acc);
+    if (lane == kWave - 1) s_w[w] = inc;
+    __syncthreads();
+    uint32_t before = 0, all = 0;
+    for (int k = 0; k < 1024 / kWave; k++) {
+        const uint32_t v = s_w[k];
+        if (k < w) before += v;
+        all += v;
+    }
+    uint32_t run = before + inc - acc;
+    for (int64_t b = b0; b < b1; b++) {
+        const uint32_t v = in[b];
+        out[b] = run;
+        run += v;
+    }
+    if (t == 0 && total) *total = all;
+}
+
 __global__ void k_fill(uint32_t *p, int64_t n, uint32_t v) {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < n) p[i] = v;
@@ -101,6 +131,11 @@ size_t scan_tmp_bytes(int64_t n) { return align_up((size_t)(blocks_for(n, kTile)
 int scan_u32(sfcnl_ctx ctx, const uint32_t *in, uint32_t *out, int64_t n, uint32_t *d_total, void *tmp) {
     if (n <= 0) {
         if (d_total) return fill_u32(ctx, d_total, 1, 0);
+        return SFCNL_OK;
+    }
+    if (n <= kSmallScan) {
+        k_scan_small<<<1, 1024, 0, ctx->stream>>>(in, out, n, d_total);
+        SFCNL_LAUNCHED(ctx);
         return SFCNL_OK;
     }
     unsigned nb = blocks_for(n, kTile);

@@ -285,3 +285,27 @@ def test_seeded_batch_matches_single(env, mode):
         assert r1.converged
         np.testing.assert_array_equal(hb[lo:lo + sy.n], h1.cpu().numpy())
         assert res.sys_rounds[s] == r1.iters
+
+
+@pytest.mark.parametrize("max_iters", [3, 6, 7])
+def test_round_limit_with_graph_replays(env, max_iters):
+    """Rounds are replayed several per graph launch; a round limit that cuts
+    through a replay still runs exactly max_iters rounds: the graph run ends
+    with the radii, counts and unconverged total of the run without graphs."""
+    sf, ctx, torch = env
+    T = 60
+    systems = _perturbed(_systems([6000, 300, 9000], T, 950), 951, spread=4.0)
+    b = _batch(sf, ctx, systems)
+    keys, xs, ys, zs, hs = _batch_arrays(sf, ctx, torch, b, systems)
+    h0 = hs.clone()
+    out = {}
+    for use_graph in (True, False):
+        hs.copy_(h0)
+        res = sf.batch_h_iterate(ctx, b, keys, xs, ys, zs, hs, target=T, tol=1, max_iters=max_iters,
+                                 use_graph=use_graph)
+        out[use_graph] = (hs.cpu().numpy(), res.nnb.cpu().numpy(), res.unconverged, res.iters, res.converged)
+    a, c = out[True], out[False]
+    assert a[2:] == c[2:]
+    np.testing.assert_array_equal(a[0], c[0])
+    np.testing.assert_array_equal(a[1], c[1])
+    assert a[3] <= max_iters and (a[4] or a[3] == max_iters)

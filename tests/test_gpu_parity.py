@@ -352,3 +352,71 @@ def test_uniform_2m_sampled(env, half):
     # under max(h_i, h_j): ~190 j-clusters per super-cluster in the full list,
     # ~97 in the half list (each pair once)
     assert g["nl"].bytes_per_particle() < (2.4 if half else 4.25)
+
+
+def test_staging_sized_by_total_length(env):
+    """A Plummer sphere (radii for ~60 neighbours at the local density) whose
+    40 central particles have radius 0.6: the super-clusters holding them list
+    thousands of j-clusters (above 4,096), the others about a hundred. The
+    staging list is sized by the total list length (every super-cluster's
+    first 64-entry chunk plus shared chunks), so the build succeeds with
+    staging room near the mean list length; every pool word equals the
+    oracle's."""
+    sf, ctx, torch = env
+    s = workloads.plummer(40000, 78, target=60.0)
+    r = np.sqrt(s.x.astype(np.float64) ** 2 + s.y ** 2 + s.z ** 2)
+    a = 0.1
+    dens = s.n * 3.0 / (4.0 * np.pi * a ** 3) * (1.0 + r ** 2 / a ** 2) ** -2.5
+    s.h = ((3.0 * 60.0 / (4.0 * np.pi * dens)) ** (1.0 / 3.0)).astype(np.float32)
+    core = np.argsort(r)[:40]
+    s.h[core] = np.float32(0.6)
+    x, y, z, h = (_dev(torch, a) for a in (s.x, s.y, s.z, s.h))
+    keys, perm = sf.sfc_sort(ctx, x, y, z, s.box)
+    xs, ys, zs, hs = sf.sfc_gather(ctx, perm, [x, y, z, h])
+    bbox = sf.build_clusters(ctx, xs, ys, zs, hs)
+    nl = sf.build_nlist(ctx, keys, xs, ys, zs, hs, bbox, max_j_per_sc=64)
+    info = _u32(nl.sc_info)
+    nj = info[:, 1].astype(np.int64)
+    total = int(nj.sum())
+    _say("longest list %d, total %d entries over %d super-clusters; max_j_per_sc grew to %d"
+         % (nj.max(), total, nj.shape[0], nl.max_j_per_sc))
+    assert nj.max() > 4096
+    # staging entries (whole chunks per super-cluster on average) within 1.5x
+    # of the entries the lists hold
+    staging = nj.shape[0] * ((nl.max_j_per_sc + 63) // 64) * 64
+    assert staging * 6 <= 1.5 * total * 6, (staging, total)
+    xa, ya, za, ha = (t.cpu().numpy() for t in (xs, ys, zs, hs))
+    offs, jj, mm = oracle.cluster_list(xa, ya, za, ha, 8, "grid")
+    oinfo, opool = oracle.encode_all(offs, jj, mm, 8, True)
+    np.testing.assert_array_equal(info, oinfo)
+    np.testing.assert_array_equal(_u32(nl.pool)[: nl.used_bytes // 4], opool)
+
+
+@pytest.mark.parametrize("half", [False, True])
+def test_pass_waves_per_block(env, half):
+    """The density pass's workgroup shape (1, 2 or 4 wavefronts per block, the
+    autotuner's knob) changes no result: counts exact, full-list densities
+    bit-identical, half-list densities within the atomics' summation order."""
+    sf, ctx, torch = env
+    s = workloads.uniform_varied(20011, 51, target=100.0)
+    x, y, z, h = (_dev(torch, a) for a in (s.x, s.y, s.z, s.h))
+    keys, perm = sf.sfc_sort(ctx, x, y, z, s.box)
+    xs, ys, zs, hs = sf.sfc_gather(ctx, perm, [x, y, z, h])
+    bbox = sf.build_clusters(ctx, xs, ys, zs, hs)
+    nl = sf.build_nlist(ctx, keys, xs, ys, zs, hs, bbox, half=half)
+    res = {}
+    try:
+        for w in (1, 2, 4):
+            ctx.set_pass_waves(w)
+            r, c = sf.nlist_pass(ctx, nl, xs, ys, zs, hs)
+            res[w] = (r.cpu().numpy(), c.cpu().numpy())
+    finally:
+        ctx.set_pass_waves(1)
+    for w in (2, 4):
+        np.testing.assert_array_equal(res[w][1], res[1][1])
+        if half:
+            np.testing.assert_allclose(res[w][0], res[1][0], rtol=2e-6, atol=0)
+        else:
+            np.testing.assert_array_equal(res[w][0], res[1][0])
+    with pytest.raises(sf.SfcnlError):
+        ctx.set_pass_waves(3)
