@@ -90,6 +90,22 @@ int sfc_sort_workspace(int64_t n, size_t *ws_bytes);
 int sfc_sort(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y, const float *d_z,
              const float *h_box, uint64_t *d_keys_out, uint32_t *d_perm_out, void *d_ws, size_t ws_bytes);
 
+/* sfc_sort without a caller workspace and without any device allocation, for
+ * callers that cannot allocate: code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc. Same arguments, kernels and results
+ * as sfc_sort (bit for bit); the scratch is a fixed device array of the
+ * library (about 13 MiB per GPU, held until the process ends), located once
+ * per device by sfcnl_create.
+ *   n: 0 .. SFCNL_SORT_NOALLOC_MAX_N; larger n returns SFCNL_E_ARG and
+ *     enqueues nothing.
+ * Every call on one GPU shares that array: calls that overlap on one GPU
+ * (contexts on different streams, or host threads) race and must be ordered
+ * by the caller. The array keeps the last call's contents; nothing in it needs
+ * to start at zero. */
+#define SFCNL_SORT_NOALLOC_MAX_N (1 << 20)
+int sfc_sort_noalloc(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y, const float *d_z,
+                     const float *h_box, uint64_t *d_keys_out, uint32_t *d_perm_out);
+
 /* out[f][k] = in[f][perm[k]] for nfields (1..8) float arrays of length n.
  * h_in / h_out are host arrays of device pointers; out must not alias in. */
 int sfc_gather(sfcnl_ctx ctx, int64_t n, const uint32_t *d_perm, int nfields, const float *const *h_in,

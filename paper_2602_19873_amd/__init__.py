@@ -19,7 +19,7 @@ import torch
 
 from . import _lib
 
-__all__ = ["Context", "NeighbourList", "SfcnlError", "sfc_sort", "sfc_gather", "sfc_gather_workspace", "build_clusters",
+__all__ = ["Context", "NeighbourList", "SfcnlError", "sfc_sort", "sfc_sort_noalloc", "sfc_gather", "sfc_gather_workspace", "build_clusters",
            "build_nlist", "nlist_pass", "nlist_decode", "h_iterate", "HIterResult", "Pipeline", "SC_SIZE",
            "CLUSTER_SIZE", "hseed_features", "mlp_init", "mlp_infer", "mlp_grad", "mlp_adam", "mlp_train",
            "MLP_NPARAM", "Batch", "batch_create", "batch_sort", "batch_gather", "batch_build_clusters",
@@ -117,6 +117,22 @@ def sfc_sort(ctx: Context, x, y, z, box, keys=None, perm=None, ws=None):
     ctx.check(ctx.lib.sfc_sort(ctx.handle, n, _ptr(x), _ptr(y), _ptr(z), hb, _ptr(keys), _ptr(perm), _ptr(ws),
                                ws.numel()))
     return keys, perm
+
+
+def sfc_sort_noalloc(ctx: Context, x, y, z, box, keys=None, perm=None):
+    """sfc_sort with the library's fixed device scratch instead of a workspace
+    (n <= SORT_NOALLOC_MAX_N; no device allocation inside the call)."""
+    n = x.numel()
+    for t, nm in ((x, "x"), (y, "y"), (z, "z")):
+        _check_f32(t, n, nm)
+    keys = ctx.empty(n, torch.int64) if keys is None else keys
+    perm = ctx.empty(n, torch.int32) if perm is None else perm
+    hb = (C.c_float * 6)(*[float(v) for v in box])
+    ctx.check(ctx.lib.sfc_sort_noalloc(ctx.handle, n, _ptr(x), _ptr(y), _ptr(z), hb, _ptr(keys), _ptr(perm)))
+    return keys, perm
+
+
+SORT_NOALLOC_MAX_N = _lib.SORT_NOALLOC_MAX_N
 
 
 def sfc_gather_workspace(n: int) -> int:

@@ -20,7 +20,7 @@ E_NOCONV = -5
 
 SYMBOLS = [
     "sfcnl_create", "sfcnl_destroy", "sfcnl_set_stream", "sfcnl_set_pass_waves", "sfcnl_last_error", "sfcnl_sync", "sfcnl_version",
-    "sfc_sort_workspace", "sfc_sort", "sfc_gather", "sfc_gather_workspace", "sfc_gather_ws", "build_clusters",
+    "sfc_sort_workspace", "sfc_sort", "sfc_sort_noalloc", "sfc_gather", "sfc_gather_workspace", "sfc_gather_ws", "build_clusters",
     "build_nlist_workspace", "build_nlist", "build_nlist_async", "build_nlist_result",
     "nlist_pass", "nlist_pass_lj", "build_rows_workspace", "build_rows", "rows_pass", "nlist_decode", "sfcnl_profile_begin", "sfcnl_profile_end", "sfcnl_h_iterate",
     "sfcnl_hseed_features", "sfcnl_mlp_init", "sfcnl_mlp_infer", "sfcnl_mlp_grad_workspace", "sfcnl_mlp_grad",
@@ -30,6 +30,7 @@ SYMBOLS = [
 ]
 
 BATCH_MAX_SYSTEMS = 65535
+SORT_NOALLOC_MAX_N = 1 << 20
 
 MLP_NPARAM = 4801
 HSEED_NFEAT = 8
@@ -96,6 +97,8 @@ def load():
     lib.sfc_sort_workspace.restype = i32
     lib.sfc_sort.argtypes = [vp, i64, vp, vp, vp, C.POINTER(C.c_float), vp, vp, vp, sz]
     lib.sfc_sort.restype = i32
+    lib.sfc_sort_noalloc.argtypes = [vp, i64, vp, vp, vp, C.POINTER(C.c_float), vp, vp]
+    lib.sfc_sort_noalloc.restype = i32
     lib.sfc_gather.argtypes = [vp, i64, vp, i32, C.POINTER(vp), C.POINTER(vp)]
     lib.sfc_gather.restype = i32
     lib.sfc_gather_workspace.argtypes = [i64, C.POINTER(sz)]

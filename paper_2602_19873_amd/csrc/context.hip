@@ -56,6 +56,10 @@ extern "C" int sfcnl_create(sfcnl_ctx *out, int device, void *stream) {
         free(c);
         return SFCNL_E_HIP;
     }
+    if (sort_scratch_setup(device, &c->d_sort_scratch) != SFCNL_OK) {
+        free(c);
+        return SFCNL_E_HIP;
+    }
     if (hipMalloc((void **)&c->d_status, kStWords * sizeof(uint32_t)) != hipSuccess) {
         free(c);
         return SFCNL_E_HIP;

@@ -47,6 +47,8 @@ struct sfcnl_ctx_s {
     uint32_t pend_nsc;
     // waves (super-clusters) per block of the density passes (1, 2 or 4)
     int pass_waves;
+    // device address of sfc_sort_noalloc's scratch array on this device
+    void *d_sort_scratch;
     // stage timing (sfcnl_profile_begin / _end)
     int prof_slots;
     int prof_used[SFCNL_NSTAGE];
@@ -80,7 +82,7 @@ inline void prof_mark(sfcnl_ctx ctx, int stage, bool end) {
 
 inline unsigned blocks_for(int64_t n, int per_block) { return (unsigned)((n + per_block - 1) / per_block); }
 
-inline size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
+constexpr size_t align_up(size_t v, size_t a) { return (v + a - 1) / a * a; }
 
 // Carves aligned sub-buffers out of a caller workspace.
 struct Carver {
@@ -264,6 +266,9 @@ int features_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *keys, const float *x
                   const SegTable &seg);
 // reads the status block into pinned memory (kStWords words) and waits
 int read_status(sfcnl_ctx ctx);
+// Locates sfc_sort_noalloc's fixed device scratch array on the current device
+// (once per device; sort.hip) and returns its device address in *ptr.
+int sort_scratch_setup(int device, void **ptr);
 // build_nlist's sizes and errors from a copied status block (hs)
 // (nsc: super-clusters of the build; on a staging overflow *h_max_nj is the
 // max_j_per_sc that holds every list)

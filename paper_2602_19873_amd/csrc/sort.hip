@@ -1,5 +1,7 @@
 // SFC order of the particles (Sec. II-A): 63-bit Hilbert keys, a stable LSD
 // radix sort of (key, index), and the gather of particle fields.
+#include <mutex>
+
 #include "internal.h"
 
 namespace sfcnl {
@@ -415,21 +417,13 @@ extern "C" int sfc_sort_workspace(int64_t n, size_t *ws_bytes) {
     return SFCNL_OK;
 }
 
-extern "C" int sfc_sort(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y, const float *d_z,
-                        const float *h_box, uint64_t *d_keys_out, uint32_t *d_perm_out, void *d_ws,
-                        size_t ws_bytes) {
-    if (!ctx) return SFCNL_E_ARG;
-    if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "sfc_sort: n=%lld out of range", (long long)n);
-    if (n == 0) return SFCNL_OK;
-    if (!d_x || !d_y || !d_z || !h_box || !d_keys_out || !d_perm_out || !d_ws)
-        return set_err(ctx, SFCNL_E_ARG, "sfc_sort: null pointer");
-    for (int a = 0; a < 3; a++)
-        if (!(h_box[2 * a + 1] > h_box[2 * a]) || !__builtin_isfinite(h_box[2 * a]) || !__builtin_isfinite(h_box[2 * a + 1]))
-            return set_err(ctx, SFCNL_E_ARG, "sfc_sort: box axis %d empty or not finite", a);
-    size_t need;
-    sfc_sort_workspace(n, &need);
-    if (ws_bytes < need)
-        return set_err(ctx, SFCNL_E_ARG, "sfc_sort: workspace %zu bytes < %zu needed", ws_bytes, need);
+namespace sfcnl {
+namespace {
+
+// Keys and the radix passes over a workspace already checked to be large
+// enough (sfc_sort_workspace(n) bytes at d_ws).
+int sort_impl(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y, const float *d_z, const float *h_box,
+              uint64_t *d_keys_out, uint32_t *d_perm_out, void *d_ws) {
     Carver cv{reinterpret_cast<char *>(d_ws), 0};
     SortWs s;
     carve_sort(cv, s, n);
@@ -457,6 +451,80 @@ extern "C" int sfc_sort(sfcnl_ctx ctx, int64_t n, const float *d_x, const float 
     // an even number of passes leaves the result in the output buffers
     prof_mark(ctx, kStageSort, true);
     return SFCNL_OK;
+}
+
+int sort_args(sfcnl_ctx ctx, const char *fn, int64_t n, const float *d_x, const float *d_y, const float *d_z,
+              const float *h_box, uint64_t *d_keys_out, uint32_t *d_perm_out) {
+    if (n < 0 || n >= (int64_t(1) << 31)) return set_err(ctx, SFCNL_E_ARG, "%s: n=%lld out of range", fn, (long long)n);
+    if (n == 0) return SFCNL_OK;
+    if (!d_x || !d_y || !d_z || !h_box || !d_keys_out || !d_perm_out)
+        return set_err(ctx, SFCNL_E_ARG, "%s: null pointer", fn);
+    for (int a = 0; a < 3; a++)
+        if (!(h_box[2 * a + 1] > h_box[2 * a]) || !__builtin_isfinite(h_box[2 * a]) || !__builtin_isfinite(h_box[2 * a + 1]))
+            return set_err(ctx, SFCNL_E_ARG, "%s: box axis %d empty or not finite", fn, a);
+    return SFCNL_OK;
+}
+
+// Workspace of sfc_sort_noalloc: the sort workspace at the largest n it
+// accepts (the carve's sizes with its 256-byte alignment), in a fixed array.
+constexpr size_t ws_bound(int64_t n) {
+    const size_t ntiles = (size_t)((n + kTile - 1) / kTile);
+    return 256 + align_up((size_t)n * 8, 256) + align_up((size_t)n * 4, 256) + align_up(kRadix * ntiles * 4, 256) +
+           align_up(kRadix * 4, 256) + 256;
+}
+constexpr size_t kScratchBytes = ws_bound(SFCNL_SORT_NOALLOC_MAX_N);
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+// Device address of `scratch` per device ordinal (each GPU holds its own copy
+// of the array); looked up once per device, with that device current.
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void *g_scratch_ptr[kMaxDevices];
+
+}  // namespace
+}  // namespace sfcnl
+
+int sfcnl::sort_scratch_setup(int device, void **ptr) {
+    *ptr = nullptr;
+    if (device < 0 || device >= kMaxDevices) return SFCNL_E_ARG;
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void *p = nullptr;
+        if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return SFCNL_E_HIP;
+        g_scratch_ptr[device] = p;
+    }
+    *ptr = g_scratch_ptr[device];
+    return SFCNL_OK;
+}
+
+extern "C" int sfc_sort(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y, const float *d_z,
+                        const float *h_box, uint64_t *d_keys_out, uint32_t *d_perm_out, void *d_ws,
+                        size_t ws_bytes) {
+    if (!ctx) return SFCNL_E_ARG;
+    int rc = sort_args(ctx, "sfc_sort", n, d_x, d_y, d_z, h_box, d_keys_out, d_perm_out);
+    if (rc || n == 0) return rc;
+    if (!d_ws) return set_err(ctx, SFCNL_E_ARG, "sfc_sort: null workspace");
+    size_t need;
+    sfc_sort_workspace(n, &need);
+    if (ws_bytes < need)
+        return set_err(ctx, SFCNL_E_ARG, "sfc_sort: workspace %zu bytes < %zu needed", ws_bytes, need);
+    return sort_impl(ctx, n, d_x, d_y, d_z, h_box, d_keys_out, d_perm_out, d_ws);
+}
+
+extern "C" int sfc_sort_noalloc(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y, const float *d_z,
+                                const float *h_box, uint64_t *d_keys_out, uint32_t *d_perm_out) {
+    if (!ctx) return SFCNL_E_ARG;
+    if (n > SFCNL_SORT_NOALLOC_MAX_N)
+        return set_err(ctx, SFCNL_E_ARG, "sfc_sort_noalloc: n=%lld above the maximum %d of its fixed scratch",
+                       (long long)n, SFCNL_SORT_NOALLOC_MAX_N);
+    int rc = sort_args(ctx, "sfc_sort_noalloc", n, d_x, d_y, d_z, h_box, d_keys_out, d_perm_out);
+    if (rc || n == 0) return rc;
+    if (!ctx->d_sort_scratch) return set_err(ctx, SFCNL_E_HIP, "sfc_sort_noalloc: scratch array not located");
+    size_t need;
+    sfc_sort_workspace(n, &need);
+    if (need > kScratchBytes)  // cannot happen for n within the maximum
+        return set_err(ctx, SFCNL_E_ARG, "sfc_sort_noalloc: needs %zu bytes > %zu", need, kScratchBytes);
+    return sort_impl(ctx, n, d_x, d_y, d_z, h_box, d_keys_out, d_perm_out, ctx->d_sort_scratch);
 }
 
 extern "C" int sfc_gather(sfcnl_ctx ctx, int64_t n, const uint32_t *d_perm, int nfields, const float *const *h_in,
