@@ -101,6 +101,9 @@ struct Carver {
 size_t scan_tmp_bytes(int64_t n);
 // out[i] = sum_{k<i} in[i]; *d_total = sum (may be null). in and out may alias.
 int scan_u32(sfcnl_ctx ctx, const uint32_t *in, uint32_t *out, int64_t n, uint32_t *d_total, void *tmp);
+// The same over the first min(*d_count, cap) words, the count known only on
+// the device (one block; the scan ends at that count, later words untouched).
+int scan_u32_dyn(sfcnl_ctx ctx, const uint32_t *in, uint32_t *out, const uint32_t *d_count, int64_t cap);
 // Fills n u32 words with a value (a kernel, so it can sit inside a captured graph).
 int fill_u32(sfcnl_ctx ctx, uint32_t *p, int64_t n, uint32_t v);
 
@@ -193,15 +196,15 @@ struct Octree {
     uint32_t node_cap;  // capacity of the per-node and child-slot arrays
     // per particle
     int8_t *cdig;      // common 3-bit digits with the previous key (-1 for particle 0)
-    int8_t *lam;       // common digits of key[p] and key[p + bucket] (-1 if out of range)
     int8_t *lleaf;     // octree level of the leaf holding p
     uint32_t *node_at; // index of the first node starting at particle p (leaf starts)
+    uint32_t *blk;     // node counts per block of 256 particles, then their prefix sum
     // per node (capacity: a proven upper bound on the node count)
     uint32_t *nfirst, *nend, *nesc;
     uint8_t *nlevel, *nleaf, *nnchild;
-    uint32_t *nchild;  // 8 per node
-    float4 *nbox;      // 2 per node: lo (x, y, z, hmax), hi (x, y, z, -)
-    uint32_t *cbase;   // first child slot of each node, minus one
+    uint32_t *parent;  // parent node (roots: never read)
+    uint8_t *pidx;     // index among the parent's children
+    uint32_t *cbase;   // child counts, then their prefix sum: first child slot of each node, minus one
     float4 *cs_box;    // child slots: box of the child (2 per slot)
     uint4 *cs_rec;     // child slots: {first, end, child count, first child slot}
     // box hierarchy above the cluster boxes (groups of 8, 64, ... clusters)

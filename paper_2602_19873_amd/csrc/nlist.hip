@@ -391,60 +391,51 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
         prevj = sfc_readlane(ej, (int)cnt - 1);
     };
 
-    // j-particles of candidate cluster cj in the exact-test lane roles; absent
-    // ones (past n) are put far away with a zero radius
-    auto load_j = [&](uint32_t cj, float (&xj)[kNj], float (&yj)[kNj], float (&zj)[kNj], float (&hj)[kNj]) {
-        const int64_t p0 = (int64_t)cj * CS;
-        const float *xb = a.x + p0, *yb = a.y + p0, *zb = a.z + p0, *hb = a.h + p0;
-        if (p0 + CS <= n) {
-#pragma unroll
-            for (int t = 0; t < kNj; t++) {
-                const int q = S::jpart(t, lane);
-                xj[t] = xb[q];
-                yj[t] = yb[q];
-                zj[t] = zb[q];
-                hj[t] = hb[q];
-            }
-        } else {
-#pragma unroll
-            for (int t = 0; t < kNj; t++) {
-                const int q = S::jpart(t, lane);
-                const bool v = p0 + q < n;
-                xj[t] = v ? xb[q] : kFar;
-                yj[t] = v ? yb[q] : kFar;
-                zj[t] = v ? zb[q] : kFar;
-                hj[t] = v ? hb[q] : 0.0f;
-            }
-        }
+    // Exact tests of the queued candidates, in queue order. Lane (q, p) =
+    // (lane / CS, lane % CS) loads particle p of candidate b + q, so one load
+    // per field brings the j-particles of kBatch = 64 / CS candidates, and the
+    // next batch loads while the current one's tiles run; each tile's lanes
+    // then take their j-particle from lane q CS + p with ds_bpermute (a lane
+    // exchange, no memory access). Absent particles (past n) are put far away
+    // with a zero radius; counting lists use the i radius only (a zero j
+    // radius makes max(h_i^2, h_j^2) = h_i^2).
+    constexpr int kBatch = kWave / CS;
+    uint32_t qn = 0;
+    auto load_batch = [&](uint32_t b0, float &bx, float &by, float &bz, float &bh2) {
+        const uint32_t e = b0 + (uint32_t)(lane / CS);
+        const uint32_t cj = e < qn ? queue[e].x : 0u;
+        const int64_t p = (int64_t)cj * CS + (lane & (CS - 1));
+        const bool v = e < qn && p < n;
+        bx = v ? a.x[p] : kFar;
+        by = v ? a.y[p] : kFar;
+        bz = v ? a.z[p] : kFar;
+        const float hh = v && !gather ? a.h[p] : 0.0f;
+        bh2 = hh * hh;
+    };
+    auto lane_f = [](int src, float v) {  // v of lane src (ds_bpermute takes a byte address)
+        return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
     };
 
-    // exact tests of the queued candidates, in queue order: the next entry's
-    // j-particles load while the current entry's tiles run
-    uint32_t qn = 0;
     auto drain = [&]() {
         wave_sync();
-        uint2 qe = queue[0];
-        uint32_t ncj = (uint32_t)__builtin_amdgcn_readfirstlane((int)qe.x);
-        uint32_t ncm = (uint32_t)__builtin_amdgcn_readfirstlane((int)qe.y);
-        float nx[kNj], ny[kNj], nz[kNj], nh[kNj];
-        load_j(ncj, nx, ny, nz, nh);
-        for (uint32_t e = 0; e < qn; e++) {
-            const uint32_t cjv = ncj, cmask = ncm;
+        float bx, by, bz, bh2;
+        load_batch(0, bx, by, bz, bh2);
+        for (uint32_t b0 = 0; b0 < qn; b0 += kBatch) {
+            const float cx = bx, cy = by, cz = bz, ch2 = bh2;
+            if (b0 + kBatch < qn) load_batch(b0 + kBatch, bx, by, bz, bh2);
+            const uint32_t bn = qn - b0 < (uint32_t)kBatch ? qn - b0 : (uint32_t)kBatch;
+            for (uint32_t q = 0; q < bn; q++) {
+            const uint2 qe = queue[b0 + q];
+            const uint32_t cjv = (uint32_t)__builtin_amdgcn_readfirstlane((int)qe.x);
+            const uint32_t cmask = (uint32_t)__builtin_amdgcn_readfirstlane((int)qe.y);
             float xj[kNj], yj[kNj], zj[kNj], hj2[kNj];
 #pragma unroll
             for (int t = 0; t < kNj; t++) {
-                xj[t] = nx[t];
-                yj[t] = ny[t];
-                zj[t] = nz[t];
-                // counting lists use the i radius only: a zero j radius
-                // makes max(h_i^2, h_j^2) = h_i^2
-                hj2[t] = gather ? 0.0f : nh[t] * nh[t];
-            }
-            if (e + 1 < qn) {
-                qe = queue[e + 1];
-                ncj = (uint32_t)__builtin_amdgcn_readfirstlane((int)qe.x);
-                ncm = (uint32_t)__builtin_amdgcn_readfirstlane((int)qe.y);
-                load_j(ncj, nx, ny, nz, nh);
+                const int src = (int)q * CS + S::jpart(t, lane);
+                xj[t] = lane_f(src, cx);
+                yj[t] = lane_f(src, cy);
+                zj[t] = lane_f(src, cz);
+                hj2[t] = lane_f(src, ch2);
             }
             // the j-cluster is one of our own i-clusters: exclude i == j
             // (full list) or keep only j > i (half list)
@@ -536,6 +527,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
                 ej = mine ? cjv - jbase : ej;
                 em = mine ? mask : em;
                 if ((++nj & (kWave - 1)) == 0) flush(kWave);
+            }
             }
         }
         qn = 0;

@@ -49,38 +49,33 @@ __device__ __forceinline__ void seg_range(const SegTable &seg, int64_t p, int64_
     }
 }
 
-__global__ __launch_bounds__(256) void k_digits(const uint64_t *__restrict__ keys, int64_t n, int bucket,
-                                                int8_t *__restrict__ cdig, int8_t *__restrict__ lam, SegTable seg) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (p >= n) return;
+// lam(a): common digits of key[a] and key[a + bucket] when both lie in a's
+// system, else -1 (the window [a, a + bucket] is not one system's).
+__device__ __forceinline__ int window_digits(const uint64_t *__restrict__ keys, int64_t a, int64_t n, int bucket,
+                                             const SegTable &seg) {
+    if (a < 0 || a >= n) return -1;
     int64_t lo, hi;
-    seg_range(seg, p, n, lo, hi);  // systems never share a cell: each starts its own root
-    if (p >= hi) {  // padding: starts no node (cdig >= every leaf level)
-        cdig[p] = 127;
-        lam[p] = -1;
-        return;
-    }
-    uint64_t k = keys[p];
-    cdig[p] = (int8_t)(p == lo ? -1 : sfc_common_digits(keys[p - 1], k));
-    lam[p] = (int8_t)(p + bucket < hi ? sfc_common_digits(k, keys[p + bucket]) : -1);
+    seg_range(seg, a, n, lo, hi);
+    if (a >= hi || a + bucket >= hi) return -1;
+    return sfc_common_digits(keys[a], keys[a + bucket]);
 }
 
 // Leaf level of particle p: one more than the largest lam over the bucket + 1
-// windows [p - bucket, p]. The maximum over that sliding window comes from a
-// doubling table in LDS: after the step of width d, entry k holds the largest
-// of the d values from k on, and two overlapping runs of the largest width
-// d <= bucket + 1 cover the window.
-__global__ __launch_bounds__(256) void k_leaf_level(const int8_t *__restrict__ cdig, const int8_t *__restrict__ lam,
-                                                    int64_t n, int bucket, int8_t *__restrict__ lleaf,
-                                                    uint32_t *__restrict__ cnt) {
+// windows [a, a + bucket] that hold p (a in [p - bucket, p]). The maximum over
+// that sliding window comes from a doubling table in LDS: after the step of
+// width d, entry k holds the largest of the d values from k on, and two
+// overlapping runs of the largest width d <= bucket + 1 cover the window.
+// Also writes the common digits with the previous key (cdig) and the block's
+// node count (nodes start at p for the levels (cdig, leaf level]).
+__global__ __launch_bounds__(256) void k_leaf_level(const uint64_t *__restrict__ keys, int64_t n, int bucket,
+                                                    SegTable seg, int8_t *__restrict__ cdig,
+                                                    int8_t *__restrict__ lleaf, uint32_t *__restrict__ blk) {
     constexpr int kSpan = 256 + kMaxBucket;
     __shared__ int8_t s_tab[2][kSpan];
+    __shared__ uint32_t s_w[256 / kWave];
     const int len = 256 + bucket;
     const int64_t b0 = (int64_t)blockIdx.x * 256;
-    for (int k = threadIdx.x; k < len; k += 256) {
-        const int64_t a = b0 - bucket + k;
-        s_tab[0][k] = (a >= 0 && a < n) ? lam[a] : (int8_t)-1;
-    }
+    for (int k = threadIdx.x; k < len; k += 256) s_tab[0][k] = (int8_t)window_digits(keys, b0 - bucket + k, n, bucket, seg);
     __syncthreads();
     const int win = bucket + 1;
     int d = 1, cur = 0;
@@ -96,30 +91,66 @@ __global__ __launch_bounds__(256) void k_leaf_level(const int8_t *__restrict__ c
         d *= 2;
     }
     const int64_t p = b0 + threadIdx.x;
-    if (p >= n) return;
-    const int u = s_tab[cur][threadIdx.x], v = s_tab[cur][threadIdx.x + win - d];
-    const int m = u > v ? u : v;
-    const int L = m + 1 < kMaxLevel ? m + 1 : kMaxLevel;
-    const int c = cdig[p];
-    lleaf[p] = (int8_t)L;
-    cnt[p] = c < L ? (uint32_t)(L - c) : 0u;
+    uint32_t cnt = 0;
+    if (p < n) {
+        int64_t lo, hi;
+        seg_range(seg, p, n, lo, hi);  // systems never share a cell: each starts its own root
+        int c, L;
+        if (p >= hi) {  // padding: starts no node (cdig >= every leaf level)
+            c = 127;
+            L = 0;
+        } else {
+            c = p == lo ? -1 : sfc_common_digits(keys[p - 1], keys[p]);
+            const int u = s_tab[cur][threadIdx.x], v = s_tab[cur][threadIdx.x + win - d];
+            const int m = u > v ? u : v;
+            L = m + 1 < kMaxLevel ? m + 1 : kMaxLevel;
+            cnt = c < L ? (uint32_t)(L - c) : 0u;
+        }
+        cdig[p] = (int8_t)c;
+        lleaf[p] = (int8_t)L;
+    }
+    // block total of the node counts
+    uint32_t tot = sfc_readlane(sfc_incl_scan(cnt), kWave - 1);
+    if (sfc_lane() == 0) s_w[threadIdx.x / kWave] = tot;
+    __syncthreads();
+    if (threadIdx.x == 0) blk[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
 }
 
+// Node numbers in depth-first pre-order: the prefix of the node counts over
+// the particles (the block's offset from the scanned block totals, plus an
+// exclusive scan inside the block). node_at[p] is the first node starting at
+// p or after it; the nodes starting at p are written.
 __global__ __launch_bounds__(256) void k_emit_nodes(const int8_t *__restrict__ cdig, const int8_t *__restrict__ lleaf,
-                                                    const uint32_t *__restrict__ node_at, int64_t n, uint32_t cap,
-                                                    uint32_t *__restrict__ nfirst, uint8_t *__restrict__ nlevel,
-                                                    uint8_t *__restrict__ nleaf) {
-    int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+                                                    const uint32_t *__restrict__ blk_off, int64_t n, uint32_t cap,
+                                                    uint32_t *__restrict__ node_at, uint32_t *__restrict__ nfirst,
+                                                    uint8_t *__restrict__ nlevel, uint8_t *__restrict__ nleaf) {
+    __shared__ uint32_t s_w[256 / kWave];
+    const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    int c = 0, L = 0;
+    if (p < n) {
+        c = cdig[p];
+        L = lleaf[p];
+    }
+    const uint32_t cnt = c < L ? (uint32_t)(L - c) : 0u;
+    const int lane = sfc_lane(), w = threadIdx.x / kWave;
+    const uint32_t inc = sfc_incl_scan(cnt);
+    if (lane == kWave - 1) s_w[w] = inc;
+    __syncthreads();
+    uint32_t before = blk_off[blockIdx.x];
+    for (int k = 0; k < w; k++) before += s_w[k];
+    uint32_t k = before + inc - cnt;
     if (p >= n) return;
-    int c = cdig[p], L = lleaf[p];
-    if (c >= L) return;
-    uint32_t k = node_at[p];
+    node_at[p] = k;
     for (int l = c + 1; l <= L && k < cap; l++, k++) {
         nfirst[k] = (uint32_t)p;
         nlevel[k] = (uint8_t)l;
         nleaf[k] = (uint8_t)(l == L);
     }
 }
+
+// Kernels over the nodes: the count is only known on the device, so a fixed
+// grid strides over it.
+constexpr unsigned kNodeGrid = 2048;
 
 __global__ __launch_bounds__(256) void k_node_range(const uint64_t *__restrict__ keys, int64_t n,
                                                     const uint32_t *__restrict__ node_at,
@@ -128,56 +159,61 @@ __global__ __launch_bounds__(256) void k_node_range(const uint64_t *__restrict__
                                                     const uint8_t *__restrict__ nlevel, uint32_t *__restrict__ nend,
                                                     uint32_t *__restrict__ nesc, uint32_t *status, SegTable seg) {
     const uint32_t nn = node_count(d_nnodes, cap);
-    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k == 0 && *d_nnodes > cap) atomicOr(&status[kStTree], 1u);
-    if (k >= nn) return;
-    uint32_t f = nfirst[k];
-    int L = nlevel[k];
-    int64_t slo, shi;
-    seg_range(seg, f, n, slo, shi);
-    uint32_t end = (uint32_t)shi;  // a root spans its whole system
-    if (L > 0) {
-        const int shift = 3 * (kMaxLevel - L);
-        const uint64_t pre = keys[f] >> shift;
-        uint32_t lo = f + 1, hi = (uint32_t)shi;
-        while (lo < hi) {
-            uint32_t mid = lo + (hi - lo) / 2;
-            if ((keys[mid] >> shift) == pre)
-                lo = mid + 1;
-            else
-                hi = mid;
+    const uint32_t k0 = blockIdx.x * blockDim.x + threadIdx.x;
+    if (k0 == 0 && *d_nnodes > cap) atomicOr(&status[kStTree], 1u);
+    for (uint32_t k = k0; k < nn; k += gridDim.x * blockDim.x) {
+        uint32_t f = nfirst[k];
+        int L = nlevel[k];
+        int64_t slo, shi;
+        seg_range(seg, f, n, slo, shi);
+        uint32_t end = (uint32_t)shi;  // a root spans its whole system
+        if (L > 0) {
+            const int shift = 3 * (kMaxLevel - L);
+            const uint64_t pre = keys[f] >> shift;
+            uint32_t lo = f + 1, hi = (uint32_t)shi;
+            while (lo < hi) {
+                uint32_t mid = lo + (hi - lo) / 2;
+                if ((keys[mid] >> shift) == pre)
+                    lo = mid + 1;
+                else
+                    hi = mid;
+            }
+            end = lo;
         }
-        end = lo;
+        nend[k] = end;
+        const uint32_t e = end == (uint32_t)n ? nn : node_at[end];
+        nesc[k] = e < nn ? e : nn;
     }
-    nend[k] = end;
-    const uint32_t e = end == (uint32_t)n ? nn : node_at[end];
-    nesc[k] = e < nn ? e : nn;
 }
 
-// Children of every node (up to 8, in key order) and their count, also as
-// u32 in cbase for the prefix sum that places them in child slots.
+// Children of every node (up to 8, in key order, by following escape indices
+// from the next node): each child learns its parent and its index among the
+// siblings; the parent's count goes to cbase for the prefix sum that places
+// the children in child slots.
 __global__ __launch_bounds__(256) void k_children(const uint32_t *__restrict__ d_nnodes, uint32_t cap,
                                                   const uint8_t *__restrict__ nleaf, const uint32_t *__restrict__ nesc,
-                                                  uint32_t *__restrict__ nchild, uint8_t *__restrict__ nnchild,
-                                                  uint32_t *__restrict__ cbase, uint32_t *status) {
+                                                  uint32_t *__restrict__ parent, uint8_t *__restrict__ pidx,
+                                                  uint8_t *__restrict__ nnchild, uint32_t *__restrict__ cbase,
+                                                  uint32_t *status) {
     const uint32_t nn = node_count(d_nnodes, cap);
-    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nn) return;
-    if (nleaf[k]) {
-        nnchild[k] = 0;
-        cbase[k] = 0;
-        return;
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += gridDim.x * blockDim.x) {
+        if (nleaf[k]) {
+            nnchild[k] = 0;
+            cbase[k] = 0;
+            continue;
+        }
+        uint32_t e = nesc[k], c = k + 1;
+        int i = 0;
+        while (c < e && i < 8) {
+            parent[c] = k;
+            pidx[c] = (uint8_t)i;
+            i++;
+            c = nesc[c];
+        }
+        if (c < e || i == 0) atomicOr(&status[kStTree], 2u);  // an octree node has 1..8 children
+        nnchild[k] = (uint8_t)i;
+        cbase[k] = (uint32_t)i;
     }
-    uint32_t e = nesc[k], c = k + 1;
-    int i = 0;
-    while (c < e && i < 8) {
-        nchild[8 * (size_t)k + i] = c;
-        i++;
-        c = nesc[c];
-    }
-    if (c < e || i == 0) atomicOr(&status[kStTree], 2u);  // an octree node has 1..8 children
-    nnchild[k] = (uint8_t)i;
-    cbase[k] = (uint32_t)i;
 }
 
 __device__ __forceinline__ void add_box(float4 &lo, float4 &hi, const float4 l, const float4 u) {
@@ -190,47 +226,56 @@ __device__ __forceinline__ void add_box(float4 &lo, float4 &hi, const float4 l, 
     hi.z = fmaxf(hi.z, u.z);
 }
 
-// One level of the box hierarchy: box b of level l+1 = union of boxes
-// 8b .. 8b+7 of level l.
-__global__ __launch_bounds__(256) void k_box_level(const float4 *__restrict__ below, int64_t nbelow,
-                                                   float4 *__restrict__ above, int64_t nabove) {
-    int64_t b = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (b >= nabove) return;
-    float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
-    float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
-    for (int64_t c = 8 * b; c < 8 * b + 8 && c < nbelow; c++) add_box(lo, hi, below[2 * c], below[2 * c + 1]);
-    above[2 * b] = lo;
-    above[2 * b + 1] = hi;
-}
-
-// Two levels in one launch: each thread forms one box of the level above
-// `below` (as k_box_level), and the block's first 32 threads then join each
-// 8 of those from LDS into the next level (a block covers 256 boxes of the
-// middle level, so 32 of the top one; boxes past the end are empty and join
-// as no-ops).
-__global__ __launch_bounds__(256) void k_box_level2(const float4 *__restrict__ below, int64_t nbelow,
-                                                    float4 *__restrict__ mid, int64_t nmid,
-                                                    float4 *__restrict__ above, int64_t nabove) {
+// Up to three levels of the box hierarchy in one launch: box b of a level =
+// the union of boxes 8b .. 8b+7 of the level below. Each thread forms one box
+// of the first level from `below`; the block's first 32 threads then join
+// each 8 of those (from LDS) into the second level, and its first 4 threads
+// into the third (a block covers 256 boxes of the first level, so 32 of the
+// second and 4 of the third; boxes past a level's end are empty and join as
+// no-ops). nlev (1..3) levels are written.
+__global__ __launch_bounds__(256) void k_box_levels(const float4 *__restrict__ below, int64_t nbelow, int nlev,
+                                                    float4 *__restrict__ l1, int64_t n1, float4 *__restrict__ l2,
+                                                    int64_t n2, float4 *__restrict__ l3, int64_t n3) {
     __shared__ float4 s_lo[256], s_hi[256];
     const int t = threadIdx.x;
     const int64_t b = (int64_t)blockIdx.x * 256 + t;
     float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
     float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
-    if (b < nmid) {
+    if (b < n1) {
         for (int64_t c = 8 * b; c < 8 * b + 8 && c < nbelow; c++) add_box(lo, hi, below[2 * c], below[2 * c + 1]);
-        mid[2 * b] = lo;
-        mid[2 * b + 1] = hi;
+        l1[2 * b] = lo;
+        l1[2 * b + 1] = hi;
     }
+    if (nlev < 2) return;
     s_lo[t] = lo;
     s_hi[t] = hi;
     __syncthreads();
-    const int64_t a = (int64_t)blockIdx.x * 32 + t;
-    if (t < 32 && a < nabove) {
-        float4 l2 = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
-        float4 h2 = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
-        for (int k = 0; k < 8; k++) add_box(l2, h2, s_lo[8 * t + k], s_hi[8 * t + k]);
-        above[2 * a] = l2;
-        above[2 * a + 1] = h2;
+    float4 l2o = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
+    float4 h2o = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+    if (t < 32) {
+        for (int k = 0; k < 8; k++) add_box(l2o, h2o, s_lo[8 * t + k], s_hi[8 * t + k]);
+        const int64_t a = (int64_t)blockIdx.x * 32 + t;
+        if (a < n2) {
+            l2[2 * a] = l2o;
+            l2[2 * a + 1] = h2o;
+        }
+    }
+    if (nlev < 3) return;
+    __syncthreads();
+    if (t < 32) {
+        s_lo[t] = l2o;
+        s_hi[t] = h2o;
+    }
+    __syncthreads();
+    if (t < 4) {
+        float4 l3o = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
+        float4 h3o = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+        for (int k = 0; k < 8; k++) add_box(l3o, h3o, s_lo[8 * t + k], s_hi[8 * t + k]);
+        const int64_t a = (int64_t)blockIdx.x * 4 + t;
+        if (a < n3) {
+            l3[2 * a] = l3o;
+            l3[2 * a + 1] = h3o;
+        }
     }
 }
 
@@ -240,76 +285,70 @@ struct BoxLevels {
     int cshift;  // log2 of the cluster size
 };
 
-__global__ __launch_bounds__(256) void k_node_box(const uint32_t *__restrict__ d_nnodes, uint32_t cap,
-                                                  const uint32_t *__restrict__ nfirst, const uint32_t *__restrict__ nend,
-                                                  const float *__restrict__ x, const float *__restrict__ y,
-                                                  const float *__restrict__ z, const float *__restrict__ h,
-                                                  BoxLevels L, float4 *__restrict__ nbox) {
+// Exact box of every node (the union over its particles, answered by a range
+// query over the box hierarchy: ragged particles at both ends, then whole
+// groups coarsening one level at a time), written with the node's record
+// {first, end, child count (0 = leaf), first child slot} into the node's own
+// child slot: slot 0 for the root, 1 + cbase[parent] + index among the
+// parent's children otherwise (other systems' roots have no slot; their
+// records are kept apart). The traversal reads everything about a child with
+// one round trip.
+__global__ __launch_bounds__(256) void k_node_slots(const uint32_t *__restrict__ d_nnodes, uint32_t cap,
+                                                    const uint32_t *__restrict__ nfirst,
+                                                    const uint32_t *__restrict__ nend,
+                                                    const uint8_t *__restrict__ nlevel,
+                                                    const uint8_t *__restrict__ nnchild,
+                                                    const uint32_t *__restrict__ parent,
+                                                    const uint8_t *__restrict__ pidx, const uint32_t *__restrict__ cbase,
+                                                    const float *__restrict__ x, const float *__restrict__ y,
+                                                    const float *__restrict__ z, const float *__restrict__ h,
+                                                    BoxLevels L, float4 *__restrict__ cs_box,
+                                                    uint4 *__restrict__ cs_rec) {
     const uint32_t nn = node_count(d_nnodes, cap);
-    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nn) return;
-    uint64_t a = nfirst[k], b = nend[k];
-    float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
-    float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
-    // ragged particles at both ends
-    const uint64_t cm = (1u << L.cshift) - 1u;
-    while (a < b && (a & cm)) {
-        add_box(lo, hi, make_float4(x[a], y[a], z[a], h[a]), make_float4(x[a], y[a], z[a], 0.0f));
-        a++;
-    }
-    while (b > a && (b & cm)) {
-        b--;
-        add_box(lo, hi, make_float4(x[b], y[b], z[b], h[b]), make_float4(x[b], y[b], z[b], 0.0f));
-    }
-    // [a, b) is now empty or whole clusters (both ends multiples of cs)
-    a >>= L.cshift;
-    b >>= L.cshift;
-    // whole groups, coarsening one level at a time
-    for (int l = 0; l < L.nlvl && a < b; l++) {
-        const float4 *bx = L.lvl[l];
-        const bool last = l + 1 == L.nlvl;
-        while (a < b && (last || (a & 7u))) {
-            add_box(lo, hi, bx[2 * a], bx[2 * a + 1]);
+    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += gridDim.x * blockDim.x) {
+        uint32_t slot;
+        if (nlevel[k] == 0) {
+            if (k != 0) continue;  // another system's root
+            slot = 0;
+        } else {
+            slot = 1u + cbase[parent[k]] + pidx[k];
+            if (slot >= cap) continue;  // only on a broken tree (reported elsewhere)
+        }
+        const uint32_t first = nfirst[k], end = nend[k];
+        uint64_t a = first, b = end;
+        float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
+        float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
+        // ragged particles at both ends
+        const uint64_t cm = (1u << L.cshift) - 1u;
+        while (a < b && (a & cm)) {
+            add_box(lo, hi, make_float4(x[a], y[a], z[a], h[a]), make_float4(x[a], y[a], z[a], 0.0f));
             a++;
         }
-        while (b > a && (last || (b & 7u))) {
+        while (b > a && (b & cm)) {
             b--;
-            add_box(lo, hi, bx[2 * b], bx[2 * b + 1]);
+            add_box(lo, hi, make_float4(x[b], y[b], z[b], h[b]), make_float4(x[b], y[b], z[b], 0.0f));
         }
-        a >>= 3;
-        b >>= 3;
-    }
-    nbox[2 * (size_t)k] = lo;
-    nbox[2 * (size_t)k + 1] = hi;
-}
-
-// Child slot 0 holds the root; node k's children occupy slots
-// 1 + cbase[k] ... in key order. A slot carries the child's box and its
-// record {first, end, child count (0 = leaf), first child slot}, so the
-// traversal reads everything about a child with one round trip.
-__global__ __launch_bounds__(256) void k_child_slots(const uint32_t *__restrict__ d_nnodes, uint32_t cap,
-                                                     const uint32_t *__restrict__ nfirst,
-                                                     const uint32_t *__restrict__ nend,
-                                                     const uint32_t *__restrict__ nchild,
-                                                     const uint8_t *__restrict__ nnchild,
-                                                     const uint32_t *__restrict__ cbase, const float4 *__restrict__ nbox,
-                                                     float4 *__restrict__ cs_box, uint4 *__restrict__ cs_rec) {
-    const uint32_t nn = node_count(d_nnodes, cap);
-    uint32_t k = blockIdx.x * blockDim.x + threadIdx.x;
-    if (k >= nn) return;
-    if (k == 0) {
-        cs_box[0] = nbox[0];
-        cs_box[1] = nbox[1];
-        cs_rec[0] = make_uint4(nfirst[0], nend[0], nnchild[0], 1u + cbase[0]);
-    }
-    const uint32_t nc = nnchild[k];
-    for (uint32_t i = 0; i < nc; i++) {
-        const uint32_t c = nchild[8 * (size_t)k + i];
-        const uint32_t slot = 1u + cbase[k] + i;
-        if (c >= nn || slot >= cap) continue;  // only on a broken tree (reported elsewhere)
-        cs_box[2 * (size_t)slot] = nbox[2 * (size_t)c];
-        cs_box[2 * (size_t)slot + 1] = nbox[2 * (size_t)c + 1];
-        cs_rec[slot] = make_uint4(nfirst[c], nend[c], nnchild[c], 1u + cbase[c]);
+        // [a, b) is now empty or whole clusters (both ends multiples of cs)
+        a >>= L.cshift;
+        b >>= L.cshift;
+        // whole groups, coarsening one level at a time
+        for (int l = 0; l < L.nlvl && a < b; l++) {
+            const float4 *bx = L.lvl[l];
+            const bool last = l + 1 == L.nlvl;
+            while (a < b && (last || (a & 7u))) {
+                add_box(lo, hi, bx[2 * a], bx[2 * a + 1]);
+                a++;
+            }
+            while (b > a && (last || (b & 7u))) {
+                b--;
+                add_box(lo, hi, bx[2 * b], bx[2 * b + 1]);
+            }
+            a >>= 3;
+            b >>= 3;
+        }
+        cs_box[2 * (size_t)slot] = lo;
+        cs_box[2 * (size_t)slot + 1] = hi;
+        cs_rec[slot] = make_uint4(first, end, nnchild[k], 1u + cbase[k]);
     }
 }
 
@@ -359,17 +398,17 @@ void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket, int nsys, int cs
     size_t nc = node_capacity(n, bucket, nsys);
     t.node_cap = (uint32_t)nc;
     t.cdig = cv.take<int8_t>((size_t)n);
-    t.lam = cv.take<int8_t>((size_t)n);
     t.lleaf = cv.take<int8_t>((size_t)n);
     t.node_at = cv.take<uint32_t>((size_t)n + 1);
+    t.blk = cv.take<uint32_t>((size_t)blocks_for(n, 256) + 1);
     t.nfirst = cv.take<uint32_t>(nc);
     t.nend = cv.take<uint32_t>(nc);
     t.nesc = cv.take<uint32_t>(nc);
     t.nlevel = cv.take<uint8_t>(nc);
     t.nleaf = cv.take<uint8_t>(nc);
     t.nnchild = cv.take<uint8_t>(nc);
-    t.nchild = cv.take<uint32_t>(8 * nc);
-    t.nbox = cv.take<float4>(2 * nc);
+    t.parent = cv.take<uint32_t>(nc);
+    t.pidx = cv.take<uint8_t>(nc);
     t.cbase = cv.take<uint32_t>(nc);
     t.cs_box = cv.take<float4>(2 * nc);
     t.cs_rec = cv.take<uint4>(nc);
@@ -377,7 +416,7 @@ void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket, int nsys, int cs
     t.nboxlvl = box_levels(n, cs, sizes);
     for (int l = 0; l < t.nboxlvl; l++) t.boxlvl[l] = cv.take<float4>(2 * (size_t)sizes[l]);
     t.d_nnodes = cv.take<uint32_t>(4);
-    t.scan_tmp = cv.take<char>(scan_tmp_bytes((int64_t)nc > n + 1 ? (int64_t)nc : n + 1));
+    t.scan_tmp = cv.take<char>(scan_tmp_bytes((int64_t)blocks_for(n, 256) + 1));
 }
 
 int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x, const float *y, const float *z,
@@ -387,25 +426,28 @@ int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x,
     if (B < 1 || B > kMaxBucket) return set_err(ctx, SFCNL_E_ARG, "octree: bucket %d out of range", B);
     hipStream_t st = ctx->stream;
     const unsigned gp = blocks_for(n, 256);
-    k_digits<<<gp, 256, 0, st>>>(keys, n, B, t.cdig, t.lam, seg);
+    // leaf levels and per-block node counts, their prefix sum (the total is
+    // the node count), then the nodes in depth-first pre-order
+    k_leaf_level<<<gp, 256, 0, st>>>(keys, n, B, seg, t.cdig, t.lleaf, t.blk);
     SFCNL_LAUNCHED(ctx);
-    uint32_t *cnt = t.node_at;  // counts, scanned in place
-    k_leaf_level<<<gp, 256, 0, st>>>(t.cdig, t.lam, n, B, t.lleaf, cnt);
-    SFCNL_LAUNCHED(ctx);
-    int rc = scan_u32(ctx, cnt, t.node_at, n, t.d_nnodes, t.scan_tmp);
+    int rc = scan_u32(ctx, t.blk, t.blk, (int64_t)gp, t.d_nnodes, t.scan_tmp);
     if (rc) return rc;
     const uint32_t cap = t.node_cap;
-    k_emit_nodes<<<gp, 256, 0, st>>>(t.cdig, t.lleaf, t.node_at, n, cap, t.nfirst, t.nlevel, t.nleaf);
+    k_emit_nodes<<<gp, 256, 0, st>>>(t.cdig, t.lleaf, t.blk, n, cap, t.node_at, t.nfirst, t.nlevel, t.nleaf);
     SFCNL_LAUNCHED(ctx);
-    // the node count is only known on the device: launch for the proven upper
-    // bound; threads past the count return at once
-    const unsigned gn = blocks_for((int64_t)cap, 256);
+    // the node count is only known on the device: a fixed grid strides over it
+    const unsigned gn = blocks_for((int64_t)cap, 256) < kNodeGrid ? blocks_for((int64_t)cap, 256) : kNodeGrid;
     k_node_range<<<gn, 256, 0, st>>>(keys, n, t.node_at, t.d_nnodes, cap, t.nfirst, t.nlevel, t.nend, t.nesc,
                                      ctx->d_status, seg);
     SFCNL_LAUNCHED(ctx);
-    k_children<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nleaf, t.nesc, t.nchild, t.nnchild, t.cbase, ctx->d_status);
+    k_children<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nleaf, t.nesc, t.parent, t.pidx, t.nnchild, t.cbase,
+                                   ctx->d_status);
     SFCNL_LAUNCHED(ctx);
-    // box hierarchy over the cluster boxes, then exact node boxes
+    // contiguous child slots: prefix sum of the child counts over the nodes
+    rc = scan_u32_dyn(ctx, t.cbase, t.cbase, t.d_nnodes, (int64_t)cap);
+    if (rc) return rc;
+    // box hierarchy over the cluster boxes (three levels per launch), then the
+    // exact node boxes and records in their slots
     int64_t sizes[kMaxBoxLevels];
     const int nl = box_levels(n, t.cs, sizes);
     BoxLevels L;
@@ -414,30 +456,17 @@ int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x,
     L.cshift = t.cs == 4 ? 2 : (t.cs == 16 ? 4 : 3);
     int64_t below = (n + t.cs - 1) / t.cs;
     for (int l = 0; l < nl;) {
-        if (l + 1 < nl) {  // two levels per launch
-            k_box_level2<<<blocks_for(sizes[l], 256), 256, 0, st>>>(L.lvl[l], below, t.boxlvl[l], sizes[l],
-                                                                    t.boxlvl[l + 1], sizes[l + 1]);
-            SFCNL_LAUNCHED(ctx);
-            L.lvl[l + 1] = t.boxlvl[l];
-            L.lvl[l + 2] = t.boxlvl[l + 1];
-            below = sizes[l + 1];
-            l += 2;
-        } else {
-            k_box_level<<<blocks_for(sizes[l], 256), 256, 0, st>>>(L.lvl[l], below, t.boxlvl[l], sizes[l]);
-            SFCNL_LAUNCHED(ctx);
-            L.lvl[l + 1] = t.boxlvl[l];
-            below = sizes[l];
-            l += 1;
-        }
+        const int nlev = nl - l < 3 ? nl - l : 3;
+        k_box_levels<<<blocks_for(sizes[l], 256), 256, 0, st>>>(
+            L.lvl[l], below, nlev, t.boxlvl[l], sizes[l], nlev > 1 ? t.boxlvl[l + 1] : nullptr,
+            nlev > 1 ? sizes[l + 1] : 0, nlev > 2 ? t.boxlvl[l + 2] : nullptr, nlev > 2 ? sizes[l + 2] : 0);
+        SFCNL_LAUNCHED(ctx);
+        for (int k = 0; k < nlev; k++) L.lvl[l + 1 + k] = t.boxlvl[l + k];
+        below = sizes[l + nlev - 1];
+        l += nlev;
     }
-    k_node_box<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nfirst, t.nend, x, y, z, h, L, t.nbox);
-    SFCNL_LAUNCHED(ctx);
-    // contiguous child slots (the node count is on the device: scan the
-    // capacity, counts past the node count are never read)
-    rc = scan_u32(ctx, t.cbase, t.cbase, (int64_t)cap, nullptr, t.scan_tmp);
-    if (rc) return rc;
-    k_child_slots<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nfirst, t.nend, t.nchild, t.nnchild, t.cbase, t.nbox,
-                                      t.cs_box, t.cs_rec);
+    k_node_slots<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nfirst, t.nend, t.nlevel, t.nnchild, t.parent, t.pidx,
+                                     t.cbase, x, y, z, h, L, t.cs_box, t.cs_rec);
     SFCNL_LAUNCHED(ctx);
     if (seg.on()) {
         k_roots<<<blocks_for(seg.nsys, 64), 64, 0, st>>>(seg, t.node_at, t.nfirst, t.nend, t.nnchild, t.cbase,

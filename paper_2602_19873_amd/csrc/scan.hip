@@ -89,34 +89,69 @@ __global__ __launch_bounds__(kThreads) void k_down(const uint32_t *in, uint32_t 
     }
 }
 
-// The whole scan in one block for short arrays: thread t takes a contiguous
-// run of about n / 1024 words (reads it, then writes it, so in == out works).
-constexpr int64_t kSmallScan = int64_t(1) << 16;
+// The whole scan in one block for short arrays, in chunks of 32768 words
+// staged through LDS: a coalesced load of the chunk, then thread t scans the
+// contiguous run [32 t, 32 t + 32) (one padding word after every 32 keeps
+// those runs on distinct banks), then a coalesced store; a carry joins the
+// chunks (in == out works). With d_count the length is min(*d_count, n).
+constexpr int kSmallThreads = 1024;
+constexpr int kSmallPer = 32;
+constexpr int64_t kSmallChunk = (int64_t)kSmallThreads * kSmallPer;
+constexpr int64_t kSmallScan = 4 * kSmallChunk;  // longest static scan done by one block
 
-__global__ __launch_bounds__(1024) void k_scan_small(const uint32_t *in, uint32_t *out, int64_t n, uint32_t *total) {
-    __shared__ uint32_t s_w[1024 / kWave];
+__device__ __forceinline__ int small_slot(int i) { return i + (i >> 5); }
+
+__global__ __launch_bounds__(kSmallThreads) void k_scan_small(const uint32_t *in, uint32_t *out, int64_t n,
+                                                              const uint32_t *d_count, uint32_t *total) {
+    __shared__ uint32_t s_v[kSmallChunk + kSmallChunk / kSmallPer];
+    __shared__ uint32_t s_w[kSmallThreads / kWave];
     const int t = threadIdx.x;
-    const int64_t per = (n + 1023) / 1024;
-    const int64_t b0 = t * per < n ? t * per : n, b1 = b0 + per < n ? b0 + per : n;
-    uint32_t acc = 0;
-    for (int64_t b = b0; b < b1; b++) acc += in[b];
+    if (d_count) {
+        const int64_t c = *d_count;
+        n = c < n ? c : n;
+    }
     const int lane = sfc_lane(), w = t / kWave;
-    const uint32_t inc = sfc_incl_scan(acc);
-    if (lane == kWave - 1) s_w[w] = inc;
-    __syncthreads();
-    uint32_t before = 0, all = 0;
-    for (int k = 0; k < 1024 / kWave; k++) {
-        const uint32_t v = s_w[k];
-        if (k < w) before += v;
-        all += v;
+    uint32_t carry = 0;
+    for (int64_t c0 = 0; c0 < n; c0 += kSmallChunk) {
+        const int m = (int)(n - c0 < kSmallChunk ? n - c0 : kSmallChunk);
+#pragma unroll
+        for (int k = 0; k < kSmallPer; k++) {
+            const int i = k * kSmallThreads + t;
+            s_v[small_slot(i)] = i < m ? in[c0 + i] : 0u;
+        }
+        __syncthreads();
+        uint32_t acc = 0;
+        const int b0 = t * kSmallPer;
+#pragma unroll
+        for (int k = 0; k < kSmallPer; k++) acc += s_v[small_slot(b0 + k)];
+        const uint32_t inc = sfc_incl_scan(acc);
+        if (lane == kWave - 1) s_w[w] = inc;
+        __syncthreads();
+        uint32_t before = 0, all = 0;
+#pragma unroll
+        for (int k = 0; k < kSmallThreads / kWave; k++) {
+            const uint32_t v = s_w[k];
+            if (k < w) before += v;
+            all += v;
+        }
+        uint32_t run = carry + before + inc - acc;
+#pragma unroll
+        for (int k = 0; k < kSmallPer; k++) {
+            const int q = small_slot(b0 + k);
+            const uint32_t v = s_v[q];
+            s_v[q] = run;
+            run += v;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kSmallPer; k++) {
+            const int i = k * kSmallThreads + t;
+            if (i < m) out[c0 + i] = s_v[small_slot(i)];
+        }
+        carry += all;
+        __syncthreads();  // the next chunk overwrites s_v and s_w
     }
-    uint32_t run = before + inc - acc;
-    for (int64_t b = b0; b < b1; b++) {
-        const uint32_t v = in[b];
-        out[b] = run;
-        run += v;
-    }
-    if (t == 0 && total) *total = all;
+    if (t == 0 && total) *total = carry;
 }
 
 __global__ void k_fill(uint32_t *p, int64_t n, uint32_t v) {
@@ -134,7 +169,7 @@ int scan_u32(sfcnl_ctx ctx, const uint32_t *in, uint32_t *out, int64_t n, uint32
         return SFCNL_OK;
     }
     if (n <= kSmallScan) {
-        k_scan_small<<<1, 1024, 0, ctx->stream>>>(in, out, n, d_total);
+        k_scan_small<<<1, kSmallThreads, 0, ctx->stream>>>(in, out, n, nullptr, d_total);
         SFCNL_LAUNCHED(ctx);
         return SFCNL_OK;
     }
@@ -146,6 +181,13 @@ int scan_u32(sfcnl_ctx ctx, const uint32_t *in, uint32_t *out, int64_t n, uint32
     k_top<<<1, 1024, 0, ctx->stream>>>(sums, nb, d_total);
     SFCNL_LAUNCHED(ctx);
     k_down<<<nb, kThreads, 0, ctx->stream>>>(in, out, n, sums);
+    SFCNL_LAUNCHED(ctx);
+    return SFCNL_OK;
+}
+
+int scan_u32_dyn(sfcnl_ctx ctx, const uint32_t *in, uint32_t *out, const uint32_t *d_count, int64_t cap) {
+    if (cap <= 0) return SFCNL_OK;
+    k_scan_small<<<1, kSmallThreads, 0, ctx->stream>>>(in, out, cap, d_count, nullptr);
     SFCNL_LAUNCHED(ctx);
     return SFCNL_OK;
 }
