@@ -84,37 +84,48 @@ __device__ __forceinline__ uint32_t nibbles_of(uint32_t v) { return (32u - (uint
 // ---------------------------------------------------------------------------
 // Clusters: bounding boxes and radius maxima, input checks.
 // ---------------------------------------------------------------------------
+template <int CS>
 __global__ __launch_bounds__(256) void k_cluster_bbox(int64_t n, const float *__restrict__ x,
                                                       const float *__restrict__ y, const float *__restrict__ z,
                                                       const float *__restrict__ h, float4 *__restrict__ bbox,
-                                                      uint32_t *status, SegTable seg, int cs) {
+                                                      uint32_t *status, SegTable seg) {
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (c >= (n + cs - 1) / cs) return;
+    if (c >= (n + CS - 1) / CS) return;
     // batched systems: particles from pend on are padding (NaN, ignored by
     // fminf / fmaxf and never checked)
     int64_t pend = n;
     if (seg.on()) {
-        const int sy = seg.sc_sys[c * cs / kScSize];
+        const int sy = seg.sc_sys[c * CS / kScSize];
         pend = (int64_t)seg.pbase[sy] + seg.count[sy];
+    }
+    // unconditional loads from a clamped index, all in flight together
+    float px[CS], py[CS], pz[CS], ph[CS];
+#pragma unroll
+    for (int k = 0; k < CS; k++) {
+        const int64_t p = c * CS + k;
+        const int64_t q = p < n ? p : n - 1;
+        px[k] = x[q];
+        py[k] = y[q];
+        pz[k] = z[q];
+        ph[k] = h[q];
     }
     float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
     float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
     uint32_t bad = 0;
 #pragma unroll
-    for (int k = 0; k < 16; k++) {
-        int64_t p = c * cs + k;
-        if (k < cs && p < n) {
-            float px = x[p], py = y[p], pz = z[p], ph = h[p];
+    for (int k = 0; k < CS; k++) {
+        const int64_t p = c * CS + k;
+        if (p < n) {
             const bool pad = p >= pend;
-            if (!pad && !(isfinite(px) && isfinite(py) && isfinite(pz))) bad |= 1u;
-            if (!pad && !(isfinite(ph) && ph > 0.0f)) bad |= 2u;
-            lo.x = fminf(lo.x, px);
-            lo.y = fminf(lo.y, py);
-            lo.z = fminf(lo.z, pz);
-            lo.w = fmaxf(lo.w, ph);
-            hi.x = fmaxf(hi.x, px);
-            hi.y = fmaxf(hi.y, py);
-            hi.z = fmaxf(hi.z, pz);
+            if (!pad && !(isfinite(px[k]) && isfinite(py[k]) && isfinite(pz[k]))) bad |= 1u;
+            if (!pad && !(isfinite(ph[k]) && ph[k] > 0.0f)) bad |= 2u;
+            lo.x = fminf(lo.x, px[k]);
+            lo.y = fminf(lo.y, py[k]);
+            lo.z = fminf(lo.z, pz[k]);
+            lo.w = fmaxf(lo.w, ph[k]);
+            hi.x = fmaxf(hi.x, px[k]);
+            hi.y = fmaxf(hi.y, py[k]);
+            hi.z = fmaxf(hi.z, pz[k]);
         }
     }
     bbox[2 * c] = lo;
@@ -556,11 +567,13 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
             // survivors (nonempty i-cluster masks) join the queue in order
             for (int64_t cb = c0; cb <= c1; cb += kSlots) {
                 const int64_t cj = cb + lane / kNsub;
+                // unconditional loads from a clamped index, then the select
+                const int64_t cjc = cj <= c1 ? cj : c1;
+                const float4 l = a.bbox[2 * cjc], u = a.bbox[2 * cjc + 1];
                 float4 blo = empty_lo, bhi = empty_hi;
                 if (cj <= c1) {
-                    const float4 l = a.bbox[2 * cj];
                     blo = make_float4(l.x, l.y, l.z, gather ? 0.0f : l.w);  // own radius only when counting
-                    bhi = a.bbox[2 * cj + 1];
+                    bhi = u;
                 }
                 const uint64_t bal = sfc_ballot(boxes_near<kPbc>(ilo, ihi, blo, bhi, per));
                 if (bal) {
@@ -577,17 +590,15 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
             // lane (ch, g): child ch = lane / 8 of the node against group g's box
             const int ch = lane >> 3;
             const bool act = ch < (int)nchild;
-            const uint32_t slot = cslot + (uint32_t)ch;
-            bool hit = false;
-            uint4 crec = make_uint4(0u, 0u, 0u, 0u);
-            if (act) {
-                const float4 l = a.cs_box[2 * (size_t)slot];
-                const float4 lo = make_float4(l.x, l.y, l.z, gather ? 0.0f : l.w);  // own radius only when counting
-                const float4 hi = a.cs_box[2 * (size_t)slot + 1];
-                crec = a.cs_rec[slot];
-                // a half list never needs a node that ends before the super-cluster
-                hit = boxes_near<kPbc>(glo, ghi, lo, hi, per) && (!half || crec.y > own_p0);
-            }
+            // unconditional loads from a clamped slot (an internal node has
+            // at least one child), then the select
+            const uint32_t slot = cslot + (uint32_t)(act ? ch : 0);
+            const float4 l = a.cs_box[2 * (size_t)slot];
+            const float4 hi = a.cs_box[2 * (size_t)slot + 1];
+            const uint4 crec = a.cs_rec[slot];
+            const float4 lo = make_float4(l.x, l.y, l.z, gather ? 0.0f : l.w);  // own radius only when counting
+            // a half list never needs a node that ends before the super-cluster
+            const bool hit = act && boxes_near<kPbc>(glo, ghi, lo, hi, per) && (!half || crec.y > own_p0);
             const uint32_t keep = nonzero_bytes(sfc_ballot(hit));
             const int cnt = __popc(keep);
             if (sp + cnt > kStackCap) {  // cannot happen in a valid octree (depth <= 21)
@@ -794,8 +805,14 @@ int sfcnl::clusters_impl(sfcnl_ctx ctx, int64_t n, const float *x, const float *
     if (n == 0) return SFCNL_OK;
     const int64_t nclu = (n + cs - 1) / cs;
     prof_mark(ctx, kStageClusters, false);
-    k_cluster_bbox<<<blocks_for(nclu, 256), 256, 0, ctx->stream>>>(n, x, y, z, h, reinterpret_cast<float4 *>(bbox),
-                                                                   ctx->d_status, seg, cs);
+    float4 *b4 = reinterpret_cast<float4 *>(bbox);
+    const unsigned g = blocks_for(nclu, 256);
+    if (cs == 4)
+        k_cluster_bbox<4><<<g, 256, 0, ctx->stream>>>(n, x, y, z, h, b4, ctx->d_status, seg);
+    else if (cs == 16)
+        k_cluster_bbox<16><<<g, 256, 0, ctx->stream>>>(n, x, y, z, h, b4, ctx->d_status, seg);
+    else
+        k_cluster_bbox<8><<<g, 256, 0, ctx->stream>>>(n, x, y, z, h, b4, ctx->d_status, seg);
     SFCNL_LAUNCHED(ctx);
     prof_mark(ctx, kStageClusters, true);
     return SFCNL_OK;

@@ -114,10 +114,21 @@ __global__ __launch_bounds__(kSmallThreads) void k_scan_small(const uint32_t *in
     uint32_t carry = 0;
     for (int64_t c0 = 0; c0 < n; c0 += kSmallChunk) {
         const int m = (int)(n - c0 < kSmallChunk ? n - c0 : kSmallChunk);
+        // unconditional loads from a clamped index (m >= 1), eight in flight
+        // together (more would spill); the select happens afterwards
+#pragma unroll 1
+        for (int g = 0; g < kSmallPer; g += 8) {
+            uint32_t ld[8];
 #pragma unroll
-        for (int k = 0; k < kSmallPer; k++) {
-            const int i = k * kSmallThreads + t;
-            s_v[small_slot(i)] = i < m ? in[c0 + i] : 0u;
+            for (int k = 0; k < 8; k++) {
+                const int i = (g + k) * kSmallThreads + t;
+                ld[k] = in[c0 + (i < m ? i : m - 1)];
+            }
+#pragma unroll
+            for (int k = 0; k < 8; k++) {
+                const int i = (g + k) * kSmallThreads + t;
+                s_v[small_slot(i)] = i < m ? ld[k] : 0u;
+            }
         }
         __syncthreads();
         uint32_t acc = 0;

@@ -125,11 +125,30 @@ __global__ __launch_bounds__(kThreads) void k_hist(const uint64_t *__restrict__ 
     s_h[t] = 0;
     __syncthreads();
     int64_t base = (int64_t)blockIdx.x * kTile;
+    // unconditional loads from a clamped index, all in flight together
+    uint32_t d[kItems];
+    if (dg.sys_off) {
+        uint32_t v[kItems];
 #pragma unroll
-    for (int k = 0; k < kItems; k++) {
-        int64_t i = base + k * kThreads + t;
-        if (i < n) atomicAdd(&s_h[dg(dg.sys_off ? 0ull : keys[i], dg.sys_off ? vals[i] : 0u)], 1u);
+        for (int k = 0; k < kItems; k++) {
+            const int64_t i = base + k * kThreads + t;
+            v[k] = vals[i < n ? i : n - 1];
+        }
+#pragma unroll
+        for (int k = 0; k < kItems; k++) d[k] = dg(0ull, v[k]);
+    } else {
+        uint64_t kk[kItems];
+#pragma unroll
+        for (int k = 0; k < kItems; k++) {
+            const int64_t i = base + k * kThreads + t;
+            kk[k] = keys[i < n ? i : n - 1];
+        }
+#pragma unroll
+        for (int k = 0; k < kItems; k++) d[k] = dg(kk[k], 0u);
     }
+#pragma unroll
+    for (int k = 0; k < kItems; k++)
+        if (base + k * kThreads + t < n) atomicAdd(&s_h[d[k]], 1u);
     __syncthreads();
     hist[(size_t)t * ntiles + blockIdx.x] = s_h[t];
 }
@@ -193,12 +212,19 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
     uint64_t key[kItems];
     uint32_t val[kItems], lrank[kItems];
     const uint64_t lt = sfc_lt_mask();
+    // unconditional loads from a clamped index (tile_n >= 1), all in flight
+    // together
+#pragma unroll
+    for (int k = 0; k < kItems; k++) {
+        const int li = w * (kItems * kWave) + k * kWave + lane;  // striped: wave, item, lane
+        const int lc = li < tile_n ? li : tile_n - 1;
+        key[k] = kin[base + lc];
+        val[k] = vin[base + lc];
+    }
 #pragma unroll
     for (int k = 0; k < kItems; k++) {
         int li = w * (kItems * kWave) + k * kWave + lane;  // striped: wave, item, lane
         bool valid = li < tile_n;
-        key[k] = valid ? kin[base + li] : 0ull;
-        val[k] = valid ? vin[base + li] : 0u;
         uint32_t d = valid ? dg(key[k], val[k]) : 0u;
         uint64_t m = sfc_ballot(valid);
 #pragma unroll
