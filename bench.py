@@ -29,8 +29,9 @@ FP32_PEAK_TFLOPS = 157.3      # 256 CU x 2.4 GHz x 128 FP32 lanes (dual-issue) x
 #   HBM stages: bytes per particle the stage must move at minimum.
 #   ALU stages: FP32 flops (an FMA counts 2) per particle-pair test.
 BYTES_PER_PARTICLE = {
-    "keys": 12 + 8 + 4,            # read x, y, z; write key and index
-    "sort": 8 * (12 + 12) + 8,     # 8 digit passes: read + write key/index; one histogram read
+    "keys": 12 + 8 + 4,            # read x, y, z; write key and index (the first pass's histogram on the way)
+    "sort": 2 * (12 + 12) + 8 + 12 + 12,  # 2 prefix passes: read + write key/index, one histogram read;
+                                          # the local sort reads + writes key/index once
     "gather": 4 + 4 * (4 + 4),     # read perm; read + write x, y, z, h
     "clusters": 16 + 4,            # read x, y, z, h; write 32 B per 8-particle cluster
     "octree": 8 + 4,               # read the sorted keys and the cluster boxes (nodes are ~1/16 of that)
@@ -134,12 +135,12 @@ def source_sha(path):
 
 # Kernels of each stage of a step (for the counter-byte figures).
 STAGE_KERNELS = {
-    "keys": ["k_keys"],
-    "sort": ["k_hist", "k_digit_scan", "k_scatter"],
+    "keys": ["k_keys_hist"],
+    "sort": ["k_hist", "k_digit_scan", "k_scatter", "k_local_sort"],
     "gather": ["k_pack4", "k_gather4"],
     "clusters": ["k_cluster_bbox"],
-    "octree": ["k_digits", "k_leaf_level", "k_emit_nodes", "k_node_range", "k_children", "k_box_level2",
-               "k_node_box", "k_child_count", "k_child_slots"],
+    "octree": ["k_leaf_level", "k_emit_nodes", "k_node_range", "k_children", "k_box_levels",
+               "k_node_slots"],
 }
 
 

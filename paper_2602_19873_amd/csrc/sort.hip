@@ -296,6 +296,339 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
     }
 }
 
+// ---------------------------------------------------------------------------
+// Sort of one system. Two stable counting passes order the particles by the
+// top 16 key bits (digit bits 47..54, then 55..62; the keys kernel also
+// builds the first pass's tile histograms), which leaves runs of equal 16-bit
+// prefixes in input order. One more kernel then sorts every run by the whole
+// key, stably, in LDS: block b takes the runs that begin in particles
+// [b T, b T + T) (the last of them may extend past that range). The result is
+// the stable order by the full key, as eight 8-bit passes would give, in
+// seven launches instead of twenty-five. A run too long for LDS is sorted by
+// one block in passes through global memory.
+// ---------------------------------------------------------------------------
+
+constexpr int kPreShift = 47;      // the runs share key bits 47..62
+constexpr int kLocTile = 2048;     // run starts handled per block
+constexpr int kLocCap = 4096;      // longest range sorted in LDS
+constexpr int kLocItems = kLocCap / kThreads;  // 16 per thread
+
+__device__ __forceinline__ uint64_t key_prefix(uint64_t k) { return k >> kPreShift; }
+
+// Keys and indices as k_keys, plus the tile histograms of key bits 47..54.
+__global__ __launch_bounds__(kThreads) void k_keys_hist(int64_t n, const float *__restrict__ x,
+                                                        const float *__restrict__ y, const float *__restrict__ z,
+                                                        float lox, float sx, float loy, float sy, float loz, float sz,
+                                                        uint64_t *__restrict__ keys, uint32_t *__restrict__ idx,
+                                                        uint32_t ntiles, uint32_t *__restrict__ hist, uint32_t *status) {
+    __shared__ uint32_t s_h[kRadix];
+    const int t = threadIdx.x;
+    s_h[t] = 0;
+    const int64_t base = (int64_t)blockIdx.x * kTile;
+    float px[kItems], py[kItems], pz[kItems];
+#pragma unroll
+    for (int k = 0; k < kItems; k++) {
+        const int64_t i = base + k * kThreads + t;
+        const int64_t ic = i < n ? i : n - 1;
+        px[k] = x[ic];
+        py[k] = y[ic];
+        pz[k] = z[ic];
+    }
+    __syncthreads();
+    bool bad = false;
+#pragma unroll
+    for (int k = 0; k < kItems; k++) {
+        const int64_t i = base + k * kThreads + t;
+        if (i < n) {
+            if (!(isfinite(px[k]) && isfinite(py[k]) && isfinite(pz[k]))) bad = true;
+            const uint64_t key = hilbert_key(quantise(px[k], lox, sx), quantise(py[k], loy, sy), quantise(pz[k], loz, sz));
+            keys[i] = key;
+            idx[i] = (uint32_t)i;
+            atomicAdd(&s_h[(uint32_t)(key >> kPreShift) & 255u], 1u);
+        }
+    }
+    if (bad) atomicOr(&status[kStInputErr], 1u);
+    __syncthreads();
+    hist[(size_t)t * ntiles + blockIdx.x] = s_h[t];
+}
+
+// Stable LSD sort of m <= kLocCap (key, value) pairs held in LDS by bits
+// [0, hb] of the key, 8 bits per pass, with the 256 threads of the block.
+// Element e sits in wave e / 1024, step e / 64 % 16, lane e % 64, so ranking
+// the steps in order and the waves in order keeps equal digits in place.
+__device__ __forceinline__ void lds_radix(uint64_t *sk, uint32_t *sv, int m, int hb, uint32_t (*s_cnt)[kRadix], uint32_t *s_w) {
+    const int t = threadIdx.x, lane = sfc_lane(), w = t / kWave;
+    const uint64_t lt = sfc_lt_mask();
+    for (int lo = 0; lo <= hb; lo += 8) {
+#pragma unroll
+        for (int k = 0; k < kWavesPerBlock; k++) s_cnt[k][t] = 0;
+        uint64_t key[kLocItems];
+        uint32_t val[kLocItems], lrank[kLocItems];
+#pragma unroll
+        for (int k = 0; k < kLocItems; k++) {
+            const int e = w * (kLocItems * kWave) + k * kWave + lane;
+            const int ec = e < m ? e : m - 1;
+            key[k] = sk[ec];
+            val[k] = sv[ec];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kLocItems; k++) {
+            const int e = w * (kLocItems * kWave) + k * kWave + lane;
+            const bool valid = e < m;
+            const uint32_t d = (uint32_t)(key[k] >> lo) & 255u;
+            uint64_t mm = sfc_ballot(valid);
+#pragma unroll
+            for (int b = 0; b < 8; b++) {
+                const bool bit = (d >> b) & 1u;
+                const uint64_t bb = sfc_ballot(valid && bit);
+                mm &= bit ? bb : ~bb;
+            }
+            const uint32_t r = (uint32_t)sfc_popc(mm & lt);
+            const uint32_t before = valid ? s_cnt[w][d] : 0u;
+            __builtin_amdgcn_wave_barrier();
+            lrank[k] = before + r;
+            if (valid && r == 0) s_cnt[w][d] = before + (uint32_t)sfc_popc(mm);
+            __builtin_amdgcn_wave_barrier();
+        }
+        __syncthreads();
+        // digit t: its start over the block, then each wave's start inside it
+        uint32_t c[kWavesPerBlock], tot = 0;
+#pragma unroll
+        for (int k = 0; k < kWavesPerBlock; k++) {
+            c[k] = s_cnt[k][t];
+            tot += c[k];
+        }
+        const uint32_t inc = sfc_incl_scan(tot);
+        if (lane == kWave - 1) s_w[w] = inc;
+        __syncthreads();
+        uint32_t run = inc - tot;
+        for (int k = 0; k < w; k++) run += s_w[k];
+#pragma unroll
+        for (int k = 0; k < kWavesPerBlock; k++) {
+            s_cnt[k][t] = run;
+            run += c[k];
+        }
+        __syncthreads();
+#pragma unroll
+        for (int k = 0; k < kLocItems; k++) {
+            const int e = w * (kLocItems * kWave) + k * kWave + lane;
+            if (e < m) {
+                const uint32_t d = (uint32_t)(key[k] >> lo) & 255u;
+                const uint32_t q = s_cnt[w][d] + lrank[k];
+                sk[q] = key[k];
+                sv[q] = val[k];
+            }
+        }
+        __syncthreads();
+    }
+}
+
+// Highest bit in which the keys of [r0, r1) differ (-1 if all are equal),
+// over the whole block (s_or: one LDS word pair).
+__device__ __forceinline__ int range_diff_bit(const uint64_t *__restrict__ keys, int64_t r0, int64_t r1, unsigned long long *s_or) {
+    const uint64_t k0 = keys[r0];
+    uint64_t acc = 0;
+    for (int64_t i = r0 + threadIdx.x; i < r1; i += kThreads) acc |= keys[i] ^ k0;
+    if (threadIdx.x == 0) *s_or = 0ull;
+    __syncthreads();
+    if (acc) atomicOr(s_or, (unsigned long long)acc);
+    __syncthreads();
+    const uint64_t all = *s_or;
+    __syncthreads();
+    return all ? 63 - __clzll((long long)all) : -1;
+}
+
+// Sorts [r0, r1) (whole runs, at most kLocCap pairs) by the full key in LDS.
+__device__ __forceinline__ void sort_range_lds(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, int64_t r0, int64_t r1,
+                               uint64_t *sk, uint32_t *sv, uint32_t (*s_cnt)[kRadix], uint32_t *s_w,
+                               unsigned long long *s_or) {
+    const int m = (int)(r1 - r0);
+    if (m < 2) return;
+    const int t = threadIdx.x;
+    for (int e = t; e < m; e += kThreads) {
+        sk[e] = keys[r0 + e];
+        sv[e] = vals[r0 + e];
+    }
+    const int hb = range_diff_bit(keys, r0, r1, s_or);
+    if (hb < 0) return;  // equal keys: input order is already the order
+    lds_radix(sk, sv, m, hb, s_cnt, s_w);
+    for (int e = t; e < m; e += kThreads) {
+        keys[r0 + e] = sk[e];
+        vals[r0 + e] = sv[e];
+    }
+}
+
+// Sorts one long run [r0, r1) (equal prefixes, so bits below 47 decide) by one
+// block in stable 8-bit passes through global memory, ping-ponging with the
+// same range of (tk, tv); tiles of kLocCap pairs are ranked in LDS in order.
+__device__ __forceinline__ void sort_range_stream(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                  uint64_t *__restrict__ tk, uint32_t *__restrict__ tv, int64_t r0, int64_t r1,
+                                  uint32_t (*s_cnt)[kRadix], uint32_t *s_w, uint32_t *s_run,
+                                  unsigned long long *s_or) {
+    const int t = threadIdx.x, lane = sfc_lane(), w = t / kWave;
+    const uint64_t lt = sfc_lt_mask();
+    const int hb = range_diff_bit(keys, r0, r1, s_or);
+    if (hb < 0) return;
+    uint64_t *ka = keys, *kb = tk;
+    uint32_t *va = vals, *vb = tv;
+    int npass = 0;
+    for (int lo = 0; lo <= hb; lo += 8, npass++) {
+        // digit totals over the run, then running starts
+        s_run[t] = 0;
+        __syncthreads();
+        for (int64_t i = r0 + t; i < r1; i += kThreads) atomicAdd(&s_run[(uint32_t)(ka[i] >> lo) & 255u], 1u);
+        __syncthreads();
+        {
+            const uint32_t v = s_run[t];
+            const uint32_t inc = sfc_incl_scan(v);
+            if (lane == kWave - 1) s_w[w] = inc;
+            __syncthreads();
+            uint32_t ex = inc - v;
+            for (int k = 0; k < w; k++) ex += s_w[k];
+            __syncthreads();
+            s_run[t] = ex;
+        }
+        for (int64_t c0 = r0; c0 < r1; c0 += kLocCap) {
+            const int m = (int)(r1 - c0 < kLocCap ? r1 - c0 : kLocCap);
+#pragma unroll
+            for (int k = 0; k < kWavesPerBlock; k++) s_cnt[k][t] = 0;
+            __syncthreads();
+            uint64_t key[kLocItems];
+            uint32_t val[kLocItems], lrank[kLocItems];
+#pragma unroll
+            for (int k = 0; k < kLocItems; k++) {
+                const int e = w * (kLocItems * kWave) + k * kWave + lane;
+                const int ec = e < m ? e : m - 1;
+                key[k] = ka[c0 + ec];
+                val[k] = va[c0 + ec];
+            }
+#pragma unroll
+            for (int k = 0; k < kLocItems; k++) {
+                const int e = w * (kLocItems * kWave) + k * kWave + lane;
+                const bool valid = e < m;
+                const uint32_t d = (uint32_t)(key[k] >> lo) & 255u;
+                uint64_t mm = sfc_ballot(valid);
+#pragma unroll
+                for (int b = 0; b < 8; b++) {
+                    const bool bit = (d >> b) & 1u;
+                    const uint64_t bb = sfc_ballot(valid && bit);
+                    mm &= bit ? bb : ~bb;
+                }
+                const uint32_t r = (uint32_t)sfc_popc(mm & lt);
+                const uint32_t before = valid ? s_cnt[w][d] : 0u;
+                __builtin_amdgcn_wave_barrier();
+                lrank[k] = before + r;
+                if (valid && r == 0) s_cnt[w][d] = before + (uint32_t)sfc_popc(mm);
+                __builtin_amdgcn_wave_barrier();
+            }
+            __syncthreads();
+            // digit t: the running start, then each wave's start inside the tile
+            uint32_t c[kWavesPerBlock], tot = 0;
+#pragma unroll
+            for (int k = 0; k < kWavesPerBlock; k++) {
+                c[k] = s_cnt[k][t];
+                tot += c[k];
+            }
+            uint32_t run = s_run[t];
+#pragma unroll
+            for (int k = 0; k < kWavesPerBlock; k++) {
+                s_cnt[k][t] = run;
+                run += c[k];
+            }
+            __syncthreads();
+#pragma unroll
+            for (int k = 0; k < kLocItems; k++) {
+                const int e = w * (kLocItems * kWave) + k * kWave + lane;
+                if (e < m) {
+                    const uint32_t d = (uint32_t)(key[k] >> lo) & 255u;
+                    const int64_t q = r0 + s_cnt[w][d] + lrank[k];
+                    kb[q] = key[k];
+                    vb[q] = val[k];
+                }
+            }
+            __syncthreads();
+            s_run[t] += tot;
+            __syncthreads();
+        }
+        uint64_t *tk2 = ka;
+        ka = kb;
+        kb = tk2;
+        uint32_t *tv2 = va;
+        va = vb;
+        vb = tv2;
+        // the next pass reads what this one wrote (other threads' stores):
+        // a device-scope fence, so that no stale line of the vector cache
+        // serves those reads
+        __threadfence();
+        __syncthreads();
+    }
+    if (npass & 1) {  // the result is in the temporary range: copy it back
+        for (int64_t i = r0 + t; i < r1; i += kThreads) {
+            keys[i] = tk[i];
+            vals[i] = tv[i];
+        }
+    }
+}
+
+__global__ __launch_bounds__(kThreads) void k_local_sort(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals,
+                                                         uint64_t *__restrict__ tk, uint32_t *__restrict__ tv,
+                                                         int64_t n) {
+    __shared__ uint64_t sk[kLocCap];
+    __shared__ uint32_t sv[kLocCap];
+    __shared__ uint32_t s_cnt[kWavesPerBlock][kRadix];
+    __shared__ uint32_t s_run[kRadix];
+    __shared__ uint32_t s_w[kWavesPerBlock];
+    __shared__ unsigned long long s_or;
+    __shared__ uint32_t s_first, s_last, s_end;
+    const int t = threadIdx.x;
+    const int64_t b0 = (int64_t)blockIdx.x * kLocTile;
+    if (b0 >= n) return;
+    const int64_t b1 = b0 + kLocTile < n ? b0 + kLocTile : n;
+    if (t == 0) {
+        s_first = 0xFFFFFFFFu;
+        s_last = 0u;
+        s_end = (uint32_t)b1;
+    }
+    __syncthreads();
+    // the runs that begin in [b0, b1): the first and the last of them
+    for (int64_t i = b0 + t; i < b1; i += kThreads) {
+        const bool start = i == 0 || key_prefix(keys[i]) != key_prefix(keys[i - 1]);
+        if (start) {
+            atomicMin(&s_first, (uint32_t)i);
+            atomicMax(&s_last, (uint32_t)i);
+        }
+    }
+    // the last run ends at the first key past b1 - 1 with a larger prefix
+    if (t == 0 && b1 < n) {
+        const uint64_t p = key_prefix(keys[b1 - 1]);
+        uint32_t lo = (uint32_t)b1, hi = (uint32_t)n;
+        while (lo < hi) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if (key_prefix(keys[mid]) == p)
+                lo = mid + 1;
+            else
+                hi = mid;
+        }
+        s_end = lo;
+    }
+    __syncthreads();
+    if (s_first == 0xFFFFFFFFu) return;  // inside a run that began in an earlier block
+    const int64_t r0 = s_first, rl = s_last, r1 = s_end;
+    if (r1 - r0 <= kLocCap) {
+        sort_range_lds(keys, vals, r0, r1, sk, sv, s_cnt, s_w, &s_or);
+        return;
+    }
+    // too long for LDS: the runs before the last one (fewer than kLocTile
+    // pairs), then the last run alone
+    sort_range_lds(keys, vals, r0, rl, sk, sv, s_cnt, s_w, &s_or);
+    __syncthreads();
+    if (r1 - rl <= kLocCap)
+        sort_range_lds(keys, vals, rl, r1, sk, sv, s_cnt, s_w, &s_or);
+    else
+        sort_range_stream(keys, vals, tk, tv, rl, r1, s_cnt, s_w, s_run, &s_or);
+}
+
 struct GatherArgs {
     const float *in[8];
     float *out[8];
@@ -455,26 +788,26 @@ int sort_impl(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y, cons
     carve_sort(cv, s, n);
 
     hipStream_t st = ctx->stream;
+    const uint32_t ntiles = blocks_for(n, kTile);
+    // keys with the first pass's tile histograms
     prof_mark(ctx, kStageKeys, false);
-    k_keys<<<blocks_for(n, 256), 256, 0, st>>>(n, d_x, d_y, d_z, h_box[0], box_scale(h_box[0], h_box[1]), h_box[2],
-                                               box_scale(h_box[2], h_box[3]), h_box[4], box_scale(h_box[4], h_box[5]),
-                                               d_keys_out, d_perm_out, ctx->d_status);
+    k_keys_hist<<<ntiles, kThreads, 0, st>>>(n, d_x, d_y, d_z, h_box[0], box_scale(h_box[0], h_box[1]), h_box[2],
+                                             box_scale(h_box[2], h_box[3]), h_box[4], box_scale(h_box[4], h_box[5]),
+                                             d_keys_out, d_perm_out, ntiles, s.hist, ctx->d_status);
     SFCNL_LAUNCHED(ctx);
     prof_mark(ctx, kStageKeys, true);
     prof_mark(ctx, kStageSort, false);
-    uint64_t *ka = d_keys_out, *kb = s.ktmp;
-    uint32_t *va = d_perm_out, *vb = s.vtmp;
-    for (int pass = 0; pass < kPasses; pass++) {
-        int rc = radix_pass(ctx, s, ka, va, kb, vb, n, DigitOf{8 * pass, nullptr, 0});
-        if (rc) return rc;
-        uint64_t *tk = ka;
-        ka = kb;
-        kb = tk;
-        uint32_t *tv = va;
-        va = vb;
-        vb = tv;
-    }
-    // an even number of passes leaves the result in the output buffers
+    // stable passes on key bits 47..54, then 55..62 (back into the outputs)
+    const DigitOf lo8{kPreShift, nullptr, 0}, hi8{kPreShift + 8, nullptr, 0};
+    k_digit_scan<<<kRadix, kThreads, 0, st>>>(s.hist, ntiles, s.dtot);
+    SFCNL_LAUNCHED(ctx);
+    k_scatter<<<ntiles, kThreads, 0, st>>>(d_keys_out, d_perm_out, s.ktmp, s.vtmp, n, lo8, ntiles, s.hist, s.dtot);
+    SFCNL_LAUNCHED(ctx);
+    int rc = radix_pass(ctx, s, s.ktmp, s.vtmp, d_keys_out, d_perm_out, n, hi8);
+    if (rc) return rc;
+    // every run of equal 16-bit prefixes by the full key
+    k_local_sort<<<blocks_for(n, kLocTile), kThreads, 0, st>>>(d_keys_out, d_perm_out, s.ktmp, s.vtmp, n);
+    SFCNL_LAUNCHED(ctx);
     prof_mark(ctx, kStageSort, true);
     return SFCNL_OK;
 }
