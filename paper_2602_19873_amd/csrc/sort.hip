@@ -297,38 +297,45 @@ __global__ __launch_bounds__(kThreads) void k_scatter(const uint64_t *__restrict
 }
 
 // ---------------------------------------------------------------------------
-// Sort of one system. Two stable counting passes order the particles by the
-// top 16 key bits (digit bits 47..54, then 55..62; the keys kernel also
-// builds the first pass's tile histograms), which leaves runs of equal 16-bit
-// prefixes in input order. One more kernel then sorts every run by the whole
-// key, stably, in LDS: block b takes the runs that begin in particles
-// [b T, b T + T) (the last of them may extend past that range). The result is
-// the stable order by the full key, as eight 8-bit passes would give, in
-// seven launches instead of twenty-five. A run too long for LDS is sorted by
-// one block in passes through global memory.
+// Sort of one system. Three stable counting passes order the particles by the
+// top 24 key bits (digit bits 39..46, 47..54, 55..62; the keys kernel also
+// builds the first pass's tile histograms), which leaves runs of equal 24-bit
+// prefixes in input order -- mostly single particles, as a prefix is a cell
+// of octree level 8. One more kernel then sorts every longer run by the whole
+// key, stably: block b takes the runs that begin in particles [b T, b T + T)
+// (the last of them may extend past that range). The result is the stable
+// order by the full key, as eight 8-bit passes would give, in ten launches
+// instead of twenty-five. A run too long for LDS is sorted by one block in
+// passes through global memory.
 // ---------------------------------------------------------------------------
 
-constexpr int kPreShift = 47;      // the runs share key bits 47..62
+constexpr int kPreShift = 39;      // the runs share key bits 39..62
 constexpr int kLocTile = 2048;     // run starts handled per block
-constexpr int kLocCap = 4096;      // longest range sorted in LDS
-constexpr int kLocItems = kLocCap / kThreads;  // 16 per thread
+constexpr int kLocCap = 2048;      // longest range sorted in LDS
+constexpr int kLocItems = kLocCap / kThreads;  // 8 per thread
+constexpr int kRankRun = 64;       // runs up to this length are placed by counting
 
 __device__ __forceinline__ uint64_t key_prefix(uint64_t k) { return k >> kPreShift; }
 
-// Keys and indices as k_keys, plus the tile histograms of key bits 47..54.
-__global__ __launch_bounds__(kThreads) void k_keys_hist(int64_t n, const float *__restrict__ x,
-                                                        const float *__restrict__ y, const float *__restrict__ z,
-                                                        float lox, float sx, float loy, float sy, float loz, float sz,
-                                                        uint64_t *__restrict__ keys, uint32_t *__restrict__ idx,
-                                                        uint32_t ntiles, uint32_t *__restrict__ hist, uint32_t *status) {
+// Keys and indices as k_keys, plus the tile histograms of key bits 39..46
+// (a tile of kTile particles per block of 1024 threads, two each).
+constexpr int kKeysThreads = 1024;
+constexpr int kKeysItems = kTile / kKeysThreads;
+
+__global__ __launch_bounds__(kKeysThreads) void k_keys_hist(int64_t n, const float *__restrict__ x,
+                                                            const float *__restrict__ y, const float *__restrict__ z,
+                                                            float lox, float sx, float loy, float sy, float loz,
+                                                            float sz, uint64_t *__restrict__ keys,
+                                                            uint32_t *__restrict__ idx, uint32_t ntiles,
+                                                            uint32_t *__restrict__ hist, uint32_t *status) {
     __shared__ uint32_t s_h[kRadix];
     const int t = threadIdx.x;
-    s_h[t] = 0;
+    if (t < kRadix) s_h[t] = 0;
     const int64_t base = (int64_t)blockIdx.x * kTile;
-    float px[kItems], py[kItems], pz[kItems];
+    float px[kKeysItems], py[kKeysItems], pz[kKeysItems];
 #pragma unroll
-    for (int k = 0; k < kItems; k++) {
-        const int64_t i = base + k * kThreads + t;
+    for (int k = 0; k < kKeysItems; k++) {
+        const int64_t i = base + k * kKeysThreads + t;
         const int64_t ic = i < n ? i : n - 1;
         px[k] = x[ic];
         py[k] = y[ic];
@@ -337,8 +344,8 @@ __global__ __launch_bounds__(kThreads) void k_keys_hist(int64_t n, const float *
     __syncthreads();
     bool bad = false;
 #pragma unroll
-    for (int k = 0; k < kItems; k++) {
-        const int64_t i = base + k * kThreads + t;
+    for (int k = 0; k < kKeysItems; k++) {
+        const int64_t i = base + k * kKeysThreads + t;
         if (i < n) {
             if (!(isfinite(px[k]) && isfinite(py[k]) && isfinite(pz[k]))) bad = true;
             const uint64_t key = hilbert_key(quantise(px[k], lox, sx), quantise(py[k], loy, sy), quantise(pz[k], loz, sz));
@@ -349,7 +356,7 @@ __global__ __launch_bounds__(kThreads) void k_keys_hist(int64_t n, const float *
     }
     if (bad) atomicOr(&status[kStInputErr], 1u);
     __syncthreads();
-    hist[(size_t)t * ntiles + blockIdx.x] = s_h[t];
+    if (t < kRadix) hist[(size_t)t * ntiles + blockIdx.x] = s_h[t];
 }
 
 // Stable LSD sort of m <= kLocCap (key, value) pairs held in LDS by bits
@@ -440,22 +447,77 @@ __device__ __forceinline__ int range_diff_bit(const uint64_t *__restrict__ keys,
 }
 
 // Sorts [r0, r1) (whole runs, at most kLocCap pairs) by the full key in LDS.
-__device__ __forceinline__ void sort_range_lds(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, int64_t r0, int64_t r1,
-                               uint64_t *sk, uint32_t *sv, uint32_t (*s_cnt)[kRadix], uint32_t *s_w,
-                               unsigned long long *s_or) {
+// Runs of up to kRankRun pairs (the common case) are placed by counting:
+// each pair finds its run in LDS and its place in it from the smaller keys
+// and the equal keys before it (which keeps equal keys in input order), and
+// only pairs of runs longer than one are written; all reads come from LDS,
+// so those global writes race with nothing. A range holding a longer run is
+// sorted by the LDS radix passes instead.
+__device__ __forceinline__ void sort_range_lds(uint64_t *__restrict__ keys, uint32_t *__restrict__ vals, int64_t r0,
+                                               int64_t r1, uint64_t *sk, uint32_t *sv, uint32_t (*s_cnt)[kRadix],
+                                               uint32_t *s_w, unsigned long long *s_or) {
     const int m = (int)(r1 - r0);
     if (m < 2) return;
     const int t = threadIdx.x;
-    for (int e = t; e < m; e += kThreads) {
-        sk[e] = keys[r0 + e];
-        sv[e] = vals[r0 + e];
+    {
+        // unconditional loads from a clamped index, all in flight together
+        uint64_t lk[kLocItems];
+        uint32_t lv[kLocItems];
+#pragma unroll
+        for (int k = 0; k < kLocItems; k++) {
+            const int e = k * kThreads + t;
+            const int ec = e < m ? e : m - 1;
+            lk[k] = keys[r0 + ec];
+            lv[k] = vals[r0 + ec];
+        }
+#pragma unroll
+        for (int k = 0; k < kLocItems; k++) {
+            const int e = k * kThreads + t;
+            if (e < m) {
+                sk[e] = lk[k];
+                sv[e] = lv[k];
+            }
+        }
     }
-    const int hb = range_diff_bit(keys, r0, r1, s_or);
-    if (hb < 0) return;  // equal keys: input order is already the order
-    lds_radix(sk, sv, m, hb, s_cnt, s_w);
-    for (int e = t; e < m; e += kThreads) {
-        keys[r0 + e] = sk[e];
-        vals[r0 + e] = sv[e];
+    __syncthreads();
+    int ra[kLocItems], rb[kLocItems];
+    bool longrun = false;
+#pragma unroll
+    for (int k = 0; k < kLocItems; k++) {
+        const int e = k * kThreads + t;
+        int a = e, b = e + 1;
+        if (e < m) {
+            const uint64_t p = key_prefix(sk[e]);
+            while (a > 0 && e - a < kRankRun && key_prefix(sk[a - 1]) == p) a--;
+            while (b < m && b - e <= kRankRun && key_prefix(sk[b]) == p) b++;
+        }
+        ra[k] = a;
+        rb[k] = b;
+        if (b - a > kRankRun) longrun = true;
+    }
+    if (__syncthreads_or(longrun)) {
+        const int hb = range_diff_bit(keys, r0, r1, s_or);
+        if (hb < 0) return;  // equal keys: input order is already the order
+        lds_radix(sk, sv, m, hb, s_cnt, s_w);
+        for (int e = t; e < m; e += kThreads) {
+            keys[r0 + e] = sk[e];
+            vals[r0 + e] = sv[e];
+        }
+        return;
+    }
+#pragma unroll
+    for (int k = 0; k < kLocItems; k++) {
+        const int e = k * kThreads + t;
+        const int a = ra[k], b = rb[k];
+        if (e >= m || b - a == 1) continue;  // a run of one stays where it is
+        const uint64_t key = sk[e];
+        int r = 0;
+        for (int q = a; q < b; q++) {
+            const uint64_t kq = sk[q];
+            r += (kq < key || (kq == key && q < e)) ? 1 : 0;
+        }
+        keys[r0 + a + r] = key;
+        vals[r0 + a + r] = sv[e];
     }
 }
 
@@ -591,26 +653,49 @@ __global__ __launch_bounds__(kThreads) void k_local_sort(uint64_t *__restrict__ 
         s_end = (uint32_t)b1;
     }
     __syncthreads();
-    // the runs that begin in [b0, b1): the first and the last of them
-    for (int64_t i = b0 + t; i < b1; i += kThreads) {
-        const bool start = i == 0 || key_prefix(keys[i]) != key_prefix(keys[i - 1]);
-        if (start) {
-            atomicMin(&s_first, (uint32_t)i);
-            atomicMax(&s_last, (uint32_t)i);
+    // the runs that begin in [b0, b1): the first and the last of them (keys
+    // and their predecessors loaded unconditionally from clamped indices, all
+    // in flight together; one LDS atomic per wave)
+    {
+        uint64_t kc[kLocTile / kThreads], kp[kLocTile / kThreads];
+#pragma unroll
+        for (int k = 0; k < kLocTile / kThreads; k++) {
+            const int64_t i = b0 + k * kThreads + t;
+            const int64_t ic = i < b1 ? i : b1 - 1;
+            kc[k] = keys[ic];
+            kp[k] = keys[ic > 0 ? ic - 1 : 0];
+        }
+        uint32_t first = 0xFFFFFFFFu, last = 0u;
+#pragma unroll
+        for (int k = 0; k < kLocTile / kThreads; k++) {
+            const int64_t i = b0 + k * kThreads + t;
+            const bool start = i < b1 && (i == 0 || key_prefix(kc[k]) != key_prefix(kp[k]));
+            const uint64_t bal = sfc_ballot(start);
+            if (bal) {
+                const int64_t wbase = b0 + k * kThreads + (t & ~(kWave - 1));
+                first = min(first, (uint32_t)(wbase + __ffsll((long long)bal) - 1));
+                last = max(last, (uint32_t)(wbase + 63 - __clzll((long long)bal)));
+            }
+        }
+        if (sfc_lane() == 0) {
+            if (first != 0xFFFFFFFFu) atomicMin(&s_first, first);
+            atomicMax(&s_last, last);
         }
     }
-    // the last run ends at the first key past b1 - 1 with a larger prefix
-    if (t == 0 && b1 < n) {
+    // the last run ends at the first key past b1 - 1 with a larger prefix:
+    // the first wave looks 64 keys at a time (runs are short but for
+    // clustered inputs)
+    if (t < kWave && b1 < n) {
         const uint64_t p = key_prefix(keys[b1 - 1]);
-        uint32_t lo = (uint32_t)b1, hi = (uint32_t)n;
-        while (lo < hi) {
-            const uint32_t mid = lo + (hi - lo) / 2;
-            if (key_prefix(keys[mid]) == p)
-                lo = mid + 1;
-            else
-                hi = mid;
+        for (int64_t c0 = b1; c0 < n; c0 += kWave) {
+            const int64_t i = c0 + t;
+            const uint64_t diff = sfc_ballot(i < n && key_prefix(keys[i < n ? i : n - 1]) != p);
+            if (diff) {
+                if (t == 0) s_end = (uint32_t)(c0 + __ffsll((long long)diff) - 1);
+                break;
+            }
+            if (c0 + kWave >= n && t == 0) s_end = (uint32_t)n;
         }
-        s_end = lo;
     }
     __syncthreads();
     if (s_first == 0xFFFFFFFFu) return;  // inside a run that began in an earlier block
@@ -789,23 +874,25 @@ int sort_impl(sfcnl_ctx ctx, int64_t n, const float *d_x, const float *d_y, cons
 
     hipStream_t st = ctx->stream;
     const uint32_t ntiles = blocks_for(n, kTile);
-    // keys with the first pass's tile histograms
+    // keys (into the temporary buffers) with the first pass's tile histograms
     prof_mark(ctx, kStageKeys, false);
-    k_keys_hist<<<ntiles, kThreads, 0, st>>>(n, d_x, d_y, d_z, h_box[0], box_scale(h_box[0], h_box[1]), h_box[2],
-                                             box_scale(h_box[2], h_box[3]), h_box[4], box_scale(h_box[4], h_box[5]),
-                                             d_keys_out, d_perm_out, ntiles, s.hist, ctx->d_status);
+    k_keys_hist<<<ntiles, kKeysThreads, 0, st>>>(n, d_x, d_y, d_z, h_box[0], box_scale(h_box[0], h_box[1]), h_box[2],
+                                                 box_scale(h_box[2], h_box[3]), h_box[4], box_scale(h_box[4], h_box[5]),
+                                                 s.ktmp, s.vtmp, ntiles, s.hist, ctx->d_status);
     SFCNL_LAUNCHED(ctx);
     prof_mark(ctx, kStageKeys, true);
     prof_mark(ctx, kStageSort, false);
-    // stable passes on key bits 47..54, then 55..62 (back into the outputs)
-    const DigitOf lo8{kPreShift, nullptr, 0}, hi8{kPreShift + 8, nullptr, 0};
+    // stable passes on key bits 39..46, 47..54, 55..62 (the last into the outputs)
+    const DigitOf d0{kPreShift, nullptr, 0}, d1{kPreShift + 8, nullptr, 0}, d2{kPreShift + 16, nullptr, 0};
     k_digit_scan<<<kRadix, kThreads, 0, st>>>(s.hist, ntiles, s.dtot);
     SFCNL_LAUNCHED(ctx);
-    k_scatter<<<ntiles, kThreads, 0, st>>>(d_keys_out, d_perm_out, s.ktmp, s.vtmp, n, lo8, ntiles, s.hist, s.dtot);
+    k_scatter<<<ntiles, kThreads, 0, st>>>(s.ktmp, s.vtmp, d_keys_out, d_perm_out, n, d0, ntiles, s.hist, s.dtot);
     SFCNL_LAUNCHED(ctx);
-    int rc = radix_pass(ctx, s, s.ktmp, s.vtmp, d_keys_out, d_perm_out, n, hi8);
+    int rc = radix_pass(ctx, s, d_keys_out, d_perm_out, s.ktmp, s.vtmp, n, d1);
     if (rc) return rc;
-    // every run of equal 16-bit prefixes by the full key
+    rc = radix_pass(ctx, s, s.ktmp, s.vtmp, d_keys_out, d_perm_out, n, d2);
+    if (rc) return rc;
+    // every run of equal 24-bit prefixes by the full key
     k_local_sort<<<blocks_for(n, kLocTile), kThreads, 0, st>>>(d_keys_out, d_perm_out, s.ktmp, s.vtmp, n);
     SFCNL_LAUNCHED(ctx);
     prof_mark(ctx, kStageSort, true);

@@ -1,7 +1,8 @@
-"""SFC sort (Sec. II-A: Hilbert order) on inputs that drive its long-run path:
-particles packed into one cell of the top 16 key bits (so one run is longer
-than the LDS capacity and is sorted by one block through global memory, with
-an even or an odd number of passes), such a cluster inside a uniform
+"""SFC sort (Sec. II-A: Hilbert order) on inputs that drive its long-run paths:
+particles packed into cells of the top 24 key bits (octree level 8), so that
+runs of equal prefixes are longer than a count-placed run (sorted by LDS radix
+passes) or than the LDS capacity (sorted by one block through global memory,
+with an even or an odd number of passes), such clusters inside a uniform
 background, and all particles at one point. Keys and order must equal the
 oracle's keys and a stable argsort of them, bit for bit."""
 import numpy as np
@@ -44,20 +45,21 @@ def _check(sf, ctx, pts):
     assert np.array_equal(keys.cpu().numpy().view(np.uint64), ko[po])
 
 
-def test_one_long_run_even_passes(env):
-    # a cube of side 2^-7 inside one level-6 cell: the top 16 bits agree, the
-    # keys differ below bit ~42 (six 8-bit passes)
+def test_long_runs_odd_passes(env):
+    # one level-7 cell filled: eight runs of ~7,500 (its level-8 cells), keys
+    # differing in bits 0..38 (five passes, the result copied back from the
+    # temporary range)
     sf, ctx = env
     rng = np.random.default_rng(7001)
     _check(sf, ctx, _cluster(rng, 60_000, (0.3125, 0.5, 0.1875), 2.0 ** -7))
 
 
-def test_one_long_run_odd_passes(env):
-    # one level-10 cell filled: keys differ only in bits 0..32 (five passes,
-    # the result copied back from the temporary range)
+def test_one_long_run_even_passes(env):
+    # one level-11 cell filled: one run, keys differing in bits 0..29 (four
+    # passes)
     sf, ctx = env
     rng = np.random.default_rng(7002)
-    _check(sf, ctx, _cluster(rng, 9_000, (0.625, 0.25, 0.75), 2.0 ** -10))
+    _check(sf, ctx, _cluster(rng, 9_000, (0.625, 0.25, 0.75), 2.0 ** -11))
 
 
 def test_long_runs_in_uniform_background(env):
@@ -66,7 +68,10 @@ def test_long_runs_in_uniform_background(env):
     pts = np.concatenate([rng.random((3, 70_000)).astype(np.float32),
                           _cluster(rng, 20_000, (0.5, 0.5, 0.5), 2.0 ** -8),
                           _cluster(rng, 5_000, (0.125, 0.875, 0.25), 2.0 ** -9),
-                          _cluster(rng, 4_100, (0.0625, 0.0625, 0.9375), 2.0 ** -10)], axis=1)
+                          _cluster(rng, 4_100, (0.0625, 0.0625, 0.9375), 2.0 ** -10),
+                          _cluster(rng, 1_500, (0.75, 0.125, 0.5), 2.0 ** -9),
+                          _cluster(rng, 100, (0.875, 0.625, 0.0625), 2.0 ** -12),
+                          _cluster(rng, 65, (0.25, 0.375, 0.625), 2.0 ** -12)], axis=1)
     pts = pts[:, rng.permutation(pts.shape[1])]
     _check(sf, ctx, np.ascontiguousarray(pts))
 
