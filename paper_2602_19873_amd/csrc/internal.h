@@ -106,6 +106,8 @@ int scan_u32(sfcnl_ctx ctx, const uint32_t *in, uint32_t *out, int64_t n, uint32
 int scan_u32_dyn(sfcnl_ctx ctx, const uint32_t *in, uint32_t *out, const uint32_t *d_count, int64_t cap);
 // Fills n u32 words with a value (a kernel, so it can sit inside a captured graph).
 int fill_u32(sfcnl_ctx ctx, uint32_t *p, int64_t n, uint32_t v);
+// The same over two arrays of n words in one launch (q may be null).
+int fill2_u32(sfcnl_ctx ctx, uint32_t *p, uint32_t *q, int64_t n, uint32_t v);
 
 // ---- batched systems ----
 // Several independent systems laid out one after another from padded bases

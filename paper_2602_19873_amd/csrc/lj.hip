@@ -470,12 +470,10 @@ extern "C" int nlist_pass_lj(sfcnl_ctx ctx, int64_t n, int cluster_size, int com
     prof_mark(ctx, kStagePass, false);
     if (half) {
         // accumulators start at zero (fill kernels, so the call can sit in a graph)
-        float *outs[4] = {d_fx, d_fy, d_fz, d_epot};
-        for (float *o : outs) {
-            if (!o) continue;
-            const int rc = fill_u32(ctx, reinterpret_cast<uint32_t *>(o), n, 0u);
-            if (rc) return rc;
-        }
+        int rc = fill2_u32(ctx, reinterpret_cast<uint32_t *>(d_fx), reinterpret_cast<uint32_t *>(d_fy), n, 0u);
+        if (rc) return rc;
+        rc = fill2_u32(ctx, reinterpret_cast<uint32_t *>(d_fz), reinterpret_cast<uint32_t *>(d_epot), n, 0u);
+        if (rc) return rc;
     }
     if (a.per.on())
         launch_lj_any<true>(cluster_size, half, variant, g, st, a);

@@ -647,6 +647,8 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_encode(EncArgs a) {
     const int w = threadIdx.x / kWave;
     // wave-uniform: keep the super-cluster index (and all derived from it) scalar
     const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w));
+    // the pool total (the scan's last entry) into the status block
+    if (blockIdx.x == 0 && threadIdx.x == 0) a.status[kStTotalLo] = a.sc_off[a.nsc];
     if (s >= a.nsc) return;
     const uint32_t nj = a.sc_nj[s];
     const uint32_t off = a.sc_off[s];
@@ -725,8 +727,6 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_encode(EncArgs a) {
         prevj = sfc_readlane(j, (int)cnt - 1);
     }
 }
-
-__global__ void k_finish(const uint32_t *total, uint32_t *status) { status[kStTotalLo] = *total; }
 
 struct NlistWs {
     Octree tree;
@@ -944,8 +944,6 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     k_encode<<<gb, kWave * kWavesPerBlock, 0, st>>>(ea);
     SFCNL_LAUNCHED(ctx);
     prof_mark(ctx, kStageEncode, true);
-    k_finish<<<1, 1, 0, st>>>(ws.sc_off + nsc, ctx->d_status);
-    SFCNL_LAUNCHED(ctx);
     if (!readback) return SFCNL_OK;
 
     rc = read_status(ctx);

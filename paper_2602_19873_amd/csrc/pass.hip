@@ -545,12 +545,8 @@ int sfcnl::pass_impl(sfcnl_ctx ctx, int64_t n, int cs, int compress, int half, c
     prof_mark(ctx, kStagePass, false);
     if (half) {
         // accumulators start at zero (fill kernels, so the call can sit in a graph)
-        int rc = fill_u32(ctx, reinterpret_cast<uint32_t *>(d_rho), n, 0u);
+        int rc = fill2_u32(ctx, reinterpret_cast<uint32_t *>(d_rho), reinterpret_cast<uint32_t *>(d_nnb), n, 0u);
         if (rc) return rc;
-        if (d_nnb) {
-            rc = fill_u32(ctx, reinterpret_cast<uint32_t *>(d_nnb), n, 0u);
-            if (rc) return rc;
-        }
     }
     if (per.on())
         launch_any<true>(cs, half, variant, g, tpb, st, a);

@@ -117,7 +117,7 @@ __global__ __launch_bounds__(kSmallThreads) void k_scan_small(const uint32_t *in
         // unconditional loads from a clamped index (m >= 1), eight in flight
         // together (more would spill); the select happens afterwards
 #pragma unroll 1
-        for (int g = 0; g < kSmallPer; g += 8) {
+        for (int g = 0; g < kSmallPer && g * kSmallThreads < m; g += 8) {
             uint32_t ld[8];
 #pragma unroll
             for (int k = 0; k < 8; k++) {
@@ -129,6 +129,12 @@ __global__ __launch_bounds__(kSmallThreads) void k_scan_small(const uint32_t *in
                 const int i = (g + k) * kSmallThreads + t;
                 s_v[small_slot(i)] = i < m ? ld[k] : 0u;
             }
+        }
+        // groups past the end hold zeros
+#pragma unroll 1
+        for (int g = ((m + 8 * kSmallThreads - 1) / (8 * kSmallThreads)) * 8; g < kSmallPer; g += 8) {
+#pragma unroll
+            for (int k = 0; k < 8; k++) s_v[small_slot((g + k) * kSmallThreads + t)] = 0u;
         }
         __syncthreads();
         uint32_t acc = 0;
@@ -170,6 +176,15 @@ __global__ void k_fill(uint32_t *p, int64_t n, uint32_t v) {
     if (i < n) p[i] = v;
 }
 
+// Two arrays of n words at once (q may be null).
+__global__ void k_fill2(uint32_t *p, uint32_t *q, int64_t n, uint32_t v) {
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) {
+        p[i] = v;
+        if (q) q[i] = v;
+    }
+}
+
 }  // namespace
 
 size_t scan_tmp_bytes(int64_t n) { return align_up((size_t)(blocks_for(n, kTile) + 1) * 4, 256); }
@@ -206,6 +221,13 @@ int scan_u32_dyn(sfcnl_ctx ctx, const uint32_t *in, uint32_t *out, const uint32_
 int fill_u32(sfcnl_ctx ctx, uint32_t *p, int64_t n, uint32_t v) {
     if (n <= 0) return SFCNL_OK;
     k_fill<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(p, n, v);
+    SFCNL_LAUNCHED(ctx);
+    return SFCNL_OK;
+}
+
+int fill2_u32(sfcnl_ctx ctx, uint32_t *p, uint32_t *q, int64_t n, uint32_t v) {
+    if (n <= 0) return SFCNL_OK;
+    k_fill2<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(p, q, n, v);
     SFCNL_LAUNCHED(ctx);
     return SFCNL_OK;
 }
