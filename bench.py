@@ -30,8 +30,8 @@ FP32_PEAK_TFLOPS = 157.3      # 256 CU x 2.4 GHz x 128 FP32 lanes (dual-issue) x
 #   ALU stages: FP32 flops (an FMA counts 2) per particle-pair test.
 BYTES_PER_PARTICLE = {
     "keys": 12 + 8 + 4,            # read x, y, z; write key and index (the first pass's histogram on the way)
-    "sort": 2 * (12 + 12) + 8 + 12 + 12,  # 2 prefix passes: read + write key/index, one histogram read;
-                                          # the local sort reads + writes key/index once
+    "sort": 3 * (12 + 12) + 2 * 8 + 12,  # 3 prefix passes: read + write key/index, two histogram reads of
+                                         # the keys; the local sort reads key/index once (rewrites ~1.5 %)
     "gather": 4 + 4 * (4 + 4),     # read perm; read + write x, y, z, h
     "clusters": 16 + 4,            # read x, y, z, h; write 32 B per 8-particle cluster
     "octree": 8 + 4,               # read the sorted keys and the cluster boxes (nodes are ~1/16 of that)
