@@ -219,6 +219,11 @@ struct Octree {
 void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket, int nsys, int cs);
 int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x, const float *y,
                  const float *z, const float *h, const float4 *cluster_box, const SegTable &seg);
+// The two halves of octree_build: the nodes, ranges and child slots from the
+// sorted keys alone, then the node boxes from the cluster boxes and particles.
+int octree_topology(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const SegTable &seg);
+int octree_geometry(sfcnl_ctx ctx, Octree &t, const float *x, const float *y, const float *z, const float *h,
+                    const float4 *cluster_box, const SegTable &seg);
 
 // build_nlist without argument checks; `readback` waits for the stream and
 // reports capacity and input errors (otherwise the flags stay on the device).

@@ -994,6 +994,23 @@ extern "C" int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, con
                             pool_bytes, SegTable{}, true, h_used_bytes, h_max_nj);
 }
 
+// The async build's bookkeeping: the status block copied behind the work,
+// an event marking the copy.
+static int mark_pending(sfcnl_ctx ctx, int64_t n, const sfcnl_nlist_opts *opts, size_t pool_bytes) {
+    if (n > 0) {
+        SFCNL_HIP(ctx, hipMemcpyAsync(ctx->h_pend, ctx->d_status, kStWords * sizeof(uint32_t),
+                                      hipMemcpyDeviceToHost, ctx->stream));
+    } else {
+        memset(ctx->h_pend, 0, kStWords * sizeof(uint32_t));
+    }
+    SFCNL_HIP(ctx, hipEventRecord(ctx->ev_pend, ctx->stream));
+    ctx->pend = 1;
+    ctx->pend_pool_bytes = pool_bytes;
+    ctx->pend_max_j = opts->max_j_per_sc;
+    ctx->pend_nsc = (uint32_t)((n + kScSize - 1) / kScSize);
+    return SFCNL_OK;
+}
+
 extern "C" int build_nlist_async(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_x,
                                  const float *d_y, const float *d_z, const float *d_h, const float *d_bbox,
                                  const sfcnl_nlist_opts *opts, void *d_ws, size_t ws_bytes, uint32_t *d_sc_info,
@@ -1011,17 +1028,8 @@ extern "C" int build_nlist_async(sfcnl_ctx ctx, int64_t n, const uint64_t *d_key
         rc = nlist_build_impl(ctx, n, d_keys, d_x, d_y, d_z, d_h, d_bbox, *opts, d_ws, ws_bytes, d_sc_info, d_pool,
                               pool_bytes, SegTable{}, false, &used, &maxnj);
         if (rc) return rc;
-        SFCNL_HIP(ctx, hipMemcpyAsync(ctx->h_pend, ctx->d_status, kStWords * sizeof(uint32_t),
-                                      hipMemcpyDeviceToHost, ctx->stream));
-    } else {
-        memset(ctx->h_pend, 0, kStWords * sizeof(uint32_t));
     }
-    SFCNL_HIP(ctx, hipEventRecord(ctx->ev_pend, ctx->stream));
-    ctx->pend = 1;
-    ctx->pend_pool_bytes = pool_bytes;
-    ctx->pend_max_j = opts->max_j_per_sc;
-    ctx->pend_nsc = (uint32_t)((n + kScSize - 1) / kScSize);
-    return SFCNL_OK;
+    return mark_pending(ctx, n, opts, pool_bytes);
 }
 
 extern "C" int build_nlist_result(sfcnl_ctx ctx, size_t *h_used_bytes, int64_t *h_max_nj) {

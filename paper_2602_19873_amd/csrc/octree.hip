@@ -49,16 +49,8 @@ __device__ __forceinline__ void seg_range(const SegTable &seg, int64_t p, int64_
     }
 }
 
-// lam(a): common digits of key[a] and key[a + bucket] when both lie in a's
-// system, else -1 (the window [a, a + bucket] is not one system's).
-__device__ __forceinline__ int window_digits(const uint64_t *__restrict__ keys, int64_t a, int64_t n, int bucket,
-                                             const SegTable &seg) {
-    if (a < 0 || a >= n) return -1;
-    int64_t lo, hi;
-    seg_range(seg, a, n, lo, hi);
-    if (a >= hi || a + bucket >= hi) return -1;
-    return sfc_common_digits(keys[a], keys[a + bucket]);
-}
+// lam(a) below: the common digits of key[a] and key[a + bucket] when both lie
+// in a's system, else -1 (the window [a, a + bucket] is not one system's).
 
 // Leaf level of particle p: one more than the largest lam over the bucket + 1
 // windows [a, a + bucket] that hold p (a in [p - bucket, p]). The maximum over
@@ -75,7 +67,33 @@ __global__ __launch_bounds__(256) void k_leaf_level(const uint64_t *__restrict__
     __shared__ uint32_t s_w[256 / kWave];
     const int len = 256 + bucket;
     const int64_t b0 = (int64_t)blockIdx.x * 256;
-    for (int k = threadIdx.x; k < len; k += 256) s_tab[0][k] = (int8_t)window_digits(keys, b0 - bucket + k, n, bucket, seg);
+    {
+        // the window entries (len <= 512: two per thread) and the own key with
+        // its predecessor, loaded unconditionally from clamped indices so that
+        // they are in flight together
+        uint64_t ka[2], kb[2];
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+            const int64_t a = b0 - bucket + r * 256 + threadIdx.x;
+            const int64_t ac = a < 0 ? 0 : (a >= n ? n - 1 : a);
+            const int64_t bc = a + bucket < 0 ? 0 : (a + bucket >= n ? n - 1 : a + bucket);
+            ka[r] = keys[ac];
+            kb[r] = keys[bc];
+        }
+#pragma unroll
+        for (int r = 0; r < 2; r++) {
+            const int k = r * 256 + threadIdx.x;
+            if (k >= len) continue;
+            const int64_t a = b0 - bucket + k;
+            int lam = -1;
+            if (a >= 0 && a < n) {
+                int64_t lo, hi;
+                seg_range(seg, a, n, lo, hi);
+                if (a < hi && a + bucket < hi) lam = sfc_common_digits(ka[r], kb[r]);
+            }
+            s_tab[0][k] = (int8_t)lam;
+        }
+    }
     __syncthreads();
     const int win = bucket + 1;
     int d = 1, cur = 0;
@@ -391,6 +409,12 @@ static int box_levels(int64_t n, int cs, int64_t *sizes) {
     return nl;
 }
 
+// Grid of the kernels over nodes (they stride over the device-side count).
+static unsigned node_grid(const Octree &t) {
+    const unsigned g = blocks_for((int64_t)t.node_cap, 256);
+    return g < kNodeGrid ? g : kNodeGrid;
+}
+
 void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket, int nsys, int cs) {
     t.n = n;
     t.bucket = bucket;
@@ -419,8 +443,7 @@ void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket, int nsys, int cs
     t.scan_tmp = cv.take<char>(scan_tmp_bytes((int64_t)blocks_for(n, 256) + 1));
 }
 
-int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x, const float *y, const float *z,
-                 const float *h, const float4 *cluster_box, const SegTable &seg) {
+int octree_topology(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const SegTable &seg) {
     const int64_t n = t.n;
     const int B = t.bucket;
     if (B < 1 || B > kMaxBucket) return set_err(ctx, SFCNL_E_ARG, "octree: bucket %d out of range", B);
@@ -436,7 +459,7 @@ int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x,
     k_emit_nodes<<<gp, 256, 0, st>>>(t.cdig, t.lleaf, t.blk, n, cap, t.node_at, t.nfirst, t.nlevel, t.nleaf);
     SFCNL_LAUNCHED(ctx);
     // the node count is only known on the device: a fixed grid strides over it
-    const unsigned gn = blocks_for((int64_t)cap, 256) < kNodeGrid ? blocks_for((int64_t)cap, 256) : kNodeGrid;
+    const unsigned gn = node_grid(t);
     k_node_range<<<gn, 256, 0, st>>>(keys, n, t.node_at, t.d_nnodes, cap, t.nfirst, t.nlevel, t.nend, t.nesc,
                                      ctx->d_status, seg);
     SFCNL_LAUNCHED(ctx);
@@ -444,8 +467,15 @@ int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x,
                                    ctx->d_status);
     SFCNL_LAUNCHED(ctx);
     // contiguous child slots: prefix sum of the child counts over the nodes
-    rc = scan_u32_dyn(ctx, t.cbase, t.cbase, t.d_nnodes, (int64_t)cap);
-    if (rc) return rc;
+    return scan_u32_dyn(ctx, t.cbase, t.cbase, t.d_nnodes, (int64_t)cap);
+}
+
+int octree_geometry(sfcnl_ctx ctx, Octree &t, const float *x, const float *y, const float *z, const float *h,
+                    const float4 *cluster_box, const SegTable &seg) {
+    const int64_t n = t.n;
+    hipStream_t st = ctx->stream;
+    const uint32_t cap = t.node_cap;
+    const unsigned gn = node_grid(t);
     // box hierarchy over the cluster boxes (three levels per launch), then the
     // exact node boxes and records in their slots
     int64_t sizes[kMaxBoxLevels];
@@ -474,6 +504,13 @@ int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x,
         SFCNL_LAUNCHED(ctx);
     }
     return SFCNL_OK;
+}
+
+int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x, const float *y, const float *z,
+                 const float *h, const float4 *cluster_box, const SegTable &seg) {
+    const int rc = octree_topology(ctx, t, keys, seg);
+    if (rc) return rc;
+    return octree_geometry(ctx, t, x, y, z, h, cluster_box, seg);
 }
 
 }  // namespace sfcnl
