@@ -84,7 +84,7 @@ __device__ __forceinline__ uint32_t nibbles_of(uint32_t v) { return (32u - (uint
 // ---------------------------------------------------------------------------
 // Clusters: bounding boxes and radius maxima, input checks.
 // ---------------------------------------------------------------------------
-template <int CS>
+template <int CS, bool kVec>
 __global__ __launch_bounds__(256) void k_cluster_bbox(int64_t n, const float *__restrict__ x,
                                                       const float *__restrict__ y, const float *__restrict__ z,
                                                       const float *__restrict__ h, float4 *__restrict__ bbox,
@@ -98,16 +98,34 @@ __global__ __launch_bounds__(256) void k_cluster_bbox(int64_t n, const float *__
         const int sy = seg.sc_sys[c * CS / kScSize];
         pend = (int64_t)seg.pbase[sy] + seg.count[sy];
     }
-    // unconditional loads from a clamped index, all in flight together
+    // a whole cluster of 16-byte-aligned fields comes as CS / 4 float4 loads
+    // per field (one request per 16 bytes instead of one per 4); the last,
+    // partial cluster or unaligned fields read each particle from a clamped
+    // index; all loads are in flight together
     float px[CS], py[CS], pz[CS], ph[CS];
+    if (kVec && c * CS + CS <= n) {
+        const float4 *x4 = reinterpret_cast<const float4 *>(x) + c * (CS / 4);
+        const float4 *y4 = reinterpret_cast<const float4 *>(y) + c * (CS / 4);
+        const float4 *z4 = reinterpret_cast<const float4 *>(z) + c * (CS / 4);
+        const float4 *h4 = reinterpret_cast<const float4 *>(h) + c * (CS / 4);
 #pragma unroll
-    for (int k = 0; k < CS; k++) {
-        const int64_t p = c * CS + k;
-        const int64_t q = p < n ? p : n - 1;
-        px[k] = x[q];
-        py[k] = y[q];
-        pz[k] = z[q];
-        ph[k] = h[q];
+        for (int q = 0; q < CS / 4; q++) {
+            const float4 vx = x4[q], vy = y4[q], vz = z4[q], vh = h4[q];
+            px[4 * q] = vx.x, px[4 * q + 1] = vx.y, px[4 * q + 2] = vx.z, px[4 * q + 3] = vx.w;
+            py[4 * q] = vy.x, py[4 * q + 1] = vy.y, py[4 * q + 2] = vy.z, py[4 * q + 3] = vy.w;
+            pz[4 * q] = vz.x, pz[4 * q + 1] = vz.y, pz[4 * q + 2] = vz.z, pz[4 * q + 3] = vz.w;
+            ph[4 * q] = vh.x, ph[4 * q + 1] = vh.y, ph[4 * q + 2] = vh.z, ph[4 * q + 3] = vh.w;
+        }
+    } else {
+#pragma unroll
+        for (int k = 0; k < CS; k++) {
+            const int64_t p = c * CS + k;
+            const int64_t q = p < n ? p : n - 1;
+            px[k] = x[q];
+            py[k] = y[q];
+            pz[k] = z[q];
+            ph[k] = h[q];
+        }
     }
     float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
     float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
@@ -673,8 +691,12 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_encode(EncArgs a) {
     for (uint32_t b0 = 0; b0 < nj; b0 += kWave) {
         const uint32_t cnt = nj - b0 < (uint32_t)kWave ? nj - b0 : (uint32_t)kWave;
         const bool valid = (uint32_t)lane < cnt;
-        const uint32_t j = valid ? a.list_j[(size_t)chunk * kWave + lane] : 0u;
-        const uint32_t m = valid ? (uint32_t)a.list_m[(size_t)chunk * kWave + lane] : 0u;
+        // every lane of a 64-entry chunk is inside the staging arrays: the
+        // loads go out unconditionally, the select follows
+        const uint32_t jl = a.list_j[(size_t)chunk * kWave + lane];
+        const uint32_t ml = (uint32_t)a.list_m[(size_t)chunk * kWave + lane];
+        const uint32_t j = valid ? jl : 0u;
+        const uint32_t m = valid ? ml : 0u;
         if (b0 + kWave < nj) chunk = a.chunk_next[chunk];
         // masks of this block: 4 (or 2) consecutive entries per word
         if (a.mask_bytes == 1) {
@@ -807,12 +829,19 @@ int sfcnl::clusters_impl(sfcnl_ctx ctx, int64_t n, const float *x, const float *
     prof_mark(ctx, kStageClusters, false);
     float4 *b4 = reinterpret_cast<float4 *>(bbox);
     const unsigned g = blocks_for(nclu, 256);
-    if (cs == 4)
-        k_cluster_bbox<4><<<g, 256, 0, ctx->stream>>>(n, x, y, z, h, b4, ctx->d_status, seg);
-    else if (cs == 16)
-        k_cluster_bbox<16><<<g, 256, 0, ctx->stream>>>(n, x, y, z, h, b4, ctx->d_status, seg);
-    else
-        k_cluster_bbox<8><<<g, 256, 0, ctx->stream>>>(n, x, y, z, h, b4, ctx->d_status, seg);
+    const bool vec = ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y) |
+                       reinterpret_cast<uintptr_t>(z) | reinterpret_cast<uintptr_t>(h)) & 15u) == 0;
+    hipStream_t st = ctx->stream;
+    if (cs == 4) {
+        if (vec) k_cluster_bbox<4, true><<<g, 256, 0, st>>>(n, x, y, z, h, b4, ctx->d_status, seg);
+        else k_cluster_bbox<4, false><<<g, 256, 0, st>>>(n, x, y, z, h, b4, ctx->d_status, seg);
+    } else if (cs == 16) {
+        if (vec) k_cluster_bbox<16, true><<<g, 256, 0, st>>>(n, x, y, z, h, b4, ctx->d_status, seg);
+        else k_cluster_bbox<16, false><<<g, 256, 0, st>>>(n, x, y, z, h, b4, ctx->d_status, seg);
+    } else {
+        if (vec) k_cluster_bbox<8, true><<<g, 256, 0, st>>>(n, x, y, z, h, b4, ctx->d_status, seg);
+        else k_cluster_bbox<8, false><<<g, 256, 0, st>>>(n, x, y, z, h, b4, ctx->d_status, seg);
+    }
     SFCNL_LAUNCHED(ctx);
     prof_mark(ctx, kStageClusters, true);
     return SFCNL_OK;

@@ -420,3 +420,31 @@ def test_pass_waves_per_block(env, half):
             np.testing.assert_array_equal(res[w][0], res[1][0])
     with pytest.raises(sf.SfcnlError):
         ctx.set_pass_waves(3)
+
+
+@pytest.mark.parametrize("cs", [4, 8, 16])
+def test_cluster_boxes_unaligned_fields(env, cs):
+    # fields 4 bytes off a 16-byte boundary take the per-particle loads, aligned
+    # ones the vector loads: the boxes agree bit for bit, and with the oracle
+    sf, ctx, torch = env
+    n = 10_007
+    _say("cluster boxes unaligned cs=%d n=%d" % (cs, n))
+    s = workloads.uniform_varied(n, 5100 + cs, target=40.0)
+    keys = oracle.hilbert_keys(s.x, s.y, s.z, s.box)
+    order = np.argsort(keys, kind="stable")
+    cols = [np.ascontiguousarray(a[order]) for a in (s.x, s.y, s.z, s.h)]
+    big = [_dev(torch, np.concatenate([np.zeros(1, np.float32), c])) for c in cols]
+    off = [b[1:] for b in big]  # storage offset 4 bytes
+    ali = [_dev(torch, c) for c in cols]
+    nc = (n + cs - 1) // cs
+    b_off = torch.empty((nc, 8), dtype=torch.float32, device="cuda")
+    b_ali = torch.empty((nc, 8), dtype=torch.float32, device="cuda")
+    sf.build_clusters(ctx, *off, cs, b_off)
+    sf.build_clusters(ctx, *ali, cs, b_ali)
+    torch.cuda.synchronize()
+    assert off[0].data_ptr() % 16 == 4 and ali[0].data_ptr() % 16 == 0
+    assert torch.equal(b_off, b_ali)
+    ref = oracle.cluster_bboxes(*cols, cs)
+    got = b_ali.cpu().numpy()
+    np.testing.assert_array_equal(got[:, :4], ref[:, :4])
+    np.testing.assert_array_equal(got[:, 4:7], ref[:, 4:7])
