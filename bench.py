@@ -645,6 +645,10 @@ def time_steps(sf, torch, ctx, s, args, steps, warmup, copy_probe=0):
         torch.cuda.synchronize()
         del src, dst
         log("copy probe: %d MiB" % copy_probe)
+    # the timed steps: HIP events bracket only the traversal (the dominant
+    # kernel, for the roofline); a timing event makes the stream drain the
+    # work before it, so bracketing every stage would slow the step
+    ctx.profile_stages(["traverse"])
     ctx.profile_begin(steps)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -652,7 +656,19 @@ def time_steps(sf, torch, ctx, s, args, steps, warmup, copy_probe=0):
         pipe.step(x, y, z, h)
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    timed = ctx.profile_end()
+    # the per-stage breakdown: as many steps again with every stage bracketed
+    ctx.profile_stages(None)
+    ctx.profile_begin(steps)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    for _ in range(steps):
+        pipe.step(x, y, z, h)
+    torch.cuda.synchronize()
+    t3 = time.perf_counter()
     prof = ctx.profile_end()
+    prof["traverse"] = timed["traverse"]
+    prof["_ms_all_stages_bracketed"] = ((t3 - t2) * 1e3 / steps, 0)
     st = list_stats(sf, ctx, pipe.nl)
     del pipe, x, y, z, h
     torch.cuda.empty_cache()
@@ -666,7 +682,7 @@ def stage_table(prof, st, n, half, counters):
     bytes the counters saw per step as a fraction of the HBM peak."""
     stages = {}
     for name, (ms, calls) in prof.items():
-        if calls == 0:
+        if calls == 0 or name.startswith("_"):
             continue
         avg = ms / calls
         d = {"ms": avg}
@@ -720,7 +736,7 @@ def extra_config(sf, torch, ctx, args, name):
         torch.cuda.empty_cache()
     steps = max(5, args.steps // 2)
     ms, prof, st = time_steps(sf, torch, ctx, s, args, steps, args.warmup)
-    build = sum(v[0] / v[1] for k, v in prof.items() if v[1] and k != "pass")
+    build = sum(v[0] / v[1] for k, v in prof.items() if v[1] and k != "pass" and not k.startswith("_"))
     pas = prof["pass"][0] / prof["pass"][1] if prof.get("pass", (0, 0))[1] else 0.0
     log("%s: n=%d %.3f ms/step (build %.3f, pass %.3f) %.3f B/p" % (name, s.n, ms, build, pas,
                                                                     st["bytes_per_particle"]))
@@ -765,6 +781,9 @@ def run_step(args, sf, torch, ctx):
         "bytes_per_particle": st["bytes_per_particle"],
         "list": st,
         "stages_ms": {k: v["ms"] for k, v in stages.items()},
+        "stages_note": "stage times from %d more steps with every stage bracketed by HIP events (%.3f ms per step "
+                       "there); the traversal (the roofline kernel) from the timed steps, where only it is "
+                       "bracketed" % (args.steps, prof["_ms_all_stages_bracketed"][0]),
         "stages": stages,
         "roofline": roofline,
         "roofline_additive": additive,

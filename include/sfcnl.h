@@ -505,6 +505,13 @@ int sfcnl_batch_h_iterate(sfcnl_ctx ctx, sfcnl_batch b, const uint64_t *d_keys, 
 #define SFCNL_NSTAGE 8
 int sfcnl_profile_begin(sfcnl_ctx ctx, int slots);
 int sfcnl_profile_end(sfcnl_ctx ctx, double *h_ms, int64_t *h_calls);
+/* Restricts the event recording of the context's stage timing to the stages
+ * whose bit is set in stage_mask (bit s = stage s; the default, set by
+ * sfcnl_create, is all stages). A timing event makes the stream drain the work
+ * before it, so a step timed with every stage bracketed runs slower than
+ * without; timing one stage keeps that cost to its own two events. Bits above
+ * the stage count return SFCNL_E_ARG. */
+int sfcnl_profile_stages(sfcnl_ctx ctx, uint32_t stage_mask);
 
 #ifdef __cplusplus
 }

@@ -86,6 +86,11 @@ class Context:
         """Start per-stage event timing (see sfcnl_profile_begin)."""
         self.check(self.lib.sfcnl_profile_begin(self.handle, slots))
 
+    def profile_stages(self, stages=None):
+        """Record stage events only for the named stages (None: all)."""
+        mask = (1 << _lib.NSTAGE) - 1 if stages is None else sum(1 << _lib.STAGES.index(s) for s in stages)
+        self.check(self.lib.sfcnl_profile_stages(self.handle, mask))
+
     def profile_end(self):
         """Stop stage timing: {stage: (total ms, calls)}."""
         ms = (C.c_double * _lib.NSTAGE)()

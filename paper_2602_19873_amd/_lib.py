@@ -22,7 +22,7 @@ SYMBOLS = [
     "sfcnl_create", "sfcnl_destroy", "sfcnl_set_stream", "sfcnl_set_pass_waves", "sfcnl_last_error", "sfcnl_sync", "sfcnl_version",
     "sfc_sort_workspace", "sfc_sort", "sfc_sort_noalloc", "sfc_gather", "sfc_gather_workspace", "sfc_gather_ws", "build_clusters",
     "build_nlist_workspace", "build_nlist", "build_nlist_async", "build_nlist_result",
-    "nlist_pass", "nlist_pass_lj", "build_rows_workspace", "build_rows", "rows_pass", "nlist_decode", "sfcnl_profile_begin", "sfcnl_profile_end", "sfcnl_h_iterate",
+    "nlist_pass", "nlist_pass_lj", "build_rows_workspace", "build_rows", "rows_pass", "nlist_decode", "sfcnl_profile_begin", "sfcnl_profile_end", "sfcnl_profile_stages", "sfcnl_h_iterate",
     "sfcnl_hseed_features", "sfcnl_mlp_init", "sfcnl_mlp_infer", "sfcnl_mlp_grad_workspace", "sfcnl_mlp_grad",
     "sfcnl_mlp_adam", "sfcnl_batch_create", "sfcnl_batch_destroy", "sfcnl_batch_layout", "sfcnl_batch_sort_workspace",
     "sfcnl_batch_sort", "sfcnl_batch_gather", "sfcnl_batch_nlist_workspace", "sfcnl_batch_build_clusters",
@@ -150,6 +150,8 @@ def load():
     lib.sfcnl_profile_begin.restype = i32
     lib.sfcnl_profile_end.argtypes = [vp, C.POINTER(C.c_double), C.POINTER(i64)]
     lib.sfcnl_profile_end.restype = i32
+    lib.sfcnl_profile_stages.argtypes = [vp, C.c_uint32]
+    lib.sfcnl_profile_stages.restype = i32
     P64 = C.POINTER(i64)
     lib.sfcnl_batch_create.argtypes = [vp, i32, P64, C.POINTER(C.c_float), C.POINTER(vp)]
     lib.sfcnl_batch_create.restype = i32

@@ -52,6 +52,7 @@ extern "C" int sfcnl_create(sfcnl_ctx *out, int device, void *stream) {
     c->device = device;
     c->stream = (hipStream_t)stream;
     c->pass_waves = 1;
+    c->prof_mask = (1u << SFCNL_NSTAGE) - 1u;
     if (hipSetDevice(device) != hipSuccess) {
         free(c);
         return SFCNL_E_HIP;
@@ -133,6 +134,13 @@ extern "C" int sfcnl_profile_end(sfcnl_ctx ctx, double *h_ms, int64_t *h_calls) 
         h_calls[s] = ctx->prof_slots ? ctx->prof_used[s] : 0;
     }
     prof_release(ctx);
+    return SFCNL_OK;
+}
+
+extern "C" int sfcnl_profile_stages(sfcnl_ctx ctx, uint32_t stage_mask) {
+    if (!ctx) return SFCNL_E_ARG;
+    if (stage_mask >> SFCNL_NSTAGE) return set_err(ctx, SFCNL_E_ARG, "profile: stage mask 0x%x has bits past the stages", stage_mask);
+    ctx->prof_mask = stage_mask;
     return SFCNL_OK;
 }
 

@@ -49,8 +49,9 @@ struct sfcnl_ctx_s {
     int pass_waves;
     // device address of sfc_sort_noalloc's scratch array on this device
     void *d_sort_scratch;
-    // stage timing (sfcnl_profile_begin / _end)
+    // stage timing (sfcnl_profile_begin / _end), for the stages in prof_mask
     int prof_slots;
+    uint32_t prof_mask;
     int prof_used[SFCNL_NSTAGE];
     hipEvent_t *prof_ev[SFCNL_NSTAGE];  // 2 * prof_slots events per stage
 };
@@ -73,7 +74,7 @@ enum Stage : int { kStageKeys = 0, kStageSort, kStageGather, kStageClusters, kSt
 
 // Brackets one stage of a call with events when profiling is on.
 inline void prof_mark(sfcnl_ctx ctx, int stage, bool end) {
-    if (!ctx->prof_slots) return;
+    if (!ctx->prof_slots || !((ctx->prof_mask >> stage) & 1u)) return;
     int k = ctx->prof_used[stage];
     if (k >= ctx->prof_slots) return;
     (void)hipEventRecord(ctx->prof_ev[stage][2 * k + (end ? 1 : 0)], ctx->stream);
