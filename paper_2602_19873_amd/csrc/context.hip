@@ -61,7 +61,7 @@ extern "C" int sfcnl_create(sfcnl_ctx *out, int device, void *stream) {
         free(c);
         return SFCNL_E_HIP;
     }
-    if (hipMalloc((void **)&c->d_status, kStWords * sizeof(uint32_t)) != hipSuccess) {
+    if (hipMalloc((void **)&c->d_status, kStatusAlloc * sizeof(uint32_t)) != hipSuccess) {
         free(c);
         return SFCNL_E_HIP;
     }
@@ -84,7 +84,7 @@ extern "C" int sfcnl_create(sfcnl_ctx *out, int device, void *stream) {
         free(c);
         return SFCNL_E_HIP;
     }
-    if (fill_u32(c, c->d_status, kStWords, 0) != SFCNL_OK || hipStreamSynchronize(c->stream) != hipSuccess) {
+    if (fill_u32(c, c->d_status, kStatusAlloc, 0) != SFCNL_OK || hipStreamSynchronize(c->stream) != hipSuccess) {
         (void)hipEventDestroy(c->ev_pend);
         (void)hipHostFree(c->h_pend);
         (void)hipHostFree(c->h_status);

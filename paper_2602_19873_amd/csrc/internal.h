@@ -25,9 +25,19 @@ enum StatusWord : int {
     kStScratch = 4,      // set if a list found no staging room
     kStTree = 5,         // octree invariant broken (internal error)
     kStUnconverged = 6,  // h iteration: particles that moved this round
-    kStChunks = 7,       // shared staging chunks requested by the traversal
+    kStChunks = 7,       // shared staging chunks the lists asked for (taken, plus requests left unserved)
     kStWords = 16
 };
+
+// Shared staging chunks are handed out by kChunkStripes counters that follow
+// the status words in the same allocation, each on its own 128-byte line:
+// stripe k gives out ids k, k + kChunkStripes, k + 2 kChunkStripes, ..., so
+// that the super-clusters' requests spread over many addresses instead of
+// queueing on one. Word 1 of a stripe's line holds the longest list among
+// the super-clusters s with s % kChunkStripes = k.
+constexpr int kChunkStripes = 64;
+constexpr int kStripeWords = 32;
+constexpr int kStatusAlloc = kStWords + kChunkStripes * kStripeWords;  // words of the device status allocation
 
 }  // namespace sfcnl
 

@@ -23,6 +23,8 @@
 // writes masks and nibble segments.
 #include <cstring>
 
+#include <utility>
+
 #include "internal.h"
 
 namespace sfcnl {
@@ -173,12 +175,13 @@ struct TravArgs {
     const uint32_t *gate;  // nullable: every list empty when *gate <= gate_max
     uint32_t gate_max;
     // staging: 64-entry chunks; chunk s is super-cluster s's first, longer
-    // lists continue in chunks nsc + id taken from a shared counter
-    // (status[kStChunks]); chunk_next links a list's chunks in order
+    // lists continue in chunks nsc + id taken from the stripe counters
+    // (take_chunk); chunk_next links a list's chunks in order
     uint32_t *list_j;
     uint16_t *list_m;
     uint32_t *chunk_next;
     uint32_t nshared;      // shared chunks (ids 0 .. nshared - 1)
+    uint32_t *chunk_ctr;   // the stripe counters that hand them out, word 1 of each the stripe's longest list (zeroed before the build)
     uint32_t *sc_nj, *sc_words;
     uint32_t *status;
 };
@@ -224,6 +227,22 @@ __device__ __forceinline__ void box_union(float4 &lo, float4 &hi, float4 blo, fl
     hi.z = fmaxf(hi.z, bhi.z);
 }
 
+constexpr uint32_t kNoChunk = 0xFFFFFFFFu;
+
+// A shared staging chunk for super-cluster s: from stripe s % kChunkStripes,
+// else from the next stripes while one is used up; kNoChunk once all are
+// (every one of the nshared ids is taken). Called by one lane.
+__device__ uint32_t take_chunk(uint32_t *ctr, uint32_t nshared, uint32_t s) {
+    for (uint32_t t = 0; t < (uint32_t)kChunkStripes; t++) {
+        const uint32_t k = (s + t) % kChunkStripes;
+        if (k >= nshared) continue;  // an empty stripe
+        const uint32_t cap = (nshared - k + kChunkStripes - 1) / kChunkStripes;
+        const uint32_t i = atomicAdd(&ctr[k * kStripeWords], 1u);
+        if (i < cap) return k + kChunkStripes * i;
+    }
+    return kNoChunk;
+}
+
 // Bit k of the result: byte k of b is nonzero.
 __device__ __forceinline__ uint32_t nonzero_bytes(uint64_t b) {
     b |= b >> 4;
@@ -231,6 +250,24 @@ __device__ __forceinline__ uint32_t nonzero_bytes(uint64_t b) {
     b |= b >> 1;
     b &= 0x0101010101010101ull;
     return (uint32_t)((b * 0x0102040810204080ull) >> 56);
+}
+
+// f(std::integral_constant<int, i>{}) for i = 0 .. N - 1
+template <int N, typename F, int... I>
+__device__ __forceinline__ void static_for_impl(F &&f, std::integer_sequence<int, I...>) {
+    (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F>
+__device__ __forceinline__ void static_for(F &&f) {
+    static_for_impl<N>(f, std::make_integer_sequence<int, N>{});
+}
+
+// v of lane P of the quad (DPP quad_perm broadcast). With all rows and banks
+// enabled and bound_ctrl set, the compiler folds the move into the consuming
+// instruction's first operand, so the broadcast costs no instruction.
+template <int P>
+__device__ __forceinline__ float quad_bcast(float v) {
+    return __int_as_float(__builtin_amdgcn_mov_dpp(__float_as_int(v), P * 0x55, 0xF, 0xF, true));
 }
 
 // max of two squared radii (both >= +0): the integer order of their bit
@@ -260,20 +297,37 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
     }
     const int64_t n = a.n;
     const bool gather = a.p_active != nullptr;
-    // i particles; absent ones are put far away so that no test accepts them
+    // i particles; absent ones are put far away so that no test accepts them.
+    // Cluster size 8 keeps them in LDS for its lane-parallel tiles (lane l
+    // loads particle l; particle 8c + l' sits at 9c + l', a padding slot after
+    // each cluster keeps the clusters on distinct banks), the other sizes in
+    // the registers of their tile lanes.
+    constexpr bool kLaneTiles = CS == 8;
+    __shared__ float4 s_ip[kWavesPerBlock][kLaneTiles ? 72 : 1];
     float ix[kNreg], iy[kNreg], iz[kNreg], ih2[kNreg];
+    float lh2 = 0.0f;  // cluster size 8: the squared radius of particle lane
     bool big = false;  // a radius reaches half a period
-#pragma unroll
-    for (int k = 0; k < kNreg; k++) {
-        const int64_t i = (int64_t)s * kScSize + S::ipart(k, lane);
+    if constexpr (kLaneTiles) {
+        const int64_t i = (int64_t)s * kScSize + lane;
         const bool v = i < n;
-        ix[k] = v ? a.x[i] : kFar;
-        iy[k] = v ? a.y[i] : kFar;
-        iz[k] = v ? a.z[i] : kFar;
         float hh = v ? a.h[i] : 0.0f;
-        if (kPbc) big = big || !(hh < a.per.hmin);
+        if (kPbc) big = !(hh < a.per.hmin);
         if (gather && v && !a.p_active[i]) hh = 0.0f;  // counting list: flagged particles only
-        ih2[k] = hh * hh;
+        lh2 = hh * hh;
+        s_ip[w][9 * (lane >> 3) + (lane & 7)] = make_float4(v ? a.x[i] : kFar, v ? a.y[i] : kFar, v ? a.z[i] : kFar, lh2);
+    } else {
+#pragma unroll
+        for (int k = 0; k < kNreg; k++) {
+            const int64_t i = (int64_t)s * kScSize + S::ipart(k, lane);
+            const bool v = i < n;
+            ix[k] = v ? a.x[i] : kFar;
+            iy[k] = v ? a.y[i] : kFar;
+            iz[k] = v ? a.z[i] : kFar;
+            float hh = v ? a.h[i] : 0.0f;
+            if (kPbc) big = big || !(hh < a.per.hmin);
+            if (gather && v && !a.p_active[i]) hh = 0.0f;  // counting list: flagged particles only
+            ih2[k] = hh * hh;
+        }
     }
     if (kPbc && sfc_ballot(big) && lane == 0) atomicOr(&a.status[kStInputErr], 8u);
     const uint32_t own_c0 = s * kNsub;  // first i-cluster of this super-cluster
@@ -310,9 +364,13 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
         // registers (a radius 0 box passes no test)
         __shared__ float s_hmax[kWavesPerBlock][kScSize];
         float *hm = s_hmax[w];
+        if constexpr (kLaneTiles) {
+            hm[lane] = __builtin_sqrtf(lh2);
+        } else {
 #pragma unroll
-        for (int k = 0; k < kNreg; k++) {
-            if ((CS == 8 ? (lane & 7) : (lane & 3)) == 0) hm[S::ipart(k, lane)] = __builtin_sqrtf(ih2[k]);
+            for (int k = 0; k < kNreg; k++) {
+                if ((lane & 3) == 0) hm[S::ipart(k, lane)] = __builtin_sqrtf(ih2[k]);
+            }
         }
         wave_sync();
         auto rmax = [&](int p0, int cnt) {
@@ -398,13 +456,14 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
     bool staged = true;        // false once the shared chunks ran out
     auto flush = [&](uint32_t cnt) {
         if (nj > cnt) {  // beyond the first chunk: take a shared one
-            uint32_t id = 0;
-            if (lane == 0) id = atomicAdd(&a.status[kStChunks], 1u);
+            uint32_t id = kNoChunk;
+            if (lane == 0 && staged) id = take_chunk(a.chunk_ctr, a.nshared, s);
             id = (uint32_t)__builtin_amdgcn_readfirstlane((int)id);
-            if (staged && id < a.nshared) {
+            if (id != kNoChunk) {
                 if (lane == 0) a.chunk_next[chunk] = a.nsc + id;
                 chunk = a.nsc + id;
             } else {
+                if (lane == 0) atomicAdd(&a.status[kStChunks], 1u);  // a request left unserved (sizes the retry)
                 staged = false;
             }
         }
@@ -430,28 +489,43 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
     // radius makes max(h_i^2, h_j^2) = h_i^2).
     constexpr int kBatch = kWave / CS;
     uint32_t qn = 0;
-    auto load_batch = [&](uint32_t b0, float &bx, float &by, float &bz, float &bh2) {
+    // The loads read a clamped index unconditionally, so they stay in flight
+    // while the current batch's tiles run (a load behind a branch, or one
+    // whose value is used at once, ends with a wait); validity and the squared
+    // radius apply when the batch is used (drains run with qn >= 1).
+    struct JLoad {
+        float x, y, z, h;
+        bool v;
+    };
+    auto load_batch = [&](uint32_t b0, JLoad &f) {
         const uint32_t e = b0 + (uint32_t)(lane / CS);
-        const uint32_t cj = e < qn ? queue[e].x : 0u;
+        const uint32_t cj = queue[e < qn ? e : qn - 1u].x;
         const int64_t p = (int64_t)cj * CS + (lane & (CS - 1));
-        const bool v = e < qn && p < n;
-        bx = v ? a.x[p] : kFar;
-        by = v ? a.y[p] : kFar;
-        bz = v ? a.z[p] : kFar;
-        const float hh = v && !gather ? a.h[p] : 0.0f;
-        bh2 = hh * hh;
+        const int64_t pc = p < n ? p : n - 1;
+        f.v = e < qn && p < n;
+        f.x = a.x[pc];
+        f.y = a.y[pc];
+        f.z = a.z[pc];
+        f.h = a.h[pc];
+    };
+    auto batch_vals = [&](const JLoad &f) {
+        const float hh = f.v && !gather ? f.h : 0.0f;
+        return make_float4(f.v ? f.x : kFar, f.v ? f.y : kFar, f.v ? f.z : kFar, hh * hh);
     };
     auto lane_f = [](int src, float v) {  // v of lane src (ds_bpermute takes a byte address)
         return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
     };
 
-    auto drain = [&]() {
+    // Cluster sizes 4 and 16: one step tests the 64 particle pairs of one
+    // tile (CS = 4: four), the queued candidates one after another.
+    auto drain_regs = [&]() {
         wave_sync();
-        float bx, by, bz, bh2;
-        load_batch(0, bx, by, bz, bh2);
+        JLoad f;
+        load_batch(0, f);
         for (uint32_t b0 = 0; b0 < qn; b0 += kBatch) {
-            const float cx = bx, cy = by, cz = bz, ch2 = bh2;
-            if (b0 + kBatch < qn) load_batch(b0 + kBatch, bx, by, bz, bh2);
+            const float4 c = batch_vals(f);
+            const float cx = c.x, cy = c.y, cz = c.z, ch2 = c.w;
+            if (b0 + kBatch < qn) load_batch(b0 + kBatch, f);
             const uint32_t bn = qn - b0 < (uint32_t)kBatch ? qn - b0 : (uint32_t)kBatch;
             for (uint32_t q = 0; q < bn; q++) {
             const uint2 qe = queue[b0 + q];
@@ -473,37 +547,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
                 return half ? (ci < self_c || (ci == self_c && jpos > ipos)) : (ci != self_c || jpos != ipos);
             };
             uint32_t mask = 0;
-            if (CS == 8) {
-                const int jl = lane & 7, il = lane >> 3;
-                if (self_c < 0) {  // another super-cluster's j-cluster: the plain test
-#pragma unroll
-                    for (int c = 0; c < kNreg; c++) {
-                        if ((cmask >> c) & 1u) {
-                            float dx = xj[0] - ix[c];
-                            float dy = yj[0] - iy[c];
-                            float dz = zj[0] - iz[c];
-                            if (kPbc) wrap(dx, dy, dz);
-                            const float dxx = dx * dx;
-                            const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                            if (sfc_ballot(d2 < max_sq(ih2[c], hj2[0]))) mask |= 1u << c;
-                        }
-                    }
-                } else {
-#pragma unroll
-                    for (int c = 0; c < kNreg; c++) {
-                        if ((cmask >> c) & 1u) {
-                            float dx = xj[0] - ix[c];
-                            float dy = yj[0] - iy[c];
-                            float dz = zj[0] - iz[c];
-                            if (kPbc) wrap(dx, dy, dz);
-                            const float dxx = dx * dx;
-                            const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                            const bool pr = d2 < max_sq(ih2[c], hj2[0]) && keep(c, il, jl);
-                            if (sfc_ballot(pr)) mask |= 1u << c;
-                        }
-                    }
-                }
-            } else if (CS == 4) {
+            if constexpr (CS == 4) {
                 const int jl = lane & 3, il = (lane >> 2) & 3, q = lane >> 4;
 #pragma unroll
                 for (int k = 0; k < kNreg; k++) {
@@ -561,6 +605,139 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
         }
         qn = 0;
         wave_sync();
+    };
+
+    // Cluster size 8: lane-parallel tiles. A batch is 8 queued candidates;
+    // bit 8q + c of W says that the box test kept i-cluster c for candidate
+    // q. W's set bits, numbered in order, are the batch's tiles, and a round
+    // hands tiles 8r .. 8r + 7 to the eight groups of 8 lanes: lane (g, l)
+    // takes i-particle l of its tile's i-cluster and steps through the 8
+    // j-particles of its candidate, one pair per step, so one step tests one
+    // pair of each of 8 tiles. A tile passes if a lane of its group saw a
+    // pair; the results go back to W's bit positions (R), whose bytes are the
+    // candidates' masks. The j-particles of the batch wait in LDS (candidate
+    // q's particle p at 9q + p).
+    __shared__ float4 s_jp[kWavesPerBlock][kLaneTiles ? 72 : 1];
+    // tile t of the batch: byte offsets of its i-cluster in s_ip (bits 0-10),
+    // of its candidate's own i-cluster if it is one of ours, else 8 clusters
+    // (bits 11-21), and of its candidate in s_jp (bits 22-31)
+    __shared__ uint32_t s_tile[kWavesPerBlock][kLaneTiles ? 64 : 1];
+    __shared__ uint2 s_ent[kWavesPerBlock][kLaneTiles ? 8 : 1];
+    __shared__ uint64_t s_hits[kWavesPerBlock][kLaneTiles ? 8 : 1];
+    if constexpr (kLaneTiles) s_tile[w][lane] = 0u;  // entries past a batch's tiles stay valid offsets
+    auto drain_lanes = [&]() {
+        wave_sync();
+        constexpr uint32_t kRow = 9 * sizeof(float4);  // one cluster's stride in s_ip and s_jp
+        constexpr uint64_t kBytes = 0x0101010101010101ull;
+        const int g = lane >> 3, l = lane & 7;
+        const char *ipb = reinterpret_cast<const char *>(s_ip[w]) + l * sizeof(float4);
+        const char *jpb = reinterpret_cast<const char *>(s_jp[w]);
+        JLoad f;
+        load_batch(0, f);
+        for (uint32_t b0 = 0; b0 < qn; b0 += kBatch) {
+            s_jp[w][9 * g + l] = batch_vals(f);
+            if (b0 + kBatch < qn) load_batch(b0 + kBatch, f);
+            // lane (g, l): candidate b0 + g against i-cluster l
+            const uint32_t e = b0 + (uint32_t)g;
+            const bool ev = e < qn;
+            const uint2 qe = queue[ev ? e : b0];
+            const uint32_t rel = qe.x - own_c0;  // below 8: the candidate is our own i-cluster rel
+            const bool bit = ev && ((qe.y >> l) & 1u);
+            const uint64_t W = sfc_ballot(bit);
+            const bool mixed = sfc_ballot(ev && rel < 8u) != 0;  // a candidate of the batch is ours
+            const int T = sfc_popc(W);
+            const uint32_t k = __builtin_amdgcn_mbcnt_hi((uint32_t)(W >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)W, 0u));
+            if (bit) s_tile[w][k] = kRow * (uint32_t)l | (kRow * (rel < 8u ? rel : 8u)) << 11 | (kRow * (uint32_t)g) << 22;
+            wave_sync();
+            // s_hits[r]: round r's ballot (byte g: group g, i.e. tile 8r + g,
+            // saw a pair); bytes of tiles past T are never read
+            for (int r = 0; 8 * r < T; r++) {
+                const uint32_t tv = s_tile[w][8 * r + g];  // tiles past T: stale, masked below
+                const uint32_t ioff = tv & 0x7FFu, soff = (tv >> 11) & 0x7FFu;
+                const float4 ip = *reinterpret_cast<const float4 *>(ipb + ioff);
+                // lane (g, l) holds j-particles l % 4 and 4 + l % 4 of its
+                // candidate; step p takes particle p from lane p % 4 of the
+                // quad (a DPP operand, no LDS traffic)
+                const float4 *jb = reinterpret_cast<const float4 *>(jpb + (tv >> 22));
+                const float4 ja = jb[l & 3], jz = jb[4 + (l & 3)];
+                uint64_t acc = 0;
+                if (!mixed) {
+                    static_for<CS>([&](auto pc) {
+                        constexpr int p = decltype(pc)::value;
+                        const float4 &jq = p < 4 ? ja : jz;
+                        float dx = quad_bcast<p & 3>(jq.x) - ip.x;
+                        float dy = quad_bcast<p & 3>(jq.y) - ip.y;
+                        float dz = quad_bcast<p & 3>(jq.z) - ip.z;
+                        if (kPbc) wrap(dx, dy, dz);
+                        const float dxx = dx * dx;
+                        const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
+                        acc |= sfc_ballot(d2 < max_sq(quad_bcast<p & 3>(jq.w), ip.w));
+                    });
+                } else {
+                    // pairs within our own super-cluster: i = 8c + l and
+                    // j = 8c' + p; the half list keeps j > i (c < c', or
+                    // c = c' and l < p), the full list all but i = j
+                    const uint64_t below = sfc_ballot(ioff < soff), same = sfc_ballot(ioff == soff);
+                    static_for<CS>([&](auto pc) {
+                        constexpr int p = decltype(pc)::value;
+                        const float4 &jq = p < 4 ? ja : jz;
+                        float dx = quad_bcast<p & 3>(jq.x) - ip.x;
+                        float dy = quad_bcast<p & 3>(jq.y) - ip.y;
+                        float dz = quad_bcast<p & 3>(jq.z) - ip.z;
+                        if (kPbc) wrap(dx, dy, dz);
+                        const float dxx = dx * dx;
+                        const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
+                        const uint64_t keep = half ? below | (same & (((1ull << p) - 1ull) * kBytes)) : ~(same & ((1ull << p) * kBytes));
+                        acc |= sfc_ballot(d2 < max_sq(quad_bcast<p & 3>(jq.w), ip.w)) & keep;
+                    });
+                }
+                if (lane == 0) s_hits[w][r] = acc;
+            }
+            wave_sync();
+            // W's bit of rank k: tile k, byte k % 8 of round k / 8
+            const uint32_t hw = reinterpret_cast<const uint32_t *>(s_hits[w])[(k >> 2) & 15u];
+            const uint64_t R = sfc_ballot(bit && ((hw >> (8 * (k & 3u))) & 0xFFu) != 0u);
+            // candidate g's mask is byte g of R; the nonempty ones join the
+            // list in queue order (lane (nj + rank) % 64 of ej / em)
+            const uint32_t mq = lane < kBatch ? (uint32_t)(R >> ((8 * lane) & 63)) & 0xFFu : 0u;
+            const uint64_t ne = sfc_ballot(mq != 0u);
+            if (ne) {
+                const uint32_t cnt = (uint32_t)sfc_popc(ne);
+                if (mq) {
+                    const uint32_t rk = __builtin_amdgcn_mbcnt_lo((uint32_t)ne, 0u);
+                    s_ent[w][rk] = make_uint2(queue[b0 + lane].x - jbase, mq);
+                }
+                wave_sync();
+                const uint32_t base = nj & (kWave - 1);
+                const uint32_t first = cnt < kWave - base ? cnt : kWave - base;
+                const uint32_t d = (uint32_t)lane - base;
+                if (d < first) {
+                    const uint2 v = s_ent[w][d];
+                    ej = v.x;
+                    em = v.y;
+                }
+                nj += first;
+                if ((nj & (kWave - 1)) == 0) flush(kWave);
+                if (cnt > first) {
+                    if ((uint32_t)lane < cnt - first) {
+                        const uint2 v = s_ent[w][first + lane];
+                        ej = v.x;
+                        em = v.y;
+                    }
+                    nj += cnt - first;
+                }
+                wave_sync();  // the next batch rewrites s_ent
+            }
+        }
+        qn = 0;
+        wave_sync();
+    };
+
+    auto drain = [&]() {
+        if constexpr (kLaneTiles)
+            drain_lanes();
+        else
+            drain_regs();
     };
 
     const uint64_t lt = sfc_lt_mask();
@@ -637,7 +814,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
         const uint32_t mwords = (nj * S::kMaskBytes + 3u) / 4u;
         a.sc_nj[s] = staged ? nj : kUnstaged;
         a.sc_words[s] = staged ? mwords + (a.compress ? seg_words : nj) : 0u;
-        atomicMax(&a.status[kStMaxNj], nj);
+        atomicMax(&a.chunk_ctr[(s % kChunkStripes) * kStripeWords + 1], nj);  // longest list, per stripe
         if (!staged) atomicOr(&a.status[kStScratch], 1u);
     }
 }
@@ -656,6 +833,8 @@ struct EncArgs {
     uint32_t *sc_info;
     uint32_t *pool;
     uint64_t pool_words;
+    const uint32_t *chunk_ctr;  // the traversal's stripe counters
+    uint32_t nshared;
     uint32_t *status;
 };
 
@@ -665,8 +844,28 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) void k_encode(EncArgs a) {
     const int w = threadIdx.x / kWave;
     // wave-uniform: keep the super-cluster index (and all derived from it) scalar
     const uint32_t s = (uint32_t)__builtin_amdgcn_readfirstlane((int)(xcd_remap(blockIdx.x, gridDim.x) * kWavesPerBlock + w));
-    // the pool total (the scan's last entry) into the status block
-    if (blockIdx.x == 0 && threadIdx.x == 0) a.status[kStTotalLo] = a.sc_off[a.nsc];
+    // the pool total (the scan's last entry) into the status block, the
+    // shared staging chunks taken added to the requests left unserved (a
+    // stripe counter runs past its share when a request probes it full), and
+    // the longest list over the stripes' maxima
+    if (blockIdx.x == 0 && w == 0) {
+        uint32_t taken = 0, longest = 0;
+        if ((uint32_t)lane < (uint32_t)kChunkStripes) {
+            longest = a.chunk_ctr[lane * kStripeWords + 1];
+            if ((uint32_t)lane < a.nshared) {
+                const uint32_t cap = (a.nshared - lane + kChunkStripes - 1) / kChunkStripes;
+                taken = min(a.chunk_ctr[lane * kStripeWords], cap);
+            }
+        }
+        const uint32_t tot = sfc_readlane(sfc_incl_scan(taken), kWave - 1);
+#pragma unroll
+        for (int d = 1; d < kWave; d <<= 1) longest = max(longest, (uint32_t)__shfl_xor((int)longest, d, kWave));
+        if (lane == 0) {
+            a.status[kStTotalLo] = a.sc_off[a.nsc];
+            a.status[kStChunks] += tot;
+            a.status[kStMaxNj] = max(a.status[kStMaxNj], longest);
+        }
+    }
     if (s >= a.nsc) return;
     const uint32_t nj = a.sc_nj[s];
     const uint32_t off = a.sc_off[s];
@@ -906,7 +1105,7 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     const uint32_t nclu = (uint32_t)((n + cs - 1) / cs);
     hipStream_t st = ctx->stream;
 
-    int rc = fill_u32(ctx, ctx->d_status + kStPoolOverflow, kStWords - kStPoolOverflow, 0);
+    int rc = fill_u32(ctx, ctx->d_status + kStPoolOverflow, kStatusAlloc - kStPoolOverflow, 0);  // with the stripe counters
     if (rc) return rc;
     if (!reuse_tree) {  // else the tree of the previous build (same keys and bucket) serves
         prof_mark(ctx, kStageOctree, false);
@@ -942,6 +1141,7 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     ta.list_m = ws.list_m;
     ta.chunk_next = ws.chunk_next;
     ta.nshared = ws.nchunks - nsc;
+    ta.chunk_ctr = ctx->d_status + kStWords;
     ta.sc_nj = ws.sc_nj;
     ta.sc_words = ws.sc_words;
     ta.status = ctx->d_status;
@@ -969,6 +1169,8 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     ea.sc_info = d_sc_info;
     ea.pool = d_pool;
     ea.pool_words = pool_bytes / 4;
+    ea.chunk_ctr = ctx->d_status + kStWords;
+    ea.nshared = ws.nchunks - nsc;
     ea.status = ctx->d_status;
     k_encode<<<gb, kWave * kWavesPerBlock, 0, st>>>(ea);
     SFCNL_LAUNCHED(ctx);
