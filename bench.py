@@ -645,19 +645,8 @@ def time_steps(sf, torch, ctx, s, args, steps, warmup, copy_probe=0):
         torch.cuda.synchronize()
         del src, dst
         log("copy probe: %d MiB" % copy_probe)
-    # the timed steps: HIP events bracket only the traversal (the dominant
-    # kernel, for the roofline); a timing event makes the stream drain the
-    # work before it, so bracketing every stage would slow the step
-    ctx.profile_stages(["traverse"])
-    ctx.profile_begin(steps)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(steps):
-        pipe.step(x, y, z, h)
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    timed = ctx.profile_end()
-    # the per-stage breakdown: as many steps again with every stage bracketed
+    # the per-stage breakdown first: as many steps as timed, every stage
+    # bracketed by HIP events
     ctx.profile_stages(None)
     ctx.profile_begin(steps)
     torch.cuda.synchronize()
@@ -667,8 +656,22 @@ def time_steps(sf, torch, ctx, s, args, steps, warmup, copy_probe=0):
     torch.cuda.synchronize()
     t3 = time.perf_counter()
     prof = ctx.profile_end()
-    prof["traverse"] = timed["traverse"]
+    # the timed steps: events bracket only the dominant stage (its kernel is
+    # the roofline line's); a timing event makes the stream drain the work
+    # before it, so bracketing every stage would slow the step
+    dom = max((k for k, v in prof.items() if v[1]), key=lambda k: prof[k][0] / prof[k][1])
+    ctx.profile_stages([dom])
+    ctx.profile_begin(steps)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        pipe.step(x, y, z, h)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    timed = ctx.profile_end()
+    prof[dom] = timed[dom]
     prof["_ms_all_stages_bracketed"] = ((t3 - t2) * 1e3 / steps, 0)
+    prof["_live"] = (dom, 0)
     st = list_stats(sf, ctx, pipe.nl)
     del pipe, x, y, z, h
     torch.cuda.empty_cache()
@@ -755,7 +758,7 @@ def run_step(args, sf, torch, ctx):
     log("timed %d steps: %.3f ms/step" % (args.steps, ms_step))
     counters = read_counters(n)
     stages = stage_table(prof, st, n, bool(args.half), counters)
-    dom = max((k for k in stages if "bound" in stages[k]), key=lambda k: stages[k]["ms"])
+    dom = prof["_live"][0]  # the dominant stage, timed live in the timed steps
     dd = stages[dom]
     hb = "true" if args.half else "false"
     kernel_of = {"traverse": "k_traverse<%d,%s,false>" % (args.cluster_size, hb),
@@ -782,8 +785,8 @@ def run_step(args, sf, torch, ctx):
         "list": st,
         "stages_ms": {k: v["ms"] for k, v in stages.items()},
         "stages_note": "stage times from %d more steps with every stage bracketed by HIP events (%.3f ms per step "
-                       "there); the traversal (the roofline kernel) from the timed steps, where only it is "
-                       "bracketed" % (args.steps, prof["_ms_all_stages_bracketed"][0]),
+                       "there); the dominant stage (%s, the roofline kernel's) from the timed steps, where only it "
+                       "is bracketed" % (args.steps, prof["_ms_all_stages_bracketed"][0], dom),
         "stages": stages,
         "roofline": roofline,
         "roofline_additive": additive,
