@@ -22,6 +22,16 @@ using namespace passk;
 // than four for the half-list pass on the uniform benchmark); the batch
 // autotuner times all three.
 constexpr int kPassWavesMax = 4;
+// LDS per wave of the cluster-size-8 symmetric pass: a batch's 64
+// j-particles (x, y, z, h^2), their 1/h and masses, and every tile lane's
+// j-side partial sum and count for each of the batch's 8 entries
+constexpr int kPassLds8 = (6 + 2 * 8) * kWave * 4;
+
+// orders a wave's LDS accesses around it (the wave runs in lockstep)
+__device__ __forceinline__ void pass_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
 
 struct PassArgs {
     int64_t n;
@@ -88,8 +98,11 @@ __device__ __forceinline__ void tile_pair(float xj, float yj, float zj, float mj
 // Both passes are bound by VALU issue; for cluster sizes 4 and 8 six waves
 // per SIMD (at most 80 VGPRs, a few registers spilled) hide more of the load
 // latency than five without spills: measured 8 % faster for either list
-// form. Cluster size 16 holds four j-particles per lane; under the same cap it
-// spills heavily, so it keeps its own register count.
+// form. The symmetric pass of cluster size 8, which takes its entries in
+// batches, needs more registers and runs five waves (2 registers spilled
+// with compression; six waves spilled more and ran 2 % slower). Cluster size 16 holds four
+// j-particles per lane; under the same cap it spills heavily, so it keeps
+// its own register count.
 template <int CS, bool kCompress, bool kMass, bool kCount, bool kPbc>
 __global__ __launch_bounds__(kWave * kPassWavesMax) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 1 : 6))) void k_pass(PassArgs a) {
     constexpr int kNsub = kScSize / CS;
@@ -267,7 +280,7 @@ __device__ __forceinline__ void half_pair(float xj, float yj, float zj, float mj
 }
 
 template <int CS, bool kCompress, bool kMass, bool kCount, bool kPbc>
-__global__ __launch_bounds__(kWave * kPassWavesMax) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 1 : 6))) void k_pass_half(PassArgs a) {
+__global__ __launch_bounds__(kWave * kPassWavesMax) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 1 : (CS == 8 ? 5 : 6)))) void k_pass_half(PassArgs a) {
     constexpr int kNsub = kScSize / CS;
     constexpr int kNreg = CS == 8 ? 8 : 4;
     constexpr int kNj = CS == 16 ? 4 : 1;
@@ -309,6 +322,95 @@ __global__ __launch_bounds__(kWave * kPassWavesMax) __attribute__((amdgpu_waves_
     const uint8_t *mbytes = reinterpret_cast<const uint8_t *>(a.pool + off);
     const uint16_t *mshorts = reinterpret_cast<const uint16_t *>(a.pool + off);
     const uint32_t jbase = a.seg.on() ? a.seg.pbase[a.seg.sc_sys[s]] / CS : 0u;
+    // Cluster size 8: the entries of a decoded segment 8 at a time. Lane
+    // (q, r) = (lane / 8, lane % 8) loads particle r of the batch's entry q
+    // (one load per field for the batch; loading the next batch behind the
+    // current one's tiles measured slower, the extra registers spilled),
+    // derives its squared radius and reciprocal once and leaves them in LDS,
+    // where the tile lanes of entry q read
+    // j-particle jq. Every tile lane's j-side partial sum and count of an
+    // entry go to LDS too, and after the batch lane (q, r) adds the 8 partials
+    // of its particle and updates rho and nnb with one atomic each.
+    // this wave's LDS (one wave-uniform base; the arrays at fixed offsets)
+    extern __shared__ float4 s_pass_dyn[];
+    float *const s_base = reinterpret_cast<float *>(s_pass_dyn) +
+                          (size_t)__builtin_amdgcn_readfirstlane(w) * (kPassLds8 / 4);
+    float4 *const s_jb = reinterpret_cast<float4 *>(s_base);
+    float *const s_jh = s_base + 4 * kWave;
+    float *const s_jm = s_base + 5 * kWave;
+    float *const s_ja = s_base + 6 * kWave;
+    int *const s_jc = reinterpret_cast<int *>(s_base + 14 * kWave);
+    struct JLoad {
+        float x, y, z, h, m;
+        uint32_t q;  // particle index (n < 2^31)
+        bool v;
+    };
+    auto load_batch8 = [&](uint32_t jvl, uint32_t q0, uint32_t cnt, JLoad &f) {
+        const uint32_t e = q0 + (uint32_t)(lane >> 3);
+        f.v = e < cnt;
+        const uint32_t cjb = (uint32_t)__shfl((int)jvl, (int)(f.v ? e : q0), kWave);
+        f.q = cjb * CS + (uint32_t)(lane & 7);
+        f.v = f.v && f.q < n;
+        const uint32_t qc = f.q < n ? f.q : (uint32_t)(n - 1);  // loads of a clamped index stay in flight
+        f.x = a.x[qc];
+        f.y = a.y[qc];
+        f.z = a.z[qc];
+        f.h = a.h[qc];
+        f.m = kMass ? a.m[qc] : 1.0f;
+    };
+    auto half_entries8 = [&](uint32_t mvl, uint32_t jvl, uint32_t cnt) {
+        JLoad f;
+        load_batch8(jvl, 0, cnt, f);
+        for (uint32_t q0 = 0; q0 < cnt; q0 += 8) {
+            // the batch's j-particles into LDS (absent ones: far away, radius
+            // -1, mass 0; NaN padding never pairs either)
+            const float hh = f.v ? f.h : -1.0f;
+            const bool vh = hh > 0.0f;
+            s_jb[lane] = make_float4(f.v ? f.x : kFar, f.v ? f.y : kFar, f.v ? f.z : kFar, vh ? hh * hh : -1.0f);
+            s_jh[lane] = vh ? __builtin_amdgcn_rcpf(hh) : 1.0f;
+            if (kMass) s_jm[lane] = vh ? f.m : 0.0f;
+            const bool ev = f.v;
+            const uint32_t jq_p = f.q;  // this lane's batch particle (for the atomics)
+            pass_wave_sync();
+            const uint32_t bn = cnt - q0 < 8u ? cnt - q0 : 8u;
+            const int il = lane & 7;
+            for (uint32_t q = 0; q < bn; q++) {
+                const uint32_t mk = sfc_readlane(mvl, (int)(q0 + q));
+                const uint32_t cj = sfc_readlane(jvl, (int)(q0 + q));
+                const float4 jb = s_jb[q * 8 + jq];
+                const float hjinv = s_jh[q * 8 + jq];
+                const float mj = kMass ? s_jm[q * 8 + jq] : 1.0f;
+                float accj = 0.0f;
+                int cntj = 0;
+                // inside the super-cluster only j > i counts
+                const int self_c = (cj >= own_c0 && cj < own_c0 + kNsub) ? (int)(cj - own_c0) : -1;
+#pragma unroll
+                for (int c = 0; c < kNreg; c++)
+                    if (((mk >> c) & 1u) && (self_c < 0 || c < self_c || (c == self_c && jq > il)))
+                        half_pair<kMass, kPbc>(jb.x, jb.y, jb.z, mj, jb.w, hjinv, ix[c], iy[c], iz[c], im[c], ih2[c],
+                                               ihinv[c], acc[c], cnt_nb[c], accj, cntj, a.per);
+                s_ja[q * kWave + lane] = accj;
+                s_jc[q * kWave + lane] = cntj;
+            }
+            pass_wave_sync();
+            // lane (q, r): j-particle r of entry q, whose 8 partials (tile
+            // lanes 8r .. 8r + 7 of entry q) sit at 8 lane .. 8 lane + 7
+            if (ev && (uint32_t)(lane >> 3) < bn) {
+                const int4 c0 = reinterpret_cast<const int4 *>(s_jc)[2 * lane];
+                const int4 c1 = reinterpret_cast<const int4 *>(s_jc)[2 * lane + 1];
+                const int c = ((c0.x + c0.y) + (c0.z + c0.w)) + ((c1.x + c1.y) + (c1.z + c1.w));
+                if (c != 0) {
+                    const float4 a0 = reinterpret_cast<const float4 *>(s_ja)[2 * lane];
+                    const float4 a1 = reinterpret_cast<const float4 *>(s_ja)[2 * lane + 1];
+                    atomicAdd(&a.rho[jq_p], ((a0.x + a0.y) + (a0.z + a0.w)) + ((a1.x + a1.y) + (a1.z + a1.w)));
+                    if (kCount) atomicAdd(&a.nnb[jq_p], c);
+                }
+            }
+            pass_wave_sync();  // the next batch rewrites the LDS arrays
+            if (q0 + 8 < cnt) load_batch8(jvl, q0 + 8, cnt, f);
+        }
+    };
+
     uint32_t p = off + (nj * (CS == 4 ? 2u : 1u) + 3u) / 4u;
     uint32_t prevj = 0xFFFFFFFFu;
     for (uint32_t b0 = 0; b0 < nj; b0 += kWave) {
@@ -323,6 +425,10 @@ __global__ __launch_bounds__(kWave * kPassWavesMax) __attribute__((amdgpu_waves_
         if ((uint32_t)lane < cnt) mv = CS == 4 ? (uint32_t)mshorts[b0 + lane] : (uint32_t)mbytes[b0 + lane];
         prevj = sfc_readlane(jv, (int)cnt - 1);
         jv += jbase;
+        if constexpr (CS == 8) {
+            half_entries8(mv, jv, cnt);
+            continue;
+        }
         // software pipeline: the next entry's j-particles load while the
         // current entry's tiles run
         float nx[kNj], ny[kNj], nz[kNj], nm[kNj], nh[kNj];
@@ -364,14 +470,8 @@ __global__ __launch_bounds__(kWave * kPassWavesMax) __attribute__((amdgpu_waves_
             auto keep = [&](int ci, int ipos, int jpos) {
                 return self_c < 0 || ci < self_c || (ci == self_c && jpos > ipos);
             };
-            if (CS == 8) {
-                const int il = lane & 7;
-#pragma unroll
-                for (int c = 0; c < kNreg; c++)
-                    if (((mk >> c) & 1u) && keep(c, il, jq))
-                        half_pair<kMass, kPbc>(xj[0], yj[0], zj[0], mj[0], hj2[0], hjinv[0], ix[c], iy[c], iz[c],
-                                               im[c], ih2[c], ihinv[c], acc[c], cnt_nb[c], accj[0], cntj[0], a.per);
-            } else if (CS == 4) {
+            // (cluster size 8 takes its entries in batches, above)
+            if constexpr (CS == 4) {
                 const int il = lane & 3, q = (lane >> 2) & 3;
 #pragma unroll
                 for (int k = 0; k < kNreg; k++)
@@ -494,15 +594,16 @@ void launch_pass(int variant, unsigned g, unsigned tpb, hipStream_t st, const Pa
 
 template <int CS, bool kPbc>
 void launch_pass_half(int variant, unsigned g, unsigned tpb, hipStream_t st, const PassArgs &a) {
+    const size_t lds = CS == 8 ? (size_t)(tpb / kWave) * kPassLds8 : 0;
     switch (variant) {
-        case 7: k_pass_half<CS, true, true, true, kPbc><<<g, tpb, 0, st>>>(a); break;
-        case 6: k_pass_half<CS, true, true, false, kPbc><<<g, tpb, 0, st>>>(a); break;
-        case 5: k_pass_half<CS, true, false, true, kPbc><<<g, tpb, 0, st>>>(a); break;
-        case 4: k_pass_half<CS, true, false, false, kPbc><<<g, tpb, 0, st>>>(a); break;
-        case 3: k_pass_half<CS, false, true, true, kPbc><<<g, tpb, 0, st>>>(a); break;
-        case 2: k_pass_half<CS, false, true, false, kPbc><<<g, tpb, 0, st>>>(a); break;
-        case 1: k_pass_half<CS, false, false, true, kPbc><<<g, tpb, 0, st>>>(a); break;
-        default: k_pass_half<CS, false, false, false, kPbc><<<g, tpb, 0, st>>>(a); break;
+        case 7: k_pass_half<CS, true, true, true, kPbc><<<g, tpb, lds, st>>>(a); break;
+        case 6: k_pass_half<CS, true, true, false, kPbc><<<g, tpb, lds, st>>>(a); break;
+        case 5: k_pass_half<CS, true, false, true, kPbc><<<g, tpb, lds, st>>>(a); break;
+        case 4: k_pass_half<CS, true, false, false, kPbc><<<g, tpb, lds, st>>>(a); break;
+        case 3: k_pass_half<CS, false, true, true, kPbc><<<g, tpb, lds, st>>>(a); break;
+        case 2: k_pass_half<CS, false, true, false, kPbc><<<g, tpb, lds, st>>>(a); break;
+        case 1: k_pass_half<CS, false, false, true, kPbc><<<g, tpb, lds, st>>>(a); break;
+        default: k_pass_half<CS, false, false, false, kPbc><<<g, tpb, lds, st>>>(a); break;
     }
 }
 
