@@ -30,6 +30,11 @@
 namespace sfcnl {
 namespace {
 
+// Lambdas of the traversal kernel are always inlined: a lambda left as a call
+// takes the kernel's argument block by reference, which then lives in
+// scratch memory, and every pointer from it is loaded through scratch.
+#define SFC_INLINE __attribute__((always_inline))
+
 // One wavefront (one super-cluster) per block for the traversal and the
 // encoder: a block's resources are released only when its slowest wave ends,
 // and super-clusters differ in work; measured 10 % faster than four.
@@ -373,7 +378,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
             }
         }
         wave_sync();
-        auto rmax = [&](int p0, int cnt) {
+        auto rmax = [&](int p0, int cnt) SFC_INLINE {
             float r = 0.0f;
             for (int q = 0; q < cnt; q++) r = fmaxf(r, hm[p0 + q]);
             return r;
@@ -422,7 +427,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
     }
     const Period per = wraps ? a.per : Period{};
     // minimum images of a pair's components on periodic axes
-    auto wrap = [&](float &dx, float &dy, float &dz) {
+    auto wrap = [&](float &dx, float &dy, float &dz) SFC_INLINE {
         if (wraps) wave_min_image(dx, dy, dz, a.per);
     };
 
@@ -454,7 +459,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
     uint32_t ej = 0, em = 0;
     uint32_t chunk = s;        // chunk being filled
     bool staged = true;        // false once the shared chunks ran out
-    auto flush = [&](uint32_t cnt) {
+    auto flush = [&](uint32_t cnt) SFC_INLINE {
         if (nj > cnt) {  // beyond the first chunk: take a shared one
             uint32_t id = kNoChunk;
             if (lane == 0 && staged) id = take_chunk(a.chunk_ctr, a.nshared, s);
@@ -497,7 +502,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
         float x, y, z, h;
         bool v;
     };
-    auto load_batch = [&](uint32_t b0, JLoad &f) {
+    auto load_batch = [&](uint32_t b0, JLoad &f) SFC_INLINE {
         const uint32_t e = b0 + (uint32_t)(lane / CS);
         const uint32_t cj = queue[e < qn ? e : qn - 1u].x;
         const int64_t p = (int64_t)cj * CS + (lane & (CS - 1));
@@ -508,17 +513,17 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
         f.z = a.z[pc];
         f.h = a.h[pc];
     };
-    auto batch_vals = [&](const JLoad &f) {
+    auto batch_vals = [&](const JLoad &f) SFC_INLINE {
         const float hh = f.v && !gather ? f.h : 0.0f;
         return make_float4(f.v ? f.x : kFar, f.v ? f.y : kFar, f.v ? f.z : kFar, hh * hh);
     };
-    auto lane_f = [](int src, float v) {  // v of lane src (ds_bpermute takes a byte address)
+    auto lane_f = [](int src, float v) SFC_INLINE {  // v of lane src (ds_bpermute takes a byte address)
         return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
     };
 
     // Cluster sizes 4 and 16: one step tests the 64 particle pairs of one
     // tile (CS = 4: four), the queued candidates one after another.
-    auto drain_regs = [&]() {
+    auto drain_regs = [&]() SFC_INLINE {
         wave_sync();
         JLoad f;
         load_batch(0, f);
@@ -543,7 +548,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
             // the j-cluster is one of our own i-clusters: exclude i == j
             // (full list) or keep only j > i (half list)
             const int self_c = (cjv >= own_c0 && cjv < own_c0 + kNsub) ? (int)(cjv - own_c0) : -1;
-            auto keep = [&](int ci, int ipos, int jpos) {
+            auto keep = [&](int ci, int ipos, int jpos) SFC_INLINE {
                 return half ? (ci < self_c || (ci == self_c && jpos > ipos)) : (ci != self_c || jpos != ipos);
             };
             uint32_t mask = 0;
@@ -625,7 +630,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
     __shared__ uint2 s_ent[kWavesPerBlock][kLaneTiles ? 8 : 1];
     __shared__ uint64_t s_hits[kWavesPerBlock][kLaneTiles ? 8 : 1];
     if constexpr (kLaneTiles) s_tile[w][lane] = 0u;  // entries past a batch's tiles stay valid offsets
-    auto drain_lanes = [&]() {
+    auto drain_lanes = [&]() SFC_INLINE {
         wave_sync();
         constexpr uint32_t kRow = 9 * sizeof(float4);  // one cluster's stride in s_ip and s_jp
         constexpr uint64_t kBytes = 0x0101010101010101ull;
@@ -733,7 +738,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
         wave_sync();
     };
 
-    auto drain = [&]() {
+    auto drain = [&]() SFC_INLINE {
         if constexpr (kLaneTiles)
             drain_lanes();
         else
