@@ -280,7 +280,7 @@ def run_hiter(args, sf, torch, ctx):
            "systems": results}
     if train:
         out["seed_training"] = train
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def run_batch(args, sf, torch, ctx):
@@ -400,7 +400,7 @@ def run_batch(args, sf, torch, ctx):
            "seeded_per_system": sseed, "speedup_vs_plain_per_system": plain["ms"] / best["ms"],
            "autotune": tuned, "seed_training": {"pairs": int(feat.shape[0]), "seconds": train_s,
                                                 "loss_first": losses[0], "loss_last": losses[-1]}}
-    print(json.dumps(out), flush=True)
+    return out
 
 
 def run_lj(args, sf, torch, ctx):
@@ -577,7 +577,8 @@ def main():
     ap.add_argument("--copy-probe", type=int, default=0,
                     help="after warm-up, copy this many MiB once (counter calibration)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-extra", action="store_true", help="skip the 32k and 8M build + pass figures")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 32k and 8M build + pass figures, the 8M "
+                                                             "h-iteration and the 64-system batch")
     ap.add_argument("--mode", choices=["step", "hiter", "batch", "lj", "rows"], default="step")
     ap.add_argument("--target", type=int, default=0, help="neighbour target (hiter 100, batch 150)")
     ap.add_argument("--nsys", type=int, default=64)
@@ -614,10 +615,10 @@ def main():
             run_rows(args, sf, torch, ctx)
         elif args.mode == "hiter":
             args.target = args.target or 100
-            run_hiter(args, sf, torch, ctx)
+            print(json.dumps(run_hiter(args, sf, torch, ctx)), flush=True)
         else:
             args.target = args.target or 150
-            run_batch(args, sf, torch, ctx)
+            print(json.dumps(run_batch(args, sf, torch, ctx)), flush=True)
         ctx.close()
         return
 
@@ -793,6 +794,22 @@ def run_step(args, sf, torch, ctx):
     }
     if not args.no_extra:
         out["configs"] = {name: extra_config(sf, torch, ctx, args, name) for name in ("uniform_32k", "evrard_8m")}
+        # the learned seed on the 8M sphere (and on its training generator at
+        # 8M) against the plain iteration, and the 64-system batch, each with
+        # one untimed and one timed run (the other modes' lines time more)
+        import copy
+        ha = copy.copy(args)
+        ha.steps, ha.warmup, ha.mlp, ha.target, ha.n = 1, 1, 1, 100, 0
+        hr = run_hiter(ha, sf, torch, ctx)
+        out["configs"]["evrard_8m_hiter"] = {k: hr[k] for k in ("metric", "value", "unit", "ms_per_step", "config",
+                                                               "systems", "seed_training")}
+        ba = copy.copy(args)
+        ba.steps, ba.warmup, ba.target = 1, 1, 150
+        br = run_batch(ba, sf, torch, ctx)
+        out["configs"]["batch_64"] = {k: br[k] for k in ("metric", "value", "unit", "ms_per_step", "config",
+                                                        "batched_seeded_graph", "plain_per_system",
+                                                        "batched_plain_graph", "seeded_per_system",
+                                                        "speedup_vs_plain_per_system", "autotune")}
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) on %d particles" % n)
         out["cpu_baseline"] = cpu_baseline(s)
