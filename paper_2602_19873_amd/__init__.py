@@ -251,10 +251,15 @@ def build_nlist(ctx: Context, keys, x, y, z, h, bbox, compress: bool = True, lea
                                  C.byref(o), _ptr(ws), ws.numel(), _ptr(sc_info), _ptr(pool), pool.numel() * 4,
                                  C.byref(used), C.byref(maxnj))
         if rc == _lib.E_CAPACITY and grow:
+            grown = False
             if maxnj.value > max_j_per_sc:
                 max_j_per_sc = int(maxnj.value)
+                grown = True
             if used.value > pool.numel() * 4:
                 pool = ctx.empty(used.value // 4 + 1024, torch.int32)
+                grown = True
+            if not grown:  # the reported sizes already held: retrying would not change anything
+                ctx.check(rc)
             continue
         ctx.check(rc)
         nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, used.value, maxnj.value,
@@ -376,6 +381,8 @@ def build_rows(ctx: Context, nl: NeighbourList, x, y, z, h, compress: bool = Tru
                                 _ptr(x), _ptr(y), _ptr(z), _ptr(h), int(bool(compress)), _period_arg(nl.period),
                                 _ptr(ws), ws.numel(), _ptr(row_info), _ptr(pool), pool.numel() * 4, C.byref(used))
         if rc == _lib.E_CAPACITY and grow:
+            if used.value <= pool.numel() * 4:  # the reported size already held: retrying would not change anything
+                ctx.check(rc)
             pool = ctx.empty(used.value // 4 + 1024, torch.int32)
             continue
         ctx.check(rc)
@@ -754,10 +761,15 @@ def batch_build_nlist(ctx: Context, b: Batch, keys, x, y, z, h, bbox, compress: 
                                              _ptr(bbox), C.byref(o), _ptr(ws), ws.numel(), _ptr(sc_info), _ptr(pool),
                                              pool.numel() * 4, C.byref(used), C.byref(maxnj))
         if rc == _lib.E_CAPACITY and grow:
+            grown = False
             if maxnj.value > max_j_per_sc:
                 max_j_per_sc = int(maxnj.value)
+                grown = True
             if used.value > pool.numel() * 4:
                 pool = ctx.empty(used.value // 4 + 1024, torch.int32)
+                grown = True
+            if not grown:  # the reported sizes already held: retrying would not change anything
+                ctx.check(rc)
             continue
         ctx.check(rc)
         nl = NeighbourList(n, cluster_size, bool(compress), sc_info[:nsc], pool, used.value, maxnj.value,
