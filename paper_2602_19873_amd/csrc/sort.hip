@@ -2,6 +2,7 @@
 // radix sort of (key, index), and the gather of particle fields.
 #include <mutex>
 
+#include "hilbert_table.h"
 #include "internal.h"
 
 namespace sfcnl {
@@ -11,51 +12,34 @@ namespace {
 // Hilbert keys
 // ---------------------------------------------------------------------------
 
-// Bit b of v (21 bits) moves to bit 3b.
-__device__ __forceinline__ uint64_t spread3(uint32_t v) {
-    uint64_t x = v & 0x1fffffu;
-    x = (x | (x << 32)) & 0x001f00000000ffffull;
-    x = (x | (x << 16)) & 0x001f0000ff0000ffull;
-    x = (x | (x << 8)) & 0x100f00f00f00f00full;
-    x = (x | (x << 4)) & 0x10c30c30c30c30c3ull;
-    x = (x | (x << 2)) & 0x1249249249249249ull;
-    return x;
+// The key tables (hilbert_table.h) in device memory; each block that makes
+// keys copies them into LDS, where the lanes' lookups land at random.
+__device__ const hilbert::Tables kHilbertTables = hilbert::kTables;
+constexpr int kHilbertWords = (int)(sizeof(hilbert::Tables) / 4);  // 16-bit entries, two per word
+
+// Cooperative copy of the key tables into LDS (the caller synchronises).
+__device__ __forceinline__ void hilbert_tables_to_lds(uint32_t *s_tab) {
+    const uint32_t *g = reinterpret_cast<const uint32_t *>(&kHilbertTables);
+    for (int i = (int)threadIdx.x; i < kHilbertWords; i += (int)blockDim.x) s_tab[i] = g[i];
 }
 
-// Hilbert index of a 21-bit cell (Skilling 2004, transpose form): walk the
-// levels from the top, at each level inverting or exchanging the lower bits
-// of axis 0 against every axis, then Gray-encode across the axes, then read
-// the transposed words out with axis 0 as the top bit of each 3-bit digit.
-__device__ __forceinline__ uint64_t hilbert_key(uint32_t a0, uint32_t a1, uint32_t a2) {
+// Hilbert key of a 21-bit cell (a0, a1, a2) from the tables in LDS: the top
+// level from the start state, then the levels two at a time (11 lookups);
+// digit k (axis 0 in its top bit) lands at key bits 3k .. 3k + 2.
+__device__ __forceinline__ uint64_t hilbert_key(uint32_t a0, uint32_t a1, uint32_t a2, const uint32_t *s_tab) {
+    const hilbert::Tables &T = *reinterpret_cast<const hilbert::Tables *>(s_tab);
+    uint32_t e = T.start[((a0 >> 20) & 1u) << 2 | ((a1 >> 20) & 1u) << 1 | ((a2 >> 20) & 1u)];
+    uint64_t key = e & 7u;
+    uint32_t st = e >> 3;
 #pragma unroll
-    for (int b = 20; b >= 1; b--) {
-        const uint32_t q = 1u << b, low = q - 1u;
-        if (a0 & q) a0 ^= low;
-        uint32_t t1 = (a0 ^ a1) & low;
-        if (a1 & q) {
-            a0 ^= low;
-        } else {
-            a0 ^= t1;
-            a1 ^= t1;
-        }
-        uint32_t t2 = (a0 ^ a2) & low;
-        if (a2 & q) {
-            a0 ^= low;
-        } else {
-            a0 ^= t2;
-            a2 ^= t2;
-        }
+    for (int k = 18; k >= 0; k -= 2) {
+        const uint32_t o = __builtin_amdgcn_ubfe(a0, k, 2) << 4 | __builtin_amdgcn_ubfe(a1, k, 2) << 2 |
+                           __builtin_amdgcn_ubfe(a2, k, 2);
+        e = T.pair[st << 6 | o];
+        key = key << 6 | (e & 63u);
+        st = e >> 6;
     }
-    a1 ^= a0;
-    a2 ^= a1;
-    uint32_t flip = 0;
-#pragma unroll
-    for (int b = 20; b >= 1; b--)
-        if (a2 & (1u << b)) flip ^= (1u << b) - 1u;
-    a0 ^= flip;
-    a1 ^= flip;
-    a2 ^= flip;
-    return (spread3(a0) << 2) | (spread3(a1) << 1) | spread3(a2);
+    return key;
 }
 
 __device__ __forceinline__ uint32_t quantise(float x, float lo, float s) {
@@ -64,18 +48,6 @@ __device__ __forceinline__ uint32_t quantise(float x, float lo, float s) {
     if (!(t > 0.0f)) return 0u;
     if (t >= 2097151.0f) return 2097151u;
     return (uint32_t)t;
-}
-
-__global__ __launch_bounds__(256) void k_keys(int64_t n, const float *__restrict__ x, const float *__restrict__ y,
-                                              const float *__restrict__ z, float lox, float sx, float loy, float sy,
-                                              float loz, float sz, uint64_t *__restrict__ keys,
-                                              uint32_t *__restrict__ idx, uint32_t *status) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    float px = x[i], py = y[i], pz = z[i];
-    if (!(isfinite(px) && isfinite(py) && isfinite(pz))) atomicOr(&status[kStInputErr], 1u);
-    keys[i] = hilbert_key(quantise(px, lox, sx), quantise(py, loy, sy), quantise(pz, loz, sz));
-    idx[i] = (uint32_t)i;
 }
 
 // ---------------------------------------------------------------------------
@@ -329,6 +301,7 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys_hist(int64_t n, const flo
                                                             uint32_t *__restrict__ idx, uint32_t ntiles,
                                                             uint32_t *__restrict__ hist, uint32_t *status) {
     __shared__ uint32_t s_h[kRadix];
+    __shared__ uint32_t s_tab[kHilbertWords];
     const int t = threadIdx.x;
     if (t < kRadix) s_h[t] = 0;
     const int64_t base = (int64_t)blockIdx.x * kTile;
@@ -341,6 +314,7 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys_hist(int64_t n, const flo
         py[k] = y[ic];
         pz[k] = z[ic];
     }
+    hilbert_tables_to_lds(s_tab);
     __syncthreads();
     bool bad = false;
 #pragma unroll
@@ -348,7 +322,8 @@ __global__ __launch_bounds__(kKeysThreads) void k_keys_hist(int64_t n, const flo
         const int64_t i = base + k * kKeysThreads + t;
         if (i < n) {
             if (!(isfinite(px[k]) && isfinite(py[k]) && isfinite(pz[k]))) bad = true;
-            const uint64_t key = hilbert_key(quantise(px[k], lox, sx), quantise(py[k], loy, sy), quantise(pz[k], loz, sz));
+            const uint64_t key =
+                hilbert_key(quantise(px[k], lox, sx), quantise(py[k], loy, sy), quantise(pz[k], loz, sz), s_tab);
             keys[i] = key;
             idx[i] = (uint32_t)i;
             atomicAdd(&s_h[(uint32_t)(key >> kPreShift) & 255u], 1u);
@@ -786,13 +761,16 @@ __global__ __launch_bounds__(256) void k_batch_keys(int64_t n, const float *__re
                                                     const float *__restrict__ lo, const float *__restrict__ sc,
                                                     uint64_t *__restrict__ keys, uint32_t *__restrict__ idx,
                                                     uint32_t *status) {
+    __shared__ uint32_t s_tab[kHilbertWords];
+    hilbert_tables_to_lds(s_tab);
+    __syncthreads();
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     const uint32_t sy = system_of((uint32_t)i, in_off, nsys);
     float px = x[i], py = y[i], pz = z[i];
     if (!(isfinite(px) && isfinite(py) && isfinite(pz))) atomicOr(&status[kStInputErr], 1u);
     keys[i] = hilbert_key(quantise(px, lo[3 * sy], sc[3 * sy]), quantise(py, lo[3 * sy + 1], sc[3 * sy + 1]),
-                          quantise(pz, lo[3 * sy + 2], sc[3 * sy + 2]));
+                          quantise(pz, lo[3 * sy + 2], sc[3 * sy + 2]), s_tab);
     idx[i] = (uint32_t)i;
 }
 
