@@ -10,17 +10,19 @@
 // and the list is sorted without a sort (Sec. II-A). At a leaf, 64 lanes test
 // the i-cluster boxes against the boxes of the leaf's candidate j-clusters;
 // each candidate with a nonempty i-cluster mask joins an LDS queue. Once 64
-// are queued (and at the end) the queue is drained in order: every candidate
-// loads its own j-particles (the next candidate's load overlapping the
-// current one's tests) and each i-cluster of its mask gets one 64-lane step
-// of exact particle tests (lane (il, jl) = (lane / 8, lane % 8) holds
-// particle il of every i-cluster). Box tests are conservative under FP32
-// rounding (rounding is monotone), so they never drop a pair the exact test
-// keeps; the masks are exact.
+// are queued (and at the end) the queue is drained in order, the
+// j-particles of a batch of queued candidates arriving with one load per
+// field while the previous batch's tests run. For cluster size 8 the exact
+// tests are lane-parallel over the batch's (candidate, i-cluster) tiles: a
+// group of 8 lanes takes one tile and steps through its 8 j-particles (see
+// drain_lanes); sizes 4 and 16 give each tile one 64-lane step. Box tests
+// are conservative under FP32 rounding (rounding is monotone), so they
+// never drop a pair the exact test keeps; the masks are exact.
 //
 // The list is staged in 64-entry chunks with its encoded size computed on the
-// fly, a prefix sum places the super-clusters in order, and a second kernel
-// writes masks and nibble segments.
+// fly (a super-cluster's first chunk is its own, later ones come from 64
+// striped counters), a prefix sum places the super-clusters in order, and a
+// second kernel writes masks and nibble segments.
 #include <cstring>
 
 #include <utility>
@@ -186,7 +188,7 @@ struct TravArgs {
     uint16_t *list_m;
     uint32_t *chunk_next;
     uint32_t nshared;      // shared chunks (ids 0 .. nshared - 1)
-    uint32_t *chunk_ctr;   // the stripe counters that hand them out, word 1 of each the stripe's longest list (zeroed before the build)
+    uint32_t *chunk_ctr;   // the stripe counters that hand them out; word 1 of each line holds the stripe's longest list (zeroed before the build)
     uint32_t *sc_nj, *sc_words;
     uint32_t *status;
 };
@@ -657,7 +659,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
             // s_hits[r]: round r's ballot (byte g: group g, i.e. tile 8r + g,
             // saw a pair); bytes of tiles past T are never read
             for (int r = 0; 8 * r < T; r++) {
-                const uint32_t tv = s_tile[w][8 * r + g];  // tiles past T: stale, masked below
+                const uint32_t tv = s_tile[w][8 * r + g];  // tiles past T: stale valid offsets, results unread
                 const uint32_t ioff = tv & 0x7FFu, soff = (tv >> 11) & 0x7FFu;
                 const float4 ip = *reinterpret_cast<const float4 *>(ipb + ioff);
                 // lane (g, l) holds j-particles l % 4 and 4 + l % 4 of its

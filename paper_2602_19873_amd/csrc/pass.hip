@@ -5,9 +5,11 @@
 // on one wavefront and accumulate the SPH density and the neighbour count.
 //
 // Lane (il, jl) = (lane / 8, lane % 8) keeps i-particle il of every i-cluster
-// in registers and loads j-particle jl of the current j-cluster, so a tile is
+// in registers and takes j-particle jl of the current j-cluster, so a tile is
 // one 64-lane step with no cross-lane traffic; the 8 partial sums per
-// i-particle are combined once at the end.
+// i-particle are combined once at the end. (The symmetric pass puts the
+// i-side in the low lane bits instead, and for cluster size 8 takes its list
+// entries in batches of 8; see k_pass_half.)
 #include "internal.h"
 #include "pass_common.h"
 
@@ -100,9 +102,9 @@ __device__ __forceinline__ void tile_pair(float xj, float yj, float zj, float mj
 // latency than five without spills: measured 8 % faster for either list
 // form. The symmetric pass of cluster size 8, which takes its entries in
 // batches, needs more registers and runs five waves (2 registers spilled
-// with compression; six waves spilled more and ran 2 % slower). Cluster size 16 holds four
-// j-particles per lane; under the same cap it spills heavily, so it keeps
-// its own register count.
+// with compression; six waves spilled more and ran 2 % slower). Cluster size
+// 16 holds four j-particles per lane; under the same cap it spills heavily,
+// so it keeps its own register count.
 template <int CS, bool kCompress, bool kMass, bool kCount, bool kPbc>
 __global__ __launch_bounds__(kWave * kPassWavesMax) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 1 : 6))) void k_pass(PassArgs a) {
     constexpr int kNsub = kScSize / CS;
@@ -327,10 +329,10 @@ __global__ __launch_bounds__(kWave * kPassWavesMax) __attribute__((amdgpu_waves_
     // (one load per field for the batch; loading the next batch behind the
     // current one's tiles measured slower, the extra registers spilled),
     // derives its squared radius and reciprocal once and leaves them in LDS,
-    // where the tile lanes of entry q read
-    // j-particle jq. Every tile lane's j-side partial sum and count of an
-    // entry go to LDS too, and after the batch lane (q, r) adds the 8 partials
-    // of its particle and updates rho and nnb with one atomic each.
+    // where the tile lanes of entry q read j-particle jq. Every tile lane's
+    // j-side partial sum and count of an entry go to LDS too, and after the
+    // batch lane (q, r) adds the 8 partials of its particle and updates rho
+    // and nnb with one atomic each.
     // this wave's LDS (one wave-uniform base; the arrays at fixed offsets)
     extern __shared__ float4 s_pass_dyn[];
     float *const s_base = reinterpret_cast<float *>(s_pass_dyn) +
