@@ -8,7 +8,10 @@
 // that share an i-particle at the end and stored. Half list: lane roles of
 // the symmetric density pass; each stored pair adds its force to i and the
 // opposite force to j (Newton's third law), the j side reduced over its DPP
-// row group before one atomic per component.
+// row group before one atomic per component. At cluster size 8 both passes
+// take list entries 8 at a time, their j-particles fetched into LDS with one
+// load per field, and the half pass adds the j sums of 8 entries with one
+// atomic per lane and component.
 //
 // Absent i-particles sit at +kAway and absent j-particles at -kAway: every
 // squared distance that involves one overflows to +inf and fails the cutoff
@@ -42,6 +45,12 @@ struct LjArgs {
     float *fx, *fy, *fz, *ep;
     Period per;   // periodic axes (used by the kPbc kernels)
 };
+
+// orders a wave's LDS accesses around it (the wave runs in lockstep)
+__device__ __forceinline__ void lj_wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
 
 // minimum images of a pair's components on periodic axes
 template <bool kPbc>
@@ -136,6 +145,39 @@ __global__ __launch_bounds__(kWave * kLjWaves) __attribute__((amdgpu_waves_per_e
             qj[t] = kQ ? (vj ? a.q[jp] : 0.0f) : 0.0f;
         }
     };
+    // Cluster size 8: the entries of a decoded segment 8 at a time. Lane
+    // (q, r) = (lane / 8, lane % 8) loads particle r of the batch's entry q
+    // (one load per field for the batch) into LDS, where the tile lanes of
+    // entry q read j-particle jl.
+    __shared__ float4 s_jb[kLjWaves][CS == 8 ? kWave : 1];  // x, y, z, charge
+    auto entries8 = [&](uint32_t mvl, uint32_t jvl, uint32_t cnt) __attribute__((always_inline)) {
+        const int il = lane >> 3;
+        for (uint32_t q0 = 0; q0 < cnt; q0 += 8) {
+            const uint32_t e = q0 + (uint32_t)(lane >> 3);
+            const bool ev = e < cnt;
+            const uint32_t cjb = (uint32_t)__shfl((int)jvl, (int)(ev ? e : q0), kWave);
+            const uint32_t pq = cjb * CS + (uint32_t)(lane & 7);  // n < 2^31
+            const bool pv = ev && pq < n;
+            const uint32_t pc = pq < n ? pq : (uint32_t)(n - 1);  // loads of a clamped index go out together
+            const float bx = a.x[pc], by = a.y[pc], bz = a.z[pc];
+            const float bq = kQ ? a.q[pc] : 0.0f;
+            lj_wave_sync();  // the previous batch's reads are done
+            s_jb[w][lane] = make_float4(pv ? bx : -kAway, pv ? by : -kAway, pv ? bz : -kAway, pv ? bq : 0.0f);
+            lj_wave_sync();
+            const uint32_t bn = cnt - q0 < 8u ? cnt - q0 : 8u;
+            for (uint32_t q = 0; q < bn; q++) {
+                const uint32_t mk = sfc_readlane(mvl, (int)(q0 + q));
+                const uint32_t cj = sfc_readlane(jvl, (int)(q0 + q));
+                const float4 jb = s_jb[w][q * 8 + jl];
+                const int self_c = (cj >= own_c0 && cj < own_c0 + kNsub) ? (int)(cj - own_c0) : -1;
+#pragma unroll
+                for (int c = 0; c < kNreg; c++)
+                    if ((mk >> c) & 1u)
+                        lj_tile<kQ, kE, kPbc>(jb.x, jb.y, jb.z, jb.w, ix[c], iy[c], iz[c], ikq[c], c == self_c && il == jl, a,
+                                              gx[c], gy[c], gz[c], ge[c]);
+            }
+        }
+    };
     for (uint32_t b0 = 0; b0 < nj; b0 += kWave) {
         const uint32_t cnt = nj - b0 < (uint32_t)kWave ? nj - b0 : (uint32_t)kWave;
         uint32_t jv;
@@ -146,6 +188,10 @@ __global__ __launch_bounds__(kWave * kLjWaves) __attribute__((amdgpu_waves_per_e
         uint32_t mv = 0u;
         if ((uint32_t)lane < cnt) mv = CS == 4 ? (uint32_t)mshorts[b0 + lane] : (uint32_t)mbytes[b0 + lane];
         prevj = sfc_readlane(jv, (int)cnt - 1);
+        if constexpr (CS == 8) {
+            entries8(mv, jv, cnt);
+            continue;
+        }
         // the next entry's j-particles load while the current entry's tiles run
         uint32_t cj = sfc_readlane(jv, 0);
         float xj[kNj], yj[kNj], zj[kNj], qj[kNj];
@@ -222,8 +268,10 @@ __global__ __launch_bounds__(kWave * kLjWaves) __attribute__((amdgpu_waves_per_e
     }
 }
 
+// The batched entries of cluster size 8 need more registers: five waves per
+// SIMD without spills run faster than six with them.
 template <int CS, bool kCompress, bool kQ, bool kE, bool kPbc>
-__global__ __launch_bounds__(kWave * kLjWaves) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 1 : 6))) void k_pass_lj_half(LjArgs a) {
+__global__ __launch_bounds__(kWave * kLjWaves) __attribute__((amdgpu_waves_per_eu(CS == 16 ? 1 : (CS == 8 ? 5 : 6)))) void k_pass_lj_half(LjArgs a) {
     constexpr int kNsub = kScSize / CS;
     constexpr int kNreg = CS == 8 ? 8 : 4;
     constexpr int kNj = CS == 16 ? 4 : 1;
@@ -253,6 +301,93 @@ __global__ __launch_bounds__(kWave * kLjWaves) __attribute__((amdgpu_waves_per_e
     const uint32_t off = a.sc_info[2 * s], nj = a.sc_info[2 * s + 1];
     const uint8_t *mbytes = reinterpret_cast<const uint8_t *>(a.pool + off);
     const uint16_t *mshorts = reinterpret_cast<const uint16_t *>(a.pool + off);
+    // Cluster size 8: the entries of a decoded segment 8 at a time. Lane
+    // (q, r) = (lane / 8, lane % 8) loads particle r of the batch's entry q
+    // (one load per field for the batch) and leaves it in LDS, where the tile
+    // lanes of entry q read j-particle jq. An entry's j-side sums (over the 8
+    // lanes of each j-particle, by DPP) and whether the j-particle formed a
+    // pair go to LDS too, and after the batch lane (q, r) adds its particle's
+    // sums with one atomic per component.
+    __shared__ float4 s_jb[kLjWaves][CS == 8 ? kWave : 1];  // x, y, z, charge
+    __shared__ float4 s_jh[kLjWaves][CS == 8 ? kWave : 1];  // j-side force (and energy) sums
+    __shared__ uint32_t s_jhit[kLjWaves][CS == 8 ? kWave : 1];
+    auto entries8 = [&](uint32_t mvl, uint32_t jvl, uint32_t cnt) __attribute__((always_inline)) {
+        const int il = lane & 7;
+        for (uint32_t q0 = 0; q0 < cnt; q0 += 8) {
+            const uint32_t e = q0 + (uint32_t)(lane >> 3);
+            bool ev = e < cnt;
+            const uint32_t cjb = (uint32_t)__shfl((int)jvl, (int)(ev ? e : q0), kWave);
+            const uint32_t pq = cjb * CS + (uint32_t)(lane & 7);  // n < 2^31
+            ev = ev && pq < n;
+            const uint32_t pc = pq < n ? pq : (uint32_t)(n - 1);  // loads of a clamped index go out together
+            const float bx = a.x[pc], by = a.y[pc], bz = a.z[pc];
+            const float bq = kQ ? a.q[pc] : 0.0f;
+            s_jb[w][lane] = make_float4(ev ? bx : -kAway, ev ? by : -kAway, ev ? bz : -kAway, ev ? bq : 0.0f);
+            lj_wave_sync();
+            const uint32_t bn = cnt - q0 < 8u ? cnt - q0 : 8u;
+            for (uint32_t q = 0; q < bn; q++) {
+                const uint32_t mk = sfc_readlane(mvl, (int)(q0 + q));
+                const uint32_t cj = sfc_readlane(jvl, (int)(q0 + q));
+                const float4 jb = s_jb[w][q * 8 + jq];
+                float hx = 0.0f, hy = 0.0f, hz = 0.0f, he = 0.0f;
+                uint64_t jm = 0;  // lanes that formed a pair
+                // inside the super-cluster only j > i counts
+                const int self_c = (cj >= own_c0 && cj < own_c0 + kNsub) ? (int)(cj - own_c0) : -1;
+#pragma unroll
+                for (int c = 0; c < kNreg; c++) {
+                    if (!((mk >> c) & 1u)) continue;
+                    const bool kp = self_c < 0 || c < self_c || (c == self_c && jq > il);
+                    float dx = jb.x - ix[c];
+                    float dy = jb.y - iy[c];
+                    float dz = jb.z - iz[c];
+                    wrap3<kPbc>(dx, dy, dz, a.per);
+                    const float dxx = dx * dx;
+                    const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
+                    const bool in = kp && d2 < a.rc2;
+                    const uint64_t bal = sfc_ballot(in);
+                    if (bal) {
+                        jm |= bal;
+                        float fr, u = 0.0f;
+                        lj_factor<kQ, kE>(d2, ikq[c] * jb.w, a, fr, u);
+                        fr = in ? fr : 0.0f;
+                        const float px = fr * dx, py = fr * dy, pz = fr * dz;
+                        gx[c] += px;
+                        gy[c] += py;
+                        gz[c] += pz;
+                        hx += px;
+                        hy += py;
+                        hz += pz;
+                        if (kE) {
+                            const float uu = in ? u : 0.0f;
+                            ge[c] += uu;
+                            he += uu;
+                        }
+                    }
+                }
+                if (jm) {
+                    group_sum<kIL>(hx);
+                    group_sum<kIL>(hy);
+                    group_sum<kIL>(hz);
+                    if (kE) group_sum<kIL>(he);
+                }
+                if (il == 0) {
+                    s_jh[w][q * 8 + jq] = make_float4(hx, hy, hz, he);
+                    s_jhit[w][q * 8 + jq] = ((jm >> (8 * jq)) & 0xFFull) != 0 ? 1u : 0u;
+                }
+            }
+            lj_wave_sync();
+            // lane (q, r): j-particle r of entry q
+            if (ev && (uint32_t)(lane >> 3) < bn && s_jhit[w][lane]) {
+                const float4 hv = s_jh[w][lane];
+                atomicAdd(&a.fx[pq], hv.x);
+                atomicAdd(&a.fy[pq], hv.y);
+                atomicAdd(&a.fz[pq], hv.z);
+                if (kE) atomicAdd(&a.ep[pq], 0.5f * hv.w);
+            }
+            lj_wave_sync();  // the next batch rewrites the LDS arrays
+        }
+    };
+
     uint32_t p = off + (nj * (CS == 4 ? 2u : 1u) + 3u) / 4u;
     uint32_t prevj = 0xFFFFFFFFu;
     for (uint32_t b0 = 0; b0 < nj; b0 += kWave) {
@@ -265,6 +400,10 @@ __global__ __launch_bounds__(kWave * kLjWaves) __attribute__((amdgpu_waves_per_e
         uint32_t mv = 0u;
         if ((uint32_t)lane < cnt) mv = CS == 4 ? (uint32_t)mshorts[b0 + lane] : (uint32_t)mbytes[b0 + lane];
         prevj = sfc_readlane(jv, (int)cnt - 1);
+        if constexpr (CS == 8) {
+            entries8(mv, jv, cnt);
+            continue;
+        }
         float nx[kNj], ny[kNj], nz[kNj], nq[kNj];
         auto load_j = [&](uint32_t cjn) {
 #pragma unroll
