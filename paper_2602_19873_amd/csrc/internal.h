@@ -228,11 +228,15 @@ struct Octree {
 };
 
 void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket, int nsys, int cs);
+// clear / nclear: device words the build's first launch zeroes on the way
+// (counters of the caller that must start at zero), or none.
 int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x, const float *y,
-                 const float *z, const float *h, const float4 *cluster_box, const SegTable &seg);
+                 const float *z, const float *h, const float4 *cluster_box, const SegTable &seg,
+                 uint32_t *clear = nullptr, int nclear = 0);
 // The two halves of octree_build: the nodes, ranges and child slots from the
 // sorted keys alone, then the node boxes from the cluster boxes and particles.
-int octree_topology(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const SegTable &seg);
+int octree_topology(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const SegTable &seg, uint32_t *clear = nullptr,
+                    int nclear = 0);
 int octree_geometry(sfcnl_ctx ctx, Octree &t, const float *x, const float *y, const float *z, const float *h,
                     const float4 *cluster_box, const SegTable &seg);
 

@@ -1111,11 +1111,18 @@ int sfcnl::nlist_build_impl(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, co
     const uint32_t nclu = (uint32_t)((n + cs - 1) / cs);
     hipStream_t st = ctx->stream;
 
-    int rc = fill_u32(ctx, ctx->d_status + kStPoolOverflow, kStatusAlloc - kStPoolOverflow, 0);  // with the stripe counters
-    if (rc) return rc;
-    if (!reuse_tree) {  // else the tree of the previous build (same keys and bucket) serves
+    // the status words and stripe counters start at zero: cleared by the
+    // octree's first launch, or by a fill when the tree is reused
+    uint32_t *const st_clear = ctx->d_status + kStPoolOverflow;
+    const int st_nclear = kStatusAlloc - kStPoolOverflow;
+    int rc = SFCNL_OK;
+    if (reuse_tree) {  // the tree of the previous build (same keys and bucket) serves
+        rc = fill_u32(ctx, st_clear, st_nclear, 0);
+        if (rc) return rc;
+    } else {
         prof_mark(ctx, kStageOctree, false);
-        rc = octree_build(ctx, ws.tree, d_keys, d_x, d_y, d_z, d_h, reinterpret_cast<const float4 *>(d_bbox), seg);
+        rc = octree_build(ctx, ws.tree, d_keys, d_x, d_y, d_z, d_h, reinterpret_cast<const float4 *>(d_bbox), seg,
+                          st_clear, st_nclear);
         if (rc) return rc;
         if (per.on()) {
             k_check_span<<<1, 1, 0, st>>>(ws.tree.cs_box, per, ctx->d_status);

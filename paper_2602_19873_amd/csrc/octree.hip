@@ -58,11 +58,16 @@ __device__ __forceinline__ void seg_range(const SegTable &seg, int64_t p, int64_
 // width d, entry k holds the largest of the d values from k on, and two
 // overlapping runs of the largest width d <= bucket + 1 cover the window.
 // Also writes the common digits with the previous key (cdig) and the block's
-// node count (nodes start at p for the levels (cdig, leaf level]).
+// node count (nodes start at p for the levels (cdig, leaf level]). Block 0
+// also zeroes the nclear words at clear (the caller's counters that must start
+// at zero; this saves their own launch).
 __global__ __launch_bounds__(256) void k_leaf_level(const uint64_t *__restrict__ keys, int64_t n, int bucket,
                                                     SegTable seg, int8_t *__restrict__ cdig,
-                                                    int8_t *__restrict__ lleaf, uint32_t *__restrict__ blk) {
+                                                    int8_t *__restrict__ lleaf, uint32_t *__restrict__ blk,
+                                                    uint32_t *__restrict__ clear, int nclear) {
     constexpr int kSpan = 256 + kMaxBucket;
+    if (blockIdx.x == 0)
+        for (int k = threadIdx.x; k < nclear; k += 256) clear[k] = 0u;
     __shared__ int8_t s_tab[2][kSpan];
     __shared__ uint32_t s_w[256 / kWave];
     const int len = 256 + bucket;
@@ -311,6 +316,19 @@ struct BoxLevels {
 // parent's children otherwise (other systems' roots have no slot; their
 // records are kept apart). The traversal reads everything about a child with
 // one round trip.
+//
+// A node's range [first, end) leaves, at level l (level 0: particles; level
+// l >= 1: the boxes of L.lvl[l - 1], each covering 2^sh particles), the whole
+// units [A, B) with A = ceil(first / 2^sh) and B = floor(end / 2^sh); of
+// these, the level takes the ragged ones at both ends (those whose unit of
+// the next level is not whole inside), and the coarsest level takes them
+// all. So every (level, end) part is known up front: 16 lanes share a node,
+// lane q taking the parts q, q + 16, ... (part 2l + e: level l, end e), with
+// its loads issued together, and the lanes then join their boxes. Minimum
+// and maximum are exact and idempotent, so neither the order of the joins
+// nor the repeats of a clamped index change the box.
+constexpr int kSlotLanes = 16;
+
 __global__ __launch_bounds__(256) void k_node_slots(const uint32_t *__restrict__ d_nnodes, uint32_t cap,
                                                     const uint32_t *__restrict__ nfirst,
                                                     const uint32_t *__restrict__ nend,
@@ -323,7 +341,10 @@ __global__ __launch_bounds__(256) void k_node_slots(const uint32_t *__restrict__
                                                     BoxLevels L, float4 *__restrict__ cs_box,
                                                     uint4 *__restrict__ cs_rec) {
     const uint32_t nn = node_count(d_nnodes, cap);
-    for (uint32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < nn; k += gridDim.x * blockDim.x) {
+    const int q = threadIdx.x % kSlotLanes;
+    const uint32_t gstride = gridDim.x * (blockDim.x / kSlotLanes);
+    // a node's lanes share k and so every branch below
+    for (uint32_t k = (blockIdx.x * blockDim.x + threadIdx.x) / kSlotLanes; k < nn; k += gstride) {
         uint32_t slot;
         if (nlevel[k] == 0) {
             if (k != 0) continue;  // another system's root
@@ -333,40 +354,72 @@ __global__ __launch_bounds__(256) void k_node_slots(const uint32_t *__restrict__
             if (slot >= cap) continue;  // only on a broken tree (reported elsewhere)
         }
         const uint32_t first = nfirst[k], end = nend[k];
-        uint64_t a = first, b = end;
         float4 lo = make_float4(INFINITY, INFINITY, INFINITY, 0.0f);
         float4 hi = make_float4(-INFINITY, -INFINITY, -INFINITY, 0.0f);
-        // ragged particles at both ends
-        const uint64_t cm = (1u << L.cshift) - 1u;
-        while (a < b && (a & cm)) {
-            add_box(lo, hi, make_float4(x[a], y[a], z[a], h[a]), make_float4(x[a], y[a], z[a], 0.0f));
-            a++;
-        }
-        while (b > a && (b & cm)) {
-            b--;
-            add_box(lo, hi, make_float4(x[b], y[b], z[b], h[b]), make_float4(x[b], y[b], z[b], 0.0f));
-        }
-        // [a, b) is now empty or whole clusters (both ends multiples of cs)
-        a >>= L.cshift;
-        b >>= L.cshift;
-        // whole groups, coarsening one level at a time
-        for (int l = 0; l < L.nlvl && a < b; l++) {
-            const float4 *bx = L.lvl[l];
-            const bool last = l + 1 == L.nlvl;
-            while (a < b && (last || (a & 7u))) {
-                add_box(lo, hi, bx[2 * a], bx[2 * a + 1]);
-                a++;
+        for (int part = q; part < 2 * (L.nlvl + 1); part += kSlotLanes) {
+            const int l = part >> 1;
+            const int sh = l == 0 ? 0 : L.cshift + 3 * (l - 1);
+            const uint64_t A = ((uint64_t)first + ((1ull << sh) - 1ull)) >> sh;
+            const uint64_t B = (uint64_t)end >> sh;
+            if (A >= B) continue;
+            // the ragged units: [A, f) at the front, [b, B) at the back
+            uint64_t i0, i1;
+            if (l == L.nlvl) {  // the coarsest level takes all (with the front part)
+                i0 = A;
+                i1 = (part & 1) ? A : B;
+            } else {
+                const uint64_t m = l == 0 ? (1ull << L.cshift) - 1ull : 7ull;
+                const uint64_t f = ((A + m) & ~m) < B ? (A + m) & ~m : B;
+                const uint64_t b = (B & ~m) > f ? B & ~m : f;
+                i0 = (part & 1) ? b : A;
+                i1 = (part & 1) ? B : f;
             }
-            while (b > a && (last || (b & 7u))) {
-                b--;
-                add_box(lo, hi, bx[2 * b], bx[2 * b + 1]);
+            if (l == 0) {
+                for (uint64_t t0 = i0; t0 < i1; t0 += 4) {
+                    float px[4], py[4], pz[4], ph[4];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const uint64_t t = t0 + u < i1 ? t0 + u : i1 - 1;
+                        px[u] = x[t];
+                        py[u] = y[t];
+                        pz[u] = z[t];
+                        ph[u] = h[t];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; u++)
+                        add_box(lo, hi, make_float4(px[u], py[u], pz[u], ph[u]), make_float4(px[u], py[u], pz[u], 0.0f));
+                }
+            } else {
+                const float4 *bx = L.lvl[l - 1];
+                for (uint64_t t0 = i0; t0 < i1; t0 += 4) {
+                    float4 bl[4], bh[4];
+#pragma unroll
+                    for (int u = 0; u < 4; u++) {
+                        const uint64_t t = t0 + u < i1 ? t0 + u : i1 - 1;
+                        bl[u] = bx[2 * t];
+                        bh[u] = bx[2 * t + 1];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 4; u++) add_box(lo, hi, bl[u], bh[u]);
+                }
             }
-            a >>= 3;
-            b >>= 3;
         }
-        cs_box[2 * (size_t)slot] = lo;
-        cs_box[2 * (size_t)slot + 1] = hi;
-        cs_rec[slot] = make_uint4(first, end, nnchild[k], 1u + cbase[k]);
+        // join the lanes' boxes (groups of kSlotLanes aligned lanes)
+#pragma unroll
+        for (int d = 1; d < kSlotLanes; d <<= 1) {
+            lo.x = fminf(lo.x, __shfl_xor(lo.x, d, kSlotLanes));
+            lo.y = fminf(lo.y, __shfl_xor(lo.y, d, kSlotLanes));
+            lo.z = fminf(lo.z, __shfl_xor(lo.z, d, kSlotLanes));
+            lo.w = fmaxf(lo.w, __shfl_xor(lo.w, d, kSlotLanes));
+            hi.x = fmaxf(hi.x, __shfl_xor(hi.x, d, kSlotLanes));
+            hi.y = fmaxf(hi.y, __shfl_xor(hi.y, d, kSlotLanes));
+            hi.z = fmaxf(hi.z, __shfl_xor(hi.z, d, kSlotLanes));
+        }
+        if (q == 0) {
+            cs_box[2 * (size_t)slot] = lo;
+            cs_box[2 * (size_t)slot + 1] = hi;
+            cs_rec[slot] = make_uint4(first, end, nnchild[k], 1u + cbase[k]);
+        }
     }
 }
 
@@ -443,7 +496,7 @@ void octree_carve(Carver &cv, Octree &t, int64_t n, int bucket, int nsys, int cs
     t.scan_tmp = cv.take<char>(scan_tmp_bytes((int64_t)blocks_for(n, 256) + 1));
 }
 
-int octree_topology(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const SegTable &seg) {
+int octree_topology(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const SegTable &seg, uint32_t *clear, int nclear) {
     const int64_t n = t.n;
     const int B = t.bucket;
     if (B < 1 || B > kMaxBucket) return set_err(ctx, SFCNL_E_ARG, "octree: bucket %d out of range", B);
@@ -451,7 +504,7 @@ int octree_topology(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const SegTab
     const unsigned gp = blocks_for(n, 256);
     // leaf levels and per-block node counts, their prefix sum (the total is
     // the node count), then the nodes in depth-first pre-order
-    k_leaf_level<<<gp, 256, 0, st>>>(keys, n, B, seg, t.cdig, t.lleaf, t.blk);
+    k_leaf_level<<<gp, 256, 0, st>>>(keys, n, B, seg, t.cdig, t.lleaf, t.blk, clear, clear ? nclear : 0);
     SFCNL_LAUNCHED(ctx);
     int rc = scan_u32(ctx, t.blk, t.blk, (int64_t)gp, t.d_nnodes, t.scan_tmp);
     if (rc) return rc;
@@ -495,7 +548,8 @@ int octree_geometry(sfcnl_ctx ctx, Octree &t, const float *x, const float *y, co
         below = sizes[l + nlev - 1];
         l += nlev;
     }
-    k_node_slots<<<gn, 256, 0, st>>>(t.d_nnodes, cap, t.nfirst, t.nend, t.nlevel, t.nnchild, t.parent, t.pidx,
+    // kSlotLanes lanes per node: a grid of twice the node kernels' blocks
+    k_node_slots<<<2 * gn, 256, 0, st>>>(t.d_nnodes, cap, t.nfirst, t.nend, t.nlevel, t.nnchild, t.parent, t.pidx,
                                      t.cbase, x, y, z, h, L, t.cs_box, t.cs_rec);
     SFCNL_LAUNCHED(ctx);
     if (seg.on()) {
@@ -507,8 +561,8 @@ int octree_geometry(sfcnl_ctx ctx, Octree &t, const float *x, const float *y, co
 }
 
 int octree_build(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const float *x, const float *y, const float *z,
-                 const float *h, const float4 *cluster_box, const SegTable &seg) {
-    const int rc = octree_topology(ctx, t, keys, seg);
+                 const float *h, const float4 *cluster_box, const SegTable &seg, uint32_t *clear, int nclear) {
+    const int rc = octree_topology(ctx, t, keys, seg, clear, nclear);
     if (rc) return rc;
     return octree_geometry(ctx, t, x, y, z, h, cluster_box, seg);
 }

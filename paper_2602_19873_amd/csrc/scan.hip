@@ -171,17 +171,27 @@ __global__ __launch_bounds__(kSmallThreads) void k_scan_small(const uint32_t *in
     if (t == 0 && total) *total = carry;
 }
 
-__global__ void k_fill(uint32_t *p, int64_t n, uint32_t v) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i < n) p[i] = v;
+// Fills of n words, four per thread: 16-byte stores where the array is
+// 16-byte aligned (the host checks), the last ragged words one at a time.
+__device__ __forceinline__ void fill4(uint32_t *p, int64_t n, int64_t i, uint32_t v, bool vec) {
+    if (vec && i + 4 <= n) {
+        *reinterpret_cast<uint4 *>(p + i) = make_uint4(v, v, v, v);
+    } else {
+        for (int64_t k = i; k < i + 4 && k < n; k++) p[k] = v;
+    }
+}
+
+__global__ void k_fill(uint32_t *p, int64_t n, uint32_t v, bool vec) {
+    const int64_t i = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
+    if (i < n) fill4(p, n, i, v, vec);
 }
 
 // Two arrays of n words at once (q may be null).
-__global__ void k_fill2(uint32_t *p, uint32_t *q, int64_t n, uint32_t v) {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+__global__ void k_fill2(uint32_t *p, uint32_t *q, int64_t n, uint32_t v, bool vec) {
+    const int64_t i = 4 * ((int64_t)blockIdx.x * blockDim.x + threadIdx.x);
     if (i < n) {
-        p[i] = v;
-        if (q) q[i] = v;
+        fill4(p, n, i, v, vec);
+        if (q) fill4(q, n, i, v, vec);
     }
 }
 
@@ -220,14 +230,14 @@ int scan_u32_dyn(sfcnl_ctx ctx, const uint32_t *in, uint32_t *out, const uint32_
 
 int fill_u32(sfcnl_ctx ctx, uint32_t *p, int64_t n, uint32_t v) {
     if (n <= 0) return SFCNL_OK;
-    k_fill<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(p, n, v);
+    k_fill<<<blocks_for((n + 3) / 4, 256), 256, 0, ctx->stream>>>(p, n, v, ((uintptr_t)p & 15u) == 0);
     SFCNL_LAUNCHED(ctx);
     return SFCNL_OK;
 }
 
 int fill2_u32(sfcnl_ctx ctx, uint32_t *p, uint32_t *q, int64_t n, uint32_t v) {
     if (n <= 0) return SFCNL_OK;
-    k_fill2<<<blocks_for(n, 256), 256, 0, ctx->stream>>>(p, q, n, v);
+    k_fill2<<<blocks_for((n + 3) / 4, 256), 256, 0, ctx->stream>>>(p, q, n, v, (((uintptr_t)p | (uintptr_t)q) & 15u) == 0);
     SFCNL_LAUNCHED(ctx);
     return SFCNL_OK;
 }
