@@ -57,47 +57,50 @@ __device__ __forceinline__ void seg_range(const SegTable &seg, int64_t p, int64_
 // that sliding window comes from a doubling table in LDS: after the step of
 // width d, entry k holds the largest of the d values from k on, and two
 // overlapping runs of the largest width d <= bucket + 1 cover the window.
-// Also writes the common digits with the previous key (cdig) and the block's
-// node count (nodes start at p for the levels (cdig, leaf level]). Block 0
-// also zeroes the nclear words at clear (the caller's counters that must start
-// at zero; this saves their own launch).
+// A block takes kLeafPer consecutive groups of 256 particles, the keys they
+// need staged once in LDS. Also writes the common digits with the previous key
+// (cdig) and the node count of every group of 256 particles (nodes start at p
+// for the levels (cdig, leaf level]). Block 0 also zeroes the nclear words at
+// clear (the caller's counters that must start at zero; this saves their own
+// launch).
+constexpr int kLeafPer = 4;
+constexpr int kLeafSpan = 256 * kLeafPer;
+
 __global__ __launch_bounds__(256) void k_leaf_level(const uint64_t *__restrict__ keys, int64_t n, int bucket,
                                                     SegTable seg, int8_t *__restrict__ cdig,
                                                     int8_t *__restrict__ lleaf, uint32_t *__restrict__ blk,
                                                     uint32_t *__restrict__ clear, int nclear) {
-    constexpr int kSpan = 256 + kMaxBucket;
+    __shared__ uint64_t s_key[kLeafSpan + 2 * kMaxBucket];  // keys b0 - bucket .. b0 + span + bucket - 1
+    __shared__ int8_t s_tab[2][kLeafSpan + kMaxBucket];  // bytes (measured faster than words)
+    __shared__ uint32_t s_w[kLeafPer][256 / kWave];
     if (blockIdx.x == 0)
         for (int k = threadIdx.x; k < nclear; k += 256) clear[k] = 0u;
-    __shared__ int8_t s_tab[2][kSpan];
-    __shared__ uint32_t s_w[256 / kWave];
-    const int len = 256 + bucket;
-    const int64_t b0 = (int64_t)blockIdx.x * 256;
+    const int len = kLeafSpan + bucket;  // window starts b0 - bucket .. b0 + span - 1
+    const int nkey = len + bucket;
+    const int64_t b0 = (int64_t)blockIdx.x * kLeafSpan;
+    // keys from clamped indices, loaded unconditionally (in flight together)
     {
-        // the window entries (len <= 512: two per thread) and the own key with
-        // its predecessor, loaded unconditionally from clamped indices so that
-        // they are in flight together
-        uint64_t ka[2], kb[2];
+        constexpr int kRounds = (kLeafSpan + 2 * kMaxBucket) / 256;
+        uint64_t kv[kRounds];
 #pragma unroll
-        for (int r = 0; r < 2; r++) {
+        for (int r = 0; r < kRounds; r++) {
             const int64_t a = b0 - bucket + r * 256 + threadIdx.x;
-            const int64_t ac = a < 0 ? 0 : (a >= n ? n - 1 : a);
-            const int64_t bc = a + bucket < 0 ? 0 : (a + bucket >= n ? n - 1 : a + bucket);
-            ka[r] = keys[ac];
-            kb[r] = keys[bc];
+            kv[r] = keys[a < 0 ? 0 : (a >= n ? n - 1 : a)];
         }
 #pragma unroll
-        for (int r = 0; r < 2; r++) {
-            const int k = r * 256 + threadIdx.x;
-            if (k >= len) continue;
-            const int64_t a = b0 - bucket + k;
-            int lam = -1;
-            if (a >= 0 && a < n) {
-                int64_t lo, hi;
-                seg_range(seg, a, n, lo, hi);
-                if (a < hi && a + bucket < hi) lam = sfc_common_digits(ka[r], kb[r]);
-            }
-            s_tab[0][k] = (int8_t)lam;
+        for (int r = 0; r < kRounds; r++)
+            if (r * 256 + (int)threadIdx.x < nkey) s_key[r * 256 + threadIdx.x] = kv[r];
+    }
+    __syncthreads();
+    for (int k = threadIdx.x; k < len; k += 256) {
+        const int64_t a = b0 - bucket + k;
+        int lam = -1;
+        if (a >= 0 && a < n) {
+            int64_t lo, hi;
+            seg_range(seg, a, n, lo, hi);
+            if (a < hi && a + bucket < hi) lam = sfc_common_digits(s_key[k], s_key[k + bucket]);
         }
+        s_tab[0][k] = (int8_t)lam;
     }
     __syncthreads();
     const int win = bucket + 1;
@@ -113,30 +116,38 @@ __global__ __launch_bounds__(256) void k_leaf_level(const uint64_t *__restrict__
         cur ^= 1;
         d *= 2;
     }
-    const int64_t p = b0 + threadIdx.x;
-    uint32_t cnt = 0;
-    if (p < n) {
-        int64_t lo, hi;
-        seg_range(seg, p, n, lo, hi);  // systems never share a cell: each starts its own root
-        int c, L;
-        if (p >= hi) {  // padding: starts no node (cdig >= every leaf level)
-            c = 127;
-            L = 0;
-        } else {
-            c = p == lo ? -1 : sfc_common_digits(keys[p - 1], keys[p]);
-            const int u = s_tab[cur][threadIdx.x], v = s_tab[cur][threadIdx.x + win - d];
-            const int m = u > v ? u : v;
-            L = m + 1 < kMaxLevel ? m + 1 : kMaxLevel;
-            cnt = c < L ? (uint32_t)(L - c) : 0u;
+#pragma unroll
+    for (int r = 0; r < kLeafPer; r++) {
+        const int k = r * 256 + threadIdx.x;  // particle b0 + k; its window starts at table entry k
+        const int64_t p = b0 + k;
+        uint32_t cnt = 0;
+        if (p < n) {
+            int64_t lo, hi;
+            seg_range(seg, p, n, lo, hi);  // systems never share a cell: each starts its own root
+            int c, L;
+            if (p >= hi) {  // padding: starts no node (cdig >= every leaf level)
+                c = 127;
+                L = 0;
+            } else {
+                c = p == lo ? -1 : sfc_common_digits(s_key[bucket + k - 1], s_key[bucket + k]);
+                const int u = s_tab[cur][k], v = s_tab[cur][k + win - d];
+                const int m = u > v ? u : v;
+                L = m + 1 < kMaxLevel ? m + 1 : kMaxLevel;
+                cnt = c < L ? (uint32_t)(L - c) : 0u;
+            }
+            cdig[p] = (int8_t)c;
+            lleaf[p] = (int8_t)L;
         }
-        cdig[p] = (int8_t)c;
-        lleaf[p] = (int8_t)L;
+        // the group's total of the node counts
+        const uint32_t tot = sfc_readlane(sfc_incl_scan(cnt), kWave - 1);
+        if (sfc_lane() == 0) s_w[r][threadIdx.x / kWave] = tot;
     }
-    // block total of the node counts
-    uint32_t tot = sfc_readlane(sfc_incl_scan(cnt), kWave - 1);
-    if (sfc_lane() == 0) s_w[threadIdx.x / kWave] = tot;
     __syncthreads();
-    if (threadIdx.x == 0) blk[blockIdx.x] = s_w[0] + s_w[1] + s_w[2] + s_w[3];
+    if (threadIdx.x < kLeafPer) {
+        const int r = threadIdx.x;
+        const int64_t g = (int64_t)blockIdx.x * kLeafPer + r;  // group of 256 particles
+        if (g * 256 < n) blk[g] = s_w[r][0] + s_w[r][1] + s_w[r][2] + s_w[r][3];
+    }
 }
 
 // Node numbers in depth-first pre-order: the prefix of the node counts over
@@ -504,7 +515,8 @@ int octree_topology(sfcnl_ctx ctx, Octree &t, const uint64_t *keys, const SegTab
     const unsigned gp = blocks_for(n, 256);
     // leaf levels and per-block node counts, their prefix sum (the total is
     // the node count), then the nodes in depth-first pre-order
-    k_leaf_level<<<gp, 256, 0, st>>>(keys, n, B, seg, t.cdig, t.lleaf, t.blk, clear, clear ? nclear : 0);
+    k_leaf_level<<<blocks_for(n, kLeafSpan), 256, 0, st>>>(keys, n, B, seg, t.cdig, t.lleaf, t.blk, clear,
+                                                          clear ? nclear : 0);
     SFCNL_LAUNCHED(ctx);
     int rc = scan_u32(ctx, t.blk, t.blk, (int64_t)gp, t.d_nnodes, t.scan_tmp);
     if (rc) return rc;
