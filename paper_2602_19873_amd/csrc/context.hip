@@ -71,13 +71,16 @@ extern "C" int sfcnl_create(sfcnl_ctx *out, int device, void *stream) {
         return SFCNL_E_HIP;
     }
     memset(c->h_status, 0, kStWords * sizeof(uint32_t));
-    if (hipHostMalloc((void **)&c->h_pend, kStWords * sizeof(uint32_t), hipHostMallocDefault) != hipSuccess) {
+    // coherent: the device's stores reach the host while later work still runs
+    if (hipHostMalloc((void **)&c->h_pend, kStWords * sizeof(uint64_t), hipHostMallocMapped | hipHostMallocCoherent) !=
+        hipSuccess) {
         (void)hipHostFree(c->h_status);
         (void)hipFree(c->d_status);
         free(c);
         return SFCNL_E_HIP;
     }
-    if (hipEventCreateWithFlags(&c->ev_pend, hipEventDisableTiming) != hipSuccess) {
+    memset(c->h_pend, 0, kStWords * sizeof(uint64_t));
+    if (hipHostGetDevicePointer((void **)&c->d_pend, c->h_pend, 0) != hipSuccess) {
         (void)hipHostFree(c->h_pend);
         (void)hipHostFree(c->h_status);
         (void)hipFree(c->d_status);
@@ -85,7 +88,6 @@ extern "C" int sfcnl_create(sfcnl_ctx *out, int device, void *stream) {
         return SFCNL_E_HIP;
     }
     if (fill_u32(c, c->d_status, kStatusAlloc, 0) != SFCNL_OK || hipStreamSynchronize(c->stream) != hipSuccess) {
-        (void)hipEventDestroy(c->ev_pend);
         (void)hipHostFree(c->h_pend);
         (void)hipHostFree(c->h_status);
         (void)hipFree(c->d_status);
@@ -148,7 +150,6 @@ extern "C" void sfcnl_destroy(sfcnl_ctx ctx) {
     if (!ctx) return;
     prof_release(ctx);
     (void)hipStreamSynchronize(ctx->stream);
-    (void)hipEventDestroy(ctx->ev_pend);
     (void)hipHostFree(ctx->h_pend);
     (void)hipHostFree(ctx->h_status);
     (void)hipFree(ctx->d_status);

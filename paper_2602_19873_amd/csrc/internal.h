@@ -47,10 +47,13 @@ struct sfcnl_ctx_s {
     uint32_t *d_status;
     uint32_t *h_status;
     char err[512];
-    // build_nlist_async: status block copied behind the build, the event
-    // that marks the copy, and what the result call needs for its messages
-    uint32_t *h_pend;
-    hipEvent_t ev_pend;
+    // build_nlist_async: the status block written behind the build by a
+    // one-wave kernel into coherent pinned memory (d_pend is its device
+    // view), each word as one 64-bit store with the build's number pend_seq
+    // in the high half; and what the result call needs for its messages
+    uint64_t *h_pend;
+    uint64_t *d_pend;
+    uint32_t pend_seq;
     int pend;
     size_t pend_pool_bytes;
     int pend_max_j;

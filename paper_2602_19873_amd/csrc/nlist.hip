@@ -1238,16 +1238,25 @@ extern "C" int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, con
                             pool_bytes, SegTable{}, true, h_used_bytes, h_max_nj);
 }
 
-// The async build's bookkeeping: the status block copied behind the work,
-// an event marking the copy.
-static int mark_pending(sfcnl_ctx ctx, int64_t n, const sfcnl_nlist_opts *opts, size_t pool_bytes) {
-    if (n > 0) {
-        SFCNL_HIP(ctx, hipMemcpyAsync(ctx->h_pend, ctx->d_status, kStWords * sizeof(uint32_t),
-                                      hipMemcpyDeviceToHost, ctx->stream));
-    } else {
-        memset(ctx->h_pend, 0, kStWords * sizeof(uint32_t));
+// The async build's status to the host: word k (zero when `zero`) with the
+// build's number in the high half, as one 64-bit store (single-copy atomic),
+// so the host knows each word's build without a fence between the stores.
+// One wave.
+__global__ void k_post_status(const uint32_t *__restrict__ status, uint64_t *out, uint32_t seq, int zero) {
+    const int t = threadIdx.x;
+    if (t < kStWords) {
+        const uint32_t v = zero ? 0u : status[t];
+        __hip_atomic_store(out + t, ((uint64_t)seq << 32) | v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
     }
-    SFCNL_HIP(ctx, hipEventRecord(ctx->ev_pend, ctx->stream));
+}
+
+// The async build's bookkeeping: the status block posted behind the work
+// (a kernel instead of a copy and an event, whose barrier would stall the
+// stream), numbered so that the result call knows it when it arrives.
+static int mark_pending(sfcnl_ctx ctx, int64_t n, const sfcnl_nlist_opts *opts, size_t pool_bytes) {
+    ctx->pend_seq = ctx->pend_seq + 1u ? ctx->pend_seq + 1u : 1u;  // 0: nothing posted yet
+    k_post_status<<<1, kWave, 0, ctx->stream>>>(ctx->d_status, ctx->d_pend, ctx->pend_seq, n > 0 ? 0 : 1);
+    SFCNL_LAUNCHED(ctx);
     ctx->pend = 1;
     ctx->pend_pool_bytes = pool_bytes;
     ctx->pend_max_j = opts->max_j_per_sc;
@@ -1283,7 +1292,30 @@ extern "C" int build_nlist_result(sfcnl_ctx ctx, size_t *h_used_bytes, int64_t *
     *h_max_nj = 0;
     if (!ctx->pend) return set_err(ctx, SFCNL_E_ARG, "build_nlist_result: no build_nlist_async pending");
     ctx->pend = 0;
-    SFCNL_HIP(ctx, hipEventSynchronize(ctx->ev_pend));
-    return nlist_status(ctx, ctx->h_pend, ctx->pend_pool_bytes, ctx->pend_max_j, ctx->pend_nsc, h_used_bytes,
-                        h_max_nj);
+    // wait until every status word carries the build's number; every 256
+    // rounds the stream's state is asked: an error ends the wait, and an idle
+    // stream means the post has run (its stores are visible by then)
+    const uint32_t seq = ctx->pend_seq;
+    uint32_t hs[kStWords];
+    for (uint32_t spin = 1;; spin++) {
+        int have = 0;
+        for (int k = 0; k < kStWords; k++) {
+            const uint64_t v = __atomic_load_n(&ctx->h_pend[k], __ATOMIC_ACQUIRE);
+            hs[k] = (uint32_t)v;
+            have += (uint32_t)(v >> 32) == seq;
+        }
+        if (have == kStWords) break;
+        if (spin % 256u) continue;
+        const hipError_t e = hipStreamQuery(ctx->stream);
+        if (e == hipErrorNotReady) continue;
+        if (e != hipSuccess) return set_err(ctx, SFCNL_E_HIP, "build_nlist_result: %s", hipGetErrorString(e));
+        for (int k = 0; k < kStWords; k++) {
+            const uint64_t v = __atomic_load_n(&ctx->h_pend[k], __ATOMIC_ACQUIRE);
+            if ((uint32_t)(v >> 32) != seq)
+                return set_err(ctx, SFCNL_E_HIP, "build_nlist_result: the stream is idle but the build's status did not arrive");
+            hs[k] = (uint32_t)v;
+        }
+        break;
+    }
+    return nlist_status(ctx, hs, ctx->pend_pool_bytes, ctx->pend_max_j, ctx->pend_nsc, h_used_bytes, h_max_nj);
 }
