@@ -20,6 +20,7 @@
 #include <cmath>
 
 #include "internal.h"
+
 #include "pass_common.h"
 
 namespace sfcnl {
@@ -52,6 +53,47 @@ __device__ __forceinline__ void lj_wave_sync() {
     __builtin_amdgcn_wave_barrier();
 }
 
+// Box of a wave's i-particles (absent ones, far away, make it huge).
+struct IBox {
+    float lo[3] = {0.0f, 0.0f, 0.0f}, hi[3] = {0.0f, 0.0f, 0.0f};
+};
+template <int kNreg>
+__device__ __forceinline__ void wave_range(const float (&v)[kNreg], float &lo, float &hi) {
+    lo = v[0];
+    hi = v[0];
+#pragma unroll
+    for (int k = 1; k < kNreg; k++) {
+        lo = fminf(lo, v[k]);
+        hi = fmaxf(hi, v[k]);
+    }
+#pragma unroll
+    for (int d = 1; d < kWave; d <<= 1) {
+        lo = fminf(lo, __shfl_xor(lo, d, kWave));
+        hi = fmaxf(hi, __shfl_xor(hi, d, kWave));
+    }
+    // wave-uniform: scalar registers
+    lo = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, lo)));
+    hi = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, hi)));
+}
+template <int kNreg>
+__device__ __forceinline__ IBox ibox_of(const float (&ix)[kNreg], const float (&iy)[kNreg], const float (&iz)[kNreg]) {
+    IBox b;
+    wave_range<kNreg>(ix, b.lo[0], b.hi[0]);
+    wave_range<kNreg>(iy, b.lo[1], b.hi[1]);
+    wave_range<kNreg>(iz, b.lo[2], b.hi[2]);
+    return b;
+}
+// True if the difference of j and some point of the box exceeds half a
+// period on a periodic axis. FP32 subtraction is monotonic, so when it is
+// false every pair of j with a particle inside the box has |fl(x_j - x_i)| at
+// most half a period on every axis: its minimum image is the difference
+// itself, and a batch of such j-particles can skip the wrap.
+__device__ __forceinline__ bool far_from_box(float4 j, const IBox &b, const Period &p) {
+    return fmaxf(fabsf(j.x - b.lo[0]), fabsf(j.x - b.hi[0])) > p.hL[0] ||
+           fmaxf(fabsf(j.y - b.lo[1]), fabsf(j.y - b.hi[1])) > p.hL[1] ||
+           fmaxf(fabsf(j.z - b.lo[2]), fabsf(j.z - b.hi[2])) > p.hL[2];
+}
+
 // minimum images of a pair's components on periodic axes
 template <bool kPbc>
 __device__ __forceinline__ void wrap3(float &dx, float &dy, float &dz, const Period &p) {
@@ -75,15 +117,16 @@ __device__ __forceinline__ void lj_factor(float d2, float kqq, const LjArgs &a, 
 }
 
 // One pair of a full-list tile. g accumulates fr * (x_j - x_i) (the force on
-// i is its negative), ge the pair energies.
+// i is its negative), ge the pair energies. wrap (wave-uniform) false: no
+// pair of the tile can need a minimum image.
 template <bool kQ, bool kE, bool kPbc>
 __device__ __forceinline__ void lj_tile(float xj, float yj, float zj, float qj, float xi, float yi, float zi,
                                         float kqi, bool self_pair, const LjArgs &a, float &gx, float &gy, float &gz,
-                                        float &ge) {
+                                        float &ge, bool wrap = true) {
     float dx = xj - xi;
     float dy = yj - yi;
     float dz = zj - zi;
-    wrap3<kPbc>(dx, dy, dz, a.per);
+    if (wrap) wrap3<kPbc>(dx, dy, dz, a.per);
     const float dxx = dx * dx;
     const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
     const bool in = d2 < a.rc2 && !self_pair;
@@ -149,6 +192,10 @@ __global__ __launch_bounds__(kWave * kLjWaves) __attribute__((amdgpu_waves_per_e
     // (q, r) = (lane / 8, lane % 8) loads particle r of the batch's entry q
     // (one load per field for the batch) into LDS, where the tile lanes of
     // entry q read j-particle jl.
+    const IBox ib = kPbc && CS == 8 ? ibox_of<kNreg>(ix, iy, iz) : IBox{};
+    auto batch_wraps = [&](float4 jp, bool used) __attribute__((always_inline)) {
+        return sfc_ballot(used && far_from_box(jp, ib, a.per)) != 0;
+    };
     __shared__ float4 s_jb[kLjWaves][CS == 8 ? kWave : 1];  // x, y, z, charge
     auto entries8 = [&](uint32_t mvl, uint32_t jvl, uint32_t cnt) __attribute__((always_inline)) {
         const int il = lane >> 3;
@@ -162,9 +209,11 @@ __global__ __launch_bounds__(kWave * kLjWaves) __attribute__((amdgpu_waves_per_e
             const float bx = a.x[pc], by = a.y[pc], bz = a.z[pc];
             const float bq = kQ ? a.q[pc] : 0.0f;
             lj_wave_sync();  // the previous batch's reads are done
-            s_jb[w][lane] = make_float4(pv ? bx : -kAway, pv ? by : -kAway, pv ? bz : -kAway, pv ? bq : 0.0f);
+            const float4 jv4 = make_float4(pv ? bx : -kAway, pv ? by : -kAway, pv ? bz : -kAway, pv ? bq : 0.0f);
+            s_jb[w][lane] = jv4;
             lj_wave_sync();
             const uint32_t bn = cnt - q0 < 8u ? cnt - q0 : 8u;
+            const bool wrap = kPbc && batch_wraps(jv4, (uint32_t)(lane >> 3) < bn);
             for (uint32_t q = 0; q < bn; q++) {
                 const uint32_t mk = sfc_readlane(mvl, (int)(q0 + q));
                 const uint32_t cj = sfc_readlane(jvl, (int)(q0 + q));
@@ -173,8 +222,8 @@ __global__ __launch_bounds__(kWave * kLjWaves) __attribute__((amdgpu_waves_per_e
 #pragma unroll
                 for (int c = 0; c < kNreg; c++)
                     if ((mk >> c) & 1u)
-                        lj_tile<kQ, kE, kPbc>(jb.x, jb.y, jb.z, jb.w, ix[c], iy[c], iz[c], ikq[c], c == self_c && il == jl, a,
-                                              gx[c], gy[c], gz[c], ge[c]);
+                        lj_tile<kQ, kE, kPbc>(jb.x, jb.y, jb.z, jb.w, ix[c], iy[c], iz[c], ikq[c], c == self_c && il == jl,
+                                              a, gx[c], gy[c], gz[c], ge[c], wrap);
             }
         }
     };
@@ -308,6 +357,10 @@ __global__ __launch_bounds__(kWave * kLjWaves) __attribute__((amdgpu_waves_per_e
     // lanes of each j-particle, by DPP) and whether the j-particle formed a
     // pair go to LDS too, and after the batch lane (q, r) adds its particle's
     // sums with one atomic per component.
+    const IBox ib = kPbc && CS == 8 ? ibox_of<kNreg>(ix, iy, iz) : IBox{};
+    auto batch_wraps = [&](float4 jp, bool used) __attribute__((always_inline)) {
+        return sfc_ballot(used && far_from_box(jp, ib, a.per)) != 0;
+    };
     __shared__ float4 s_jb[kLjWaves][CS == 8 ? kWave : 1];  // x, y, z, charge
     __shared__ float4 s_jh[kLjWaves][CS == 8 ? kWave : 1];  // j-side force (and energy) sums
     __shared__ uint32_t s_jhit[kLjWaves][CS == 8 ? kWave : 1];
@@ -322,9 +375,11 @@ __global__ __launch_bounds__(kWave * kLjWaves) __attribute__((amdgpu_waves_per_e
             const uint32_t pc = pq < n ? pq : (uint32_t)(n - 1);  // loads of a clamped index go out together
             const float bx = a.x[pc], by = a.y[pc], bz = a.z[pc];
             const float bq = kQ ? a.q[pc] : 0.0f;
-            s_jb[w][lane] = make_float4(ev ? bx : -kAway, ev ? by : -kAway, ev ? bz : -kAway, ev ? bq : 0.0f);
+            const float4 jv4 = make_float4(ev ? bx : -kAway, ev ? by : -kAway, ev ? bz : -kAway, ev ? bq : 0.0f);
+            s_jb[w][lane] = jv4;
             lj_wave_sync();
             const uint32_t bn = cnt - q0 < 8u ? cnt - q0 : 8u;
+            const bool wrap = kPbc && batch_wraps(jv4, (uint32_t)(lane >> 3) < bn);
             for (uint32_t q = 0; q < bn; q++) {
                 const uint32_t mk = sfc_readlane(mvl, (int)(q0 + q));
                 const uint32_t cj = sfc_readlane(jvl, (int)(q0 + q));
@@ -340,7 +395,7 @@ __global__ __launch_bounds__(kWave * kLjWaves) __attribute__((amdgpu_waves_per_e
                     float dx = jb.x - ix[c];
                     float dy = jb.y - iy[c];
                     float dz = jb.z - iz[c];
-                    wrap3<kPbc>(dx, dy, dz, a.per);
+                    if (wrap) wrap3<kPbc>(dx, dy, dz, a.per);  // wave-uniform
                     const float dxx = dx * dx;
                     const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
                     const bool in = kp && d2 < a.rc2;
