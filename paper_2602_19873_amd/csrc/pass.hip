@@ -266,11 +266,11 @@ __global__ __launch_bounds__(kWave * kPassWavesMax) __attribute__((amdgpu_waves_
 template <bool kMass, bool kPbc>
 __device__ __forceinline__ void half_pair(float xj, float yj, float zj, float mj, float hj2, float hjinv, float xi,
                                           float yi, float zi, float mi, float hi2, float hiinv, float &acc_i,
-                                          int &cnt_i, float &acc_j, int &cnt_j, const Period &per) {
+                                          int &cnt_i, float &acc_j, int &cnt_j, const Period &per, bool wrap = true) {
     float dx = xj - xi;
     float dy = yj - yi;
     float dz = zj - zi;
-    if (kPbc) wave_min_image(dx, dy, dz, per);  // minimum images on periodic axes
+    if (kPbc && wrap) wave_min_image(dx, dy, dz, per);  // minimum images on periodic axes (wrap: wave-uniform)
     const float dxx = dx * dx;
     const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
     cnt_i += d2 < hi2 ? 1 : 0;
@@ -324,6 +324,9 @@ __global__ __launch_bounds__(kWave * kPassWavesMax) __attribute__((amdgpu_waves_
     const uint8_t *mbytes = reinterpret_cast<const uint8_t *>(a.pool + off);
     const uint16_t *mshorts = reinterpret_cast<const uint16_t *>(a.pool + off);
     const uint32_t jbase = a.seg.on() ? a.seg.pbase[a.seg.sc_sys[s]] / CS : 0u;
+    // periodic: a batch whose j-particles all lie within half a period of
+    // both ends of the i-box skips the minimum image (far_from_box)
+    const IBox ib = kPbc && CS == 8 ? ibox_of<kNreg>(ix, iy, iz) : IBox{};
     // Cluster size 8: the entries of a decoded segment 8 at a time. Lane
     // (q, r) = (lane / 8, lane % 8) loads particle r of the batch's entry q
     // (one load per field for the batch; loading the next batch behind the
@@ -368,13 +371,15 @@ __global__ __launch_bounds__(kWave * kPassWavesMax) __attribute__((amdgpu_waves_
             // -1, mass 0; NaN padding never pairs either)
             const float hh = f.v ? f.h : -1.0f;
             const bool vh = hh > 0.0f;
-            s_jb[lane] = make_float4(f.v ? f.x : kFar, f.v ? f.y : kFar, f.v ? f.z : kFar, vh ? hh * hh : -1.0f);
+            const float4 jv4 = make_float4(f.v ? f.x : kFar, f.v ? f.y : kFar, f.v ? f.z : kFar, vh ? hh * hh : -1.0f);
+            s_jb[lane] = jv4;
             s_jh[lane] = vh ? __builtin_amdgcn_rcpf(hh) : 1.0f;
             if (kMass) s_jm[lane] = vh ? f.m : 0.0f;
             const bool ev = f.v;
             const uint32_t jq_p = f.q;  // this lane's batch particle (for the atomics)
             pass_wave_sync();
             const uint32_t bn = cnt - q0 < 8u ? cnt - q0 : 8u;
+            const bool wrap = kPbc && sfc_ballot((uint32_t)(lane >> 3) < bn && far_from_box(jv4, ib, a.per)) != 0;
             const int il = lane & 7;
             for (uint32_t q = 0; q < bn; q++) {
                 const uint32_t mk = sfc_readlane(mvl, (int)(q0 + q));
@@ -390,7 +395,7 @@ __global__ __launch_bounds__(kWave * kPassWavesMax) __attribute__((amdgpu_waves_
                 for (int c = 0; c < kNreg; c++)
                     if (((mk >> c) & 1u) && (self_c < 0 || c < self_c || (c == self_c && jq > il)))
                         half_pair<kMass, kPbc>(jb.x, jb.y, jb.z, mj, jb.w, hjinv, ix[c], iy[c], iz[c], im[c], ih2[c],
-                                               ihinv[c], acc[c], cnt_nb[c], accj, cntj, a.per);
+                                               ihinv[c], acc[c], cnt_nb[c], accj, cntj, a.per, wrap);
                 s_ja[q * kWave + lane] = accj;
                 s_jc[q * kWave + lane] = cntj;
             }
