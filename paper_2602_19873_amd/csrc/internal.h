@@ -160,6 +160,21 @@ __device__ __forceinline__ float min_image(float d, float L, float hL) {
     return fabsf(d) > hL ? d - copysignf(L, d) : d;
 }
 
+// Box of a wave's i-particles (absent ones, far away, make it huge).
+struct IBox {
+    float lo[3] = {0.0f, 0.0f, 0.0f}, hi[3] = {0.0f, 0.0f, 0.0f};
+};
+// True if the difference of j and some point of the box exceeds half a
+// period on a periodic axis. FP32 subtraction is monotonic, so when it is
+// false every pair of j with a particle inside the box has |fl(x_j - x_i)| at
+// most half a period on every axis: its minimum image is the difference
+// itself, and a batch of such j-particles can skip the wrap.
+__device__ __forceinline__ bool far_from_box(float4 j, const IBox &b, const Period &p) {
+    return fmaxf(fabsf(j.x - b.lo[0]), fabsf(j.x - b.hi[0])) > p.hL[0] ||
+           fmaxf(fabsf(j.y - b.lo[1]), fabsf(j.y - b.hi[1])) > p.hL[1] ||
+           fmaxf(fabsf(j.z - b.lo[2]), fabsf(j.z - b.hi[2])) > p.hL[2];
+}
+
 }  // namespace sfcnl
 
 // A batch of independent systems (batch.hip). Input particles are the

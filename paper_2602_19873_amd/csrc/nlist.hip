@@ -24,7 +24,7 @@
 // striped counters), a prefix sum places the super-clusters in order, and a
 // second kernel writes masks and nibble segments.
 #include <cstring>
-
+#include <type_traits>
 #include <utility>
 
 #include "internal.h"
@@ -402,6 +402,7 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
     // open-boundary tests; the margin on R keeps the decision on the safe side
     // of FP32 rounding, so no accepted pair changes.
     bool wraps = false;
+    IBox sbox;  // the super-cluster's box (positions), for the batches' own decision
     if (kPbc) {
         float slo[3] = {glo.x, glo.y, glo.z}, shi[3] = {ghi.x, ghi.y, ghi.z};
         float r = glo.w;  // full build: replaced by the largest radius of all
@@ -426,6 +427,11 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
             }
         }
         wraps = sfc_ballot(w_lane) != 0;
+#pragma unroll
+        for (int t = 0; t < 3; t++) {  // wave-uniform: scalar registers
+            sbox.lo[t] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, slo[t])));
+            sbox.hi[t] = __builtin_bit_cast(float, __builtin_amdgcn_readfirstlane(__builtin_bit_cast(int, shi[t])));
+        }
     }
     const Period per = wraps ? a.per : Period{};
     // minimum images of a pair's components on periodic axes
@@ -642,7 +648,13 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
         JLoad f;
         load_batch(0, f);
         for (uint32_t b0 = 0; b0 < qn; b0 += kBatch) {
-            s_jp[w][9 * g + l] = batch_vals(f);
+            const float4 jv = batch_vals(f);
+            s_jp[w][9 * g + l] = jv;
+            // a wrapping super-cluster still skips the minimum images for a
+            // batch whose j-particles all lie within half a period of both
+            // ends of its box on every periodic axis (far_from_box)
+            bool bwrap = false;
+            if constexpr (kPbc) bwrap = wraps && sfc_ballot(b0 + (uint32_t)g < qn && far_from_box(jv, sbox, a.per)) != 0;
             if (b0 + kBatch < qn) load_batch(b0 + kBatch, f);
             // lane (g, l): candidate b0 + g against i-cluster l
             const uint32_t e = b0 + (uint32_t)g;
@@ -667,36 +679,52 @@ __global__ __launch_bounds__(kWave * kWavesPerBlock) __attribute__((amdgpu_waves
                 // quad (a DPP operand, no LDS traffic)
                 const float4 *jb = reinterpret_cast<const float4 *>(jpb + (tv >> 22));
                 const float4 ja = jb[l & 3], jz = jb[4 + (l & 3)];
-                uint64_t acc = 0;
-                if (!mixed) {
-                    static_for<CS>([&](auto pc) {
-                        constexpr int p = decltype(pc)::value;
-                        const float4 &jq = p < 4 ? ja : jz;
-                        float dx = quad_bcast<p & 3>(jq.x) - ip.x;
-                        float dy = quad_bcast<p & 3>(jq.y) - ip.y;
-                        float dz = quad_bcast<p & 3>(jq.z) - ip.z;
-                        if (kPbc) wrap(dx, dy, dz);
-                        const float dxx = dx * dx;
-                        const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                        acc |= sfc_ballot(d2 < max_sq(quad_bcast<p & 3>(jq.w), ip.w));
-                    });
+                // the round's tests; batches that can wrap take the minimum
+                // images (one wave-uniform choice per round keeps the 8 steps
+                // free of branches)
+                auto tests = [&](auto wrapc) SFC_INLINE {
+                    constexpr bool kW = decltype(wrapc)::value;
+                    uint64_t t = 0;
+                    if (!mixed) {
+                        static_for<CS>([&](auto pc) {
+                            constexpr int p = decltype(pc)::value;
+                            const float4 &jq = p < 4 ? ja : jz;
+                            float dx = quad_bcast<p & 3>(jq.x) - ip.x;
+                            float dy = quad_bcast<p & 3>(jq.y) - ip.y;
+                            float dz = quad_bcast<p & 3>(jq.z) - ip.z;
+                            if constexpr (kW) wave_min_image(dx, dy, dz, a.per);
+                            const float dxx = dx * dx;
+                            const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
+                            t |= sfc_ballot(d2 < max_sq(quad_bcast<p & 3>(jq.w), ip.w));
+                        });
+                    } else {
+                        // pairs within our own super-cluster: i = 8c + l and
+                        // j = 8c' + p; the half list keeps j > i (c < c', or
+                        // c = c' and l < p), the full list all but i = j
+                        const uint64_t below = sfc_ballot(ioff < soff), same = sfc_ballot(ioff == soff);
+                        static_for<CS>([&](auto pc) {
+                            constexpr int p = decltype(pc)::value;
+                            const float4 &jq = p < 4 ? ja : jz;
+                            float dx = quad_bcast<p & 3>(jq.x) - ip.x;
+                            float dy = quad_bcast<p & 3>(jq.y) - ip.y;
+                            float dz = quad_bcast<p & 3>(jq.z) - ip.z;
+                            if constexpr (kW) wave_min_image(dx, dy, dz, a.per);
+                            const float dxx = dx * dx;
+                            const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
+                            const uint64_t keep = half ? below | (same & (((1ull << p) - 1ull) * kBytes)) : ~(same & ((1ull << p) * kBytes));
+                            t |= sfc_ballot(d2 < max_sq(quad_bcast<p & 3>(jq.w), ip.w)) & keep;
+                        });
+                    }
+                    return t;
+                };
+                uint64_t acc;
+                if constexpr (kPbc) {
+                    if (bwrap)
+                        acc = tests(std::true_type{});
+                    else
+                        acc = tests(std::false_type{});
                 } else {
-                    // pairs within our own super-cluster: i = 8c + l and
-                    // j = 8c' + p; the half list keeps j > i (c < c', or
-                    // c = c' and l < p), the full list all but i = j
-                    const uint64_t below = sfc_ballot(ioff < soff), same = sfc_ballot(ioff == soff);
-                    static_for<CS>([&](auto pc) {
-                        constexpr int p = decltype(pc)::value;
-                        const float4 &jq = p < 4 ? ja : jz;
-                        float dx = quad_bcast<p & 3>(jq.x) - ip.x;
-                        float dy = quad_bcast<p & 3>(jq.y) - ip.y;
-                        float dz = quad_bcast<p & 3>(jq.z) - ip.z;
-                        if (kPbc) wrap(dx, dy, dz);
-                        const float dxx = dx * dx;
-                        const float d2 = __builtin_fmaf(dz, dz, __builtin_fmaf(dy, dy, dxx));
-                        const uint64_t keep = half ? below | (same & (((1ull << p) - 1ull) * kBytes)) : ~(same & ((1ull << p) * kBytes));
-                        acc |= sfc_ballot(d2 < max_sq(quad_bcast<p & 3>(jq.w), ip.w)) & keep;
-                    });
+                    acc = tests(std::false_type{});
                 }
                 if (lane == 0) s_hits[w][r] = acc;
             }

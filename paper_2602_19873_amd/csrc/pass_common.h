@@ -105,10 +105,6 @@ __device__ __forceinline__ int ipart_sym(int k, int lane) {
     return CS == 8 ? 8 * k + (lane & 7) : 16 * k + (lane & 15);
 }
 
-// Box of a wave's i-particles (absent ones, far away, make it huge).
-struct IBox {
-    float lo[3] = {0.0f, 0.0f, 0.0f}, hi[3] = {0.0f, 0.0f, 0.0f};
-};
 template <int kNreg>
 __device__ __forceinline__ void wave_range(const float (&v)[kNreg], float &lo, float &hi) {
     lo = v[0];
@@ -134,16 +130,6 @@ __device__ __forceinline__ IBox ibox_of(const float (&ix)[kNreg], const float (&
     wave_range<kNreg>(iy, b.lo[1], b.hi[1]);
     wave_range<kNreg>(iz, b.lo[2], b.hi[2]);
     return b;
-}
-// True if the difference of j and some point of the box exceeds half a
-// period on a periodic axis. FP32 subtraction is monotonic, so when it is
-// false every pair of j with a particle inside the box has |fl(x_j - x_i)| at
-// most half a period on every axis: its minimum image is the difference
-// itself, and a batch of such j-particles can skip the wrap.
-__device__ __forceinline__ bool far_from_box(float4 j, const IBox &b, const Period &p) {
-    return fmaxf(fabsf(j.x - b.lo[0]), fabsf(j.x - b.hi[0])) > p.hL[0] ||
-           fmaxf(fabsf(j.y - b.lo[1]), fabsf(j.y - b.hi[1])) > p.hL[1] ||
-           fmaxf(fabsf(j.z - b.lo[2]), fabsf(j.z - b.hi[2])) > p.hL[2];
 }
 
 }  // namespace passk
