@@ -106,6 +106,8 @@ __global__ void k_publish_total(const uint32_t *total, uint32_t *status) { statu
 // wins up to about a quarter of the particles.
 uint32_t count_path_limit(int64_t n) { return (uint32_t)(n / 4 + 64); }
 
+
+
 // Grid of the per-particle recount: up to 8192 wavefronts.
 unsigned count_blocks(uint32_t total) {
     const uint32_t b = (total + 3u) / 4u;
@@ -167,7 +169,9 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
     // The first round counts every particle with the requested list form;
     // later rounds rebuild full lists only for super-clusters where a radius
     // moved (the counts of the others cannot change: n_i depends on h_i only),
-    // and a converged run ends with one list build in the requested form.
+    // (with a half list requested and the automatic recount, those rounds
+    // rebuild every super-cluster's half list instead), and a converged run
+    // ends with one list build in the requested form.
     sfcnl_nlist_opts it_nl = *nl_opts;
     it_nl.half = 0;
     const ActiveWs act = nlist_ws_active(d_ws, n, it_nl, 1);
@@ -175,31 +179,40 @@ extern "C" int sfcnl_h_iterate(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys,
     bool list_final = false;
     for (int it = 0; it < it_opts->max_iters; it++) {
         const bool first = it == 0;
-        const sfcnl_nlist_opts &o = first ? *nl_opts : it_nl;
+        const bool per_particle = !first && (it_opts->recount == 2 ||
+                                             (it_opts->recount == 0 && S.unconverged <= count_path_limit(n)));
+        // every super-cluster in the requested form: the first round, and with
+        // the automatic recount and a half list every round that builds lists.
+        // The counting lists are full lists (each pair twice): on the 8M 1/r
+        // sphere, where nearly every super-cluster holds a moved particle in
+        // those rounds, they cost more than the half list and its symmetric
+        // pass (27.5 against 31.4 ms to converge). Counts, and so rounds and
+        // radii, are the same either way (n_i depends on h_i only).
+        const bool full = first || (it_opts->recount == 0 && nl_opts->half && !per_particle);
+        const sfcnl_nlist_opts &o = full ? *nl_opts : it_nl;
         int rc = SFCNL_OK;
-        if (first) {
+        if (full) {
             rc = clusters_impl(ctx, n, d_x, d_y, d_z, d_h, o.cluster_size, d_bbox, SegTable{});
             if (rc) return rc;
         }
-        const bool per_particle = it_opts->recount == 2 ||
-                                  (it_opts->recount == 0 && S.unconverged <= count_path_limit(n));
-        if (!first && per_particle) {
+        if (per_particle) {
             // few moved: one wavefront per moved particle on the last octree
             rc = count_moved_impl(ctx, n, act, d_x, d_y, d_z, d_h, d_m, d_rho, d_nnb, SegTable{},
                                   make_period(o.period), nullptr, 0, count_blocks((uint32_t)S.unconverged));
             if (rc) return rc;
         } else {
-            // later rounds: counting lists of the moved particles, same octree
+            // full rounds: every super-cluster in the requested form; the
+            // others: counting lists of the moved particles, same octree
             rc = nlist_build_impl(ctx, n, d_keys, d_x, d_y, d_z, d_h, d_bbox, o, d_ws, ws_bytes, d_sc_info, d_pool,
-                                  pool_bytes, SegTable{}, true, &S.used_bytes, &S.max_nj, first ? nullptr : act.sc,
-                                  first ? nullptr : act.p, !first);
+                                  pool_bytes, SegTable{}, true, &S.used_bytes, &S.max_nj, full ? nullptr : act.sc,
+                                  full ? nullptr : act.p, !full);
             if (rc) return rc;
             rc = pass_impl(ctx, n, o.cluster_size, o.compress, o.half, d_sc_info, d_pool, d_x, d_y, d_z, d_h, d_m,
-                           d_rho, d_nnb, SegTable{}, make_period(o.period), first ? nullptr : act.sc,
-                           first ? nullptr : act.p);
+                           d_rho, d_nnb, SegTable{}, make_period(o.period), full ? nullptr : act.sc,
+                           full ? nullptr : act.p);
             if (rc) return rc;
         }
-        list_final = first;
+        list_final = full;
         const float *proposal = nullptr;
         if (seed && seed->mode == SFCNL_SEED_AFTER_FIRST && first) {  // learned step from the first counts
             rc = sfcnl_hseed_features(ctx, n, d_keys, d_x, d_y, d_z, d_h, d_nnb, seed->box_edge, it_opts->target,
