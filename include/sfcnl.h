@@ -211,7 +211,10 @@ int build_nlist(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d
  * SFCNL_E_ARG. A list that does not fit is recorded as empty in sc_info, so a
  * pass enqueued before the result stays inside the pool; on SFCNL_E_CAPACITY
  * the build (and such a pass) must be redone with the sizes reported. The
- * buffers must stay untouched until the result call. */
+ * buffers must stay untouched until the result call. The result call polls
+ * pinned host memory that a one-wave kernel behind the build writes (no
+ * event, whose barrier would stall the stream), so it keeps the calling
+ * thread busy while it waits; a stream error ends the wait with SFCNL_E_HIP. */
 int build_nlist_async(sfcnl_ctx ctx, int64_t n, const uint64_t *d_keys, const float *d_x, const float *d_y,
                       const float *d_z, const float *d_h, const float *d_bbox, const sfcnl_nlist_opts *opts,
                       void *d_ws, size_t ws_bytes, uint32_t *d_sc_info, uint32_t *d_pool, size_t pool_bytes);
