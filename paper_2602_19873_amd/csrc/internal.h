@@ -160,7 +160,8 @@ __device__ __forceinline__ float min_image(float d, float L, float hL) {
     return fabsf(d) > hL ? d - copysignf(L, d) : d;
 }
 
-// Box of a wave's i-particles (absent ones, far away, make it huge).
+// Box of particle positions (a wave's i-particles, or a super-cluster in the
+// traversal); absent particles, placed far away, make it huge.
 struct IBox {
     float lo[3] = {0.0f, 0.0f, 0.0f}, hi[3] = {0.0f, 0.0f, 0.0f};
 };

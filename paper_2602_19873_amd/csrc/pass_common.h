@@ -1,8 +1,8 @@
 // Pieces shared by the list passes (the SPH density pass and the
 // Lennard-Jones + Coulomb pass): the wave-level decoder of one compressed
 // segment (Sec. II-B), the XCD-aware block order, the lane roles that map
-// list tiles onto a wavefront, DPP sums inside lane groups, and the test that
-// lets a batch of periodic pairs skip the minimum image.
+// list tiles onto a wavefront, DPP sums inside lane groups, and the wave's
+// i-box that the periodic batch test (far_from_box) takes.
 #pragma once
 #include "internal.h"
 
